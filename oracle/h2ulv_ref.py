@@ -1,0 +1,707 @@
+"""Plain FP64 CPU oracle of the H^2-ULV factorization without trailing
+sub-matrix dependencies (Ma, Deshmukh, Yokota; arXiv 2208.10907).
+
+TEST INFRASTRUCTURE.  Only the test suite, the package smoke check and the
+benchmark's CPU-baseline leg may import or run this module.  The product path
+(the HIP library) never calls it, and the two share no code: the only common
+module is ``workloads`` (seeded point clouds and right-hand sides).
+
+The oracle is deliberately plain: NumPy/SciPy in float64, one box at a time,
+steps in the order the paper gives them.  LAPACK routines serve as single steps
+(dgetrf/dgetrs for block LU, dgeqp3 for the column-pivoted QR, dgeqrf/dorgqr
+for the orthogonal complement).
+
+Method map (paper section / equation):
+  tree + admissibility ........ Sec. I (strong admissibility), Sec. III-D (binary tree)
+  dense / low-rank blocks ..... Sec. II-D: dense blocks only for inadmissible pairs
+  fill-in pre-computation ..... Sec. III-B, Fig. "fill-in"
+  shared basis [F A] .......... Sec. III-C, Eq. (fillu)/(fillv)
+  QR / ID, skeleton split ..... Sec. II-A, Eq. (u)/(v)
+  USV rotation ................ Sec. II-B, Eq. (rs) (dense) and Eq. (ss) (low-rank)
+  RR elimination .............. Sec. II-B, Eq. (lu) and the two triangular solves
+  Schur update of SS .......... Sec. II-B, the S^SS update equation
+  merge into parent ........... Sec. II-C, the 2x2 merge of S^SS blocks
+  root LU ..................... Sec. II-B, Eq. (BLR2final)
+  solve ....................... Sec. II-B, the three-step forward/backward solve
+
+Readings where the paper is silent (each is listed in the design notes):
+  * kernel 1/r (Laplace) or exp(-alpha r)/r (Yukawa), diagonal entry ``diag``;
+  * k-d tree: split along the widest bounding-box axis (lowest axis on ties),
+    stable sort by (coordinate, original index), left child gets floor(n/2);
+    L = smallest integer with leaf * 2^L >= N;
+  * admissible iff |c_i - c_j| > eta (r_i + r_j), centre = bounding-box
+    midpoint, radius = half the bounding-box diagonal;
+  * fill-in F_ij = sum over k in Near(i) cap Near(j), k not in {i,j}, of
+    D_ik D_kk^-1 D_kj, into every reachable (i,j) (diagonal included);
+  * the shared basis comes from a row interpolative decomposition of
+    M'_i = [K(P_i, far) | T^-1 F_i+] (pivoted QR of M'^T), made orthogonal
+    by a Householder QR of W = T W'; U = [U^S U^R] (skeleton columns first);
+  * rank k = number of leading pivots with |R_tt| > tol |R_00|, capped;
+  * off-diagonal dense blocks keep only their S^SS quadrant after rotation;
+  * symmetric kernels: V = U.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+# status codes (identical numbering to the C-ABI)
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_OOM = -2
+ERR_HIP = -3
+ERR_SINGULAR = -4
+ERR_DUPLICATE_POINTS = -5
+ERR_NOT_CONVERGED = -6
+
+LAPLACE = 0
+YUKAWA = 1
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+@dataclass
+class Params:
+    kernel: int = LAPLACE
+    alpha: float = 0.0
+    diag: float = 1e3
+    eta: float = 1.0
+    leaf: int = 64
+    tol: float = 1e-8
+    rank_cap: int = 0          # 0 = no cap
+    far_sample: int = 32       # 0 = exact far field, s > 0 = sampled
+
+
+def params_from_problem(prob) -> Params:
+    return Params(prob.kernel, prob.alpha, prob.diag, prob.eta, prob.leaf,
+                  prob.tol, prob.rank_cap, prob.far_sample)
+
+
+def check_params(X: np.ndarray, p: Params) -> None:
+    if X.ndim != 2 or X.shape[1] != 3 or X.shape[0] < 1:
+        raise OracleError(ERR_INVALID_ARG, "points must be N x 3, N >= 1")
+    if not np.all(np.isfinite(X)):
+        raise OracleError(ERR_INVALID_ARG, "non-finite point coordinate")
+    if p.leaf < 2 or p.eta < 0 or not math.isfinite(p.eta):
+        raise OracleError(ERR_INVALID_ARG, "leaf >= 2 and eta >= 0 required")
+    if p.tol < 0 or not math.isfinite(p.tol) or p.rank_cap < 0 or p.far_sample < 0:
+        raise OracleError(ERR_INVALID_ARG, "tol, rank_cap, far_sample must be >= 0")
+    if p.kernel not in (LAPLACE, YUKAWA) or not math.isfinite(p.diag):
+        raise OracleError(ERR_INVALID_ARG, "unknown kernel or bad diagonal")
+
+
+# ---------------------------------------------------------------------------
+# Kernel matrix (Sec. IV: Laplace Green's function; Sec. V: Yukawa potential)
+# ---------------------------------------------------------------------------
+def kernel_block(X: np.ndarray, rows: np.ndarray, cols: np.ndarray, p: Params) -> np.ndarray:
+    """K(X[rows], X[cols]); entry = diag where the row and column are the same
+    point, kernel(|x_i - x_j|) otherwise.  Coincident distinct points raise
+    DUPLICATE_POINTS."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    if rows.size == 0 or cols.size == 0:
+        return np.zeros((rows.size, cols.size))
+    xr, xc = X[rows], X[cols]
+    r2 = np.zeros((rows.size, cols.size))
+    for c in range(3):
+        d = xr[:, c][:, None] - xc[:, c][None, :]
+        r2 += d * d
+    r = np.sqrt(r2)
+    same = rows[:, None] == cols[None, :]
+    if np.any((r == 0.0) & ~same):
+        raise OracleError(ERR_DUPLICATE_POINTS, "two distinct points coincide")
+    rs = np.where(same, 1.0, r)
+    if p.kernel == LAPLACE:
+        K = 1.0 / rs
+    else:
+        K = np.exp(-p.alpha * rs) / rs
+    return np.where(same, p.diag, K)
+
+
+def dense_matrix(X: np.ndarray, p: Params) -> np.ndarray:
+    idx = np.arange(X.shape[0])
+    return kernel_block(X, idx, idx, p)
+
+
+def matvec_exact(X: np.ndarray, x: np.ndarray, p: Params, chunk: int = 1024) -> np.ndarray:
+    """y = A x with A generated on the fly: y_i = diag x_i + sum_{j != i} K(r_ij) x_j."""
+    n = X.shape[0]
+    x2 = x.reshape(n, -1)
+    y = np.zeros_like(x2, dtype=np.float64)
+    cols = np.arange(n)
+    for s in range(0, n, chunk):
+        rows = np.arange(s, min(n, s + chunk))
+        y[rows] = kernel_block(X, rows, cols, p) @ x2
+    return y.reshape(x.shape)
+
+
+# ---------------------------------------------------------------------------
+# Cluster tree (Sec. III-D: full binary tree over the point set)
+# ---------------------------------------------------------------------------
+@dataclass
+class Tree:
+    L: int
+    perm: np.ndarray                 # tree position -> original point index
+    start: list                      # start[l][i]
+    end: list
+    centre: list                     # centre[l]: (2^l, 3)
+    radius: list                     # radius[l]: (2^l,)
+
+
+def tree_depth(n: int, leaf: int) -> int:
+    L = 0
+    while leaf * (1 << L) < n:
+        L += 1
+    return L
+
+
+def build_tree(X: np.ndarray, leaf: int) -> Tree:
+    n = X.shape[0]
+    L = tree_depth(n, leaf)
+    perm = np.arange(n, dtype=np.int64)
+    start, end, centre, radius = [], [], [], []
+    ranges = [(0, n)]
+    for lev in range(L + 1):
+        st = np.array([a for a, _ in ranges], dtype=np.int64)
+        en = np.array([b for _, b in ranges], dtype=np.int64)
+        cen = np.zeros((len(ranges), 3))
+        rad = np.zeros(len(ranges))
+        nxt = []
+        for bi, (a, b) in enumerate(ranges):
+            pts = perm[a:b]
+            lo = X[pts].min(axis=0)
+            hi = X[pts].max(axis=0)
+            cen[bi] = 0.5 * (lo + hi)
+            d = hi - lo
+            rad[bi] = 0.5 * math.sqrt(float(d[0]) * d[0] + float(d[1]) * d[1] + float(d[2]) * d[2])
+            if lev < L:
+                axis = int(np.argmax(hi - lo))
+                order = np.lexsort((pts, X[pts, axis]))
+                perm[a:b] = pts[order]
+                mid = a + (b - a) // 2
+                nxt += [(a, mid), (mid, b)]
+        start.append(st)
+        end.append(en)
+        centre.append(cen)
+        radius.append(rad)
+        ranges = nxt
+    return Tree(L, perm, start, end, centre, radius)
+
+
+# ---------------------------------------------------------------------------
+# Near / far lists (strong admissibility, Sec. I and II-D)
+# ---------------------------------------------------------------------------
+def build_lists(tree: Tree, eta: float):
+    near = [[[0]]]
+    far = [[[]]]
+    for lev in range(1, tree.L + 1):
+        nb = 1 << lev
+        nl = [[] for _ in range(nb)]
+        fl = [[] for _ in range(nb)]
+        c, r = tree.centre[lev], tree.radius[lev]
+        for pbox in range(nb // 2):
+            for q in near[lev - 1][pbox]:
+                for i in (2 * pbox, 2 * pbox + 1):
+                    for j in (2 * q, 2 * q + 1):
+                        d = c[i] - c[j]
+                        dist = math.sqrt(float(d[0]) * d[0] + float(d[1]) * d[1] + float(d[2]) * d[2])
+                        if dist > eta * (float(r[i]) + float(r[j])):
+                            fl[i].append(j)
+                        else:
+                            nl[i].append(j)
+        near.append([sorted(x) for x in nl])
+        far.append([sorted(x) for x in fl])
+    return near, far
+
+
+def fill_targets(near_l, i: int):
+    """Column boxes j that receive a fill-in in block row i: every j that shares a
+    near box k (k != i, k != j) with i.  Sorted ascending; includes i itself when
+    i has a near neighbour."""
+    js = set()
+    for k in near_l[i]:
+        if k == i:
+            continue
+        for j in near_l[k]:
+            if j != k:
+                js.add(j)
+    return sorted(js)
+
+
+def box_points(tree: Tree, lev: int, q: int) -> np.ndarray:
+    return tree.perm[tree.start[lev][q]:tree.end[lev][q]]
+
+
+def far_columns(tree: Tree, near, far, lev: int, i: int, P, s: int) -> np.ndarray:
+    """Point indices that represent the far field of box i at level lev.
+    s == 0: every point outside the near boxes of i (the literal A_{i,+}).
+    s > 0: candidate rows P[lev][q] of every q in Far_lev(i), then for each
+    ancestor level (nearest first) and each of its far boxes, all points if the
+    box holds at most s points, else s evenly strided points."""
+    if s == 0:
+        mask = np.ones(tree.perm.size, dtype=bool)
+        for j in near[lev][i]:
+            mask[tree.start[lev][j]:tree.end[lev][j]] = False
+        return tree.perm[mask]
+    parts = [np.asarray(P[lev][q], dtype=np.int64) for q in far[lev][i]]
+    a = i
+    for la in range(lev - 1, 0, -1):
+        a >>= 1
+        for q in far[la][a]:
+            pts = box_points(tree, la, q)
+            nq = pts.size
+            if nq <= s:
+                parts.append(pts)
+            else:
+                t = np.arange(s)
+                parts.append(pts[((t + 0.5) * nq / s).astype(np.int64)])
+    if not parts:
+        return np.zeros(0, dtype=np.int64)
+    return np.concatenate(parts)
+
+
+# ---------------------------------------------------------------------------
+# Row interpolative decomposition and orthogonal complement
+# (Sec. II-A Eq. (u): column-pivoted QR, Q kept; ID allowed; Sec. III-C)
+# ---------------------------------------------------------------------------
+def row_id(M: np.ndarray, tol: float, cap: int):
+    """Row ID of M (m x n): M ~= W' M[piv[:k], :].
+
+    Column-pivoted Householder QR of M^T (LAPACK dgeqp3): M^T Pi = Q R.
+    k = number of leading t with |R_tt| > tol |R_00| (then capped).
+    W' has the identity on rows piv[:k] and (R11^-1 R12)^T on rows piv[k:].
+    Returns (k, piv, Wp, absdiag)."""
+    m, n = M.shape
+    if m == 0:
+        return 0, np.zeros(0, dtype=np.int64), np.zeros((0, 0)), np.zeros(0)
+    if n == 0:
+        return 0, np.arange(m), np.zeros((m, 0)), np.zeros(0)
+    qr, jpvt, tau, work, info = sla.lapack.dgeqp3(np.asfortranarray(M.T.copy()))
+    piv = np.asarray(jpvt, dtype=np.int64) - 1
+    steps = min(m, n)
+    R = np.triu(qr[:steps, :])
+    dg = np.abs(np.diag(R))
+    k = 0
+    if dg[0] > 0:
+        thr = tol * dg[0]
+        while k < steps and dg[k] > thr:
+            k += 1
+    cap_eff = min(m, n) if cap <= 0 else min(cap, m, n)
+    k = min(k, cap_eff)
+    Wp = np.zeros((m, k))
+    if k > 0:
+        Wp[piv[:k], np.arange(k)] = 1.0
+        if k < m:
+            E = sla.solve_triangular(R[:k, :k], R[:k, k:], lower=False)
+            Wp[piv[k:], :] = E.T
+    return k, piv, Wp, dg
+
+
+def complement_basis(W: np.ndarray):
+    """Householder QR of W (m x k), LAPACK convention: W = Q [T; 0].
+    Returns U = Q (m x m, orthogonal, skeleton columns first) and T (k x k)."""
+    m, k = W.shape
+    if k == 0:
+        return np.eye(m), np.zeros((0, 0))
+    Q, Rw = np.linalg.qr(W, mode="complete")
+    return Q, Rw[:k, :k]
+
+
+# ---------------------------------------------------------------------------
+# Block LU helpers (Sec. II-B Eq. (lu); partial pivoting, LAPACK dgetrf)
+# ---------------------------------------------------------------------------
+def lu(A: np.ndarray):
+    if A.shape[0] == 0:
+        return (A.copy(), np.zeros(0, dtype=np.int32))
+    lu_, piv = sla.lu_factor(A, check_finite=False)
+    d = np.diag(lu_)
+    if np.any(d == 0) or not np.all(np.isfinite(lu_)):
+        raise OracleError(ERR_SINGULAR, "zero or non-finite pivot")
+    return lu_, piv
+
+
+def apply_pinv(piv, B):
+    """P^T B for LAPACK row interchanges (sequential swaps)."""
+    B = np.array(B, dtype=np.float64, copy=True)
+    for t, pt in enumerate(piv):
+        if pt != t:
+            B[[t, pt]] = B[[pt, t]]
+    return B
+
+
+def lower_solve(lu_, B):
+    return sla.solve_triangular(lu_, B, lower=True, unit_diagonal=True, check_finite=False)
+
+
+def upper_solve(lu_, B):
+    return sla.solve_triangular(lu_, B, lower=False, check_finite=False)
+
+
+# ---------------------------------------------------------------------------
+# Factorization
+# ---------------------------------------------------------------------------
+@dataclass
+class BoxFactor:
+    m: int
+    k: int
+    U: np.ndarray          # m x m, [U^S U^R]
+    T: np.ndarray          # k x k
+    sk: np.ndarray         # skeleton point indices (pivot order)
+    piv: np.ndarray        # row-ID pivots (indices into the box's candidate rows)
+    lu: np.ndarray = None  # LU of S^RR (r x r)
+    lupiv: np.ndarray = None
+    URS: np.ndarray = None  # L^-1 P^T S^RS   (r x k)
+    LSR: np.ndarray = None  # S^SR U^-1       (k x r)
+    absdiag: np.ndarray = None
+
+
+@dataclass
+class Factor:
+    X: np.ndarray
+    params: Params
+    tree: Tree
+    near: list
+    far: list
+    levels: dict = field(default_factory=dict)   # lev -> list[BoxFactor]
+    cand: dict = field(default_factory=dict)     # lev -> list of candidate point arrays
+    root_lu: tuple = None
+    m_root: int = 0
+    stats: dict = field(default_factory=dict)
+
+
+def _offdiag_dropped(U_i, D, U_j, k_i, k_j):
+    """Norm of the dropped (non-SS) quadrants of a rotated off-diagonal block."""
+    S = U_i.T @ D @ U_j
+    tot = np.linalg.norm(D)
+    S[:k_i, :k_j] = 0.0
+    return np.linalg.norm(S), tot
+
+
+def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
+              level_stop: int | None = None, boxes: set | None = None) -> Factor:
+    """H^2-ULV factorization without trailing sub-matrix dependencies.
+
+    Level loop from the leaves up (Sec. III-B..III-C, then Sec. II-B/II-C):
+      (a) dense blocks D_ij for j in Near(i)      (leaf: kernel; upper: merged S)
+      (b) fill-ins F_ij = sum_k D_ik D_kk^-1 D_kj  (Sec. III-B)
+      (c) shared basis from [K(P_i, far) | T^-1 F_i+] by row ID + QR (Eq. fillu)
+      (d) low-rank couplings S^SS_ij = T_i K(sk_i, sk_j) T_j^T   (Eq. ss)
+      (e) rotation S_ii = U_i^T D_ii U_i, near S^SS_ij = U^S_i^T D_ij U^S_j (Eq. rs)
+      (f) LU of S^RR, triangular solves, Schur update of S^SS    (Eq. lu ff.)
+      merge children's S^SS into the parent's dense blocks       (Sec. II-C)
+    then the root LU (Eq. BLR2final).
+
+    ``level_stop``/``boxes``: stop after the basis step of that level, for the
+    given boxes only (used to time or check a sample of one level)."""
+    X = np.asarray(X, dtype=np.float64)
+    check_params(X, p)
+    tree = build_tree(X, p.leaf)
+    near, far = build_lists(tree, p.eta)
+    fac = Factor(X, p, tree, near, far)
+    L = tree.L
+    flops = {"fill": 0.0, "basis": 0.0, "rotate": 0.0, "couple": 0.0, "elim": 0.0, "root": 0.0}
+    dropped = []
+    kevals = 0
+
+    if L == 0:
+        idx = tree.perm.copy()
+        D0 = kernel_block(X, idx, idx, p)
+        fac.root_lu = lu(D0)
+        fac.m_root = D0.shape[0]
+        flops["root"] += 2.0 / 3.0 * fac.m_root ** 3
+        fac.stats = {"flops": flops, "kevals": D0.size}
+        return fac
+
+    # candidate rows and T-hat blocks of the current level
+    P = {L: [box_points(tree, L, i) for i in range(1 << L)]}
+    That = None                    # per box: list of triangular blocks (upper levels)
+    Sblk = None                    # previous level's S^SS blocks: dict (c, d) -> array
+    for lev in range(L, 0, -1):
+        nb = 1 << lev
+        Pl = P[lev]
+        m = [len(Pl[i]) for i in range(nb)]
+        # (a) dense blocks
+        D = {}
+        for i in range(nb):
+            for j in near[lev][i]:
+                if lev == L:
+                    D[i, j] = kernel_block(X, Pl[i], Pl[j], p)
+                    kevals += m[i] * m[j]
+                else:
+                    c1, c2 = 2 * i, 2 * i + 1
+                    d1, d2 = 2 * j, 2 * j + 1
+                    D[i, j] = np.block([[Sblk[c1, d1], Sblk[c1, d2]],
+                                        [Sblk[c2, d1], Sblk[c2, d2]]])
+        # (b) fill-ins: one LU per diagonal block, one solve per near block
+        dlu = {}
+        Y = {}
+        for k in range(nb):
+            if m[k] == 0:
+                continue
+            dlu[k] = lu(D[k, k])
+            flops["fill"] += 2.0 / 3.0 * m[k] ** 3
+            for j in near[lev][k]:
+                if j != k:
+                    Y[k, j] = sla.lu_solve(dlu[k], D[k, j], check_finite=False)
+                    flops["fill"] += 2.0 * m[k] ** 2 * m[j]
+        fac.cand[lev] = Pl
+        bf = [None] * nb
+        todo = range(nb) if (level_stop is None or lev != level_stop or boxes is None) else sorted(boxes)
+        for i in todo:
+            # F_ij for every reachable j
+            Fcols = []
+            for j in fill_targets(near[lev], i):
+                F = np.zeros((m[i], m[j]))
+                for k in near[lev][i]:
+                    if k == i or k == j or j not in near[lev][k]:
+                        continue
+                    F += D[i, k] @ Y[k, j]
+                    flops["fill"] += 2.0 * m[i] * m[k] * m[j]
+                Fcols.append(F)
+            Fi = np.concatenate(Fcols, axis=1) if Fcols else np.zeros((m[i], 0))
+            if lev < L and m[i] > 0:
+                # map fill-ins to point-row coordinates: T-hat^-1 F
+                Fi = Fi.copy()
+                off = 0
+                for Tc in That[i]:
+                    kc = Tc.shape[0]
+                    if kc:
+                        Fi[off:off + kc] = sla.solve_triangular(Tc, Fi[off:off + kc], lower=False)
+                    off += kc
+            fcols = far_columns(tree, near, far, lev, i, P, p.far_sample)
+            Kf = kernel_block(X, Pl[i], fcols, p)
+            kevals += Kf.size
+            M = np.concatenate([Kf, Fi], axis=1)
+            # (c) row ID + orthogonal complement
+            k_i, piv, Wp, dg = row_id(M, p.tol, p.rank_cap)
+            ncol = M.shape[1]
+            flops["basis"] += 2.0 * ncol * m[i] ** 2 - 2.0 / 3.0 * min(ncol, m[i]) ** 3 if ncol >= m[i] else 2.0 * m[i] * ncol ** 2 - 2.0 / 3.0 * ncol ** 3
+            if lev < L and m[i] > 0:
+                W = np.zeros_like(Wp)
+                off = 0
+                for Tc in That[i]:
+                    kc = Tc.shape[0]
+                    W[off:off + kc] = Tc @ Wp[off:off + kc]
+                    off += kc
+            else:
+                W = Wp
+            U, T = complement_basis(W)
+            flops["basis"] += 4.0 * m[i] * k_i * k_i + 4.0 * m[i] ** 2 * k_i
+            bf[i] = BoxFactor(m[i], k_i, U, T, np.asarray(Pl[i])[piv[:k_i]], piv, absdiag=dg)
+        if level_stop is not None and lev == level_stop:
+            fac.levels[lev] = bf
+            fac.stats = {"flops": flops, "kevals": kevals}
+            return fac
+        # (d) low-rank couplings
+        Snew = {}
+        for i in range(nb):
+            for j in far[lev][i]:
+                Kc = kernel_block(X, bf[i].sk, bf[j].sk, p)
+                kevals += Kc.size
+                Snew[i, j] = bf[i].T @ Kc @ bf[j].T.T
+                ki, kj = bf[i].k, bf[j].k
+                flops["couple"] += 2.0 * ki * ki * kj + 2.0 * ki * kj * kj
+        # (e) rotation + (f) elimination
+        for i in range(nb):
+            Ui, ki = bf[i].U, bf[i].k
+            for j in near[lev][i]:
+                if j == i:
+                    continue
+                Uj, kj = bf[j].U, bf[j].k
+                Snew[i, j] = Ui[:, :ki].T @ D[i, j] @ Uj[:, :kj]
+                flops["rotate"] += 2.0 * m[i] * m[j] * kj + 2.0 * ki * m[i] * kj
+                if diagnostics:
+                    dropped.append(_offdiag_dropped(Ui, D[i, j], Uj, ki, kj))
+            S = Ui.T @ D[i, i] @ Ui
+            flops["rotate"] += 4.0 * m[i] ** 3
+            r = m[i] - ki
+            if r > 0:
+                lu_, lp = lu(S[ki:, ki:])
+                URS = lower_solve(lu_, apply_pinv(lp, S[ki:, :ki]))
+                # L^SR = S^SR U^-1  <=>  U^T L^SR^T = S^SR^T
+                LSR = sla.solve_triangular(lu_, S[:ki, ki:].T, trans="T", lower=False,
+                                           check_finite=False).T if ki else np.zeros((0, r))
+                Snew[i, i] = S[:ki, :ki] - LSR @ URS
+                bf[i].lu, bf[i].lupiv, bf[i].URS, bf[i].LSR = lu_, lp, URS, LSR
+                flops["elim"] += 2.0 / 3.0 * r ** 3 + 2.0 * r * r * ki + 2.0 * ki * ki * r
+            else:
+                Snew[i, i] = S[:ki, :ki].copy()
+        fac.levels[lev] = bf
+        # merge: next level's candidate rows and T-hat
+        if lev > 1:
+            P[lev - 1] = [np.concatenate([bf[2 * q].sk, bf[2 * q + 1].sk]) for q in range(nb // 2)]
+            That = [[bf[2 * q].T, bf[2 * q + 1].T] for q in range(nb // 2)]
+        Sblk = Snew
+    # root
+    D0 = np.block([[Sblk[0, 0], Sblk[0, 1]], [Sblk[1, 0], Sblk[1, 1]]])
+    fac.m_root = D0.shape[0]
+    fac.root_lu = lu(D0) if fac.m_root > 0 else (D0, np.zeros(0, dtype=np.int32))
+    flops["root"] += 2.0 / 3.0 * fac.m_root ** 3
+    fac.stats = {"flops": flops, "kevals": kevals}
+    if diagnostics:
+        fac.stats["dropped"] = dropped
+    return fac
+
+
+# ---------------------------------------------------------------------------
+# Solve (Sec. II-B: L z = U^T b, U y = z, x = V^T y, applied level by level)
+# ---------------------------------------------------------------------------
+def solve(fac: Factor, B: np.ndarray) -> np.ndarray:
+    tree = fac.tree
+    L = tree.L
+    B = np.asarray(B, dtype=np.float64)
+    vec = B.ndim == 1
+    B2 = B.reshape(B.shape[0], -1)
+    bt = B2[tree.perm]
+    if L == 0:
+        lu_, lp = fac.root_lu
+        x = sla.lu_solve((lu_, lp), bt, check_finite=False)
+        out = np.empty_like(x)
+        out[tree.perm] = x
+        return out.reshape(B.shape)
+    # forward
+    rhs = [bt[tree.start[L][i]:tree.end[L][i]] for i in range(1 << L)]
+    saved = {}
+    for lev in range(L, 0, -1):
+        bf = fac.levels[lev]
+        cs = []
+        for i, f in enumerate(bf):
+            c = f.U.T @ rhs[i]
+            k = f.k
+            cS, cR = c[:k].copy(), c[k:]
+            yR = None
+            if f.m - k > 0:
+                yR = lower_solve(f.lu, apply_pinv(f.lupiv, cR))
+                if k:
+                    cS -= f.LSR @ yR
+            saved[lev, i] = yR
+            cs.append(cS)
+        rhs = [np.concatenate([cs[2 * q], cs[2 * q + 1]]) for q in range(len(bf) // 2)]
+    b0 = rhs[0]
+    x0 = sla.lu_solve(fac.root_lu, b0, check_finite=False) if fac.m_root else b0
+    xs = [x0]
+    # backward
+    for lev in range(1, L + 1):
+        bf = fac.levels[lev]
+        nxt = []
+        for q in range(len(bf) // 2):
+            xp = xs[q]
+            k1 = bf[2 * q].k
+            for i, xS in ((2 * q, xp[:k1]), (2 * q + 1, xp[k1:])):
+                f = bf[i]
+                if f.m - f.k > 0:
+                    xR = upper_solve(f.lu, saved[lev, i] - f.URS @ xS)
+                    nxt.append(f.U @ np.concatenate([xS, xR]))
+                else:
+                    nxt.append(f.U @ xS)
+        xs = nxt
+    xt = np.concatenate(xs)
+    out = np.empty_like(xt)
+    out[tree.perm] = xt
+    return out[:, 0] if vec else out
+
+
+def logabsdet(fac: Factor) -> float:
+    """log|det A~| = sum log|diag U^RR| over all boxes + log|det D_root|
+    (U and V are orthogonal)."""
+    s = 0.0
+    for lev, bf in fac.levels.items():
+        for f in bf:
+            if f.lu is not None:
+                s += float(np.sum(np.log(np.abs(np.diag(f.lu)))))
+    if fac.m_root:
+        s += float(np.sum(np.log(np.abs(np.diag(fac.root_lu[0])))))
+    return s
+
+
+def refine(fac: Factor, B: np.ndarray, rtol: float = 1e-10, max_iter: int = 20):
+    """Classical iterative refinement with the exact FP64 matvec:
+    x = solve(b); repeat r = b - A x, stop when max_c |r_c|/|b_c| <= rtol,
+    else x += solve(r).  Returns (x, iterations, relres)."""
+    X, p = fac.X, fac.params
+    x = solve(fac, B)
+    bn = np.linalg.norm(B.reshape(B.shape[0], -1), axis=0)
+    bn[bn == 0] = 1.0
+    for it in range(max_iter + 1):
+        r = B - matvec_exact(X, x, p)
+        rel = float(np.max(np.linalg.norm(r.reshape(r.shape[0], -1), axis=0) / bn))
+        if rel <= rtol:
+            return x, it, rel
+        if it == max_iter:
+            break
+        x = x + solve(fac, r)
+    raise OracleError(ERR_NOT_CONVERGED, f"refinement stalled at {rel:.3e}")
+
+
+def assemble_dense(fac: Factor) -> np.ndarray:
+    """The matrix A~ that the factorization represents exactly, assembled densely
+    in the original point order: at each level
+      A~_l = U_l [[blkdiag S^RR, blkdiag S^RS], [blkdiag S^SR, A~_{l-1} + blkdiag S^SR S^RR^-1 S^RS]] U_l^T
+    (rows of each box ordered [S; R]).  Small N only."""
+    tree = fac.tree
+    L = tree.L
+    lu_, lp = fac.root_lu
+    if fac.m_root:
+        Lm = np.tril(lu_, -1) + np.eye(fac.m_root)
+        Um = np.triu(lu_)
+        A = apply_pinv_inverse(lp, Lm @ Um)
+    else:
+        A = np.zeros((0, 0))
+    for lev in range(1, L + 1):
+        bf = fac.levels[lev]
+        ks = [f.k for f in bf]
+        ms = [f.m for f in bf]
+        ntot = sum(ms)
+        ktot = sum(ks)
+        # per-box ordering: all S parts first (box order), then R parts (box order)
+        G = np.zeros((ntot, ntot))
+        G[:ktot, :ktot] = A
+        roff = ktot
+        soff = 0
+        pos = []  # (S range, R range) per box in G coordinates
+        for f in bf:
+            k, r = f.k, f.m - f.k
+            sR = slice(roff, roff + r)
+            sS = slice(soff, soff + k)
+            if r > 0:
+                Lm = np.tril(f.lu, -1) + np.eye(r)
+                Um = np.triu(f.lu)
+                SRR = apply_pinv_inverse(f.lupiv, Lm @ Um)
+                SRS = apply_pinv_inverse(f.lupiv, Lm @ f.URS)
+                SSR = f.LSR @ Um
+                G[sR, sR] = SRR
+                G[sR, sS] = SRS
+                G[sS, sR] = SSR
+                G[sS, sS] += SSR @ np.linalg.solve(SRR, SRS)
+            pos.append((sS, sR))
+            roff += r
+            soff += k
+        # map G coordinates to per-box [S;R] rotated coordinates, then apply U
+        order = np.concatenate([np.r_[s.start:s.stop, r.start:r.stop] for s, r in pos]).astype(np.int64)
+        Gb = G[np.ix_(order, order)]
+        Ubig = sla.block_diag(*[f.U for f in bf]) if bf else np.zeros((0, 0))
+        A = Ubig @ Gb @ Ubig.T
+    out = np.empty_like(A)
+    out[np.ix_(tree.perm, tree.perm)] = A
+    return out
+
+
+def apply_pinv_inverse(piv, B):
+    """P B for LAPACK row interchanges (undo of apply_pinv)."""
+    B = np.array(B, dtype=np.float64, copy=True)
+    for t in range(len(piv) - 1, -1, -1):
+        pt = piv[t]
+        if pt != t:
+            B[[t, pt]] = B[[pt, t]]
+    return B
+
+
+def total_flops(fac: Factor) -> float:
+    return float(sum(fac.stats["flops"].values()))
