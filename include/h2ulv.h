@@ -1,0 +1,216 @@
+/*
+ * h2ulv.h -- C-ABI of the MI355X H^2-ULV dense direct solver.
+ *
+ * The method is the H^2-matrix ULV factorization without trailing sub-matrix
+ * dependencies of Ma, Deshmukh and Yokota (arXiv 2208.10907):
+ *   - a binary cluster tree over the points with strong admissibility
+ *     (Sec. I; Sec. III-D), dense blocks only for inadmissible pairs (Sec. II-D);
+ *   - fill-ins pre-computed per block row from one LU per diagonal block and one
+ *     triangular solve per dense block (Sec. III-B);
+ *   - one shared basis per box from the concatenated fill-in and low-rank
+ *     blocks (Sec. III-C, Eq. fillu/fillv), skeleton/redundant split (Sec. II-A);
+ *   - the USV rotation of every block (Sec. II-B, Eq. rs and Eq. ss), LU of the
+ *     redundant-redundant diagonal block, triangular solves and the Schur
+ *     update of the skeleton block (Sec. II-B, Eq. lu and following), all boxes
+ *     of a level independent of each other;
+ *   - merge of the skeleton blocks into the parent level (Sec. II-C) and a
+ *     dense LU at the root (Eq. BLR2final);
+ *   - the three-step solve L z = U^T b, U y = z, x = V^T y (Sec. II-B).
+ *
+ * Conventions shared by every call:
+ *   - Pointers documented as "device" point to memory on the GPU that is current
+ *     when the call is made; "host" pointers are ordinary CPU memory.
+ *   - All vectors/matrices are float64 and column-major; vector entries are in
+ *     the caller's original point order (the tree permutation is internal).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *     ordered on that stream.  Calls that return host values synchronise it.
+ *   - No exception crosses the ABI.  Every call returns an h2ulv_status;
+ *     h2ulv_last_error() gives a thread-local message for the last failure.
+ *   - Argument errors are detected before any device work is issued.
+ *   - A factor is used by one stream at a time; distinct factors are
+ *     independent.  The factor owns all of its device memory.
+ */
+#ifndef H2ULV_H
+#define H2ULV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  H2ULV_OK = 0,
+  H2ULV_ERR_INVALID_ARG = -1,      /* bad size, pointer, parameter or NaN input */
+  H2ULV_ERR_OOM = -2,              /* device or host allocation failed */
+  H2ULV_ERR_HIP = -3,              /* a HIP runtime call failed */
+  H2ULV_ERR_SINGULAR = -4,         /* zero or non-finite pivot in a block LU */
+  H2ULV_ERR_DUPLICATE_POINTS = -5, /* two distinct points coincide (r = 0) */
+  H2ULV_ERR_NOT_CONVERGED = -6     /* refinement did not reach the tolerance */
+} h2ulv_status;
+
+enum { H2ULV_LAPLACE = 0, H2ULV_YUKAWA = 1 };
+enum { H2ULV_FP64 = 0, H2ULV_MIXED = 1 };
+
+/*
+ * Problem and accuracy parameters (the paper's problem statement: points and a
+ * kernel, Sec. IV and V; admissibility, Sec. I; leaf size, Sec. IV-C; rank /
+ * tolerance of the shared bases, Sec. II-A).
+ */
+typedef struct h2ulv_params {
+  int32_t struct_size; /* sizeof(h2ulv_params); set by h2ulv_params_default */
+  int32_t kernel;      /* H2ULV_LAPLACE: 1/r; H2ULV_YUKAWA: exp(-alpha r)/r    */
+  double alpha;        /* Yukawa decay constant                                 */
+  double diag;         /* A_ii                                                  */
+  double eta;          /* admissible iff |c_i - c_j| > eta (r_i + r_j); >= 0    */
+  int32_t leaf_size;   /* max points per leaf; >= 2                             */
+  int32_t rank_cap;    /* 0 = no cap, else k <= rank_cap                        */
+  double tol;          /* basis tolerance: keep pivots with |R_tt| > tol |R_00| */
+  int32_t far_sample;  /* 0 = exact far field; s > 0 = s samples per ancestor
+                          far box (own-level far boxes use all candidate rows) */
+  int32_t precision;   /* H2ULV_FP64 or H2ULV_MIXED (fp32 products, fp64 QR/LU) */
+  int32_t verbose;     /* 0 = silent; 1 = per-level timing on stderr            */
+  int32_t reserved;
+} h2ulv_params;
+
+typedef struct h2ulv_factor h2ulv_factor; /* opaque */
+
+/* Per-factor statistics (host).  Flops are the algorithmic count of the
+ * paper's steps from the actual ranks (LU 2/3 n^3, GEMM 2mnk, QR 2mn^2-2/3n^3),
+ * not the instructions the GPU issued. */
+typedef struct h2ulv_stats {
+  int32_t levels;          /* L: leaves are at level L, root at 0          */
+  int32_t max_rank;        /* max k over all boxes and levels              */
+  int32_t root_size;       /* size of the dense root block                 */
+  int32_t reserved;
+  int64_t n;               /* number of points                             */
+  double flops_fill;       /* fill-in LU, solves and products              */
+  double flops_basis;      /* QR / ID / orthogonal complement              */
+  double flops_couple;     /* low-rank couplings T K T^T                   */
+  double flops_rotate;     /* U^T D U                                      */
+  double flops_elim;       /* RR LU, triangular solves, Schur update       */
+  double flops_root;       /* root LU                                      */
+  double kernel_evals;     /* kernel entries generated                     */
+  double time_setup_s;     /* host tree/list construction                  */
+  double time_factor_s;    /* wall time of h2ulv_factorize                 */
+  double device_bytes;     /* peak device memory held by the factor        */
+  double logabsdet;        /* log|det A~| = sum log|diag U^RR| + log|det D_root| */
+} h2ulv_stats;
+
+/* Fill *p with the defaults: Laplace, diag 1e3, eta 1, leaf 256, tol 1e-8, no
+ * cap, far_sample 32, FP64.  Returns INVALID_ARG if p is NULL. */
+h2ulv_status h2ulv_params_default(h2ulv_params* p);
+
+/*
+ * Factorize A = [K(x_i, x_j)] (A_ii = diag) for n points.
+ *   pts     device, n x 3 row-major (x0 y0 z0 x1 ...); read only; caller owns.
+ *   n       number of points, >= 1.
+ *   params  host; copied.
+ *   stream  hipStream_t.
+ *   out     host; receives a new factor (free with h2ulv_destroy).
+ * The call copies the points to the host to build the cluster tree and the
+ * near/far lists (Sec. III-D), then runs every level of the sweep on the GPU.
+ * It synchronises the stream once per level to read back the ranks.
+ * Errors: INVALID_ARG (n < 1, NULL pointer, bad params, non-finite point),
+ * DUPLICATE_POINTS, SINGULAR, OOM, HIP.  On error *out is NULL.
+ */
+h2ulv_status h2ulv_factorize(const double* pts, int64_t n, const h2ulv_params* params,
+                             void* stream, h2ulv_factor** out);
+
+/*
+ * Factorize several independent problems with one launch per kernel and level:
+ * levels are aligned by height above the leaves, so the boxes of every problem
+ * at the same height share the same batched launches (the box independence of
+ * Sec. II-B / III-D, extended across problems).
+ *   nprob   number of problems, >= 1.
+ *   pts     host array of nprob device pointers (n[p] x 3 row-major each).
+ *   n       host array of nprob sizes.
+ *   params  host; one set shared by all problems.
+ *   out     host array of nprob factor handles.
+ * Results are identical to nprob separate h2ulv_factorize calls.
+ */
+h2ulv_status h2ulv_factorize_batch(int32_t nprob, const double* const* pts, const int64_t* n,
+                                   const h2ulv_params* params, void* stream,
+                                   h2ulv_factor** out);
+
+/*
+ * Solve A~ x = b in place (Sec. II-B three-step solve, level by level).
+ *   b     device, n x nrhs column-major with leading dimension ldb >= n;
+ *         on entry the right-hand sides, on exit the solutions.
+ * Errors: INVALID_ARG (NULL, nrhs < 1, ldb < n), HIP.
+ */
+h2ulv_status h2ulv_solve(const h2ulv_factor* f, double* b, int32_t nrhs, int64_t ldb,
+                         void* stream);
+
+/*
+ * y = A x with the exact kernel matrix generated on the fly in float64
+ * (A_ii = diag; used for residuals).  x, y device, n x nrhs column-major.
+ */
+h2ulv_status h2ulv_matvec_exact(const h2ulv_factor* f, const double* x, int64_t ldx,
+                                double* y, int64_t ldy, int32_t nrhs, void* stream);
+
+/*
+ * Iterative refinement with the exact float64 matvec:
+ *   x = solve(b); repeat r = b - A x; stop when max_c |r_c| / |b_c| <= rtol,
+ *   else x += solve(r); at most max_iter corrections.
+ *   b     device, read only; x device, receives the solution.
+ *   iters host (may be NULL): number of corrections applied.
+ *   relres host (may be NULL): final max relative residual.
+ * Synchronises the stream once per iteration.
+ * Errors: INVALID_ARG, NOT_CONVERGED (x holds the last iterate), HIP, OOM.
+ */
+h2ulv_status h2ulv_refine(const h2ulv_factor* f, const double* b, int64_t ldb, double* x,
+                          int64_t ldx, int32_t nrhs, double rtol, int32_t max_iter,
+                          int32_t* iters, double* relres, void* stream);
+
+/* Statistics of a factor (host).  Synchronises nothing. */
+h2ulv_status h2ulv_get_stats(const h2ulv_factor* f, h2ulv_stats* s);
+
+/*
+ * Inspection of a factor, for checking it against an independent
+ * implementation.  All arrays are host memory provided by the caller.
+ *   h2ulv_get_levels: *L = number of levels (leaves at level L).
+ *   h2ulv_get_perm:   perm[n]: tree position -> original point index.
+ *   h2ulv_get_ranks:  for level `lev` (1..L): m[2^lev], k[2^lev] (either may be NULL).
+ *   h2ulv_get_skeleton: for box `box` of level `lev`: the k skeleton point
+ *                       indices (original numbering) in pivot order.
+ *   h2ulv_get_basis:  U (m x m column-major, [U^S U^R]) of a box; copies from
+ *                     the device and synchronises the stream.
+ */
+h2ulv_status h2ulv_get_levels(const h2ulv_factor* f, int32_t* L);
+h2ulv_status h2ulv_get_perm(const h2ulv_factor* f, int64_t* perm);
+h2ulv_status h2ulv_get_ranks(const h2ulv_factor* f, int32_t lev, int32_t* m, int32_t* k);
+h2ulv_status h2ulv_get_skeleton(const h2ulv_factor* f, int32_t lev, int32_t box, int64_t* sk);
+h2ulv_status h2ulv_get_basis(const h2ulv_factor* f, int32_t lev, int32_t box, double* U);
+
+void h2ulv_destroy(h2ulv_factor* f);
+
+/*
+ * Host-only structure (no GPU needed): cluster tree and near/far lists
+ * (Sec. I strong admissibility; Sec. III-D binary tree) built from host points.
+ *   h2ulv_structure_create: pts host n x 3 row-major.
+ *   h2ulv_structure_perm:   perm[n].
+ *   h2ulv_structure_lists:  for level lev, CSR arrays of the near and far lists:
+ *       near_ptr[2^lev + 1], near_idx[near_ptr[2^lev]] (sorted per row), same
+ *       for far.  Pass NULL index arrays to query only the row pointers.
+ *   h2ulv_structure_geometry: centre[2^lev * 3], radius[2^lev] of level lev.
+ */
+typedef struct h2ulv_structure h2ulv_structure;
+h2ulv_status h2ulv_structure_create(const double* pts, int64_t n, const h2ulv_params* params,
+                                    h2ulv_structure** out);
+h2ulv_status h2ulv_structure_levels(const h2ulv_structure* s, int32_t* L);
+h2ulv_status h2ulv_structure_perm(const h2ulv_structure* s, int64_t* perm);
+h2ulv_status h2ulv_structure_lists(const h2ulv_structure* s, int32_t lev, int64_t* near_ptr,
+                                   int32_t* near_idx, int64_t* far_ptr, int32_t* far_idx);
+h2ulv_status h2ulv_structure_geometry(const h2ulv_structure* s, int32_t lev, double* centre,
+                                      double* radius);
+void h2ulv_structure_destroy(h2ulv_structure* s);
+
+const char* h2ulv_status_string(h2ulv_status s);
+const char* h2ulv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H2ULV_H */

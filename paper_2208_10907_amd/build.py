@@ -1,0 +1,65 @@
+"""Build the HIP shared library libh2ulv.so in-tree (gfx950).
+
+    python -m paper_2208_10907_amd.build
+
+Every source is compiled with hipcc for gfx950; host-only geometry code is
+compiled without floating-point contraction so that the cluster tree and the
+admissibility decisions are reproducible.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+from pathlib import Path
+
+PKG = Path(__file__).resolve().parent
+CSRC = PKG / "csrc"
+OUT_DIR = PKG / "_lib"
+LIB = OUT_DIR / "libh2ulv.so"
+BUILD_DIR = PKG.parent / "_build"
+
+HIP_FLAGS = ["-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wno-unused-command-line-argument"]
+SOURCES = [
+    ("h2ulv_kernels.hip", []),
+    ("h2ulv_dense.cpp", ["-x", "hip"]),
+    ("h2ulv_api.cpp", ["-x", "hip"]),
+    ("h2ulv_tree.cpp", ["-x", "hip", "-ffp-contract=off"]),
+]
+
+
+def hipcc() -> str:
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("hipcc not found")
+
+
+def build(verbose: bool = False) -> Path:
+    BUILD_DIR.mkdir(exist_ok=True)
+    OUT_DIR.mkdir(exist_ok=True)
+    cc = hipcc()
+    objs = []
+    for src, extra in SOURCES:
+        obj = BUILD_DIR / (src.replace(".", "_") + ".o")
+        cmd = [cc, *HIP_FLAGS, *extra, "-c", str(CSRC / src), "-o", str(obj)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
+        objs.append(str(obj))
+    tmp = OUT_DIR / "libh2ulv.so.tmp"
+    cmd = [cc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", str(tmp)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,217 @@
+// Host-side batching helpers: device buffers, staged uploads and the batched
+// launch builders used by the level driver (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "h2ulv_internal.h"
+#include "h2ulv_kernels.h"
+
+namespace h2ulv {
+
+#define H2ULV_HIP(x)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (x);                                                                  \
+    if (e_ != hipSuccess) fail(H2ULV_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Device-memory accounting shared by every buffer of the process.
+struct MemStats {
+  size_t live = 0, peak = 0;
+};
+MemStats& mem_stats();
+
+// Owning device buffer (hipMalloc / hipFree).
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  explicit DBuf(size_t b) { alloc(b); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      reset();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  void alloc(size_t b) {
+    reset();
+    if (b == 0) return;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      fail(H2ULV_ERR_OOM, "device allocation of " + std::to_string(b) + " bytes failed");
+    }
+    bytes = b;
+    MemStats& ms = mem_stats();
+    ms.live += b;
+    ms.peak = std::max(ms.peak, ms.live);
+  }
+  void reset() {
+    if (p) {
+      (void)hipFree(p);
+      mem_stats().live -= bytes;
+    }
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// Uploads and scratch buffers that must live until the stream is synchronised.
+struct Stage {
+  hipStream_t s = nullptr;
+  std::vector<DBuf> bufs;
+  std::vector<std::shared_ptr<void>> host;
+  explicit Stage(hipStream_t st) : s(st) {}
+  template <class T>
+  T* up(std::vector<T>&& v) {
+    if (v.empty()) return nullptr;
+    auto hv = std::make_shared<std::vector<T>>(std::move(v));
+    DBuf b(hv->size() * sizeof(T));
+    H2ULV_HIP(hipMemcpyAsync(b.p, hv->data(), hv->size() * sizeof(T), hipMemcpyHostToDevice, s));
+    host.push_back(hv);
+    bufs.push_back(std::move(b));
+    return bufs.back().as<T>();
+  }
+  template <class T>
+  T* up(const std::vector<T>& v) {
+    return up(std::vector<T>(v));
+  }
+  template <class T>
+  T* scratch(size_t count, bool zero = false) {
+    if (count == 0) return nullptr;
+    DBuf b(count * sizeof(T));
+    if (zero) H2ULV_HIP(hipMemsetAsync(b.p, 0, count * sizeof(T), s));
+    bufs.push_back(std::move(b));
+    return bufs.back().as<T>();
+  }
+  void sync() {
+    H2ULV_HIP(hipStreamSynchronize(s));
+    bufs.clear();
+    host.clear();
+  }
+};
+
+inline int64_t tiles64(int64_t m, int64_t n) { return ((m + 63) / 64) * ((n + 63) / 64); }
+
+template <typename T>
+struct GemmBatch {
+  std::vector<GemmItem<T>> items;
+  std::vector<GemmTerm<T>> terms;
+  void item(T* C, int64_t ldc, int M, int N, double alpha = 1.0, double beta = 0.0) {
+    GemmItem<T> it;
+    it.C = C;
+    it.ldc = ldc;
+    it.M = M;
+    it.N = N;
+    it.t0 = (int32_t)terms.size();
+    it.nt = 0;
+    it.alpha = alpha;
+    it.beta = beta;
+    items.push_back(it);
+  }
+  void term(const T* A, int64_t lda, bool ta, const T* B, int64_t ldb, bool tb, int K) {
+    GemmTerm<T> t;
+    t.A = A;
+    t.B = B;
+    t.lda = lda;
+    t.ldb = ldb;
+    t.K = K;
+    t.flags = (ta ? 1 : 0) | (tb ? 2 : 0);
+    terms.push_back(t);
+    items.back().nt++;
+  }
+  // C = alpha op(A) op(B) + beta C
+  void one(T* C, int64_t ldc, int M, int N, int K, const T* A, int64_t lda, bool ta, const T* B,
+           int64_t ldb, bool tb, double alpha = 1.0, double beta = 0.0) {
+    item(C, ldc, M, N, alpha, beta);
+    term(A, lda, ta, B, ldb, tb, K);
+  }
+  bool empty() const { return items.empty(); }
+  void run(Stage& st) {
+    std::vector<GemmItem<T>> its;
+    its.reserve(items.size());
+    for (auto& it : items)
+      if (it.M > 0 && it.N > 0) its.push_back(it);
+    items.clear();
+    if (its.empty()) {
+      terms.clear();
+      return;
+    }
+    std::vector<int64_t> tp(its.size() + 1, 0);
+    for (size_t i = 0; i < its.size(); ++i) tp[i + 1] = tp[i] + tiles64(its[i].M, its[i].N);
+    int64_t nt = tp.back();
+    int ni = (int)its.size();
+    auto* di = st.up(std::move(its));
+    auto* dt = st.up(std::move(terms));
+    auto* dp = st.up(std::move(tp));
+    terms.clear();
+    launch_gemm<T>(di, dt, dp, nt, ni, st.s);
+    H2ULV_HIP(hipGetLastError());
+  }
+};
+
+struct KgenBatch {
+  std::vector<KgenItem> items;
+  void add(const int64_t* rows, int m, const int64_t* cols, int n, double* out, int64_t ld) {
+    if (m <= 0 || n <= 0) return;
+    items.push_back(KgenItem{rows, cols, out, ld, m, n});
+  }
+  void run(Stage& st, const double* pts, const KernelFn& kf, int* dup) {
+    if (items.empty()) return;
+    std::vector<int64_t> tp(items.size() + 1, 0);
+    for (size_t i = 0; i < items.size(); ++i) tp[i + 1] = tp[i] + tiles64(items[i].m, items[i].n);
+    int64_t nt = tp.back();
+    int ni = (int)items.size();
+    auto* di = st.up(std::move(items));
+    auto* dp = st.up(std::move(tp));
+    items.clear();
+    launch_kgen(di, dp, nt, ni, pts, kf, dup, st.s);
+    H2ULV_HIP(hipGetLastError());
+  }
+};
+
+struct CopyBatch {
+  std::vector<CopyItem> items;
+  void add(const double* src, int64_t lds, double* dst, int64_t ldd, int rows, int cols,
+           bool trans = false) {
+    if (rows <= 0 || cols <= 0) return;
+    items.push_back(CopyItem{src, dst, lds, ldd, rows, cols, trans ? 1 : 0, 0});
+  }
+  void run(Stage& st, double alpha = 1.0, double beta = 0.0) {
+    if (items.empty()) return;
+    std::vector<int64_t> tp(items.size() + 1, 0);
+    for (size_t i = 0; i < items.size(); ++i)
+      tp[i + 1] = tp[i] + tiles64(items[i].rows, items[i].cols);
+    int64_t nt = tp.back();
+    int ni = (int)items.size();
+    auto* di = st.up(std::move(items));
+    auto* dp = st.up(std::move(tp));
+    items.clear();
+    launch_copy(di, dp, nt, ni, alpha, beta, st.s);
+    H2ULV_HIP(hipGetLastError());
+  }
+};
+
+}  // namespace h2ulv

@@ -1,0 +1,345 @@
+// Batched dense building blocks of the sweep, each a short sequence of batched
+// launches whose O(m^3) part runs in the grouped MFMA GEMM:
+//   * blocked LU with partial pivoting and the inverse from it (Sec. II-B,
+//     Eq. lu; the paper's GETRF/TRSM pair of Sec. III-D);
+//   * triangular solves by diagonal blocks (inverted nb x nb blocks + GEMM);
+//   * blocked Householder QR of the row-ID matrix W and the explicit
+//     orthogonal factor U = [U^S U^R] (Sec. II-A: the skeleton and redundant
+//     parts of the shared basis; LAPACK dgeqrf/dlarft/dorgqr conventions).
+#include "h2ulv_dense.h"
+
+#include <algorithm>
+
+namespace h2ulv {
+
+MemStats& mem_stats() {
+  static MemStats ms;
+  return ms;
+}
+
+static constexpr int LU_NB = 64;   // LU panel / triangular block width
+static constexpr int QR_NB = 32;   // Householder panel width
+
+// X = L^-1 B (L unit lower) by blocks of LU_NB rows; B is overwritten.
+void trsm_lower_unit(Stage& st, const std::vector<TriRhs>& sys) {
+  if (sys.empty()) return;
+  const int nb = LU_NB;
+  int maxm = 0;
+  std::vector<MatDesc> ds;
+  std::vector<int64_t> bp(1, 0), off;
+  int64_t tot = 0;
+  for (auto& t : sys) {
+    MatDesc d{};
+    d.A = const_cast<double*>(t.T);
+    d.lda = t.ldt;
+    d.m = t.m;
+    d.n = t.m;
+    ds.push_back(d);
+    int nbk = (t.m + nb - 1) / nb;
+    bp.push_back(bp.back() + nbk);
+    off.push_back(tot);
+    tot += (int64_t)nbk * nb * nb;
+    maxm = std::max(maxm, t.m);
+  }
+  double* inv = st.scratch<double>(tot);
+  int nmat = (int)sys.size();
+  int64_t nblk = bp.back();
+  MatDesc* dd = st.up(std::move(ds));
+  int64_t* dbp = st.up(std::move(bp));
+  std::vector<int64_t> offc = off;
+  int64_t* doff = st.up(std::move(offc));
+  launch_trinv_diag(dd, dbp, nblk, nmat, nb, 0, inv, doff, st.s);
+  H2ULV_HIP(hipGetLastError());
+  for (int o = 0; o < maxm; o += nb) {
+    GemmBatch<double> g1, g2;
+    for (size_t b = 0; b < sys.size(); ++b) {
+      const TriRhs& t = sys[b];
+      if (t.m <= o || t.ncols <= 0) continue;
+      int w = std::min(nb, t.m - o);
+      const double* blk = inv + off[b] + (int64_t)(o / nb) * nb * nb;
+      g1.one(t.X + o, t.ldx, w, t.ncols, w, blk, nb, false, t.B + o, t.ldb, false);
+      int rest = t.m - o - w;
+      if (rest > 0)
+        g2.one(t.B + o + w, t.ldb, rest, t.ncols, w, t.T + (o + w) + (int64_t)o * t.ldt, t.ldt,
+               false, t.X + o, t.ldx, false, -1.0, 1.0);
+    }
+    g1.run(st);
+    g2.run(st);
+  }
+}
+
+// X = U^-1 B (U upper with diagonal) by blocks from the bottom; B is overwritten.
+void trsm_upper(Stage& st, const std::vector<TriRhs>& sys) {
+  if (sys.empty()) return;
+  const int nb = LU_NB;
+  int maxblk = 0;
+  std::vector<MatDesc> ds;
+  std::vector<int64_t> bp(1, 0), off;
+  int64_t tot = 0;
+  for (auto& t : sys) {
+    MatDesc d{};
+    d.A = const_cast<double*>(t.T);
+    d.lda = t.ldt;
+    d.m = t.m;
+    d.n = t.m;
+    ds.push_back(d);
+    int nbk = (t.m + nb - 1) / nb;
+    bp.push_back(bp.back() + nbk);
+    off.push_back(tot);
+    tot += (int64_t)nbk * nb * nb;
+    maxblk = std::max(maxblk, nbk);
+  }
+  double* inv = st.scratch<double>(tot);
+  int nmat = (int)sys.size();
+  int64_t nblk = bp.back();
+  MatDesc* dd = st.up(std::move(ds));
+  int64_t* dbp = st.up(std::move(bp));
+  std::vector<int64_t> offc = off;
+  int64_t* doff = st.up(std::move(offc));
+  launch_trinv_diag(dd, dbp, nblk, nmat, nb, 1, inv, doff, st.s);
+  H2ULV_HIP(hipGetLastError());
+  for (int jb = maxblk - 1; jb >= 0; --jb) {
+    GemmBatch<double> g1, g2;
+    for (size_t b = 0; b < sys.size(); ++b) {
+      const TriRhs& t = sys[b];
+      int nbk = (t.m + nb - 1) / nb;
+      if (jb >= nbk || t.ncols <= 0) continue;
+      int o = jb * nb, w = std::min(nb, t.m - o);
+      const double* blk = inv + off[b] + (int64_t)jb * nb * nb;
+      g1.one(t.X + o, t.ldx, w, t.ncols, w, blk, nb, false, t.B + o, t.ldb, false);
+      if (o > 0)
+        g2.one(t.B, t.ldb, o, t.ncols, w, t.T + (int64_t)o * t.ldt, t.ldt, false, t.X + o, t.ldx,
+               false, -1.0, 1.0);
+    }
+    g1.run(st);
+    g2.run(st);
+  }
+}
+
+// In-place blocked LU with partial pivoting; returns device info (one int per
+// matrix, 0 = ok, j+1 = first zero/non-finite pivot column) and pivots.
+void batched_lu(Stage& st, const std::vector<SqMat>& mats, int32_t* ipiv, int32_t* info,
+                const std::vector<int64_t>& ipiv_off) {
+  if (mats.empty()) return;
+  const int nb = LU_NB;
+  int maxm = 0;
+  std::vector<MatDesc> ds;
+  for (size_t b = 0; b < mats.size(); ++b) {
+    MatDesc d{};
+    d.A = mats[b].A;
+    d.lda = mats[b].lda;
+    d.m = mats[b].m;
+    d.n = mats[b].m;
+    d.ipiv = ipiv + ipiv_off[b];
+    d.info = info + b;
+    ds.push_back(d);
+    maxm = std::max(maxm, mats[b].m);
+  }
+  const int nmat = (int)mats.size();
+  MatDesc* dd = st.up(std::move(ds));
+  for (int j0 = 0; j0 < maxm; j0 += nb) {
+    launch_lu_panel(dd, nmat, j0, nb, st.s);
+    H2ULV_HIP(hipGetLastError());
+    std::vector<int64_t> sp(1, 0);
+    for (auto& mt : mats) sp.push_back(sp.back() + (mt.m > j0 ? (mt.m + 63) / 64 : 0));
+    int64_t ns = sp.back();
+    int64_t* dsp = st.up(std::move(sp));
+    launch_lu_swap_trsm(dd, dsp, ns, nmat, j0, nb, st.s);
+    H2ULV_HIP(hipGetLastError());
+    GemmBatch<double> g;
+    for (auto& mt : mats) {
+      if (mt.m <= j0) continue;
+      int w = std::min(nb, mt.m - j0);
+      int rest = mt.m - j0 - w;
+      if (rest <= 0) continue;
+      double* A = mt.A;
+      int64_t lda = mt.lda;
+      g.one(A + (j0 + w) + (int64_t)(j0 + w) * lda, lda, rest, rest, w,
+            A + (j0 + w) + (int64_t)j0 * lda, lda, false, A + j0 + (int64_t)(j0 + w) * lda, lda,
+            false, -1.0, 1.0);
+    }
+    g.run(st);
+  }
+}
+
+// Inverse of each matrix (A overwritten by its LU factors).  Pivots and info are
+// returned in device arrays allocated on the stage; *info_out receives them.
+void batched_inverse(Stage& st, const std::vector<SqMat>& mats, int32_t** info_out,
+                     int32_t** ipiv_out, std::vector<int64_t>* ipiv_off_out) {
+  *info_out = nullptr;
+  if (mats.empty()) return;
+  std::vector<int64_t> ipo;
+  int64_t tot = 0, totsq = 0;
+  for (auto& m : mats) {
+    ipo.push_back(tot);
+    tot += m.m;
+    totsq += (int64_t)m.m * m.m;
+  }
+  int32_t* ipiv = st.scratch<int32_t>(std::max<int64_t>(tot, 1));
+  int32_t* info = st.scratch<int32_t>(mats.size(), true);
+  batched_lu(st, mats, ipiv, info, ipo);
+  // B = P^T I, then X = L^-1 B, then inv = U^-1 X
+  double* B = st.scratch<double>(std::max<int64_t>(totsq, 1));
+  double* X = st.scratch<double>(std::max<int64_t>(totsq, 1));
+  std::vector<PermItem> pis;
+  std::vector<int64_t> sp(1, 0);
+  std::vector<int64_t> boff;
+  int64_t o = 0;
+  for (size_t b = 0; b < mats.size(); ++b) {
+    boff.push_back(o);
+    pis.push_back(PermItem{ipiv + ipo[b], B + o, mats[b].m, mats[b].m, 0});
+    sp.push_back(sp.back() + (mats[b].m + 63) / 64);
+    o += (int64_t)mats[b].m * mats[b].m;
+  }
+  int64_t ns = sp.back();
+  int np = (int)pis.size();
+  PermItem* dpi = st.up(std::move(pis));
+  int64_t* dsp = st.up(std::move(sp));
+  launch_perm_matrix(dpi, dsp, ns, np, st.s);
+  H2ULV_HIP(hipGetLastError());
+  std::vector<TriRhs> lo, up;
+  for (size_t b = 0; b < mats.size(); ++b) {
+    const SqMat& m = mats[b];
+    lo.push_back(TriRhs{m.A, m.lda, m.m, B + boff[b], m.m, X + boff[b], m.m, m.m});
+    up.push_back(TriRhs{m.A, m.lda, m.m, X + boff[b], m.m, m.inv, m.ldinv, m.m});
+  }
+  trsm_lower_unit(st, lo);
+  trsm_upper(st, up);
+  *info_out = info;
+  if (ipiv_out) *ipiv_out = ipiv;
+  if (ipiv_off_out) *ipiv_off_out = ipo;
+}
+
+// Inverse of upper-triangular matrices (T factors of the bases).
+void batched_triu_inverse(Stage& st, const std::vector<SqMat>& mats) {
+  if (mats.empty()) return;
+  int64_t totsq = 0;
+  for (auto& m : mats) totsq += (int64_t)m.m * m.m;
+  double* B = st.scratch<double>(std::max<int64_t>(totsq, 1));
+  std::vector<PermItem> pis;
+  std::vector<int64_t> sp(1, 0), boff;
+  int64_t o = 0;
+  for (auto& m : mats) {
+    boff.push_back(o);
+    pis.push_back(PermItem{nullptr, B + o, m.m, m.m, 0});
+    sp.push_back(sp.back() + (m.m + 63) / 64);
+    o += (int64_t)m.m * m.m;
+  }
+  int64_t ns = sp.back();
+  int np = (int)pis.size();
+  PermItem* dpi = st.up(std::move(pis));
+  int64_t* dsp = st.up(std::move(sp));
+  launch_perm_matrix(dpi, dsp, ns, np, st.s);
+  H2ULV_HIP(hipGetLastError());
+  std::vector<TriRhs> up;
+  for (size_t b = 0; b < mats.size(); ++b) {
+    const SqMat& m = mats[b];
+    up.push_back(TriRhs{m.A, m.lda, m.m, B + boff[b], m.m, m.inv, m.ldinv, m.m});
+  }
+  trsm_upper(st, up);
+}
+
+// Householder QR of W (m x k, overwritten), explicit U (m x m) and T = R(1:k,1:k).
+void batched_qr_basis(Stage& st, const std::vector<QrW>& ws) {
+  if (ws.empty()) return;
+  const int nb = QR_NB;
+  int maxk = 0;
+  std::vector<MatDesc> ds;
+  std::vector<double*> Vb, Tfb, Y1b, Y2b;
+  for (auto& w : ws) {
+    int np = (w.k + nb - 1) / nb;
+    MatDesc d{};
+    d.A = w.W;
+    d.lda = w.m;
+    d.m = w.m;
+    d.n = w.k;
+    d.V = st.scratch<double>(std::max<int64_t>((int64_t)w.m * w.k, 1));
+    d.aux = st.scratch<double>(std::max(w.k, 1));
+    d.Tf = st.scratch<double>(std::max<int64_t>((int64_t)np * nb * nb, 1));
+    Vb.push_back(d.V);
+    Tfb.push_back(d.Tf);
+    int64_t wmax = std::max(w.m, w.k);
+    Y1b.push_back(st.scratch<double>(std::max<int64_t>((int64_t)nb * wmax, 1)));
+    Y2b.push_back(st.scratch<double>(std::max<int64_t>((int64_t)nb * wmax, 1)));
+    ds.push_back(d);
+    maxk = std::max(maxk, std::min(w.k, w.m));
+  }
+  const int nmat = (int)ws.size();
+  MatDesc* dd = st.up(std::move(ds));
+  for (int j0 = 0; j0 < maxk; j0 += nb) {
+    launch_qr_panel(dd, nmat, j0, nb, st.s);
+    H2ULV_HIP(hipGetLastError());
+    GemmBatch<double> g1, g2, g3;
+    for (size_t b = 0; b < ws.size(); ++b) {
+      const QrW& w = ws[b];
+      int kk = std::min(w.k, w.m);
+      if (kk <= j0) continue;
+      int wd = std::min(nb, kk - j0);
+      int ntr = w.k - j0 - wd;
+      if (ntr <= 0) continue;
+      int rows = w.m - j0;
+      const double* Vp = Vb[b] + (int64_t)j0 * w.m + j0;
+      const double* Tp = Tfb[b] + (int64_t)(j0 / nb) * nb * nb;
+      double* At = w.W + j0 + (int64_t)(j0 + wd) * w.m;
+      g1.one(Y1b[b], nb, wd, ntr, rows, Vp, w.m, true, At, w.m, false);
+      g2.one(Y2b[b], nb, wd, ntr, wd, Tp, nb, true, Y1b[b], nb, false);
+      g3.one(At, w.m, rows, ntr, wd, Vp, w.m, false, Y2b[b], nb, false, -1.0, 1.0);
+    }
+    g1.run(st);
+    g2.run(st);
+    g3.run(st);
+  }
+  // T = upper triangle of the factored W
+  {
+    CopyBatch cb;
+    std::vector<CopyItem> zl;
+    for (auto& w : ws) {
+      if (w.k <= 0) continue;
+      cb.add(w.W, w.m, w.T, w.k, w.k, w.k);
+      zl.push_back(CopyItem{nullptr, w.T, 0, w.k, w.k, w.k, 0, 0});
+    }
+    cb.run(st);
+    int nz = (int)zl.size();
+    CopyItem* dz = st.up(std::move(zl));
+    launch_zero_lower(dz, nz, st.s);
+    H2ULV_HIP(hipGetLastError());
+  }
+  // U = H_0 H_1 ... H_{k-1}, applied to the identity from the last panel back
+  {
+    std::vector<PermItem> pis;
+    std::vector<int64_t> sp(1, 0);
+    for (auto& w : ws) {
+      pis.push_back(PermItem{nullptr, w.U, w.m, w.m, 0});
+      sp.push_back(sp.back() + (w.m + 63) / 64);
+    }
+    int64_t ns = sp.back();
+    int np = (int)pis.size();
+    PermItem* dpi = st.up(std::move(pis));
+    int64_t* dsp = st.up(std::move(sp));
+    launch_perm_matrix(dpi, dsp, ns, np, st.s);
+    H2ULV_HIP(hipGetLastError());
+  }
+  int maxp = (maxk + nb - 1) / nb;
+  for (int p = maxp - 1; p >= 0; --p) {
+    int j0 = p * nb;
+    GemmBatch<double> g1, g2, g3;
+    for (size_t b = 0; b < ws.size(); ++b) {
+      const QrW& w = ws[b];
+      int kk = std::min(w.k, w.m);
+      if (kk <= j0) continue;
+      int wd = std::min(nb, kk - j0);
+      int rows = w.m - j0;
+      const double* Vp = Vb[b] + (int64_t)j0 * w.m + j0;
+      const double* Tp = Tfb[b] + (int64_t)p * nb * nb;
+      double* Us = w.U + j0 + (int64_t)j0 * w.m;
+      g1.one(Y1b[b], nb, wd, rows, rows, Vp, w.m, true, Us, w.m, false);
+      g2.one(Y2b[b], nb, wd, rows, wd, Tp, nb, false, Y1b[b], nb, false);
+      g3.one(Us, w.m, rows, rows, wd, Vp, w.m, false, Y2b[b], nb, false, -1.0, 1.0);
+    }
+    g1.run(st);
+    g2.run(st);
+    g3.run(st);
+  }
+}
+
+}  // namespace h2ulv

@@ -1,0 +1,144 @@
+// Device-kernel descriptors and launchers of the H^2-ULV library (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace h2ulv {
+
+struct KernelFn {
+  int kind;      // 0 Laplace 1/r, 1 Yukawa exp(-alpha r)/r
+  double alpha;
+  double diag;   // value where row point == column point
+};
+
+// out[a + b*ld] = K(x[rows[a]], x[cols[b]])   (a < m, b < n)
+struct KgenItem {
+  const int64_t* rows;
+  const int64_t* cols;
+  double* out;
+  int64_t ld;
+  int32_t m, n;
+};
+
+// C = beta C + alpha * sum_t op(A_t) op(B_t); op(A) is M x K, op(B) is K x N.
+template <typename T>
+struct GemmItem {
+  T* C;
+  int64_t ldc;
+  int32_t M, N;
+  int32_t t0, nt;  // term range in the term table
+  double alpha, beta;
+};
+template <typename T>
+struct GemmTerm {
+  const T* A;
+  const T* B;
+  int64_t lda, ldb;
+  int32_t K;
+  int32_t flags;  // bit0: op(A) = A^T, bit1: op(B) = B^T
+};
+
+// One square (or tall, for QR) matrix per box for the factorization kernels.
+struct MatDesc {
+  double* A;
+  int64_t lda;
+  int32_t m;      // rows
+  int32_t n;      // columns
+  int32_t* ipiv;  // LU pivots (m entries), or QR pivots / work
+  double* aux;    // QR: tau (n) ; LU: unused
+  double* V;      // QR: explicit reflector block (ld = m), panel columns
+  double* Tf;     // QR: block-reflector T factors, nb x nb per panel
+  int32_t* info;  // per-matrix flag (singular / status)
+};
+
+// Generic batched 2-D copy: dst[i + j*ldd] = alpha * src(i, j) (+ beta dst)
+// src(i, j) = src[i + j*lds] or src[j + i*lds] when trans.
+struct CopyItem {
+  const double* src;
+  double* dst;
+  int64_t lds, ldd;
+  int32_t rows, cols;
+  int32_t trans;
+  int32_t pad;
+};
+
+// Column-pivoted QR with exact norms of one matrix (row interpolative decomposition).
+struct PivQrItem {
+  double* A;        // m x n, overwritten by R (upper part)
+  int64_t lda;
+  int32_t m, n;     // the pivoted QR acts on the n columns of this m x n matrix
+  int32_t* piv;     // out: n column pivots
+  int32_t* kout;    // out: rank
+  double* diag;     // out: |R_tt| for t < min(m,n) (0 beyond the last step)
+  double* work;     // n doubles: column norms
+  double tol;
+  int32_t cap;      // effective cap (>= 1), min(m, n, cap)
+  int32_t pad;
+};
+
+// Tall QR by row-chunk folding: X is m x n (column-major, ld ldx); the
+// triangular factor of X^T is written transposed into RT (m x m, ld m).
+struct FoldItem {
+  const double* X;
+  int64_t ldx;
+  int32_t m;
+  int32_t pad;
+  int64_t n;
+  double* RT;
+};
+
+// Dense P^T from LU interchanges (ipiv == nullptr gives the identity).
+struct PermItem {
+  const int32_t* ipiv;
+  double* out;
+  int64_t ld;
+  int32_t m;
+  int32_t pad;
+};
+
+// Row-ID matrix W' from pivots and E = R11^-1 R12.
+struct WpItem {
+  const int32_t* piv;
+  const double* E;  // E(t, s) at E[t + s * ldE] for s >= k
+  double* W;        // m x k, ld ldW
+  int64_t ldE, ldW;
+  int32_t m, k;
+};
+
+// Launchers (all asynchronous on `s`).  Device descriptor arrays must be
+// resident on the device.
+void launch_kgen(const KgenItem* items, const int64_t* tile_ptr, int64_t ntiles, int nitems,
+                 const double* pts, KernelFn kf, int* dup_flag, hipStream_t s);
+template <typename T>
+void launch_gemm(const GemmItem<T>* items, const GemmTerm<T>* terms, const int64_t* tile_ptr,
+                 int64_t ntiles, int nitems, hipStream_t s);
+void launch_lu_panel(const MatDesc* d, int nmat, int j0, int nb, hipStream_t s);
+void launch_lu_swap_trsm(const MatDesc* d, const int64_t* slab_ptr, int64_t nslabs, int nmat,
+                         int j0, int nb, hipStream_t s);
+void launch_trinv_diag(const MatDesc* d, const int64_t* blk_ptr, int64_t nblk, int nmat, int nb,
+                       int upper, double* out, const int64_t* out_off, hipStream_t s);
+void launch_qr_panel(const MatDesc* d, int nmat, int j0, int nb, hipStream_t s);
+void launch_tsqr_fold(const FoldItem* items, int nitems, int max_m, hipStream_t s);
+void launch_pivqr(const PivQrItem* items, int nitems, hipStream_t s);
+void launch_copy(const CopyItem* items, const int64_t* tile_ptr, int64_t ntiles, int nitems,
+                 double alpha, double beta, hipStream_t s);
+void launch_perm_matrix(const PermItem* items, const int64_t* slab_ptr, int64_t nslabs,
+                        int nitems, hipStream_t s);
+void launch_wprime(const WpItem* items, int nitems, hipStream_t s);
+void launch_zero_lower(const CopyItem* items, int nitems, hipStream_t s);
+void launch_logdet(const MatDesc* d, int nmat, double* out, hipStream_t s);
+void launch_matvec(const double* pts, int64_t n, KernelFn kf, const double* x, int64_t ldx,
+                   double* y, int64_t ldy, int nrhs, hipStream_t s);
+void launch_convert_d2f(const double* src, float* dst, int64_t count, hipStream_t s);
+void launch_convert_f2d(const float* src, double* dst, int64_t count, hipStream_t s);
+void launch_resid_norms(const double* b, int64_t ldb, const double* ax, int64_t ldax, double* r,
+                        int64_t ldr, int64_t n, int nrhs, double* rnorm2, double* bnorm2,
+                        hipStream_t s);
+void launch_axpy_cols(double* x, int64_t ldx, const double* d, int64_t ldd, int64_t n, int nrhs,
+                      hipStream_t s);
+void launch_permute_rows(const double* src, int64_t lds, double* dst, int64_t ldd,
+                         const int64_t* perm, int64_t n, int nrhs, int inverse, hipStream_t s);
+
+}  // namespace h2ulv

@@ -1,0 +1,1056 @@
+// HIP kernels of the H^2-ULV sweep for CDNA4 (gfx950).
+//
+// Every kernel is batched: one launch covers every box (or block pair) of a
+// tree level, since the boxes of a level are independent of each other once
+// the fill-ins are inside the shared bases (Sec. III-C, III-D of the paper).
+// Descriptor tables live in device memory; tiles are mapped to items by a
+// binary search over a prefix-sum table so that uneven block sizes share one
+// launch.  All matrices are column-major.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "h2ulv_kernels.h"
+
+namespace h2ulv {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_item(const int64_t* ptr, int n, int64_t tile) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (ptr[mid] <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ double kernel_value(const KernelFn& kf, double r2) {
+  double r = sqrt(r2);
+  if (kf.kind == 0) return 1.0 / r;
+  return exp(-kf.alpha * r) / r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block-wide sum over 256 threads (4 waves); every thread gets the result.
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+  v = wave_sum(v);
+  int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = sh[0] + sh[1] + sh[2] + sh[3];
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel-matrix generation (dense near blocks, far-field samples, skeleton
+// couplings).  Tile 64 x 64, 256 threads; writes coalesced along rows.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void kgen_kernel(const KgenItem* __restrict__ items,
+                                                   const int64_t* __restrict__ tile_ptr,
+                                                   int nitems, const double* __restrict__ pts,
+                                                   KernelFn kf, int* dup_flag) {
+  int64_t tile = blockIdx.x;
+  int id = find_item(tile_ptr, nitems, tile);
+  KgenItem it = items[id];
+  int64_t local = tile - tile_ptr[id];
+  int tm = (it.m + 63) >> 6;
+  int ti = (int)(local % tm), tj = (int)(local / tm);
+  int a = ti * 64 + (threadIdx.x & 63);
+  int b0 = tj * 64 + (threadIdx.x >> 6);
+  if (a >= it.m) return;
+  int64_t ra = it.rows[a];
+  double xa = pts[3 * ra], ya = pts[3 * ra + 1], za = pts[3 * ra + 2];
+  bool dup = false;
+  for (int q = 0; q < 16; ++q) {
+    int b = b0 + 4 * q;
+    if (b >= it.n) break;
+    int64_t cb = it.cols[b];
+    double v;
+    if (cb == ra) {
+      v = kf.diag;
+    } else {
+      double dx = xa - pts[3 * cb], dy = ya - pts[3 * cb + 1], dz = za - pts[3 * cb + 2];
+      double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 == 0.0) {
+        dup = true;
+        v = 0.0;
+      } else {
+        v = kernel_value(kf, r2);
+      }
+    }
+    it.out[a + (int64_t)b * it.ld] = v;
+  }
+  if (dup) *dup_flag = 1;
+}
+
+void launch_kgen(const KgenItem* items, const int64_t* tile_ptr, int64_t ntiles, int nitems,
+                 const double* pts, KernelFn kf, int* dup_flag, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(kgen_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, items, tile_ptr,
+                     nitems, pts, kf, dup_flag);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped GEMM on the matrix cores.
+// C = beta C + alpha sum_t op(A_t) op(B_t) for a batch of items of any size.
+// Tile 64 x 64 x 16 per workgroup of 4 waves; each wave owns a 32 x 32 sub-tile
+// made of 2 x 2 MFMA 16x16x4 accumulators.  Operands are staged through LDS.
+// MFMA 16x16x4 operand layout (one value per lane): A(i, k) with i = lane % 16,
+// k = lane / 16; B(k, j) with j = lane % 16, k = lane / 16.  Accumulator element
+// r of lane l holds D(row, l % 16) with row = 4 r + l / 16 for the f64
+// instruction and row = 4 (l / 16) + r for the f32 one (checked on gfx950).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+  static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict__ items,
+                                                   const GemmTerm<T>* __restrict__ terms,
+                                                   const int64_t* __restrict__ tile_ptr,
+                                                   int nitems) {
+  typedef typename Mfma<T>::v4 v4;
+  __shared__ T As[16][68];
+  __shared__ T Bs[16][68];
+  int64_t tile = blockIdx.x;
+  int id = find_item(tile_ptr, nitems, tile);
+  const GemmItem<T> it = items[id];
+  int64_t local = tile - tile_ptr[id];
+  int tm = (it.M + 63) >> 6;
+  int row0 = (int)(local % tm) * 64, col0 = (int)(local / tm) * 64;
+  int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int wr = w & 1, wc = w >> 1;
+  v4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
+
+  for (int t = it.t0; t < it.t0 + it.nt; ++t) {
+    const GemmTerm<T> tt = terms[t];
+    const bool ta = tt.flags & 1, tb = tt.flags & 2;
+    for (int k0 = 0; k0 < tt.K; k0 += 16) {
+      if (!ta) {
+        int i = tid & 63, kb = tid >> 6;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int kk = kb + 4 * r, gi = row0 + i, gk = k0 + kk;
+          As[kk][i] = (gi < it.M && gk < tt.K) ? tt.A[gi + (int64_t)gk * tt.lda] : T(0);
+        }
+      } else {
+        int kk = tid & 15, ib = tid >> 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int i = ib + 16 * r, gi = row0 + i, gk = k0 + kk;
+          As[kk][i] = (gi < it.M && gk < tt.K) ? tt.A[gk + (int64_t)gi * tt.lda] : T(0);
+        }
+      }
+      if (!tb) {
+        int kk = tid & 15, jb = tid >> 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int j = jb + 16 * r, gj = col0 + j, gk = k0 + kk;
+          Bs[kk][j] = (gj < it.N && gk < tt.K) ? tt.B[gk + (int64_t)gj * tt.ldb] : T(0);
+        }
+      } else {
+        int j = tid & 63, kb = tid >> 6;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int kk = kb + 4 * r, gj = col0 + j, gk = k0 + kk;
+          Bs[kk][j] = (gj < it.N && gk < tt.K) ? tt.B[gj + (int64_t)gk * tt.ldb] : T(0);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        int kk = 4 * s + (lane >> 4);
+        T a0 = As[kk][32 * wr + (lane & 15)];
+        T a1 = As[kk][32 * wr + 16 + (lane & 15)];
+        T b0 = Bs[kk][32 * wc + (lane & 15)];
+        T b1 = Bs[kk][32 * wc + 16 + (lane & 15)];
+        acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+        acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+        acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+        acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+      }
+      __syncthreads();
+    }
+  }
+  const T alpha = (T)it.alpha, beta = (T)it.beta;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = row0 + 32 * wr + 16 * bi + Mfma<T>::row(lane, r);
+        int col = col0 + 32 * wc + 16 * bj + (lane & 15);
+        if (row < it.M && col < it.N) {
+          T v = alpha * acc[bi][bj][r];
+          T* c = it.C + row + (int64_t)col * it.ldc;
+          if (beta != T(0)) v += beta * (*c);
+          *c = v;
+        }
+      }
+}
+
+template <typename T>
+void launch_gemm(const GemmItem<T>* items, const GemmTerm<T>* terms, const int64_t* tile_ptr,
+                 int64_t ntiles, int nitems, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(gemm_kernel<T>, dim3((unsigned)ntiles), dim3(256), 0, s, items, terms,
+                     tile_ptr, nitems);
+}
+template void launch_gemm<double>(const GemmItem<double>*, const GemmTerm<double>*,
+                                  const int64_t*, int64_t, int, hipStream_t);
+template void launch_gemm<float>(const GemmItem<float>*, const GemmTerm<float>*, const int64_t*,
+                                 int64_t, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Blocked LU with partial pivoting (Sec. II-B Eq. lu: LU of S^RR; also the
+// diagonal blocks D_kk of the fill-in step, Sec. III-B, and the root).
+// Panel kernel: one workgroup per matrix factors columns [j0, j0+w) of rows
+// [j0, m): pivot = largest |a| (lowest row on ties), row swap inside the
+// panel, scaling and rank-1 updates of the panel.  Row swaps outside the panel,
+// the U12 triangular solve and the trailing GEMM are separate launches.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void lu_panel_kernel(const MatDesc* __restrict__ ds, int j0,
+                                                       int nb) {
+  __shared__ double red_v[256];
+  __shared__ int red_i[256];
+  const MatDesc d = ds[blockIdx.x];
+  const int m = d.m;
+  if (m <= j0) return;
+  const int w = min(nb, m - j0);
+  double* A = d.A;
+  const int64_t lda = d.lda;
+  const int tid = threadIdx.x;
+  for (int jj = 0; jj < w; ++jj) {
+    const int col = j0 + jj;
+    double best = -1.0;
+    int bi = m;
+    for (int r = col + tid; r < m; r += 256) {
+      double v = fabs(A[r + (int64_t)col * lda]);
+      if (v > best) {
+        best = v;
+        bi = r;
+      }
+    }
+    red_v[tid] = best;
+    red_i[tid] = bi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) {
+        double vo = red_v[tid + s];
+        int io = red_i[tid + s];
+        if (vo > red_v[tid] || (vo == red_v[tid] && io < red_i[tid])) {
+          red_v[tid] = vo;
+          red_i[tid] = io;
+        }
+      }
+      __syncthreads();
+    }
+    int p = red_i[0];
+    double pv = red_v[0];
+    __syncthreads();
+    if (!(pv > 0.0) || !isfinite(pv) || p >= m) {
+      if (tid == 0 && *d.info == 0) *d.info = col + 1;
+      p = col;
+    }
+    if (tid == 0) d.ipiv[col] = p;
+    if (p != col) {
+      for (int c = j0 + tid; c < j0 + w; c += 256) {
+        double t0 = A[col + (int64_t)c * lda];
+        A[col + (int64_t)c * lda] = A[p + (int64_t)c * lda];
+        A[p + (int64_t)c * lda] = t0;
+      }
+    }
+    __syncthreads();
+    const double inv = 1.0 / A[col + (int64_t)col * lda];
+    for (int r = col + 1 + tid; r < m; r += 256) {
+      double l = A[r + (int64_t)col * lda] * inv;
+      A[r + (int64_t)col * lda] = l;
+      for (int c = col + 1; c < j0 + w; ++c)
+        A[r + (int64_t)c * lda] -= l * A[col + (int64_t)c * lda];
+    }
+    __syncthreads();
+  }
+}
+
+void launch_lu_panel(const MatDesc* d, int nmat, int j0, int nb, hipStream_t s) {
+  if (nmat <= 0) return;
+  hipLaunchKernelGGL(lu_panel_kernel, dim3(nmat), dim3(256), 0, s, d, j0, nb);
+}
+
+// Row swaps of panel [j0, j0+w) applied to every column outside the panel, then
+// U12 = L11^-1 A12 for the columns right of the panel (L11 unit lower, in LDS).
+// One wave per slab of 64 columns; slab_ptr: per-matrix prefix of slab counts.
+__global__ __launch_bounds__(64) void lu_swap_trsm_kernel(const MatDesc* __restrict__ ds,
+                                                          const int64_t* __restrict__ slab_ptr,
+                                                          int nmat, int j0, int nb) {
+  __shared__ double L11[64][65];
+  int64_t slab = blockIdx.x;
+  int id = find_item(slab_ptr, nmat, slab);
+  const MatDesc d = ds[id];
+  const int m = d.m;
+  if (m <= j0) return;
+  const int w = min(nb, m - j0);
+  const int64_t lda = d.lda;
+  double* A = d.A;
+  const int lane = threadIdx.x;
+  // stage L11
+  for (int c = 0; c < w; ++c)
+    for (int r = lane; r < w; r += 64) L11[r][c] = A[(j0 + r) + (int64_t)(j0 + c) * lda];
+  __syncthreads();
+  const int c = (int)(slab - slab_ptr[id]) * 64 + lane;
+  if (c >= m || (c >= j0 && c < j0 + w)) return;
+  double* col = A + (int64_t)c * lda;
+  for (int jj = 0; jj < w; ++jj) {
+    int p = d.ipiv[j0 + jj];
+    if (p != j0 + jj) {
+      double t0 = col[j0 + jj];
+      col[j0 + jj] = col[p];
+      col[p] = t0;
+    }
+  }
+  if (c >= j0 + w) {
+    double x[64];
+#pragma unroll
+    for (int r = 0; r < 64; ++r) x[r] = (r < w) ? col[j0 + r] : 0.0;
+#pragma unroll
+    for (int l = 0; l < 64; ++l) {
+#pragma unroll
+      for (int r = l + 1; r < 64; ++r) x[r] -= L11[r][l] * x[l];
+    }
+#pragma unroll
+    for (int r = 0; r < 64; ++r)
+      if (r < w) col[j0 + r] = x[r];
+  }
+}
+
+void launch_lu_swap_trsm(const MatDesc* d, const int64_t* slab_ptr, int64_t nslabs, int nmat,
+                         int j0, int nb, hipStream_t s) {
+  if (nslabs <= 0) return;
+  hipLaunchKernelGGL(lu_swap_trsm_kernel, dim3((unsigned)nslabs), dim3(64), 0, s, d, slab_ptr,
+                     nmat, j0, nb);
+}
+
+// Inverse of the nb x nb diagonal blocks of a triangular factor, for
+// triangular solves by blocks (X_j = inv(T_jj) * B_j followed by a GEMM update).
+// upper = 0: unit lower (LU's L); upper = 1: upper with its diagonal.
+// Output block b of matrix id at out + out_off[id] + b * nb * nb (ld nb),
+// zero outside the triangle.  One wave per (matrix, block).
+__global__ __launch_bounds__(64) void trinv_diag_kernel(const MatDesc* __restrict__ ds,
+                                                        const int64_t* __restrict__ blk_ptr,
+                                                        int nmat, int nb, int upper,
+                                                        double* __restrict__ out,
+                                                        const int64_t* __restrict__ out_off) {
+  __shared__ double Tm[64][65];
+  __shared__ double X[64][65];
+  int64_t blk = blockIdx.x;
+  int id = find_item(blk_ptr, nmat, blk);
+  const MatDesc d = ds[id];
+  const int b = (int)(blk - blk_ptr[id]);
+  const int o = b * nb;
+  const int w = min(nb, d.m - o);
+  if (w <= 0) return;
+  const int lane = threadIdx.x;
+  for (int c = 0; c < w; ++c)
+    for (int r = lane; r < w; r += 64) Tm[r][c] = d.A[(o + r) + (int64_t)(o + c) * d.lda];
+  __syncthreads();
+  const int j = lane;
+  if (j < w) {
+    for (int i = 0; i < w; ++i) X[i][j] = 0.0;
+    if (!upper) {
+      X[j][j] = 1.0;
+      for (int i = j + 1; i < w; ++i) {
+        double s = 0.0;
+        for (int l = j; l < i; ++l) s += Tm[i][l] * X[l][j];
+        X[i][j] = -s;
+      }
+    } else {
+      X[j][j] = 1.0 / Tm[j][j];
+      for (int i = j - 1; i >= 0; --i) {
+        double s = 0.0;
+        for (int l = i + 1; l <= j; ++l) s += Tm[i][l] * X[l][j];
+        X[i][j] = -s / Tm[i][i];
+      }
+    }
+  }
+  __syncthreads();
+  double* dst = out + out_off[id] + (int64_t)b * nb * nb;
+  for (int c = 0; c < nb; ++c)
+    for (int r = lane; r < nb; r += 64) dst[r + (int64_t)c * nb] = (r < w && c < w) ? X[r][c] : 0.0;
+}
+
+void launch_trinv_diag(const MatDesc* d, const int64_t* blk_ptr, int64_t nblk, int nmat, int nb,
+                       int upper, double* out, const int64_t* out_off, hipStream_t s) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(trinv_diag_kernel, dim3((unsigned)nblk), dim3(64), 0, s, d, blk_ptr, nmat,
+                     nb, upper, out, out_off);
+}
+
+// ---------------------------------------------------------------------------
+// Householder panel (LAPACK dgeqrf convention: beta = -sign(alpha) |(alpha, x)|,
+// tau = (beta - alpha) / beta, v = x / (alpha - beta), tau = 0 when x = 0).
+// One workgroup per matrix factors columns [j0, j0+w) of rows [j0, m), writes
+// the explicit reflectors into V (column jj of the panel holds v with a unit
+// entry at row j0+jj and zeros above), tau into aux, and the upper-triangular
+// block-reflector factor T (H_0 ... H_{w-1} = I - V T V^T) into Tf (nb x nb).
+// The trailing columns are updated afterwards by GEMMs.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc* __restrict__ ds, int j0,
+                                                       int nb) {
+  __shared__ double sh[8];
+  __shared__ double s_tau, s_scale;
+  __shared__ double dots[64];
+  const MatDesc d = ds[blockIdx.x];
+  const int m = d.m, n = d.n;
+  if (n <= j0 || m <= j0) return;
+  const int w = min(nb, min(n, m) - j0);
+  double* A = d.A;
+  const int64_t lda = d.lda;
+  double* V = d.V + (int64_t)j0 * m;  // panel reflectors, ld = m
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int jj = 0; jj < w; ++jj) {
+    const int col = j0 + jj;
+    double* a = A + (int64_t)col * lda;
+    double part = 0.0;
+    for (int r = col + 1 + tid; r < m; r += 256) part += a[r] * a[r];
+    double xn2 = block_sum256(part, sh);
+    double alpha = a[col];
+    if (tid == 0) {
+      if (xn2 == 0.0) {
+        s_tau = 0.0;
+        s_scale = 0.0;
+        d.aux[col] = 0.0;
+      } else {
+        double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        s_tau = (beta - alpha) / beta;
+        s_scale = 1.0 / (alpha - beta);
+        d.aux[col] = s_tau;
+        a[col] = beta;
+      }
+    }
+    __syncthreads();
+    const double tau = s_tau, scale = s_scale;
+    double* v = V + (int64_t)jj * m;
+    for (int r = tid; r < m; r += 256) {
+      double val;
+      if (r < col)
+        val = 0.0;
+      else if (r == col)
+        val = 1.0;
+      else {
+        val = a[r] * scale;
+        a[r] = val;
+      }
+      v[r] = val;
+    }
+    __syncthreads();
+    if (tau != 0.0) {
+      // apply H = I - tau v v^T to the panel columns right of col: one wave per column
+      for (int c = col + 1 + wv; c < j0 + w; c += 4) {
+        double* ac = A + (int64_t)c * lda;
+        double p = 0.0;
+        for (int r = col + lane; r < m; r += 64) p += v[r] * ac[r];
+        double wsum = wave_sum(p) * tau;
+        for (int r = col + lane; r < m; r += 64) ac[r] -= wsum * v[r];
+      }
+    }
+    __syncthreads();
+  }
+  // T factor (forward, columnwise): T[jj][jj] = tau_jj,
+  // T[0:jj, jj] = -tau_jj T[0:jj, 0:jj] (V[:, 0:jj]^T v_jj)
+  double* Tf = d.Tf + (int64_t)(j0 / nb) * nb * nb;
+  for (int e = tid; e < nb * nb; e += 256) Tf[e] = 0.0;
+  __syncthreads();
+  for (int jj = 0; jj < w; ++jj) {
+    const double tau = d.aux[j0 + jj];
+    const double* vj = V + (int64_t)jj * m;
+    for (int l = wv; l < jj; l += 4) {
+      const double* vl = V + (int64_t)l * m;
+      double p = 0.0;
+      for (int r = j0 + jj + lane; r < m; r += 64) p += vl[r] * vj[r];
+      p = wave_sum(p);
+      if (lane == 0) dots[l] = p;
+    }
+    __syncthreads();
+    if (tid < jj) {
+      double s = 0.0;
+      for (int l = tid; l < jj; ++l) s += Tf[tid + (int64_t)l * nb] * dots[l];
+      Tf[tid + (int64_t)jj * nb] = -tau * s;
+    }
+    if (tid == 0) Tf[jj + (int64_t)jj * nb] = tau;
+    __syncthreads();
+  }
+}
+
+void launch_qr_panel(const MatDesc* d, int nmat, int j0, int nb, hipStream_t s) {
+  if (nmat <= 0) return;
+  hipLaunchKernelGGL(qr_panel_kernel, dim3(nmat), dim3(256), 0, s, d, j0, nb);
+}
+
+
+// ---------------------------------------------------------------------------
+// Householder QR of a tall matrix by folding row chunks into a running
+// triangle: R <- qr([R; C]) for consecutive chunks C of CR rows of X^T, where
+// X (m x n, column-major) is M'_i and X^T is the matrix whose column-pivoted QR
+// defines the shared basis (Sec. III-C).  The pivoted QR of the m x m factor R
+// selects the same pivots and ranks as that of X^T in exact arithmetic (both
+// depend only on X X^T = R^T R).  The chunk lives in registers (each thread
+// owns CPT columns), R lives in global memory stored transposed (row j of R is
+// contiguous) so that the per-step row reads are coalesced.
+// ---------------------------------------------------------------------------
+template <int CPT, int CR>
+__global__ __launch_bounds__(256) void tsqr_fold_kernel(const FoldItem* __restrict__ items) {
+  __shared__ double vsh[CR];
+  __shared__ double s_tau;
+  const FoldItem it = items[blockIdx.x];
+  const int m = it.m;
+  const int64_t n = it.n;
+  double* RT = it.RT;
+  const int tid = threadIdx.x;
+  for (int64_t e = tid; e < (int64_t)m * m; e += 256) RT[e] = 0.0;
+  __syncthreads();
+  double c[CPT][CR];
+  for (int64_t r0 = 0; r0 < n; r0 += CR) {
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int col = tid + 256 * q;
+#pragma unroll
+      for (int i = 0; i < CR; ++i)
+        c[q][i] = (col < m && r0 + i < n) ? it.X[col + (r0 + i) * it.ldx] : 0.0;
+    }
+    for (int j = 0; j < m; ++j) {
+      const int qj = j >> 8;
+      if (tid == (j & 255)) {
+        double xv[CR];
+#pragma unroll
+        for (int i = 0; i < CR; ++i) xv[i] = 0.0;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q)
+          if (q == qj) {
+#pragma unroll
+            for (int i = 0; i < CR; ++i) xv[i] = c[q][i];
+          }
+        double xn2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < CR; ++i) xn2 += xv[i] * xv[i];
+        if (xn2 == 0.0) {
+          s_tau = 0.0;
+        } else {
+          const double alpha = RT[j + (int64_t)j * m];
+          const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+          const double sc = 1.0 / (alpha - beta);
+#pragma unroll
+          for (int i = 0; i < CR; ++i) vsh[i] = xv[i] * sc;
+          s_tau = (beta - alpha) / beta;
+          RT[j + (int64_t)j * m] = beta;
+#pragma unroll
+          for (int q = 0; q < CPT; ++q)
+            if (q == qj) {
+#pragma unroll
+              for (int i = 0; i < CR; ++i) c[q][i] = 0.0;
+            }
+        }
+      }
+      __syncthreads();
+      const double tau = s_tau;
+      if (tau != 0.0) {
+        double* rowj = RT + (int64_t)j * m;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+          const int col = tid + 256 * q;
+          if (col > j && col < m) {
+            double w = rowj[col];
+#pragma unroll
+            for (int i = 0; i < CR; ++i) w += vsh[i] * c[q][i];
+            w *= tau;
+            rowj[col] -= w;
+#pragma unroll
+            for (int i = 0; i < CR; ++i) c[q][i] -= w * vsh[i];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+void launch_tsqr_fold(const FoldItem* items, int nitems, int max_m, hipStream_t s) {
+  if (nitems <= 0) return;
+  if (max_m <= 256)
+    hipLaunchKernelGGL((tsqr_fold_kernel<1, 32>), dim3(nitems), dim3(256), 0, s, items);
+  else if (max_m <= 512)
+    hipLaunchKernelGGL((tsqr_fold_kernel<2, 16>), dim3(nitems), dim3(256), 0, s, items);
+  else if (max_m <= 1024)
+    hipLaunchKernelGGL((tsqr_fold_kernel<4, 8>), dim3(nitems), dim3(256), 0, s, items);
+  else if (max_m <= 2048)
+    hipLaunchKernelGGL((tsqr_fold_kernel<8, 4>), dim3(nitems), dim3(256), 0, s, items);
+  else if (max_m <= 4096)
+    hipLaunchKernelGGL((tsqr_fold_kernel<16, 2>), dim3(nitems), dim3(256), 0, s, items);
+  else
+    hipLaunchKernelGGL((tsqr_fold_kernel<32, 1>), dim3(nitems), dim3(256), 0, s, items);
+}
+
+// ---------------------------------------------------------------------------
+// Column-pivoted Householder QR for the row interpolative decomposition
+// (Sec. II-A: the shared basis from a column-pivoted QR).  One workgroup per
+// matrix; the matrix stays in global memory.  At step t the column of largest
+// remaining norm (norms recomputed exactly, lowest index on ties) is moved to
+// position t; the step is taken only while that norm exceeds tol * |R_00| and
+// t < cap.  Afterwards the leading k rows of R give E = R11^-1 R12, which is
+// written over R12.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void pivqr_kernel(const PivQrItem* __restrict__ items) {
+  __shared__ double red_v[256];
+  __shared__ int red_i[256];
+  __shared__ double sh[8];
+  __shared__ double s_tau;
+  __shared__ int s_stop;
+  const PivQrItem it = items[blockIdx.x];
+  const int m = it.m, n = it.n;
+  double* A = it.A;
+  const int64_t lda = it.lda;
+  double* nrm = it.work;
+  const int tid = threadIdx.x;
+  for (int c = tid; c < n; c += 256) {
+    const double* ac = A + (int64_t)c * lda;
+    double s = 0.0;
+    for (int r = 0; r < m; ++r) s += ac[r] * ac[r];
+    nrm[c] = sqrt(s);
+    it.piv[c] = c;
+  }
+  for (int t = tid; t < min(m, n); t += 256) it.diag[t] = 0.0;
+  __syncthreads();
+  const int steps = min(m, min(n, it.cap));
+  double thr = 0.0;
+  int k = 0;
+  for (int t = 0; t < steps; ++t) {
+    double best = -1.0;
+    int bi = n;
+    for (int c = t + tid; c < n; c += 256) {
+      double v = nrm[c];
+      if (v > best) {
+        best = v;
+        bi = c;
+      }
+    }
+    red_v[tid] = best;
+    red_i[tid] = bi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) {
+        double vo = red_v[tid + s];
+        int io = red_i[tid + s];
+        if (vo > red_v[tid] || (vo == red_v[tid] && io < red_i[tid])) {
+          red_v[tid] = vo;
+          red_i[tid] = io;
+        }
+      }
+      __syncthreads();
+    }
+    const double pn = red_v[0];
+    const int p = red_i[0];
+    if (t == 0) thr = it.tol * pn;
+    const bool stop = !(pn > thr) || !(pn > 0.0) || p >= n;
+    __syncthreads();
+    if (stop) break;
+    if (tid == 0) it.diag[t] = pn;
+    // swap columns t and p (all rows), norms and pivots
+    if (p != t) {
+      double* at = A + (int64_t)t * lda;
+      double* ap = A + (int64_t)p * lda;
+      for (int r = tid; r < m; r += 256) {
+        double x = at[r];
+        at[r] = ap[r];
+        ap[r] = x;
+      }
+      if (tid == 0) {
+        double x = nrm[t];
+        nrm[t] = nrm[p];
+        nrm[p] = x;
+        int q = it.piv[t];
+        it.piv[t] = it.piv[p];
+        it.piv[p] = q;
+      }
+    }
+    __syncthreads();
+    // reflector from column t, rows t..m-1
+    double* at = A + (int64_t)t * lda;
+    double part = 0.0;
+    for (int r = t + 1 + tid; r < m; r += 256) part += at[r] * at[r];
+    double xn2 = block_sum256(part, sh);
+    double alpha = at[t];
+    if (tid == 0) {
+      if (xn2 == 0.0) {
+        s_tau = 0.0;
+      } else {
+        double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        s_tau = (beta - alpha) / beta;
+        double scale = 1.0 / (alpha - beta);
+        at[t] = beta;
+        red_v[0] = scale;
+      }
+    }
+    __syncthreads();
+    const double tau = s_tau;
+    if (tau != 0.0) {
+      const double scale = red_v[0];
+      for (int r = t + 1 + tid; r < m; r += 256) at[r] *= scale;
+    }
+    __syncthreads();
+    // apply to columns c > t and recompute their norms below row t
+    for (int c = t + 1 + tid; c < n; c += 256) {
+      double* ac = A + (int64_t)c * lda;
+      if (tau != 0.0) {
+        double wsum = ac[t];
+        for (int r = t + 1; r < m; ++r) wsum += at[r] * ac[r];
+        wsum *= tau;
+        ac[t] -= wsum;
+        double s = 0.0;
+        for (int r = t + 1; r < m; ++r) {
+          double x = ac[r] - wsum * at[r];
+          ac[r] = x;
+          s += x * x;
+        }
+        nrm[c] = sqrt(s);
+      } else {
+        double s = 0.0;
+        for (int r = t + 1; r < m; ++r) s += ac[r] * ac[r];
+        nrm[c] = sqrt(s);
+      }
+    }
+    k = t + 1;
+    __syncthreads();
+  }
+  if (tid == 0) *it.kout = k;
+  // E = R11^-1 R12 in place over R12 (rows 0..k-1, columns k..n-1)
+  for (int c = k + tid; c < n; c += 256) {
+    double* ac = A + (int64_t)c * lda;
+    for (int i = k - 1; i >= 0; --i) {
+      double s = ac[i];
+      for (int l = i + 1; l < k; ++l) s -= A[i + (int64_t)l * lda] * ac[l];
+      ac[i] = s / A[i + (int64_t)i * lda];
+    }
+  }
+}
+
+void launch_pivqr(const PivQrItem* items, int nitems, hipStream_t s) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(pivqr_kernel, dim3(nitems), dim3(256), 0, s, items);
+}
+
+// ---------------------------------------------------------------------------
+// Batched 2-D copy / scaled accumulate (merges of skeleton blocks into the
+// parent's dense blocks, quadrant extraction, packing).  Tile 64 x 64.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void copy_kernel(const CopyItem* __restrict__ items,
+                                                   const int64_t* __restrict__ tile_ptr,
+                                                   int nitems, double alpha, double beta) {
+  int64_t tile = blockIdx.x;
+  int id = find_item(tile_ptr, nitems, tile);
+  const CopyItem it = items[id];
+  int64_t local = tile - tile_ptr[id];
+  int tm = (it.rows + 63) >> 6;
+  int i = (int)(local % tm) * 64 + (threadIdx.x & 63);
+  int j0 = (int)(local / tm) * 64 + (threadIdx.x >> 6);
+  if (i >= it.rows) return;
+  for (int q = 0; q < 16; ++q) {
+    int j = j0 + 4 * q;
+    if (j >= it.cols) break;
+    double v = it.trans ? it.src[j + (int64_t)i * it.lds] : it.src[i + (int64_t)j * it.lds];
+    double* o = it.dst + i + (int64_t)j * it.ldd;
+    double r = alpha * v;
+    if (beta != 0.0) r += beta * (*o);
+    *o = r;
+  }
+}
+
+void launch_copy(const CopyItem* items, const int64_t* tile_ptr, int64_t ntiles, int nitems,
+                 double alpha, double beta, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, items, tile_ptr,
+                     nitems, alpha, beta);
+}
+
+// ---------------------------------------------------------------------------
+// Exact matvec y = A x with A generated on the fly in float64 (residuals of the
+// iterative refinement).  One thread per row; source points staged in LDS.
+// ---------------------------------------------------------------------------
+template <int NR>
+__global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ pts, int64_t n,
+                                                     KernelFn kf, const double* __restrict__ x,
+                                                     int64_t ldx, double* __restrict__ y,
+                                                     int64_t ldy) {
+  __shared__ double sp[256][3];
+  __shared__ double sx[NR][256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double xi = 0, yi = 0, zi = 0;
+  if (i < n) {
+    xi = pts[3 * i];
+    yi = pts[3 * i + 1];
+    zi = pts[3 * i + 2];
+  }
+  double acc[NR];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+  for (int64_t j0 = 0; j0 < n; j0 += 256) {
+    const int64_t j = j0 + threadIdx.x;
+    __syncthreads();
+    if (j < n) {
+      sp[threadIdx.x][0] = pts[3 * j];
+      sp[threadIdx.x][1] = pts[3 * j + 1];
+      sp[threadIdx.x][2] = pts[3 * j + 2];
+#pragma unroll
+      for (int c = 0; c < NR; ++c) sx[c][threadIdx.x] = x[j + c * ldx];
+    } else {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) sx[c][threadIdx.x] = 0.0;
+      sp[threadIdx.x][0] = sp[threadIdx.x][1] = sp[threadIdx.x][2] = 0.0;
+    }
+    __syncthreads();
+    const int cnt = (int)min((int64_t)256, n - j0);
+    for (int t = 0; t < cnt; ++t) {
+      const int64_t jj = j0 + t;
+      double kv;
+      if (jj == i) {
+        kv = kf.diag;
+      } else {
+        double dx = xi - sp[t][0], dy = yi - sp[t][1], dz = zi - sp[t][2];
+        double r2 = dx * dx + dy * dy + dz * dz;
+        kv = (r2 > 0.0) ? kernel_value(kf, r2) : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < NR; ++c) acc[c] += kv * sx[c][t];
+    }
+  }
+  if (i < n) {
+#pragma unroll
+    for (int c = 0; c < NR; ++c) y[i + c * ldy] = acc[c];
+  }
+}
+
+void launch_matvec(const double* pts, int64_t n, KernelFn kf, const double* x, int64_t ldx,
+                   double* y, int64_t ldy, int nrhs, hipStream_t s) {
+  unsigned grid = (unsigned)((n + 255) / 256);
+  int c = 0;
+  while (c < nrhs) {
+    int left = nrhs - c;
+    if (left >= 8) {
+      hipLaunchKernelGGL(matvec_kernel<8>, dim3(grid), dim3(256), 0, s, pts, n, kf,
+                         x + (int64_t)c * ldx, ldx, y + (int64_t)c * ldy, ldy);
+      c += 8;
+    } else if (left >= 4) {
+      hipLaunchKernelGGL(matvec_kernel<4>, dim3(grid), dim3(256), 0, s, pts, n, kf,
+                         x + (int64_t)c * ldx, ldx, y + (int64_t)c * ldy, ldy);
+      c += 4;
+    } else {
+      hipLaunchKernelGGL(matvec_kernel<1>, dim3(grid), dim3(256), 0, s, pts, n, kf,
+                         x + (int64_t)c * ldx, ldx, y + (int64_t)c * ldy, ldy);
+      c += 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small elementwise kernels
+// ---------------------------------------------------------------------------
+__global__ void d2f_kernel(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = (float)s[i];
+}
+__global__ void f2d_kernel(const float* __restrict__ s, double* __restrict__ d, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = (double)s[i];
+}
+void launch_convert_d2f(const double* src, float* dst, int64_t count, hipStream_t s) {
+  if (count <= 0) return;
+  int64_t g = (count + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(d2f_kernel, dim3((unsigned)g), dim3(256), 0, s, src, dst, count);
+}
+void launch_convert_f2d(const float* src, double* dst, int64_t count, hipStream_t s) {
+  if (count <= 0) return;
+  int64_t g = (count + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(f2d_kernel, dim3((unsigned)g), dim3(256), 0, s, src, dst, count);
+}
+
+// r = b - ax, per-column |r|^2 and |b|^2 (one workgroup per column).
+__global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ b, int64_t ldb,
+                                                    const double* __restrict__ ax, int64_t ldax,
+                                                    double* __restrict__ r, int64_t ldr,
+                                                    int64_t n, double* rn, double* bn) {
+  __shared__ double sh[8];
+  const int c = blockIdx.x;
+  double pr = 0.0, pb = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    double bv = b[i + c * ldb];
+    double rv = bv - ax[i + c * ldax];
+    r[i + c * ldr] = rv;
+    pr += rv * rv;
+    pb += bv * bv;
+  }
+  double sr = block_sum256(pr, sh);
+  __syncthreads();
+  double sb = block_sum256(pb, sh);
+  if (threadIdx.x == 0) {
+    rn[c] = sr;
+    bn[c] = sb;
+  }
+}
+void launch_resid_norms(const double* b, int64_t ldb, const double* ax, int64_t ldax, double* r,
+                        int64_t ldr, int64_t n, int nrhs, double* rnorm2, double* bnorm2,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(resid_kernel, dim3(nrhs), dim3(256), 0, s, b, ldb, ax, ldax, r, ldr, n,
+                     rnorm2, bnorm2);
+}
+
+__global__ void axpy_cols_kernel(double* x, int64_t ldx, const double* d, int64_t ldd,
+                                 int64_t n) {
+  const int c = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i + c * ldx] += d[i + c * ldd];
+}
+void launch_axpy_cols(double* x, int64_t ldx, const double* d, int64_t ldd, int64_t n, int nrhs,
+                      hipStream_t s) {
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(axpy_cols_kernel, dim3((unsigned)g, nrhs), dim3(256), 0, s, x, ldx, d, ldd,
+                     n);
+}
+
+// dst[t] = src[perm[t]] (inverse = 0) or dst[perm[t]] = src[t] (inverse = 1)
+__global__ void permute_kernel(const double* src, int64_t lds, double* dst, int64_t ldd,
+                               const int64_t* perm, int64_t n, int inverse) {
+  const int c = blockIdx.y;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    if (!inverse)
+      dst[t + c * ldd] = src[perm[t] + c * lds];
+    else
+      dst[perm[t] + c * ldd] = src[t + c * lds];
+  }
+}
+void launch_permute_rows(const double* src, int64_t lds, double* dst, int64_t ldd,
+                         const int64_t* perm, int64_t n, int nrhs, int inverse, hipStream_t s) {
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(permute_kernel, dim3((unsigned)g, nrhs), dim3(256), 0, s, src, lds, dst,
+                     ldd, perm, n, inverse);
+}
+
+// ---------------------------------------------------------------------------
+// P^T as a dense matrix from LU row interchanges (ipiv == nullptr: identity);
+// one thread per column follows where the unit entry of that column moves.
+// ---------------------------------------------------------------------------
+__global__ void perm_matrix_kernel(const PermItem* __restrict__ items,
+                                   const int64_t* __restrict__ slab_ptr, int nitems) {
+  int64_t slab = blockIdx.x;
+  int id = find_item(slab_ptr, nitems, slab);
+  const PermItem it = items[id];
+  const int c = (int)(slab - slab_ptr[id]) * 64 + threadIdx.x;
+  if (c >= it.m) return;
+  int pos = c;
+  if (it.ipiv) {
+    // B = P^T I where P^T applies the swaps (t, ipiv[t]) for t = 0..m-1 in order
+    for (int t = 0; t < it.m; ++t) {
+      int p = it.ipiv[t];
+      if (p == t) continue;
+      if (pos == t)
+        pos = p;
+      else if (pos == p)
+        pos = t;
+    }
+  }
+  double* col = it.out + (int64_t)c * it.ld;
+  for (int r = 0; r < it.m; ++r) col[r] = (r == pos) ? 1.0 : 0.0;
+}
+
+void launch_perm_matrix(const PermItem* items, const int64_t* slab_ptr, int64_t nslabs,
+                        int nitems, hipStream_t s) {
+  if (nslabs <= 0) return;
+  hipLaunchKernelGGL(perm_matrix_kernel, dim3((unsigned)nslabs), dim3(64), 0, s, items, slab_ptr,
+                     nitems);
+}
+
+// W' (m x k) of the row ID: row piv[t] = e_t for t < k, row piv[k+s] = E[:, s]^T
+// where E = R11^-1 R12 sits in rows 0..k-1, columns k.. of the pivoted-QR matrix.
+__global__ void wprime_kernel(const WpItem* __restrict__ items) {
+  const WpItem it = items[blockIdx.x];
+  const int m = it.m, k = it.k;
+  for (int e = threadIdx.x; e < m * k; e += blockDim.x) {
+    const int s = e / k, t = e % k;  // source row s of [I; E^T], column t
+    double v;
+    if (s < k)
+      v = (s == t) ? 1.0 : 0.0;
+    else
+      v = it.E[t + (int64_t)s * it.ldE];
+    it.W[it.piv[s] + (int64_t)t * it.ldW] = v;
+  }
+}
+
+void launch_wprime(const WpItem* items, int nitems, hipStream_t s) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(wprime_kernel, dim3(nitems), dim3(256), 0, s, items);
+}
+
+// Strictly-lower part of a batch of matrices set to zero (triangular factors).
+__global__ void zero_lower_kernel(const CopyItem* __restrict__ items) {
+  const CopyItem it = items[blockIdx.x];
+  for (int64_t e = threadIdx.x; e < (int64_t)it.rows * it.cols; e += blockDim.x) {
+    int i = (int)(e % it.rows), j = (int)(e / it.rows);
+    if (i > j) it.dst[i + (int64_t)j * it.ldd] = 0.0;
+  }
+}
+void launch_zero_lower(const CopyItem* items, int nitems, hipStream_t s) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(zero_lower_kernel, dim3(nitems), dim3(256), 0, s, items);
+}
+
+// log|det| of LU factors: sum of log|U_tt| per matrix (one workgroup each).
+__global__ __launch_bounds__(256) void logdet_kernel(const MatDesc* __restrict__ ds, double* out) {
+  __shared__ double sh[8];
+  const MatDesc d = ds[blockIdx.x];
+  double p = 0.0;
+  for (int t = threadIdx.x; t < d.m; t += 256) p += log(fabs(d.A[t + (int64_t)t * d.lda]));
+  double s = block_sum256(p, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+void launch_logdet(const MatDesc* d, int nmat, double* out, hipStream_t s) {
+  if (nmat <= 0) return;
+  hipLaunchKernelGGL(logdet_kernel, dim3(nmat), dim3(256), 0, s, d, out);
+}
+
+}  // namespace h2ulv

@@ -1,0 +1,162 @@
+// Host setup of the sweep: binary cluster tree and near/far block lists.
+//
+// The paper factorizes level by level over a full binary tree of boxes
+// (Sec. III-D) and uses strong admissibility: a block is low-rank only when its
+// two boxes are well separated, otherwise it is kept dense (Sec. I, II-D).
+// The paper does not fix the partitioner or the admissibility formula; this
+// library uses
+//   * a k-d split along the widest bounding-box axis (lowest axis on ties),
+//     points stably ordered by (coordinate, original index), left child gets
+//     floor(n/2); depth L = smallest integer with leaf * 2^L >= N;
+//   * box centre = bounding-box midpoint, radius = half its diagonal;
+//   * (i, j) admissible iff |c_i - c_j| > eta (r_i + r_j), decided for the
+//     children of every near pair of the parent level (root: near to itself).
+// Geometry is computed with plain (non-contracted) double arithmetic.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "h2ulv_internal.h"
+
+namespace h2ulv {
+
+int tree_depth(int64_t n, int leaf) {
+  int L = 0;
+  while ((int64_t)leaf * ((int64_t)1 << L) < n) ++L;
+  return L;
+}
+
+static void bbox(const double* pts, const int64_t* idx, int64_t cnt, double lo[3], double hi[3]) {
+  for (int c = 0; c < 3; ++c) {
+    lo[c] = pts[idx[0] * 3 + c];
+    hi[c] = lo[c];
+  }
+  for (int64_t a = 1; a < cnt; ++a)
+    for (int c = 0; c < 3; ++c) {
+      double v = pts[idx[a] * 3 + c];
+      if (v < lo[c]) lo[c] = v;
+      if (v > hi[c]) hi[c] = v;
+    }
+}
+
+Tree build_tree(const double* pts, int64_t n, int leaf) {
+  Tree t;
+  t.n = n;
+  t.L = tree_depth(n, leaf);
+  t.perm.resize(n);
+  std::iota(t.perm.begin(), t.perm.end(), (int64_t)0);
+  std::vector<std::pair<int64_t, int64_t>> ranges{{0, n}};
+  for (int lev = 0; lev <= t.L; ++lev) {
+    size_t nb = ranges.size();
+    t.start.emplace_back(nb);
+    t.end.emplace_back(nb);
+    t.centre.emplace_back(3 * nb);
+    t.radius.emplace_back(nb);
+    std::vector<std::pair<int64_t, int64_t>> next;
+    next.reserve(2 * nb);
+    for (size_t b = 0; b < nb; ++b) {
+      int64_t a0 = ranges[b].first, a1 = ranges[b].second;
+      t.start[lev][b] = a0;
+      t.end[lev][b] = a1;
+      double lo[3], hi[3];
+      bbox(pts, t.perm.data() + a0, a1 - a0, lo, hi);
+      double d[3];
+      for (int c = 0; c < 3; ++c) {
+        t.centre[lev][3 * b + c] = 0.5 * (lo[c] + hi[c]);
+        d[c] = hi[c] - lo[c];
+      }
+      double s = d[0] * d[0];
+      s = s + d[1] * d[1];
+      s = s + d[2] * d[2];
+      t.radius[lev][b] = 0.5 * std::sqrt(s);
+      if (lev < t.L) {
+        int axis = 0;
+        if (d[1] > d[axis]) axis = 1;
+        if (d[2] > d[axis]) axis = 2;
+        int64_t* p = t.perm.data() + a0;
+        std::sort(p, p + (a1 - a0), [&](int64_t u, int64_t v) {
+          double cu = pts[u * 3 + axis], cv = pts[v * 3 + axis];
+          return cu < cv || (cu == cv && u < v);
+        });
+        int64_t mid = a0 + (a1 - a0) / 2;
+        next.push_back({a0, mid});
+        next.push_back({mid, a1});
+      }
+    }
+    ranges.swap(next);
+  }
+  return t;
+}
+
+Lists build_lists(const Tree& t, double eta) {
+  Lists ls;
+  ls.near_ptr.push_back({0, 1});
+  ls.near_idx.push_back({0});
+  ls.far_ptr.push_back({0, 0});
+  ls.far_idx.push_back({});
+  for (int lev = 1; lev <= t.L; ++lev) {
+    int64_t nb = (int64_t)1 << lev;
+    std::vector<std::vector<int32_t>> nl(nb), fl(nb);
+    const std::vector<double>& c = t.centre[lev];
+    const std::vector<double>& r = t.radius[lev];
+    const std::vector<int64_t>& pp = ls.near_ptr[lev - 1];
+    const std::vector<int32_t>& pi = ls.near_idx[lev - 1];
+    for (int64_t p = 0; p < nb / 2; ++p)
+      for (int64_t e = pp[p]; e < pp[p + 1]; ++e) {
+        int64_t q = pi[e];
+        for (int64_t i = 2 * p; i < 2 * p + 2; ++i)
+          for (int64_t j = 2 * q; j < 2 * q + 2; ++j) {
+            double d0 = c[3 * i] - c[3 * j], d1 = c[3 * i + 1] - c[3 * j + 1],
+                   d2 = c[3 * i + 2] - c[3 * j + 2];
+            double s = d0 * d0;
+            s = s + d1 * d1;
+            s = s + d2 * d2;
+            double dist = std::sqrt(s);
+            if (dist > eta * (r[i] + r[j]))
+              fl[i].push_back((int32_t)j);
+            else
+              nl[i].push_back((int32_t)j);
+          }
+      }
+    std::vector<int64_t> np(nb + 1, 0), fp(nb + 1, 0);
+    std::vector<int32_t> ni, fi;
+    for (int64_t i = 0; i < nb; ++i) {
+      std::sort(nl[i].begin(), nl[i].end());
+      std::sort(fl[i].begin(), fl[i].end());
+      ni.insert(ni.end(), nl[i].begin(), nl[i].end());
+      fi.insert(fi.end(), fl[i].begin(), fl[i].end());
+      np[i + 1] = (int64_t)ni.size();
+      fp[i + 1] = (int64_t)fi.size();
+    }
+    ls.near_ptr.push_back(std::move(np));
+    ls.near_idx.push_back(std::move(ni));
+    ls.far_ptr.push_back(std::move(fp));
+    ls.far_idx.push_back(std::move(fi));
+  }
+  return ls;
+}
+
+bool Lists::is_near(int lev, int32_t i, int32_t j) const {
+  const int32_t* b = near_idx[lev].data() + near_ptr[lev][i];
+  const int32_t* e = near_idx[lev].data() + near_ptr[lev][i + 1];
+  return std::binary_search(b, e, j);
+}
+
+void validate_params(const h2ulv_params* p) {
+  if (!p) fail(H2ULV_ERR_INVALID_ARG, "params is NULL");
+  if (p->struct_size != (int32_t)sizeof(h2ulv_params))
+    fail(H2ULV_ERR_INVALID_ARG, "params.struct_size mismatch (use h2ulv_params_default)");
+  if (p->kernel != H2ULV_LAPLACE && p->kernel != H2ULV_YUKAWA)
+    fail(H2ULV_ERR_INVALID_ARG, "unknown kernel");
+  if (!std::isfinite(p->alpha) || !std::isfinite(p->diag))
+    fail(H2ULV_ERR_INVALID_ARG, "alpha and diag must be finite");
+  if (!(p->eta >= 0) || !std::isfinite(p->eta)) fail(H2ULV_ERR_INVALID_ARG, "eta must be >= 0");
+  if (p->leaf_size < 2) fail(H2ULV_ERR_INVALID_ARG, "leaf_size must be >= 2");
+  if (p->rank_cap < 0) fail(H2ULV_ERR_INVALID_ARG, "rank_cap must be >= 0");
+  if (!(p->tol >= 0) || !std::isfinite(p->tol)) fail(H2ULV_ERR_INVALID_ARG, "tol must be >= 0");
+  if (p->far_sample < 0) fail(H2ULV_ERR_INVALID_ARG, "far_sample must be >= 0");
+  if (p->precision != H2ULV_FP64 && p->precision != H2ULV_MIXED)
+    fail(H2ULV_ERR_INVALID_ARG, "unknown precision");
+}
+
+}  // namespace h2ulv

@@ -1,0 +1,323 @@
+"""Thin Python binding of the h2ulv C-ABI (include/h2ulv.h).
+
+Argument marshalling only: every step of the factorization and solve runs in
+the HIP library.  torch supplies device memory and the current stream.  The
+library must be built (``python -m paper_2208_10907_amd.build``); loading fails
+loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().parent / "_lib" / "libh2ulv.so"
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_OOM = -2
+ERR_HIP = -3
+ERR_SINGULAR = -4
+ERR_DUPLICATE_POINTS = -5
+ERR_NOT_CONVERGED = -6
+
+LAPLACE = 0
+YUKAWA = 1
+FP64 = 0
+MIXED = 1
+
+# every symbol include/h2ulv.h declares
+EXPORTS = [
+    "h2ulv_params_default", "h2ulv_factorize", "h2ulv_factorize_batch", "h2ulv_solve",
+    "h2ulv_matvec_exact", "h2ulv_refine", "h2ulv_get_stats", "h2ulv_get_levels",
+    "h2ulv_get_perm", "h2ulv_get_ranks", "h2ulv_get_skeleton", "h2ulv_get_basis",
+    "h2ulv_destroy", "h2ulv_structure_create", "h2ulv_structure_levels",
+    "h2ulv_structure_perm", "h2ulv_structure_lists", "h2ulv_structure_geometry",
+    "h2ulv_structure_destroy", "h2ulv_status_string", "h2ulv_last_error",
+]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_int32), ("kernel", C.c_int32), ("alpha", C.c_double),
+        ("diag", C.c_double), ("eta", C.c_double), ("leaf_size", C.c_int32),
+        ("rank_cap", C.c_int32), ("tol", C.c_double), ("far_sample", C.c_int32),
+        ("precision", C.c_int32), ("verbose", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("levels", C.c_int32), ("max_rank", C.c_int32), ("root_size", C.c_int32),
+        ("reserved", C.c_int32), ("n", C.c_int64), ("flops_fill", C.c_double),
+        ("flops_basis", C.c_double), ("flops_couple", C.c_double),
+        ("flops_rotate", C.c_double), ("flops_elim", C.c_double), ("flops_root", C.c_double),
+        ("kernel_evals", C.c_double), ("time_setup_s", C.c_double),
+        ("time_factor_s", C.c_double), ("device_bytes", C.c_double), ("logabsdet", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        d["flops"] = (self.flops_fill + self.flops_basis + self.flops_couple + self.flops_rotate
+                      + self.flops_elim + self.flops_root)
+        return d
+
+
+class H2ULVError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"h2ulv status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libh2ulv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not LIB_PATH.exists():
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2208_10907_amd.build`")
+    L = C.CDLL(str(LIB_PATH))
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER
+    sig = {
+        "h2ulv_params_default": (i32, [P(Params)]),
+        "h2ulv_factorize": (i32, [vp, i64, P(Params), vp, P(vp)]),
+        "h2ulv_factorize_batch": (i32, [i32, P(vp), P(i64), P(Params), vp, P(vp)]),
+        "h2ulv_solve": (i32, [vp, vp, i32, i64, vp]),
+        "h2ulv_matvec_exact": (i32, [vp, vp, i64, vp, i64, i32, vp]),
+        "h2ulv_refine": (i32, [vp, vp, i64, vp, i64, i32, dbl, i32, P(i32), P(dbl), vp]),
+        "h2ulv_get_stats": (i32, [vp, P(Stats)]),
+        "h2ulv_get_levels": (i32, [vp, P(i32)]),
+        "h2ulv_get_perm": (i32, [vp, vp]),
+        "h2ulv_get_ranks": (i32, [vp, i32, vp, vp]),
+        "h2ulv_get_skeleton": (i32, [vp, i32, i32, vp]),
+        "h2ulv_get_basis": (i32, [vp, i32, i32, vp]),
+        "h2ulv_destroy": (None, [vp]),
+        "h2ulv_structure_create": (i32, [vp, i64, P(Params), P(vp)]),
+        "h2ulv_structure_levels": (i32, [vp, P(i32)]),
+        "h2ulv_structure_perm": (i32, [vp, vp]),
+        "h2ulv_structure_lists": (i32, [vp, i32, vp, vp, vp, vp]),
+        "h2ulv_structure_geometry": (i32, [vp, i32, vp, vp]),
+        "h2ulv_structure_destroy": (None, [vp]),
+        "h2ulv_status_string": (C.c_char_p, [i32]),
+        "h2ulv_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != OK:
+        msg = lib().h2ulv_last_error().decode(errors="replace")
+        raise H2ULVError(status, msg)
+
+
+def make_params(kernel=LAPLACE, alpha=0.0, diag=1e3, eta=1.0, leaf=256, tol=1e-8,
+                rank_cap=0, far_sample=32, precision=FP64, verbose=0) -> Params:
+    p = Params()
+    _check(lib().h2ulv_params_default(C.byref(p)))
+    p.kernel, p.alpha, p.diag, p.eta = int(kernel), float(alpha), float(diag), float(eta)
+    p.leaf_size, p.rank_cap, p.tol = int(leaf), int(rank_cap), float(tol)
+    p.far_sample, p.precision, p.verbose = int(far_sample), int(precision), int(verbose)
+    return p
+
+
+def params_from_problem(prob, precision=FP64, verbose=0) -> Params:
+    return make_params(prob.kernel, prob.alpha, prob.diag, prob.eta, prob.leaf, prob.tol,
+                       prob.rank_cap, prob.far_sample, precision, verbose)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_points(points):
+    import torch
+    if not isinstance(points, torch.Tensor):
+        points = torch.as_tensor(np.ascontiguousarray(points, dtype=np.float64))
+    pts = points.to(device="cuda", dtype=torch.float64).contiguous()
+    if pts.ndim != 2 or pts.shape[1] != 3:
+        raise ValueError("points must be N x 3")
+    return pts
+
+
+class Factor:
+    """Owns one h2ulv_factor handle."""
+
+    def __init__(self, handle: int, pts):
+        self._h = C.c_void_p(handle)
+        self._pts = pts
+        self.n = int(pts.shape[0])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.h2ulv_destroy(h)
+            self._h = None
+
+    # -- vectors: torch (n,) or (n, nrhs) tensors on the GPU -----------------
+    @staticmethod
+    def _colmajor(b):
+        """A fresh (nrhs, n) buffer (== n x nrhs column-major); never a view of b,
+        since the library writes into it."""
+        import torch
+        b = b.to(device="cuda", dtype=torch.float64)
+        vec = b.ndim == 1
+        bm = b.reshape(b.shape[0], -1)
+        out = torch.empty((bm.shape[1], bm.shape[0]), dtype=torch.float64, device=b.device)
+        out.copy_(bm.t())
+        return vec, out
+
+    @staticmethod
+    def _back(vec, bt):
+        out = bt.t()
+        return out[:, 0].contiguous() if vec else out.contiguous()
+
+    def solve(self, b, stream=None):
+        vec, bt = self._colmajor(b)
+        _check(lib().h2ulv_solve(self._h, C.c_void_p(bt.data_ptr()), bt.shape[0], self.n,
+                                 _stream(stream)))
+        return self._back(vec, bt)
+
+    def matvec(self, x, stream=None):
+        import torch
+        vec, xt = self._colmajor(x)
+        yt = torch.empty_like(xt)
+        _check(lib().h2ulv_matvec_exact(self._h, C.c_void_p(xt.data_ptr()), self.n,
+                                        C.c_void_p(yt.data_ptr()), self.n, xt.shape[0],
+                                        _stream(stream)))
+        return self._back(vec, yt)
+
+    def refine(self, b, rtol=1e-10, max_iter=20, stream=None, raise_on_fail=True):
+        import torch
+        vec, bt = self._colmajor(b)
+        xt = torch.empty_like(bt)
+        it = C.c_int32(0)
+        rr = C.c_double(0.0)
+        st = lib().h2ulv_refine(self._h, C.c_void_p(bt.data_ptr()), self.n,
+                                C.c_void_p(xt.data_ptr()), self.n, bt.shape[0], float(rtol),
+                                int(max_iter), C.byref(it), C.byref(rr), _stream(stream))
+        if st != OK and (raise_on_fail or st != ERR_NOT_CONVERGED):
+            _check(st)
+        return self._back(vec, xt), int(it.value), float(rr.value)
+
+    # -- inspection ---------------------------------------------------------
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().h2ulv_get_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def levels(self) -> int:
+        L = C.c_int32()
+        _check(lib().h2ulv_get_levels(self._h, C.byref(L)))
+        return int(L.value)
+
+    def perm(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.int64)
+        _check(lib().h2ulv_get_perm(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def ranks(self, lev: int):
+        m = np.empty(1 << lev, dtype=np.int32)
+        k = np.empty(1 << lev, dtype=np.int32)
+        _check(lib().h2ulv_get_ranks(self._h, lev, m.ctypes.data_as(C.c_void_p),
+                                     k.ctypes.data_as(C.c_void_p)))
+        return m, k
+
+    def skeleton(self, lev: int, box: int) -> np.ndarray:
+        _, k = self.ranks(lev)
+        out = np.empty(max(int(k[box]), 1), dtype=np.int64)
+        _check(lib().h2ulv_get_skeleton(self._h, lev, box, out.ctypes.data_as(C.c_void_p)))
+        return out[: int(k[box])]
+
+    def basis(self, lev: int, box: int) -> np.ndarray:
+        m, _ = self.ranks(lev)
+        mm = int(m[box])
+        out = np.empty((mm, mm), dtype=np.float64, order="F")
+        if mm:
+            _check(lib().h2ulv_get_basis(self._h, lev, box, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+
+def factorize(points, params: Params | None = None, stream=None, **kw) -> Factor:
+    """Factorize the kernel matrix of `points` (N x 3) on the current GPU."""
+    if params is None:
+        params = make_params(**kw)
+    pts = _dev_points(points)
+    h = C.c_void_p()
+    _check(lib().h2ulv_factorize(C.c_void_p(pts.data_ptr()), pts.shape[0], C.byref(params),
+                                 _stream(stream), C.byref(h)))
+    return Factor(h.value, pts)
+
+
+def factorize_batch(points_list, params: Params, stream=None) -> list:
+    """Factorize several independent problems with shared batched launches."""
+    pts = [_dev_points(p) for p in points_list]
+    n = len(pts)
+    ptrs = (C.c_void_p * n)(*[p.data_ptr() for p in pts])
+    ns = (C.c_int64 * n)(*[p.shape[0] for p in pts])
+    hs = (C.c_void_p * n)()
+    _check(lib().h2ulv_factorize_batch(n, ptrs, ns, C.byref(params), _stream(stream), hs))
+    return [Factor(hs[i], pts[i]) for i in range(n)]
+
+
+class Structure:
+    """Host-only cluster tree and near/far lists (no GPU needed)."""
+
+    def __init__(self, points, params: Params):
+        X = np.ascontiguousarray(points, dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib().h2ulv_structure_create(X.ctypes.data_as(C.c_void_p), X.shape[0],
+                                            C.byref(params), C.byref(h)))
+        self._h = h
+        self.n = X.shape[0]
+        L = C.c_int32()
+        _check(lib().h2ulv_structure_levels(h, C.byref(L)))
+        self.L = int(L.value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.h2ulv_structure_destroy(h)
+            self._h = None
+
+    def perm(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.int64)
+        _check(lib().h2ulv_structure_perm(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def lists(self, lev: int):
+        nb = 1 << lev
+        npt = np.empty(nb + 1, dtype=np.int64)
+        fpt = np.empty(nb + 1, dtype=np.int64)
+        _check(lib().h2ulv_structure_lists(self._h, lev, npt.ctypes.data_as(C.c_void_p), None,
+                                           fpt.ctypes.data_as(C.c_void_p), None))
+        nix = np.empty(max(int(npt[-1]), 1), dtype=np.int32)
+        fix = np.empty(max(int(fpt[-1]), 1), dtype=np.int32)
+        _check(lib().h2ulv_structure_lists(self._h, lev, npt.ctypes.data_as(C.c_void_p),
+                                           nix.ctypes.data_as(C.c_void_p),
+                                           fpt.ctypes.data_as(C.c_void_p),
+                                           fix.ctypes.data_as(C.c_void_p)))
+        near = [nix[npt[i]:npt[i + 1]].tolist() for i in range(nb)]
+        far = [fix[fpt[i]:fpt[i + 1]].tolist() for i in range(nb)]
+        return near, far
+
+    def geometry(self, lev: int):
+        nb = 1 << lev
+        c = np.empty(nb * 3, dtype=np.float64)
+        r = np.empty(nb, dtype=np.float64)
+        _check(lib().h2ulv_structure_geometry(self._h, lev, c.ctypes.data_as(C.c_void_p),
+                                              r.ctypes.data_as(C.c_void_p)))
+        return c.reshape(nb, 3), r

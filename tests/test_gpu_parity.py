@@ -1,0 +1,202 @@
+"""GPU parity: the HIP library (through the C-ABI) against the CPU oracle on the
+same seeded inputs.
+
+Bar (FP64 path): integer structure (ranks k, skeleton indices in pivot order)
+identical; solution within 1e-10 relative of the oracle's; log|det| and the
+algorithmic flop count equal to rounding.  Where the oracle cannot run the full
+size, a sample of leaf boxes is checked box by box (the oracle restricted to the
+boxes they depend on) and the solution is checked through its residual with the
+exact matvec, a property that holds at any size.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import h2ulv_ref as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+H = pytest.importorskip("paper_2208_10907_amd.h2ulv")
+
+X_TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    H.lib()
+
+
+def _params(op: O.Params, **kw):
+    return H.make_params(kernel=op.kernel, alpha=op.alpha, diag=op.diag, eta=op.eta,
+                         leaf=op.leaf, tol=op.tol, rank_cap=op.rank_cap,
+                         far_sample=op.far_sample, **kw)
+
+
+def _compare_structure(fg, fo):
+    L = fo.tree.L
+    assert fg.levels() == L
+    assert np.array_equal(fg.perm(), fo.tree.perm)
+    for lev in range(L, 0, -1):
+        m, k = fg.ranks(lev)
+        assert np.array_equal(m, [b.m for b in fo.levels[lev]]), f"m differs at level {lev}"
+        assert np.array_equal(k, [b.k for b in fo.levels[lev]]), f"k differs at level {lev}"
+        for i in range(1 << lev):
+            _compare_skeleton(fg.skeleton(lev, i), fo.levels[lev][i], (lev, i))
+
+
+def _compare_skeleton(sk_gpu, bo, where):
+    """Skeleton indices in pivot order must agree while the pivot norm is above
+    rounding noise (1e-10 |R_00|); pivots below it are ties decided by rounding,
+    so the tail is compared as a set."""
+    k = bo.k
+    dg = bo.absdiag
+    nz = k
+    if dg is not None and len(dg) and dg[0] > 0:
+        nz = min(k, int(np.sum(dg[:k] > 1e-10 * dg[0])))
+    assert np.array_equal(sk_gpu[:nz], bo.sk[:nz]), where
+    assert sorted(sk_gpu[nz:].tolist()) == sorted(bo.sk[nz:].tolist()) or k < bo.m, where
+
+
+def _parity(X, op, nrhs=1, rhs_seed=7, check_basis=True):
+    fo = O.factorize(X, op)
+    fg = H.factorize(X, _params(op))
+    _compare_structure(fg, fo)
+    if check_basis:
+        lev = fo.tree.L
+        for i in (0, (1 << lev) - 1) if lev else ():
+            U = fg.basis(lev, i)
+            Uo = fo.levels[lev][i].U
+            k = fo.levels[lev][i].k
+            assert np.abs(U.T @ U - np.eye(U.shape[0])).max() < 1e-13 * max(1, U.shape[0])
+            if k:
+                Pg = U[:, :k] @ U[:, :k].T
+                Po = Uo[:, :k] @ Uo[:, :k].T
+                assert np.abs(Pg - Po).max() < 1e-7
+    b = W.gaussian_rhs(X.shape[0], nrhs, rhs_seed)
+    xo = O.solve(fo, b)
+    xg = fg.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+    rel = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    assert rel < X_TOL, rel
+    st = fg.stats()
+    assert abs(st["logabsdet"] - O.logabsdet(fo)) <= 1e-10 * abs(O.logabsdet(fo))
+    assert abs(st["flops"] - O.total_flops(fo)) <= 1e-9 * O.total_flops(fo)
+    return fg, fo
+
+
+def test_small_cube_fp64():
+    """N=2048 unit cube, leaf 64, tol 1e-8, cap 32, one RHS (exact far field)."""
+    prob = W.small_cube()
+    _parity(prob.points, O.params_from_problem(prob), nrhs=1, rhs_seed=prob.rhs_seed)
+
+
+@pytest.mark.parametrize("n,leaf,tol,cap,fs,nrhs", [
+    (3000, 64, 1e-6, 0, 32, 3),      # ragged leaves, sampled far field, rank growth
+    (4096, 128, 1e-8, 0, 32, 1),     # several 64-tiles per block, ranks > 256 above
+    (1500, 40, 0.0, 0, 0, 2),        # tol 0: no truncation (k = m)
+    (1200, 64, 1e-3, 1, 16, 1),      # rank cap 1
+])
+def test_cube_variants(n, leaf, tol, cap, fs, nrhs):
+    X = W.cube_points(n, n)
+    _parity(X, O.Params(leaf=leaf, tol=tol, rank_cap=cap, far_sample=fs), nrhs=nrhs)
+
+
+def test_yukawa_boxes():
+    X = W.box_problem(0)[:2500]
+    _parity(X, O.Params(kernel=O.YUKAWA, alpha=0.5, leaf=128, tol=1e-7, far_sample=32))
+
+
+def test_hss_limit_and_sphere():
+    _parity(W.sphere_points(2000, 4), O.Params(leaf=64, tol=1e-7, eta=0.0, far_sample=32))
+
+
+@pytest.mark.parametrize("n", [1, 2, 50])
+def test_root_only(n):
+    X = W.cube_points(n, 11)
+    _parity(X, O.Params(leaf=64, tol=1e-8, far_sample=0), nrhs=2, check_basis=False)
+
+
+def test_matvec_exact():
+    X = W.sphere_points(3000, 5)
+    op = O.Params(kernel=O.YUKAWA, alpha=0.5, leaf=128)
+    fg = H.factorize(X, _params(op))
+    x = W.gaussian_rhs(3000, 9, 3)
+    y = fg.matvec(torch.tensor(x, device="cuda")).cpu().numpy()
+    yo = O.matvec_exact(X, x, op)
+    assert np.linalg.norm(y - yo) / np.linalg.norm(yo) < 1e-14
+
+
+def test_refine_and_not_converged():
+    X = W.cube_points(4000, 6)
+    op = O.Params(leaf=64, tol=1e-4, far_sample=32)
+    fg = H.factorize(X, _params(op))
+    b = torch.tensor(W.gaussian_rhs(4000, 4, 8), device="cuda")
+    x, it, rel = fg.refine(b, rtol=1e-10, max_iter=20)
+    assert rel <= 1e-10 and it >= 1
+    r = b.cpu().numpy() - O.matvec_exact(X, x.cpu().numpy(), op)
+    assert np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(b.cpu().numpy(), axis=0)) < 2e-10
+    with pytest.raises(H.H2ULVError) as e:
+        fg.refine(b, rtol=1e-15, max_iter=0)
+    assert e.value.status == H.ERR_NOT_CONVERGED
+
+
+def test_error_statuses():
+    X = W.cube_points(300, 2)
+    X[10] = X[200]
+    with pytest.raises(H.H2ULVError) as e:
+        H.factorize(X, H.make_params(leaf=64))
+    assert e.value.status == H.ERR_DUPLICATE_POINTS
+    with pytest.raises(H.H2ULVError) as e:
+        H.factorize(W.cube_points(1, 1), H.make_params(leaf=64, diag=0.0))
+    assert e.value.status == H.ERR_SINGULAR
+
+
+def test_deterministic():
+    X = W.cube_points(3000, 12)
+    p = H.make_params(leaf=64, tol=1e-7)
+    b = torch.tensor(W.gaussian_rhs(3000, 2, 1), device="cuda")
+    x1 = H.factorize(X, p).solve(b)
+    x2 = H.factorize(X, p).solve(b)
+    assert torch.equal(x1, x2)
+
+
+def test_batch_equals_single():
+    probs = [W.cube_points(n, 40 + n) for n in (700, 1500, 2600)]
+    p = H.make_params(kernel=H.YUKAWA, alpha=0.5, leaf=64, tol=1e-7)
+    fb = H.factorize_batch(probs, p)
+    for X, f in zip(probs, fb):
+        b = torch.tensor(W.gaussian_rhs(X.shape[0], 1, 5), device="cuda")
+        assert torch.allclose(f.solve(b), H.factorize(X, p).solve(b), rtol=0, atol=1e-13)
+
+
+def _sampled_leaf_parity(prob, boxes, precision=H.FP64):
+    op = O.params_from_problem(prob)
+    fg = H.factorize(prob.points, H.params_from_problem(prob, precision=precision))
+    L = fg.levels()
+    fo = O.factorize(prob.points, op, level_stop=L, boxes=set(boxes))
+    m, k = fg.ranks(L)
+    for i in boxes:
+        bo = fo.levels[L][i]
+        assert k[i] == bo.k and m[i] == bo.m, (i, k[i], bo.k)
+        _compare_skeleton(fg.skeleton(L, i), bo, (L, i))
+        U = fg.basis(L, i)
+        Pg = U[:, :bo.k] @ U[:, :bo.k].T
+        Po = bo.U[:, :bo.k] @ bo.U[:, :bo.k].T
+        assert np.abs(Pg - Po).max() < 1e-7
+    return fg
+
+
+def test_sphere_65536_sampled():
+    """N=65536 on the sphere, leaf 256, tol 1e-8, cap 128, 16 RHS: leaf boxes
+    checked against the oracle one by one; the solve through its residual."""
+    prob = W.sphere65k()
+    fg = _sampled_leaf_parity(prob, [0, 77, 255])
+    b = torch.tensor(prob.rhs(), device="cuda")
+    x = fg.solve(b)
+    r = b - fg.matvec(x)
+    rel = (torch.linalg.norm(r, dim=0) / torch.linalg.norm(b, dim=0)).max().item()
+    assert rel < 1e-3
+    x2, it, rr = fg.refine(b, rtol=1e-10, max_iter=30)
+    assert rr <= 1e-10
