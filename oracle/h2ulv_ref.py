@@ -427,9 +427,18 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
         nb = 1 << lev
         Pl = P[lev]
         m = [len(Pl[i]) for i in range(nb)]
+        # rows needed when only a sample of boxes of the stopping level is wanted:
+        # the sample, their near boxes (whose LU and solves feed the fill-ins)
+        need = None
+        if level_stop is not None and lev == level_stop and boxes is not None:
+            need = set(boxes)
+            for i in boxes:
+                need.update(near[lev][i])
         # (a) dense blocks
         D = {}
         for i in range(nb):
+            if need is not None and i not in need:
+                continue
             for j in near[lev][i]:
                 if lev == L:
                     D[i, j] = kernel_block(X, Pl[i], Pl[j], p)
@@ -443,7 +452,7 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
         dlu = {}
         Y = {}
         for k in range(nb):
-            if m[k] == 0:
+            if m[k] == 0 or (need is not None and k not in need):
                 continue
             dlu[k] = lu(D[k, k])
             flops["fill"] += 2.0 / 3.0 * m[k] ** 3
