@@ -417,23 +417,28 @@ void Factorizer::level(int lev) {
   DBuf PQ(std::max<int64_t>(offSq[nb], 1) * sizeof(double));
   DBuf pivd(std::max<int64_t>(cand_off[nb], 1) * sizeof(int32_t));
   DBuf kd(std::max(nb, 1) * sizeof(int32_t));
+  H2ULV_HIP(hipMemsetAsync(PQ.p, 0, PQ.bytes, s));
   {
     size_t freeb = 0, totb = 0;
     H2ULV_HIP(hipMemGetInfo(&freeb, &totb));
-    int64_t budget = (int64_t)(freeb * 0.5) / (int64_t)sizeof(double);
+    int64_t budget = (int64_t)(freeb * 0.4) / (int64_t)sizeof(double);
     budget = std::max<int64_t>(budget, 1 << 20);
+    auto box_words = [&](int i) {
+      // M'^T plus the QR workspaces of its chunks (reflector panels, T, GEMM scratch)
+      return (int64_t)m[i] * ncols[i] * 3 / 2 + 8 * (int64_t)m[i] * m[i] + 4096;
+    };
     int i0 = 0;
     while (i0 < nb) {
       int i1 = i0;
       int64_t acc = 0;
-      while (i1 < nb && (i1 == i0 || acc + (int64_t)m[i1] * ncols[i1] + offSq[i1 + 1] - offSq[i1] <= budget)) {
-        acc += (int64_t)m[i1] * ncols[i1] + (offSq[i1 + 1] - offSq[i1]);
+      while (i1 < nb && (i1 == i0 || acc + box_words(i1) <= budget)) {
+        acc += box_words(i1);
         ++i1;
       }
+      // M'^T (ncols x m, column-major): far-field rows then fill-in rows
       std::vector<int64_t> moff(i1 - i0 + 1, 0);
       for (int i = i0; i < i1; ++i) moff[i - i0 + 1] = moff[i - i0] + (int64_t)m[i] * ncols[i];
       DBuf Mb(std::max<int64_t>(moff.back(), 1) * sizeof(double));
-      DBuf RTb(std::max<int64_t>(offSq[i1] - offSq[i0], 1) * sizeof(double));
       double* Mp = Mb.as<double>();
       KgenBatch kb;
       GemmBatch<double> g;
@@ -447,51 +452,145 @@ void Factorizer::level(int lev) {
       for (int i = i0; i < i1; ++i) {
         if (m[i] == 0) continue;
         double* Mi = Mp + moff[i - i0];
+        const int64_t ld = ncols[i];
         int64_t nf = (int64_t)farcols[i].size();
-        kb.add(candp(i), m[i], dfc + fc_off[i - i0], (int)nf, Mi, m[i]);
+        kb.add(dfc + fc_off[i - i0], (int)nf, candp(i), m[i], Mi, ld);
         kevals += (double)m[i] * nf;
-        int64_t col = nf;
+        int64_t row = nf;
         for (int j : targets[i]) {
           if (m[j] > 0) {
-            g.item(Mi + col * m[i], m[i], m[i], m[j]);
+            // (T^-1 F_ij)^T = sum_k D_kj^T Z'_ik^T
+            g.item(Mi + row, ld, m[j], m[i]);
             for (int64_t e = np[i]; e < np[i + 1]; ++e) {
               int k = ni[e];
               if (k == i || k == j || m[k] == 0) continue;
               int64_t ekj = csr_find(np, ni, k, j);
               if (ekj < 0) continue;
-              g.term(Zp + Doff[e], m[i], false, Dp + Doff[ekj], m[k], false, m[k]);
+              g.term(Dp + Doff[ekj], m[k], true, Zp + Doff[e], m[i], true, m[k]);
               flops_fill += 2.0 * m[i] * (double)m[k] * m[j];
             }
           }
-          col += m[j];
+          row += m[j];
         }
       }
       kb.run(st, F.pts.as<double>(), kf, dup);
       g.run(st);
       tick("c_fill_gemm");
-      // tall QR by folding, then the pivoted QR of its triangle
-      std::vector<FoldItem> fold;
-      CopyBatch tr;
-      std::vector<PivQrItem> pq;
-      int maxm = 0;
-      double* nrm = st.scratch<double>(std::max<int64_t>(cand_off[i1] - cand_off[i0], 1));
-      double* dg = st.scratch<double>(std::max<int64_t>(cand_off[i1] - cand_off[i0], 1));
+      // tall QR of every M'^T: a tree of blocked Householder QRs (leaf chunks of
+      // 4m rows factored in place, then stacked triangles merged pairwise)
+      struct Rref {
+        double* p;
+        int64_t ld;
+        int r;
+      };
+      std::vector<std::vector<Rref>> cur(i1 - i0);
+      std::vector<TallQr> leaf;
       for (int i = i0; i < i1; ++i) {
-        if (m[i] == 0) continue;
-        double* RTi = RTb.as<double>() + (offSq[i] - offSq[i0]);
-        FoldItem fi;
-        fi.X = Mp + moff[i - i0];
-        fi.ldx = m[i];
-        fi.m = m[i];
-        fi.pad = 0;
-        fi.n = ncols[i];
-        fi.RT = RTi;
-        fold.push_back(fi);
-        maxm = std::max(maxm, m[i]);
-        double* PQi = PQ.as<double>() + offSq[i];
-        tr.add(RTi, m[i], PQi, m[i], m[i], m[i], true);
-        int capeff = (int)std::min<int64_t>(m[i], ncols[i]);
-        if (F.p.rank_cap > 0) capeff = std::min(capeff, F.p.rank_cap);
+        if (m[i] == 0 || ncols[i] == 0) continue;
+        double* Mi = Mp + moff[i - i0];
+        const int64_t h = std::max<int64_t>(4 * (int64_t)m[i], 256);
+        for (int64_t r0 = 0; r0 < ncols[i]; r0 += h) {
+          int hc = (int)std::min<int64_t>(h, ncols[i] - r0);
+          leaf.push_back(TallQr{Mi + r0, ncols[i], hc, m[i]});
+          cur[i - i0].push_back(Rref{Mi + r0, ncols[i], std::min(hc, m[i])});
+        }
+        double nc = (double)ncols[i], mm = (double)m[i];
+        flops_basis += (nc >= mm) ? 2.0 * nc * mm * mm - 2.0 / 3.0 * mm * mm * mm
+                                  : 2.0 * mm * nc * nc - 2.0 / 3.0 * nc * nc * nc;
+      }
+      batched_qr_R(st, leaf);
+      std::vector<DBuf> rounds;
+      for (;;) {
+        int64_t words = 0;
+        bool more = false;
+        for (auto& v : cur)
+          for (size_t q = 0; q + 1 < v.size(); q += 2) {
+            words += (int64_t)(v[q].r + v[q + 1].r) * m[i0 + (&v - &cur[0])];
+            more = true;
+          }
+        if (!more) break;
+        DBuf buf(std::max<int64_t>(words, 1) * sizeof(double));
+        double* bp = buf.as<double>();
+        int64_t off = 0;
+        CopyBatch cb;
+        std::vector<CopyItem> zl;
+        std::vector<TallQr> qs;
+        for (size_t bi = 0; bi < cur.size(); ++bi) {
+          auto& v = cur[bi];
+          const int mi = m[i0 + (int)bi];
+          std::vector<Rref> nxt;
+          for (size_t q = 0; q < v.size(); q += 2) {
+            if (q + 1 == v.size()) {
+              nxt.push_back(v[q]);
+              continue;
+            }
+            const Rref& ra = v[q];
+            const Rref& rb = v[q + 1];
+            const int hs = ra.r + rb.r;
+            double* S = bp + off;
+            off += (int64_t)hs * mi;
+            cb.add(ra.p, ra.ld, S, hs, ra.r, mi);
+            cb.add(rb.p, rb.ld, S + ra.r, hs, rb.r, mi);
+            zl.push_back(CopyItem{nullptr, S, 0, hs, ra.r, mi, 0, 0});
+            zl.push_back(CopyItem{nullptr, S + ra.r, 0, hs, rb.r, mi, 0, 0});
+            qs.push_back(TallQr{S, hs, hs, mi});
+            nxt.push_back(Rref{S, hs, std::min(hs, mi)});
+          }
+          v.swap(nxt);
+        }
+        cb.run(st);
+        int nz = (int)zl.size();
+        CopyItem* dz = st.up(std::move(zl));
+        launch_zero_lower(dz, nz, s);
+        H2ULV_HIP(hipGetLastError());
+        batched_qr_R(st, qs);
+        rounds.push_back(std::move(buf));
+      }
+      // final triangles into the m x m pivoted-QR matrices (zero below)
+      {
+        CopyBatch cb;
+        std::vector<CopyItem> zl;
+        for (size_t bi = 0; bi < cur.size(); ++bi) {
+          if (cur[bi].empty()) continue;
+          const int i = i0 + (int)bi;
+          const Rref& r = cur[bi][0];
+          double* PQi = PQ.as<double>() + offSq[i];
+          cb.add(r.p, r.ld, PQi, m[i], r.r, m[i]);
+          zl.push_back(CopyItem{nullptr, PQi, 0, m[i], r.r, m[i], 0, 0});
+        }
+        cb.run(st);
+        int nz = (int)zl.size();
+        CopyItem* dz = st.up(std::move(zl));
+        launch_zero_lower(dz, nz, s);
+        H2ULV_HIP(hipGetLastError());
+      }
+      tick("c_tsqr");
+      st.sync();
+      i0 = i1;
+    }
+  }
+  // column-pivoted QR of each m x m triangle: small boxes one workgroup each,
+  // large boxes over many workgroups, one step per pair of launches
+  std::vector<int> capeff(nb, 0);
+  for (int i = 0; i < nb; ++i) {
+    capeff[i] = (int)std::min<int64_t>(m[i], ncols[i]);
+    if (F.p.rank_cap > 0) capeff[i] = std::min(capeff[i], F.p.rank_cap);
+  }
+  const int BIG = 512;
+  DBuf Ebuf;
+  std::vector<int64_t> offE(nb + 1, 0);
+  {
+    std::vector<PivQrItem> pq;
+    std::vector<PivQrState> big;
+    std::vector<int> bigid;
+    double* nrm = st.scratch<double>(std::max<int64_t>(cand_off[nb], 1));
+    double* dg = st.scratch<double>(std::max<int64_t>(cand_off[nb], 1));
+    double* scal = st.scratch<double>(2 * (size_t)nb + 2);
+    int32_t* flg = st.scratch<int32_t>(2 * (size_t)nb + 2);
+    for (int i = 0; i < nb; ++i) {
+      if (m[i] == 0) continue;
+      double* PQi = PQ.as<double>() + offSq[i];
+      if (m[i] <= BIG) {
         PivQrItem it{};
         it.A = PQi;
         it.lda = m[i];
@@ -499,45 +598,77 @@ void Factorizer::level(int lev) {
         it.n = m[i];
         it.piv = pivd.as<int32_t>() + cand_off[i];
         it.kout = kd.as<int32_t>() + i;
-        it.diag = dg + (cand_off[i] - cand_off[i0]);
-        it.work = nrm + (cand_off[i] - cand_off[i0]);
+        it.diag = dg + cand_off[i];
+        it.work = nrm + cand_off[i];
         it.tol = F.p.tol;
-        it.cap = capeff;
+        it.cap = std::max(capeff[i], 0);
         pq.push_back(it);
-        double nc = (double)ncols[i], mm = (double)m[i];
-        flops_basis += (nc >= mm) ? 2.0 * nc * mm * mm - 2.0 / 3.0 * mm * mm * mm
-                                  : 2.0 * mm * nc * nc - 2.0 / 3.0 * nc * nc * nc;
+      } else {
+        PivQrState ps{};
+        ps.A = PQi;
+        ps.lda = m[i];
+        ps.m = m[i];
+        ps.cap = capeff[i];
+        ps.nrm = nrm + cand_off[i];
+        ps.piv = pivd.as<int32_t>() + cand_off[i];
+        ps.scal = scal + 2 * i;
+        ps.flags = flg + 2 * i;
+        ps.tol = F.p.tol;
+        big.push_back(ps);
+        bigid.push_back(i);
       }
-      // one launch per row-count bucket, so that each box's fold (and its
-      // rounding) depends only on its own size
-      {
-        const int bounds[6] = {256, 512, 1024, 2048, 4096, 1 << 30};
-        int lo = 0;
-        for (int bk = 0; bk < 6; ++bk) {
-          std::vector<FoldItem> part;
-          for (auto& f : fold)
-            if (f.m > lo && f.m <= bounds[bk]) part.push_back(f);
-          lo = bounds[bk];
-          if (part.empty()) continue;
-          int np_ = (int)part.size();
-          int mx = 0;
-          for (auto& f : part) mx = std::max(mx, f.m);
-          FoldItem* dfold = st.up(std::move(part));
-          launch_tsqr_fold(dfold, np_, mx, s);
-          H2ULV_HIP(hipGetLastError());
-        }
-      }
-      (void)maxm;
-      tick("c_tsqr");
-      tr.run(st);
-      int npq = (int)pq.size();
-      PivQrItem* dpq = st.up(std::move(pq));
-      launch_pivqr(dpq, npq, s);
-      H2ULV_HIP(hipGetLastError());
-      tick("c_pivqr");
-      st.sync();
-      i0 = i1;
     }
+    int npq = (int)pq.size();
+    PivQrItem* dpq = st.up(std::move(pq));
+    launch_pivqr(dpq, npq, s);
+    H2ULV_HIP(hipGetLastError());
+    if (!big.empty()) {
+      int nbig = (int)big.size();
+      int maxcap = 0;
+      std::vector<int64_t> sp(1, 0);
+      for (auto& b : big) {
+        sp.push_back(sp.back() + (b.m + 3) / 4);
+        maxcap = std::max(maxcap, b.cap);
+      }
+      int64_t ns = sp.back();
+      PivQrState* dst_ = st.up(std::move(big));
+      int64_t* dsp = st.up(std::move(sp));
+      launch_pivqr_init(dst_, dsp, ns, nbig, s);
+      for (int t = 0; t < maxcap; ++t) {
+        launch_pivqr_pick(dst_, nbig, t, s);
+        launch_pivqr_apply(dst_, dsp, ns, nbig, t, s);
+      }
+      H2ULV_HIP(hipGetLastError());
+      std::vector<int32_t> hf(2 * (size_t)nb + 2);
+      H2ULV_HIP(hipMemcpyAsync(hf.data(), flg, hf.size() * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+      H2ULV_HIP(hipStreamSynchronize(s));
+      // E = R11^-1 R12 by triangular blocks
+      for (int i : bigid) lf.k[i] = hf[2 * i + 1];
+      for (int i = 0; i < nb; ++i) {
+        bool isbig = m[i] > BIG;
+        offE[i + 1] = offE[i] + (isbig ? (int64_t)lf.k[i] * (m[i] - lf.k[i]) : 0);
+      }
+      Ebuf.alloc(std::max<int64_t>(offE[nb], 1) * sizeof(double));
+      std::vector<TriRhs> sys;
+      for (int i : bigid) {
+        int ki = lf.k[i];
+        if (ki == 0 || ki == m[i]) continue;
+        double* PQi = PQ.as<double>() + offSq[i];
+        sys.push_back(TriRhs{PQi, m[i], ki, PQi + (int64_t)ki * m[i], m[i],
+                             Ebuf.as<double>() + offE[i], ki, m[i] - ki});
+      }
+      trsm_upper(st, sys);
+      std::vector<int32_t> hk(2);
+      for (int i : bigid) {
+        hk[0] = lf.k[i];
+        H2ULV_HIP(hipMemcpyAsync(kd.as<int32_t>() + i, hk.data(), sizeof(int32_t),
+                                 hipMemcpyHostToDevice, s));
+        H2ULV_HIP(hipStreamSynchronize(s));
+      }
+    }
+    tick("c_pivqr");
+    st.sync();
   }
   Z.reset();
   check_dup();
@@ -574,9 +705,12 @@ void Factorizer::level(int lev) {
     std::vector<WpItem> wi;
     for (int i = 0; i < nb; ++i) {
       if (k[i] == 0) continue;
-      wi.push_back(WpItem{pivd.as<int32_t>() + cand_off[i], PQ.as<double>() + offSq[i],
-                          (upper ? Wp.as<double>() : W.as<double>()) + offW[i], m[i], m[i], m[i],
-                          k[i]});
+      const bool isbig = m[i] > BIG;
+      const double* E = isbig ? Ebuf.as<double>() + offE[i]
+                              : PQ.as<double>() + offSq[i] + (int64_t)k[i] * m[i];
+      wi.push_back(WpItem{pivd.as<int32_t>() + cand_off[i], E,
+                          (upper ? Wp.as<double>() : W.as<double>()) + offW[i],
+                          isbig ? std::max(k[i], 1) : m[i], m[i], m[i], k[i]});
     }
     int nw = (int)wi.size();
     WpItem* dwi = st.up(std::move(wi));
@@ -611,6 +745,7 @@ void Factorizer::level(int lev) {
   }
   PQ.reset();
   pivd.reset();
+  Ebuf.reset();
   tick("c_basis_qr");
 
   // new skeleton blocks of this level: near pairs then far pairs

@@ -239,6 +239,58 @@ void batched_triu_inverse(Stage& st, const std::vector<SqMat>& mats) {
   trsm_upper(st, up);
 }
 
+// Blocked Householder QR of tall (or short) matrices, R only: the panel of nb
+// columns is factored by one workgroup, the trailing columns are updated by
+// three GEMMs with the explicit panel reflectors and their T factor.
+void batched_qr_R(Stage& st, const std::vector<TallQr>& ms) {
+  if (ms.empty()) return;
+  const int nb = QR_NB;
+  int maxk = 0;
+  std::vector<MatDesc> ds;
+  std::vector<double*> Vb, Tfb, Y1b, Y2b;
+  for (auto& a : ms) {
+    MatDesc d{};
+    d.A = a.A;
+    d.lda = a.lda;
+    d.m = a.h;
+    d.n = a.m;
+    d.V = st.scratch<double>(std::max<int64_t>((int64_t)a.h * nb, 1));
+    d.aux = st.scratch<double>(std::max(a.m, 1));
+    d.Tf = st.scratch<double>((int64_t)nb * nb);
+    d.panel_ws = 1;
+    Vb.push_back(d.V);
+    Tfb.push_back(d.Tf);
+    Y1b.push_back(st.scratch<double>(std::max<int64_t>((int64_t)nb * a.m, 1)));
+    Y2b.push_back(st.scratch<double>(std::max<int64_t>((int64_t)nb * a.m, 1)));
+    ds.push_back(d);
+    maxk = std::max(maxk, std::min(a.h, a.m));
+  }
+  const int nmat = (int)ms.size();
+  MatDesc* dd = st.up(std::move(ds));
+  for (int j0 = 0; j0 < maxk; j0 += nb) {
+    launch_qr_panel(dd, nmat, j0, nb, st.s);
+    H2ULV_HIP(hipGetLastError());
+    GemmBatch<double> g1, g2, g3;
+    for (size_t b = 0; b < ms.size(); ++b) {
+      const TallQr& a = ms[b];
+      int kk = std::min(a.h, a.m);
+      if (kk <= j0) continue;
+      int wd = std::min(nb, kk - j0);
+      int ntr = a.m - j0 - wd;
+      if (ntr <= 0) continue;
+      int rows = a.h - j0;
+      const double* Vp = Vb[b] + j0;
+      double* At = a.A + j0 + (int64_t)(j0 + wd) * a.lda;
+      g1.one(Y1b[b], nb, wd, ntr, rows, Vp, a.h, true, At, a.lda, false);
+      g2.one(Y2b[b], nb, wd, ntr, wd, Tfb[b], nb, true, Y1b[b], nb, false);
+      g3.one(At, a.lda, rows, ntr, wd, Vp, a.h, false, Y2b[b], nb, false, -1.0, 1.0);
+    }
+    g1.run(st);
+    g2.run(st);
+    g3.run(st);
+  }
+}
+
 // Householder QR of W (m x k, overwritten), explicit U (m x m) and T = R(1:k,1:k).
 void batched_qr_basis(Stage& st, const std::vector<QrW>& ws) {
   if (ws.empty()) return;

@@ -32,6 +32,16 @@ struct QrW {
   double* T;  // k x k (ld k) result
 };
 
+// Tall (or short) matrix factored in place by blocked Householder QR; on
+// return its upper triangle (rows < min(h, m)) holds R.
+struct TallQr {
+  double* A;
+  int64_t lda;
+  int h;  // rows
+  int m;  // columns
+};
+
+void batched_qr_R(Stage& st, const std::vector<TallQr>& ms);
 void trsm_lower_unit(Stage& st, const std::vector<TriRhs>& sys);
 void trsm_upper(Stage& st, const std::vector<TriRhs>& sys);
 void batched_lu(Stage& st, const std::vector<SqMat>& mats, int32_t* ipiv, int32_t* info,

@@ -51,6 +51,8 @@ struct MatDesc {
   double* V;      // QR: explicit reflector block (ld = m), panel columns
   double* Tf;     // QR: block-reflector T factors, nb x nb per panel
   int32_t* info;  // per-matrix flag (singular / status)
+  int32_t panel_ws;  // QR: V and Tf hold only the current panel
+  int32_t pad;
 };
 
 // Generic batched 2-D copy: dst[i + j*ldd] = alpha * src(i, j) (+ beta dst)
@@ -78,15 +80,18 @@ struct PivQrItem {
   int32_t pad;
 };
 
-// Tall QR by row-chunk folding: X is m x n (column-major, ld ldx); the
-// triangular factor of X^T is written transposed into RT (m x m, ld m).
-struct FoldItem {
-  const double* X;
-  int64_t ldx;
+// Column-pivoted QR of one large matrix spread over many workgroups, one step
+// per pair of launches (pick/reflect, then apply/renormalise).
+struct PivQrState {
+  double* A;       // m x m, in place
+  int64_t lda;
   int32_t m;
-  int32_t pad;
-  int64_t n;
-  double* RT;
+  int32_t cap;     // steps allowed: min(m, ncols, cap)
+  double* nrm;     // m column norms
+  int32_t* piv;    // m pivots
+  double* scal;    // [0] tau of the current step, [1] threshold tol |R_00|
+  int32_t* flags;  // [0] stopped, [1] rank k so far
+  double tol;
 };
 
 // Dense P^T from LU interchanges (ipiv == nullptr gives the identity).
@@ -98,10 +103,10 @@ struct PermItem {
   int32_t pad;
 };
 
-// Row-ID matrix W' from pivots and E = R11^-1 R12.
+// Row-ID matrix W' from pivots and E = R11^-1 R12 (k x (m-k)).
 struct WpItem {
   const int32_t* piv;
-  const double* E;  // E(t, s) at E[t + s * ldE] for s >= k
+  const double* E;  // E(t, s) at E[t + s * ldE], s < m - k
   double* W;        // m x k, ld ldW
   int64_t ldE, ldW;
   int32_t m, k;
@@ -120,7 +125,11 @@ void launch_lu_swap_trsm(const MatDesc* d, const int64_t* slab_ptr, int64_t nsla
 void launch_trinv_diag(const MatDesc* d, const int64_t* blk_ptr, int64_t nblk, int nmat, int nb,
                        int upper, double* out, const int64_t* out_off, hipStream_t s);
 void launch_qr_panel(const MatDesc* d, int nmat, int j0, int nb, hipStream_t s);
-void launch_tsqr_fold(const FoldItem* items, int nitems, int max_m, hipStream_t s);
+void launch_pivqr_init(const PivQrState* st, const int64_t* slab_ptr, int64_t nslabs, int n,
+                       hipStream_t s);
+void launch_pivqr_pick(const PivQrState* st, int n, int t, hipStream_t s);
+void launch_pivqr_apply(const PivQrState* st, const int64_t* slab_ptr, int64_t nslabs, int n,
+                        int t, hipStream_t s);
 void launch_pivqr(const PivQrItem* items, int nitems, hipStream_t s);
 void launch_copy(const CopyItem* items, const int64_t* tile_ptr, int64_t ntiles, int nitems,
                  double alpha, double beta, hipStream_t s);

@@ -436,7 +436,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc* __restrict
   const int w = min(nb, min(n, m) - j0);
   double* A = d.A;
   const int64_t lda = d.lda;
-  double* V = d.V + (int64_t)j0 * m;  // panel reflectors, ld = m
+  double* V = d.panel_ws ? d.V : d.V + (int64_t)j0 * m;  // panel reflectors, ld = m
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int jj = 0; jj < w; ++jj) {
     const int col = j0 + jj;
@@ -488,7 +488,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc* __restrict
   }
   // T factor (forward, columnwise): T[jj][jj] = tau_jj,
   // T[0:jj, jj] = -tau_jj T[0:jj, 0:jj] (V[:, 0:jj]^T v_jj)
-  double* Tf = d.Tf + (int64_t)(j0 / nb) * nb * nb;
+  double* Tf = d.panel_ws ? d.Tf : d.Tf + (int64_t)(j0 / nb) * nb * nb;
   for (int e = tid; e < nb * nb; e += 256) Tf[e] = 0.0;
   __syncthreads();
   for (int jj = 0; jj < w; ++jj) {
@@ -517,108 +517,6 @@ void launch_qr_panel(const MatDesc* d, int nmat, int j0, int nb, hipStream_t s) 
   hipLaunchKernelGGL(qr_panel_kernel, dim3(nmat), dim3(256), 0, s, d, j0, nb);
 }
 
-
-// ---------------------------------------------------------------------------
-// Householder QR of a tall matrix by folding row chunks into a running
-// triangle: R <- qr([R; C]) for consecutive chunks C of CR rows of X^T, where
-// X (m x n, column-major) is M'_i and X^T is the matrix whose column-pivoted QR
-// defines the shared basis (Sec. III-C).  The pivoted QR of the m x m factor R
-// selects the same pivots and ranks as that of X^T in exact arithmetic (both
-// depend only on X X^T = R^T R).  The chunk lives in registers (each thread
-// owns CPT columns), R lives in global memory stored transposed (row j of R is
-// contiguous) so that the per-step row reads are coalesced.
-// ---------------------------------------------------------------------------
-template <int CPT, int CR>
-__global__ __launch_bounds__(256) void tsqr_fold_kernel(const FoldItem* __restrict__ items) {
-  __shared__ double vsh[CR];
-  __shared__ double s_tau;
-  const FoldItem it = items[blockIdx.x];
-  const int m = it.m;
-  const int64_t n = it.n;
-  double* RT = it.RT;
-  const int tid = threadIdx.x;
-  for (int64_t e = tid; e < (int64_t)m * m; e += 256) RT[e] = 0.0;
-  __syncthreads();
-  double c[CPT][CR];
-  for (int64_t r0 = 0; r0 < n; r0 += CR) {
-#pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int col = tid + 256 * q;
-#pragma unroll
-      for (int i = 0; i < CR; ++i)
-        c[q][i] = (col < m && r0 + i < n) ? it.X[col + (r0 + i) * it.ldx] : 0.0;
-    }
-    for (int j = 0; j < m; ++j) {
-      const int qj = j >> 8;
-      if (tid == (j & 255)) {
-        double xv[CR];
-#pragma unroll
-        for (int i = 0; i < CR; ++i) xv[i] = 0.0;
-#pragma unroll
-        for (int q = 0; q < CPT; ++q)
-          if (q == qj) {
-#pragma unroll
-            for (int i = 0; i < CR; ++i) xv[i] = c[q][i];
-          }
-        double xn2 = 0.0;
-#pragma unroll
-        for (int i = 0; i < CR; ++i) xn2 += xv[i] * xv[i];
-        if (xn2 == 0.0) {
-          s_tau = 0.0;
-        } else {
-          const double alpha = RT[j + (int64_t)j * m];
-          const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-          const double sc = 1.0 / (alpha - beta);
-#pragma unroll
-          for (int i = 0; i < CR; ++i) vsh[i] = xv[i] * sc;
-          s_tau = (beta - alpha) / beta;
-          RT[j + (int64_t)j * m] = beta;
-#pragma unroll
-          for (int q = 0; q < CPT; ++q)
-            if (q == qj) {
-#pragma unroll
-              for (int i = 0; i < CR; ++i) c[q][i] = 0.0;
-            }
-        }
-      }
-      __syncthreads();
-      const double tau = s_tau;
-      if (tau != 0.0) {
-        double* rowj = RT + (int64_t)j * m;
-#pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-          const int col = tid + 256 * q;
-          if (col > j && col < m) {
-            double w = rowj[col];
-#pragma unroll
-            for (int i = 0; i < CR; ++i) w += vsh[i] * c[q][i];
-            w *= tau;
-            rowj[col] -= w;
-#pragma unroll
-            for (int i = 0; i < CR; ++i) c[q][i] -= w * vsh[i];
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-void launch_tsqr_fold(const FoldItem* items, int nitems, int max_m, hipStream_t s) {
-  if (nitems <= 0) return;
-  if (max_m <= 256)
-    hipLaunchKernelGGL((tsqr_fold_kernel<1, 32>), dim3(nitems), dim3(256), 0, s, items);
-  else if (max_m <= 512)
-    hipLaunchKernelGGL((tsqr_fold_kernel<2, 16>), dim3(nitems), dim3(256), 0, s, items);
-  else if (max_m <= 1024)
-    hipLaunchKernelGGL((tsqr_fold_kernel<4, 8>), dim3(nitems), dim3(256), 0, s, items);
-  else if (max_m <= 2048)
-    hipLaunchKernelGGL((tsqr_fold_kernel<8, 4>), dim3(nitems), dim3(256), 0, s, items);
-  else if (max_m <= 4096)
-    hipLaunchKernelGGL((tsqr_fold_kernel<16, 2>), dim3(nitems), dim3(256), 0, s, items);
-  else
-    hipLaunchKernelGGL((tsqr_fold_kernel<32, 1>), dim3(nitems), dim3(256), 0, s, items);
-}
 
 // ---------------------------------------------------------------------------
 // Column-pivoted Householder QR for the row interpolative decomposition
@@ -766,6 +664,185 @@ __global__ __launch_bounds__(256) void pivqr_kernel(const PivQrItem* __restrict_
 void launch_pivqr(const PivQrItem* items, int nitems, hipStream_t s) {
   if (nitems <= 0) return;
   hipLaunchKernelGGL(pivqr_kernel, dim3(nitems), dim3(256), 0, s, items);
+}
+
+
+// ---------------------------------------------------------------------------
+// Column-pivoted QR of large matrices over many workgroups.  Same decisions as
+// the one-workgroup kernel (largest exact remaining norm, lowest index on ties,
+// continue while it exceeds tol |R_00| and the cap allows), one step per pair
+// of launches: pick (one workgroup per matrix: pivot search, column swap,
+// reflector) and apply (one wave per trailing column: reflector update and
+// exact norm of the column below the new row).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void pivqr_init_kernel(const PivQrState* __restrict__ sts,
+                                                         const int64_t* __restrict__ slab_ptr,
+                                                         int n) {
+  int64_t slab = blockIdx.x;
+  int id = find_item(slab_ptr, n, slab);
+  const PivQrState st = sts[id];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = (int)(slab - slab_ptr[id]) * 4 + w;
+  if (c == 0 && threadIdx.x == 0) {
+    st.flags[0] = 0;
+    st.flags[1] = 0;
+    st.scal[0] = 0.0;
+    st.scal[1] = 0.0;
+  }
+  if (c >= st.m) return;
+  const double* ac = st.A + (int64_t)c * st.lda;
+  double p = 0.0;
+  for (int r = lane; r < st.m; r += 64) p += ac[r] * ac[r];
+  p = wave_sum(p);
+  if (lane == 0) {
+    st.nrm[c] = sqrt(p);
+    st.piv[c] = c;
+  }
+}
+
+void launch_pivqr_init(const PivQrState* st, const int64_t* slab_ptr, int64_t nslabs, int n,
+                       hipStream_t s) {
+  if (nslabs <= 0) return;
+  hipLaunchKernelGGL(pivqr_init_kernel, dim3((unsigned)nslabs), dim3(256), 0, s, st, slab_ptr, n);
+}
+
+__global__ __launch_bounds__(256) void pivqr_pick_kernel(const PivQrState* __restrict__ sts,
+                                                         int t) {
+  __shared__ double red_v[256];
+  __shared__ int red_i[256];
+  __shared__ double sh[8];
+  const PivQrState st = sts[blockIdx.x];
+  if (st.flags[0]) return;
+  const int m = st.m, tid = threadIdx.x;
+  if (t >= st.cap) {
+    if (tid == 0) st.flags[0] = 1;
+    return;
+  }
+  double best = -1.0;
+  int bi = m;
+  for (int c = t + tid; c < m; c += 256) {
+    double v = st.nrm[c];
+    if (v > best) {
+      best = v;
+      bi = c;
+    }
+  }
+  red_v[tid] = best;
+  red_i[tid] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      double vo = red_v[tid + s];
+      int io = red_i[tid + s];
+      if (vo > red_v[tid] || (vo == red_v[tid] && io < red_i[tid])) {
+        red_v[tid] = vo;
+        red_i[tid] = io;
+      }
+    }
+    __syncthreads();
+  }
+  const double pn = red_v[0];
+  const int p = red_i[0];
+  const double thr = (t == 0) ? st.tol * pn : st.scal[1];
+  const bool stop = !(pn > thr) || !(pn > 0.0) || p >= m;
+  __syncthreads();
+  if (stop) {
+    if (tid == 0) st.flags[0] = 1;
+    return;
+  }
+  double* A = st.A;
+  const int64_t lda = st.lda;
+  if (p != t) {
+    double* at = A + (int64_t)t * lda;
+    double* ap = A + (int64_t)p * lda;
+    for (int r = tid; r < m; r += 256) {
+      double x = at[r];
+      at[r] = ap[r];
+      ap[r] = x;
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && p != t) {
+    double x = st.nrm[t];
+    st.nrm[t] = st.nrm[p];
+    st.nrm[p] = x;
+    int q = st.piv[t];
+    st.piv[t] = st.piv[p];
+    st.piv[p] = q;
+  }
+  double* at = A + (int64_t)t * lda;
+  double part = 0.0;
+  for (int r = t + 1 + tid; r < m; r += 256) part += at[r] * at[r];
+  const double xn2 = block_sum256(part, sh);
+  const double alpha = at[t];
+  double tau = 0.0, scale = 0.0;
+  if (xn2 != 0.0) {
+    const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+    tau = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  __syncthreads();
+  if (tau != 0.0) {
+    for (int r = t + 1 + tid; r < m; r += 256) at[r] *= scale;
+  }
+  if (tid == 0) {
+    if (tau != 0.0) at[t] = -copysign(sqrt(alpha * alpha + xn2), alpha);
+    st.scal[0] = tau;
+    if (t == 0) st.scal[1] = thr;
+    st.flags[1] = t + 1;
+  }
+}
+
+void launch_pivqr_pick(const PivQrState* st, int n, int t, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(pivqr_pick_kernel, dim3(n), dim3(256), 0, s, st, t);
+}
+
+__global__ __launch_bounds__(256) void pivqr_apply_kernel(const PivQrState* __restrict__ sts,
+                                                          const int64_t* __restrict__ slab_ptr,
+                                                          int n, int t) {
+  int64_t slab = blockIdx.x;
+  int id = find_item(slab_ptr, n, slab);
+  const PivQrState st = sts[id];
+  // stopped before or at this step: flags[1] is the rank, equal to t + 1 only
+  // when step t was taken
+  if (st.flags[1] != t + 1) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = t + 1 + (int)(slab - slab_ptr[id]) * 4 + w;
+  if (c >= st.m) return;
+  const double tau = st.scal[0];
+  const int m = st.m;
+  const double* v = st.A + (int64_t)t * st.lda;
+  double* ac = st.A + (int64_t)c * st.lda;
+  if (tau != 0.0) {
+    double p = 0.0;
+    for (int r = t + 1 + lane; r < m; r += 64) p += v[r] * ac[r];
+    p = wave_sum(p);
+    const double wsum = (ac[t] + p) * tau;
+    double s2 = 0.0;
+    for (int r = t + 1 + lane; r < m; r += 64) {
+      double x = ac[r] - wsum * v[r];
+      ac[r] = x;
+      s2 += x * x;
+    }
+    s2 = wave_sum(s2);
+    if (lane == 0) {
+      ac[t] -= wsum;
+      st.nrm[c] = sqrt(s2);
+    }
+  } else {
+    double s2 = 0.0;
+    for (int r = t + 1 + lane; r < m; r += 64) s2 += ac[r] * ac[r];
+    s2 = wave_sum(s2);
+    if (lane == 0) st.nrm[c] = sqrt(s2);
+  }
+}
+
+void launch_pivqr_apply(const PivQrState* st, const int64_t* slab_ptr, int64_t nslabs, int n,
+                        int t, hipStream_t s) {
+  if (nslabs <= 0) return;
+  hipLaunchKernelGGL(pivqr_apply_kernel, dim3((unsigned)nslabs), dim3(256), 0, s, st, slab_ptr,
+                     n, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1016,7 +1093,7 @@ __global__ void wprime_kernel(const WpItem* __restrict__ items) {
     if (s < k)
       v = (s == t) ? 1.0 : 0.0;
     else
-      v = it.E[t + (int64_t)s * it.ldE];
+      v = it.E[t + (int64_t)(s - k) * it.ldE];
     it.W[it.piv[s] + (int64_t)t * it.ldW] = v;
   }
 }
