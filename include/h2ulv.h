@@ -207,6 +207,27 @@ h2ulv_status h2ulv_structure_geometry(const h2ulv_structure* s, int32_t lev, dou
                                       double* radius);
 void h2ulv_structure_destroy(h2ulv_structure* s);
 
+/*
+ * Kernel timing (the measurement behind the reported roofline fractions).
+ * h2ulv_profile_enable(1) clears earlier records and starts recording a pair of
+ * HIP events around every batched launch of the main kernels, on the stream
+ * the launch uses; h2ulv_profile_enable(0) stops recording.
+ * h2ulv_profile_read waits for the recorded events, aggregates them per kernel
+ * (launch count, summed duration, summed algorithmic flops and operand bytes:
+ * GEMM 2MNK flops and (MK + KN + MN) element bytes; kernel generation counts
+ * entries in `flops`) into out[0 .. min(max, count) - 1] and clears the
+ * records.  *count receives the number of distinct kernels.  Host memory.
+ */
+typedef struct h2ulv_kernel_profile {
+  char name[32];
+  int64_t launches;
+  double time_ms;
+  double flops;
+  double bytes;
+} h2ulv_kernel_profile;
+h2ulv_status h2ulv_profile_enable(int32_t on);
+h2ulv_status h2ulv_profile_read(h2ulv_kernel_profile* out, int32_t max, int32_t* count);
+
 const char* h2ulv_status_string(h2ulv_status s);
 const char* h2ulv_last_error(void);
 

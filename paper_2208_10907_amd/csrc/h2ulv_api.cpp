@@ -620,7 +620,10 @@ void Factorizer::level(int lev) {
     }
     int npq = (int)pq.size();
     PivQrItem* dpq = st.up(std::move(pq));
-    launch_pivqr(dpq, npq, s);
+    {
+      ProfScope ps("pivqr_small", 0, 0, s);
+      launch_pivqr(dpq, npq, s);
+    }
     H2ULV_HIP(hipGetLastError());
     if (!big.empty()) {
       int nbig = (int)big.size();
@@ -633,10 +636,13 @@ void Factorizer::level(int lev) {
       int64_t ns = sp.back();
       PivQrState* dst_ = st.up(std::move(big));
       int64_t* dsp = st.up(std::move(sp));
-      launch_pivqr_init(dst_, dsp, ns, nbig, s);
-      for (int t = 0; t < maxcap; ++t) {
-        launch_pivqr_pick(dst_, nbig, t, s);
-        launch_pivqr_apply(dst_, dsp, ns, nbig, t, s);
+      {
+        ProfScope ps("pivqr_large", 0, 0, s);
+        launch_pivqr_init(dst_, dsp, ns, nbig, s);
+        for (int t = 0; t < maxcap; ++t) {
+          launch_pivqr_pick(dst_, nbig, t, s);
+          launch_pivqr_apply(dst_, dsp, ns, nbig, t, s);
+        }
       }
       H2ULV_HIP(hipGetLastError());
       std::vector<int32_t> hf(2 * (size_t)nb + 2);
@@ -1457,5 +1463,54 @@ const char* h2ulv_status_string(h2ulv_status s) {
 }
 
 const char* h2ulv_last_error(void) { return g_last_error.c_str(); }
+
+h2ulv_status h2ulv_profile_enable(int32_t on) {
+  return guarded([&] {
+    Profiler& p = profiler();
+    for (auto& r : p.recs) {
+      p.pool.push_back(r.a);
+      p.pool.push_back(r.b);
+    }
+    p.recs.clear();
+    p.on = on != 0;
+  });
+}
+
+h2ulv_status h2ulv_profile_read(h2ulv_kernel_profile* out, int32_t max, int32_t* count) {
+  if (!count || (max > 0 && !out)) {
+    g_last_error = "bad profile arguments";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  return guarded([&] {
+    Profiler& p = profiler();
+    std::vector<std::string> names;
+    std::map<std::string, h2ulv_kernel_profile> agg;
+    for (auto& r : p.recs) {
+      H2ULV_HIP(hipEventSynchronize(r.b));
+      float ms = 0;
+      H2ULV_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      auto it = agg.find(r.name);
+      if (it == agg.end()) {
+        h2ulv_kernel_profile z{};
+        std::snprintf(z.name, sizeof(z.name), "%s", r.name);
+        it = agg.emplace(r.name, z).first;
+        names.push_back(r.name);
+      }
+      it->second.launches += 1;
+      it->second.time_ms += ms;
+      it->second.flops += r.flops;
+      it->second.bytes += r.bytes;
+      p.pool.push_back(r.a);
+      p.pool.push_back(r.b);
+    }
+    p.recs.clear();
+    int c = 0;
+    for (auto& nm : names) {
+      if (c < max) out[c] = agg[nm];
+      ++c;
+    }
+    *count = c;
+  });
+}
 
 }  // extern "C"

@@ -27,6 +27,53 @@ struct MemStats {
 };
 MemStats& mem_stats();
 
+// Per-kernel launch timing with HIP events recorded on the launch stream
+// (enabled through h2ulv_profile_enable).
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t ev() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+};
+Profiler& profiler();
+
+// RAII scope: records a start event now and a stop event when destroyed.
+struct ProfScope {
+  Profiler* p = nullptr;
+  ProfRec r{};
+  hipStream_t s;
+  ProfScope(const char* name, double flops, double bytes, hipStream_t st) : s(st) {
+    Profiler& pr = profiler();
+    if (!pr.on) return;
+    p = &pr;
+    r.name = name;
+    r.flops = flops;
+    r.bytes = bytes;
+    r.a = pr.ev();
+    r.b = pr.ev();
+    (void)hipEventRecord(r.a, s);
+  }
+  ~ProfScope() {
+    if (!p) return;
+    (void)hipEventRecord(r.b, s);
+    p->recs.push_back(r);
+  }
+};
+
 // Owning device buffer (hipMalloc / hipFree).
 struct DBuf {
   void* p = nullptr;
@@ -78,21 +125,62 @@ struct DBuf {
   }
 };
 
+// Pinned host staging + device memory for launch descriptors: uploads are
+// appended to the current chunk (256-byte aligned) and copied asynchronously;
+// chunks are recycled at the next synchronisation.
+struct DescArena {
+  struct Chunk {
+    char* host = nullptr;
+    DBuf dev;
+    size_t cap = 0, used = 0;
+  };
+  std::vector<Chunk> chunks;
+  ~DescArena() {
+    for (auto& c : chunks)
+      if (c.host) (void)hipHostFree(c.host);
+  }
+  void* put(const void* src, size_t bytes, hipStream_t s) {
+    size_t need = (bytes + 255) & ~(size_t)255;
+    Chunk* c = nullptr;
+    for (auto& ch : chunks)
+      if (ch.cap - ch.used >= need) {
+        c = &ch;
+        break;
+      }
+    if (!c) {
+      Chunk nc;
+      nc.cap = std::max<size_t>(need, (size_t)32 << 20);
+      if (hipHostMalloc((void**)&nc.host, nc.cap, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(H2ULV_ERR_OOM, "pinned host allocation failed");
+      }
+      nc.dev.alloc(nc.cap);
+      chunks.push_back(std::move(nc));
+      c = &chunks.back();
+    }
+    char* h = c->host + c->used;
+    char* d = c->dev.as<char>() + c->used;
+    std::memcpy(h, src, bytes);
+    c->used += need;
+    H2ULV_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+    return d;
+  }
+  void recycle() {
+    for (auto& c : chunks) c.used = 0;
+  }
+};
+
 // Uploads and scratch buffers that must live until the stream is synchronised.
 struct Stage {
   hipStream_t s = nullptr;
   std::vector<DBuf> bufs;
   std::vector<std::shared_ptr<void>> host;
+  DescArena desc;
   explicit Stage(hipStream_t st) : s(st) {}
   template <class T>
   T* up(std::vector<T>&& v) {
     if (v.empty()) return nullptr;
-    auto hv = std::make_shared<std::vector<T>>(std::move(v));
-    DBuf b(hv->size() * sizeof(T));
-    H2ULV_HIP(hipMemcpyAsync(b.p, hv->data(), hv->size() * sizeof(T), hipMemcpyHostToDevice, s));
-    host.push_back(hv);
-    bufs.push_back(std::move(b));
-    return bufs.back().as<T>();
+    return static_cast<T*>(desc.put(v.data(), v.size() * sizeof(T), s));
   }
   template <class T>
   T* up(const std::vector<T>& v) {
@@ -110,10 +198,16 @@ struct Stage {
     H2ULV_HIP(hipStreamSynchronize(s));
     bufs.clear();
     host.clear();
+    desc.recycle();
+  }
+  ~Stage() {
+    // the descriptor arena and scratch buffers may still be read by queued work
+    (void)hipStreamSynchronize(s);
   }
 };
 
 inline int64_t tiles64(int64_t m, int64_t n) { return ((m + 63) / 64) * ((n + 63) / 64); }
+inline int64_t tiles_of(int64_t m, int64_t n, int t) { return ((m + t - 1) / t) * ((n + t - 1) / t); }
 
 template <typename T>
 struct GemmBatch {
@@ -159,15 +253,36 @@ struct GemmBatch {
       terms.clear();
       return;
     }
+    // 128 x 128 tiles when the items fill them well and give enough work-groups
+    double useful = 0, cover128 = 0;
+    int64_t n128 = 0;
+    for (auto& it : its) {
+      useful += (double)it.M * it.N;
+      int64_t t = tiles_of(it.M, it.N, 128);
+      n128 += t;
+      cover128 += 16384.0 * t;
+    }
+    const int tile = (n128 >= 512 && useful >= 0.6 * cover128) ? 128 : 64;
     std::vector<int64_t> tp(its.size() + 1, 0);
-    for (size_t i = 0; i < its.size(); ++i) tp[i + 1] = tp[i] + tiles64(its[i].M, its[i].N);
+    for (size_t i = 0; i < its.size(); ++i) tp[i + 1] = tp[i] + tiles_of(its[i].M, its[i].N, tile);
     int64_t nt = tp.back();
     int ni = (int)its.size();
+    double fl = 0, by = 0;
+    if (profiler().on)
+      for (auto& it : its)
+        for (int t = it.t0; t < it.t0 + it.nt; ++t) {
+          double K = terms[t].K;
+          fl += 2.0 * it.M * it.N * K;
+          by += ((double)it.M * K + K * it.N) * sizeof(T);
+        }
+    if (profiler().on)
+      for (auto& it : its) by += (double)it.M * it.N * sizeof(T) * (it.beta != 0.0 ? 2 : 1);
     auto* di = st.up(std::move(its));
     auto* dt = st.up(std::move(terms));
     auto* dp = st.up(std::move(tp));
     terms.clear();
-    launch_gemm<T>(di, dt, dp, nt, ni, st.s);
+    ProfScope ps(sizeof(T) == 8 ? "gemm_f64" : "gemm_f32", fl, by, st.s);
+    launch_gemm<T>(di, dt, dp, nt, ni, tile, st.s);
     H2ULV_HIP(hipGetLastError());
   }
 };
@@ -184,9 +299,12 @@ struct KgenBatch {
     for (size_t i = 0; i < items.size(); ++i) tp[i + 1] = tp[i] + tiles64(items[i].m, items[i].n);
     int64_t nt = tp.back();
     int ni = (int)items.size();
+    double ev = 0;
+    for (auto& it : items) ev += (double)it.m * it.n;
     auto* di = st.up(std::move(items));
     auto* dp = st.up(std::move(tp));
     items.clear();
+    ProfScope ps("kgen", ev, ev * 8.0, st.s);
     launch_kgen(di, dp, nt, ni, pts, kf, dup, st.s);
     H2ULV_HIP(hipGetLastError());
   }
@@ -206,9 +324,12 @@ struct CopyBatch {
       tp[i + 1] = tp[i] + tiles64(items[i].rows, items[i].cols);
     int64_t nt = tp.back();
     int ni = (int)items.size();
+    double by = 0;
+    for (auto& it : items) by += 16.0 * it.rows * it.cols;
     auto* di = st.up(std::move(items));
     auto* dp = st.up(std::move(tp));
     items.clear();
+    ProfScope ps("copy", 0, by, st.s);
     launch_copy(di, dp, nt, ni, alpha, beta, st.s);
     H2ULV_HIP(hipGetLastError());
   }

@@ -17,6 +17,11 @@ MemStats& mem_stats() {
   return ms;
 }
 
+Profiler& profiler() {
+  static Profiler p;
+  return p;
+}
+
 static constexpr int LU_NB = 64;   // LU panel / triangular block width
 static constexpr int QR_NB = 32;   // Householder panel width
 
@@ -138,7 +143,16 @@ void batched_lu(Stage& st, const std::vector<SqMat>& mats, int32_t* ipiv, int32_
   const int nmat = (int)mats.size();
   MatDesc* dd = st.up(std::move(ds));
   for (int j0 = 0; j0 < maxm; j0 += nb) {
-    launch_lu_panel(dd, nmat, j0, nb, st.s);
+    {
+      double fl = 0;
+      for (auto& mt : mats)
+        if (mt.m > j0) {
+          double w = std::min(nb, mt.m - j0), h = mt.m - j0;
+          fl += 2.0 * h * w * w / 2.0;
+        }
+      ProfScope ps("lu_panel", fl, 0, st.s);
+      launch_lu_panel(dd, nmat, j0, nb, st.s);
+    }
     H2ULV_HIP(hipGetLastError());
     std::vector<int64_t> sp(1, 0);
     for (auto& mt : mats) sp.push_back(sp.back() + (mt.m > j0 ? (mt.m + 63) / 64 : 0));
@@ -248,27 +262,49 @@ void batched_qr_R(Stage& st, const std::vector<TallQr>& ms) {
   int maxk = 0;
   std::vector<MatDesc> ds;
   std::vector<double*> Vb, Tfb, Y1b, Y2b;
+  int64_t sv = 0, sa = 0, sy = 0;
   for (auto& a : ms) {
+    sv += (int64_t)a.h * nb;
+    sa += std::max(a.m, 1);
+    sy += (int64_t)nb * std::max(a.m, 1);
+  }
+  double* Vall = st.scratch<double>(std::max<int64_t>(sv, 1));
+  double* Aall = st.scratch<double>(std::max<int64_t>(sa, 1));
+  double* Tall = st.scratch<double>((int64_t)nb * nb * ms.size());
+  double* Y1all = st.scratch<double>(std::max<int64_t>(sy, 1));
+  double* Y2all = st.scratch<double>(std::max<int64_t>(sy, 1));
+  sv = sa = sy = 0;
+  for (size_t q = 0; q < ms.size(); ++q) {
+    const TallQr& a = ms[q];
     MatDesc d{};
     d.A = a.A;
     d.lda = a.lda;
     d.m = a.h;
     d.n = a.m;
-    d.V = st.scratch<double>(std::max<int64_t>((int64_t)a.h * nb, 1));
-    d.aux = st.scratch<double>(std::max(a.m, 1));
-    d.Tf = st.scratch<double>((int64_t)nb * nb);
+    d.V = Vall + sv;
+    d.aux = Aall + sa;
+    d.Tf = Tall + (int64_t)nb * nb * q;
     d.panel_ws = 1;
     Vb.push_back(d.V);
     Tfb.push_back(d.Tf);
-    Y1b.push_back(st.scratch<double>(std::max<int64_t>((int64_t)nb * a.m, 1)));
-    Y2b.push_back(st.scratch<double>(std::max<int64_t>((int64_t)nb * a.m, 1)));
+    Y1b.push_back(Y1all + sy);
+    Y2b.push_back(Y2all + sy);
+    sv += (int64_t)a.h * nb;
+    sa += std::max(a.m, 1);
+    sy += (int64_t)nb * std::max(a.m, 1);
     ds.push_back(d);
     maxk = std::max(maxk, std::min(a.h, a.m));
   }
   const int nmat = (int)ms.size();
   MatDesc* dd = st.up(std::move(ds));
   for (int j0 = 0; j0 < maxk; j0 += nb) {
-    launch_qr_panel(dd, nmat, j0, nb, st.s);
+    {
+      double fl = 0;
+      for (auto& a : ms)
+        if (std::min(a.h, a.m) > j0) fl += 2.0 * (a.h - j0) * (double)nb * nb;
+      ProfScope ps("qr_panel", fl, 0, st.s);
+      launch_qr_panel(dd, nmat, j0, nb, st.s);
+    }
     H2ULV_HIP(hipGetLastError());
     GemmBatch<double> g1, g2, g3;
     for (size_t b = 0; b < ms.size(); ++b) {
@@ -298,6 +334,20 @@ void batched_qr_basis(Stage& st, const std::vector<QrW>& ws) {
   int maxk = 0;
   std::vector<MatDesc> ds;
   std::vector<double*> Vb, Tfb, Y1b, Y2b;
+  int64_t sv = 0, sa = 0, st_ = 0, sy = 0;
+  for (auto& w : ws) {
+    int np = (w.k + nb - 1) / nb;
+    sv += std::max<int64_t>((int64_t)w.m * w.k, 1);
+    sa += std::max(w.k, 1);
+    st_ += std::max<int64_t>((int64_t)np * nb * nb, 1);
+    sy += (int64_t)nb * std::max(std::max(w.m, w.k), 1);
+  }
+  double* Vall = st.scratch<double>(sv);
+  double* Aall = st.scratch<double>(sa);
+  double* Tall = st.scratch<double>(st_);
+  double* Y1all = st.scratch<double>(sy);
+  double* Y2all = st.scratch<double>(sy);
+  sv = sa = st_ = sy = 0;
   for (auto& w : ws) {
     int np = (w.k + nb - 1) / nb;
     MatDesc d{};
@@ -305,14 +355,17 @@ void batched_qr_basis(Stage& st, const std::vector<QrW>& ws) {
     d.lda = w.m;
     d.m = w.m;
     d.n = w.k;
-    d.V = st.scratch<double>(std::max<int64_t>((int64_t)w.m * w.k, 1));
-    d.aux = st.scratch<double>(std::max(w.k, 1));
-    d.Tf = st.scratch<double>(std::max<int64_t>((int64_t)np * nb * nb, 1));
+    d.V = Vall + sv;
+    d.aux = Aall + sa;
+    d.Tf = Tall + st_;
     Vb.push_back(d.V);
     Tfb.push_back(d.Tf);
-    int64_t wmax = std::max(w.m, w.k);
-    Y1b.push_back(st.scratch<double>(std::max<int64_t>((int64_t)nb * wmax, 1)));
-    Y2b.push_back(st.scratch<double>(std::max<int64_t>((int64_t)nb * wmax, 1)));
+    Y1b.push_back(Y1all + sy);
+    Y2b.push_back(Y2all + sy);
+    sv += std::max<int64_t>((int64_t)w.m * w.k, 1);
+    sa += std::max(w.k, 1);
+    st_ += std::max<int64_t>((int64_t)np * nb * nb, 1);
+    sy += (int64_t)nb * std::max(std::max(w.m, w.k), 1);
     ds.push_back(d);
     maxk = std::max(maxk, std::min(w.k, w.m));
   }

@@ -118,7 +118,7 @@ void launch_kgen(const KgenItem* items, const int64_t* tile_ptr, int64_t ntiles,
                  const double* pts, KernelFn kf, int* dup_flag, hipStream_t s);
 template <typename T>
 void launch_gemm(const GemmItem<T>* items, const GemmTerm<T>* terms, const int64_t* tile_ptr,
-                 int64_t ntiles, int nitems, hipStream_t s);
+                 int64_t ntiles, int nitems, int tile, hipStream_t s);
 void launch_lu_panel(const MatDesc* d, int nmat, int j0, int nb, hipStream_t s);
 void launch_lu_swap_trsm(const MatDesc* d, const int64_t* slab_ptr, int64_t nslabs, int nmat,
                          int j0, int nb, hipStream_t s);

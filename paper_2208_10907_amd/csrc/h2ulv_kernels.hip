@@ -130,87 +130,132 @@ struct Mfma<float> {
   }
 };
 
-template <typename T>
+template <typename T, int TM, int TN>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict__ items,
                                                    const GemmTerm<T>* __restrict__ terms,
                                                    const int64_t* __restrict__ tile_ptr,
                                                    int nitems) {
   typedef typename Mfma<T>::v4 v4;
-  __shared__ T As[16][68];
-  __shared__ T Bs[16][68];
+  constexpr int BM = TM / 32, BN = TN / 32;  // 16x16 blocks per wave (2 x 2 waves)
+  constexpr int LA = TM / 16, LB = TN / 16;  // elements per thread per K tile
+  __shared__ T As[16][TM + 4];
+  __shared__ T Bs[16][TN + 4];
   int64_t tile = blockIdx.x;
   int id = find_item(tile_ptr, nitems, tile);
   const GemmItem<T> it = items[id];
   int64_t local = tile - tile_ptr[id];
-  int tm = (it.M + 63) >> 6;
-  int row0 = (int)(local % tm) * 64, col0 = (int)(local / tm) * 64;
-  int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  int wr = w & 1, wc = w >> 1;
-  v4 acc[2][2];
+  const int tm = (it.M + TM - 1) / TM;
+  const int row0 = (int)(local % tm) * TM, col0 = (int)(local / tm) * TN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w & 1, wc = w >> 1;
+  v4 acc[BM][BN];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < BM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
-
-  for (int t = it.t0; t < it.t0 + it.nt; ++t) {
-    const GemmTerm<T> tt = terms[t];
-    const bool ta = tt.flags & 1, tb = tt.flags & 2;
-    for (int k0 = 0; k0 < tt.K; k0 += 16) {
-      if (!ta) {
-        int i = tid & 63, kb = tid >> 6;
+    for (int b = 0; b < BN; ++b) acc[a][b] = v4{0, 0, 0, 0};
+  T ra[LA], rb[LB];
+  // load K tile (term t, offset k0) of op(A) and op(B) into registers
+  auto load = [&](int t, int k0) {
+    const GemmTerm<T>& tt = terms[t];
+    if (!(tt.flags & 1)) {
+      const int i = tid % TM, kb = tid / TM;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int kk = kb + 4 * r, gi = row0 + i, gk = k0 + kk;
-          As[kk][i] = (gi < it.M && gk < tt.K) ? tt.A[gi + (int64_t)gk * tt.lda] : T(0);
-        }
-      } else {
-        int kk = tid & 15, ib = tid >> 4;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int i = ib + 16 * r, gi = row0 + i, gk = k0 + kk;
-          As[kk][i] = (gi < it.M && gk < tt.K) ? tt.A[gk + (int64_t)gi * tt.lda] : T(0);
-        }
+      for (int r = 0; r < LA; ++r) {
+        const int kk = kb + (256 / TM) * r, gi = row0 + i, gk = k0 + kk;
+        ra[r] = (gi < it.M && gk < tt.K) ? tt.A[gi + (int64_t)gk * tt.lda] : T(0);
       }
-      if (!tb) {
-        int kk = tid & 15, jb = tid >> 4;
+    } else {
+      const int kk = tid & 15, ib = tid >> 4;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int j = jb + 16 * r, gj = col0 + j, gk = k0 + kk;
-          Bs[kk][j] = (gj < it.N && gk < tt.K) ? tt.B[gk + (int64_t)gj * tt.ldb] : T(0);
-        }
-      } else {
-        int j = tid & 63, kb = tid >> 6;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int kk = kb + 4 * r, gj = col0 + j, gk = k0 + kk;
-          Bs[kk][j] = (gj < it.N && gk < tt.K) ? tt.B[gj + (int64_t)gk * tt.ldb] : T(0);
-        }
+      for (int r = 0; r < LA; ++r) {
+        const int i = ib + 16 * r, gi = row0 + i, gk = k0 + kk;
+        ra[r] = (gi < it.M && gk < tt.K) ? tt.A[gk + (int64_t)gi * tt.lda] : T(0);
       }
+    }
+    if (!(tt.flags & 2)) {
+      const int kk = tid & 15, jb = tid >> 4;
+#pragma unroll
+      for (int r = 0; r < LB; ++r) {
+        const int j = jb + 16 * r, gj = col0 + j, gk = k0 + kk;
+        rb[r] = (gj < it.N && gk < tt.K) ? tt.B[gk + (int64_t)gj * tt.ldb] : T(0);
+      }
+    } else {
+      const int j = tid % TN, kb = tid / TN;
+#pragma unroll
+      for (int r = 0; r < LB; ++r) {
+        const int kk = kb + (256 / TN) * r, gj = col0 + j, gk = k0 + kk;
+        rb[r] = (gj < it.N && gk < tt.K) ? tt.B[gj + (int64_t)gk * tt.ldb] : T(0);
+      }
+    }
+  };
+  auto store = [&](int t) {
+    const GemmTerm<T>& tt = terms[t];
+    if (!(tt.flags & 1)) {
+      const int i = tid % TM, kb = tid / TM;
+#pragma unroll
+      for (int r = 0; r < LA; ++r) As[kb + (256 / TM) * r][i] = ra[r];
+    } else {
+      const int kk = tid & 15, ib = tid >> 4;
+#pragma unroll
+      for (int r = 0; r < LA; ++r) As[kk][ib + 16 * r] = ra[r];
+    }
+    if (!(tt.flags & 2)) {
+      const int kk = tid & 15, jb = tid >> 4;
+#pragma unroll
+      for (int r = 0; r < LB; ++r) Bs[kk][jb + 16 * r] = rb[r];
+    } else {
+      const int j = tid % TN, kb = tid / TN;
+#pragma unroll
+      for (int r = 0; r < LB; ++r) Bs[kb + (256 / TN) * r][j] = rb[r];
+    }
+  };
+  // flattened (term, k0) sequence of K tiles
+  int t = it.t0;
+  const int tend = it.t0 + it.nt;
+  while (t < tend && terms[t].K <= 0) ++t;
+  if (t < tend) {
+    int k0 = 0;
+    load(t, k0);
+    for (;;) {
       __syncthreads();
+      store(t);
+      __syncthreads();
+      // advance to the next tile and prefetch it while this one is consumed
+      int tn = t, kn = k0 + 16;
+      if (kn >= terms[tn].K) {
+        kn = 0;
+        ++tn;
+        while (tn < tend && terms[tn].K <= 0) ++tn;
+      }
+      const bool more = tn < tend;
+      if (more) load(tn, kn);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        int kk = 4 * s + (lane >> 4);
-        T a0 = As[kk][32 * wr + (lane & 15)];
-        T a1 = As[kk][32 * wr + 16 + (lane & 15)];
-        T b0 = Bs[kk][32 * wc + (lane & 15)];
-        T b1 = Bs[kk][32 * wc + 16 + (lane & 15)];
-        acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
-        acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
-        acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
-        acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+        const int kk = 4 * s + (lane >> 4);
+        T av[BM], bv[BN];
+#pragma unroll
+        for (int a = 0; a < BM; ++a) av[a] = As[kk][(TM / 2) * wr + 16 * a + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < BN; ++b) bv[b] = Bs[kk][(TN / 2) * wc + 16 * b + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < BM; ++a)
+#pragma unroll
+          for (int b = 0; b < BN; ++b) acc[a][b] = Mfma<T>::mac(av[a], bv[b], acc[a][b]);
       }
-      __syncthreads();
+      if (!more) break;
+      t = tn;
+      k0 = kn;
     }
   }
   const T alpha = (T)it.alpha, beta = (T)it.beta;
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int bj = 0; bj < BN; ++bj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int row = row0 + 32 * wr + 16 * bi + Mfma<T>::row(lane, r);
-        int col = col0 + 32 * wc + 16 * bj + (lane & 15);
+        const int row = row0 + (TM / 2) * wr + 16 * bi + Mfma<T>::row(lane, r);
+        const int col = col0 + (TN / 2) * wc + 16 * bj + (lane & 15);
         if (row < it.M && col < it.N) {
           T v = alpha * acc[bi][bj][r];
           T* c = it.C + row + (int64_t)col * it.ldc;
@@ -222,15 +267,19 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
 
 template <typename T>
 void launch_gemm(const GemmItem<T>* items, const GemmTerm<T>* terms, const int64_t* tile_ptr,
-                 int64_t ntiles, int nitems, hipStream_t s) {
+                 int64_t ntiles, int nitems, int tile, hipStream_t s) {
   if (ntiles <= 0) return;
-  hipLaunchKernelGGL(gemm_kernel<T>, dim3((unsigned)ntiles), dim3(256), 0, s, items, terms,
-                     tile_ptr, nitems);
+  if (tile == 128)
+    hipLaunchKernelGGL((gemm_kernel<T, 128, 128>), dim3((unsigned)ntiles), dim3(256), 0, s,
+                       items, terms, tile_ptr, nitems);
+  else
+    hipLaunchKernelGGL((gemm_kernel<T, 64, 64>), dim3((unsigned)ntiles), dim3(256), 0, s, items,
+                       terms, tile_ptr, nitems);
 }
 template void launch_gemm<double>(const GemmItem<double>*, const GemmTerm<double>*,
-                                  const int64_t*, int64_t, int, hipStream_t);
+                                  const int64_t*, int64_t, int, int, hipStream_t);
 template void launch_gemm<float>(const GemmItem<float>*, const GemmTerm<float>*, const int64_t*,
-                                 int64_t, int, hipStream_t);
+                                 int64_t, int, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Blocked LU with partial pivoting (Sec. II-B Eq. lu: LU of S^RR; also the
@@ -441,9 +490,14 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc* __restrict
   for (int jj = 0; jj < w; ++jj) {
     const int col = j0 + jj;
     double* a = A + (int64_t)col * lda;
-    double part = 0.0;
-    for (int r = col + 1 + tid; r < m; r += 256) part += a[r] * a[r];
-    double xn2 = block_sum256(part, sh);
+    double part = 0.0, part1 = 0.0;
+    int rr = col + 1 + tid;
+    for (; rr + 256 < m; rr += 512) {
+      part += a[rr] * a[rr];
+      part1 += a[rr + 256] * a[rr + 256];
+    }
+    for (; rr < m; rr += 256) part += a[rr] * a[rr];
+    double xn2 = block_sum256(part + part1, sh);
     double alpha = a[col];
     if (tid == 0) {
       if (xn2 == 0.0) {
@@ -478,10 +532,24 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc* __restrict
       // apply H = I - tau v v^T to the panel columns right of col: one wave per column
       for (int c = col + 1 + wv; c < j0 + w; c += 4) {
         double* ac = A + (int64_t)c * lda;
-        double p = 0.0;
-        for (int r = col + lane; r < m; r += 64) p += v[r] * ac[r];
-        double wsum = wave_sum(p) * tau;
-        for (int r = col + lane; r < m; r += 64) ac[r] -= wsum * v[r];
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+        int r = col + lane;
+        for (; r + 192 < m; r += 256) {
+          p0 += v[r] * ac[r];
+          p1 += v[r + 64] * ac[r + 64];
+          p2 += v[r + 128] * ac[r + 128];
+          p3 += v[r + 192] * ac[r + 192];
+        }
+        for (; r < m; r += 64) p0 += v[r] * ac[r];
+        double wsum = wave_sum((p0 + p1) + (p2 + p3)) * tau;
+        r = col + lane;
+        for (; r + 192 < m; r += 256) {
+          ac[r] -= wsum * v[r];
+          ac[r + 64] -= wsum * v[r + 64];
+          ac[r + 128] -= wsum * v[r + 128];
+          ac[r + 192] -= wsum * v[r + 192];
+        }
+        for (; r < m; r += 64) ac[r] -= wsum * v[r];
       }
     }
     __syncthreads();
@@ -496,9 +564,14 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc* __restrict
     const double* vj = V + (int64_t)jj * m;
     for (int l = wv; l < jj; l += 4) {
       const double* vl = V + (int64_t)l * m;
-      double p = 0.0;
-      for (int r = j0 + jj + lane; r < m; r += 64) p += vl[r] * vj[r];
-      p = wave_sum(p);
+      double p = 0.0, q = 0.0;
+      int r = j0 + jj + lane;
+      for (; r + 64 < m; r += 128) {
+        p += vl[r] * vj[r];
+        q += vl[r + 64] * vj[r + 64];
+      }
+      for (; r < m; r += 64) p += vl[r] * vj[r];
+      p = wave_sum(p + q);
       if (lane == 0) dots[l] = p;
     }
     __syncthreads();
@@ -815,17 +888,33 @@ __global__ __launch_bounds__(256) void pivqr_apply_kernel(const PivQrState* __re
   const double* v = st.A + (int64_t)t * st.lda;
   double* ac = st.A + (int64_t)c * st.lda;
   if (tau != 0.0) {
-    double p = 0.0;
-    for (int r = t + 1 + lane; r < m; r += 64) p += v[r] * ac[r];
-    p = wave_sum(p);
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+    int r = t + 1 + lane;
+    for (; r + 192 < m; r += 256) {
+      p0 += v[r] * ac[r];
+      p1 += v[r + 64] * ac[r + 64];
+      p2 += v[r + 128] * ac[r + 128];
+      p3 += v[r + 192] * ac[r + 192];
+    }
+    for (; r < m; r += 64) p0 += v[r] * ac[r];
+    const double p = wave_sum((p0 + p1) + (p2 + p3));
     const double wsum = (ac[t] + p) * tau;
-    double s2 = 0.0;
-    for (int r = t + 1 + lane; r < m; r += 64) {
+    double s0 = 0.0, s1 = 0.0;
+    r = t + 1 + lane;
+    for (; r + 64 < m; r += 128) {
+      double x0 = ac[r] - wsum * v[r];
+      double x1 = ac[r + 64] - wsum * v[r + 64];
+      ac[r] = x0;
+      ac[r + 64] = x1;
+      s0 += x0 * x0;
+      s1 += x1 * x1;
+    }
+    for (; r < m; r += 64) {
       double x = ac[r] - wsum * v[r];
       ac[r] = x;
-      s2 += x * x;
+      s0 += x * x;
     }
-    s2 = wave_sum(s2);
+    double s2 = wave_sum(s0 + s1);
     if (lane == 0) {
       ac[t] -= wsum;
       st.nrm[c] = sqrt(s2);

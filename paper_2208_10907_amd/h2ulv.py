@@ -35,6 +35,7 @@ EXPORTS = [
     "h2ulv_destroy", "h2ulv_structure_create", "h2ulv_structure_levels",
     "h2ulv_structure_perm", "h2ulv_structure_lists", "h2ulv_structure_geometry",
     "h2ulv_structure_destroy", "h2ulv_status_string", "h2ulv_last_error",
+    "h2ulv_profile_enable", "h2ulv_profile_read",
 ]
 
 
@@ -62,6 +63,11 @@ class Stats(C.Structure):
         d["flops"] = (self.flops_fill + self.flops_basis + self.flops_couple + self.flops_rotate
                       + self.flops_elim + self.flops_root)
         return d
+
+
+class KernelProfile(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("time_ms", C.c_double),
+                ("flops", C.c_double), ("bytes", C.c_double)]
 
 
 class H2ULVError(RuntimeError):
@@ -106,6 +112,8 @@ def lib() -> C.CDLL:
         "h2ulv_structure_destroy": (None, [vp]),
         "h2ulv_status_string": (C.c_char_p, [i32]),
         "h2ulv_last_error": (C.c_char_p, []),
+        "h2ulv_profile_enable": (i32, [i32]),
+        "h2ulv_profile_read": (i32, [P(KernelProfile), i32, P(i32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -321,3 +329,21 @@ class Structure:
         _check(lib().h2ulv_structure_geometry(self._h, lev, c.ctypes.data_as(C.c_void_p),
                                               r.ctypes.data_as(C.c_void_p)))
         return c.reshape(nb, 3), r
+
+
+def profile_enable(on: bool = True) -> None:
+    """Start (or stop) recording per-kernel launch times with HIP events."""
+    _check(lib().h2ulv_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """Per-kernel launches, summed time (ms), algorithmic flops and bytes."""
+    arr = (KernelProfile * 64)()
+    cnt = C.c_int32(0)
+    _check(lib().h2ulv_profile_read(arr, 64, C.byref(cnt)))
+    out = {}
+    for i in range(min(cnt.value, 64)):
+        r = arr[i]
+        out[r.name.decode()] = {"launches": int(r.launches), "time_ms": float(r.time_ms),
+                                "flops": float(r.flops), "bytes": float(r.bytes)}
+    return out
