@@ -117,12 +117,17 @@ def main() -> int:
         del f
         return t1 - t0, t2 - t1, iters, rel, st
 
-    for _ in range(args.warmup):
-        step()
+    for w in range(args.warmup):
+        r = step()
+        print(f"bench: warmup step {w + 1}/{args.warmup} done ({r[0]:.2f} s factorize, "
+              f"{r[1]:.2f} s refine)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     H.profile_enable(True)
     t_start = time.perf_counter()
-    res = [step() for _ in range(args.steps)]
+    res = []
+    for i in range(args.steps):
+        res.append(step())
+        print(f"bench: timed step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     prof = H.profile_read()

@@ -73,6 +73,14 @@ namespace h2ulv {
 
 static KernelFn kfn(const h2ulv_params& p) { return KernelFn{p.kernel, p.alpha, p.diag}; }
 
+// float copy of a device array (mixed precision: operands of the FP32 products)
+static DBuf to_f32(const double* src, int64_t count, hipStream_t s) {
+  DBuf b(std::max<int64_t>(count, 1) * sizeof(float));
+  launch_convert_d2f(src, b.as<float>(), count, s);
+  H2ULV_HIP(hipGetLastError());
+  return b;
+}
+
 // far-field column indices of box i at level lev (see the oracle's docstring for
 // the two modes): exact = every point outside the near boxes; sampled = all
 // candidate rows of the own-level far boxes + strided samples of ancestors' far
@@ -335,6 +343,12 @@ void Factorizer::level(int lev) {
   tick("b_inverse");
   // inverse T factors of the children (T-hat^-1 is block diagonal)
   const bool upper = lev < L;
+  // mixed precision: the rotations, low-rank couplings and Schur updates run on
+  // FP32 matrix cores with FP32 accumulation; the fill-in products stay FP64
+  // because they feed the rank-revealing QR, whose decisions at tol ~1e-6 sit at
+  // FP32 rounding level (FP32 fill-ins inflate the upper-level ranks several
+  // times); inverses, QR/ID, solve and residual are FP64 as well
+  const bool mixed = F.p.precision == H2ULV_MIXED;
   std::vector<int64_t> offTinv;
   DBuf Tinv;
   if (upper) {
@@ -413,6 +427,8 @@ void Factorizer::level(int lev) {
     for (int j : targets[i]) nc += m[j];
     ncols[i] = nc;
   }
+  DBuf D32;
+  if (mixed) D32 = to_f32(Dp, Doff[nnear], s);
   // per-box pivoted-QR matrices (m x m) kept until W' is built
   DBuf PQ(std::max<int64_t>(offSq[nb], 1) * sizeof(double));
   DBuf pivd(std::max<int64_t>(cand_off[nb], 1) * sizeof(int32_t));
@@ -787,23 +803,49 @@ void Factorizer::level(int lev) {
     double* Kc = st.scratch<double>(std::max<int64_t>(kcoff[nfar], 1));
     double* Tmp = st.scratch<double>(std::max<int64_t>(kcoff[nfar], 1));
     KgenBatch kb;
-    GemmBatch<double> g1, g2;
     for (int i = 0; i < nb; ++i)
       for (int64_t e = fp[i]; e < fp[i + 1]; ++e) {
         int j = fi[e];
         if (k[i] == 0 || k[j] == 0) continue;
         kb.add(dsk + skoff[i], k[i], dsk + skoff[j], k[j], Kc + kcoff[e], k[i]);
         kevals += (double)k[i] * k[j];
-        // tmp = Kc T_j^T ; S = T_i tmp
-        g1.one(Tmp + kcoff[e], k[i], k[i], k[j], k[j], Kc + kcoff[e], k[i], false,
-               lf.Tt.as<double>() + lf.offT[j], k[j], true);
-        g2.one(Sh + shat_far_off[e], k[i], k[i], k[j], k[i], lf.Tt.as<double>() + lf.offT[i],
-               k[i], false, Tmp + kcoff[e], k[i], false);
         flops_couple += 2.0 * k[i] * (double)k[j] * k[j] + 2.0 * k[i] * (double)k[i] * k[j];
       }
     kb.run(st, F.pts.as<double>(), kf, dup);
-    g1.run(st);
-    g2.run(st);
+    // tmp = Kc T_j^T ; S = T_i tmp
+    if (!mixed) {
+      GemmBatch<double> g1, g2;
+      for (int i = 0; i < nb; ++i)
+        for (int64_t e = fp[i]; e < fp[i + 1]; ++e) {
+          int j = fi[e];
+          if (k[i] == 0 || k[j] == 0) continue;
+          g1.one(Tmp + kcoff[e], k[i], k[i], k[j], k[j], Kc + kcoff[e], k[i], false,
+                 lf.Tt.as<double>() + lf.offT[j], k[j], true);
+          g2.one(Sh + shat_far_off[e], k[i], k[i], k[j], k[i], lf.Tt.as<double>() + lf.offT[i],
+                 k[i], false, Tmp + kcoff[e], k[i], false);
+        }
+      g1.run(st);
+      g2.run(st);
+    } else {
+      DBuf Kc32 = to_f32(Kc, kcoff[nfar], s);
+      DBuf T32 = to_f32(lf.Tt.as<double>(), lf.offT[nb], s);
+      DBuf Tmp32(std::max<int64_t>(kcoff[nfar], 1) * sizeof(float));
+      const float* Tf = T32.as<float>();
+      GemmBatch<float> g1;
+      GemmBatch<float, double> g2;
+      for (int i = 0; i < nb; ++i)
+        for (int64_t e = fp[i]; e < fp[i + 1]; ++e) {
+          int j = fi[e];
+          if (k[i] == 0 || k[j] == 0) continue;
+          g1.one(Tmp32.as<float>() + kcoff[e], k[i], k[i], k[j], k[j],
+                 Kc32.as<float>() + kcoff[e], k[i], false, Tf + lf.offT[j], k[j], true);
+          g2.one(Sh + shat_far_off[e], k[i], k[i], k[j], k[i], Tf + lf.offT[i], k[i], false,
+                 Tmp32.as<float>() + kcoff[e], k[i], false);
+        }
+      g1.run(st);
+      g2.run(st);
+      st.sync();
+    }
     st.sync();
   }
 
@@ -819,32 +861,60 @@ void Factorizer::level(int lev) {
   lf.Sinv.alloc(std::max<int64_t>(lf.offR[nb], 1) * sizeof(double));
   lf.Xs.alloc(std::max<int64_t>(lf.offX[nb], 1) * sizeof(double));
   lf.SSR.alloc(std::max<int64_t>(lf.offX[nb], 1) * sizeof(double));
+  DBuf U32;
   {
     // off-diagonal near blocks: S_ij = U^S_i^T D_ij U^S_j
     std::vector<int64_t> toff(nnear + 1, 0);
     for (int i = 0; i < nb; ++i)
       for (int64_t e = np[i]; e < np[i + 1]; ++e) toff[e + 1] = toff[e] + (int64_t)m[i] * k[ni[e]];
-    double* Tmp = st.scratch<double>(std::max<int64_t>(toff[nnear], 1));
-    GemmBatch<double> g1, g2;
-    const double* U = lf.U.as<double>();
+    if (mixed) U32 = to_f32(lf.U.as<double>(), lf.offU[nb], s);
     for (int i = 0; i < nb; ++i)
       for (int64_t e = np[i]; e < np[i + 1]; ++e) {
         int j = ni[e];
         if (j == i || k[i] == 0 || k[j] == 0) continue;
-        g1.one(Tmp + toff[e], m[i], m[i], k[j], m[j], Dp + Doff[e], m[i], false, U + lf.offU[j],
-               m[j], false);
-        g2.one(Sh + shat_near_off[e], k[i], k[i], k[j], m[i], U + lf.offU[i], m[i], true,
-               Tmp + toff[e], m[i], false);
         flops_rotate += 2.0 * m[i] * (double)m[j] * k[j] + 2.0 * k[i] * (double)m[i] * k[j];
       }
-    g1.run(st);
-    g2.run(st);
+    if (!mixed) {
+      double* Tmp = st.scratch<double>(std::max<int64_t>(toff[nnear], 1));
+      GemmBatch<double> g1, g2;
+      const double* U = lf.U.as<double>();
+      for (int i = 0; i < nb; ++i)
+        for (int64_t e = np[i]; e < np[i + 1]; ++e) {
+          int j = ni[e];
+          if (j == i || k[i] == 0 || k[j] == 0) continue;
+          g1.one(Tmp + toff[e], m[i], m[i], k[j], m[j], Dp + Doff[e], m[i], false, U + lf.offU[j],
+                 m[j], false);
+          g2.one(Sh + shat_near_off[e], k[i], k[i], k[j], m[i], U + lf.offU[i], m[i], true,
+                 Tmp + toff[e], m[i], false);
+        }
+      g1.run(st);
+      g2.run(st);
+    } else {
+      float* Tmp = st.scratch<float>(std::max<int64_t>(toff[nnear], 1));
+      GemmBatch<float> g1;
+      GemmBatch<float, double> g2;
+      const float* U = U32.as<float>();
+      const float* D32p = D32.as<float>();
+      for (int i = 0; i < nb; ++i)
+        for (int64_t e = np[i]; e < np[i + 1]; ++e) {
+          int j = ni[e];
+          if (j == i || k[i] == 0 || k[j] == 0) continue;
+          g1.one(Tmp + toff[e], m[i], m[i], k[j], m[j], D32p + Doff[e], m[i], false,
+                 U + lf.offU[j], m[j], false);
+          g2.one(Sh + shat_near_off[e], k[i], k[i], k[j], m[i], U + lf.offU[i], m[i], true,
+                 Tmp + toff[e], m[i], false);
+        }
+      g1.run(st);
+      g2.run(st);
+    }
     st.sync();
   }
   {
     // diagonal: S_ii = U_i^T D_ii U_i
     DBuf S(std::max<int64_t>(offSq[nb], 1) * sizeof(double));
-    {
+    for (int i = 0; i < nb; ++i)
+      if (m[i] > 0) flops_rotate += 4.0 * std::pow((double)m[i], 3);
+    if (!mixed) {
       DBuf Tmp(std::max<int64_t>(offSq[nb], 1) * sizeof(double));
       GemmBatch<double> g1, g2;
       const double* U = lf.U.as<double>();
@@ -854,13 +924,31 @@ void Factorizer::level(int lev) {
                U + lf.offU[i], m[i], false);
         g2.one(S.as<double>() + offSq[i], m[i], m[i], m[i], m[i], U + lf.offU[i], m[i], true,
                Tmp.as<double>() + offSq[i], m[i], false);
-        flops_rotate += 4.0 * std::pow((double)m[i], 3);
+      }
+      g1.run(st);
+      g2.run(st);
+      st.sync();
+    } else {
+      DBuf Tmp(std::max<int64_t>(offSq[nb], 1) * sizeof(float));
+      GemmBatch<float> g1;
+      GemmBatch<float, double> g2;
+      const float* U = U32.as<float>();
+      const float* D32p = D32.as<float>();
+      for (int i = 0; i < nb; ++i) {
+        if (m[i] == 0) continue;
+        int64_t e = csr_find(np, ni, i, i);
+        g1.one(Tmp.as<float>() + offSq[i], m[i], m[i], m[i], m[i], D32p + Doff[e], m[i], false,
+               U + lf.offU[i], m[i], false);
+        g2.one(S.as<double>() + offSq[i], m[i], m[i], m[i], m[i], U + lf.offU[i], m[i], true,
+               Tmp.as<float>() + offSq[i], m[i], false);
       }
       g1.run(st);
       g2.run(st);
       st.sync();
     }
     D.reset();
+    D32.reset();
+    U32.reset();
     tick("e_rotate");
     // S^RR inverse, X = S^RR^-1 S^RS, S^SR copy, Schur update into the new diagonal block
     DBuf RRw(std::max<int64_t>(lf.offR[nb], 1) * sizeof(double));
@@ -918,12 +1006,31 @@ void Factorizer::level(int lev) {
       const double* Si = S.as<double>() + offSq[i];
       g1.one(lf.Xs.as<double>() + lf.offX[i], r, r, ki, r, lf.Sinv.as<double>() + lf.offR[i], r,
              false, Si + ki, m[i], false);
-      int64_t e = csr_find(np, ni, i, i);
-      g2.one(Sh + shat_near_off[e], ki, ki, ki, r, lf.SSR.as<double>() + lf.offX[i], ki, false,
-             lf.Xs.as<double>() + lf.offX[i], r, false, -1.0, 1.0);
     }
     g1.run(st);
-    g2.run(st);
+    if (!mixed) {
+      for (int i = 0; i < nb; ++i) {
+        int r = m[i] - k[i], ki = k[i];
+        if (r == 0 || ki == 0) continue;
+        int64_t e = csr_find(np, ni, i, i);
+        g2.one(Sh + shat_near_off[e], ki, ki, ki, r, lf.SSR.as<double>() + lf.offX[i], ki, false,
+               lf.Xs.as<double>() + lf.offX[i], r, false, -1.0, 1.0);
+      }
+      g2.run(st);
+    } else {
+      DBuf SSR32 = to_f32(lf.SSR.as<double>(), lf.offX[nb], s);
+      DBuf X32 = to_f32(lf.Xs.as<double>(), lf.offX[nb], s);
+      GemmBatch<float, double> g3;
+      for (int i = 0; i < nb; ++i) {
+        int r = m[i] - k[i], ki = k[i];
+        if (r == 0 || ki == 0) continue;
+        int64_t e = csr_find(np, ni, i, i);
+        g3.one(Sh + shat_near_off[e], ki, ki, ki, r, SSR32.as<float>() + lf.offX[i], ki, false,
+               X32.as<float>() + lf.offX[i], r, false, -1.0, 1.0);
+      }
+      g3.run(st);
+      st.sync();
+    }
     st.sync();
   }
   tick("f_elim");

@@ -209,12 +209,13 @@ struct Stage {
 inline int64_t tiles64(int64_t m, int64_t n) { return ((m + 63) / 64) * ((n + 63) / 64); }
 inline int64_t tiles_of(int64_t m, int64_t n, int t) { return ((m + t - 1) / t) * ((n + t - 1) / t); }
 
-template <typename T>
+// TI: operand type (MFMA precision), TC: type of the result C.
+template <typename T, typename TC = T>
 struct GemmBatch {
-  std::vector<GemmItem<T>> items;
+  std::vector<GemmItem<TC>> items;
   std::vector<GemmTerm<T>> terms;
-  void item(T* C, int64_t ldc, int M, int N, double alpha = 1.0, double beta = 0.0) {
-    GemmItem<T> it;
+  void item(TC* C, int64_t ldc, int M, int N, double alpha = 1.0, double beta = 0.0) {
+    GemmItem<TC> it;
     it.C = C;
     it.ldc = ldc;
     it.M = M;
@@ -237,14 +238,14 @@ struct GemmBatch {
     items.back().nt++;
   }
   // C = alpha op(A) op(B) + beta C
-  void one(T* C, int64_t ldc, int M, int N, int K, const T* A, int64_t lda, bool ta, const T* B,
+  void one(TC* C, int64_t ldc, int M, int N, int K, const T* A, int64_t lda, bool ta, const T* B,
            int64_t ldb, bool tb, double alpha = 1.0, double beta = 0.0) {
     item(C, ldc, M, N, alpha, beta);
     term(A, lda, ta, B, ldb, tb, K);
   }
   bool empty() const { return items.empty(); }
   void run(Stage& st) {
-    std::vector<GemmItem<T>> its;
+    std::vector<GemmItem<TC>> its;
     its.reserve(items.size());
     for (auto& it : items)
       if (it.M > 0 && it.N > 0) its.push_back(it);
@@ -253,18 +254,29 @@ struct GemmBatch {
       terms.clear();
       return;
     }
-    // 128 x 128 tiles when the items fill them well and give enough work-groups
+    // tile shape (measured on gfx950): FP64 64 x 64 (the 128 x 128 variant runs one
+    // wave per SIMD and is slower); FP32 128 x 128 when the items fill the tiles;
+    // 32 x 128 when every item has at most 32 rows (Householder V^T A products)
     double useful = 0, cover128 = 0;
     int64_t n128 = 0;
+    int maxM = 0;
     for (auto& it : its) {
       useful += (double)it.M * it.N;
       int64_t t = tiles_of(it.M, it.N, 128);
       n128 += t;
       cover128 += 16384.0 * t;
+      maxM = std::max(maxM, it.M);
     }
-    const int tile = (n128 >= 512 && useful >= 0.6 * cover128) ? 128 : 64;
+    int tile = 64;
+    if (maxM <= 32)
+      tile = 32;
+    else if (sizeof(T) == 4 && n128 >= 512 && useful >= 0.6 * cover128)
+      tile = 128;
+    auto ntile = [&](const GemmItem<TC>& it) {
+      return tile == 32 ? (int64_t)((it.N + 127) / 128) : tiles_of(it.M, it.N, tile);
+    };
     std::vector<int64_t> tp(its.size() + 1, 0);
-    for (size_t i = 0; i < its.size(); ++i) tp[i + 1] = tp[i] + tiles_of(its[i].M, its[i].N, tile);
+    for (size_t i = 0; i < its.size(); ++i) tp[i + 1] = tp[i] + ntile(its[i]);
     int64_t nt = tp.back();
     int ni = (int)its.size();
     double fl = 0, by = 0;
@@ -276,13 +288,13 @@ struct GemmBatch {
           by += ((double)it.M * K + K * it.N) * sizeof(T);
         }
     if (profiler().on)
-      for (auto& it : its) by += (double)it.M * it.N * sizeof(T) * (it.beta != 0.0 ? 2 : 1);
+      for (auto& it : its) by += (double)it.M * it.N * sizeof(TC) * (it.beta != 0.0 ? 2 : 1);
     auto* di = st.up(std::move(its));
     auto* dt = st.up(std::move(terms));
     auto* dp = st.up(std::move(tp));
     terms.clear();
     ProfScope ps(sizeof(T) == 8 ? "gemm_f64" : "gemm_f32", fl, by, st.s);
-    launch_gemm<T>(di, dt, dp, nt, ni, tile, st.s);
+    launch_gemm<T, TC>(di, dt, dp, nt, ni, tile, st.s);
     H2ULV_HIP(hipGetLastError());
   }
 };

@@ -116,8 +116,9 @@ struct WpItem {
 // resident on the device.
 void launch_kgen(const KgenItem* items, const int64_t* tile_ptr, int64_t ntiles, int nitems,
                  const double* pts, KernelFn kf, int* dup_flag, hipStream_t s);
-template <typename T>
-void launch_gemm(const GemmItem<T>* items, const GemmTerm<T>* terms, const int64_t* tile_ptr,
+// TI: operand / MFMA type (f64 or f32, accumulation in that type); TC: type of C.
+template <typename TI, typename TC>
+void launch_gemm(const GemmItem<TC>* items, const GemmTerm<TI>* terms, const int64_t* tile_ptr,
                  int64_t ntiles, int nitems, int tile, hipStream_t s);
 void launch_lu_panel(const MatDesc* d, int nmat, int j0, int nb, hipStream_t s);
 void launch_lu_swap_trsm(const MatDesc* d, const int64_t* slab_ptr, int64_t nslabs, int nmat,

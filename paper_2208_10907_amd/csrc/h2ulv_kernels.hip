@@ -130,8 +130,8 @@ struct Mfma<float> {
   }
 };
 
-template <typename T, int TM, int TN>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict__ items,
+template <typename T, typename TC, int TM, int TN>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<TC>* __restrict__ items,
                                                    const GemmTerm<T>* __restrict__ terms,
                                                    const int64_t* __restrict__ tile_ptr,
                                                    int nitems) {
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
   __shared__ T Bs[16][TN + 4];
   int64_t tile = blockIdx.x;
   int id = find_item(tile_ptr, nitems, tile);
-  const GemmItem<T> it = items[id];
+  const GemmItem<TC> it = items[id];
   int64_t local = tile - tile_ptr[id];
   const int tm = (it.M + TM - 1) / TM;
   const int row0 = (int)(local % tm) * TM, col0 = (int)(local / tm) * TN;
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
       k0 = kn;
     }
   }
-  const T alpha = (T)it.alpha, beta = (T)it.beta;
+  const TC alpha = (TC)it.alpha, beta = (TC)it.beta;
 #pragma unroll
   for (int bi = 0; bi < BM; ++bi)
 #pragma unroll
@@ -257,29 +257,34 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
         const int row = row0 + (TM / 2) * wr + 16 * bi + Mfma<T>::row(lane, r);
         const int col = col0 + (TN / 2) * wc + 16 * bj + (lane & 15);
         if (row < it.M && col < it.N) {
-          T v = alpha * acc[bi][bj][r];
-          T* c = it.C + row + (int64_t)col * it.ldc;
-          if (beta != T(0)) v += beta * (*c);
+          TC v = alpha * (TC)acc[bi][bj][r];
+          TC* c = it.C + row + (int64_t)col * it.ldc;
+          if (beta != TC(0)) v += beta * (*c);
           *c = v;
         }
       }
 }
 
-template <typename T>
-void launch_gemm(const GemmItem<T>* items, const GemmTerm<T>* terms, const int64_t* tile_ptr,
+template <typename TI, typename TC>
+void launch_gemm(const GemmItem<TC>* items, const GemmTerm<TI>* terms, const int64_t* tile_ptr,
                  int64_t ntiles, int nitems, int tile, hipStream_t s) {
   if (ntiles <= 0) return;
   if (tile == 128)
-    hipLaunchKernelGGL((gemm_kernel<T, 128, 128>), dim3((unsigned)ntiles), dim3(256), 0, s,
+    hipLaunchKernelGGL((gemm_kernel<TI, TC, 128, 128>), dim3((unsigned)ntiles), dim3(256), 0, s,
+                       items, terms, tile_ptr, nitems);
+  else if (tile == 32)  // 32 x 128 tiles for batches whose items have M <= 32
+    hipLaunchKernelGGL((gemm_kernel<TI, TC, 32, 128>), dim3((unsigned)ntiles), dim3(256), 0, s,
                        items, terms, tile_ptr, nitems);
   else
-    hipLaunchKernelGGL((gemm_kernel<T, 64, 64>), dim3((unsigned)ntiles), dim3(256), 0, s, items,
-                       terms, tile_ptr, nitems);
+    hipLaunchKernelGGL((gemm_kernel<TI, TC, 64, 64>), dim3((unsigned)ntiles), dim3(256), 0, s,
+                       items, terms, tile_ptr, nitems);
 }
-template void launch_gemm<double>(const GemmItem<double>*, const GemmTerm<double>*,
-                                  const int64_t*, int64_t, int, int, hipStream_t);
-template void launch_gemm<float>(const GemmItem<float>*, const GemmTerm<float>*, const int64_t*,
-                                 int64_t, int, int, hipStream_t);
+template void launch_gemm<double, double>(const GemmItem<double>*, const GemmTerm<double>*,
+                                          const int64_t*, int64_t, int, int, hipStream_t);
+template void launch_gemm<float, float>(const GemmItem<float>*, const GemmTerm<float>*,
+                                        const int64_t*, int64_t, int, int, hipStream_t);
+template void launch_gemm<float, double>(const GemmItem<double>*, const GemmTerm<float>*,
+                                         const int64_t*, int64_t, int, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Blocked LU with partial pivoting (Sec. II-B Eq. lu: LU of S^RR; also the

@@ -200,3 +200,23 @@ def test_sphere_65536_sampled():
     assert rel < 0.1  # rank cap 128 limits one solve's accuracy; refinement recovers it
     x2, it, rr = fg.refine(b, rtol=1e-10, max_iter=30)
     assert rr <= 1e-10
+
+
+def test_mixed_precision_refines_to_fp64_accuracy():
+    """FP32 fill-in products, couplings, rotations and Schur updates with FP64
+    QR/ID, inverses, solve and residual: one solve is close to the FP64
+    factor's, and refinement with the exact FP64 matvec reaches 1e-10."""
+    X = W.cube_points(6000, 21)
+    prob_kw = dict(leaf=128, tol=1e-6, far_sample=32)
+    f64 = H.factorize(X, H.make_params(**prob_kw))
+    f32 = H.factorize(X, H.make_params(precision=H.MIXED, **prob_kw))
+    b = torch.tensor(W.gaussian_rhs(6000, 3, 4), device="cuda")
+    x64 = f64.solve(b)
+    x32 = f32.solve(b)
+    one_shot = (torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)).item()
+    assert one_shot < 1e-3, one_shot
+    y64, it64, r64 = f64.refine(b, rtol=1e-10, max_iter=40)
+    y32, it32, r32 = f32.refine(b, rtol=1e-10, max_iter=40)
+    assert r64 <= 1e-10 and r32 <= 1e-10
+    assert (torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64)).item() < 1e-8
+    assert it32 <= it64 + 3
