@@ -26,6 +26,7 @@ HIP_FLAGS = ["-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",
 SOURCES = [
     ("h2ulv_kernels.hip", []),
     ("h2ulv_dense.cpp", ["-x", "hip"]),
+    ("h2ulv_factor.cpp", ["-x", "hip"]),
     ("h2ulv_api.cpp", ["-x", "hip"]),
     ("h2ulv_tree.cpp", ["-x", "hip", "-ffp-contract=off"]),
 ]

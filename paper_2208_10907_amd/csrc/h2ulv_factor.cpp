@@ -1,0 +1,1466 @@
+// H^2-ULV factorization without trailing sub-matrix dependencies: the batched
+// level driver.  Each level of the tree is one batched pass over all of its
+// boxes (Sec. III of Ma, Deshmukh, Yokota, arXiv 2208.10907), and several
+// independent problems go through the same launches: problems are aligned by
+// height above their leaves, and every phase of a level gathers the work items
+// of all problems of the group before it launches.
+//   (a) dense blocks of the inadmissible pairs (leaf: kernel evaluation; upper
+//       levels: the children's skeleton blocks merged 2 x 2, Sec. II-C);
+//   (b) fill-ins F_ij = sum_k D_ik D_kk^-1 D_kj into every reachable (i, j),
+//       from one inverse per diagonal block (Sec. III-B);
+//   (c) shared basis from M'_i = [K(P_i, far) | T^-1 F_i+] (Sec. III-C,
+//       Eq. fillu): tall Householder QR, column-pivoted QR of its triangle,
+//       row ID W', and the orthogonal factor of W = T W' (Sec. II-A);
+//   (d) low-rank couplings S_ij = T_i K(sk_i, sk_j) T_j^T (Eq. ss);
+//   (e) rotation S_ii = U_i^T D_ii U_i and S^SS_ij = U^S_i^T D_ij U^S_j (Eq. rs);
+//   (f) elimination of the redundant part: inverse of S^RR, S^RR^-1 S^RS and
+//       the Schur update S^SS - S^SR S^RR^-1 S^RS (Sec. II-B, Eq. lu ff.);
+// then the root blocks are inverted (Eq. BLR2final).  Ranks are read back once
+// per level to size the next level.
+#include "h2ulv_factor.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <numeric>
+
+namespace h2ulv {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+KernelFn kfn(const h2ulv_params& p) { return KernelFn{p.kernel, p.alpha, p.diag}; }
+
+namespace {
+
+// float copy of a device array (mixed precision: operands of the FP32 products)
+DBuf to_f32(const double* src, int64_t count, hipStream_t s) {
+  DBuf b(std::max<int64_t>(count, 1) * sizeof(float));
+  launch_convert_d2f(src, b.as<float>(), count, s);
+  H2ULV_HIP(hipGetLastError());
+  return b;
+}
+
+// far-field column indices of box i at level lev: exact = every point outside
+// the near boxes; sampled = all candidate rows of the own-level far boxes +
+// strided samples of the ancestors' far boxes (all points of a box holding at
+// most s points).
+std::vector<int64_t> far_columns(const Tree& t, const Lists& ls, int lev, int i,
+                                 const std::vector<std::vector<int64_t>>& cand, int s) {
+  std::vector<int64_t> out;
+  if (s == 0) {
+    std::vector<char> mask(t.n, 1);
+    for (int64_t e = ls.near_ptr[lev][i]; e < ls.near_ptr[lev][i + 1]; ++e) {
+      int j = ls.near_idx[lev][e];
+      for (int64_t a = t.start[lev][j]; a < t.end[lev][j]; ++a) mask[a] = 0;
+    }
+    for (int64_t a = 0; a < t.n; ++a)
+      if (mask[a]) out.push_back(t.perm[a]);
+    return out;
+  }
+  for (int64_t e = ls.far_ptr[lev][i]; e < ls.far_ptr[lev][i + 1]; ++e) {
+    int q = ls.far_idx[lev][e];
+    out.insert(out.end(), cand[q].begin(), cand[q].end());
+  }
+  int a = i;
+  for (int la = lev - 1; la >= 1; --la) {
+    a >>= 1;
+    for (int64_t e = ls.far_ptr[la][a]; e < ls.far_ptr[la][a + 1]; ++e) {
+      int q = ls.far_idx[la][e];
+      int64_t s0 = t.start[la][q], nq = t.end[la][q] - s0;
+      if (nq <= s) {
+        for (int64_t u = 0; u < nq; ++u) out.push_back(t.perm[s0 + u]);
+      } else {
+        for (int u = 0; u < s; ++u) out.push_back(t.perm[s0 + (int64_t)((u + 0.5) * nq / s)]);
+      }
+    }
+  }
+  return out;
+}
+
+std::vector<int> fill_targets(const Lists& ls, int lev, int i) {
+  std::vector<int> js;
+  for (int64_t e = ls.near_ptr[lev][i]; e < ls.near_ptr[lev][i + 1]; ++e) {
+    int k = ls.near_idx[lev][e];
+    if (k == i) continue;
+    for (int64_t f = ls.near_ptr[lev][k]; f < ls.near_ptr[lev][k + 1]; ++f) {
+      int j = ls.near_idx[lev][f];
+      if (j != k) js.push_back(j);
+    }
+  }
+  std::sort(js.begin(), js.end());
+  js.erase(std::unique(js.begin(), js.end()), js.end());
+  return js;
+}
+
+int64_t csr_find(const std::vector<int64_t>& ptr, const std::vector<int32_t>& idx, int i, int j) {
+  auto b = idx.begin() + ptr[i], e = idx.begin() + ptr[i + 1];
+  auto it = std::lower_bound(b, e, j);
+  if (it != e && *it == j) return it - idx.begin();
+  return -1;
+}
+
+void check_info(const int32_t* dinfo, size_t n, hipStream_t s, const char* what) {
+  if (!dinfo || n == 0) return;
+  std::vector<int32_t> h(n);
+  H2ULV_HIP(hipMemcpyAsync(h.data(), dinfo, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  H2ULV_HIP(hipStreamSynchronize(s));
+  for (size_t i = 0; i < n; ++i)
+    if (h[i] != 0)
+      fail(H2ULV_ERR_SINGULAR, std::string("zero or non-finite pivot in ") + what);
+}
+
+// One problem of the batch: its factor, its place in the shared point buffer
+// and the state of the level being factored.
+struct Prob {
+  h2ulv_factor* F = nullptr;
+  int64_t poff = 0;  // offset of its points in the shared point buffer
+  double fl_fill = 0, fl_basis = 0, fl_couple = 0, fl_rotate = 0, fl_elim = 0, fl_root = 0,
+         kevals = 0;
+
+  // skeleton blocks of the level just finished, keyed by CSR position (near
+  // pairs, then far pairs)
+  DBuf Shat;
+  std::vector<int64_t> shat_near_off, shat_far_off;
+
+  // level state
+  int lev = 0, nb = 0;
+  std::vector<int64_t> cand_all, cand_off;
+  DBuf dcand;
+  std::vector<int64_t> Doff, offSq, offTinv, offE, offW, ncols;
+  DBuf D, Dinv, Tinv, Z, D32, PQ, pivd, kd, Ebuf, S;
+  std::vector<std::vector<int>> targets;
+  std::vector<std::vector<int64_t>> farcols;
+  std::vector<int> capeff;
+
+  int L() const { return F->tree.L; }
+  LevelFactor& lf() { return F->levels[lev]; }
+  const std::vector<int64_t>& np() const { return F->lists.near_ptr[lev]; }
+  const std::vector<int32_t>& ni() const { return F->lists.near_idx[lev]; }
+  const std::vector<int64_t>& fp() const { return F->lists.far_ptr[lev]; }
+  const std::vector<int32_t>& fi() const { return F->lists.far_idx[lev]; }
+  int64_t nnear() const { return np()[nb]; }
+  int64_t nfar() const { return fp()[nb]; }
+  const int64_t* candp(int i) const { return dcand.as<int64_t>() + cand_off[i]; }
+  double* Dblk(int i, int j) { return D.as<double>() + Doff[csr_find(np(), ni(), i, j)]; }
+
+  const double* shat_block(int clev, int c, int d, int64_t* ld) {
+    const Lists& ls = F->lists;
+    *ld = F->levels[clev].k[c];
+    int64_t e = csr_find(ls.near_ptr[clev], ls.near_idx[clev], c, d);
+    if (e >= 0) return Shat.as<double>() + shat_near_off[e];
+    e = csr_find(ls.far_ptr[clev], ls.far_idx[clev], c, d);
+    if (e < 0) fail(H2ULV_ERR_HIP, "internal: child pair is neither near nor far");
+    return Shat.as<double>() + shat_far_off[e];
+  }
+
+  // device bytes the level's transient buffers need at their peak (dense
+  // blocks, their fill-in products and the per-box square workspaces)
+  double level_bytes(bool mixed) const {
+    const auto& m = F->levels[lev].cand;
+    double dw = 0, sq = 0;
+    for (int i = 0; i < nb; ++i) {
+      double mi = (double)m[i].size();
+      sq += mi * mi;
+      for (int64_t e = np()[i]; e < np()[i + 1]; ++e) dw += mi * (double)m[ni()[e]].size();
+    }
+    return 8.0 * (3.0 * dw + 4.0 * sq) + (mixed ? 4.0 * dw : 0.0);
+  }
+
+  void end_level() {
+    cand_all.clear();
+    cand_off.clear();
+    Doff.clear();
+    offSq.clear();
+    offTinv.clear();
+    offE.clear();
+    offW.clear();
+    ncols.clear();
+    targets.clear();
+    farcols.clear();
+    capeff.clear();
+    for (DBuf* b : {&dcand, &D, &Dinv, &Tinv, &Z, &D32, &PQ, &pivd, &kd, &Ebuf, &S}) b->reset();
+  }
+};
+
+struct Driver {
+  hipStream_t s;
+  h2ulv_params p;
+  KernelFn kf;
+  bool mixed;
+  const double* pts = nullptr;  // shared points of all problems (n x 3 each)
+  DBuf dupbuf;
+  int* dup = nullptr;
+
+  // per-step wall times (verbose mode synchronises at each step)
+  std::map<std::string, double> step_time;
+  double t_last = 0;
+
+  Driver(hipStream_t st, const h2ulv_params& pr)
+      : s(st), p(pr), kf(kfn(pr)), mixed(pr.precision == H2ULV_MIXED) {
+    dupbuf.alloc(sizeof(int));
+    dup = dupbuf.as<int>();
+    H2ULV_HIP(hipMemsetAsync(dup, 0, sizeof(int), s));
+  }
+
+  void tick(const char* name) {
+    if (!p.verbose) return;
+    H2ULV_HIP(hipStreamSynchronize(s));
+    double t = now_s();
+    if (name) step_time[name] += t - t_last;
+    t_last = t;
+  }
+
+  void check_dup() {
+    int h = 0;
+    H2ULV_HIP(hipMemcpyAsync(&h, dup, sizeof(int), hipMemcpyDeviceToHost, s));
+    H2ULV_HIP(hipStreamSynchronize(s));
+    if (h) fail(H2ULV_ERR_DUPLICATE_POINTS, "two distinct points coincide");
+  }
+
+  void level(const std::vector<Prob*>& G);
+  void roots(const std::vector<Prob*>& G);
+
+ private:
+  void dense_blocks(Stage& st, const std::vector<Prob*>& G);
+  void fill_products(Stage& st, const std::vector<Prob*>& G);
+  void basis_triangles(Stage& st, const std::vector<Prob*>& G);
+  void pivoted_qr(Stage& st, const std::vector<Prob*>& G);
+  void bases(Stage& st, const std::vector<Prob*>& G);
+  void couplings(Stage& st, const std::vector<Prob*>& G);
+  void rotations(Stage& st, const std::vector<Prob*>& G);
+  void elimination(Stage& st, const std::vector<Prob*>& G);
+};
+
+// ---- (a) dense blocks ---------------------------------------------------------
+void Driver::dense_blocks(Stage& st, const std::vector<Prob*>& G) {
+  KgenBatch kb;
+  CopyBatch cb;
+  for (Prob* P : G) {
+    LevelFactor& lf = P->lf();
+    const int nb = P->nb;
+    const std::vector<int>& m = lf.m;
+    const auto& np = P->np();
+    const auto& ni = P->ni();
+    const int64_t nnear = P->nnear();
+    P->Doff.assign(nnear + 1, 0);
+    for (int i = 0; i < nb; ++i)
+      for (int64_t e = np[i]; e < np[i + 1]; ++e)
+        P->Doff[e + 1] = P->Doff[e] + (int64_t)m[i] * m[ni[e]];
+    P->D.alloc(std::max<int64_t>(P->Doff[nnear], 1) * sizeof(double));
+    double* Dp = P->D.as<double>();
+    if (P->lev == P->L()) {
+      for (int i = 0; i < nb; ++i)
+        for (int64_t e = np[i]; e < np[i + 1]; ++e) {
+          int j = ni[e];
+          kb.add(P->candp(i), m[i], P->candp(j), m[j], Dp + P->Doff[e], m[i]);
+          P->kevals += (double)m[i] * m[j];
+        }
+    } else {
+      const std::vector<int>& kc = P->F->levels[P->lev + 1].k;
+      for (int i = 0; i < nb; ++i)
+        for (int64_t e = np[i]; e < np[i + 1]; ++e) {
+          int j = ni[e];
+          double* out = Dp + P->Doff[e];
+          int rows[2] = {2 * i, 2 * i + 1}, cols[2] = {2 * j, 2 * j + 1};
+          int ro = 0;
+          for (int a = 0; a < 2; ++a) {
+            int co = 0;
+            for (int b = 0; b < 2; ++b) {
+              int64_t ld;
+              const double* src = P->shat_block(P->lev + 1, rows[a], cols[b], &ld);
+              cb.add(src, std::max<int64_t>(ld, 1), out + ro + (int64_t)co * m[i], m[i],
+                     kc[rows[a]], kc[cols[b]]);
+              co += kc[cols[b]];
+            }
+            ro += kc[rows[a]];
+          }
+        }
+    }
+  }
+  kb.run(st, pts, kf, dup);
+  cb.run(st);
+  st.sync();
+  for (Prob* P : G) P->Shat.reset();  // children's skeleton blocks are merged now
+}
+
+// ---- (b) fill-ins: inverses of the diagonal blocks and Z'_ik = T^-1 D_ik D_kk^-1
+void Driver::fill_products(Stage& st, const std::vector<Prob*>& G) {
+  {
+    std::vector<DBuf> LUw;
+    CopyBatch cb;
+    std::vector<SqMat> mats;
+    for (Prob* P : G) {
+      const int nb = P->nb;
+      const std::vector<int>& m = P->lf().m;
+      P->offSq.assign(nb + 1, 0);
+      for (int i = 0; i < nb; ++i) P->offSq[i + 1] = P->offSq[i] + (int64_t)m[i] * m[i];
+      P->Dinv.alloc(std::max<int64_t>(P->offSq[nb], 1) * sizeof(double));
+      LUw.emplace_back(std::max<int64_t>(P->offSq[nb], 1) * sizeof(double));
+      double* W = LUw.back().as<double>();
+      for (int i = 0; i < nb; ++i) {
+        if (m[i] == 0) continue;
+        cb.add(P->Dblk(i, i), m[i], W + P->offSq[i], m[i], m[i], m[i]);
+        mats.push_back(SqMat{W + P->offSq[i], m[i], m[i], P->Dinv.as<double>() + P->offSq[i], m[i]});
+        P->fl_fill += 2.0 / 3.0 * std::pow((double)m[i], 3);
+      }
+    }
+    cb.run(st);
+    int32_t* info = nullptr;
+    batched_inverse(st, mats, &info, nullptr, nullptr);
+    check_info(info, mats.size(), s, "a diagonal block (fill-in step)");
+    st.sync();
+  }
+  tick("b_inverse");
+  // inverse T factors of the children (T-hat^-1 is block diagonal)
+  {
+    std::vector<DBuf> Tw;
+    CopyBatch cb;
+    std::vector<SqMat> mats;
+    for (Prob* P : G) {
+      if (P->lev == P->L()) continue;
+      const int nb = P->nb;
+      const LevelFactor& ch = P->F->levels[P->lev + 1];
+      P->offTinv.assign(2 * nb + 1, 0);
+      for (int c = 0; c < 2 * nb; ++c)
+        P->offTinv[c + 1] = P->offTinv[c] + (int64_t)ch.k[c] * ch.k[c];
+      P->Tinv.alloc(std::max<int64_t>(P->offTinv[2 * nb], 1) * sizeof(double));
+      Tw.emplace_back(std::max<int64_t>(P->offTinv[2 * nb], 1) * sizeof(double));
+      double* W = Tw.back().as<double>();
+      for (int c = 0; c < 2 * nb; ++c) {
+        if (ch.k[c] == 0) continue;
+        cb.add(ch.Tt.as<double>() + ch.offT[c], ch.k[c], W + P->offTinv[c], ch.k[c], ch.k[c],
+               ch.k[c]);
+        mats.push_back(SqMat{W + P->offTinv[c], ch.k[c], ch.k[c],
+                             P->Tinv.as<double>() + P->offTinv[c], ch.k[c]});
+      }
+    }
+    if (!mats.empty()) {
+      cb.run(st);
+      batched_triu_inverse(st, mats);
+      st.sync();
+    }
+  }
+  // Z'_ik for k in Near(i) \ {i}, stored at the CSR position of (i, k)
+  {
+    std::vector<DBuf> Ztmp;
+    GemmBatch<double> g, g2;
+    for (Prob* P : G) {
+      const int nb = P->nb;
+      const std::vector<int>& m = P->lf().m;
+      const auto& np = P->np();
+      const auto& ni = P->ni();
+      const bool upper = P->lev < P->L();
+      const int64_t words = std::max<int64_t>(P->Doff[P->nnear()], 1);
+      P->Z.alloc(words * sizeof(double));
+      double* Zp = P->Z.as<double>();
+      double* Zt = Zp;
+      if (upper) {
+        Ztmp.emplace_back(words * sizeof(double));
+        Zt = Ztmp.back().as<double>();
+      }
+      const double* Dp = P->D.as<double>();
+      for (int i = 0; i < nb; ++i)
+        for (int64_t e = np[i]; e < np[i + 1]; ++e) {
+          int k = ni[e];
+          if (k == i || m[i] == 0 || m[k] == 0) continue;
+          g.one(Zt + P->Doff[e], m[i], m[i], m[k], m[k], Dp + P->Doff[e], m[i], false,
+                P->Dinv.as<double>() + P->offSq[k], m[k], false);
+          P->fl_fill += 2.0 * m[i] * (double)m[k] * m[k];
+          if (!upper) continue;
+          const LevelFactor& ch = P->F->levels[P->lev + 1];
+          int k1 = ch.k[2 * i], k2 = ch.k[2 * i + 1];
+          const double* Ti = P->Tinv.as<double>();
+          if (k1 > 0)
+            g2.one(Zp + P->Doff[e], m[i], k1, m[k], k1, Ti + P->offTinv[2 * i], k1, false,
+                   Zt + P->Doff[e], m[i], false);
+          if (k2 > 0)
+            g2.one(Zp + P->Doff[e] + k1, m[i], k2, m[k], k2, Ti + P->offTinv[2 * i + 1], k2,
+                   false, Zt + P->Doff[e] + k1, m[i], false);
+        }
+    }
+    g.run(st);
+    g2.run(st);
+    st.sync();
+  }
+  for (Prob* P : G) {
+    P->Dinv.reset();
+    P->Tinv.reset();
+  }
+}
+
+// ---- (c) M'^T, its tall QR (chunked over boxes by memory) -> m x m triangles
+void Driver::basis_triangles(Stage& st, const std::vector<Prob*>& G) {
+  struct Box {
+    Prob* P;
+    int i;
+  };
+  std::vector<Box> boxes;
+  for (Prob* P : G) {
+    LevelFactor& lf = P->lf();
+    const int nb = P->nb;
+    const std::vector<int>& m = lf.m;
+    const Lists& ls = P->F->lists;
+    P->targets.assign(nb, {});
+    P->farcols.assign(nb, {});
+    P->ncols.assign(nb, 0);
+    for (int i = 0; i < nb; ++i) {
+      P->targets[i] = fill_targets(ls, P->lev, i);
+      P->farcols[i] = far_columns(P->F->tree, ls, P->lev, i, lf.cand, p.far_sample);
+      int64_t nc = (int64_t)P->farcols[i].size();
+      for (int j : P->targets[i]) nc += m[j];
+      P->ncols[i] = nc;
+      boxes.push_back(Box{P, i});
+    }
+    // mixed precision: the rotations, low-rank couplings and Schur updates run on
+    // FP32 matrix cores with FP32 accumulation; the fill-in products stay FP64
+    // because they feed the rank-revealing QR, whose decisions at tol ~1e-6 sit
+    // at FP32 rounding level (FP32 fill-ins inflate the upper-level ranks several
+    // times); inverses, QR/ID, solve and residual are FP64 as well
+    if (mixed) P->D32 = to_f32(P->D.as<double>(), P->Doff[P->nnear()], s);
+    // per-box pivoted-QR matrices (m x m) kept until W' is built
+    P->PQ.alloc(std::max<int64_t>(P->offSq[nb], 1) * sizeof(double));
+    P->pivd.alloc(std::max<int64_t>(P->cand_off[nb], 1) * sizeof(int32_t));
+    P->kd.alloc(std::max(nb, 1) * sizeof(int32_t));
+    H2ULV_HIP(hipMemsetAsync(P->PQ.p, 0, P->PQ.bytes, s));
+  }
+  size_t freeb = 0, totb = 0;
+  H2ULV_HIP(hipMemGetInfo(&freeb, &totb));
+  int64_t budget = (int64_t)(freeb * 0.4) / (int64_t)sizeof(double);
+  budget = std::max<int64_t>(budget, 1 << 20);
+  auto box_words = [&](const Box& b) {
+    // M'^T plus the QR workspaces of its chunks (reflector panels, T, GEMM scratch)
+    const int64_t mi = b.P->lf().m[b.i];
+    return mi * b.P->ncols[b.i] * 3 / 2 + 8 * mi * mi + 4096;
+  };
+  const size_t nbox = boxes.size();
+  size_t b0 = 0;
+  while (b0 < nbox) {
+    size_t b1 = b0;
+    int64_t acc = 0;
+    while (b1 < nbox && (b1 == b0 || acc + box_words(boxes[b1]) <= budget)) {
+      acc += box_words(boxes[b1]);
+      ++b1;
+    }
+    const size_t nc = b1 - b0;
+    // M'^T (ncols x m, column-major): far-field rows then fill-in rows
+    std::vector<int64_t> moff(nc + 1, 0);
+    for (size_t q = 0; q < nc; ++q) {
+      const Box& b = boxes[b0 + q];
+      moff[q + 1] = moff[q] + (int64_t)b.P->lf().m[b.i] * b.P->ncols[b.i];
+    }
+    DBuf Mb(std::max<int64_t>(moff.back(), 1) * sizeof(double));
+    double* Mp = Mb.as<double>();
+    std::vector<int64_t> fc_all, fc_off(nc, 0);
+    for (size_t q = 0; q < nc; ++q) {
+      const Box& b = boxes[b0 + q];
+      fc_off[q] = (int64_t)fc_all.size();
+      for (int64_t c : b.P->farcols[b.i]) fc_all.push_back(c + b.P->poff);
+    }
+    const int64_t* dfc = st.up(std::move(fc_all));
+    KgenBatch kb;
+    GemmBatch<double> g;
+    for (size_t q = 0; q < nc; ++q) {
+      Prob* P = boxes[b0 + q].P;
+      const int i = boxes[b0 + q].i;
+      const std::vector<int>& m = P->lf().m;
+      if (m[i] == 0) continue;
+      const auto& np = P->np();
+      const auto& ni = P->ni();
+      double* Mi = Mp + moff[q];
+      const int64_t ld = P->ncols[i];
+      const int64_t nf = (int64_t)P->farcols[i].size();
+      kb.add(dfc + fc_off[q], (int)nf, P->candp(i), m[i], Mi, ld);
+      P->kevals += (double)m[i] * nf;
+      int64_t row = nf;
+      for (int j : P->targets[i]) {
+        if (m[j] > 0) {
+          // (T^-1 F_ij)^T = sum_k D_kj^T Z'_ik^T
+          g.item(Mi + row, ld, m[j], m[i]);
+          for (int64_t e = np[i]; e < np[i + 1]; ++e) {
+            int k = ni[e];
+            if (k == i || k == j || m[k] == 0) continue;
+            int64_t ekj = csr_find(np, ni, k, j);
+            if (ekj < 0) continue;
+            g.term(P->D.as<double>() + P->Doff[ekj], m[k], true, P->Z.as<double>() + P->Doff[e],
+                   m[i], true, m[k]);
+            P->fl_fill += 2.0 * m[i] * (double)m[k] * m[j];
+          }
+        }
+        row += m[j];
+      }
+    }
+    kb.run(st, pts, kf, dup);
+    g.run(st);
+    tick("c_fill_gemm");
+    // tall QR of every M'^T: a tree of blocked Householder QRs (leaf chunks of
+    // 4m rows factored in place, then stacked triangles merged pairwise)
+    struct Rref {
+      double* p;
+      int64_t ld;
+      int r;
+    };
+    std::vector<std::vector<Rref>> cur(nc);
+    std::vector<int> mq(nc);
+    std::vector<TallQr> leaf;
+    for (size_t q = 0; q < nc; ++q) {
+      Prob* P = boxes[b0 + q].P;
+      const int i = boxes[b0 + q].i;
+      const int mi = P->lf().m[i];
+      const int64_t nci = P->ncols[i];
+      mq[q] = mi;
+      if (mi == 0 || nci == 0) continue;
+      double* Mi = Mp + moff[q];
+      const int64_t h = std::max<int64_t>(4 * (int64_t)mi, 256);
+      for (int64_t r0 = 0; r0 < nci; r0 += h) {
+        int hc = (int)std::min<int64_t>(h, nci - r0);
+        leaf.push_back(TallQr{Mi + r0, nci, hc, mi});
+        cur[q].push_back(Rref{Mi + r0, nci, std::min(hc, mi)});
+      }
+      double ncd = (double)nci, mm = (double)mi;
+      P->fl_basis += (ncd >= mm) ? 2.0 * ncd * mm * mm - 2.0 / 3.0 * mm * mm * mm
+                                 : 2.0 * mm * ncd * ncd - 2.0 / 3.0 * ncd * ncd * ncd;
+    }
+    batched_qr_R(st, leaf);
+    std::vector<DBuf> rounds;
+    for (;;) {
+      int64_t words = 0;
+      bool more = false;
+      for (size_t q = 0; q < nc; ++q)
+        for (size_t u = 0; u + 1 < cur[q].size(); u += 2) {
+          words += (int64_t)(cur[q][u].r + cur[q][u + 1].r) * mq[q];
+          more = true;
+        }
+      if (!more) break;
+      DBuf buf(std::max<int64_t>(words, 1) * sizeof(double));
+      double* bp = buf.as<double>();
+      int64_t off = 0;
+      CopyBatch cb;
+      std::vector<CopyItem> zl;
+      std::vector<TallQr> qs;
+      for (size_t q = 0; q < nc; ++q) {
+        auto& v = cur[q];
+        const int mi = mq[q];
+        std::vector<Rref> nxt;
+        for (size_t u = 0; u < v.size(); u += 2) {
+          if (u + 1 == v.size()) {
+            nxt.push_back(v[u]);
+            continue;
+          }
+          const Rref& ra = v[u];
+          const Rref& rb = v[u + 1];
+          const int hs = ra.r + rb.r;
+          double* Sb = bp + off;
+          off += (int64_t)hs * mi;
+          cb.add(ra.p, ra.ld, Sb, hs, ra.r, mi);
+          cb.add(rb.p, rb.ld, Sb + ra.r, hs, rb.r, mi);
+          zl.push_back(CopyItem{nullptr, Sb, 0, hs, ra.r, mi, 0, 0});
+          zl.push_back(CopyItem{nullptr, Sb + ra.r, 0, hs, rb.r, mi, 0, 0});
+          qs.push_back(TallQr{Sb, hs, hs, mi});
+          nxt.push_back(Rref{Sb, hs, std::min(hs, mi)});
+        }
+        v.swap(nxt);
+      }
+      cb.run(st);
+      int nz = (int)zl.size();
+      CopyItem* dz = st.up(std::move(zl));
+      launch_zero_lower(dz, nz, s);
+      H2ULV_HIP(hipGetLastError());
+      batched_qr_R(st, qs);
+      rounds.push_back(std::move(buf));
+    }
+    // final triangles into the m x m pivoted-QR matrices (zero below)
+    {
+      CopyBatch cb;
+      std::vector<CopyItem> zl;
+      for (size_t q = 0; q < nc; ++q) {
+        if (cur[q].empty()) continue;
+        Prob* P = boxes[b0 + q].P;
+        const int i = boxes[b0 + q].i;
+        const int mi = mq[q];
+        const Rref& r = cur[q][0];
+        double* PQi = P->PQ.as<double>() + P->offSq[i];
+        cb.add(r.p, r.ld, PQi, mi, r.r, mi);
+        zl.push_back(CopyItem{nullptr, PQi, 0, mi, r.r, mi, 0, 0});
+      }
+      cb.run(st);
+      int nz = (int)zl.size();
+      CopyItem* dz = st.up(std::move(zl));
+      launch_zero_lower(dz, nz, s);
+      H2ULV_HIP(hipGetLastError());
+    }
+    tick("c_tsqr");
+    st.sync();
+    b0 = b1;
+  }
+}
+
+// ---- (c) column-pivoted QR of each m x m triangle: small boxes one workgroup
+// each, large boxes over many workgroups, one pivot step per pair of launches;
+// then ranks, pivots and skeletons to the host
+void Driver::pivoted_qr(Stage& st, const std::vector<Prob*>& G) {
+  const int BIG = 512;
+  struct Big {
+    Prob* P;
+    int i;
+    int64_t g;
+  };
+  std::vector<Big> bigs;
+  int64_t tot_cand = 0, tot_box = 0;
+  for (Prob* P : G) {
+    tot_cand += P->cand_off[P->nb];
+    tot_box += P->nb;
+  }
+  std::vector<PivQrItem> pq;
+  std::vector<PivQrState> big;
+  double* nrm = st.scratch<double>(std::max<int64_t>(tot_cand, 1));
+  double* dg = st.scratch<double>(std::max<int64_t>(tot_cand, 1));
+  double* scal = st.scratch<double>(2 * (size_t)tot_box + 2);
+  int32_t* flg = st.scratch<int32_t>(2 * (size_t)tot_box + 2);
+  {
+    int64_t co = 0, bo = 0;
+    for (Prob* P : G) {
+      const int nb = P->nb;
+      const std::vector<int>& m = P->lf().m;
+      P->capeff.assign(nb, 0);
+      for (int i = 0; i < nb; ++i) {
+        P->capeff[i] = (int)std::min<int64_t>(m[i], P->ncols[i]);
+        if (p.rank_cap > 0) P->capeff[i] = std::min(P->capeff[i], p.rank_cap);
+      }
+      for (int i = 0; i < nb; ++i) {
+        if (m[i] == 0) continue;
+        double* PQi = P->PQ.as<double>() + P->offSq[i];
+        const int64_t c = co + P->cand_off[i];
+        if (m[i] <= BIG) {
+          PivQrItem it{};
+          it.A = PQi;
+          it.lda = m[i];
+          it.m = m[i];
+          it.n = m[i];
+          it.piv = P->pivd.as<int32_t>() + P->cand_off[i];
+          it.kout = P->kd.as<int32_t>() + i;
+          it.diag = dg + c;
+          it.work = nrm + c;
+          it.tol = p.tol;
+          it.cap = std::max(P->capeff[i], 0);
+          pq.push_back(it);
+        } else {
+          PivQrState ps{};
+          ps.A = PQi;
+          ps.lda = m[i];
+          ps.m = m[i];
+          ps.cap = P->capeff[i];
+          ps.nrm = nrm + c;
+          ps.piv = P->pivd.as<int32_t>() + P->cand_off[i];
+          ps.scal = scal + 2 * (bo + i);
+          ps.flags = flg + 2 * (bo + i);
+          ps.tol = p.tol;
+          big.push_back(ps);
+          bigs.push_back(Big{P, i, bo + i});
+        }
+      }
+      co += P->cand_off[nb];
+      bo += nb;
+    }
+  }
+  int npq = (int)pq.size();
+  PivQrItem* dpq = st.up(std::move(pq));
+  {
+    ProfScope ps("pivqr_small", 0, 0, s);
+    launch_pivqr(dpq, npq, s);
+  }
+  H2ULV_HIP(hipGetLastError());
+  std::map<std::pair<Prob*, int>, int> bigk;
+  if (!big.empty()) {
+    int nbig = (int)big.size();
+    int maxcap = 0;
+    std::vector<int64_t> sp(1, 0);
+    for (auto& b : big) {
+      sp.push_back(sp.back() + (b.m + 3) / 4);
+      maxcap = std::max(maxcap, b.cap);
+    }
+    int64_t ns = sp.back();
+    PivQrState* dst_ = st.up(std::move(big));
+    int64_t* dsp = st.up(std::move(sp));
+    {
+      ProfScope ps("pivqr_large", 0, 0, s);
+      launch_pivqr_init(dst_, dsp, ns, nbig, s);
+      for (int t = 0; t < maxcap; ++t) {
+        launch_pivqr_pick(dst_, nbig, t, s);
+        launch_pivqr_apply(dst_, dsp, ns, nbig, t, s);
+      }
+    }
+    H2ULV_HIP(hipGetLastError());
+    std::vector<int32_t> hf(2 * (size_t)tot_box + 2);
+    H2ULV_HIP(hipMemcpyAsync(hf.data(), flg, hf.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                             s));
+    H2ULV_HIP(hipStreamSynchronize(s));
+    for (const Big& b : bigs) bigk[{b.P, b.i}] = hf[2 * b.g + 1];
+    // E = R11^-1 R12 by triangular blocks (large boxes; small ones hold E in place)
+    std::vector<TriRhs> sys;
+    for (Prob* P : G) {
+      const int nb = P->nb;
+      const std::vector<int>& m = P->lf().m;
+      P->offE.assign(nb + 1, 0);
+      for (int i = 0; i < nb; ++i) {
+        auto it = bigk.find({P, i});
+        int64_t words = it == bigk.end() ? 0 : (int64_t)it->second * (m[i] - it->second);
+        P->offE[i + 1] = P->offE[i] + words;
+      }
+      if (P->offE[nb] > 0) P->Ebuf.alloc(P->offE[nb] * sizeof(double));
+    }
+    for (const Big& b : bigs) {
+      Prob* P = b.P;
+      const int i = b.i, mi = P->lf().m[i], ki = bigk[{P, i}];
+      if (ki == 0 || ki == mi) continue;
+      double* PQi = P->PQ.as<double>() + P->offSq[i];
+      sys.push_back(TriRhs{PQi, mi, ki, PQi + (int64_t)ki * mi, mi,
+                           P->Ebuf.as<double>() + P->offE[i], ki, mi - ki});
+    }
+    trsm_upper(st, sys);
+  }
+  tick("c_pivqr");
+  st.sync();
+  for (Prob* P : G) P->Z.reset();
+  check_dup();
+  // ranks and pivots to the host
+  std::vector<std::vector<int32_t>> hk(G.size()), hp(G.size());
+  for (size_t g = 0; g < G.size(); ++g) {
+    Prob* P = G[g];
+    hk[g].resize(P->nb);
+    hp[g].resize(P->cand_off[P->nb]);
+    H2ULV_HIP(hipMemcpyAsync(hk[g].data(), P->kd.p, P->nb * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
+    if (!hp[g].empty())
+      H2ULV_HIP(hipMemcpyAsync(hp[g].data(), P->pivd.p, hp[g].size() * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+  }
+  H2ULV_HIP(hipStreamSynchronize(s));
+  for (size_t g = 0; g < G.size(); ++g) {
+    Prob* P = G[g];
+    LevelFactor& lf = P->lf();
+    lf.k.assign(P->nb, 0);
+    lf.sk.assign(P->nb, {});
+    for (int i = 0; i < P->nb; ++i) {
+      auto it = bigk.find({P, i});
+      lf.k[i] = lf.m[i] == 0 ? 0 : (it != bigk.end() ? it->second : hk[g][i]);
+      lf.sk[i].resize(lf.k[i]);
+      const int32_t* piv = hp[g].data() + P->cand_off[i];
+      for (int t = 0; t < lf.k[i]; ++t) lf.sk[i][t] = lf.cand[i][piv[t]];
+    }
+  }
+}
+
+// ---- (c) W', W = T-hat W', its QR -> U, T ------------------------------------
+void Driver::bases(Stage& st, const std::vector<Prob*>& G) {
+  const int BIG = 512;
+  std::vector<DBuf> Wps, Ws;
+  std::vector<WpItem> wi;
+  GemmBatch<double> g;
+  std::vector<QrW> qs;
+  for (Prob* P : G) {
+    LevelFactor& lf = P->lf();
+    const int nb = P->nb;
+    const std::vector<int>& m = lf.m;
+    const std::vector<int>& k = lf.k;
+    const bool upper = P->lev < P->L();
+    lf.offU.assign(nb + 1, 0);
+    lf.offT.assign(nb + 1, 0);
+    P->offW.assign(nb + 1, 0);
+    for (int i = 0; i < nb; ++i) {
+      lf.offU[i + 1] = lf.offU[i] + (int64_t)m[i] * m[i];
+      lf.offT[i + 1] = lf.offT[i] + (int64_t)k[i] * k[i];
+      P->offW[i + 1] = P->offW[i] + (int64_t)m[i] * k[i];
+    }
+    lf.U.alloc(std::max<int64_t>(lf.offU[nb], 1) * sizeof(double));
+    lf.Tt.alloc(std::max<int64_t>(lf.offT[nb], 1) * sizeof(double));
+    const int64_t ww = std::max<int64_t>(P->offW[nb], 1) * sizeof(double);
+    Ws.emplace_back(ww);
+    double* W = Ws.back().as<double>();
+    double* Wp = W;
+    if (upper) {
+      Wps.emplace_back(ww);
+      Wp = Wps.back().as<double>();
+    }
+    for (int i = 0; i < nb; ++i) {
+      if (k[i] == 0) continue;
+      const bool isbig = m[i] > BIG;
+      const double* E = isbig ? P->Ebuf.as<double>() + P->offE[i]
+                              : P->PQ.as<double>() + P->offSq[i] + (int64_t)k[i] * m[i];
+      wi.push_back(WpItem{P->pivd.as<int32_t>() + P->cand_off[i], E, Wp + P->offW[i],
+                          isbig ? std::max(k[i], 1) : m[i], m[i], m[i], k[i]});
+    }
+    if (upper) {
+      const LevelFactor& ch = P->F->levels[P->lev + 1];
+      for (int i = 0; i < nb; ++i) {
+        if (k[i] == 0) continue;
+        int k1 = ch.k[2 * i], k2 = ch.k[2 * i + 1];
+        double* Wi = W + P->offW[i];
+        const double* Wpi = Wp + P->offW[i];
+        if (k1 > 0)
+          g.one(Wi, m[i], k1, k[i], k1, ch.Tt.as<double>() + ch.offT[2 * i], k1, false, Wpi, m[i],
+                false);
+        if (k2 > 0)
+          g.one(Wi + k1, m[i], k2, k[i], k2, ch.Tt.as<double>() + ch.offT[2 * i + 1], k2, false,
+                Wpi + k1, m[i], false);
+      }
+    }
+    for (int i = 0; i < nb; ++i) {
+      if (m[i] == 0) continue;
+      qs.push_back(QrW{W + P->offW[i], m[i], k[i], lf.U.as<double>() + lf.offU[i],
+                       lf.Tt.as<double>() + lf.offT[i]});
+      P->fl_basis += 4.0 * m[i] * (double)k[i] * k[i] + 4.0 * (double)m[i] * m[i] * k[i];
+    }
+  }
+  int nw = (int)wi.size();
+  WpItem* dwi = st.up(std::move(wi));
+  launch_wprime(dwi, nw, s);
+  H2ULV_HIP(hipGetLastError());
+  g.run(st);
+  batched_qr_basis(st, qs);
+  st.sync();
+  for (Prob* P : G) {
+    P->PQ.reset();
+    P->pivd.reset();
+    P->Ebuf.reset();
+    P->kd.reset();
+  }
+}
+
+// ---- (d) low-rank couplings -------------------------------------------------
+void Driver::couplings(Stage& st, const std::vector<Prob*>& G) {
+  // new skeleton blocks of this level: near pairs then far pairs
+  for (Prob* P : G) {
+    const int nb = P->nb;
+    const std::vector<int>& k = P->lf().k;
+    const auto& np = P->np();
+    const auto& ni = P->ni();
+    const auto& fp = P->fp();
+    const auto& fi = P->fi();
+    P->shat_near_off.assign(P->nnear() + 1, 0);
+    P->shat_far_off.assign(P->nfar() + 1, 0);
+    int64_t tot = 0;
+    for (int i = 0; i < nb; ++i)
+      for (int64_t e = np[i]; e < np[i + 1]; ++e) {
+        P->shat_near_off[e] = tot;
+        tot += (int64_t)k[i] * k[ni[e]];
+      }
+    for (int i = 0; i < nb; ++i)
+      for (int64_t e = fp[i]; e < fp[i + 1]; ++e) {
+        P->shat_far_off[e] = tot;
+        tot += (int64_t)k[i] * k[fi[e]];
+      }
+    P->Shat.alloc(std::max<int64_t>(tot, 1) * sizeof(double));
+  }
+  std::vector<int64_t> skall;
+  std::vector<std::vector<int64_t>> skoff(G.size()), kcoff(G.size());
+  for (size_t g = 0; g < G.size(); ++g) {
+    Prob* P = G[g];
+    const LevelFactor& lf = P->lf();
+    skoff[g].assign(P->nb + 1, 0);
+    for (int i = 0; i < P->nb; ++i) {
+      skoff[g][i] = (int64_t)skall.size();
+      for (int64_t a : lf.sk[i]) skall.push_back(a + P->poff);
+    }
+    const auto& fp = P->fp();
+    const auto& fi = P->fi();
+    kcoff[g].assign(P->nfar() + 1, 0);
+    for (int i = 0; i < P->nb; ++i)
+      for (int64_t e = fp[i]; e < fp[i + 1]; ++e)
+        kcoff[g][e + 1] = kcoff[g][e] + (int64_t)lf.k[i] * lf.k[fi[e]];
+  }
+  const int64_t* dsk = st.up(std::move(skall));
+  std::vector<double*> Kc(G.size()), Tmp(G.size());
+  KgenBatch kb;
+  for (size_t g = 0; g < G.size(); ++g) {
+    Prob* P = G[g];
+    const std::vector<int>& k = P->lf().k;
+    const auto& fp = P->fp();
+    const auto& fi = P->fi();
+    const int64_t words = std::max<int64_t>(kcoff[g].back(), 1);
+    Kc[g] = st.scratch<double>(words);
+    Tmp[g] = st.scratch<double>(words);
+    for (int i = 0; i < P->nb; ++i)
+      for (int64_t e = fp[i]; e < fp[i + 1]; ++e) {
+        int j = fi[e];
+        if (k[i] == 0 || k[j] == 0) continue;
+        kb.add(dsk + skoff[g][i], k[i], dsk + skoff[g][j], k[j], Kc[g] + kcoff[g][e], k[i]);
+        P->kevals += (double)k[i] * k[j];
+        P->fl_couple += 2.0 * k[i] * (double)k[j] * k[j] + 2.0 * k[i] * (double)k[i] * k[j];
+      }
+  }
+  kb.run(st, pts, kf, dup);
+  // tmp = Kc T_j^T ; S = T_i tmp
+  if (!mixed) {
+    GemmBatch<double> g1, g2;
+    for (size_t g = 0; g < G.size(); ++g) {
+      Prob* P = G[g];
+      const LevelFactor& lf = P->lf();
+      const std::vector<int>& k = lf.k;
+      const auto& fp = P->fp();
+      const auto& fi = P->fi();
+      double* Sh = P->Shat.as<double>();
+      for (int i = 0; i < P->nb; ++i)
+        for (int64_t e = fp[i]; e < fp[i + 1]; ++e) {
+          int j = fi[e];
+          if (k[i] == 0 || k[j] == 0) continue;
+          const int64_t o = kcoff[g][e];
+          g1.one(Tmp[g] + o, k[i], k[i], k[j], k[j], Kc[g] + o, k[i], false,
+                 lf.Tt.as<double>() + lf.offT[j], k[j], true);
+          g2.one(Sh + P->shat_far_off[e], k[i], k[i], k[j], k[i], lf.Tt.as<double>() + lf.offT[i],
+                 k[i], false, Tmp[g] + o, k[i], false);
+        }
+    }
+    g1.run(st);
+    g2.run(st);
+    st.sync();
+  } else {
+    std::vector<DBuf> Kc32, T32, Tmp32;
+    GemmBatch<float> g1;
+    GemmBatch<float, double> g2;
+    for (size_t g = 0; g < G.size(); ++g) {
+      Prob* P = G[g];
+      const LevelFactor& lf = P->lf();
+      const std::vector<int>& k = lf.k;
+      const auto& fp = P->fp();
+      const auto& fi = P->fi();
+      double* Sh = P->Shat.as<double>();
+      Kc32.push_back(to_f32(Kc[g], kcoff[g].back(), s));
+      T32.push_back(to_f32(lf.Tt.as<double>(), lf.offT[P->nb], s));
+      Tmp32.emplace_back(std::max<int64_t>(kcoff[g].back(), 1) * sizeof(float));
+      const float* Tf = T32.back().as<float>();
+      const float* Kf = Kc32.back().as<float>();
+      float* Tm = Tmp32.back().as<float>();
+      for (int i = 0; i < P->nb; ++i)
+        for (int64_t e = fp[i]; e < fp[i + 1]; ++e) {
+          int j = fi[e];
+          if (k[i] == 0 || k[j] == 0) continue;
+          const int64_t o = kcoff[g][e];
+          g1.one(Tm + o, k[i], k[i], k[j], k[j], Kf + o, k[i], false, Tf + lf.offT[j], k[j], true);
+          g2.one(Sh + P->shat_far_off[e], k[i], k[i], k[j], k[i], Tf + lf.offT[i], k[i], false,
+                 Tm + o, k[i], false);
+        }
+    }
+    g1.run(st);
+    g2.run(st);
+    st.sync();
+  }
+}
+
+// ---- (e) rotation -------------------------------------------------------------
+void Driver::rotations(Stage& st, const std::vector<Prob*>& G) {
+  std::vector<DBuf> U32(G.size());
+  // off-diagonal near blocks: S_ij = U^S_i^T D_ij U^S_j
+  {
+    GemmBatch<double> g1, g2;
+    GemmBatch<float> h1;
+    GemmBatch<float, double> h2;
+    for (size_t g = 0; g < G.size(); ++g) {
+      Prob* P = G[g];
+      const LevelFactor& lf = P->lf();
+      const std::vector<int>& m = lf.m;
+      const std::vector<int>& k = lf.k;
+      const auto& np = P->np();
+      const auto& ni = P->ni();
+      std::vector<int64_t> toff(P->nnear() + 1, 0);
+      for (int i = 0; i < P->nb; ++i)
+        for (int64_t e = np[i]; e < np[i + 1]; ++e)
+          toff[e + 1] = toff[e] + (int64_t)m[i] * k[ni[e]];
+      for (int i = 0; i < P->nb; ++i)
+        for (int64_t e = np[i]; e < np[i + 1]; ++e) {
+          int j = ni[e];
+          if (j == i || k[i] == 0 || k[j] == 0) continue;
+          P->fl_rotate += 2.0 * m[i] * (double)m[j] * k[j] + 2.0 * k[i] * (double)m[i] * k[j];
+        }
+      double* Sh = P->Shat.as<double>();
+      if (!mixed) {
+        double* Tmp = st.scratch<double>(std::max<int64_t>(toff.back(), 1));
+        const double* U = lf.U.as<double>();
+        const double* Dp = P->D.as<double>();
+        for (int i = 0; i < P->nb; ++i)
+          for (int64_t e = np[i]; e < np[i + 1]; ++e) {
+            int j = ni[e];
+            if (j == i || k[i] == 0 || k[j] == 0) continue;
+            g1.one(Tmp + toff[e], m[i], m[i], k[j], m[j], Dp + P->Doff[e], m[i], false,
+                   U + lf.offU[j], m[j], false);
+            g2.one(Sh + P->shat_near_off[e], k[i], k[i], k[j], m[i], U + lf.offU[i], m[i], true,
+                   Tmp + toff[e], m[i], false);
+          }
+      } else {
+        U32[g] = to_f32(lf.U.as<double>(), lf.offU[P->nb], s);
+        float* Tmp = st.scratch<float>(std::max<int64_t>(toff.back(), 1));
+        const float* U = U32[g].as<float>();
+        const float* D32p = P->D32.as<float>();
+        for (int i = 0; i < P->nb; ++i)
+          for (int64_t e = np[i]; e < np[i + 1]; ++e) {
+            int j = ni[e];
+            if (j == i || k[i] == 0 || k[j] == 0) continue;
+            h1.one(Tmp + toff[e], m[i], m[i], k[j], m[j], D32p + P->Doff[e], m[i], false,
+                   U + lf.offU[j], m[j], false);
+            h2.one(Sh + P->shat_near_off[e], k[i], k[i], k[j], m[i], U + lf.offU[i], m[i], true,
+                   Tmp + toff[e], m[i], false);
+          }
+      }
+    }
+    g1.run(st);
+    g2.run(st);
+    h1.run(st);
+    h2.run(st);
+    st.sync();
+  }
+  // diagonal: S_ii = U_i^T D_ii U_i
+  {
+    std::vector<DBuf> Tmps;
+    GemmBatch<double> g1, g2;
+    GemmBatch<float> h1;
+    GemmBatch<float, double> h2;
+    for (size_t g = 0; g < G.size(); ++g) {
+      Prob* P = G[g];
+      const LevelFactor& lf = P->lf();
+      const std::vector<int>& m = lf.m;
+      const int nb = P->nb;
+      P->S.alloc(std::max<int64_t>(P->offSq[nb], 1) * sizeof(double));
+      double* Sp = P->S.as<double>();
+      for (int i = 0; i < nb; ++i)
+        if (m[i] > 0) P->fl_rotate += 4.0 * std::pow((double)m[i], 3);
+      if (!mixed) {
+        Tmps.emplace_back(std::max<int64_t>(P->offSq[nb], 1) * sizeof(double));
+        double* Tmp = Tmps.back().as<double>();
+        const double* U = lf.U.as<double>();
+        for (int i = 0; i < nb; ++i) {
+          if (m[i] == 0) continue;
+          g1.one(Tmp + P->offSq[i], m[i], m[i], m[i], m[i], P->Dblk(i, i), m[i], false,
+                 U + lf.offU[i], m[i], false);
+          g2.one(Sp + P->offSq[i], m[i], m[i], m[i], m[i], U + lf.offU[i], m[i], true,
+                 Tmp + P->offSq[i], m[i], false);
+        }
+      } else {
+        Tmps.emplace_back(std::max<int64_t>(P->offSq[nb], 1) * sizeof(float));
+        float* Tmp = Tmps.back().as<float>();
+        const float* U = U32[g].as<float>();
+        const float* D32p = P->D32.as<float>();
+        for (int i = 0; i < nb; ++i) {
+          if (m[i] == 0) continue;
+          int64_t e = csr_find(P->np(), P->ni(), i, i);
+          h1.one(Tmp + P->offSq[i], m[i], m[i], m[i], m[i], D32p + P->Doff[e], m[i], false,
+                 U + lf.offU[i], m[i], false);
+          h2.one(Sp + P->offSq[i], m[i], m[i], m[i], m[i], U + lf.offU[i], m[i], true,
+                 Tmp + P->offSq[i], m[i], false);
+        }
+      }
+    }
+    g1.run(st);
+    g2.run(st);
+    h1.run(st);
+    h2.run(st);
+    st.sync();
+  }
+  for (Prob* P : G) {
+    P->D.reset();
+    P->D32.reset();
+  }
+}
+
+// ---- (f) elimination: S^RR inverse, X = S^RR^-1 S^RS, S^SR copy and the Schur
+// update into the new diagonal skeleton block
+void Driver::elimination(Stage& st, const std::vector<Prob*>& G) {
+  std::vector<DBuf> RRw;
+  CopyBatch cb, cs, css;
+  std::vector<SqMat> mats;
+  std::vector<Prob*> owner;
+  for (Prob* P : G) {
+    LevelFactor& lf = P->lf();
+    const int nb = P->nb;
+    const std::vector<int>& m = lf.m;
+    const std::vector<int>& k = lf.k;
+    lf.offR.assign(nb + 1, 0);
+    lf.offX.assign(nb + 1, 0);
+    for (int i = 0; i < nb; ++i) {
+      int r = m[i] - k[i];
+      lf.offR[i + 1] = lf.offR[i] + (int64_t)r * r;
+      lf.offX[i + 1] = lf.offX[i] + (int64_t)r * k[i];
+    }
+    lf.Sinv.alloc(std::max<int64_t>(lf.offR[nb], 1) * sizeof(double));
+    lf.Xs.alloc(std::max<int64_t>(lf.offX[nb], 1) * sizeof(double));
+    lf.SSR.alloc(std::max<int64_t>(lf.offX[nb], 1) * sizeof(double));
+    RRw.emplace_back(std::max<int64_t>(lf.offR[nb], 1) * sizeof(double));
+    double* RR = RRw.back().as<double>();
+    double* Sh = P->Shat.as<double>();
+    for (int i = 0; i < nb; ++i) {
+      int r = m[i] - k[i], ki = k[i];
+      const double* Si = P->S.as<double>() + P->offSq[i];
+      if (r > 0) {
+        cb.add(Si + ki + (int64_t)ki * m[i], m[i], RR + lf.offR[i], r, r, r);
+        mats.push_back(SqMat{RR + lf.offR[i], r, r, lf.Sinv.as<double>() + lf.offR[i], r});
+        owner.push_back(P);
+        if (ki > 0) cs.add(Si + (int64_t)ki * m[i], m[i], lf.SSR.as<double>() + lf.offX[i], ki, ki, r);
+        P->fl_elim += 2.0 / 3.0 * r * (double)r * r + 2.0 * ki * (double)r * r +
+                      2.0 * ki * (double)ki * r;
+      }
+      if (ki > 0) {
+        int64_t e = csr_find(P->np(), P->ni(), i, i);
+        css.add(Si, m[i], Sh + P->shat_near_off[e], ki, ki, ki);
+      }
+    }
+  }
+  cb.run(st);
+  cs.run(st);
+  css.run(st);
+  int32_t* info = nullptr;
+  int32_t* ipiv = nullptr;
+  std::vector<int64_t> ipo;
+  batched_inverse(st, mats, &info, &ipiv, &ipo);
+  // log|det S^RR| from the LU diagonals
+  if (!mats.empty()) {
+    std::vector<MatDesc> ds;
+    for (auto& mt : mats) {
+      MatDesc d{};
+      d.A = mt.A;
+      d.lda = mt.lda;
+      d.m = mt.m;
+      ds.push_back(d);
+    }
+    int nd = (int)ds.size();
+    double* ld = st.scratch<double>(nd);
+    MatDesc* dd = st.up(std::move(ds));
+    launch_logdet(dd, nd, ld, s);
+    std::vector<double> hl(nd);
+    H2ULV_HIP(hipMemcpyAsync(hl.data(), ld, nd * sizeof(double), hipMemcpyDeviceToHost, s));
+    check_info(info, mats.size(), s, "S^RR (elimination step)");
+    for (int q = 0; q < nd; ++q) owner[q]->F->stats.logabsdet += hl[q];
+  }
+  GemmBatch<double> g1, g2;
+  GemmBatch<float, double> g3;
+  std::vector<DBuf> SSR32, X32;
+  for (Prob* P : G) {
+    LevelFactor& lf = P->lf();
+    const std::vector<int>& m = lf.m;
+    const std::vector<int>& k = lf.k;
+    for (int i = 0; i < P->nb; ++i) {
+      int r = m[i] - k[i], ki = k[i];
+      if (r == 0 || ki == 0) continue;
+      const double* Si = P->S.as<double>() + P->offSq[i];
+      g1.one(lf.Xs.as<double>() + lf.offX[i], r, r, ki, r, lf.Sinv.as<double>() + lf.offR[i], r,
+             false, Si + ki, m[i], false);
+    }
+  }
+  g1.run(st);
+  for (Prob* P : G) {
+    LevelFactor& lf = P->lf();
+    const std::vector<int>& m = lf.m;
+    const std::vector<int>& k = lf.k;
+    double* Sh = P->Shat.as<double>();
+    const float* S32 = nullptr;
+    const float* X32p = nullptr;
+    if (mixed) {
+      SSR32.push_back(to_f32(lf.SSR.as<double>(), lf.offX[P->nb], s));
+      X32.push_back(to_f32(lf.Xs.as<double>(), lf.offX[P->nb], s));
+      S32 = SSR32.back().as<float>();
+      X32p = X32.back().as<float>();
+    }
+    for (int i = 0; i < P->nb; ++i) {
+      int r = m[i] - k[i], ki = k[i];
+      if (r == 0 || ki == 0) continue;
+      int64_t e = csr_find(P->np(), P->ni(), i, i);
+      if (!mixed)
+        g2.one(Sh + P->shat_near_off[e], ki, ki, ki, r, lf.SSR.as<double>() + lf.offX[i], ki,
+               false, lf.Xs.as<double>() + lf.offX[i], r, false, -1.0, 1.0);
+      else
+        g3.one(Sh + P->shat_near_off[e], ki, ki, ki, r, S32 + lf.offX[i], ki, false,
+               X32p + lf.offX[i], r, false, -1.0, 1.0);
+    }
+  }
+  g2.run(st);
+  g3.run(st);
+  st.sync();
+}
+
+void Driver::level(const std::vector<Prob*>& G) {
+  Stage st(s);
+  for (Prob* P : G) {
+    LevelFactor& lf = P->lf();
+    const int nb = 1 << P->lev;
+    P->nb = nb;
+    lf.lev = P->lev;
+    lf.nb = nb;
+    lf.m.resize(nb);
+    P->cand_off.assign(nb + 1, 0);
+    for (int i = 0; i < nb; ++i) {
+      lf.m[i] = (int)lf.cand[i].size();
+      P->cand_off[i + 1] = P->cand_off[i] + lf.m[i];
+    }
+    // candidate rows on the device as indices into the shared point buffer;
+    // the host vector stays alive until the level ends
+    P->cand_all.clear();
+    P->cand_all.reserve(P->cand_off[nb]);
+    for (int i = 0; i < nb; ++i)
+      for (int64_t a : lf.cand[i]) P->cand_all.push_back(a + P->poff);
+    P->dcand.alloc(std::max<int64_t>(P->cand_off[nb], 1) * sizeof(int64_t));
+    if (P->cand_off[nb] > 0)
+      H2ULV_HIP(hipMemcpyAsync(P->dcand.p, P->cand_all.data(), P->cand_off[nb] * sizeof(int64_t),
+                               hipMemcpyHostToDevice, s));
+  }
+  tick(nullptr);
+  dense_blocks(st, G);
+  tick("a_dense");
+  fill_products(st, G);
+  tick("b_zprod");
+  basis_triangles(st, G);
+  pivoted_qr(st, G);
+  bases(st, G);
+  tick("c_basis_qr");
+  couplings(st, G);
+  tick("d_couple");
+  rotations(st, G);
+  tick("e_rotate");
+  elimination(st, G);
+  tick("f_elim");
+  st.sync();
+  for (Prob* P : G) {
+    // next level's candidate rows: the children's skeletons
+    if (P->lev > 1) {
+      LevelFactor& lf = P->lf();
+      LevelFactor& pa = P->F->levels[P->lev - 1];
+      pa.cand.assign(P->nb / 2, {});
+      for (int q = 0; q < P->nb / 2; ++q) {
+        pa.cand[q] = lf.sk[2 * q];
+        pa.cand[q].insert(pa.cand[q].end(), lf.sk[2 * q + 1].begin(), lf.sk[2 * q + 1].end());
+      }
+    }
+    P->end_level();
+  }
+}
+
+void Driver::roots(const std::vector<Prob*>& G) {
+  Stage st(s);
+  std::vector<DBuf> D0(G.size());
+  KgenBatch kb;
+  CopyBatch cb;
+  std::vector<int64_t> perms;
+  std::vector<int64_t> permoff(G.size(), 0);
+  for (size_t g = 0; g < G.size(); ++g) {
+    Prob* P = G[g];
+    if (P->L() != 0) continue;
+    permoff[g] = (int64_t)perms.size();
+    for (int64_t a : P->F->tree.perm) perms.push_back(a + P->poff);
+  }
+  const int64_t* dperm = st.up(std::move(perms));
+  for (size_t g = 0; g < G.size(); ++g) {
+    Prob* P = G[g];
+    h2ulv_factor& F = *P->F;
+    int m0;
+    if (P->L() == 0) {
+      m0 = (int)F.n;
+      D0[g].alloc((size_t)m0 * m0 * sizeof(double));
+      kb.add(dperm + permoff[g], m0, dperm + permoff[g], m0, D0[g].as<double>(), m0);
+      P->kevals += (double)m0 * m0;
+    } else {
+      const std::vector<int>& k = F.levels[1].k;
+      m0 = k[0] + k[1];
+      D0[g].alloc(std::max<size_t>((size_t)m0 * m0, 1) * sizeof(double));
+      int ro = 0;
+      for (int a = 0; a < 2; ++a) {
+        int co = 0;
+        for (int b = 0; b < 2; ++b) {
+          int64_t ld;
+          const double* src = P->shat_block(1, a, b, &ld);
+          cb.add(src, std::max<int64_t>(ld, 1), D0[g].as<double>() + ro + (int64_t)co * m0, m0,
+                 k[a], k[b]);
+          co += k[b];
+        }
+        ro += k[a];
+      }
+    }
+    F.m_root = m0;
+    F.root_inv.alloc(std::max<size_t>((size_t)m0 * m0, 1) * sizeof(double));
+  }
+  kb.run(st, pts, kf, dup);
+  cb.run(st);
+  st.sync();
+  check_dup();
+  for (Prob* P : G) P->Shat.reset();
+  std::vector<SqMat> mats;
+  std::vector<Prob*> owner;
+  std::vector<MatDesc> ds;
+  for (size_t g = 0; g < G.size(); ++g) {
+    Prob* P = G[g];
+    const int m0 = P->F->m_root;
+    if (m0 == 0) continue;
+    mats.push_back(SqMat{D0[g].as<double>(), m0, m0, P->F->root_inv.as<double>(), m0});
+    owner.push_back(P);
+    MatDesc d{};
+    d.A = D0[g].as<double>();
+    d.lda = m0;
+    d.m = m0;
+    ds.push_back(d);
+    P->fl_root += 2.0 / 3.0 * std::pow((double)m0, 3);
+  }
+  if (!mats.empty()) {
+    int32_t* info = nullptr;
+    batched_inverse(st, mats, &info, nullptr, nullptr);
+    int nd = (int)ds.size();
+    double* ld = st.scratch<double>(nd);
+    MatDesc* dd = st.up(std::move(ds));
+    launch_logdet(dd, nd, ld, s);
+    std::vector<double> hl(nd);
+    H2ULV_HIP(hipMemcpyAsync(hl.data(), ld, nd * sizeof(double), hipMemcpyDeviceToHost, s));
+    check_info(info, mats.size(), s, "the root block");
+    for (int q = 0; q < nd; ++q) owner[q]->F->stats.logabsdet += hl[q];
+  }
+  st.sync();
+}
+
+}  // namespace
+
+std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
+                                          const std::vector<int64_t>& n,
+                                          const h2ulv_params& params, hipStream_t s) {
+  validate_params(&params);
+  const size_t np = pts.size();
+  double t0 = now_s();
+  std::vector<std::unique_ptr<h2ulv_factor>> F(np);
+  int64_t ntot = 0;
+  for (size_t q = 0; q < np; ++q) {
+    if (!pts[q]) fail(H2ULV_ERR_INVALID_ARG, "pts is NULL");
+    if (n[q] < 1) fail(H2ULV_ERR_INVALID_ARG, "n must be >= 1");
+    if (n[q] > ((int64_t)1 << 31) - 1) fail(H2ULV_ERR_INVALID_ARG, "n too large");
+    ntot += n[q];
+  }
+  for (size_t q = 0; q < np; ++q) {
+    std::vector<double> hp(n[q] * 3);
+    H2ULV_HIP(hipMemcpyAsync(hp.data(), pts[q], n[q] * 3 * sizeof(double), hipMemcpyDeviceToHost,
+                             s));
+    H2ULV_HIP(hipStreamSynchronize(s));
+    for (double v : hp)
+      if (!std::isfinite(v)) fail(H2ULV_ERR_INVALID_ARG, "non-finite point coordinate");
+    F[q] = std::make_unique<h2ulv_factor>();
+    F[q]->p = params;
+    F[q]->n = n[q];
+    F[q]->tree = build_tree(hp.data(), n[q], params.leaf_size);
+    F[q]->lists = build_lists(F[q]->tree, params.eta);
+  }
+  double t1 = now_s();
+  for (size_t q = 0; q < np; ++q) {
+    h2ulv_factor& f = *F[q];
+    f.pts.alloc(f.n * 3 * sizeof(double));
+    H2ULV_HIP(hipMemcpyAsync(f.pts.p, pts[q], f.n * 3 * sizeof(double), hipMemcpyDeviceToDevice,
+                             s));
+    f.perm.alloc(f.n * sizeof(int64_t));
+    H2ULV_HIP(hipMemcpyAsync(f.perm.p, f.tree.perm.data(), f.n * sizeof(int64_t),
+                             hipMemcpyHostToDevice, s));
+    H2ULV_HIP(hipStreamSynchronize(s));
+  }
+  // one point buffer for every kernel evaluation of the batch
+  DBuf shared;
+  std::vector<Prob> probs(np);
+  const double* allpts = F[0]->pts.as<double>();
+  if (np > 1) {
+    shared.alloc(ntot * 3 * sizeof(double));
+    int64_t off = 0;
+    for (size_t q = 0; q < np; ++q) {
+      H2ULV_HIP(hipMemcpyAsync(shared.as<double>() + off * 3, F[q]->pts.p,
+                               F[q]->n * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+      probs[q].poff = off;
+      off += F[q]->n;
+    }
+    allpts = shared.as<double>();
+  }
+  mem_stats().peak = mem_stats().live;
+  Driver drv(s, params);
+  drv.pts = allpts;
+  int H = 0;
+  for (size_t q = 0; q < np; ++q) {
+    Prob& P = probs[q];
+    h2ulv_factor& f = *F[q];
+    P.F = &f;
+    const int L = f.tree.L;
+    H = std::max(H, L);
+    f.levels.resize(L + 1);
+    if (L == 0) continue;
+    LevelFactor& lf = f.levels[L];
+    lf.cand.resize((size_t)1 << L);
+    for (int i = 0; i < (1 << L); ++i)
+      lf.cand[i].assign(f.tree.perm.begin() + f.tree.start[L][i],
+                        f.tree.perm.begin() + f.tree.end[L][i]);
+  }
+  // levels aligned by height above the leaves; the active problems of a height
+  // are split into groups whose level buffers fit the free device memory
+  for (int h = 0; h < H; ++h) {
+    std::vector<Prob*> act;
+    for (Prob& P : probs)
+      if (P.F->tree.L - h >= 1) {
+        P.lev = P.F->tree.L - h;
+        P.nb = 1 << P.lev;
+        act.push_back(&P);
+      }
+    size_t freeb = 0, totb = 0;
+    H2ULV_HIP(hipMemGetInfo(&freeb, &totb));
+    const double cap = 0.45 * (double)freeb;
+    const bool mixed = params.precision == H2ULV_MIXED;
+    size_t a0 = 0;
+    while (a0 < act.size()) {
+      double t_lev = now_s();
+      std::vector<Prob*> grp;
+      double acc = 0;
+      while (a0 < act.size()) {
+        double b = act[a0]->level_bytes(mixed);
+        if (!grp.empty() && acc + b > cap) break;
+        acc += b;
+        grp.push_back(act[a0++]);
+      }
+      drv.level(grp);
+      if (params.verbose) {
+        int mm = 0, mk = 0, nbx = 0;
+        for (Prob* P : grp) {
+          const LevelFactor& lf = P->F->levels[P->lev];
+          nbx += lf.nb;
+          for (int x : lf.m) mm = std::max(mm, x);
+          for (int x : lf.k) mk = std::max(mk, x);
+        }
+        std::fprintf(stderr, "[h2ulv] height %d: %zu problem(s), %d boxes, max m %d, max k %d, "
+                     "%.3f s |", h, grp.size(), nbx, mm, mk, now_s() - t_lev);
+        for (auto& kv : drv.step_time) std::fprintf(stderr, " %s %.3f", kv.first.c_str(), kv.second);
+        std::fprintf(stderr, "\n");
+        drv.step_time.clear();
+      }
+    }
+  }
+  {
+    std::vector<Prob*> all;
+    for (Prob& P : probs) all.push_back(&P);
+    drv.roots(all);
+  }
+  H2ULV_HIP(hipStreamSynchronize(s));
+  double t2 = now_s();
+  std::vector<h2ulv_factor*> out(np);
+  for (size_t q = 0; q < np; ++q) {
+    Prob& P = probs[q];
+    h2ulv_factor& f = *F[q];
+    h2ulv_stats& st = f.stats;
+    st.levels = f.tree.L;
+    st.n = f.n;
+    st.root_size = f.m_root;
+    int mx = 0;
+    for (auto& lf : f.levels)
+      for (int x : lf.k) mx = std::max(mx, x);
+    st.max_rank = mx;
+    st.flops_fill = P.fl_fill;
+    st.flops_basis = P.fl_basis;
+    st.flops_couple = P.fl_couple;
+    st.flops_rotate = P.fl_rotate;
+    st.flops_elim = P.fl_elim;
+    st.flops_root = P.fl_root;
+    st.kernel_evals = P.kevals;
+    st.time_setup_s = t1 - t0;
+    st.time_factor_s = t2 - t0;
+    st.device_bytes = (double)mem_stats().peak;
+  }
+  for (size_t q = 0; q < np; ++q) out[q] = F[q].release();
+  return out;
+}
+
+}  // namespace h2ulv

@@ -1,0 +1,48 @@
+// Factor storage and the batched level driver (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "h2ulv_dense.h"
+
+namespace h2ulv {
+
+struct LevelFactor {
+  int lev = 0;
+  int nb = 0;
+  std::vector<int> m, k;
+  std::vector<std::vector<int64_t>> cand;  // candidate point indices per box
+  std::vector<std::vector<int64_t>> sk;    // skeleton point indices per box
+  // device storage (one arena each): U (m x m), Sinv (r x r), X = Sinv S^RS (r x k),
+  // SSR = S^SR (k x r), T (k x k)
+  DBuf U, Sinv, Xs, SSR, Tt;
+  std::vector<int64_t> offU, offR, offX, offT;
+};
+
+double now_s();
+KernelFn kfn(const h2ulv_params& p);
+
+// Factorize several problems (same parameters) with shared batched launches.
+// pts[p] are device pointers (n[p] x 3 row-major).  On error nothing is returned
+// (the exception carries the status).
+std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
+                                          const std::vector<int64_t>& n,
+                                          const h2ulv_params& params, hipStream_t s);
+
+}  // namespace h2ulv
+
+struct h2ulv_factor {
+  h2ulv_params p{};
+  int64_t n = 0;
+  h2ulv::Tree tree;
+  h2ulv::Lists lists;
+  h2ulv::DBuf pts;   // device copy of the points (n x 3)
+  h2ulv::DBuf perm;  // device tree permutation
+  std::vector<h2ulv::LevelFactor> levels;  // index = level (0 unused)
+  h2ulv::DBuf root_inv;
+  int m_root = 0;
+  h2ulv_stats stats{};
+};
