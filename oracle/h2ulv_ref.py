@@ -48,6 +48,8 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.linalg as sla
 
+from .rank_model import forward as mlp_forward, gaussian_matrix, predicted_rank, sketch_size
+
 # status codes (identical numbering to the C-ABI)
 OK = 0
 ERR_INVALID_ARG = -1
@@ -77,11 +79,14 @@ class Params:
     tol: float = 1e-8
     rank_cap: int = 0          # 0 = no cap
     far_sample: int = 32       # 0 = exact far field, s > 0 = sampled
+    rank_model: object = None  # MLP parameters (float32 array) or None
+    sketch_seed: int = 0       # key of the Gaussian sketches
+    oversample: int = 8        # sketch columns beyond 1.25 x the predicted rank
 
 
-def params_from_problem(prob) -> Params:
+def params_from_problem(prob, **kw) -> Params:
     return Params(prob.kernel, prob.alpha, prob.diag, prob.eta, prob.leaf,
-                  prob.tol, prob.rank_cap, prob.far_sample)
+                  prob.tol, prob.rank_cap, prob.far_sample, **kw)
 
 
 def check_params(X: np.ndarray, p: Params) -> None:
@@ -95,6 +100,8 @@ def check_params(X: np.ndarray, p: Params) -> None:
         raise OracleError(ERR_INVALID_ARG, "tol, rank_cap, far_sample must be >= 0")
     if p.kernel not in (LAPLACE, YUKAWA) or not math.isfinite(p.diag):
         raise OracleError(ERR_INVALID_ARG, "unknown kernel or bad diagonal")
+    if p.oversample < 0:
+        raise OracleError(ERR_INVALID_ARG, "oversample must be >= 0")
 
 
 # ---------------------------------------------------------------------------
@@ -315,6 +322,98 @@ def complement_basis(W: np.ndarray):
 
 
 # ---------------------------------------------------------------------------
+# Learned-rank variant of the basis step: box features, and the row ID taken
+# from a Gaussian sketch of M' sized by the predicted rank, judged by a
+# randomized probe of its error (falls back to the full pivoted QR).
+# ---------------------------------------------------------------------------
+SKETCH_PROBES = 8       # probe columns of the error check
+SKETCH_SLACK = 10.0     # allowed factor over the pivoted-QR error bound
+
+
+def box_features(X, tree: Tree, near, far, lev: int, i: int, m: int, ntargets: int,
+                 ncols: int, p: Params, child_ratio: float) -> np.ndarray:
+    """The 16 rank-model features of box i at level lev (float32):
+      0 log2(1+m)/12          candidate rows
+      1 log2(1+n_pts)/20      points of the box's subtree
+      2 lev / L
+      3 log2(1+|Near|)/6,  4 log2(1+|Far|)/6,  5 log2(1+|fill targets|)/8
+      6 log2(1+ncols)/20      columns of M'
+      7 -log10(tol)/16        (1 for tol = 0)
+      8 alpha r (Yukawa), else 0
+      9-11 sqrt of the covariance eigenvalues of the box's points (descending) / r
+      12 log2(max(r / r_root, 2^-30))/16   (0 when r_root = 0)
+      13 children's compression (k_c1 + k_c2)/(m_c1 + m_c2) above the leaves, 1 at the leaves
+      14 1 at the leaves, else 0
+      15 eta / 2
+    r is the box radius (half the bounding-box diagonal)."""
+    pts = X[box_points(tree, lev, i)]
+    n = pts.shape[0]
+    mu = pts.mean(axis=0)
+    dev = pts - mu
+    C = dev.T @ dev / n
+    lam = np.sort(np.clip(np.linalg.eigvalsh(C), 0.0, None))[::-1]
+    r = float(tree.radius[lev][i])
+    r0 = float(tree.radius[0][0])
+    f = np.zeros(16)
+    f[0] = math.log2(1 + m) / 12
+    f[1] = math.log2(1 + n) / 20
+    f[2] = lev / max(tree.L, 1)
+    f[3] = math.log2(1 + len(near[lev][i])) / 6
+    f[4] = math.log2(1 + len(far[lev][i])) / 6
+    f[5] = math.log2(1 + ntargets) / 8
+    f[6] = math.log2(1 + ncols) / 20
+    f[7] = -math.log10(p.tol) / 16 if p.tol > 0 else 1.0
+    f[8] = p.alpha * r if p.kernel == YUKAWA else 0.0
+    if r > 0:
+        f[9:12] = np.sqrt(lam) / r
+    f[12] = math.log2(max(r / r0, 2.0 ** -30)) / 16 if r0 > 0 else 0.0
+    f[13] = child_ratio
+    f[14] = 1.0 if lev == tree.L else 0.0
+    f[15] = p.eta / 2
+    return f.astype(np.float32)
+
+
+def sketch_row_id(M: np.ndarray, ell: int, tol: float, cap_eff: int, seed: int, lev: int,
+                  box: int):
+    """Row ID of M (m x n) from Y = M Omega, Omega = the box's n x (ell + q)
+    Gaussian matrix: column-pivoted QR of the first ell columns of Y (as rows of
+    Y^T), k = leading pivots with |R_tt| > tol |R_00| (at most cap_eff and ell).
+    The last q columns G of Omega probe the error: with Z = M G,
+      res = Z[piv[k:]] - E^T Z[piv[:k]],  E = R11^-1 R12,
+    and the result is accepted iff k < ell (the sketch was not exhausted) and
+      ||res||_F <= SLACK sqrt(m - k) tol max_j ||Z[j]||,
+    the pivoted-QR bound ||M - W' M[sk]||_F <= sqrt(m - k) tol |R_00| with the
+    row norms of M estimated by those of Z.
+    Returns (accepted, k, piv, Wp, absdiag)."""
+    m, n = M.shape
+    q = SKETCH_PROBES
+    Om = gaussian_matrix(seed, lev, box, n, ell + q)
+    Yt = Om.T @ M.T
+    Ys, Zt = Yt[:ell], Yt[ell:]
+    qr, jpvt, tau, work, info = sla.lapack.dgeqp3(np.asfortranarray(Ys.copy()))
+    piv = np.asarray(jpvt, dtype=np.int64) - 1
+    steps = min(ell, m)
+    R = np.triu(qr[:steps, :])
+    dg = np.abs(np.diag(R))
+    k = 0
+    if steps > 0 and dg[0] > 0:
+        thr = tol * dg[0]
+        while k < steps and dg[k] > thr:
+            k += 1
+    k = min(k, cap_eff, ell)
+    E = sla.solve_triangular(R[:k, :k], R[:k, k:], lower=False) if k else np.zeros((0, m))
+    res = Zt[:, piv[k:]] - Zt[:, piv[:k]] @ E
+    zmax = float(np.max(np.linalg.norm(Zt, axis=0))) if m else 0.0
+    ok = k < ell and float(np.linalg.norm(res)) <= SKETCH_SLACK * math.sqrt(m - k) * tol * zmax
+    Wp = np.zeros((m, k))
+    if k > 0:
+        Wp[piv[:k], np.arange(k)] = 1.0
+        if k < m:
+            Wp[piv[k:], :] = E.T
+    return ok, k, piv, Wp, dg
+
+
+# ---------------------------------------------------------------------------
 # Block LU helpers (Sec. II-B Eq. (lu); partial pivoting, LAPACK dgetrf)
 # ---------------------------------------------------------------------------
 def lu(A: np.ndarray):
@@ -360,6 +459,10 @@ class BoxFactor:
     URS: np.ndarray = None  # L^-1 P^T S^RS   (r x k)
     LSR: np.ndarray = None  # S^SR U^-1       (k x r)
     absdiag: np.ndarray = None
+    feat: np.ndarray = None  # rank-model features (float32, 16)
+    khat: int = -1           # predicted rank (-1: no model)
+    ell: int = 0             # sketch columns (0: full pivoted QR)
+    sketch: int = 0          # 0 not sketched, 1 sketch accepted, 2 fell back
 
 
 @dataclass
@@ -421,6 +524,7 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
 
     # candidate rows and T-hat blocks of the current level
     P = {L: [box_points(tree, L, i) for i in range(1 << L)]}
+    prev_bf = None
     That = None                    # per box: list of triangular blocks (upper levels)
     Sblk = None                    # previous level's S^SS blocks: dict (c, d) -> array
     for lev in range(L, 0, -1):
@@ -466,7 +570,8 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
         for i in todo:
             # F_ij for every reachable j
             Fcols = []
-            for j in fill_targets(near[lev], i):
+            targets = fill_targets(near[lev], i)
+            for j in targets:
                 F = np.zeros((m[i], m[j]))
                 for k in near[lev][i]:
                     if k == i or k == j or j not in near[lev][k]:
@@ -488,10 +593,32 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
             Kf = kernel_block(X, Pl[i], fcols, p)
             kevals += Kf.size
             M = np.concatenate([Kf, Fi], axis=1)
-            # (c) row ID + orthogonal complement
-            k_i, piv, Wp, dg = row_id(M, p.tol, p.rank_cap)
             ncol = M.shape[1]
-            flops["basis"] += 2.0 * ncol * m[i] ** 2 - 2.0 / 3.0 * min(ncol, m[i]) ** 3 if ncol >= m[i] else 2.0 * m[i] * ncol ** 2 - 2.0 / 3.0 * ncol ** 3
+            # (c) row ID + orthogonal complement; with a rank model, the row ID of
+            # a Gaussian sketch sized by the predicted rank when it is accepted
+            if lev == L:
+                ratio = 1.0
+            else:
+                c1, c2 = prev_bf[2 * i], prev_bf[2 * i + 1]
+                ratio = (c1.k + c2.k) / (c1.m + c2.m) if c1.m + c2.m > 0 else 0.0
+            feat = box_features(X, tree, near, far, lev, i, m[i], len(targets), ncol, p, ratio)
+            khat, ell, state = -1, 0, 0
+            if p.rank_model is not None:
+                y = mlp_forward(np.asarray(p.rank_model, dtype=np.float32), feat[None, :],
+                                dtype=np.float32)[0][0]
+                khat = predicted_rank(y)
+                ell = sketch_size(khat, p.oversample)
+                if ell + SKETCH_PROBES <= m[i] and ell < ncol and (p.rank_cap == 0 or ell < p.rank_cap):
+                    cap_eff = min(m[i], ncol) if p.rank_cap <= 0 else min(p.rank_cap, m[i], ncol)
+                    ok, k_i, piv, Wp, dg = sketch_row_id(M, ell, p.tol, cap_eff, p.sketch_seed,
+                                                         lev, i)
+                    state = 1 if ok else 2
+                    flops["basis"] += 2.0 * ncol * m[i] * (ell + SKETCH_PROBES)
+                else:
+                    ell = 0
+            if state != 1:
+                k_i, piv, Wp, dg = row_id(M, p.tol, p.rank_cap)
+                flops["basis"] += 2.0 * ncol * m[i] ** 2 - 2.0 / 3.0 * min(ncol, m[i]) ** 3 if ncol >= m[i] else 2.0 * m[i] * ncol ** 2 - 2.0 / 3.0 * ncol ** 3
             if lev < L and m[i] > 0:
                 W = np.zeros_like(Wp)
                 off = 0
@@ -503,7 +630,8 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                 W = Wp
             U, T = complement_basis(W)
             flops["basis"] += 4.0 * m[i] * k_i * k_i + 4.0 * m[i] ** 2 * k_i
-            bf[i] = BoxFactor(m[i], k_i, U, T, np.asarray(Pl[i])[piv[:k_i]], piv, absdiag=dg)
+            bf[i] = BoxFactor(m[i], k_i, U, T, np.asarray(Pl[i])[piv[:k_i]], piv, absdiag=dg,
+                              feat=feat, khat=khat, ell=ell, sketch=state)
         if level_stop is not None and lev == level_stop:
             fac.levels[lev] = bf
             fac.stats = {"flops": flops, "kevals": kevals}
@@ -543,6 +671,7 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
             else:
                 Snew[i, i] = S[:ki, :ki].copy()
         fac.levels[lev] = bf
+        prev_bf = bf
         # merge: next level's candidate rows and T-hat
         if lev > 1:
             P[lev - 1] = [np.concatenate([bf[2 * q].sk, bf[2 * q + 1].sk]) for q in range(nb // 2)]
