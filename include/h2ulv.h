@@ -71,10 +71,17 @@ typedef struct h2ulv_params {
                           far box (own-level far boxes use all candidate rows) */
   int32_t precision;   /* H2ULV_FP64 or H2ULV_MIXED (fp32 products, fp64 QR/LU) */
   int32_t verbose;     /* 0 = silent; 1 = per-level timing on stderr            */
-  int32_t reserved;
+  int32_t oversample;  /* learned ranks: sketch columns beyond 1.25 k-hat; >= 0 */
+  const struct h2ulv_rankmodel* rank_model; /* NULL: every basis from the full
+                          column-pivoted QR.  Else the model's predicted rank
+                          k-hat of each box sizes a Gaussian sketch of M' whose
+                          row ID replaces the full one when a randomized probe
+                          accepts it (see h2ulv_rankmodel_create)              */
+  uint64_t sketch_seed; /* key of the Gaussian sketch matrices                 */
 } h2ulv_params;
 
 typedef struct h2ulv_factor h2ulv_factor; /* opaque */
+typedef struct h2ulv_rankmodel h2ulv_rankmodel; /* opaque */
 
 /* Per-factor statistics (host).  Flops are the algorithmic count of the
  * paper's steps from the actual ranks (LU 2/3 n^3, GEMM 2mnk, QR 2mn^2-2/3n^3),
@@ -99,7 +106,8 @@ typedef struct h2ulv_stats {
 } h2ulv_stats;
 
 /* Fill *p with the defaults: Laplace, diag 1e3, eta 1, leaf 256, tol 1e-8, no
- * cap, far_sample 32, FP64.  Returns INVALID_ARG if p is NULL. */
+ * cap, far_sample 32, FP64, no rank model (oversample 8, sketch_seed 0).
+ * Returns INVALID_ARG if p is NULL. */
 h2ulv_status h2ulv_params_default(h2ulv_params* p);
 
 /*
@@ -227,6 +235,72 @@ typedef struct h2ulv_kernel_profile {
 } h2ulv_kernel_profile;
 h2ulv_status h2ulv_profile_enable(int32_t on);
 h2ulv_status h2ulv_profile_read(h2ulv_kernel_profile* out, int32_t max, int32_t* count);
+
+/*
+ * Learned rank prediction for the shared-basis step (the row ID of Sec. II-A /
+ * III-C, computed differently; the method is unchanged).
+ *
+ * Features.  Every factorization records 16 features per box and level (float32):
+ *   0 log2(1+m)/12 (candidate rows)        1 log2(1+points of the box)/20
+ *   2 level/L                              3 log2(1+|Near|)/6
+ *   4 log2(1+|Far|)/6                      5 log2(1+|fill targets|)/8
+ *   6 log2(1+columns of M')/20             7 -log10(tol)/16 (1 if tol = 0)
+ *   8 alpha r (Yukawa) else 0              9-11 sqrt(covariance eigenvalues of the
+ *                                               box's points, descending) / r
+ *   12 log2(max(r/r_root, 2^-30))/16       13 (k_c1+k_c2)/(m_c1+m_c2) of the
+ *                                              children (1 at the leaves)
+ *   14 1 at the leaves else 0              15 eta/2
+ * with r the box radius (half its bounding-box diagonal).  The training target
+ * is log2(1 + k).
+ *
+ * Model.  16 -> 64 -> 64 -> 64 (ReLU) -> 1, float32, one flat parameter array
+ * of H2ULV_MLP_NPARAM floats: W1 (64 x 16 row-major), b1, W2 (64 x 64), b2, W3,
+ * b3, w4 (64), b4.  Prediction k-hat = max(0, round(2^y - 1)).
+ *
+ * Use in the factorization (params.rank_model != NULL).  For each box the
+ * sketch size is l = ceil(1.25 k-hat) + oversample.  When l + 8 <= m,
+ * l < columns of M' and (rank_cap == 0 or l < rank_cap), the row ID comes from
+ * the column-pivoted QR of (M' Omega)^T for the box's Gaussian matrix Omega
+ * (columns of M' x l, SplitMix64 + Box-Muller keyed by sketch_seed, level and
+ * box); 8 further Gaussian columns G probe its error, and the sketch is
+ * accepted iff it was not exhausted (k < l) and
+ *   ||Z[piv[k:]] - E^T Z[piv[:k]]||_F <= 10 sqrt(m - k) tol max_j ||Z[j]||,
+ * Z = M' G, E = R11^-1 R12.  Otherwise the box uses the full pivoted QR.
+ */
+#define H2ULV_NFEAT 16
+#define H2ULV_MLP_NPARAM 9473
+
+/* New model with He-normal weights from the Gaussian generator keyed by seed
+ * (biases 0); parameters live on the current device.  Free with
+ * h2ulv_rankmodel_destroy (after every factorization that uses it). */
+h2ulv_status h2ulv_rankmodel_create(uint64_t seed, h2ulv_rankmodel** out);
+void h2ulv_rankmodel_destroy(h2ulv_rankmodel* m);
+/* Copy the H2ULV_MLP_NPARAM parameters from / to host memory (synchronous). */
+h2ulv_status h2ulv_rankmodel_set_params(h2ulv_rankmodel* m, const float* host);
+h2ulv_status h2ulv_rankmodel_get_params(const h2ulv_rankmodel* m, float* host);
+/* y[s] = model(feat[s, :]) for n samples; feat device n x 16 row-major, y device. */
+h2ulv_status h2ulv_rankmodel_forward(const h2ulv_rankmodel* m, const float* feat, int64_t n,
+                                     float* y, void* stream);
+/* grad (device, H2ULV_MLP_NPARAM) = d/dparams of mean_s (y_s - target_s)^2;
+ * *loss (host, may be NULL) = that mean.  Synchronises the stream. */
+h2ulv_status h2ulv_rankmodel_gradient(const h2ulv_rankmodel* m, const float* feat,
+                                      const float* target, int64_t n, float* grad, float* loss,
+                                      void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the given gradient. */
+h2ulv_status h2ulv_rankmodel_adam_step(h2ulv_rankmodel* m, const float* grad, float lr,
+                                       void* stream);
+/* `steps` full-batch Adam steps on (feat, target); *loss (host, may be NULL)
+ * receives the loss before the last step.  Synchronises the stream. */
+h2ulv_status h2ulv_rankmodel_train(h2ulv_rankmodel* m, const float* feat, const float* target,
+                                   int64_t n, int32_t steps, float lr, float* loss, void* stream);
+
+/* Features of level lev (1..L) of a factor: feat host 2^lev x 16 row-major,
+ * target host 2^lev (log2(1 + k)); either may be NULL. */
+h2ulv_status h2ulv_get_features(const h2ulv_factor* f, int32_t lev, float* feat, float* target);
+/* Per box of level lev: predicted rank (-1 without a model), sketch columns
+ * (0: full pivoted QR) and outcome (0 not sketched, 1 accepted, 2 fell back). */
+h2ulv_status h2ulv_get_sketch_info(const h2ulv_factor* f, int32_t lev, int32_t* khat,
+                                   int32_t* ell, int32_t* state);
 
 const char* h2ulv_status_string(h2ulv_status s);
 const char* h2ulv_last_error(void);

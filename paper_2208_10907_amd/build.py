@@ -25,6 +25,8 @@ HIP_FLAGS = ["-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",
              "-Wno-unused-command-line-argument"]
 SOURCES = [
     ("h2ulv_kernels.hip", []),
+    ("h2ulv_learned.hip", []),
+    ("h2ulv_rankmodel.cpp", ["-x", "hip"]),
     ("h2ulv_dense.cpp", ["-x", "hip"]),
     ("h2ulv_factor.cpp", ["-x", "hip"]),
     ("h2ulv_api.cpp", ["-x", "hip"]),

@@ -8,6 +8,7 @@
 #include <map>
 
 #include "h2ulv_factor.h"
+#include "h2ulv_learned.h"
 
 struct h2ulv_structure {
   h2ulv::Tree tree;
@@ -15,6 +16,13 @@ struct h2ulv_structure {
 };
 
 namespace h2ulv {
+
+h2ulv_rankmodel* rankmodel_create(uint64_t seed);
+void rankmodel_gradient(const h2ulv_rankmodel& M, const float* feat, const float* target,
+                        int64_t n, float* grad, float* loss_host, hipStream_t s);
+void rankmodel_adam(h2ulv_rankmodel& M, const float* grad, float lr, hipStream_t s);
+void rankmodel_train(h2ulv_rankmodel& M, const float* feat, const float* target, int64_t n,
+                     int steps, float lr, float* loss_host, hipStream_t s);
 
 static thread_local std::string g_last_error;
 
@@ -252,6 +260,9 @@ h2ulv_status h2ulv_params_default(h2ulv_params* p) {
   p->far_sample = 32;
   p->precision = H2ULV_FP64;
   p->verbose = 0;
+  p->oversample = 8;
+  p->rank_model = nullptr;
+  p->sketch_seed = 0;
   return H2ULV_OK;
 }
 
@@ -430,6 +441,106 @@ h2ulv_status h2ulv_structure_geometry(const h2ulv_structure* s, int32_t lev, dou
 }
 
 void h2ulv_structure_destroy(h2ulv_structure* s) { delete s; }
+
+h2ulv_status h2ulv_rankmodel_create(uint64_t seed, h2ulv_rankmodel** out) {
+  if (!out) {
+    g_last_error = "out is NULL";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  return guarded([&] { *out = rankmodel_create(seed); });
+}
+
+void h2ulv_rankmodel_destroy(h2ulv_rankmodel* m) { delete m; }
+
+h2ulv_status h2ulv_rankmodel_set_params(h2ulv_rankmodel* m, const float* host) {
+  if (!m || !host) {
+    g_last_error = "NULL argument";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  return guarded([&] {
+    H2ULV_HIP(hipMemcpy(m->theta.p, host, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice));
+  });
+}
+
+h2ulv_status h2ulv_rankmodel_get_params(const h2ulv_rankmodel* m, float* host) {
+  if (!m || !host) {
+    g_last_error = "NULL argument";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  return guarded([&] {
+    H2ULV_HIP(hipMemcpy(host, m->theta.p, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+  });
+}
+
+h2ulv_status h2ulv_rankmodel_forward(const h2ulv_rankmodel* m, const float* feat, int64_t n,
+                                     float* y, void* stream) {
+  if (!m || n < 0 || (n > 0 && (!feat || !y))) {
+    g_last_error = "bad forward arguments";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  return guarded([&] {
+    launch_mlp_forward(m->theta.as<float>(), feat, n, y, (hipStream_t)stream);
+    H2ULV_HIP(hipGetLastError());
+  });
+}
+
+h2ulv_status h2ulv_rankmodel_gradient(const h2ulv_rankmodel* m, const float* feat,
+                                      const float* target, int64_t n, float* grad, float* loss,
+                                      void* stream) {
+  if (!m || n < 1 || !feat || !target || !grad) {
+    g_last_error = "bad gradient arguments";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  return guarded(
+      [&] { rankmodel_gradient(*m, feat, target, n, grad, loss, (hipStream_t)stream); });
+}
+
+h2ulv_status h2ulv_rankmodel_adam_step(h2ulv_rankmodel* m, const float* grad, float lr,
+                                       void* stream) {
+  if (!m || !grad || !(lr >= 0.0f)) {
+    g_last_error = "bad Adam arguments";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  return guarded([&] { rankmodel_adam(*m, grad, lr, (hipStream_t)stream); });
+}
+
+h2ulv_status h2ulv_rankmodel_train(h2ulv_rankmodel* m, const float* feat, const float* target,
+                                   int64_t n, int32_t steps, float lr, float* loss, void* stream) {
+  if (!m || n < 1 || !feat || !target || steps < 0 || !(lr >= 0.0f)) {
+    g_last_error = "bad training arguments";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  return guarded(
+      [&] { rankmodel_train(*m, feat, target, n, steps, lr, loss, (hipStream_t)stream); });
+}
+
+h2ulv_status h2ulv_get_features(const h2ulv_factor* f, int32_t lev, float* feat, float* target) {
+  if (!f || lev < 1 || lev > f->tree.L) {
+    g_last_error = "bad level";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  const LevelFactor& lf = f->levels[lev];
+  if (feat) std::copy(lf.feat.begin(), lf.feat.end(), feat);
+  if (target)
+    for (int i = 0; i < lf.nb; ++i) target[i] = (float)std::log2(1.0 + lf.k[i]);
+  return H2ULV_OK;
+}
+
+h2ulv_status h2ulv_get_sketch_info(const h2ulv_factor* f, int32_t lev, int32_t* khat,
+                                   int32_t* ell, int32_t* state) {
+  if (!f || lev < 1 || lev > f->tree.L) {
+    g_last_error = "bad level";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  const LevelFactor& lf = f->levels[lev];
+  for (int i = 0; i < lf.nb; ++i) {
+    if (khat) khat[i] = lf.khat[i];
+    if (ell) ell[i] = lf.ell[i];
+    if (state) state[i] = lf.sk_state[i];
+  }
+  return H2ULV_OK;
+}
 
 const char* h2ulv_status_string(h2ulv_status s) {
   switch (s) {

@@ -18,6 +18,7 @@
 // then the root blocks are inverted (Eq. BLR2final).  Ranks are read back once
 // per level to size the next level.
 #include "h2ulv_factor.h"
+#include "h2ulv_learned.h"
 
 #include <chrono>
 #include <cmath>
@@ -131,11 +132,13 @@ struct Prob {
   int lev = 0, nb = 0;
   std::vector<int64_t> cand_all, cand_off;
   DBuf dcand;
-  std::vector<int64_t> Doff, offSq, offTinv, offE, offW, ncols;
-  DBuf D, Dinv, Tinv, Z, D32, PQ, pivd, kd, Ebuf, S;
+  std::vector<int64_t> Doff, offSq, offTinv, offW, ncols;
+  DBuf D, Dinv, Tinv, Z, D32, PQ, pivd, kd, S;
   std::vector<std::vector<int>> targets;
   std::vector<std::vector<int64_t>> farcols;
-  std::vector<int> capeff;
+  std::vector<const double*> Eptr;  // E = R11^-1 R12 of each box and its leading dimension
+  std::vector<int64_t> ldE;
+  std::vector<DBuf> Ebufs;
 
   int L() const { return F->tree.L; }
   LevelFactor& lf() { return F->levels[lev]; }
@@ -177,14 +180,20 @@ struct Prob {
     Doff.clear();
     offSq.clear();
     offTinv.clear();
-    offE.clear();
     offW.clear();
     ncols.clear();
     targets.clear();
     farcols.clear();
-    capeff.clear();
-    for (DBuf* b : {&dcand, &D, &Dinv, &Tinv, &Z, &D32, &PQ, &pivd, &kd, &Ebuf, &S}) b->reset();
+    Eptr.clear();
+    ldE.clear();
+    Ebufs.clear();
+    for (DBuf* b : {&dcand, &D, &Dinv, &Tinv, &Z, &D32, &PQ, &pivd, &kd, &S}) b->reset();
   }
+};
+
+struct Box {
+  Prob* P;
+  int i;
 };
 
 struct Driver {
@@ -228,8 +237,13 @@ struct Driver {
  private:
   void dense_blocks(Stage& st, const std::vector<Prob*>& G);
   void fill_products(Stage& st, const std::vector<Prob*>& G);
-  void basis_triangles(Stage& st, const std::vector<Prob*>& G);
-  void pivoted_qr(Stage& st, const std::vector<Prob*>& G);
+  void basis_prepare(Stage& st, const std::vector<Prob*>& G);
+  // rebuild: M' of boxes whose sketch was rejected, formed a second time (its
+  // kernel entries and fill-in products are not counted again)
+  void build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebuild = false);
+  void pivot_boxes(Stage& st, const std::vector<Box>& boxes);
+  std::vector<Box> check_sketches(Stage& st, const std::vector<Box>& boxes);
+  void row_ids(Stage& st, const std::vector<Prob*>& G);
   void bases(Stage& st, const std::vector<Prob*>& G);
   void couplings(Stage& st, const std::vector<Prob*>& G);
   void rotations(Stage& st, const std::vector<Prob*>& G);
@@ -393,13 +407,9 @@ void Driver::fill_products(Stage& st, const std::vector<Prob*>& G) {
   }
 }
 
-// ---- (c) M'^T, its tall QR (chunked over boxes by memory) -> m x m triangles
-void Driver::basis_triangles(Stage& st, const std::vector<Prob*>& G) {
-  struct Box {
-    Prob* P;
-    int i;
-  };
-  std::vector<Box> boxes;
+// ---- (c) preparation of the basis step: fill targets, far-field columns,
+// features, and (with a rank model) the predicted ranks and sketch sizes
+void Driver::basis_prepare(Stage& st, const std::vector<Prob*>& G) {
   for (Prob* P : G) {
     LevelFactor& lf = P->lf();
     const int nb = P->nb;
@@ -408,13 +418,28 @@ void Driver::basis_triangles(Stage& st, const std::vector<Prob*>& G) {
     P->targets.assign(nb, {});
     P->farcols.assign(nb, {});
     P->ncols.assign(nb, 0);
+    lf.k.assign(nb, 0);
+    lf.feat.assign((size_t)nb * MLP_NF, 0.0f);
+    lf.khat.assign(nb, -1);
+    lf.ell.assign(nb, 0);
+    lf.sk_state.assign(nb, 0);
+    P->Eptr.assign(nb, nullptr);
+    P->ldE.assign(nb, 1);
+    const bool upper = P->lev < P->L();
     for (int i = 0; i < nb; ++i) {
       P->targets[i] = fill_targets(ls, P->lev, i);
       P->farcols[i] = far_columns(P->F->tree, ls, P->lev, i, lf.cand, p.far_sample);
       int64_t nc = (int64_t)P->farcols[i].size();
       for (int j : P->targets[i]) nc += m[j];
       P->ncols[i] = nc;
-      boxes.push_back(Box{P, i});
+      double ratio = 1.0;
+      if (upper) {
+        const LevelFactor& ch = P->F->levels[P->lev + 1];
+        const int den = ch.m[2 * i] + ch.m[2 * i + 1];
+        ratio = den > 0 ? (double)(ch.k[2 * i] + ch.k[2 * i + 1]) / den : 0.0;
+      }
+      box_features(*P->F, P->lev, i, m[i], (int)P->targets[i].size(), nc, ratio,
+                   lf.feat.data() + (size_t)i * MLP_NF);
     }
     // mixed precision: the rotations, low-rank couplings and Schur updates run on
     // FP32 matrix cores with FP32 accumulation; the fill-in products stay FP64
@@ -428,14 +453,52 @@ void Driver::basis_triangles(Stage& st, const std::vector<Prob*>& G) {
     P->kd.alloc(std::max(nb, 1) * sizeof(int32_t));
     H2ULV_HIP(hipMemsetAsync(P->PQ.p, 0, P->PQ.bytes, s));
   }
+  if (!p.rank_model) return;
+  // predicted ranks: one forward pass over the features of every box
+  std::vector<float> feats;
+  for (Prob* P : G) {
+    const std::vector<float>& f = P->lf().feat;
+    feats.insert(feats.end(), f.begin(), f.end());
+  }
+  const int64_t nf = (int64_t)feats.size() / MLP_NF;
+  if (nf == 0) return;
+  const float* dfeat = st.up(std::move(feats));
+  float* dy = st.scratch<float>(nf);
+  launch_mlp_forward(p.rank_model->theta.as<float>(), dfeat, nf, dy, s);
+  H2ULV_HIP(hipGetLastError());
+  std::vector<float> hy(nf);
+  H2ULV_HIP(hipMemcpyAsync(hy.data(), dy, nf * sizeof(float), hipMemcpyDeviceToHost, s));
+  H2ULV_HIP(hipStreamSynchronize(s));
+  int64_t q = 0;
+  for (Prob* P : G) {
+    LevelFactor& lf = P->lf();
+    for (int i = 0; i < P->nb; ++i, ++q) {
+      double kh = std::floor(std::pow(2.0, (double)hy[q]) - 1.0 + 0.5);
+      if (!(kh < 1e8)) kh = 1e8;  // also catches a non-finite output
+      lf.khat[i] = std::max(0, (int)kh);
+      const int64_t ell = (5 * (int64_t)lf.khat[i] + 3) / 4 + p.oversample;
+      const int mi = lf.m[i];
+      if (ell + SKETCH_PROBES <= mi && ell < P->ncols[i] && (p.rank_cap == 0 || ell < p.rank_cap)) {
+        lf.ell[i] = (int)ell;
+        lf.sk_state[i] = 1;
+      }
+    }
+  }
+}
+
+// ---- (c) M'^T of each box (chunked over boxes by memory), then either its
+// tall QR -> m x m triangle, or (sketched boxes) [Y^T; Z^T] = Omega^T M'^T
+void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebuild) {
   size_t freeb = 0, totb = 0;
   H2ULV_HIP(hipMemGetInfo(&freeb, &totb));
   int64_t budget = (int64_t)(freeb * 0.4) / (int64_t)sizeof(double);
   budget = std::max<int64_t>(budget, 1 << 20);
+  auto sketched = [](const Box& b) { return b.P->lf().sk_state[b.i] == 1; };
   auto box_words = [&](const Box& b) {
+    const int64_t mi = b.P->lf().m[b.i], nc = b.P->ncols[b.i];
+    if (sketched(b)) return mi * nc + nc * (b.P->lf().ell[b.i] + SKETCH_PROBES) + 4096;
     // M'^T plus the QR workspaces of its chunks (reflector panels, T, GEMM scratch)
-    const int64_t mi = b.P->lf().m[b.i];
-    return mi * b.P->ncols[b.i] * 3 / 2 + 8 * mi * mi + 4096;
+    return mi * nc * 3 / 2 + 8 * mi * mi + 4096;
   };
   const size_t nbox = boxes.size();
   size_t b0 = 0;
@@ -447,13 +510,18 @@ void Driver::basis_triangles(Stage& st, const std::vector<Prob*>& G) {
       ++b1;
     }
     const size_t nc = b1 - b0;
-    // M'^T (ncols x m, column-major): far-field rows then fill-in rows
-    std::vector<int64_t> moff(nc + 1, 0);
+    // M'^T (ncols x m, column-major): far-field rows then fill-in rows; then
+    // the Gaussian matrices of the sketched boxes
+    std::vector<int64_t> moff(nc + 1, 0), ooff(nc + 1, 0);
     for (size_t q = 0; q < nc; ++q) {
       const Box& b = boxes[b0 + q];
       moff[q + 1] = moff[q] + (int64_t)b.P->lf().m[b.i] * b.P->ncols[b.i];
+      ooff[q + 1] = ooff[q] + (sketched(b) ? b.P->ncols[b.i] *
+                                                 (int64_t)(b.P->lf().ell[b.i] + SKETCH_PROBES)
+                                           : 0);
     }
     DBuf Mb(std::max<int64_t>(moff.back(), 1) * sizeof(double));
+    DBuf Ob(std::max<int64_t>(ooff.back(), 1) * sizeof(double));
     double* Mp = Mb.as<double>();
     std::vector<int64_t> fc_all, fc_off(nc, 0);
     for (size_t q = 0; q < nc; ++q) {
@@ -475,7 +543,7 @@ void Driver::basis_triangles(Stage& st, const std::vector<Prob*>& G) {
       const int64_t ld = P->ncols[i];
       const int64_t nf = (int64_t)P->farcols[i].size();
       kb.add(dfc + fc_off[q], (int)nf, P->candp(i), m[i], Mi, ld);
-      P->kevals += (double)m[i] * nf;
+      if (!rebuild) P->kevals += (double)m[i] * nf;
       int64_t row = nf;
       for (int j : P->targets[i]) {
         if (m[j] > 0) {
@@ -488,7 +556,7 @@ void Driver::basis_triangles(Stage& st, const std::vector<Prob*>& G) {
             if (ekj < 0) continue;
             g.term(P->D.as<double>() + P->Doff[ekj], m[k], true, P->Z.as<double>() + P->Doff[e],
                    m[i], true, m[k]);
-            P->fl_fill += 2.0 * m[i] * (double)m[k] * m[j];
+            if (!rebuild) P->fl_fill += 2.0 * m[i] * (double)m[k] * m[j];
           }
         }
         row += m[j];
@@ -497,8 +565,40 @@ void Driver::basis_triangles(Stage& st, const std::vector<Prob*>& G) {
     kb.run(st, pts, kf, dup);
     g.run(st);
     tick("c_fill_gemm");
-    // tall QR of every M'^T: a tree of blocked Householder QRs (leaf chunks of
-    // 4m rows factored in place, then stacked triangles merged pairwise)
+    // sketched boxes: Omega (ncols x (l + q)) and [Y^T; Z^T] = Omega^T M'^T into
+    // the box's pivoted-QR matrix ((l + q) x m, leading dimension l + q)
+    {
+      std::vector<GaussItem> gi;
+      std::vector<int64_t> tp(1, 0);
+      GemmBatch<double> gs;
+      for (size_t q = 0; q < nc; ++q) {
+        const Box& b = boxes[b0 + q];
+        if (!sketched(b)) continue;
+        Prob* P = b.P;
+        const int i = b.i, mi = P->lf().m[i];
+        const int cols = P->lf().ell[i] + SKETCH_PROBES;
+        const int64_t nci = P->ncols[i];
+        double* Om = Ob.as<double>() + ooff[q];
+        gi.push_back(GaussItem{Om, nci, (int32_t)nci, cols,
+                               sketch_key(p.sketch_seed, P->lev, i)});
+        tp.push_back(tp.back() + tiles64(nci, cols));
+        gs.one(P->PQ.as<double>() + P->offSq[i], cols, cols, mi, (int)nci, Om, nci, true,
+               Mp + moff[q], nci, false);
+        P->fl_basis += 2.0 * (double)nci * mi * cols;
+      }
+      if (!gi.empty()) {
+        const int ngi = (int)gi.size();
+        const int64_t nt = tp.back();
+        GaussItem* dgi = st.up(std::move(gi));
+        int64_t* dtp = st.up(std::move(tp));
+        ProfScope ps("gauss", 0, 0, s);
+        launch_gauss(dgi, dtp, nt, ngi, s);
+        H2ULV_HIP(hipGetLastError());
+      }
+      gs.run(st);
+    }
+    // tall QR of every other M'^T: a tree of blocked Householder QRs (leaf
+    // chunks of 4m rows factored in place, then stacked triangles merged pairwise)
     struct Rref {
       double* p;
       int64_t ld;
@@ -513,7 +613,7 @@ void Driver::basis_triangles(Stage& st, const std::vector<Prob*>& G) {
       const int mi = P->lf().m[i];
       const int64_t nci = P->ncols[i];
       mq[q] = mi;
-      if (mi == 0 || nci == 0) continue;
+      if (mi == 0 || nci == 0 || sketched(boxes[b0 + q])) continue;
       double* Mi = Mp + moff[q];
       const int64_t h = std::max<int64_t>(4 * (int64_t)mi, 256);
       for (int64_t r0 = 0; r0 < nci; r0 += h) {
@@ -599,142 +699,261 @@ void Driver::basis_triangles(Stage& st, const std::vector<Prob*>& G) {
   }
 }
 
-// ---- (c) column-pivoted QR of each m x m triangle: small boxes one workgroup
-// each, large boxes over many workgroups, one pivot step per pair of launches;
-// then ranks, pivots and skeletons to the host
-void Driver::pivoted_qr(Stage& st, const std::vector<Prob*>& G) {
+// ---- (c) column-pivoted QR of each box's matrix (the m x m triangle, or the
+// l x m sketch of a sketched box): small boxes one workgroup each, large boxes
+// over many workgroups, one pivot step per pair of launches.  Ranks come back
+// to the host; E = R11^-1 R12 is left in place (small) or solved into a
+// buffer (large).
+void Driver::pivot_boxes(Stage& st, const std::vector<Box>& boxes) {
   const int BIG = 512;
-  struct Big {
+  struct Job {
     Prob* P;
     int i;
-    int64_t g;
+    int rows;
+    int64_t lda;
+    int big;  // index into the large-box states, or -1
   };
-  std::vector<Big> bigs;
-  int64_t tot_cand = 0, tot_box = 0;
-  for (Prob* P : G) {
-    tot_cand += P->cand_off[P->nb];
-    tot_box += P->nb;
-  }
+  std::vector<Job> jobs;
+  int64_t tot_cand = 0;
+  for (const Box& b : boxes) tot_cand += b.P->lf().m[b.i];
+  const size_t nbox = boxes.size();
   std::vector<PivQrItem> pq;
   std::vector<PivQrState> big;
   double* nrm = st.scratch<double>(std::max<int64_t>(tot_cand, 1));
   double* dg = st.scratch<double>(std::max<int64_t>(tot_cand, 1));
-  double* scal = st.scratch<double>(2 * (size_t)tot_box + 2);
-  int32_t* flg = st.scratch<int32_t>(2 * (size_t)tot_box + 2);
-  {
-    int64_t co = 0, bo = 0;
-    for (Prob* P : G) {
-      const int nb = P->nb;
-      const std::vector<int>& m = P->lf().m;
-      P->capeff.assign(nb, 0);
-      for (int i = 0; i < nb; ++i) {
-        P->capeff[i] = (int)std::min<int64_t>(m[i], P->ncols[i]);
-        if (p.rank_cap > 0) P->capeff[i] = std::min(P->capeff[i], p.rank_cap);
-      }
-      for (int i = 0; i < nb; ++i) {
-        if (m[i] == 0) continue;
-        double* PQi = P->PQ.as<double>() + P->offSq[i];
-        const int64_t c = co + P->cand_off[i];
-        if (m[i] <= BIG) {
-          PivQrItem it{};
-          it.A = PQi;
-          it.lda = m[i];
-          it.m = m[i];
-          it.n = m[i];
-          it.piv = P->pivd.as<int32_t>() + P->cand_off[i];
-          it.kout = P->kd.as<int32_t>() + i;
-          it.diag = dg + c;
-          it.work = nrm + c;
-          it.tol = p.tol;
-          it.cap = std::max(P->capeff[i], 0);
-          pq.push_back(it);
-        } else {
-          PivQrState ps{};
-          ps.A = PQi;
-          ps.lda = m[i];
-          ps.m = m[i];
-          ps.cap = P->capeff[i];
-          ps.nrm = nrm + c;
-          ps.piv = P->pivd.as<int32_t>() + P->cand_off[i];
-          ps.scal = scal + 2 * (bo + i);
-          ps.flags = flg + 2 * (bo + i);
-          ps.tol = p.tol;
-          big.push_back(ps);
-          bigs.push_back(Big{P, i, bo + i});
-        }
-      }
-      co += P->cand_off[nb];
-      bo += nb;
+  double* scal = st.scratch<double>(2 * nbox + 2);
+  int32_t* flg = st.scratch<int32_t>(2 * nbox + 2);
+  int64_t co = 0;
+  for (size_t q = 0; q < nbox; ++q) {
+    Prob* P = boxes[q].P;
+    const int i = boxes[q].i;
+    const LevelFactor& lf = P->lf();
+    const int mi = lf.m[i];
+    if (mi == 0) continue;
+    int cap = (int)std::min<int64_t>(mi, P->ncols[i]);
+    if (p.rank_cap > 0) cap = std::min(cap, p.rank_cap);
+    int rows = mi;
+    int64_t lda = mi;
+    if (lf.sk_state[i] == 1) {
+      rows = lf.ell[i];
+      lda = lf.ell[i] + SKETCH_PROBES;
+      cap = std::min(cap, rows);
     }
+    double* A = P->PQ.as<double>() + P->offSq[i];
+    Job jb{P, i, rows, lda, -1};
+    if (mi <= BIG) {
+      PivQrItem it{};
+      it.A = A;
+      it.lda = lda;
+      it.m = rows;
+      it.n = mi;
+      it.piv = P->pivd.as<int32_t>() + P->cand_off[i];
+      it.kout = P->kd.as<int32_t>() + i;
+      it.diag = dg + co;
+      it.work = nrm + co;
+      it.tol = p.tol;
+      it.cap = std::max(cap, 0);
+      pq.push_back(it);
+    } else {
+      PivQrState ps{};
+      ps.A = A;
+      ps.lda = lda;
+      ps.m = rows;
+      ps.n = mi;
+      ps.cap = cap;
+      ps.nrm = nrm + co;
+      ps.piv = P->pivd.as<int32_t>() + P->cand_off[i];
+      ps.scal = scal + 2 * q;
+      ps.flags = flg + 2 * q;
+      ps.tol = p.tol;
+      jb.big = (int)big.size();
+      big.push_back(ps);
+    }
+    jobs.push_back(jb);
+    co += mi;
   }
-  int npq = (int)pq.size();
+  const int npq = (int)pq.size();
   PivQrItem* dpq = st.up(std::move(pq));
   {
     ProfScope ps("pivqr_small", 0, 0, s);
     launch_pivqr(dpq, npq, s);
   }
   H2ULV_HIP(hipGetLastError());
-  std::map<std::pair<Prob*, int>, int> bigk;
-  if (!big.empty()) {
-    int nbig = (int)big.size();
+  const int nbig = (int)big.size();
+  if (nbig > 0) {
     int maxcap = 0;
     std::vector<int64_t> sp(1, 0);
     for (auto& b : big) {
-      sp.push_back(sp.back() + (b.m + 3) / 4);
+      sp.push_back(sp.back() + (b.n + 3) / 4);
       maxcap = std::max(maxcap, b.cap);
     }
-    int64_t ns = sp.back();
+    const int64_t ns = sp.back();
     PivQrState* dst_ = st.up(std::move(big));
     int64_t* dsp = st.up(std::move(sp));
-    {
-      ProfScope ps("pivqr_large", 0, 0, s);
-      launch_pivqr_init(dst_, dsp, ns, nbig, s);
-      for (int t = 0; t < maxcap; ++t) {
-        launch_pivqr_pick(dst_, nbig, t, s);
-        launch_pivqr_apply(dst_, dsp, ns, nbig, t, s);
-      }
+    ProfScope ps("pivqr_large", 0, 0, s);
+    launch_pivqr_init(dst_, dsp, ns, nbig, s);
+    for (int t = 0; t < maxcap; ++t) {
+      launch_pivqr_pick(dst_, nbig, t, s);
+      launch_pivqr_apply(dst_, dsp, ns, nbig, t, s);
     }
     H2ULV_HIP(hipGetLastError());
-    std::vector<int32_t> hf(2 * (size_t)tot_box + 2);
-    H2ULV_HIP(hipMemcpyAsync(hf.data(), flg, hf.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
-                             s));
-    H2ULV_HIP(hipStreamSynchronize(s));
-    for (const Big& b : bigs) bigk[{b.P, b.i}] = hf[2 * b.g + 1];
-    // E = R11^-1 R12 by triangular blocks (large boxes; small ones hold E in place)
-    std::vector<TriRhs> sys;
-    for (Prob* P : G) {
-      const int nb = P->nb;
-      const std::vector<int>& m = P->lf().m;
-      P->offE.assign(nb + 1, 0);
-      for (int i = 0; i < nb; ++i) {
-        auto it = bigk.find({P, i});
-        int64_t words = it == bigk.end() ? 0 : (int64_t)it->second * (m[i] - it->second);
-        P->offE[i + 1] = P->offE[i] + words;
-      }
-      if (P->offE[nb] > 0) P->Ebuf.alloc(P->offE[nb] * sizeof(double));
-    }
-    for (const Big& b : bigs) {
-      Prob* P = b.P;
-      const int i = b.i, mi = P->lf().m[i], ki = bigk[{P, i}];
-      if (ki == 0 || ki == mi) continue;
-      double* PQi = P->PQ.as<double>() + P->offSq[i];
-      sys.push_back(TriRhs{PQi, mi, ki, PQi + (int64_t)ki * mi, mi,
-                           P->Ebuf.as<double>() + P->offE[i], ki, mi - ki});
-    }
-    trsm_upper(st, sys);
   }
+  // ranks to the host: small boxes from their rank slot, large from their flags
+  std::vector<int32_t> hf(2 * nbox + 2);
+  std::vector<std::vector<int32_t>> hk;
+  std::vector<Prob*> probs;
+  for (const Job& jb : jobs)
+    if (std::find(probs.begin(), probs.end(), jb.P) == probs.end()) probs.push_back(jb.P);
+  hk.resize(probs.size());
+  for (size_t g = 0; g < probs.size(); ++g) {
+    hk[g].resize(probs[g]->nb);
+    H2ULV_HIP(hipMemcpyAsync(hk[g].data(), probs[g]->kd.p, probs[g]->nb * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
+  }
+  if (nbig > 0)
+    H2ULV_HIP(hipMemcpyAsync(hf.data(), flg, hf.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  H2ULV_HIP(hipStreamSynchronize(s));
+  std::map<Prob*, int64_t> ewords;
+  for (size_t q = 0, j = 0; q < nbox && j < jobs.size(); ++q) {
+    if (boxes[q].P != jobs[j].P || boxes[q].i != jobs[j].i) continue;
+    Job& jb = jobs[j++];
+    LevelFactor& lf = jb.P->lf();
+    const size_t g = std::find(probs.begin(), probs.end(), jb.P) - probs.begin();
+    const int k = jb.big >= 0 ? hf[2 * q + 1] : hk[g][jb.i];
+    lf.k[jb.i] = k;
+    if (jb.big >= 0) {
+      ewords[jb.P] += (int64_t)k * (lf.m[jb.i] - k);
+    } else {
+      jb.P->Eptr[jb.i] = jb.P->PQ.as<double>() + jb.P->offSq[jb.i] + (int64_t)k * jb.lda;
+      jb.P->ldE[jb.i] = jb.lda;
+    }
+  }
+  // E = R11^-1 R12 of the large boxes by triangular blocks
+  std::map<Prob*, double*> ebase;
+  for (auto& kv : ewords) {
+    kv.first->Ebufs.emplace_back(std::max<int64_t>(kv.second, 1) * sizeof(double));
+    ebase[kv.first] = kv.first->Ebufs.back().as<double>();
+  }
+  std::vector<TriRhs> sys;
+  for (const Job& jb : jobs) {
+    if (jb.big < 0) continue;
+    LevelFactor& lf = jb.P->lf();
+    const int k = lf.k[jb.i], mi = lf.m[jb.i];
+    double*& eb = ebase[jb.P];
+    jb.P->Eptr[jb.i] = eb;
+    jb.P->ldE[jb.i] = std::max(k, 1);
+    if (k > 0 && k < mi) {
+      double* A = jb.P->PQ.as<double>() + jb.P->offSq[jb.i];
+      sys.push_back(TriRhs{A, jb.lda, k, A + (int64_t)k * jb.lda, jb.lda, eb, k, mi - k});
+    }
+    eb += (int64_t)k * (mi - k);
+  }
+  trsm_upper(st, sys);
   tick("c_pivqr");
   st.sync();
+}
+
+// ---- (c) randomized check of the sketched row IDs: with Z^T the probe rows
+// below the sketch, res = Z^T[:, piv[k:]] - Z^T[:, piv[:k]] E; accepted iff the
+// sketch was not exhausted and |res|_F <= slack sqrt(m - k) tol max_j |Z^T[:, j]|.
+// Returns the rejected boxes.
+std::vector<Box> Driver::check_sketches(Stage& st, const std::vector<Box>& boxes) {
+  const int q = SKETCH_PROBES;
+  std::vector<Box> fails, probed;
+  std::vector<GatherItem> gi;
+  std::vector<int64_t> tp(1, 0);
+  std::vector<NormItem> ni;
+  GemmBatch<double> g;
+  int64_t zw = 0;
+  for (const Box& b : boxes) {
+    const LevelFactor& lf = b.P->lf();
+    if (lf.k[b.i] >= lf.ell[b.i]) {
+      fails.push_back(b);  // exhausted: the rank may exceed the sketch
+      continue;
+    }
+    probed.push_back(b);
+    zw += (int64_t)q * lf.m[b.i];
+  }
+  if (!probed.empty()) {
+    double* Zp = st.scratch<double>(std::max<int64_t>(zw, 1));
+    double* out = st.scratch<double>(4 * probed.size());
+    int64_t off = 0;
+    for (size_t u = 0; u < probed.size(); ++u) {
+      Prob* P = probed[u].P;
+      const int i = probed[u].i;
+      const LevelFactor& lf = P->lf();
+      const int mi = lf.m[i], k = lf.k[i], ell = lf.ell[i];
+      const int64_t ldy = ell + q;
+      const double* Zt = P->PQ.as<double>() + P->offSq[i] + ell;
+      double* Zi = Zp + off;
+      off += (int64_t)q * mi;
+      gi.push_back(GatherItem{Zt, ldy, Zi, q, P->pivd.as<int32_t>() + P->cand_off[i], q, mi});
+      tp.push_back(tp.back() + tiles64(q, mi));
+      if (k > 0)
+        g.one(Zi + (int64_t)k * q, q, q, mi - k, k, Zi, q, false, P->Eptr[i], P->ldE[i], false,
+              -1.0, 1.0);
+      ni.push_back(NormItem{Zi + (int64_t)k * q, q, out + 4 * u, q, mi - k});
+      ni.push_back(NormItem{Zt, ldy, out + 4 * u + 2, q, mi});
+    }
+    const int ngi = (int)gi.size();
+    const int64_t nt = tp.back();
+    GatherItem* dgi = st.up(std::move(gi));
+    int64_t* dtp = st.up(std::move(tp));
+    launch_gather_cols(dgi, dtp, nt, ngi, s);
+    H2ULV_HIP(hipGetLastError());
+    g.run(st);
+    const int nni = (int)ni.size();
+    NormItem* dni = st.up(std::move(ni));
+    launch_norms(dni, nni, s);
+    H2ULV_HIP(hipGetLastError());
+    std::vector<double> h(4 * probed.size());
+    H2ULV_HIP(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    H2ULV_HIP(hipStreamSynchronize(s));
+    for (size_t u = 0; u < probed.size(); ++u) {
+      const LevelFactor& lf = probed[u].P->lf();
+      const int mi = lf.m[probed[u].i], k = lf.k[probed[u].i];
+      const double res = std::sqrt(h[4 * u]), zmax = std::sqrt(h[4 * u + 3]);
+      if (!(res <= SKETCH_SLACK * std::sqrt((double)(mi - k)) * p.tol * zmax))
+        fails.push_back(probed[u]);
+    }
+  }
+  st.sync();
+  return fails;
+}
+
+// ---- (c) the basis step up to the pivots: sketches and triangles, pivoted QR,
+// checks and fallback; then skeletons on the host
+void Driver::row_ids(Stage& st, const std::vector<Prob*>& G) {
+  basis_prepare(st, G);
+  std::vector<Box> all, sk;
+  for (Prob* P : G)
+    for (int i = 0; i < P->nb; ++i) {
+      all.push_back(Box{P, i});
+      if (P->lf().sk_state[i] == 1) sk.push_back(Box{P, i});
+    }
+  build_triangles(st, all);
+  pivot_boxes(st, all);
+  if (!sk.empty()) {
+    std::vector<Box> fails = check_sketches(st, sk);
+    if (!fails.empty()) {
+      // rejected sketches: the full pivoted QR of their M' (rebuilt)
+      for (const Box& b : fails) {
+        b.P->lf().sk_state[b.i] = 2;
+        const int mi = b.P->lf().m[b.i];
+        H2ULV_HIP(hipMemsetAsync(b.P->PQ.as<double>() + b.P->offSq[b.i], 0,
+                                 (size_t)mi * mi * sizeof(double), s));
+      }
+      build_triangles(st, fails, true);
+      pivot_boxes(st, fails);
+    }
+  }
   for (Prob* P : G) P->Z.reset();
   check_dup();
-  // ranks and pivots to the host
-  std::vector<std::vector<int32_t>> hk(G.size()), hp(G.size());
+  // pivots to the host: skeletons
+  std::vector<std::vector<int32_t>> hp(G.size());
   for (size_t g = 0; g < G.size(); ++g) {
     Prob* P = G[g];
-    hk[g].resize(P->nb);
     hp[g].resize(P->cand_off[P->nb]);
-    H2ULV_HIP(hipMemcpyAsync(hk[g].data(), P->kd.p, P->nb * sizeof(int32_t),
-                             hipMemcpyDeviceToHost, s));
     if (!hp[g].empty())
       H2ULV_HIP(hipMemcpyAsync(hp[g].data(), P->pivd.p, hp[g].size() * sizeof(int32_t),
                                hipMemcpyDeviceToHost, s));
@@ -743,11 +962,9 @@ void Driver::pivoted_qr(Stage& st, const std::vector<Prob*>& G) {
   for (size_t g = 0; g < G.size(); ++g) {
     Prob* P = G[g];
     LevelFactor& lf = P->lf();
-    lf.k.assign(P->nb, 0);
     lf.sk.assign(P->nb, {});
     for (int i = 0; i < P->nb; ++i) {
-      auto it = bigk.find({P, i});
-      lf.k[i] = lf.m[i] == 0 ? 0 : (it != bigk.end() ? it->second : hk[g][i]);
+      if (lf.m[i] == 0) lf.k[i] = 0;
       lf.sk[i].resize(lf.k[i]);
       const int32_t* piv = hp[g].data() + P->cand_off[i];
       for (int t = 0; t < lf.k[i]; ++t) lf.sk[i][t] = lf.cand[i][piv[t]];
@@ -757,7 +974,6 @@ void Driver::pivoted_qr(Stage& st, const std::vector<Prob*>& G) {
 
 // ---- (c) W', W = T-hat W', its QR -> U, T ------------------------------------
 void Driver::bases(Stage& st, const std::vector<Prob*>& G) {
-  const int BIG = 512;
   std::vector<DBuf> Wps, Ws;
   std::vector<WpItem> wi;
   GemmBatch<double> g;
@@ -788,11 +1004,8 @@ void Driver::bases(Stage& st, const std::vector<Prob*>& G) {
     }
     for (int i = 0; i < nb; ++i) {
       if (k[i] == 0) continue;
-      const bool isbig = m[i] > BIG;
-      const double* E = isbig ? P->Ebuf.as<double>() + P->offE[i]
-                              : P->PQ.as<double>() + P->offSq[i] + (int64_t)k[i] * m[i];
-      wi.push_back(WpItem{P->pivd.as<int32_t>() + P->cand_off[i], E, Wp + P->offW[i],
-                          isbig ? std::max(k[i], 1) : m[i], m[i], m[i], k[i]});
+      wi.push_back(WpItem{P->pivd.as<int32_t>() + P->cand_off[i], P->Eptr[i], Wp + P->offW[i],
+                          P->ldE[i], m[i], m[i], k[i]});
     }
     if (upper) {
       const LevelFactor& ch = P->F->levels[P->lev + 1];
@@ -826,7 +1039,7 @@ void Driver::bases(Stage& st, const std::vector<Prob*>& G) {
   for (Prob* P : G) {
     P->PQ.reset();
     P->pivd.reset();
-    P->Ebuf.reset();
+    P->Ebufs.clear();
     P->kd.reset();
   }
 }
@@ -1209,8 +1422,7 @@ void Driver::level(const std::vector<Prob*>& G) {
   tick("a_dense");
   fill_products(st, G);
   tick("b_zprod");
-  basis_triangles(st, G);
-  pivoted_qr(st, G);
+  row_ids(st, G);
   bases(st, G);
   tick("c_basis_qr");
   couplings(st, G);
@@ -1339,9 +1551,11 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
       if (!std::isfinite(v)) fail(H2ULV_ERR_INVALID_ARG, "non-finite point coordinate");
     F[q] = std::make_unique<h2ulv_factor>();
     F[q]->p = params;
+    F[q]->p.rank_model = nullptr;  // the factor does not keep the model
     F[q]->n = n[q];
     F[q]->tree = build_tree(hp.data(), n[q], params.leaf_size);
     F[q]->lists = build_lists(F[q]->tree, params.eta);
+    F[q]->hpts = std::move(hp);
   }
   double t1 = now_s();
   for (size_t q = 0; q < np; ++q) {

@@ -20,10 +20,21 @@ struct LevelFactor {
   // SSR = S^SR (k x r), T (k x k)
   DBuf U, Sinv, Xs, SSR, Tt;
   std::vector<int64_t> offU, offR, offX, offT;
+  // learned ranks: features (nb x 16), predicted rank, sketch columns, outcome
+  std::vector<float> feat;
+  std::vector<int> khat, ell, sk_state;
 };
 
 double now_s();
 KernelFn kfn(const h2ulv_params& p);
+
+// Sketch probes and the acceptance slack of the learned-rank basis step.
+constexpr int SKETCH_PROBES = 8;
+constexpr double SKETCH_SLACK = 10.0;
+
+// The 16 rank-model features of box i at level lev (see h2ulv_get_features).
+void box_features(const h2ulv_factor& F, int lev, int i, int m, int ntargets,
+                  int64_t ncols, double child_ratio, float* out);
 
 // Factorize several problems (same parameters) with shared batched launches.
 // pts[p] are device pointers (n[p] x 3 row-major).  On error nothing is returned
@@ -37,6 +48,7 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
 struct h2ulv_factor {
   h2ulv_params p{};
   int64_t n = 0;
+  std::vector<double> hpts;  // host copy of the points (tree geometry, features)
   h2ulv::Tree tree;
   h2ulv::Lists lists;
   h2ulv::DBuf pts;   // device copy of the points (n x 3)
@@ -45,4 +57,9 @@ struct h2ulv_factor {
   h2ulv::DBuf root_inv;
   int m_root = 0;
   h2ulv_stats stats{};
+};
+
+struct h2ulv_rankmodel {
+  h2ulv::DBuf theta, m, v;  // float parameters and Adam moments (device)
+  int64_t step = 0;         // Adam steps taken
 };

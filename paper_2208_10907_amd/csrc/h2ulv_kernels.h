@@ -83,12 +83,14 @@ struct PivQrItem {
 // Column-pivoted QR of one large matrix spread over many workgroups, one step
 // per pair of launches (pick/reflect, then apply/renormalise).
 struct PivQrState {
-  double* A;       // m x m, in place
+  double* A;       // m x n, in place
   int64_t lda;
-  int32_t m;
-  int32_t cap;     // steps allowed: min(m, ncols, cap)
-  double* nrm;     // m column norms
-  int32_t* piv;    // m pivots
+  int32_t m;       // rows
+  int32_t n;       // columns (the pivoted ones)
+  int32_t cap;     // steps allowed: at most min(m, n)
+  int32_t pad;
+  double* nrm;     // n column norms
+  int32_t* piv;    // n pivots
   double* scal;    // [0] tau of the current step, [1] threshold tol |R_00|
   int32_t* flags;  // [0] stopped, [1] rank k so far
   double tol;

@@ -767,7 +767,7 @@ __global__ __launch_bounds__(256) void pivqr_init_kernel(const PivQrState* __res
     st.scal[0] = 0.0;
     st.scal[1] = 0.0;
   }
-  if (c >= st.m) return;
+  if (c >= st.n) return;
   const double* ac = st.A + (int64_t)c * st.lda;
   double p = 0.0;
   for (int r = lane; r < st.m; r += 64) p += ac[r] * ac[r];
@@ -796,9 +796,10 @@ __global__ __launch_bounds__(256) void pivqr_pick_kernel(const PivQrState* __res
     if (tid == 0) st.flags[0] = 1;
     return;
   }
+  const int ncol = st.n;
   double best = -1.0;
-  int bi = m;
-  for (int c = t + tid; c < m; c += 256) {
+  int bi = ncol;
+  for (int c = t + tid; c < ncol; c += 256) {
     double v = st.nrm[c];
     if (v > best) {
       best = v;
@@ -822,7 +823,7 @@ __global__ __launch_bounds__(256) void pivqr_pick_kernel(const PivQrState* __res
   const double pn = red_v[0];
   const int p = red_i[0];
   const double thr = (t == 0) ? st.tol * pn : st.scal[1];
-  const bool stop = !(pn > thr) || !(pn > 0.0) || p >= m;
+  const bool stop = !(pn > thr) || !(pn > 0.0) || p >= ncol;
   __syncthreads();
   if (stop) {
     if (tid == 0) st.flags[0] = 1;
@@ -887,7 +888,7 @@ __global__ __launch_bounds__(256) void pivqr_apply_kernel(const PivQrState* __re
   if (st.flags[1] != t + 1) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c = t + 1 + (int)(slab - slab_ptr[id]) * 4 + w;
-  if (c >= st.m) return;
+  if (c >= st.n) return;
   const double tau = st.scal[0];
   const int m = st.m;
   const double* v = st.A + (int64_t)t * st.lda;

@@ -157,6 +157,7 @@ void validate_params(const h2ulv_params* p) {
   if (p->far_sample < 0) fail(H2ULV_ERR_INVALID_ARG, "far_sample must be >= 0");
   if (p->precision != H2ULV_FP64 && p->precision != H2ULV_MIXED)
     fail(H2ULV_ERR_INVALID_ARG, "unknown precision");
+  if (p->oversample < 0) fail(H2ULV_ERR_INVALID_ARG, "oversample must be >= 0");
 }
 
 }  // namespace h2ulv

@@ -35,8 +35,14 @@ EXPORTS = [
     "h2ulv_destroy", "h2ulv_structure_create", "h2ulv_structure_levels",
     "h2ulv_structure_perm", "h2ulv_structure_lists", "h2ulv_structure_geometry",
     "h2ulv_structure_destroy", "h2ulv_status_string", "h2ulv_last_error",
-    "h2ulv_profile_enable", "h2ulv_profile_read",
+    "h2ulv_profile_enable", "h2ulv_profile_read", "h2ulv_rankmodel_create",
+    "h2ulv_rankmodel_destroy", "h2ulv_rankmodel_set_params", "h2ulv_rankmodel_get_params",
+    "h2ulv_rankmodel_forward", "h2ulv_rankmodel_gradient", "h2ulv_rankmodel_adam_step",
+    "h2ulv_rankmodel_train", "h2ulv_get_features", "h2ulv_get_sketch_info",
 ]
+
+NFEAT = 16
+MLP_NPARAM = 9473
 
 
 class Params(C.Structure):
@@ -44,7 +50,8 @@ class Params(C.Structure):
         ("struct_size", C.c_int32), ("kernel", C.c_int32), ("alpha", C.c_double),
         ("diag", C.c_double), ("eta", C.c_double), ("leaf_size", C.c_int32),
         ("rank_cap", C.c_int32), ("tol", C.c_double), ("far_sample", C.c_int32),
-        ("precision", C.c_int32), ("verbose", C.c_int32), ("reserved", C.c_int32),
+        ("precision", C.c_int32), ("verbose", C.c_int32), ("oversample", C.c_int32),
+        ("rank_model", C.c_void_p), ("sketch_seed", C.c_uint64),
     ]
 
 
@@ -114,6 +121,16 @@ def lib() -> C.CDLL:
         "h2ulv_last_error": (C.c_char_p, []),
         "h2ulv_profile_enable": (i32, [i32]),
         "h2ulv_profile_read": (i32, [P(KernelProfile), i32, P(i32)]),
+        "h2ulv_rankmodel_create": (i32, [C.c_uint64, P(vp)]),
+        "h2ulv_rankmodel_destroy": (None, [vp]),
+        "h2ulv_rankmodel_set_params": (i32, [vp, vp]),
+        "h2ulv_rankmodel_get_params": (i32, [vp, vp]),
+        "h2ulv_rankmodel_forward": (i32, [vp, vp, i64, vp, vp]),
+        "h2ulv_rankmodel_gradient": (i32, [vp, vp, vp, i64, vp, P(C.c_float), vp]),
+        "h2ulv_rankmodel_adam_step": (i32, [vp, vp, C.c_float, vp]),
+        "h2ulv_rankmodel_train": (i32, [vp, vp, vp, i64, i32, C.c_float, P(C.c_float), vp]),
+        "h2ulv_get_features": (i32, [vp, i32, vp, vp]),
+        "h2ulv_get_sketch_info": (i32, [vp, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -130,18 +147,89 @@ def _check(status: int) -> None:
 
 
 def make_params(kernel=LAPLACE, alpha=0.0, diag=1e3, eta=1.0, leaf=256, tol=1e-8,
-                rank_cap=0, far_sample=32, precision=FP64, verbose=0) -> Params:
+                rank_cap=0, far_sample=32, precision=FP64, verbose=0, rank_model=None,
+                sketch_seed=0, oversample=8) -> Params:
     p = Params()
     _check(lib().h2ulv_params_default(C.byref(p)))
     p.kernel, p.alpha, p.diag, p.eta = int(kernel), float(alpha), float(diag), float(eta)
     p.leaf_size, p.rank_cap, p.tol = int(leaf), int(rank_cap), float(tol)
     p.far_sample, p.precision, p.verbose = int(far_sample), int(precision), int(verbose)
+    p.oversample, p.sketch_seed = int(oversample), int(sketch_seed)
+    p.rank_model = rank_model._h.value if rank_model is not None else None
+    p._model_ref = rank_model  # keeps the model alive as long as the parameters
     return p
 
 
-def params_from_problem(prob, precision=FP64, verbose=0) -> Params:
+def params_from_problem(prob, precision=FP64, verbose=0, **kw) -> Params:
     return make_params(prob.kernel, prob.alpha, prob.diag, prob.eta, prob.leaf, prob.tol,
-                       prob.rank_cap, prob.far_sample, precision, verbose)
+                       prob.rank_cap, prob.far_sample, precision, verbose, **kw)
+
+
+def _f32(x):
+    import torch
+    x = torch.as_tensor(x)
+    return x.to(device="cuda", dtype=torch.float32).contiguous()
+
+
+class RankModel:
+    """The rank MLP (16 features -> 3 x 64 ReLU -> 1) with its parameters on
+    the GPU; forward, gradient, Adam and the training loop run in the library."""
+
+    def __init__(self, seed: int = 0):
+        h = C.c_void_p()
+        _check(lib().h2ulv_rankmodel_create(int(seed), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.h2ulv_rankmodel_destroy(h)
+            self._h = None
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(MLP_NPARAM, dtype=np.float32)
+        _check(lib().h2ulv_rankmodel_get_params(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_params(self, theta) -> None:
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        if th.size != MLP_NPARAM:
+            raise ValueError(f"expected {MLP_NPARAM} parameters")
+        _check(lib().h2ulv_rankmodel_set_params(self._h, th.ctypes.data_as(C.c_void_p)))
+
+    def forward(self, feat, stream=None):
+        import torch
+        f = _f32(feat).reshape(-1, NFEAT)
+        y = torch.empty(f.shape[0], dtype=torch.float32, device="cuda")
+        _check(lib().h2ulv_rankmodel_forward(self._h, C.c_void_p(f.data_ptr()), f.shape[0],
+                                             C.c_void_p(y.data_ptr()), _stream(stream)))
+        return y
+
+    def gradient(self, feat, target, stream=None):
+        import torch
+        f = _f32(feat).reshape(-1, NFEAT)
+        t = _f32(target).reshape(-1)
+        g = torch.empty(MLP_NPARAM, dtype=torch.float32, device="cuda")
+        loss = C.c_float(0.0)
+        _check(lib().h2ulv_rankmodel_gradient(self._h, C.c_void_p(f.data_ptr()),
+                                              C.c_void_p(t.data_ptr()), f.shape[0],
+                                              C.c_void_p(g.data_ptr()), C.byref(loss),
+                                              _stream(stream)))
+        return g, float(loss.value)
+
+    def adam_step(self, grad, lr: float, stream=None) -> None:
+        g = _f32(grad)
+        _check(lib().h2ulv_rankmodel_adam_step(self._h, C.c_void_p(g.data_ptr()), float(lr),
+                                               _stream(stream)))
+
+    def train(self, feat, target, steps: int, lr: float = 3e-3, stream=None) -> float:
+        f = _f32(feat).reshape(-1, NFEAT)
+        t = _f32(target).reshape(-1)
+        loss = C.c_float(0.0)
+        _check(lib().h2ulv_rankmodel_train(self._h, C.c_void_p(f.data_ptr()),
+                                           C.c_void_p(t.data_ptr()), f.shape[0], int(steps),
+                                           float(lr), C.byref(loss), _stream(stream)))
+        return float(loss.value)
 
 
 def _stream(stream):
@@ -249,6 +337,24 @@ class Factor:
         out = np.empty(max(int(k[box]), 1), dtype=np.int64)
         _check(lib().h2ulv_get_skeleton(self._h, lev, box, out.ctypes.data_as(C.c_void_p)))
         return out[: int(k[box])]
+
+    def features(self, lev: int):
+        """(features (2^lev x 16, float32), targets log2(1 + k)) of a level."""
+        nb = 1 << lev
+        F = np.empty((nb, NFEAT), dtype=np.float32)
+        T = np.empty(nb, dtype=np.float32)
+        _check(lib().h2ulv_get_features(self._h, lev, F.ctypes.data_as(C.c_void_p),
+                                        T.ctypes.data_as(C.c_void_p)))
+        return F, T
+
+    def sketch_info(self, lev: int):
+        """(predicted rank, sketch columns, outcome) per box of a level."""
+        nb = 1 << lev
+        a, b, c = (np.empty(nb, dtype=np.int32) for _ in range(3))
+        _check(lib().h2ulv_get_sketch_info(self._h, lev, a.ctypes.data_as(C.c_void_p),
+                                           b.ctypes.data_as(C.c_void_p),
+                                           c.ctypes.data_as(C.c_void_p)))
+        return a, b, c
 
     def basis(self, lev: int, box: int) -> np.ndarray:
         m, _ = self.ranks(lev)

@@ -1,0 +1,243 @@
+"""GPU parity of the learned-rank pieces against the CPU oracle: the MLP's
+initialisation, forward pass, gradient and Adam update (FP32 kernels against the
+FP64 oracle, within 1e-4 relative), the box features, and factorizations whose
+bases come from sketches sized by predicted ranks (same predicted ranks, sketch
+sizes and outcomes as the oracle, then the usual structure / solution parity).
+Model weights used in the factorization tests are trained by the oracle."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import h2ulv_ref as O
+from oracle import rank_model as R
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+H = pytest.importorskip("paper_2208_10907_amd.h2ulv")
+
+MLP_TOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    H.lib()
+
+
+def _inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(0.0, 1.0, (n, R.NFEAT)).astype(np.float32)
+    t = rng.uniform(0.0, 8.0, n).astype(np.float32)
+    return X, t
+
+
+def _theta(seed):
+    th = R.init_weights(seed)
+    th = th + 0.05 * np.random.default_rng(seed).standard_normal(th.size)  # nonzero biases
+    return th.astype(np.float32)
+
+
+def test_init_matches_oracle_generator():
+    gm = H.RankModel(seed=3)
+    ref = R.init_weights(3).astype(np.float32)
+    got = gm.get_params()
+    assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n", [1, 32, 777])
+def test_forward_matches_oracle(n):
+    X, _ = _inputs(n, 10 + n)
+    th = _theta(4)
+    gm = H.RankModel()
+    gm.set_params(th)
+    y = gm.forward(torch.tensor(X, device="cuda")).cpu().numpy()
+    yo, _ = R.forward(th.astype(np.float64), X.astype(np.float64))
+    assert np.abs(y - yo).max() <= MLP_TOL * max(1.0, np.abs(yo).max())
+
+
+@pytest.mark.parametrize("n", [1, 32, 777])
+def test_gradient_matches_oracle(n):
+    X, t = _inputs(n, 20 + n)
+    th = _theta(5)
+    gm = H.RankModel()
+    gm.set_params(th)
+    g, loss = gm.gradient(torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda"))
+    g = g.cpu().numpy()
+    lo, go = R.loss_and_grad(th.astype(np.float64), X.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - lo) <= MLP_TOL * lo
+    assert np.linalg.norm(g - go) <= MLP_TOL * np.linalg.norm(go)
+    if n >= 32:  # with a tile of samples most units are active somewhere
+        assert np.count_nonzero(g) > 0.5 * R.NPARAM
+
+
+def test_adam_steps_match_oracle():
+    X, t = _inputs(300, 31)
+    th = _theta(6)
+    gm = H.RankModel()
+    gm.set_params(th)
+    tho = th.astype(np.float64)
+    m = np.zeros_like(tho)
+    v = np.zeros_like(tho)
+    for step in (1, 2, 3):
+        g, _ = gm.gradient(torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda"))
+        gm.adam_step(g, 1e-3)
+        tho, m, v = R.adam_step(tho, m, v, g.cpu().numpy().astype(np.float64), step, 1e-3)
+        got = gm.get_params()
+        assert np.abs(got - tho).max() <= 1e-6 * max(1.0, np.abs(tho).max()), step
+
+
+def test_training_follows_oracle_and_fits():
+    X, _ = _inputs(500, 41)
+    t = (X @ np.linspace(-1, 1, R.NFEAT) + 3.0).astype(np.float32)
+    th0 = R.init_weights(8).astype(np.float32)
+    gm = H.RankModel()
+    gm.set_params(th0)
+    loss = gm.train(torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda"), 40, 3e-3)
+    tho, hist = R.train(th0.astype(np.float64), X.astype(np.float64), t.astype(np.float64), 40,
+                        3e-3)
+    assert abs(loss - hist[-1]) <= 1e-3 * hist[-1]
+    # Adam normalises every step, so gradient components near zero (whose FP32
+    # and FP64 values may differ in sign) move a few parameters by up to about
+    # lr per step apart; the parameters as a whole follow the FP64 trajectory
+    d = np.abs(gm.get_params() - tho)
+    assert d.mean() <= 1e-4 * np.abs(tho).mean() * 10 and d.max() <= 4 * 3e-3
+    loss2 = gm.train(torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda"), 800, 3e-3)
+    assert loss2 < 1e-2 * hist[0]
+
+
+def _gpu_params(op: O.Params, model=None):
+    return H.make_params(kernel=op.kernel, alpha=op.alpha, diag=op.diag, eta=op.eta,
+                         leaf=op.leaf, tol=op.tol, rank_cap=op.rank_cap,
+                         far_sample=op.far_sample, rank_model=model,
+                         sketch_seed=op.sketch_seed, oversample=op.oversample)
+
+
+def test_features_match_oracle():
+    X = W.ellipsoid_points(3000, 12)
+    op = O.Params(leaf=64, tol=1e-6)
+    fo = O.factorize(X, op)
+    fg = H.factorize(X, _gpu_params(op))
+    for lev in range(fo.tree.L, 0, -1):
+        F, T = fg.features(lev)
+        Fo = np.array([b.feat for b in fo.levels[lev]])
+        assert np.abs(F - Fo).max() <= 1e-6, lev
+        assert np.allclose(T, [math.log2(1 + b.k) for b in fo.levels[lev]], rtol=0, atol=1e-6)
+
+
+def _oracle_model(train_points, op, steps=600):
+    f0 = O.factorize(train_points, op)
+    F = np.concatenate([[b.feat for b in f0.levels[l]] for l in f0.levels])
+    T = np.concatenate([[math.log2(1 + b.k) for b in f0.levels[l]] for l in f0.levels])
+    th, hist = R.train(R.init_weights(1), F, T, steps, 3e-3)
+    return th.astype(np.float32)
+
+
+def _constant_model(k):
+    parts = {name: np.zeros(s) for name, s in R.SHAPES}
+    parts["b4"][0] = math.log2(1 + k)
+    return R.pack(parts).astype(np.float32)
+
+
+@pytest.mark.parametrize("n,leaf,tol,oversample,model", [
+    (4096, 128, 1e-6, 8, "trained"),   # sketched leaves (m = 128) and upper levels
+    (4096, 128, 1e-8, 8, "trained"),   # sketched boxes with m > 512 (multi-workgroup QR)
+    (3000, 64, 1e-6, 0, "constant"),   # k-hat = 10, no oversampling: every sketch is
+                                       # exhausted and falls back to the full QR
+])
+def test_predicted_mode_parity(n, leaf, tol, oversample, model):
+    base = O.Params(leaf=leaf, tol=tol)
+    if model == "trained":
+        th = _oracle_model(W.cube_points(n, 900 + n), base)
+    else:
+        th = _constant_model(10)
+    op = O.Params(leaf=leaf, tol=tol, rank_model=th, sketch_seed=77, oversample=oversample)
+    X = W.cube_points(n, 901 + n)
+    fo = O.factorize(X, op)
+    gm = H.RankModel()
+    gm.set_params(th)
+    fg = H.factorize(X, _gpu_params(op, gm))
+    states = []
+    for lev in range(fo.tree.L, 0, -1):
+        kh, ell, stt = fg.sketch_info(lev)
+        assert np.array_equal(kh, [b.khat for b in fo.levels[lev]]), lev
+        assert np.array_equal(ell, [b.ell for b in fo.levels[lev]]), lev
+        assert np.array_equal(stt, [b.sketch for b in fo.levels[lev]]), lev
+        states += stt.tolist()
+    if model == "trained":
+        assert states.count(1) >= 2
+    else:
+        assert states.count(2) == len(states)
+    m_all = [b.m for l in fo.levels for b in fo.levels[l] if b.sketch == 1]
+    for lev in range(fo.tree.L, 0, -1):
+        m, k = fg.ranks(lev)
+        assert np.array_equal(k, [b.k for b in fo.levels[lev]]), lev
+        for i in range(1 << lev):
+            bo = fo.levels[lev][i]
+            sk = fg.skeleton(lev, i)
+            nz = bo.k
+            if bo.absdiag is not None and len(bo.absdiag) and bo.absdiag[0] > 0:
+                nz = min(bo.k, int(np.sum(bo.absdiag[:bo.k] > 1e-10 * bo.absdiag[0])))
+            assert np.array_equal(sk[:nz], bo.sk[:nz]), (lev, i)
+    b = W.gaussian_rhs(n, 2, 3)
+    xo = O.solve(fo, b)
+    xg = fg.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < 1e-10
+    st = fg.stats()
+    assert abs(st["flops"] - O.total_flops(fo)) <= 1e-9 * O.total_flops(fo)
+    if tol == 1e-8:
+        assert max(m_all) > 512
+
+
+def test_trained_model_gain():
+    """Train the rank model on the GPU from the ranks of two factorizations of
+    other point sets, then factorize a new one with predicted ranks: the basis
+    step needs far fewer flops, most sketches are accepted, and refinement
+    reaches the same 1e-10 residual."""
+    mk = lambda seed: W.ellipsoid_points(32768, seed)
+    base = H.make_params(leaf=256, tol=1e-6)
+    F, T = [], []
+    for seed in (501, 502):
+        f = H.factorize(mk(seed), base)
+        for lev in range(1, f.levels() + 1):
+            a, b = f.features(lev)
+            F.append(a)
+            T.append(b)
+        del f
+    F = np.concatenate(F)
+    T = np.concatenate(T)
+    gm = H.RankModel(seed=1)
+    loss = gm.train(torch.tensor(F, device="cuda"), torch.tensor(T, device="cuda"), 2000, 3e-3)
+    assert loss < 0.05
+    X = mk(503)
+    b = torch.tensor(W.gaussian_rhs(X.shape[0], 1, 9), device="cuda")
+    out = {}
+    for name, prm in (("plain", base),
+                      ("predicted", H.make_params(leaf=256, tol=1e-6, rank_model=gm,
+                                                  sketch_seed=5))):
+        f = H.factorize(X, prm)  # warm
+        del f
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = H.factorize(X, prm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        x, it, rel = f.refine(b, rtol=1e-10, max_iter=40)
+        st = f.stats()
+        acc = rej = 0
+        for lev in range(1, f.levels() + 1):
+            s = f.sketch_info(lev)[2]
+            acc += int((s == 1).sum())
+            rej += int((s == 2).sum())
+        out[name] = dict(time=dt, basis=st["flops_basis"], iters=it, rel=rel, acc=acc, rej=rej)
+        del f
+    print("rank model gain:", out)
+    p, q = out["plain"], out["predicted"]
+    assert q["rel"] <= 1e-10 and p["rel"] <= 1e-10
+    assert q["acc"] > 4 * max(q["rej"], 1)
+    assert q["basis"] < 0.8 * p["basis"]
+    assert q["iters"] <= p["iters"] + 3
