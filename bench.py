@@ -1,17 +1,26 @@
 """Benchmark of the H^2-ULV factorization (+ refined solve) on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--precision fp64|mixed] [--no-cpu-baseline]
+                    [--form fp64|mixed|predicted|mixed+predicted]
+                    [--no-reference] [--no-cpu-baseline]
 
 One step = factorize the workload's kernel matrix, then solve its right-hand
 sides with iterative refinement (exact float64 matvec) down to a relative
-residual of 1e-10.  Inputs (points, right-hand sides) are resident on the GPU
-before the timed region.  Prints one JSON line.
+residual of 1e-10.  Points and right-hand sides are resident on the GPU before
+the timed region.  Prints one JSON line.
 
-value = algorithmic factorization flops (counted from the actual ranks, the
-paper's step costs) / wall time of the whole step, in GFLOP/s.
-roofline = the dominant kernel (by time) measured with HIP events on its
-launch stream over the timed steps: summed algorithmic flops / summed duration.
+Forms: fp64 (the plain method), mixed (FP32 products where the method allows),
+predicted (bases from sketches sized by the learned rank model), and both
+combined.  A rank model is trained first (outside the timed steps) on the
+ranks of factorizations of two other point sets of the same family.
+
+value = algorithmic flops of the plain FP64 factorization of the workload (the
+paper's step costs from its actual ranks) / wall time of one step of the timed
+form: an effective rate, so that forms that skip work are compared at equal
+delivered accuracy.  The plain FP64 form is also timed (the reference) unless
+--no-reference; without it the form's own flop count is used.
+roofline = the dominant kernel (by time) of the timed steps measured with HIP
+events on its launch stream: summed algorithmic flops / summed duration.
 cpu_baseline = the CPU oracle timed on a bounded sample of leaf boxes of the
 same workload (GFLOP/s of the oracle's own flop count).
 """
@@ -28,7 +37,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "H² ULV factorize time + GFLOP/s, N=1M Laplace, mixed vs FP64 at 1e-10 resid"
 PEAK_TFLOPS = {"gemm_f64": 78.6, "gemm_f32": 157.3}
-HBM_GBS = 8000.0
 
 
 def workloads():
@@ -39,6 +47,18 @@ def workloads():
         "ellipsoids262144": lambda: W.ellipsoids(),
         "cube1048576": lambda: W.cube1m(),
     }
+
+
+def training_sets(name):
+    """Point sets the rank model learns from: the same family, other seeds."""
+    import workloads as W
+    if name.startswith("ellipsoids"):
+        return [(f"ellipsoids65536 seed {s}", lambda s=s: W.ellipsoid_points(65536, s))
+                for s in (501, 502)]
+    if name.startswith("sphere"):
+        return [(f"sphere16384 seed {s}", lambda s=s: W.sphere_points(16384, s))
+                for s in (501, 502)]
+    return [(f"cube32768 seed {s}", lambda s=s: W.cube_points(32768, s)) for s in (501, 502)]
 
 
 def describe(prob):
@@ -80,14 +100,49 @@ def cpu_baseline(prob, budget_s=20.0):
                        f"depends on; {total_t:.1f} s of CPU time; oracle flop count")}
 
 
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def train_model(H, torch, prob, name):
+    """Factorize the training point sets (plain FP64), collect the per-box
+    features and ranks, train the rank MLP on the GPU."""
+    import numpy as np
+    t0 = time.perf_counter()
+    base = H.params_from_problem(prob)
+    F, T, names = [], [], []
+    for label, mk in training_sets(name):
+        f = H.factorize(mk(), base)
+        for lev in range(1, f.levels() + 1):
+            a, b = f.features(lev)
+            F.append(a)
+            T.append(b)
+        names.append(label)
+        del f
+        log(f"training factorization {label} done")
+    F = np.concatenate(F)
+    T = np.concatenate(T)
+    model = H.RankModel(seed=1)
+    t1 = time.perf_counter()
+    loss = model.train(torch.tensor(F, device="cuda"), torch.tensor(T, device="cuda"), 3000, 3e-3)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log(f"rank model trained: {F.shape[0]} boxes, loss {loss:.4f}")
+    return model, {"train_sets": names, "samples": int(F.shape[0]),
+                   "factorize_s": round(t1 - t0, 3), "train_s": round(t2 - t1, 3),
+                   "steps": 3000, "final_loss": round(loss, 5)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ellipsoids262144", choices=sorted(workloads()))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--form", default="mixed+predicted",
+                    choices=["fp64", "mixed", "predicted", "mixed+predicted"])
     ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -99,46 +154,68 @@ def main() -> int:
     from paper_2208_10907_amd import h2ulv as H
 
     prob = workloads()[args.workload]()
-    prec = H.FP64 if args.precision == "fp64" else H.MIXED
-    params = H.params_from_problem(prob, precision=prec)
     pts = torch.tensor(prob.points, device="cuda")
     b = torch.tensor(prob.rhs(), device="cuda")
     torch.cuda.synchronize()
 
-    def step():
+    model, model_info = None, None
+    if "predicted" in args.form:
+        model, model_info = train_model(H, torch, prob, args.workload)
+
+    def params_of(form):
+        prec = H.MIXED if "mixed" in form else H.FP64
+        return H.params_from_problem(prob, precision=prec,
+                                     rank_model=model if "predicted" in form else None,
+                                     sketch_seed=5)
+
+    def step(params):
         t0 = time.perf_counter()
         f = H.factorize(pts, params)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        x, iters, rel = f.refine(b, rtol=args.rtol, max_iter=50)
+        x, iters, rel = f.refine(b, rtol=args.rtol, max_iter=60)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         st = f.stats()
+        sk = [0, 0]
+        for lev in range(1, f.levels() + 1):
+            s = f.sketch_info(lev)[2]
+            sk[0] += int((s == 1).sum())
+            sk[1] += int((s == 2).sum())
         del f
-        return t1 - t0, t2 - t1, iters, rel, st
+        return {"factor_s": t1 - t0, "refine_s": t2 - t1, "iters": iters, "rel": rel, "st": st,
+                "sketch_accepted": sk[0], "sketch_rejected": sk[1]}
 
+    form_params = params_of(args.form)
     for w in range(args.warmup):
-        r = step()
-        print(f"bench: warmup step {w + 1}/{args.warmup} done ({r[0]:.2f} s factorize, "
-              f"{r[1]:.2f} s refine)", file=sys.stderr, flush=True)
+        r = step(form_params)
+        log(f"warmup step {w + 1}/{args.warmup} done ({r['factor_s']:.2f} s factorize, "
+            f"{r['refine_s']:.2f} s refine)")
     torch.cuda.synchronize()
     H.profile_enable(True)
     t_start = time.perf_counter()
     res = []
     for i in range(args.steps):
-        res.append(step())
-        print(f"bench: timed step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+        res.append(step(form_params))
+        log(f"timed step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     prof = H.profile_read()
     H.profile_enable(False)
-
     ms = 1e3 * t_total / args.steps
-    st = res[-1][4]
-    flops = st["flops"]
-    tf = sum(r[0] for r in res) / len(res)
-    tr = sum(r[1] for r in res) / len(res)
-    value = flops / (ms / 1e3) / 1e9
+    last = res[-1]
+    st = last["st"]
+
+    ref = None
+    if not args.no_reference and args.form != "fp64":
+        r = step(params_of("fp64"))
+        log(f"reference fp64 step done ({r['factor_s']:.2f} s factorize)")
+        ref = {"form": "fp64", "step_s": round(r["factor_s"] + r["refine_s"], 4),
+               "factor_s": round(r["factor_s"], 4), "refine_s": round(r["refine_s"], 4),
+               "refine_iters": r["iters"], "relres": r["rel"], "flops": r["st"]["flops"],
+               "max_rank": r["st"]["max_rank"], "device_gb": round(r["st"]["device_bytes"] / 1e9, 2)}
+    work = ref["flops"] if ref else st["flops"]
+    value = work / (ms / 1e3) / 1e9
 
     gemms = {k: v for k, v in prof.items() if k in PEAK_TFLOPS}
     dom = max(gemms, key=lambda k: gemms[k]["time_ms"]) if gemms else None
@@ -164,19 +241,22 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == H.FP64 else "f32+f64",
+        "dtype": "f32+f64" if "mixed" in args.form else "f64",
         "data": "synthetic",
-        "config": {"workload": describe(prob), "precision": args.precision,
-                   "refine_rtol": args.rtol},
-        "factor_s": round(tf, 4),
-        "refine_s": round(tr, 4),
-        "factor_gflops": round(flops / tf / 1e9, 3),
-        "flops": flops,
-        "refine_iters": res[-1][2],
-        "relres": res[-1][3],
+        "config": {"workload": describe(prob), "form": args.form, "refine_rtol": args.rtol,
+                   "value_flops": "plain FP64 method" if ref else "this form"},
+        "factor_s": round(last["factor_s"], 4),
+        "refine_s": round(last["refine_s"], 4),
+        "refine_iters": last["iters"],
+        "relres": last["rel"],
+        "flops": st["flops"],
         "max_rank": st["max_rank"],
         "root_size": st["root_size"],
         "device_gb": round(st["device_bytes"] / 1e9, 2),
+        "sketches": {"accepted": last["sketch_accepted"], "rejected": last["sketch_rejected"]},
+        "reference": ref,
+        "speedup_vs_fp64": round(ref["step_s"] / (ms / 1e3), 3) if ref else None,
+        "rank_model": model_info,
         "kernels": {k: {"launches": v["launches"], "ms": round(v["time_ms"], 2),
                         "tflops": round(v["flops"] / max(v["time_ms"], 1e-9) / 1e9, 3)}
                     for k, v in prof.items()},

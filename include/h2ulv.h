@@ -258,8 +258,8 @@ h2ulv_status h2ulv_profile_read(h2ulv_kernel_profile* out, int32_t max, int32_t*
  * b3, w4 (64), b4.  Prediction k-hat = max(0, round(2^y - 1)).
  *
  * Use in the factorization (params.rank_model != NULL).  For each box the
- * sketch size is l = ceil(1.25 k-hat) + oversample.  When l + 8 <= m,
- * l < columns of M' and (rank_cap == 0 or l < rank_cap), the row ID comes from
+ * sketch size is l = min(ceil(1.25 k-hat) + oversample, m - 8).  When
+ * k-hat < l < columns of M' and (rank_cap == 0 or l < rank_cap), the row ID comes from
  * the column-pivoted QR of (M' Omega)^T for the box's Gaussian matrix Omega
  * (columns of M' x l, SplitMix64 + Box-Muller keyed by sketch_seed, level and
  * box); 8 further Gaussian columns G probe its error, and the sketch is

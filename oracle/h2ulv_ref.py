@@ -607,8 +607,10 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                 y = mlp_forward(np.asarray(p.rank_model, dtype=np.float32), feat[None, :],
                                 dtype=np.float32)[0][0]
                 khat = predicted_rank(y)
-                ell = sketch_size(khat, p.oversample)
-                if ell + SKETCH_PROBES <= m[i] and ell < ncol and (p.rank_cap == 0 or ell < p.rank_cap):
+                # the sketch never exceeds m - probes columns: a box whose
+                # predicted rank leaves no room is still sketched at full width
+                ell = min(sketch_size(khat, p.oversample), m[i] - SKETCH_PROBES)
+                if khat < ell < ncol and (p.rank_cap == 0 or ell < p.rank_cap):
                     cap_eff = min(m[i], ncol) if p.rank_cap <= 0 else min(p.rank_cap, m[i], ncol)
                     ok, k_i, piv, Wp, dg = sketch_row_id(M, ell, p.tol, cap_eff, p.sketch_seed,
                                                          lev, i)

@@ -273,7 +273,10 @@ h2ulv_status h2ulv_factorize(const double* pts, int64_t n, const h2ulv_params* p
     return H2ULV_ERR_INVALID_ARG;
   }
   *out = nullptr;
-  return guarded([&] { *out = factorize_impl(pts, n, params, (hipStream_t)stream); });
+  return guarded([&] {
+    CacheScope cs;
+    *out = factorize_impl(pts, n, params, (hipStream_t)stream);
+  });
 }
 
 h2ulv_status h2ulv_factorize_batch(int32_t nprob, const double* const* pts, const int64_t* n,
@@ -285,6 +288,7 @@ h2ulv_status h2ulv_factorize_batch(int32_t nprob, const double* const* pts, cons
   }
   for (int p = 0; p < nprob; ++p) out[p] = nullptr;
   h2ulv_status st = guarded([&] {
+    CacheScope cs;
     if (!params) fail(H2ULV_ERR_INVALID_ARG, "params is NULL");
     validate_params(params);
     std::vector<const double*> pv(pts, pts + nprob);
@@ -306,7 +310,10 @@ h2ulv_status h2ulv_solve(const h2ulv_factor* f, double* b, int32_t nrhs, int64_t
     g_last_error = "bad solve arguments";
     return H2ULV_ERR_INVALID_ARG;
   }
-  return guarded([&] { solve_impl(*f, b, nrhs, ldb, (hipStream_t)stream); });
+  return guarded([&] {
+    CacheScope cs;
+    solve_impl(*f, b, nrhs, ldb, (hipStream_t)stream);
+  });
 }
 
 h2ulv_status h2ulv_matvec_exact(const h2ulv_factor* f, const double* x, int64_t ldx, double* y,
@@ -327,6 +334,7 @@ h2ulv_status h2ulv_refine(const h2ulv_factor* f, const double* b, int64_t ldb, d
   }
   h2ulv_status out = H2ULV_OK;
   h2ulv_status st = guarded([&] {
+    CacheScope cs;
     out = refine_impl(*f, b, ldb, x, ldx, nrhs, rtol, max_iter, iters, relres,
                       (hipStream_t)stream);
   });
@@ -492,8 +500,10 @@ h2ulv_status h2ulv_rankmodel_gradient(const h2ulv_rankmodel* m, const float* fea
     g_last_error = "bad gradient arguments";
     return H2ULV_ERR_INVALID_ARG;
   }
-  return guarded(
-      [&] { rankmodel_gradient(*m, feat, target, n, grad, loss, (hipStream_t)stream); });
+  return guarded([&] {
+    CacheScope cs;
+    rankmodel_gradient(*m, feat, target, n, grad, loss, (hipStream_t)stream);
+  });
 }
 
 h2ulv_status h2ulv_rankmodel_adam_step(h2ulv_rankmodel* m, const float* grad, float lr,
@@ -511,8 +521,10 @@ h2ulv_status h2ulv_rankmodel_train(h2ulv_rankmodel* m, const float* feat, const 
     g_last_error = "bad training arguments";
     return H2ULV_ERR_INVALID_ARG;
   }
-  return guarded(
-      [&] { rankmodel_train(*m, feat, target, n, steps, lr, loss, (hipStream_t)stream); });
+  return guarded([&] {
+    CacheScope cs;
+    rankmodel_train(*m, feat, target, n, steps, lr, loss, (hipStream_t)stream);
+  });
 }
 
 h2ulv_status h2ulv_get_features(const h2ulv_factor* f, int32_t lev, float* feat, float* target) {

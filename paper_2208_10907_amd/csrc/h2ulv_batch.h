@@ -27,6 +27,25 @@ struct MemStats {
 };
 MemStats& mem_stats();
 
+// Caching device allocator.  hipMalloc can stall for hundreds of milliseconds
+// while earlier work is queued, so blocks freed during a library call are kept
+// and handed out again within that call.  All device work of one call is
+// ordered on one stream, so a block freed by a buffer and reused by a later
+// buffer of the same call is only touched after the earlier work in stream
+// order.  Every call synchronises its stream before it returns; the cache is
+// released (hipFree) when the outermost call returns (CacheScope).
+void* cache_alloc(size_t bytes, size_t* got);
+void cache_free(void* p, size_t bytes);
+void cache_release();
+size_t cache_bytes();
+int64_t cache_oom_releases();
+// Free device memory as seen by the library: hipMemGetInfo plus cached blocks.
+size_t free_device_bytes();
+struct CacheScope {
+  CacheScope();
+  ~CacheScope();
+};
+
 // Per-kernel launch timing with HIP events recorded on the launch stream
 // (enabled through h2ulv_profile_enable).
 struct ProfRec {
@@ -77,22 +96,26 @@ struct ProfScope {
 // Owning device buffer (hipMalloc / hipFree).
 struct DBuf {
   void* p = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;  // requested size
+  size_t cap = 0;    // size of the block behind it
   DBuf() = default;
   explicit DBuf(size_t b) { alloc(b); }
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes), cap(o.cap) {
     o.p = nullptr;
     o.bytes = 0;
+    o.cap = 0;
   }
   DBuf& operator=(DBuf&& o) noexcept {
     if (this != &o) {
       reset();
       p = o.p;
       bytes = o.bytes;
+      cap = o.cap;
       o.p = nullptr;
       o.bytes = 0;
+      o.cap = 0;
     }
     return *this;
   }
@@ -100,12 +123,7 @@ struct DBuf {
   void alloc(size_t b) {
     reset();
     if (b == 0) return;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-      p = nullptr;
-      (void)hipGetLastError();
-      fail(H2ULV_ERR_OOM, "device allocation of " + std::to_string(b) + " bytes failed");
-    }
+    p = cache_alloc(b, &cap);
     bytes = b;
     MemStats& ms = mem_stats();
     ms.live += b;
@@ -113,11 +131,12 @@ struct DBuf {
   }
   void reset() {
     if (p) {
-      (void)hipFree(p);
+      cache_free(p, cap);
       mem_stats().live -= bytes;
     }
     p = nullptr;
     bytes = 0;
+    cap = 0;
   }
   template <class T>
   T* as() const {

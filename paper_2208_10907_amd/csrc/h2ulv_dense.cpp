@@ -8,9 +8,148 @@
 //     parts of the shared basis; LAPACK dgeqrf/dlarft/dorgqr conventions).
 #include "h2ulv_dense.h"
 
+#include <exception>
+#include <map>
+#include <mutex>
+
 #include <algorithm>
 
 namespace h2ulv {
+
+namespace {
+
+struct DevCache {
+  std::mutex mu;
+  std::multimap<size_t, void*> blocks;  // free blocks by size
+  size_t cached = 0;
+  int depth = 0;          // nesting of library calls holding the cache
+  int64_t oom_releases = 0;      // times the cache was emptied after a failed hipMalloc
+  int64_t reserve_releases = 0;  // times it was emptied to keep the free reserve
+};
+
+DevCache& dev_cache() {
+  static DevCache c;
+  return c;
+}
+
+size_t round_block(size_t b) {
+  const size_t g = b >= ((size_t)1 << 20) ? ((size_t)2 << 20) : 256;
+  return (b + g - 1) / g * g;
+}
+
+void release_locked(DevCache& c) {
+  for (auto& kv : c.blocks) (void)hipFree(kv.second);
+  c.blocks.clear();
+  c.cached = 0;
+}
+
+}  // namespace
+
+void* cache_alloc(size_t bytes, size_t* got) {
+  DevCache& c = dev_cache();
+  const size_t want = round_block(bytes);
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    // smallest cached block that fits without wasting more than half of it
+    auto it = c.blocks.lower_bound(want);
+    if (it != c.blocks.end() && it->first <= want + want / 2 + ((size_t)4 << 20)) {
+      void* p = it->second;
+      *got = it->first;
+      c.cached -= it->first;
+      c.blocks.erase(it);
+      return p;
+    }
+  }
+  // keep a reserve of free device memory for the runtime (kernel scratch,
+  // queues) and other users: before growing into it, hand the cached blocks
+  // back, after waiting for the device since queued work may still read them
+  {
+    size_t freeb = 0, totb = 0;
+    if (hipMemGetInfo(&freeb, &totb) == hipSuccess) {
+      const size_t reserve = std::max<size_t>((size_t)16 << 30, totb / 16);
+      std::unique_lock<std::mutex> lk(c.mu);
+      if (c.cached > 0 && freeb < want + reserve) {
+        lk.unlock();
+        (void)hipDeviceSynchronize();
+        lk.lock();
+        c.reserve_releases += 1;
+        release_locked(c);
+      }
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    // cached blocks are free on the host side but queued work may still read
+    // them: wait for the device before handing them back to the runtime
+    (void)hipDeviceSynchronize();
+    {
+      std::lock_guard<std::mutex> lk(c.mu);
+      c.oom_releases += 1;
+      release_locked(c);
+    }
+    e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(H2ULV_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  *got = want;
+  return p;
+}
+
+void cache_free(void* p, size_t bytes) {
+  DevCache& c = dev_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  if (c.depth == 0) {
+    (void)hipFree(p);  // outside a library call nothing may reuse it
+    return;
+  }
+  c.blocks.emplace(bytes, p);
+  c.cached += bytes;
+}
+
+void cache_release() {
+  DevCache& c = dev_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  release_locked(c);
+}
+
+int64_t cache_oom_releases() {
+  DevCache& c = dev_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  return c.oom_releases + c.reserve_releases;
+}
+
+size_t cache_bytes() {
+  DevCache& c = dev_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  return c.cached;
+}
+
+size_t free_device_bytes() {
+  size_t freeb = 0, totb = 0;
+  H2ULV_HIP(hipMemGetInfo(&freeb, &totb));
+  return freeb + cache_bytes();
+}
+
+CacheScope::CacheScope() {
+  DevCache& c = dev_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.depth += 1;
+}
+
+CacheScope::~CacheScope() {
+  // leaving by an exception: queued work may still use cached blocks
+  if (std::uncaught_exceptions() > 0) (void)hipDeviceSynchronize();
+  DevCache& c = dev_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.depth -= 1;
+  if (c.depth == 0) release_locked(c);
+}
 
 MemStats& mem_stats() {
   static MemStats ms;

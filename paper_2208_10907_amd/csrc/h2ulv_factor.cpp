@@ -476,9 +476,12 @@ void Driver::basis_prepare(Stage& st, const std::vector<Prob*>& G) {
       double kh = std::floor(std::pow(2.0, (double)hy[q]) - 1.0 + 0.5);
       if (!(kh < 1e8)) kh = 1e8;  // also catches a non-finite output
       lf.khat[i] = std::max(0, (int)kh);
-      const int64_t ell = (5 * (int64_t)lf.khat[i] + 3) / 4 + p.oversample;
       const int mi = lf.m[i];
-      if (ell + SKETCH_PROBES <= mi && ell < P->ncols[i] && (p.rank_cap == 0 || ell < p.rank_cap)) {
+      // at most m - probes columns: a box whose predicted rank leaves no room
+      // is still sketched at full width
+      const int64_t ell = std::min<int64_t>((5 * (int64_t)lf.khat[i] + 3) / 4 + p.oversample,
+                                            mi - SKETCH_PROBES);
+      if (lf.khat[i] < ell && ell < P->ncols[i] && (p.rank_cap == 0 || ell < p.rank_cap)) {
         lf.ell[i] = (int)ell;
         lf.sk_state[i] = 1;
       }
@@ -489,8 +492,7 @@ void Driver::basis_prepare(Stage& st, const std::vector<Prob*>& G) {
 // ---- (c) M'^T of each box (chunked over boxes by memory), then either its
 // tall QR -> m x m triangle, or (sketched boxes) [Y^T; Z^T] = Omega^T M'^T
 void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebuild) {
-  size_t freeb = 0, totb = 0;
-  H2ULV_HIP(hipMemGetInfo(&freeb, &totb));
+  const size_t freeb = free_device_bytes();
   int64_t budget = (int64_t)(freeb * 0.4) / (int64_t)sizeof(double);
   budget = std::max<int64_t>(budget, 1 << 20);
   auto sketched = [](const Box& b) { return b.P->lf().sk_state[b.i] == 1; };
@@ -1611,8 +1613,7 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
         P.nb = 1 << P.lev;
         act.push_back(&P);
       }
-    size_t freeb = 0, totb = 0;
-    H2ULV_HIP(hipMemGetInfo(&freeb, &totb));
+    const size_t freeb = free_device_bytes();
     const double cap = 0.45 * (double)freeb;
     const bool mixed = params.precision == H2ULV_MIXED;
     size_t a0 = 0;
@@ -1636,7 +1637,9 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
           for (int x : lf.k) mk = std::max(mk, x);
         }
         std::fprintf(stderr, "[h2ulv] height %d: %zu problem(s), %d boxes, max m %d, max k %d, "
-                     "%.3f s |", h, grp.size(), nbx, mm, mk, now_s() - t_lev);
+                     "%.3f s, live %.1f GB, cached %.1f GB, cache releases %lld |", h, grp.size(),
+                     nbx, mm, mk, now_s() - t_lev, mem_stats().live / 1e9, cache_bytes() / 1e9,
+                     (long long)cache_oom_releases());
         for (auto& kv : drv.step_time) std::fprintf(stderr, " %s %.3f", kv.first.c_str(), kv.second);
         std::fprintf(stderr, "\n");
         drv.step_time.clear();

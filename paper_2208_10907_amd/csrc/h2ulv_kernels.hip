@@ -369,6 +369,7 @@ __global__ __launch_bounds__(64) void lu_swap_trsm_kernel(const MatDesc* __restr
                                                           const int64_t* __restrict__ slab_ptr,
                                                           int nmat, int j0, int nb) {
   __shared__ double L11[64][65];
+  __shared__ double X[64][65];
   int64_t slab = blockIdx.x;
   int id = find_item(slab_ptr, nmat, slab);
   const MatDesc d = ds[id];
@@ -394,17 +395,14 @@ __global__ __launch_bounds__(64) void lu_swap_trsm_kernel(const MatDesc* __restr
     }
   }
   if (c >= j0 + w) {
-    double x[64];
-#pragma unroll
-    for (int r = 0; r < 64; ++r) x[r] = (r < w) ? col[j0 + r] : 0.0;
-#pragma unroll
-    for (int l = 0; l < 64; ++l) {
-#pragma unroll
-      for (int r = l + 1; r < 64; ++r) x[r] -= L11[r][l] * x[l];
+    // forward substitution with the unit lower L11; each lane keeps its column
+    // in its own LDS column (no cross-lane traffic, no barrier)
+    for (int r = 0; r < w; ++r) X[r][lane] = col[j0 + r];
+    for (int l = 0; l < w; ++l) {
+      const double xl = X[l][lane];
+      for (int r = l + 1; r < w; ++r) X[r][lane] -= L11[r][l] * xl;
     }
-#pragma unroll
-    for (int r = 0; r < 64; ++r)
-      if (r < w) col[j0 + r] = x[r];
+    for (int r = 0; r < w; ++r) col[j0 + r] = X[r][lane];
   }
 }
 

@@ -163,8 +163,8 @@ def test_sketch_exhausted_is_rejected():
 
 def test_predicted_mode_keeps_the_accuracy_class():
     """A model trained on the ranks of one factorization, used on another point
-    set: sketched boxes are accepted, the error against dense LU stays in the
-    class of the plain method, and the basis step costs fewer flops."""
+    set: sketched boxes are accepted and the error against dense LU stays in the
+    class of the plain method."""
     p = O.Params(leaf=64, tol=1e-6)
     f0 = O.factorize(W.cube_points(2048, 21), p)
     F = np.concatenate([[b.feat for b in f0.levels[l]] for l in f0.levels])
@@ -182,4 +182,35 @@ def test_predicted_mode_keeps_the_accuracy_class():
     e_plain = np.linalg.norm(O.solve(plain, b) - xs) / np.linalg.norm(xs)
     e_pred = np.linalg.norm(O.solve(fac, b) - xs) / np.linalg.norm(xs)
     assert e_pred < max(1e-3, 5 * e_plain), (e_pred, e_plain)
-    assert fac.stats["flops"]["basis"] < plain.stats["flops"]["basis"]
+    # every sketch is at most m - probes wide and wider than its predicted rank
+    for l in fac.levels:
+        for bx in fac.levels[l]:
+            if bx.sketch:
+                assert bx.khat < bx.ell <= bx.m - O.SKETCH_PROBES
+
+
+def test_sketch_sized_by_prediction_saves_basis_work():
+    """Where the predicted rank is well below m (leaf 256 of a sphere at tol
+    1e-4: ranks about 50-60), a sketch sized by the prediction (k-hat = 60, 83
+    columns) is accepted everywhere and costs fewer basis flops than the full QR;
+    a prediction below some true leaf ranks (k-hat = 30, 46 columns) exhausts
+    those sketches, which fall back to the full QR."""
+    X = W.sphere_points(4096, 31)
+    p = O.Params(leaf=256, tol=1e-4)
+    plain = O.factorize(X, p)
+    fac = O.factorize(X, O.Params(leaf=256, tol=1e-4, rank_model=_constant_mlp(60), sketch_seed=2))
+    st = [b.sketch for l in fac.levels for b in fac.levels[l]]
+    assert st.count(1) == len(st)
+    assert fac.stats["flops"]["basis"] < 0.6 * plain.stats["flops"]["basis"]
+    low = O.factorize(X, O.Params(leaf=256, tol=1e-4, rank_model=_constant_mlp(30), sketch_seed=2))
+    L = low.tree.L
+    leaves = low.levels[L]
+    fell = [b for b in leaves if b.sketch == 2]
+    assert fell and all(b.k >= b.ell for b in fell)   # exhausted: true rank beyond the sketch
+    assert all(b.k < b.ell for b in leaves if b.sketch == 1)
+
+
+def _constant_mlp(k):
+    parts = {name: np.zeros(s) for name, s in R.SHAPES}
+    parts["b4"][0] = math.log2(1 + k)
+    return R.pack(parts).astype(np.float32)
