@@ -265,7 +265,8 @@ h2ulv_status h2ulv_profile_read(h2ulv_kernel_profile* out, int32_t max, int32_t*
  * box); 8 further Gaussian columns G probe its error, and the sketch is
  * accepted iff it was not exhausted (k < l) and
  *   ||Z[piv[k:]] - E^T Z[piv[:k]]||_F <= 10 sqrt(m - k) tol max_j ||Z[j]||,
- * Z = M' G, E = R11^-1 R12.  Otherwise the box uses the full pivoted QR.
+ * Z = M' G, E = R11^-1 R12.  A rejected sketch narrower than m - 8 is retried
+ * once at l = m - 8; if that is rejected too, the box uses the full pivoted QR.
  */
 #define H2ULV_NFEAT 16
 #define H2ULV_MLP_NPARAM 9473
@@ -297,8 +298,9 @@ h2ulv_status h2ulv_rankmodel_train(h2ulv_rankmodel* m, const float* feat, const 
 /* Features of level lev (1..L) of a factor: feat host 2^lev x 16 row-major,
  * target host 2^lev (log2(1 + k)); either may be NULL. */
 h2ulv_status h2ulv_get_features(const h2ulv_factor* f, int32_t lev, float* feat, float* target);
-/* Per box of level lev: predicted rank (-1 without a model), sketch columns
- * (0: full pivoted QR) and outcome (0 not sketched, 1 accepted, 2 fell back). */
+/* Per box of level lev: predicted rank (-1 without a model), sketch columns of
+ * the last attempt (0: not sketched) and outcome (0 not sketched, 1 accepted,
+ * 2 fell back to the full pivoted QR, 3 accepted on the full-width retry). */
 h2ulv_status h2ulv_get_sketch_info(const h2ulv_factor* f, int32_t lev, int32_t* khat,
                                    int32_t* ell, int32_t* state);
 

@@ -462,7 +462,8 @@ class BoxFactor:
     feat: np.ndarray = None  # rank-model features (float32, 16)
     khat: int = -1           # predicted rank (-1: no model)
     ell: int = 0             # sketch columns (0: full pivoted QR)
-    sketch: int = 0          # 0 not sketched, 1 sketch accepted, 2 fell back
+    sketch: int = 0          # 0 not sketched, 1 sketch accepted, 2 fell back to the
+                             # full QR, 3 accepted on the full-width retry
 
 
 @dataclass
@@ -616,9 +617,18 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                                                          lev, i)
                     state = 1 if ok else 2
                     flops["basis"] += 2.0 * ncol * m[i] * (ell + SKETCH_PROBES)
+                    # a rejected sketch is retried once at full width (m - probes
+                    # columns) before the full pivoted QR
+                    full = m[i] - SKETCH_PROBES
+                    if not ok and ell < full < ncol and (p.rank_cap == 0 or full < p.rank_cap):
+                        ell = full
+                        ok, k_i, piv, Wp, dg = sketch_row_id(M, ell, p.tol, cap_eff,
+                                                             p.sketch_seed, lev, i)
+                        state = 3 if ok else 2
+                        flops["basis"] += 2.0 * ncol * m[i] * (ell + SKETCH_PROBES)
                 else:
                     ell = 0
-            if state != 1:
+            if state not in (1, 3):
                 k_i, piv, Wp, dg = row_id(M, p.tol, p.rank_cap)
                 flops["basis"] += 2.0 * ncol * m[i] ** 2 - 2.0 / 3.0 * min(ncol, m[i]) ** 3 if ncol >= m[i] else 2.0 * m[i] * ncol ** 2 - 2.0 / 3.0 * ncol ** 3
             if lev < L and m[i] > 0:

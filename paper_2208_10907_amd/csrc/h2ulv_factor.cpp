@@ -936,17 +936,39 @@ void Driver::row_ids(Stage& st, const std::vector<Prob*>& G) {
   build_triangles(st, all);
   pivot_boxes(st, all);
   if (!sk.empty()) {
-    std::vector<Box> fails = check_sketches(st, sk);
-    if (!fails.empty()) {
-      // rejected sketches: the full pivoted QR of their M' (rebuilt)
-      for (const Box& b : fails) {
-        b.P->lf().sk_state[b.i] = 2;
-        const int mi = b.P->lf().m[b.i];
-        H2ULV_HIP(hipMemsetAsync(b.P->PQ.as<double>() + b.P->offSq[b.i], 0,
-                                 (size_t)mi * mi * sizeof(double), s));
+    auto clear = [&](const Box& b) {
+      const int mi = b.P->lf().m[b.i];
+      H2ULV_HIP(hipMemsetAsync(b.P->PQ.as<double>() + b.P->offSq[b.i], 0,
+                               (size_t)mi * mi * sizeof(double), s));
+    };
+    std::vector<Box> fails = check_sketches(st, sk), retry, full;
+    // a rejected sketch is retried once at full width (m - probes columns)
+    for (const Box& b : fails) {
+      LevelFactor& lf = b.P->lf();
+      const int w = lf.m[b.i] - SKETCH_PROBES;
+      if (lf.ell[b.i] < w && w < b.P->ncols[b.i] && (p.rank_cap == 0 || w < p.rank_cap)) {
+        lf.ell[b.i] = w;
+        retry.push_back(b);
+      } else {
+        full.push_back(b);
       }
-      build_triangles(st, fails, true);
-      pivot_boxes(st, fails);
+    }
+    if (!retry.empty()) {
+      for (const Box& b : retry) clear(b);
+      build_triangles(st, retry, true);
+      pivot_boxes(st, retry);
+      std::vector<Box> again = check_sketches(st, retry);
+      for (const Box& b : retry) b.P->lf().sk_state[b.i] = 3;
+      full.insert(full.end(), again.begin(), again.end());
+    }
+    if (!full.empty()) {
+      // the full pivoted QR of their M' (rebuilt)
+      for (const Box& b : full) {
+        b.P->lf().sk_state[b.i] = 2;
+        clear(b);
+      }
+      build_triangles(st, full, true);
+      pivot_boxes(st, full);
     }
   }
   for (Prob* P : G) P->Z.reset();

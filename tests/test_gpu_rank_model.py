@@ -146,8 +146,9 @@ def _constant_model(k):
 @pytest.mark.parametrize("n,leaf,tol,oversample,model", [
     (4096, 128, 1e-6, 8, "trained"),   # sketched leaves (m = 128) and upper levels
     (4096, 128, 1e-8, 8, "trained"),   # sketched boxes with m > 512 (multi-workgroup QR)
-    (3000, 64, 1e-6, 0, "constant"),   # k-hat = 10, no oversampling: every sketch is
-                                       # exhausted and falls back to the full QR
+    (3000, 64, 1e-6, 0, "constant"),   # k-hat = 10, no oversampling: every first
+                                       # sketch is exhausted; full-width retries,
+                                       # then the full QR where those fail too
 ])
 def test_predicted_mode_parity(n, leaf, tol, oversample, model):
     base = O.Params(leaf=leaf, tol=tol)
@@ -171,7 +172,7 @@ def test_predicted_mode_parity(n, leaf, tol, oversample, model):
     if model == "trained":
         assert states.count(1) >= 2
     else:
-        assert states.count(2) == len(states)
+        assert states.count(2) + states.count(3) == len(states) and states.count(2) >= 1
     m_all = [b.m for l in fo.levels for b in fo.levels[l] if b.sketch == 1]
     for lev in range(fo.tree.L, 0, -1):
         m, k = fg.ranks(lev)

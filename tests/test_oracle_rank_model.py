@@ -194,7 +194,7 @@ def test_sketch_sized_by_prediction_saves_basis_work():
     1e-4: ranks about 50-60), a sketch sized by the prediction (k-hat = 60, 83
     columns) is accepted everywhere and costs fewer basis flops than the full QR;
     a prediction below some true leaf ranks (k-hat = 30, 46 columns) exhausts
-    those sketches, which fall back to the full QR."""
+    those sketches, which are retried at full width."""
     X = W.sphere_points(4096, 31)
     p = O.Params(leaf=256, tol=1e-4)
     plain = O.factorize(X, p)
@@ -205,9 +205,10 @@ def test_sketch_sized_by_prediction_saves_basis_work():
     low = O.factorize(X, O.Params(leaf=256, tol=1e-4, rank_model=_constant_mlp(30), sketch_seed=2))
     L = low.tree.L
     leaves = low.levels[L]
-    fell = [b for b in leaves if b.sketch == 2]
-    assert fell and all(b.k >= b.ell for b in fell)   # exhausted: true rank beyond the sketch
-    assert all(b.k < b.ell for b in leaves if b.sketch == 1)
+    # exhausted first sketches are retried at full width (m - probes columns)
+    retried = [b for b in leaves if b.sketch in (2, 3)]
+    assert retried and all(b.ell == b.m - O.SKETCH_PROBES for b in retried)
+    assert all(b.k < b.ell for b in leaves if b.sketch in (1, 3))
 
 
 def _constant_mlp(k):
