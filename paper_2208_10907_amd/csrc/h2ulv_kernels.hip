@@ -975,62 +975,89 @@ void launch_copy(const CopyItem* items, const int64_t* tile_ptr, int64_t ntiles,
 // Exact matvec y = A x with A generated on the fly in float64 (residuals of the
 // iterative refinement).  One thread per row; source points staged in LDS.
 // ---------------------------------------------------------------------------
+// 1/r to full double precision: the hardware reciprocal square root (about 23
+// correct bits) followed by two Newton steps y <- y (3 - r2 y^2) / 2.
+__device__ __forceinline__ double inv_sqrt(double r2) {
+  double y = __builtin_amdgcn_rsq(r2);
+  double e = fma(-r2 * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-r2 * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// Exact y = A x with the matrix generated on the fly.  Each thread owns two
+// target points (i and i + 256) and runs over all sources staged in LDS, 256 at
+// a time; the self term is excluded by a select on r^2 > 0 and diag x_i is
+// added at the end.
 template <int NR>
 __global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ pts, int64_t n,
                                                      KernelFn kf, const double* __restrict__ x,
                                                      int64_t ldx, double* __restrict__ y,
                                                      int64_t ldy) {
-  __shared__ double sp[256][3];
+  __shared__ double sp[3][256];
   __shared__ double sx[NR][256];
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  double xi = 0, yi = 0, zi = 0;
-  if (i < n) {
-    xi = pts[3 * i];
-    yi = pts[3 * i + 1];
-    zi = pts[3 * i + 2];
-  }
-  double acc[NR];
+  const int64_t i0 = (int64_t)blockIdx.x * 512 + threadIdx.x;
+  const int64_t i1 = i0 + 256;
+  double p0[3] = {0, 0, 0}, p1[3] = {0, 0, 0};
+  if (i0 < n)
+    for (int d = 0; d < 3; ++d) p0[d] = pts[3 * i0 + d];
+  if (i1 < n)
+    for (int d = 0; d < 3; ++d) p1[d] = pts[3 * i1 + d];
+  double a0[NR], a1[NR];
 #pragma unroll
-  for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+  for (int c = 0; c < NR; ++c) a0[c] = a1[c] = 0.0;
+  const bool lap = kf.kind == 0;
   for (int64_t j0 = 0; j0 < n; j0 += 256) {
     const int64_t j = j0 + threadIdx.x;
     __syncthreads();
     if (j < n) {
-      sp[threadIdx.x][0] = pts[3 * j];
-      sp[threadIdx.x][1] = pts[3 * j + 1];
-      sp[threadIdx.x][2] = pts[3 * j + 2];
+      for (int d = 0; d < 3; ++d) sp[d][threadIdx.x] = pts[3 * j + d];
 #pragma unroll
       for (int c = 0; c < NR; ++c) sx[c][threadIdx.x] = x[j + c * ldx];
     } else {
+      // padding entries (never read: the loop below stops at the last source)
+      for (int d = 0; d < 3; ++d) sp[d][threadIdx.x] = 0.0;
 #pragma unroll
       for (int c = 0; c < NR; ++c) sx[c][threadIdx.x] = 0.0;
-      sp[threadIdx.x][0] = sp[threadIdx.x][1] = sp[threadIdx.x][2] = 0.0;
     }
     __syncthreads();
     const int cnt = (int)min((int64_t)256, n - j0);
     for (int t = 0; t < cnt; ++t) {
-      const int64_t jj = j0 + t;
-      double kv;
-      if (jj == i) {
-        kv = kf.diag;
-      } else {
-        double dx = xi - sp[t][0], dy = yi - sp[t][1], dz = zi - sp[t][2];
-        double r2 = dx * dx + dy * dy + dz * dz;
-        kv = (r2 > 0.0) ? kernel_value(kf, r2) : 0.0;
+      const double sx0 = sp[0][t], sy0 = sp[1][t], sz0 = sp[2][t];
+      double dx = p0[0] - sx0, dy = p0[1] - sy0, dz = p0[2] - sz0;
+      const double q0 = fma(dx, dx, fma(dy, dy, dz * dz));
+      dx = p1[0] - sx0;
+      dy = p1[1] - sy0;
+      dz = p1[2] - sz0;
+      const double q1 = fma(dx, dx, fma(dy, dy, dz * dz));
+      double k0 = inv_sqrt(q0), k1 = inv_sqrt(q1);
+      if (!lap) {
+        k0 *= exp(-kf.alpha * (q0 * k0));
+        k1 *= exp(-kf.alpha * (q1 * k1));
       }
+      k0 = q0 > 0.0 ? k0 : 0.0;
+      k1 = q1 > 0.0 ? k1 : 0.0;
 #pragma unroll
-      for (int c = 0; c < NR; ++c) acc[c] += kv * sx[c][t];
+      for (int c = 0; c < NR; ++c) {
+        const double xs = sx[c][t];
+        a0[c] = fma(k0, xs, a0[c]);
+        a1[c] = fma(k1, xs, a1[c]);
+      }
     }
   }
-  if (i < n) {
+  if (i0 < n) {
 #pragma unroll
-    for (int c = 0; c < NR; ++c) y[i + c * ldy] = acc[c];
+    for (int c = 0; c < NR; ++c) y[i0 + c * ldy] = fma(kf.diag, x[i0 + c * ldx], a0[c]);
+  }
+  if (i1 < n) {
+#pragma unroll
+    for (int c = 0; c < NR; ++c) y[i1 + c * ldy] = fma(kf.diag, x[i1 + c * ldx], a1[c]);
   }
 }
 
 void launch_matvec(const double* pts, int64_t n, KernelFn kf, const double* x, int64_t ldx,
                    double* y, int64_t ldy, int nrhs, hipStream_t s) {
-  unsigned grid = (unsigned)((n + 255) / 256);
+  unsigned grid = (unsigned)((n + 511) / 512);
   int c = 0;
   while (c < nrhs) {
     int left = nrhs - c;

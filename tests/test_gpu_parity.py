@@ -118,14 +118,19 @@ def test_root_only(n):
     _parity(X, O.Params(leaf=64, tol=1e-8, far_sample=0), nrhs=2, check_basis=False)
 
 
-def test_matvec_exact():
-    X = W.sphere_points(3000, 5)
-    op = O.Params(kernel=O.YUKAWA, alpha=0.5, leaf=128)
+@pytest.mark.parametrize("kernel,n,nrhs", [(O.YUKAWA, 3000, 9), (O.LAPLACE, 3001, 4),
+                                             (O.LAPLACE, 700, 1)])
+def test_matvec_exact(kernel, n, nrhs):
+    """Exact matvec (two targets per thread, 512-point blocks with a ragged
+    tail, 8/4/1 right-hand-side variants) against the oracle, column by column."""
+    X = W.sphere_points(n, 5)
+    op = O.Params(kernel=kernel, alpha=0.5, leaf=128)
     fg = H.factorize(X, _params(op))
-    x = W.gaussian_rhs(3000, 9, 3)
-    y = fg.matvec(torch.tensor(x, device="cuda")).cpu().numpy()
-    yo = O.matvec_exact(X, x, op)
-    assert np.linalg.norm(y - yo) / np.linalg.norm(yo) < 1e-14
+    x = W.gaussian_rhs(n, nrhs, 3)
+    y = fg.matvec(torch.tensor(x, device="cuda")).cpu().numpy().reshape(n, nrhs)
+    yo = O.matvec_exact(X, x, op).reshape(n, nrhs)
+    for c in range(nrhs):
+        assert np.linalg.norm(y[:, c] - yo[:, c]) / np.linalg.norm(yo[:, c]) < 1e-14, c
 
 
 def test_refine_and_not_converged():
