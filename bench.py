@@ -144,6 +144,9 @@ def main() -> int:
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--window-file", default=None,
+                    help="write the timed region's start and end (time.monotonic_ns) here, "
+                         "to match a profiler trace to the timed steps")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the distributed process tree of "
@@ -193,6 +196,7 @@ def main() -> int:
             f"{r['refine_s']:.2f} s refine)")
     torch.cuda.synchronize()
     H.profile_enable(True)
+    w_start = time.monotonic_ns()
     t_start = time.perf_counter()
     res = []
     for i in range(args.steps):
@@ -200,6 +204,9 @@ def main() -> int:
         log(f"timed step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    if args.window_file:
+        with open(args.window_file, "w") as fh:
+            fh.write(f"{w_start} {time.monotonic_ns()}\n")
     prof = H.profile_read()
     H.profile_enable(False)
     ms = 1e3 * t_total / args.steps

@@ -217,9 +217,10 @@ void h2ulv_structure_destroy(h2ulv_structure* s);
 
 /*
  * Kernel timing (the measurement behind the reported roofline fractions).
- * h2ulv_profile_enable(1) clears earlier records and starts recording a pair of
- * HIP events around every batched launch of the main kernels, on the stream
- * the launch uses; h2ulv_profile_enable(0) stops recording.
+ * h2ulv_profile_enable(1) clears earlier records, creates a pool of events and
+ * starts recording a pair of HIP events around every batched launch of the main
+ * kernels, on the stream the launch uses; h2ulv_profile_enable(0) stops
+ * recording.
  * h2ulv_profile_read waits for the recorded events, aggregates them per kernel
  * (launch count, summed duration, summed algorithmic flops and operand bytes:
  * GEMM 2MNK flops and (MK + KN + MN) element bytes; kernel generation counts
@@ -303,6 +304,15 @@ h2ulv_status h2ulv_get_features(const h2ulv_factor* f, int32_t lev, float* feat,
  * 2 fell back to the full pivoted QR, 3 accepted on the full-width retry). */
 h2ulv_status h2ulv_get_sketch_info(const h2ulv_factor* f, int32_t lev, int32_t* khat,
                                    int32_t* ell, int32_t* state);
+
+/*
+ * Device memory the library freed is kept in a cache and reused by later
+ * calls (hipMalloc/hipFree stall behind queued work).  The cache gives memory
+ * back by itself before free device memory would fall below
+ * max(16 GiB, 1/16 of the device); h2ulv_release_cache waits for the device and
+ * hands every cached block back to the runtime now.
+ */
+h2ulv_status h2ulv_release_cache(void);
 
 const char* h2ulv_status_string(h2ulv_status s);
 const char* h2ulv_last_error(void);

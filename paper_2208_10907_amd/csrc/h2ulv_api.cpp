@@ -554,6 +554,13 @@ h2ulv_status h2ulv_get_sketch_info(const h2ulv_factor* f, int32_t lev, int32_t* 
   return H2ULV_OK;
 }
 
+h2ulv_status h2ulv_release_cache(void) {
+  return guarded([&] {
+    H2ULV_HIP(hipDeviceSynchronize());
+    cache_release();
+  });
+}
+
 const char* h2ulv_status_string(h2ulv_status s) {
   switch (s) {
     case H2ULV_OK: return "ok";
@@ -578,6 +585,14 @@ h2ulv_status h2ulv_profile_enable(int32_t on) {
     }
     p.recs.clear();
     p.on = on != 0;
+    // create the events up front: hipEventCreate inside the measured work would
+    // add its own cost to every recorded launch
+    if (p.on)
+      while (p.pool.size() < 65536) {
+        hipEvent_t e;
+        H2ULV_HIP(hipEventCreate(&e));
+        p.pool.push_back(e);
+      }
   });
 }
 

@@ -28,12 +28,15 @@ struct MemStats {
 MemStats& mem_stats();
 
 // Caching device allocator.  hipMalloc can stall for hundreds of milliseconds
-// while earlier work is queued, so blocks freed during a library call are kept
-// and handed out again within that call.  All device work of one call is
+// while earlier work is queued, and hipFree of many blocks costs as much, so
+// freed blocks are kept and handed out again.  All device work of one call is
 // ordered on one stream, so a block freed by a buffer and reused by a later
 // buffer of the same call is only touched after the earlier work in stream
-// order.  Every call synchronises its stream before it returns; the cache is
-// released (hipFree) when the outermost call returns (CacheScope).
+// order; every call synchronises its stream before it returns, so blocks kept
+// across calls are idle.  The cache is handed back to the runtime when growing
+// would eat into a free-memory reserve, after a failed hipMalloc, when a call
+// fails (CacheScope), and on h2ulv_release_cache; every release waits for the
+// device first.
 void* cache_alloc(size_t bytes, size_t* got);
 void cache_free(void* p, size_t bytes);
 void cache_release();

@@ -104,10 +104,6 @@ void* cache_alloc(size_t bytes, size_t* got) {
 void cache_free(void* p, size_t bytes) {
   DevCache& c = dev_cache();
   std::lock_guard<std::mutex> lk(c.mu);
-  if (c.depth == 0) {
-    (void)hipFree(p);  // outside a library call nothing may reuse it
-    return;
-  }
   c.blocks.emplace(bytes, p);
   c.cached += bytes;
 }
@@ -143,12 +139,14 @@ CacheScope::CacheScope() {
 }
 
 CacheScope::~CacheScope() {
-  // leaving by an exception: queued work may still use cached blocks
-  if (std::uncaught_exceptions() > 0) (void)hipDeviceSynchronize();
+  // leaving by an exception: queued work may still use cached blocks, so the
+  // cache is handed back once the device is idle
+  const bool unwinding = std::uncaught_exceptions() > 0;
+  if (unwinding) (void)hipDeviceSynchronize();
   DevCache& c = dev_cache();
   std::lock_guard<std::mutex> lk(c.mu);
   c.depth -= 1;
-  if (c.depth == 0) release_locked(c);
+  if (c.depth == 0 && unwinding) release_locked(c);
 }
 
 MemStats& mem_stats() {

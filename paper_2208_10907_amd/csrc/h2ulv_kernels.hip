@@ -103,9 +103,6 @@ void launch_kgen(const KgenItem* items, const int64_t* tile_ptr, int64_t ntiles,
 
 // ---------------------------------------------------------------------------
 // Grouped GEMM on the matrix cores.
-// C = beta C + alpha sum_t op(A_t) op(B_t) for a batch of items of any size.
-// Tile 64 x 64 x 16 per workgroup of 4 waves; each wave owns a 32 x 32 sub-tile
-// made of 2 x 2 MFMA 16x16x4 accumulators.  Operands are staged through LDS.
 // MFMA 16x16x4 operand layout (one value per lane): A(i, k) with i = lane % 16,
 // k = lane / 16; B(k, j) with j = lane % 16, k = lane / 16.  Accumulator element
 // r of lane l holds D(row, l % 16) with row = 4 r + l / 16 for the f64
@@ -130,97 +127,129 @@ struct Mfma<float> {
   }
 };
 
+// C = beta C + alpha sum_t op(A_t) op(B_t) for a batch of items of any size.
+// A workgroup (4 waves, 2 x 2, each a (TM/2) x (TN/2) block of 16 x 16 MFMA
+// accumulators) owns a TM x TN tile of one item (found
+// by binary search over the tile prefix table) and runs over the flattened
+// sequence of 16-deep K tiles of all the item's terms.  The K tiles are staged
+// through two LDS buffers: the next tile is loaded from global memory into
+// registers while the MFMAs consume the current one, then stored into the other
+// buffer, with one barrier per tile; the A/B fragments of the next 4-deep step
+// are read from LDS before the MFMAs of the current step.  Interior tiles load
+// without bounds checks.
 template <typename T, typename TC, int TM, int TN>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<TC>* __restrict__ items,
-                                                   const GemmTerm<T>* __restrict__ terms,
-                                                   const int64_t* __restrict__ tile_ptr,
-                                                   int nitems) {
+                                                    const GemmTerm<T>* __restrict__ terms,
+                                                    const int64_t* __restrict__ tile_ptr,
+                                                    int nitems) {
   typedef typename Mfma<T>::v4 v4;
-  constexpr int BM = TM / 32, BN = TN / 32;  // 16x16 blocks per wave (2 x 2 waves)
-  constexpr int LA = TM / 16, LB = TN / 16;  // elements per thread per K tile
-  __shared__ T As[16][TM + 4];
-  __shared__ T Bs[16][TN + 4];
-  int64_t tile = blockIdx.x;
-  int id = find_item(tile_ptr, nitems, tile);
+  constexpr int BM = TM / 32, BN = TN / 32;
+  constexpr int LA = TM / 16, LB = TN / 16;
+  __shared__ T As[2][16][TM + 4];
+  __shared__ T Bs[2][16][TN + 4];
+  const int64_t tile = blockIdx.x;
+  const int id = find_item(tile_ptr, nitems, tile);
   const GemmItem<TC> it = items[id];
-  int64_t local = tile - tile_ptr[id];
+  const int64_t local = tile - tile_ptr[id];
   const int tm = (it.M + TM - 1) / TM;
   const int row0 = (int)(local % tm) * TM, col0 = (int)(local / tm) * TN;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w & 1, wc = w >> 1;
+  const bool rows_in = row0 + TM <= it.M, cols_in = col0 + TN <= it.N;
   v4 acc[BM][BN];
 #pragma unroll
   for (int a = 0; a < BM; ++a)
 #pragma unroll
     for (int b = 0; b < BN; ++b) acc[a][b] = v4{0, 0, 0, 0};
   T ra[LA], rb[LB];
-  // load K tile (term t, offset k0) of op(A) and op(B) into registers
   auto load = [&](int t, int k0) {
     const GemmTerm<T>& tt = terms[t];
+    const bool kin = k0 + 16 <= tt.K;
     if (!(tt.flags & 1)) {
       const int i = tid % TM, kb = tid / TM;
+      const T* p = tt.A + (row0 + i) + (int64_t)(k0 + kb) * tt.lda;
+      if (rows_in && kin) {
 #pragma unroll
-      for (int r = 0; r < LA; ++r) {
-        const int kk = kb + (256 / TM) * r, gi = row0 + i, gk = k0 + kk;
-        ra[r] = (gi < it.M && gk < tt.K) ? tt.A[gi + (int64_t)gk * tt.lda] : T(0);
+        for (int r = 0; r < LA; ++r) ra[r] = p[(int64_t)((256 / TM) * r) * tt.lda];
+      } else {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+          const int kk = kb + (256 / TM) * r, gi = row0 + i, gk = k0 + kk;
+          ra[r] = (gi < it.M && gk < tt.K) ? tt.A[gi + (int64_t)gk * tt.lda] : T(0);
+        }
       }
     } else {
       const int kk = tid & 15, ib = tid >> 4;
+      const T* p = tt.A + (k0 + kk) + (int64_t)(row0 + ib) * tt.lda;
+      if (rows_in && kin) {
 #pragma unroll
-      for (int r = 0; r < LA; ++r) {
-        const int i = ib + 16 * r, gi = row0 + i, gk = k0 + kk;
-        ra[r] = (gi < it.M && gk < tt.K) ? tt.A[gk + (int64_t)gi * tt.lda] : T(0);
+        for (int r = 0; r < LA; ++r) ra[r] = p[(int64_t)(16 * r) * tt.lda];
+      } else {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+          const int i = ib + 16 * r, gi = row0 + i, gk = k0 + kk;
+          ra[r] = (gi < it.M && gk < tt.K) ? tt.A[gk + (int64_t)gi * tt.lda] : T(0);
+        }
       }
     }
     if (!(tt.flags & 2)) {
       const int kk = tid & 15, jb = tid >> 4;
+      const T* p = tt.B + (k0 + kk) + (int64_t)(col0 + jb) * tt.ldb;
+      if (cols_in && kin) {
 #pragma unroll
-      for (int r = 0; r < LB; ++r) {
-        const int j = jb + 16 * r, gj = col0 + j, gk = k0 + kk;
-        rb[r] = (gj < it.N && gk < tt.K) ? tt.B[gk + (int64_t)gj * tt.ldb] : T(0);
+        for (int r = 0; r < LB; ++r) rb[r] = p[(int64_t)(16 * r) * tt.ldb];
+      } else {
+#pragma unroll
+        for (int r = 0; r < LB; ++r) {
+          const int j = jb + 16 * r, gj = col0 + j, gk = k0 + kk;
+          rb[r] = (gj < it.N && gk < tt.K) ? tt.B[gk + (int64_t)gj * tt.ldb] : T(0);
+        }
       }
     } else {
       const int j = tid % TN, kb = tid / TN;
+      const T* p = tt.B + (col0 + j) + (int64_t)(k0 + kb) * tt.ldb;
+      if (cols_in && kin) {
 #pragma unroll
-      for (int r = 0; r < LB; ++r) {
-        const int kk = kb + (256 / TN) * r, gj = col0 + j, gk = k0 + kk;
-        rb[r] = (gj < it.N && gk < tt.K) ? tt.B[gj + (int64_t)gk * tt.ldb] : T(0);
+        for (int r = 0; r < LB; ++r) rb[r] = p[(int64_t)((256 / TN) * r) * tt.ldb];
+      } else {
+#pragma unroll
+        for (int r = 0; r < LB; ++r) {
+          const int kk = kb + (256 / TN) * r, gj = col0 + j, gk = k0 + kk;
+          rb[r] = (gj < it.N && gk < tt.K) ? tt.B[gj + (int64_t)gk * tt.ldb] : T(0);
+        }
       }
     }
   };
-  auto store = [&](int t) {
+  auto store = [&](int t, int buf) {
     const GemmTerm<T>& tt = terms[t];
     if (!(tt.flags & 1)) {
       const int i = tid % TM, kb = tid / TM;
 #pragma unroll
-      for (int r = 0; r < LA; ++r) As[kb + (256 / TM) * r][i] = ra[r];
+      for (int r = 0; r < LA; ++r) As[buf][kb + (256 / TM) * r][i] = ra[r];
     } else {
       const int kk = tid & 15, ib = tid >> 4;
 #pragma unroll
-      for (int r = 0; r < LA; ++r) As[kk][ib + 16 * r] = ra[r];
+      for (int r = 0; r < LA; ++r) As[buf][kk][ib + 16 * r] = ra[r];
     }
     if (!(tt.flags & 2)) {
       const int kk = tid & 15, jb = tid >> 4;
 #pragma unroll
-      for (int r = 0; r < LB; ++r) Bs[kk][jb + 16 * r] = rb[r];
+      for (int r = 0; r < LB; ++r) Bs[buf][kk][jb + 16 * r] = rb[r];
     } else {
       const int j = tid % TN, kb = tid / TN;
 #pragma unroll
-      for (int r = 0; r < LB; ++r) Bs[kb + (256 / TN) * r][j] = rb[r];
+      for (int r = 0; r < LB; ++r) Bs[buf][kb + (256 / TN) * r][j] = rb[r];
     }
   };
-  // flattened (term, k0) sequence of K tiles
   int t = it.t0;
   const int tend = it.t0 + it.nt;
   while (t < tend && terms[t].K <= 0) ++t;
   if (t < tend) {
-    int k0 = 0;
+    int k0 = 0, cur = 0;
     load(t, k0);
+    store(t, 0);
+    __syncthreads();
     for (;;) {
-      __syncthreads();
-      store(t);
-      __syncthreads();
-      // advance to the next tile and prefetch it while this one is consumed
       int tn = t, kn = k0 + 16;
       if (kn >= terms[tn].K) {
         kn = 0;
@@ -229,20 +258,34 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<TC>* __restric
       }
       const bool more = tn < tend;
       if (more) load(tn, kn);
+      T av[2][BM], bv[2][BN];
+      {
+        const int kk = lane >> 4;
+#pragma unroll
+        for (int a = 0; a < BM; ++a) av[0][a] = As[cur][kk][(TM / 2) * wr + 16 * a + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < BN; ++b) bv[0][b] = Bs[cur][kk][(TN / 2) * wc + 16 * b + (lane & 15)];
+      }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int kk = 4 * s + (lane >> 4);
-        T av[BM], bv[BN];
+        if (s < 3) {
+          const int kk = 4 * (s + 1) + (lane >> 4);
 #pragma unroll
-        for (int a = 0; a < BM; ++a) av[a] = As[kk][(TM / 2) * wr + 16 * a + (lane & 15)];
+          for (int a = 0; a < BM; ++a)
+            av[(s + 1) & 1][a] = As[cur][kk][(TM / 2) * wr + 16 * a + (lane & 15)];
 #pragma unroll
-        for (int b = 0; b < BN; ++b) bv[b] = Bs[kk][(TN / 2) * wc + 16 * b + (lane & 15)];
+          for (int b = 0; b < BN; ++b)
+            bv[(s + 1) & 1][b] = Bs[cur][kk][(TN / 2) * wc + 16 * b + (lane & 15)];
+        }
 #pragma unroll
         for (int a = 0; a < BM; ++a)
 #pragma unroll
-          for (int b = 0; b < BN; ++b) acc[a][b] = Mfma<T>::mac(av[a], bv[b], acc[a][b]);
+          for (int b = 0; b < BN; ++b) acc[a][b] = Mfma<T>::mac(av[s & 1][a], bv[s & 1][b], acc[a][b]);
       }
       if (!more) break;
+      store(tn, cur ^ 1);
+      __syncthreads();
+      cur ^= 1;
       t = tn;
       k0 = kn;
     }

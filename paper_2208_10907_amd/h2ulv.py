@@ -39,6 +39,7 @@ EXPORTS = [
     "h2ulv_rankmodel_destroy", "h2ulv_rankmodel_set_params", "h2ulv_rankmodel_get_params",
     "h2ulv_rankmodel_forward", "h2ulv_rankmodel_gradient", "h2ulv_rankmodel_adam_step",
     "h2ulv_rankmodel_train", "h2ulv_get_features", "h2ulv_get_sketch_info",
+    "h2ulv_release_cache",
 ]
 
 NFEAT = 16
@@ -131,6 +132,7 @@ def lib() -> C.CDLL:
         "h2ulv_rankmodel_train": (i32, [vp, vp, vp, i64, i32, C.c_float, P(C.c_float), vp]),
         "h2ulv_get_features": (i32, [vp, i32, vp, vp]),
         "h2ulv_get_sketch_info": (i32, [vp, i32, vp, vp, vp]),
+        "h2ulv_release_cache": (i32, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -363,6 +365,11 @@ class Factor:
         if mm:
             _check(lib().h2ulv_get_basis(self._h, lev, box, out.ctypes.data_as(C.c_void_p)))
         return out
+
+
+def release_cache() -> None:
+    """Hand the library's cached device memory back to the runtime."""
+    _check(lib().h2ulv_release_cache())
 
 
 def factorize(points, params: Params | None = None, stream=None, **kw) -> Factor:
