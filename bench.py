@@ -2,12 +2,14 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--form fp64|mixed|predicted|mixed+predicted]
-                    [--no-reference] [--no-cpu-baseline]
+                    [--refine gmres|classical] [--no-reference] [--no-cpu-baseline]
 
 One step = factorize the workload's kernel matrix, then solve its right-hand
 sides with iterative refinement (exact float64 matvec) down to a relative
-residual of 1e-10.  Points and right-hand sides are resident on the GPU before
-the timed region.  Prints one JSON line.
+residual of 1e-10; by default the correction equation is solved by GMRES
+preconditioned with the ULV solve (--refine classical: x += solve(b - A x)).
+Points and right-hand sides are resident on the GPU before the timed region.
+Prints one JSON line.
 
 Forms: fp64 (the plain method), mixed (FP32 products where the method allows),
 predicted (bases from sketches sized by the learned rank model), and both
@@ -142,6 +144,8 @@ def main() -> int:
     ap.add_argument("--form", default="mixed+predicted",
                     choices=["fp64", "mixed", "predicted", "mixed+predicted"])
     ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--refine", default="gmres", choices=["gmres", "classical"],
+                    help="correction solver of the refinement (both forms use the same)")
     ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--window-file", default=None,
@@ -176,7 +180,10 @@ def main() -> int:
         f = H.factorize(pts, params)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        x, iters, rel = f.refine(b, rtol=args.rtol, max_iter=60)
+        if args.refine == "gmres":
+            x, iters, rel = f.refine_gmres(b, rtol=args.rtol, max_iter=60, restart=30)
+        else:
+            x, iters, rel = f.refine(b, rtol=args.rtol, max_iter=60)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         st = f.stats()
@@ -251,6 +258,7 @@ def main() -> int:
         "dtype": "f32+f64" if "mixed" in args.form else "f64",
         "data": "synthetic",
         "config": {"workload": describe(prob), "form": args.form, "refine_rtol": args.rtol,
+                   "refine": args.refine,
                    "value_flops": "plain FP64 method" if ref else "this form"},
         "factor_s": round(last["factor_s"], 4),
         "refine_s": round(last["refine_s"], 4),

@@ -172,6 +172,24 @@ h2ulv_status h2ulv_refine(const h2ulv_factor* f, const double* b, int64_t ldb, d
                           int64_t ldx, int32_t nrhs, double rtol, int32_t max_iter,
                           int32_t* iters, double* relres, void* stream);
 
+/*
+ * The refinement's correction equation solved by restarted GMRES, right-
+ * preconditioned by the ULV solve: x0 = solve(b); each step applies one solve
+ * and one exact matvec (as a classical refinement step does) and keeps the best
+ * correction in the Krylov space; after at most `restart` (1..30) steps the
+ * correction is added and the true residual is recomputed with the exact
+ * matvec; stop when max_c |r_c| / |b_c| <= rtol.  Right-hand sides are solved
+ * one after another.
+ *   iters  host (may be NULL): Krylov steps taken (largest over the columns).
+ *   relres host (may be NULL): final max relative residual.
+ * Synchronises the stream once per step.  Device scratch: (2 restart + 3) n doubles.
+ * Errors: INVALID_ARG, NOT_CONVERGED (after max_iter steps; x holds the last
+ * iterate), HIP, OOM.
+ */
+h2ulv_status h2ulv_refine_gmres(const h2ulv_factor* f, const double* b, int64_t ldb, double* x,
+                                int64_t ldx, int32_t nrhs, double rtol, int32_t max_iter,
+                                int32_t restart, int32_t* iters, double* relres, void* stream);
+
 /* Statistics of a factor (host).  Synchronises nothing. */
 h2ulv_status h2ulv_get_stats(const h2ulv_factor* f, h2ulv_stats* s);
 

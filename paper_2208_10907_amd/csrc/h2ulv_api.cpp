@@ -220,6 +220,131 @@ static h2ulv_status refine_impl(const h2ulv_factor& F, const double* b, int64_t 
   return H2ULV_ERR_NOT_CONVERGED;
 }
 
+// Restarted GMRES on A x = b, right-preconditioned by the ULV solve (the
+// correction equation of iterative refinement solved in a Krylov space): the
+// same two operations per step as classical refinement (one exact matvec, one
+// solve), but the correction is the best one in the space they span.  Arnoldi
+// with classical Gram-Schmidt applied twice; Givens rotations give the residual
+// estimate; every restart recomputes the true residual with the exact matvec.
+static h2ulv_status gmres_impl(const h2ulv_factor& F, const double* b, int64_t ldb, double* x,
+                               int64_t ldx, int nrhs, double rtol, int max_iter, int restart,
+                               int32_t* iters, double* relres, hipStream_t s) {
+  const int64_t n = F.n;
+  const int m = std::max(1, std::min(restart, 30));
+  constexpr int NBLK = 256;
+  DBuf Vb((int64_t)(m + 1) * n * sizeof(double)), Zb((int64_t)m * n * sizeof(double)),
+      wb(n * sizeof(double)), rb(n * sizeof(double)), part((int64_t)NBLK * 32 * sizeof(double)),
+      hd(3 * 32 * sizeof(double)), ys(32 * sizeof(double)), nr(2 * sizeof(double));
+  double* V = Vb.as<double>();
+  double* Z = Zb.as<double>();
+  double* w = wb.as<double>();
+  double* r = rb.as<double>();
+  double* h1 = hd.as<double>();
+  double* h2 = h1 + 32;
+  double* hn = h1 + 64;
+  int worst_it = 0;
+  double worst_rel = 0.0;
+  bool converged_all = true;
+  for (int c = 0; c < nrhs; ++c) {
+    const double* bc = b + (int64_t)c * ldb;
+    double* xc = x + (int64_t)c * ldx;
+    // x0 = M^-1 b
+    H2ULV_HIP(hipMemcpyAsync(xc, bc, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    solve_impl(F, xc, 1, n, s);
+    int steps = 0;
+    double rel = 0.0, bnorm = 0.0;
+    bool done = false;
+    for (;;) {
+      // true residual r = b - A x
+      matvec_impl(F, xc, n, w, n, 1, s);
+      launch_resid_norms(bc, ldb, w, n, r, n, n, 1, nr.as<double>(), nr.as<double>() + 1, s);
+      double hv[2];
+      H2ULV_HIP(hipMemcpyAsync(hv, nr.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      H2ULV_HIP(hipStreamSynchronize(s));
+      bnorm = std::sqrt(hv[1]);
+      const double beta = std::sqrt(hv[0]);
+      rel = bnorm > 0 ? beta / bnorm : beta;
+      if (rel <= rtol) {
+        done = true;
+        break;
+      }
+      if (steps >= max_iter) break;
+      // Arnoldi from v0 = r / |r|
+      launch_scale_inv_norm(V, r, nr.as<double>(), n, s);
+      std::vector<double> H((size_t)(m + 1) * m, 0.0), g(m + 1, 0.0), cs(m, 0.0), sn(m, 0.0);
+      g[0] = beta;
+      int j = 0;
+      while (j < m && steps < max_iter) {
+        double* vj = V + (int64_t)j * n;
+        double* zj = Z + (int64_t)j * n;
+        H2ULV_HIP(hipMemcpyAsync(zj, vj, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        solve_impl(F, zj, 1, n, s);
+        matvec_impl(F, zj, n, w, n, 1, s);
+        ++steps;
+        // w -= V h, twice (classical Gram-Schmidt with re-orthogonalisation)
+        for (int pass = 0; pass < 2; ++pass) {
+          double* hp = pass == 0 ? h1 : h2;
+          launch_multidot(V, n, j + 1, w, n, part.as<double>(), NBLK, hp, s);
+          Stage st(s);
+          GemmBatch<double> gb;
+          gb.one(w, n, (int)n, 1, j + 1, V, n, false, hp, j + 1, false, -1.0, 1.0);
+          gb.run(st);
+          st.sync();
+        }
+        launch_multidot(w, n, 1, w, n, part.as<double>(), NBLK, hn, s);
+        launch_scale_inv_norm(V + (int64_t)(j + 1) * n, w, hn, n, s);
+        H2ULV_HIP(hipGetLastError());
+        std::vector<double> hh(65);
+        H2ULV_HIP(hipMemcpyAsync(hh.data(), h1, 65 * sizeof(double), hipMemcpyDeviceToHost, s));
+        H2ULV_HIP(hipStreamSynchronize(s));
+        // column j of the Hessenberg matrix
+        double* col = H.data() + (size_t)j * (m + 1);
+        for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[32 + i];
+        col[j + 1] = std::sqrt(std::max(hh[64], 0.0));
+        for (int i = 0; i < j; ++i) {
+          const double a0 = col[i], a1 = col[i + 1];
+          col[i] = cs[i] * a0 + sn[i] * a1;
+          col[i + 1] = -sn[i] * a0 + cs[i] * a1;
+        }
+        const double den = std::hypot(col[j], col[j + 1]);
+        cs[j] = den > 0 ? col[j] / den : 1.0;
+        sn[j] = den > 0 ? col[j + 1] / den : 0.0;
+        col[j] = den;
+        col[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++j;
+        // stop early when the estimate is well below the target, or on breakdown
+        if (std::fabs(g[j]) <= 0.5 * rtol * bnorm || hh[64] <= 0.0) break;
+      }
+      // y = R^-1 g, x += Z y
+      std::vector<double> y(j, 0.0);
+      for (int i = j - 1; i >= 0; --i) {
+        double sacc = g[i];
+        for (int l = i + 1; l < j; ++l) sacc -= H[(size_t)l * (m + 1) + i] * y[l];
+        const double d = H[(size_t)i * (m + 1) + i];
+        y[i] = d != 0.0 ? sacc / d : 0.0;
+      }
+      H2ULV_HIP(hipMemcpyAsync(ys.p, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+      {
+        Stage st(s);
+        GemmBatch<double> gb;
+        gb.one(xc, n, (int)n, 1, j, Z, n, false, ys.as<double>(), std::max(j, 1), false, 1.0, 1.0);
+        gb.run(st);
+        st.sync();
+      }
+    }
+    worst_it = std::max(worst_it, steps);
+    worst_rel = std::max(worst_rel, rel);
+    converged_all = converged_all && done;
+  }
+  if (iters) *iters = worst_it;
+  if (relres) *relres = worst_rel;
+  if (converged_all) return H2ULV_OK;
+  g_last_error = "GMRES refinement did not reach the tolerance";
+  return H2ULV_ERR_NOT_CONVERGED;
+}
+
 template <class Fn>
 static h2ulv_status guarded(Fn&& fn) {
   try {
@@ -337,6 +462,23 @@ h2ulv_status h2ulv_refine(const h2ulv_factor* f, const double* b, int64_t ldb, d
     CacheScope cs;
     out = refine_impl(*f, b, ldb, x, ldx, nrhs, rtol, max_iter, iters, relres,
                       (hipStream_t)stream);
+  });
+  return st != H2ULV_OK ? st : out;
+}
+
+h2ulv_status h2ulv_refine_gmres(const h2ulv_factor* f, const double* b, int64_t ldb, double* x,
+                                int64_t ldx, int32_t nrhs, double rtol, int32_t max_iter,
+                                int32_t restart, int32_t* iters, double* relres, void* stream) {
+  if (!f || !b || !x || nrhs < 1 || ldb < f->n || ldx < f->n || !(rtol >= 0) || max_iter < 0 ||
+      restart < 1) {
+    g_last_error = "bad GMRES arguments";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  h2ulv_status out = H2ULV_OK;
+  h2ulv_status st = guarded([&] {
+    CacheScope cs;
+    out = gmres_impl(*f, b, ldb, x, ldx, nrhs, rtol, max_iter, restart, iters, relres,
+                     (hipStream_t)stream);
   });
   return st != H2ULV_OK ? st : out;
 }

@@ -148,6 +148,10 @@ void launch_convert_f2d(const float* src, double* dst, int64_t count, hipStream_
 void launch_resid_norms(const double* b, int64_t ldb, const double* ax, int64_t ldax, double* r,
                         int64_t ldr, int64_t n, int nrhs, double* rnorm2, double* bnorm2,
                         hipStream_t s);
+void launch_multidot(const double* V, int64_t ldv, int k, const double* w, int64_t n,
+                     double* partial, int nblk, double* out, hipStream_t s);
+void launch_scale_inv_norm(double* dst, const double* src, const double* nrm2, int64_t n,
+                           hipStream_t s);
 void launch_axpy_cols(double* x, int64_t ldx, const double* d, int64_t ldd, int64_t n, int nrhs,
                       hipStream_t s);
 void launch_permute_rows(const double* src, int64_t lds, double* dst, int64_t ldd,

@@ -1191,6 +1191,68 @@ void launch_axpy_cols(double* x, int64_t ldx, const double* d, int64_t ldd, int6
                      n);
 }
 
+// Several dot products with one vector: partial[b k + c] = sum over the rows of
+// block b of V(r, c) w(r), c < k <= 32 (grid-stride rows, fixed block count),
+// then out[c] = sum over blocks in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void multidot_kernel(const double* __restrict__ V, int64_t ldv,
+                                                       int k, const double* __restrict__ w,
+                                                       int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[4][32];
+  double acc[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) acc[c] = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) {
+    const double wr = w[r];
+#pragma unroll
+    for (int c = 0; c < 32; ++c)
+      if (c < k) acc[c] = fma(V[r + c * ldv], wr, acc[c]);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 32; ++c)
+    if (c < k) {
+      const double v = wave_sum(acc[c]);
+      if (lane == 0) sh[wv][c] = v;
+    }
+  __syncthreads();
+  if ((int)threadIdx.x < k)
+    partial[(int64_t)blockIdx.x * k + threadIdx.x] =
+        (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+}
+
+__global__ void multidot_sum_kernel(const double* __restrict__ partial, int nblk, int k,
+                                    double* __restrict__ out) {
+  const int c = threadIdx.x;
+  if (c >= k) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * k + c];
+  out[c] = s;
+}
+
+void launch_multidot(const double* V, int64_t ldv, int k, const double* w, int64_t n,
+                     double* partial, int nblk, double* out, hipStream_t s) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(multidot_kernel, dim3(nblk), dim3(256), 0, s, V, ldv, k, w, n, partial);
+  hipLaunchKernelGGL(multidot_sum_kernel, dim3(1), dim3(32), 0, s, partial, nblk, k, out);
+}
+
+// dst = src / sqrt(nrm2[0])  (dst = src when nrm2[0] is zero)
+__global__ void scale_inv_norm_kernel(double* __restrict__ dst, const double* __restrict__ src,
+                                      const double* __restrict__ nrm2, int64_t n) {
+  const double d = nrm2[0];
+  const double f = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i] * f;
+}
+
+void launch_scale_inv_norm(double* dst, const double* src, const double* nrm2, int64_t n,
+                           hipStream_t s) {
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(scale_inv_norm_kernel, dim3((unsigned)g), dim3(256), 0, s, dst, src, nrm2, n);
+}
+
 // dst[t] = src[perm[t]] (inverse = 0) or dst[perm[t]] = src[t] (inverse = 1)
 __global__ void permute_kernel(const double* src, int64_t lds, double* dst, int64_t ldd,
                                const int64_t* perm, int64_t n, int inverse) {

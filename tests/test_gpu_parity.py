@@ -133,6 +133,29 @@ def test_matvec_exact(kernel, n, nrhs):
         assert np.linalg.norm(y[:, c] - yo[:, c]) / np.linalg.norm(yo[:, c]) < 1e-14, c
 
 
+def test_refine_gmres_matches_refinement():
+    """GMRES-accelerated refinement reaches the same 1e-10 residual in no more
+    steps than classical refinement, with the same solution; a too small step
+    budget reports NOT_CONVERGED."""
+    X = W.cube_points(4000, 6)
+    op = O.Params(leaf=64, tol=1e-4, far_sample=32)
+    fg = H.factorize(X, _params(op))
+    b = torch.tensor(W.gaussian_rhs(4000, 3, 8), device="cuda")
+    x1, it1, rel1 = fg.refine(b, rtol=1e-10, max_iter=40)
+    x2, it2, rel2 = fg.refine_gmres(b, rtol=1e-10, max_iter=40, restart=20)
+    assert rel1 <= 1e-10 and rel2 <= 1e-10
+    assert it2 <= it1
+    assert torch.linalg.norm(x1 - x2) / torch.linalg.norm(x1) < 1e-8
+    # against the oracle's matrix: the residual is a property of any size
+    r = O.matvec_exact(X, x2.cpu().numpy(), op) - b.cpu().numpy()
+    assert np.linalg.norm(r) / np.linalg.norm(b.cpu().numpy()) < 1e-9
+    x3, it3, rel3 = fg.refine_gmres(b, rtol=1e-14, max_iter=2, raise_on_fail=False)
+    assert it3 <= 3 and rel3 > 1e-14
+    with pytest.raises(H.H2ULVError) as e:
+        fg.refine_gmres(b, rtol=1e-14, max_iter=2)
+    assert e.value.status == H.ERR_NOT_CONVERGED
+
+
 def test_refine_and_not_converged():
     X = W.cube_points(4000, 6)
     op = O.Params(leaf=64, tol=1e-4, far_sample=32)
