@@ -231,7 +231,15 @@ def main() -> int:
     work = ref["flops"] if ref else st["flops"]
     value = work / (ms / 1e3) / 1e9
 
-    gemms = {k: v for k, v in prof.items() if k in PEAK_TFLOPS}
+    # the GEMM profile is split by call site ("gemm_f64:<site>"): one kernel, summed
+    gemms = {}
+    for k, v in prof.items():
+        base = k.split(":")[0]
+        if base in PEAK_TFLOPS:
+            a = gemms.setdefault(base, {"launches": 0, "time_ms": 0.0, "flops": 0.0})
+            a["launches"] += v["launches"]
+            a["time_ms"] += v["time_ms"]
+            a["flops"] += v["flops"]
     dom = max(gemms, key=lambda k: gemms[k]["time_ms"]) if gemms else None
     roof = None
     if dom:

@@ -48,7 +48,8 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.linalg as sla
 
-from .rank_model import forward as mlp_forward, gaussian_matrix, predicted_rank, sketch_size
+from .rank_model import (STREAM_FAR, STREAM_FILL, forward as mlp_forward, point_rows,
+                         predicted_rank, sketch_size)
 
 # status codes (identical numbering to the C-ABI)
 OK = 0
@@ -373,10 +374,19 @@ def box_features(X, tree: Tree, near, far, lev: int, i: int, m: int, ntargets: i
     return f.astype(np.float32)
 
 
-def sketch_row_id(M: np.ndarray, ell: int, tol: float, cap_eff: int, seed: int, lev: int,
-                  box: int):
-    """Row ID of M (m x n) from Y = M Omega, Omega = the box's n x (ell + q)
-    Gaussian matrix: column-pivoted QR of the first ell columns of Y (as rows of
+def sketch_matrix(p: Params, lev: int, fcols, targets, P, npts: int, cols: int) -> np.ndarray:
+    """Omega of one box (columns of M' x cols): the far-stream rows of its far-field
+    points, then the fill-stream rows of the candidate points of every fill target
+    (the order of M''s columns)."""
+    parts = [point_rows(p.sketch_seed, lev, STREAM_FAR, fcols, npts, cols)]
+    for j in targets:
+        parts.append(point_rows(p.sketch_seed, lev, STREAM_FILL, P[lev][j], npts, cols))
+    return np.concatenate(parts, axis=0)
+
+
+def sketch_row_id(M: np.ndarray, ell: int, tol: float, cap_eff: int, Om: np.ndarray):
+    """Row ID of M (m x n) from Y = M Omega, Omega (n x (ell + q)) Gaussian with
+    rows keyed by point: column-pivoted QR of the first ell columns of Y (as rows of
     Y^T), k = leading pivots with |R_tt| > tol |R_00| (at most cap_eff and ell).
     The last q columns G of Omega probe the error: with Z = M G,
       res = Z[piv[k:]] - E^T Z[piv[:k]],  E = R11^-1 R12,
@@ -386,9 +396,7 @@ def sketch_row_id(M: np.ndarray, ell: int, tol: float, cap_eff: int, seed: int, 
     row norms of M estimated by those of Z.
     Returns (accepted, k, piv, Wp, absdiag)."""
     m, n = M.shape
-    q = SKETCH_PROBES
-    Om = gaussian_matrix(seed, lev, box, n, ell + q)
-    Yt = Om.T @ M.T
+    Yt = Om[:, :ell + SKETCH_PROBES].T @ M.T
     Ys, Zt = Yt[:ell], Yt[ell:]
     qr, jpvt, tau, work, info = sla.lapack.dgeqp3(np.asfortranarray(Ys.copy()))
     piv = np.asarray(jpvt, dtype=np.int64) - 1
@@ -567,10 +575,13 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                     flops["fill"] += 2.0 * m[k] ** 2 * m[j]
         fac.cand[lev] = Pl
         bf = [None] * nb
+        first_attempts, retries = [], []
         todo = range(nb) if (level_stop is None or lev != level_stop or boxes is None) else sorted(boxes)
         for i in todo:
-            # F_ij for every reachable j
+            # F_ij for every reachable j (its flops are counted below, unless the
+            # basis comes from a sketch, which forms M' Omega without F)
             Fcols = []
+            fl_F = 0.0
             targets = fill_targets(near[lev], i)
             for j in targets:
                 F = np.zeros((m[i], m[j]))
@@ -578,7 +589,7 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                     if k == i or k == j or j not in near[lev][k]:
                         continue
                     F += D[i, k] @ Y[k, j]
-                    flops["fill"] += 2.0 * m[i] * m[k] * m[j]
+                    fl_F += 2.0 * m[i] * m[k] * m[j]
                 Fcols.append(F)
             Fi = np.concatenate(Fcols, axis=1) if Fcols else np.zeros((m[i], 0))
             if lev < L and m[i] > 0:
@@ -604,6 +615,19 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                 ratio = (c1.k + c2.k) / (c1.m + c2.m) if c1.m + c2.m > 0 else 0.0
             feat = box_features(X, tree, near, far, lev, i, m[i], len(targets), ncol, p, ratio)
             khat, ell, state = -1, 0, 0
+
+            def attempt(width):
+                # M' Omega as formed without F: the far part K(P_i, far) Omega_far
+                # (basis) and the fill part sum_k Z'_ik Q_k (fill; the Q_k are
+                # shared by the level and counted after the loop)
+                cols = width + SKETCH_PROBES
+                flops["basis"] += 2.0 * len(fcols) * m[i] * cols
+                for k in near[lev][i]:
+                    if k != i and m[k] > 0:
+                        flops["fill"] += 2.0 * cols * m[k] * m[i]
+                Om = sketch_matrix(p, lev, fcols, targets, P, X.shape[0], cols)
+                return sketch_row_id(M, width, p.tol, cap_eff, Om)
+
             if p.rank_model is not None:
                 y = mlp_forward(np.asarray(p.rank_model, dtype=np.float32), feat[None, :],
                                 dtype=np.float32)[0][0]
@@ -613,22 +637,21 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                 ell = min(sketch_size(khat, p.oversample), m[i] - SKETCH_PROBES)
                 if khat < ell < ncol and (p.rank_cap == 0 or ell < p.rank_cap):
                     cap_eff = min(m[i], ncol) if p.rank_cap <= 0 else min(p.rank_cap, m[i], ncol)
-                    ok, k_i, piv, Wp, dg = sketch_row_id(M, ell, p.tol, cap_eff, p.sketch_seed,
-                                                         lev, i)
+                    first_attempts.append((i, ell))
+                    ok, k_i, piv, Wp, dg = attempt(ell)
                     state = 1 if ok else 2
-                    flops["basis"] += 2.0 * ncol * m[i] * (ell + SKETCH_PROBES)
                     # a rejected sketch is retried once at full width (m - probes
                     # columns) before the full pivoted QR
                     full = m[i] - SKETCH_PROBES
                     if not ok and ell < full < ncol and (p.rank_cap == 0 or full < p.rank_cap):
                         ell = full
-                        ok, k_i, piv, Wp, dg = sketch_row_id(M, ell, p.tol, cap_eff,
-                                                             p.sketch_seed, lev, i)
+                        retries.append((i, ell))
+                        ok, k_i, piv, Wp, dg = attempt(ell)
                         state = 3 if ok else 2
-                        flops["basis"] += 2.0 * ncol * m[i] * (ell + SKETCH_PROBES)
                 else:
                     ell = 0
             if state not in (1, 3):
+                flops["fill"] += fl_F
                 k_i, piv, Wp, dg = row_id(M, p.tol, p.rank_cap)
                 flops["basis"] += 2.0 * ncol * m[i] ** 2 - 2.0 / 3.0 * min(ncol, m[i]) ** 3 if ncol >= m[i] else 2.0 * m[i] * ncol ** 2 - 2.0 / 3.0 * ncol ** 3
             if lev < L and m[i] > 0:
@@ -644,6 +667,18 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
             flops["basis"] += 4.0 * m[i] * k_i * k_i + 4.0 * m[i] ** 2 * k_i
             bf[i] = BoxFactor(m[i], k_i, U, T, np.asarray(Pl[i])[piv[:k_i]], piv, absdiag=dg,
                               feat=feat, khat=khat, ell=ell, sketch=state)
+        # shared sketch blocks Q_k = sum_{j in Near(k), j != k} D_kj Omega_fill[P_j] for
+        # every box k next to a sketched box, as wide as the widest sketch of the
+        # pass (first attempts, then full-width retries)
+        for att in (first_attempts, retries):
+            if not att:
+                continue
+            cols = max(w for _, w in att) + SKETCH_PROBES
+            ks = {k for i, _ in att for k in near[lev][i] if k != i and m[k] > 0}
+            for k in ks:
+                for j in near[lev][k]:
+                    if j != k and m[j] > 0:
+                        flops["fill"] += 2.0 * m[k] * m[j] * cols
         if level_stop is not None and lev == level_stop:
             fac.levels[lev] = bf
             fac.stats = {"flops": flops, "kevals": kevals}

@@ -9,8 +9,9 @@ Two pieces that the learned-rank variant of the shared-basis step needs:
   "Fast splittable pseudorandom number generators", OOPSLA 2014) read at an
   arbitrary position of its sequence, two outputs turned into one normal
   deviate by the Box-Muller transform (Box and Muller, 1958, cosine branch).
-  The sketch matrix of box i at level l is keyed by (seed, l, i), and its entry
-  (r, c) is deviate number c * rows + r of that key.
+  The sketch rows of a point p at level l come from one of two streams (far-field
+  columns, fill-in columns) keyed by (seed, l, stream): entry (p, c) is deviate
+  number c * N + p, so a point's rows do not depend on the box being sketched.
 
 * The multilayer perceptron that predicts a box's rank: 16 features -> three
   hidden layers of width 64 with ReLU -> one linear output, trained with the
@@ -83,13 +84,22 @@ def gaussian(key: int, idx) -> np.ndarray:
     return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
 
 
-def gaussian_matrix(seed: int, lev: int, box: int, rows: int, cols: int) -> np.ndarray:
-    """rows x cols sketch matrix of a box: entry (r, c) is deviate c * rows + r."""
-    if rows == 0 or cols == 0:
-        return np.zeros((rows, cols))
-    key = box_key(seed, lev, box)
-    idx = np.arange(rows * cols, dtype=np.uint64)
-    return gaussian(key, idx).reshape(cols, rows).T.copy()
+STREAM_FAR = 0     # sketch rows of far-field columns
+STREAM_FILL = 1    # sketch rows of fill-in columns
+STREAM_BASE = 1 << 39
+
+
+def point_rows(seed: int, lev: int, stream: int, points, npts: int, cols: int) -> np.ndarray:
+    """Sketch rows of the given points (len(points) x cols): entry (r, c) is deviate
+    number c * npts + points[r] of the key of (seed, level, stream).  The rows of a
+    point do not depend on the box whose basis is sketched."""
+    points = np.asarray(points, dtype=np.int64)
+    if points.size == 0 or cols == 0:
+        return np.zeros((points.size, cols))
+    key = box_key(seed, lev, STREAM_BASE + stream)
+    c = np.arange(cols, dtype=np.uint64)[None, :]
+    idx = c * np.uint64(npts) + points.astype(np.uint64)[:, None]
+    return gaussian(key, idx.reshape(-1)).reshape(points.size, cols)
 
 
 # ---------------------------------------------------------------------------

@@ -41,7 +41,7 @@ static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, 
     double* x = st.scratch<double>(n * nrhs);
     GemmBatch<double> g;
     g.one(x, n, (int)n, nrhs, (int)n, F.root_inv.as<double>(), n, false, bt, n, false);
-    g.run(st);
+    g.run(st, "solve");
     launch_permute_rows(x, n, b, ldb, F.perm.as<int64_t>(), n, nrhs, 1, s);
     st.sync();
     return;
@@ -92,9 +92,9 @@ static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, 
                  -1.0, 1.0);
       }
     }
-    g1.run(st);
-    g2.run(st);
-    g3.run(st);
+    g1.run(st, "solve");
+    g2.run(st, "solve");
+    g3.run(st, "solve");
     // gather c^S of both children into the parent's rhs
     CopyBatch cb;
     if (lev > 1) {
@@ -121,7 +121,7 @@ static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, 
     cb.run(st);
     GemmBatch<double> g;
     g.one(x0, m0, m0, nrhs, m0, F.root_inv.as<double>(), m0, false, b0, m0, false);
-    g.run(st);
+    g.run(st, "solve");
   }
   // backward
   for (int lev = 1; lev <= L; ++lev) {
@@ -160,8 +160,8 @@ static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, 
       if (r > 0)
         g2.term(lf.U.as<double>() + lf.offU[i] + (int64_t)ki * mi, mi, false, wi, r, false, r);
     }
-    g1.run(st);
-    g2.run(st);
+    g1.run(st, "solve");
+    g2.run(st, "solve");
   }
   launch_permute_rows(bt, n, b, ldb, F.perm.as<int64_t>(), n, nrhs, 1, s);
   H2ULV_HIP(hipGetLastError());
@@ -288,7 +288,7 @@ static h2ulv_status gmres_impl(const h2ulv_factor& F, const double* b, int64_t l
           Stage st(s);
           GemmBatch<double> gb;
           gb.one(w, n, (int)n, 1, j + 1, V, n, false, hp, j + 1, false, -1.0, 1.0);
-          gb.run(st);
+          gb.run(st, "gmres");
           st.sync();
         }
         launch_multidot(w, n, 1, w, n, part.as<double>(), NBLK, hn, s);
@@ -330,7 +330,7 @@ static h2ulv_status gmres_impl(const h2ulv_factor& F, const double* b, int64_t l
         Stage st(s);
         GemmBatch<double> gb;
         gb.one(xc, n, (int)n, 1, j, Z, n, false, ys.as<double>(), std::max(j, 1), false, 1.0, 1.0);
-        gb.run(st);
+        gb.run(st, "gmres");
         st.sync();
       }
     }

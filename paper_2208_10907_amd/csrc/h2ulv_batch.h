@@ -72,6 +72,8 @@ struct Profiler {
   }
 };
 Profiler& profiler();
+// Stable name "<kernel>:<site>" for profile records.
+const char* profile_name(const char* kernel, const char* site);
 
 // RAII scope: records a start event now and a stop event when destroyed.
 struct ProfScope {
@@ -266,7 +268,8 @@ struct GemmBatch {
     term(A, lda, ta, B, ldb, tb, K);
   }
   bool empty() const { return items.empty(); }
-  void run(Stage& st) {
+  // site: label of the call site in the kernel profile ("gemm_f64:<site>")
+  void run(Stage& st, const char* site = "other") {
     std::vector<GemmItem<TC>> its;
     its.reserve(items.size());
     for (auto& it : items)
@@ -315,7 +318,9 @@ struct GemmBatch {
     auto* dt = st.up(std::move(terms));
     auto* dp = st.up(std::move(tp));
     terms.clear();
-    ProfScope ps(sizeof(T) == 8 ? "gemm_f64" : "gemm_f32", fl, by, st.s);
+    ProfScope ps(profiler().on ? profile_name(sizeof(T) == 8 ? "gemm_f64" : "gemm_f32", site)
+                               : "",
+                 fl, by, st.s);
     launch_gemm<T, TC>(di, dt, dp, nt, ni, tile, st.s);
     H2ULV_HIP(hipGetLastError());
   }

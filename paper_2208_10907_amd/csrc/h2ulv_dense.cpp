@@ -149,6 +149,14 @@ CacheScope::~CacheScope() {
   if (c.depth == 0 && unwinding) release_locked(c);
 }
 
+const char* profile_name(const char* kernel, const char* site) {
+  static std::mutex mu;
+  static std::map<std::string, std::string> names;
+  std::lock_guard<std::mutex> lk(mu);
+  std::string key = std::string(kernel) + ":" + site;
+  return names.emplace(key, key).first->second.c_str();
+}
+
 MemStats& mem_stats() {
   static MemStats ms;
   return ms;
@@ -205,8 +213,8 @@ void trsm_lower_unit(Stage& st, const std::vector<TriRhs>& sys) {
         g2.one(t.B + o + w, t.ldb, rest, t.ncols, w, t.T + (o + w) + (int64_t)o * t.ldt, t.ldt,
                false, t.X + o, t.ldx, false, -1.0, 1.0);
     }
-    g1.run(st);
-    g2.run(st);
+    g1.run(st, "trsm");
+    g2.run(st, "trsm");
   }
 }
 
@@ -253,8 +261,8 @@ void trsm_upper(Stage& st, const std::vector<TriRhs>& sys) {
         g2.one(t.B, t.ldb, o, t.ncols, w, t.T + (int64_t)o * t.ldt, t.ldt, false, t.X + o, t.ldx,
                false, -1.0, 1.0);
     }
-    g1.run(st);
-    g2.run(st);
+    g1.run(st, "trsm");
+    g2.run(st, "trsm");
   }
 }
 
@@ -309,7 +317,7 @@ void batched_lu(Stage& st, const std::vector<SqMat>& mats, int32_t* ipiv, int32_
             A + (j0 + w) + (int64_t)j0 * lda, lda, false, A + j0 + (int64_t)(j0 + w) * lda, lda,
             false, -1.0, 1.0);
     }
-    g.run(st);
+    g.run(st, "lu");
   }
 }
 
@@ -439,7 +447,7 @@ void batched_qr_R(Stage& st, const std::vector<TallQr>& ms) {
       double fl = 0;
       for (auto& a : ms)
         if (std::min(a.h, a.m) > j0) fl += 2.0 * (a.h - j0) * (double)nb * nb;
-      ProfScope ps("qr_panel", fl, 0, st.s);
+      ProfScope ps("qr_panel:tsqr", fl, 0, st.s);
       launch_qr_panel(dd, nmat, j0, nb, st.s);
     }
     H2ULV_HIP(hipGetLastError());
@@ -458,9 +466,9 @@ void batched_qr_R(Stage& st, const std::vector<TallQr>& ms) {
       g2.one(Y2b[b], nb, wd, ntr, wd, Tfb[b], nb, true, Y1b[b], nb, false);
       g3.one(At, a.lda, rows, ntr, wd, Vp, a.h, false, Y2b[b], nb, false, -1.0, 1.0);
     }
-    g1.run(st);
-    g2.run(st);
-    g3.run(st);
+    g1.run(st, "tsqr");
+    g2.run(st, "tsqr");
+    g3.run(st, "tsqr");
   }
 }
 
@@ -509,7 +517,10 @@ void batched_qr_basis(Stage& st, const std::vector<QrW>& ws) {
   const int nmat = (int)ws.size();
   MatDesc* dd = st.up(std::move(ds));
   for (int j0 = 0; j0 < maxk; j0 += nb) {
-    launch_qr_panel(dd, nmat, j0, nb, st.s);
+    {
+      ProfScope ps("qr_panel:qrbasis", 0, 0, st.s);
+      launch_qr_panel(dd, nmat, j0, nb, st.s);
+    }
     H2ULV_HIP(hipGetLastError());
     GemmBatch<double> g1, g2, g3;
     for (size_t b = 0; b < ws.size(); ++b) {
@@ -527,9 +538,9 @@ void batched_qr_basis(Stage& st, const std::vector<QrW>& ws) {
       g2.one(Y2b[b], nb, wd, ntr, wd, Tp, nb, true, Y1b[b], nb, false);
       g3.one(At, w.m, rows, ntr, wd, Vp, w.m, false, Y2b[b], nb, false, -1.0, 1.0);
     }
-    g1.run(st);
-    g2.run(st);
-    g3.run(st);
+    g1.run(st, "qrbasis");
+    g2.run(st, "qrbasis");
+    g3.run(st, "qrbasis");
   }
   // T = upper triangle of the factored W
   {
@@ -578,9 +589,9 @@ void batched_qr_basis(Stage& st, const std::vector<QrW>& ws) {
       g2.one(Y2b[b], nb, wd, rows, wd, Tp, nb, false, Y1b[b], nb, false);
       g3.one(Us, w.m, rows, rows, wd, Vp, w.m, false, Y2b[b], nb, false, -1.0, 1.0);
     }
-    g1.run(st);
-    g2.run(st);
-    g3.run(st);
+    g1.run(st, "qrbasis");
+    g2.run(st, "qrbasis");
+    g3.run(st, "qrbasis");
   }
 }
 

@@ -238,9 +238,10 @@ struct Driver {
   void dense_blocks(Stage& st, const std::vector<Prob*>& G);
   void fill_products(Stage& st, const std::vector<Prob*>& G);
   void basis_prepare(Stage& st, const std::vector<Prob*>& G);
-  // rebuild: M' of boxes whose sketch was rejected, formed a second time (its
-  // kernel entries and fill-in products are not counted again)
+  // rebuild: boxes whose sketch was rejected, sketched again at full width or
+  // given their M' (kernel entries are not counted again)
   void build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebuild = false);
+  void build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild);
   void pivot_boxes(Stage& st, const std::vector<Box>& boxes);
   std::vector<Box> check_sketches(Stage& st, const std::vector<Box>& boxes);
   void row_ids(Stage& st, const std::vector<Prob*>& G);
@@ -397,8 +398,8 @@ void Driver::fill_products(Stage& st, const std::vector<Prob*>& G) {
                    false, Zt + P->Doff[e] + k1, m[i], false);
         }
     }
-    g.run(st);
-    g2.run(st);
+    g.run(st, "fill_z");
+    g2.run(st, "fill_z");
     st.sync();
   }
   for (Prob* P : G) {
@@ -489,45 +490,222 @@ void Driver::basis_prepare(Stage& st, const std::vector<Prob*>& G) {
   }
 }
 
-// ---- (c) M'^T of each box (chunked over boxes by memory), then either its
-// tall QR -> m x m triangle, or (sketched boxes) [Y^T; Z^T] = Omega^T M'^T
+// ---- (c) sketch of M' without forming it.  Omega's rows are keyed by point:
+// far-field column p takes row p of the far stream, the fill-in columns of
+// target j take the rows G_j of j's candidates in the fill stream.  Since
+// T-hat^-1 F_ij = sum_k Z'_ik D_kj over the k next to both i and j,
+//   (M' Omega)^T = Omega_far^T K(P_i, far)^T + sum_{k in Near(i), k != i} Q_k^T Z'_ik^T,
+//   Q_k = sum_{j in Near(k), j != k} D_kj G_j,
+// and every Q_k is shared by all boxes next to k.  Q is as wide as the widest
+// sketch of the pass in its problem; box i takes its first l_i + q columns.
+void Driver::build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild) {
+  struct PS {
+    Prob* P;
+    std::vector<int> bx;
+    int C = 0;
+    std::vector<int64_t> goff, qoff;  // -1: block not needed
+  };
+  std::vector<PS> ps;
+  auto find_ps = [&](const Prob* P) -> PS* {
+    for (PS& x : ps)
+      if (x.P == P) return &x;
+    return nullptr;
+  };
+  for (const Box& b : boxes) {
+    if (!find_ps(b.P)) ps.push_back(PS{b.P, {}, 0, {}, {}});
+    find_ps(b.P)->bx.push_back(b.i);
+  }
+  int64_t gwords = 0, qwords = 0;
+  for (PS& x : ps) {
+    Prob* P = x.P;
+    const std::vector<int>& m = P->lf().m;
+    const auto& np = P->np();
+    const auto& ni = P->ni();
+    std::vector<char> needK(P->nb, 0), needJ(P->nb, 0);
+    for (int i : x.bx) {
+      x.C = std::max(x.C, P->lf().ell[i] + SKETCH_PROBES);
+      for (int64_t e = np[i]; e < np[i + 1]; ++e)
+        if (ni[e] != i && m[ni[e]] > 0) needK[ni[e]] = 1;
+    }
+    for (int k = 0; k < P->nb; ++k)
+      if (needK[k])
+        for (int64_t e = np[k]; e < np[k + 1]; ++e)
+          if (ni[e] != k && m[ni[e]] > 0) needJ[ni[e]] = 1;
+    x.goff.assign(P->nb, -1);
+    x.qoff.assign(P->nb, -1);
+    for (int j = 0; j < P->nb; ++j) {
+      if (needJ[j]) {
+        x.goff[j] = gwords;
+        gwords += (int64_t)m[j] * x.C;
+      }
+      if (needK[j]) {
+        x.qoff[j] = qwords;
+        qwords += (int64_t)m[j] * x.C;
+      }
+    }
+  }
+  DBuf Qb(std::max<int64_t>(qwords, 1) * sizeof(double));
+  double* Qp = Qb.as<double>();
+  {
+    DBuf Gb(std::max<int64_t>(gwords, 1) * sizeof(double));
+    double* Gp = Gb.as<double>();
+    std::vector<GaussItem> gi;
+    std::vector<int64_t> tp(1, 0);
+    GemmBatch<double> gq;
+    for (PS& x : ps) {
+      Prob* P = x.P;
+      const std::vector<int>& m = P->lf().m;
+      const auto& np = P->np();
+      const auto& ni = P->ni();
+      const uint64_t key = sketch_key(p.sketch_seed, P->lev, STREAM_BASE + STREAM_FILL);
+      for (int j = 0; j < P->nb; ++j) {
+        if (x.goff[j] < 0) continue;
+        gi.push_back(GaussItem{Gp + x.goff[j], m[j], P->candp(j), P->poff, P->F->n, key, m[j],
+                               x.C});
+        tp.push_back(tp.back() + tiles64(m[j], x.C));
+      }
+      for (int k = 0; k < P->nb; ++k) {
+        if (x.qoff[k] < 0) continue;
+        gq.item(Qp + x.qoff[k], m[k], m[k], x.C);
+        for (int64_t e = np[k]; e < np[k + 1]; ++e) {
+          const int j = ni[e];
+          if (j == k || m[j] == 0) continue;
+          gq.term(P->D.as<double>() + P->Doff[e], m[k], false, Gp + x.goff[j], m[j], false, m[j]);
+          P->fl_fill += 2.0 * m[k] * (double)m[j] * x.C;
+        }
+      }
+    }
+    if (!gi.empty()) {
+      const int ngi = (int)gi.size();
+      const int64_t nt = tp.back();
+      GaussItem* dgi = st.up(std::move(gi));
+      int64_t* dtp = st.up(std::move(tp));
+      ProfScope pg("gauss", 0, 0, s);
+      launch_gauss(dgi, dtp, nt, ngi, s);
+      H2ULV_HIP(hipGetLastError());
+    }
+    gq.run(st, "sketch_q");
+  }
+  // per box: K(P_i, far)^T and Omega_far, then [Y^T; Z^T] (chunked by memory)
+  std::vector<Box> order;
+  for (PS& x : ps)
+    for (int i : x.bx) order.push_back(Box{x.P, i});
+  const int64_t budget =
+      std::max<int64_t>((int64_t)(free_device_bytes() * 0.4) / (int64_t)sizeof(double), 1 << 20);
+  auto box_words = [&](const Box& b) {
+    const int64_t nf = (int64_t)b.P->farcols[b.i].size();
+    return nf * (b.P->lf().m[b.i] + b.P->lf().ell[b.i] + SKETCH_PROBES) + 4096;
+  };
+  size_t b0 = 0;
+  while (b0 < order.size()) {
+    size_t b1 = b0;
+    int64_t acc = 0;
+    while (b1 < order.size() && (b1 == b0 || acc + box_words(order[b1]) <= budget)) {
+      acc += box_words(order[b1]);
+      ++b1;
+    }
+    const size_t nc = b1 - b0;
+    std::vector<int64_t> koff(nc + 1, 0), ooff(nc + 1, 0), fc_all, fc_off(nc, 0);
+    for (size_t q = 0; q < nc; ++q) {
+      const Box& b = order[b0 + q];
+      const int64_t nf = (int64_t)b.P->farcols[b.i].size();
+      koff[q + 1] = koff[q] + nf * b.P->lf().m[b.i];
+      ooff[q + 1] = ooff[q] + nf * (b.P->lf().ell[b.i] + SKETCH_PROBES);
+      fc_off[q] = (int64_t)fc_all.size();
+      for (int64_t c : b.P->farcols[b.i]) fc_all.push_back(c + b.P->poff);
+    }
+    DBuf Kb(std::max<int64_t>(koff.back(), 1) * sizeof(double));
+    DBuf Ob(std::max<int64_t>(ooff.back(), 1) * sizeof(double));
+    const int64_t* dfc = st.up(std::move(fc_all));
+    KgenBatch kb;
+    GemmBatch<double> gs;
+    std::vector<GaussItem> gi;
+    std::vector<int64_t> tp(1, 0);
+    for (size_t q = 0; q < nc; ++q) {
+      const Box& b = order[b0 + q];
+      Prob* P = b.P;
+      const PS* x = find_ps(b.P);
+      const int i = b.i;
+      const std::vector<int>& m = P->lf().m;
+      const int mi = m[i];
+      const int ci = P->lf().ell[i] + SKETCH_PROBES;
+      const int64_t nf = (int64_t)P->farcols[i].size();
+      double* Kf = Kb.as<double>() + koff[q];
+      double* Of = Ob.as<double>() + ooff[q];
+      gs.item(P->PQ.as<double>() + P->offSq[i], ci, ci, mi);
+      if (nf > 0) {
+        kb.add(dfc + fc_off[q], (int)nf, P->candp(i), mi, Kf, nf);
+        if (!rebuild) P->kevals += (double)mi * nf;
+        gi.push_back(GaussItem{Of, nf, dfc + fc_off[q], P->poff, P->F->n,
+                               sketch_key(p.sketch_seed, P->lev, STREAM_BASE + STREAM_FAR),
+                               (int32_t)nf, ci});
+        tp.push_back(tp.back() + tiles64(nf, ci));
+        gs.term(Of, nf, true, Kf, nf, false, (int)nf);
+        P->fl_basis += 2.0 * (double)nf * mi * ci;
+      }
+      const auto& np = P->np();
+      const auto& ni = P->ni();
+      for (int64_t e = np[i]; e < np[i + 1]; ++e) {
+        const int k = ni[e];
+        if (k == i || m[k] == 0) continue;
+        gs.term(Qp + x->qoff[k], m[k], true, P->Z.as<double>() + P->Doff[e], mi, true, m[k]);
+        P->fl_fill += 2.0 * ci * (double)m[k] * mi;
+      }
+    }
+    kb.run(st, pts, kf, dup);
+    if (!gi.empty()) {
+      const int ngi = (int)gi.size();
+      const int64_t nt = tp.back();
+      GaussItem* dgi = st.up(std::move(gi));
+      int64_t* dtp = st.up(std::move(tp));
+      ProfScope pg("gauss", 0, 0, s);
+      launch_gauss(dgi, dtp, nt, ngi, s);
+      H2ULV_HIP(hipGetLastError());
+    }
+    gs.run(st, "sketch");
+    tick("c_sketch");
+    st.sync();
+    b0 = b1;
+  }
+}
+
+// ---- (c) M'^T of each remaining box (chunked over boxes by memory) and its
+// tall QR -> m x m triangle
 void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebuild) {
+  // sketched boxes never form M'; the rest get the triangle of their M'^T
+  std::vector<Box> sk, full;
+  for (const Box& b : boxes) (b.P->lf().sk_state[b.i] == 1 ? sk : full).push_back(b);
+  if (!sk.empty()) build_sketch(st, sk, rebuild);
+  if (full.empty()) return;
   const size_t freeb = free_device_bytes();
   int64_t budget = (int64_t)(freeb * 0.4) / (int64_t)sizeof(double);
   budget = std::max<int64_t>(budget, 1 << 20);
-  auto sketched = [](const Box& b) { return b.P->lf().sk_state[b.i] == 1; };
   auto box_words = [&](const Box& b) {
     const int64_t mi = b.P->lf().m[b.i], nc = b.P->ncols[b.i];
-    if (sketched(b)) return mi * nc + nc * (b.P->lf().ell[b.i] + SKETCH_PROBES) + 4096;
     // M'^T plus the QR workspaces of its chunks (reflector panels, T, GEMM scratch)
     return mi * nc * 3 / 2 + 8 * mi * mi + 4096;
   };
-  const size_t nbox = boxes.size();
+  const size_t nbox = full.size();
   size_t b0 = 0;
   while (b0 < nbox) {
     size_t b1 = b0;
     int64_t acc = 0;
-    while (b1 < nbox && (b1 == b0 || acc + box_words(boxes[b1]) <= budget)) {
-      acc += box_words(boxes[b1]);
+    while (b1 < nbox && (b1 == b0 || acc + box_words(full[b1]) <= budget)) {
+      acc += box_words(full[b1]);
       ++b1;
     }
     const size_t nc = b1 - b0;
-    // M'^T (ncols x m, column-major): far-field rows then fill-in rows; then
-    // the Gaussian matrices of the sketched boxes
-    std::vector<int64_t> moff(nc + 1, 0), ooff(nc + 1, 0);
+    // M'^T (ncols x m, column-major): far-field rows then fill-in rows
+    std::vector<int64_t> moff(nc + 1, 0);
     for (size_t q = 0; q < nc; ++q) {
-      const Box& b = boxes[b0 + q];
+      const Box& b = full[b0 + q];
       moff[q + 1] = moff[q] + (int64_t)b.P->lf().m[b.i] * b.P->ncols[b.i];
-      ooff[q + 1] = ooff[q] + (sketched(b) ? b.P->ncols[b.i] *
-                                                 (int64_t)(b.P->lf().ell[b.i] + SKETCH_PROBES)
-                                           : 0);
     }
     DBuf Mb(std::max<int64_t>(moff.back(), 1) * sizeof(double));
-    DBuf Ob(std::max<int64_t>(ooff.back(), 1) * sizeof(double));
     double* Mp = Mb.as<double>();
     std::vector<int64_t> fc_all, fc_off(nc, 0);
     for (size_t q = 0; q < nc; ++q) {
-      const Box& b = boxes[b0 + q];
+      const Box& b = full[b0 + q];
       fc_off[q] = (int64_t)fc_all.size();
       for (int64_t c : b.P->farcols[b.i]) fc_all.push_back(c + b.P->poff);
     }
@@ -535,8 +713,8 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
     KgenBatch kb;
     GemmBatch<double> g;
     for (size_t q = 0; q < nc; ++q) {
-      Prob* P = boxes[b0 + q].P;
-      const int i = boxes[b0 + q].i;
+      Prob* P = full[b0 + q].P;
+      const int i = full[b0 + q].i;
       const std::vector<int>& m = P->lf().m;
       if (m[i] == 0) continue;
       const auto& np = P->np();
@@ -545,6 +723,7 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
       const int64_t ld = P->ncols[i];
       const int64_t nf = (int64_t)P->farcols[i].size();
       kb.add(dfc + fc_off[q], (int)nf, P->candp(i), m[i], Mi, ld);
+      // a rebuilt box (a rejected sketch) has had its kernel entries counted
       if (!rebuild) P->kevals += (double)m[i] * nf;
       int64_t row = nf;
       for (int j : P->targets[i]) {
@@ -558,47 +737,15 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
             if (ekj < 0) continue;
             g.term(P->D.as<double>() + P->Doff[ekj], m[k], true, P->Z.as<double>() + P->Doff[e],
                    m[i], true, m[k]);
-            if (!rebuild) P->fl_fill += 2.0 * m[i] * (double)m[k] * m[j];
+            P->fl_fill += 2.0 * m[i] * (double)m[k] * m[j];
           }
         }
         row += m[j];
       }
     }
     kb.run(st, pts, kf, dup);
-    g.run(st);
+    g.run(st, "fill_m");
     tick("c_fill_gemm");
-    // sketched boxes: Omega (ncols x (l + q)) and [Y^T; Z^T] = Omega^T M'^T into
-    // the box's pivoted-QR matrix ((l + q) x m, leading dimension l + q)
-    {
-      std::vector<GaussItem> gi;
-      std::vector<int64_t> tp(1, 0);
-      GemmBatch<double> gs;
-      for (size_t q = 0; q < nc; ++q) {
-        const Box& b = boxes[b0 + q];
-        if (!sketched(b)) continue;
-        Prob* P = b.P;
-        const int i = b.i, mi = P->lf().m[i];
-        const int cols = P->lf().ell[i] + SKETCH_PROBES;
-        const int64_t nci = P->ncols[i];
-        double* Om = Ob.as<double>() + ooff[q];
-        gi.push_back(GaussItem{Om, nci, (int32_t)nci, cols,
-                               sketch_key(p.sketch_seed, P->lev, i)});
-        tp.push_back(tp.back() + tiles64(nci, cols));
-        gs.one(P->PQ.as<double>() + P->offSq[i], cols, cols, mi, (int)nci, Om, nci, true,
-               Mp + moff[q], nci, false);
-        P->fl_basis += 2.0 * (double)nci * mi * cols;
-      }
-      if (!gi.empty()) {
-        const int ngi = (int)gi.size();
-        const int64_t nt = tp.back();
-        GaussItem* dgi = st.up(std::move(gi));
-        int64_t* dtp = st.up(std::move(tp));
-        ProfScope ps("gauss", 0, 0, s);
-        launch_gauss(dgi, dtp, nt, ngi, s);
-        H2ULV_HIP(hipGetLastError());
-      }
-      gs.run(st);
-    }
     // tall QR of every other M'^T: a tree of blocked Householder QRs (leaf
     // chunks of 4m rows factored in place, then stacked triangles merged pairwise)
     struct Rref {
@@ -610,12 +757,12 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
     std::vector<int> mq(nc);
     std::vector<TallQr> leaf;
     for (size_t q = 0; q < nc; ++q) {
-      Prob* P = boxes[b0 + q].P;
-      const int i = boxes[b0 + q].i;
+      Prob* P = full[b0 + q].P;
+      const int i = full[b0 + q].i;
       const int mi = P->lf().m[i];
       const int64_t nci = P->ncols[i];
       mq[q] = mi;
-      if (mi == 0 || nci == 0 || sketched(boxes[b0 + q])) continue;
+      if (mi == 0 || nci == 0) continue;
       double* Mi = Mp + moff[q];
       const int64_t h = std::max<int64_t>(4 * (int64_t)mi, 256);
       for (int64_t r0 = 0; r0 < nci; r0 += h) {
@@ -681,8 +828,8 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
       std::vector<CopyItem> zl;
       for (size_t q = 0; q < nc; ++q) {
         if (cur[q].empty()) continue;
-        Prob* P = boxes[b0 + q].P;
-        const int i = boxes[b0 + q].i;
+        Prob* P = full[b0 + q].P;
+        const int i = full[b0 + q].i;
         const int mi = mq[q];
         const Rref& r = cur[q][0];
         double* PQi = P->PQ.as<double>() + P->offSq[i];
@@ -903,7 +1050,7 @@ std::vector<Box> Driver::check_sketches(Stage& st, const std::vector<Box>& boxes
     int64_t* dtp = st.up(std::move(tp));
     launch_gather_cols(dgi, dtp, nt, ngi, s);
     H2ULV_HIP(hipGetLastError());
-    g.run(st);
+    g.run(st, "probe");
     const int nni = (int)ni.size();
     NormItem* dni = st.up(std::move(ni));
     launch_norms(dni, nni, s);
@@ -1057,7 +1204,7 @@ void Driver::bases(Stage& st, const std::vector<Prob*>& G) {
   WpItem* dwi = st.up(std::move(wi));
   launch_wprime(dwi, nw, s);
   H2ULV_HIP(hipGetLastError());
-  g.run(st);
+  g.run(st, "basis");
   batched_qr_basis(st, qs);
   st.sync();
   for (Prob* P : G) {
@@ -1152,8 +1299,8 @@ void Driver::couplings(Stage& st, const std::vector<Prob*>& G) {
                  k[i], false, Tmp[g] + o, k[i], false);
         }
     }
-    g1.run(st);
-    g2.run(st);
+    g1.run(st, "couple");
+    g2.run(st, "couple");
     st.sync();
   } else {
     std::vector<DBuf> Kc32, T32, Tmp32;
@@ -1182,8 +1329,8 @@ void Driver::couplings(Stage& st, const std::vector<Prob*>& G) {
                  Tm + o, k[i], false);
         }
     }
-    g1.run(st);
-    g2.run(st);
+    g1.run(st, "couple");
+    g2.run(st, "couple");
     st.sync();
   }
 }
@@ -1243,10 +1390,10 @@ void Driver::rotations(Stage& st, const std::vector<Prob*>& G) {
           }
       }
     }
-    g1.run(st);
-    g2.run(st);
-    h1.run(st);
-    h2.run(st);
+    g1.run(st, "rotate");
+    g2.run(st, "rotate");
+    h1.run(st, "rotate");
+    h2.run(st, "rotate");
     st.sync();
   }
   // diagonal: S_ii = U_i^T D_ii U_i
@@ -1290,10 +1437,10 @@ void Driver::rotations(Stage& st, const std::vector<Prob*>& G) {
         }
       }
     }
-    g1.run(st);
-    g2.run(st);
-    h1.run(st);
-    h2.run(st);
+    g1.run(st, "rotate");
+    g2.run(st, "rotate");
+    h1.run(st, "rotate");
+    h2.run(st, "rotate");
     st.sync();
   }
   for (Prob* P : G) {
@@ -1385,7 +1532,7 @@ void Driver::elimination(Stage& st, const std::vector<Prob*>& G) {
              false, Si + ki, m[i], false);
     }
   }
-  g1.run(st);
+  g1.run(st, "elim");
   for (Prob* P : G) {
     LevelFactor& lf = P->lf();
     const std::vector<int>& m = lf.m;
@@ -1411,8 +1558,8 @@ void Driver::elimination(Stage& st, const std::vector<Prob*>& G) {
                X32p + lf.offX[i], r, false, -1.0, 1.0);
     }
   }
-  g2.run(st);
-  g3.run(st);
+  g2.run(st, "elim");
+  g3.run(st, "elim");
   st.sync();
 }
 

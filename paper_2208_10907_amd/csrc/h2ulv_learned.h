@@ -26,14 +26,24 @@ constexpr int MLP_TILE = 32;  // samples per workgroup
 // SplitMix64 (Steele, Lea, Flood 2014) read at position c of the stream that
 // starts at state `key`; Gaussian deviate number i from positions 2i, 2i+1.
 uint64_t sm64_at(uint64_t key, uint64_t c);
-uint64_t sketch_key(uint64_t seed, int lev, int box);
+// Key of stream `id` at level `lev`: position (lev << 40) | id of the seed's stream.
+uint64_t sketch_key(uint64_t seed, int lev, uint64_t id);
+// Sketch rows are keyed by point: stream STREAM_FAR for far-field columns,
+// STREAM_FILL for fill-in columns.
+constexpr uint64_t STREAM_BASE = (uint64_t)1 << 39;
+constexpr uint64_t STREAM_FAR = 0;
+constexpr uint64_t STREAM_FILL = 1;
 
-// dst(r, c) = deviate number c * rows + r of `key`   (column-major, ld)
+// dst(r, c) = deviate number c * stride + (idx[r] - sub) of `key` (column-major,
+// ld): the sketch row of point idx[r] - sub among `stride` points
 struct GaussItem {
   double* dst;
   int64_t ld;
-  int32_t rows, cols;
+  const int64_t* idx;
+  int64_t sub;
+  int64_t stride;
   uint64_t key;
+  int32_t rows, cols;
 };
 // dst(:, j) = src(:, idx[j])   (rows x cols)
 struct GatherItem {

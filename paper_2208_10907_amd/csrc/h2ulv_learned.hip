@@ -52,12 +52,12 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 
 uint64_t sm64_at(uint64_t key, uint64_t c) { return sm64_pos(key, c); }
 
-uint64_t sketch_key(uint64_t seed, int lev, int box) {
-  return sm64_pos(seed, ((uint64_t)lev << 40) | (uint64_t)box);
+uint64_t sketch_key(uint64_t seed, int lev, uint64_t id) {
+  return sm64_pos(seed, ((uint64_t)lev << 40) | id);
 }
 
 // ---------------------------------------------------------------------------
-// Gaussian sketch matrices, 64 x 64 tiles
+// Gaussian sketch rows of points, 64 x 64 tiles
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void gauss_kernel(const GaussItem* __restrict__ items,
                                                     const int64_t* __restrict__ tile_ptr,
@@ -71,7 +71,8 @@ __global__ __launch_bounds__(256) void gauss_kernel(const GaussItem* __restrict_
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int r = r0 + (e & 63), c = c0 + (e >> 6);
     if (r < it.rows && c < it.cols)
-      it.dst[r + (int64_t)c * it.ld] = gauss_at(it.key, (uint64_t)c * it.rows + r);
+      it.dst[r + (int64_t)c * it.ld] =
+          gauss_at(it.key, (uint64_t)c * (uint64_t)it.stride + (uint64_t)(it.idx[r] - it.sub));
   }
 }
 

@@ -39,11 +39,20 @@ def test_gaussian_deviates_are_standard_normal():
     assert abs(np.corrcoef(z, z2)[0, 1]) < 0.01
 
 
-def test_gaussian_matrix_layout_column_major():
-    G = R.gaussian_matrix(4, 2, 9, 5, 3)
-    key = R.box_key(4, 2, 9)
-    for r, c in [(0, 0), (4, 0), (0, 1), (3, 2)]:
-        assert G[r, c] == R.gaussian(key, np.array([c * 5 + r], dtype=np.uint64))[0]
+def test_point_rows_layout_and_independence():
+    """Entry (r, c) of a point's sketch rows is deviate c N + p of its stream; the
+    rows of a point do not depend on which other points are asked for, and the
+    far and fill streams differ."""
+    pts = np.array([7, 3, 11])
+    G = R.point_rows(4, 2, R.STREAM_FILL, pts, 20, 5)
+    key = R.box_key(4, 2, R.STREAM_BASE + R.STREAM_FILL)
+    for r, p in enumerate(pts):
+        for c in (0, 3, 4):
+            assert G[r, c] == R.gaussian(key, np.array([c * 20 + p], dtype=np.uint64))[0]
+    G2 = R.point_rows(4, 2, R.STREAM_FILL, np.array([11, 7]), 20, 5)
+    assert np.array_equal(G2, G[[2, 0]])
+    F = R.point_rows(4, 2, R.STREAM_FAR, pts, 20, 5)
+    assert not np.allclose(F, G)
 
 
 # --- MLP -----------------------------------------------------------------------
@@ -149,7 +158,8 @@ def test_sketch_row_id_exact_for_low_rank_matrix():
     skeleton rows span every row, so the interpolative decomposition is exact
     (randomized ID, Halko-Martinsson-Tropp 2011, Sec. 5.2)."""
     M = _low_rank(90, 400, 12, 4)
-    ok, k, piv, Wp, dg = O.sketch_row_id(M, 20, 1e-10, 90, 3, 1, 0)
+    Om = R.point_rows(3, 1, R.STREAM_FAR, np.arange(400), 400, 20 + O.SKETCH_PROBES)
+    ok, k, piv, Wp, dg = O.sketch_row_id(M, 20, 1e-10, 90, Om)
     assert ok and k == 12
     assert np.linalg.norm(M - Wp @ M[piv[:k]]) <= 1e-9 * np.linalg.norm(M)
     assert np.array_equal(Wp[piv[:k]], np.eye(k))
@@ -157,7 +167,8 @@ def test_sketch_row_id_exact_for_low_rank_matrix():
 
 def test_sketch_exhausted_is_rejected():
     M = _low_rank(90, 400, 30, 5)
-    ok, k, piv, Wp, dg = O.sketch_row_id(M, 16, 1e-10, 90, 3, 1, 0)
+    Om = R.point_rows(3, 1, R.STREAM_FAR, np.arange(400), 400, 16 + O.SKETCH_PROBES)
+    ok, k, piv, Wp, dg = O.sketch_row_id(M, 16, 1e-10, 90, Om)
     assert not ok and k == 16
 
 
