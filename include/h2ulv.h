@@ -278,10 +278,15 @@ h2ulv_status h2ulv_profile_read(h2ulv_kernel_profile* out, int32_t max, int32_t*
  *
  * Use in the factorization (params.rank_model != NULL).  For each box the
  * sketch size is l = min(ceil(1.25 k-hat) + oversample, m - 8).  When
- * k-hat < l < columns of M' and (rank_cap == 0 or l < rank_cap), the row ID comes from
- * the column-pivoted QR of (M' Omega)^T for the box's Gaussian matrix Omega
- * (columns of M' x l, SplitMix64 + Box-Muller keyed by sketch_seed, level and
- * box); 8 further Gaussian columns G probe its error, and the sketch is
+ * 0 < l < columns of M' and (rank_cap == 0 or l < rank_cap), the row ID comes from
+ * the column-pivoted QR of (M' Omega)^T for a Gaussian matrix Omega (columns
+ * of M' x l) whose rows are keyed by point: entry (p, c) is Box-Muller deviate
+ * number c N + p (N points) of the SplitMix64 stream at position
+ * (level << 40) | (2^39 + s) of the stream seeded by sketch_seed, s = 0 for the
+ * far-field columns and s = 1 for the fill-in columns.  M' is never formed for
+ * a sketched box: its fill part is applied as sum_k Z'_ik Q_k with
+ * Q_k = sum_j D_kj Omega_j shared by the boxes next to k.  8 further columns G
+ * of the same rows probe the error, and the sketch is
  * accepted iff it was not exhausted (k < l) and
  *   ||Z[piv[k:]] - E^T Z[piv[:k]]||_F <= 10 sqrt(m - k) tol max_j ||Z[j]||,
  * Z = M' G, E = R11^-1 R12.  A rejected sketch narrower than m - 8 is retried

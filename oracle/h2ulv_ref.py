@@ -633,9 +633,10 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                                 dtype=np.float32)[0][0]
                 khat = predicted_rank(y)
                 # the sketch never exceeds m - probes columns: a box whose
-                # predicted rank leaves no room is still sketched at full width
+                # predicted rank leaves no room (k-hat >= m - probes included) is
+                # still sketched at full width, accepted when its rank is below it
                 ell = min(sketch_size(khat, p.oversample), m[i] - SKETCH_PROBES)
-                if khat < ell < ncol and (p.rank_cap == 0 or ell < p.rank_cap):
+                if 0 < ell < ncol and (p.rank_cap == 0 or ell < p.rank_cap):
                     cap_eff = min(m[i], ncol) if p.rank_cap <= 0 else min(p.rank_cap, m[i], ncol)
                     first_attempts.append((i, ell))
                     ok, k_i, piv, Wp, dg = attempt(ell)

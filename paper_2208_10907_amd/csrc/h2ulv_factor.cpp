@@ -479,10 +479,11 @@ void Driver::basis_prepare(Stage& st, const std::vector<Prob*>& G) {
       lf.khat[i] = std::max(0, (int)kh);
       const int mi = lf.m[i];
       // at most m - probes columns: a box whose predicted rank leaves no room
-      // is still sketched at full width
+      // (k-hat >= m - probes included) is still sketched at full width, which
+      // the probe check accepts whenever its true rank is below that width
       const int64_t ell = std::min<int64_t>((5 * (int64_t)lf.khat[i] + 3) / 4 + p.oversample,
                                             mi - SKETCH_PROBES);
-      if (lf.khat[i] < ell && ell < P->ncols[i] && (p.rank_cap == 0 || ell < p.rank_cap)) {
+      if (ell > 0 && ell < P->ncols[i] && (p.rank_cap == 0 || ell < p.rank_cap)) {
         lf.ell[i] = (int)ell;
         lf.sk_state[i] = 1;
       }
@@ -891,6 +892,8 @@ void Driver::pivot_boxes(Stage& st, const std::vector<Box>& boxes) {
     double* A = P->PQ.as<double>() + P->offSq[i];
     Job jb{P, i, rows, lda, -1};
     if (mi <= BIG) {
+      // the one-workgroup kernel holds at most 512 rows and columns
+      if (rows > BIG) fail(H2ULV_ERR_HIP, "internal: pivoted-QR matrix exceeds 512 rows");
       PivQrItem it{};
       it.A = A;
       it.lda = lda;

@@ -639,150 +639,215 @@ void launch_qr_panel(const MatDesc* d, int nmat, int j0, int nb, hipStream_t s) 
 
 // ---------------------------------------------------------------------------
 // Column-pivoted Householder QR for the row interpolative decomposition
-// (Sec. II-A: the shared basis from a column-pivoted QR).  One workgroup per
-// matrix; the matrix stays in global memory.  At step t the column of largest
-// remaining norm (norms recomputed exactly, lowest index on ties) is moved to
-// position t; the step is taken only while that norm exceeds tol * |R_00| and
-// t < cap.  Afterwards the leading k rows of R give E = R11^-1 R12, which is
-// written over R12.
+// (Sec. II-A: the shared basis from a column-pivoted QR), for matrices of at
+// most PQ_MAXR rows and PQ_MAXR columns.  One workgroup of 16 waves per
+// matrix; the matrix stays in global memory and every column is read by one
+// wave (lanes over rows, coalesced), held in registers while it is updated.
+// At step t the column of largest remaining norm (norms recomputed exactly
+// after every step, lowest index on ties) is moved to position t; the step is
+// taken only while that norm exceeds tol * |R_00| and t < cap.  Afterwards
+// the leading k rows of R give E = R11^-1 R12, written over R12.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void pivqr_kernel(const PivQrItem* __restrict__ items) {
-  __shared__ double red_v[256];
-  __shared__ int red_i[256];
-  __shared__ double sh[8];
+constexpr int PQ_MAXR = 512;
+constexpr int PQ_REG = PQ_MAXR / 64;  // column values per lane
+constexpr int PQ_WAVES = 16;
+
+__global__ __launch_bounds__(1024) void pivqr_kernel(const PivQrItem* __restrict__ items) {
+  __shared__ double s_nrm[PQ_MAXR];
+  __shared__ int s_piv[PQ_MAXR];
+  __shared__ double s_v[PQ_MAXR];
+  __shared__ double s_wv[PQ_WAVES];
+  __shared__ int s_wi[PQ_WAVES];
   __shared__ double s_tau;
-  __shared__ int s_stop;
   const PivQrItem it = items[blockIdx.x];
   const int m = it.m, n = it.n;
   double* A = it.A;
   const int64_t lda = it.lda;
-  double* nrm = it.work;
-  const int tid = threadIdx.x;
-  for (int c = tid; c < n; c += 256) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int c = wv; c < n; c += PQ_WAVES) {
     const double* ac = A + (int64_t)c * lda;
-    double s = 0.0;
-    for (int r = 0; r < m; ++r) s += ac[r] * ac[r];
-    nrm[c] = sqrt(s);
-    it.piv[c] = c;
+    double sq = 0.0;
+    for (int r = lane; r < m; r += 64) sq += ac[r] * ac[r];
+    sq = wave_sum(sq);
+    if (lane == 0) s_nrm[c] = sqrt(sq);
   }
-  for (int t = tid; t < min(m, n); t += 256) it.diag[t] = 0.0;
+  for (int c = tid; c < n; c += 64 * PQ_WAVES) s_piv[c] = c;
+  for (int t = tid; t < min(m, n); t += 64 * PQ_WAVES) it.diag[t] = 0.0;
   __syncthreads();
   const int steps = min(m, min(n, it.cap));
   double thr = 0.0;
   int k = 0;
   for (int t = 0; t < steps; ++t) {
+    // pivot: largest norm among columns t..n-1, lowest index on ties
     double best = -1.0;
     int bi = n;
-    for (int c = t + tid; c < n; c += 256) {
-      double v = nrm[c];
+    for (int c = t + tid; c < n; c += 64 * PQ_WAVES) {
+      const double v = s_nrm[c];
       if (v > best) {
         best = v;
         bi = c;
       }
     }
-    red_v[tid] = best;
-    red_i[tid] = bi;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) {
-        double vo = red_v[tid + s];
-        int io = red_i[tid + s];
-        if (vo > red_v[tid] || (vo == red_v[tid] && io < red_i[tid])) {
-          red_v[tid] = vo;
-          red_i[tid] = io;
-        }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double vo = __shfl_xor(best, off, 64);
+      const int io = __shfl_xor(bi, off, 64);
+      if (vo > best || (vo == best && io < bi)) {
+        best = vo;
+        bi = io;
       }
-      __syncthreads();
     }
-    const double pn = red_v[0];
-    const int p = red_i[0];
-    if (t == 0) thr = it.tol * pn;
-    const bool stop = !(pn > thr) || !(pn > 0.0) || p >= n;
+    if (lane == 0) {
+      s_wv[wv] = best;
+      s_wi[wv] = bi;
+    }
     __syncthreads();
-    if (stop) break;
-    if (tid == 0) it.diag[t] = pn;
+    best = s_wv[0];
+    bi = s_wi[0];
+    for (int w = 1; w < PQ_WAVES; ++w) {
+      const double vo = s_wv[w];
+      const int io = s_wi[w];
+      if (vo > best || (vo == best && io < bi)) {
+        best = vo;
+        bi = io;
+      }
+    }
+    const double pn = best;
+    const int p = bi;
+    if (t == 0) thr = it.tol * pn;
+    if (!(pn > thr) || !(pn > 0.0) || p >= n) break;  // same decision in every thread
     // swap columns t and p (all rows), norms and pivots
+    double* at = A + (int64_t)t * lda;
     if (p != t) {
-      double* at = A + (int64_t)t * lda;
       double* ap = A + (int64_t)p * lda;
-      for (int r = tid; r < m; r += 256) {
-        double x = at[r];
+      for (int r = tid; r < m; r += 64 * PQ_WAVES) {
+        const double x = at[r];
         at[r] = ap[r];
         ap[r] = x;
       }
       if (tid == 0) {
-        double x = nrm[t];
-        nrm[t] = nrm[p];
-        nrm[p] = x;
-        int q = it.piv[t];
-        it.piv[t] = it.piv[p];
-        it.piv[p] = q;
+        const double x = s_nrm[t];
+        s_nrm[t] = s_nrm[p];
+        s_nrm[p] = x;
+        const int q = s_piv[t];
+        s_piv[t] = s_piv[p];
+        s_piv[p] = q;
       }
     }
     __syncthreads();
-    // reflector from column t, rows t..m-1
-    double* at = A + (int64_t)t * lda;
-    double part = 0.0;
-    for (int r = t + 1 + tid; r < m; r += 256) part += at[r] * at[r];
-    double xn2 = block_sum256(part, sh);
-    double alpha = at[t];
-    if (tid == 0) {
-      if (xn2 == 0.0) {
-        s_tau = 0.0;
-      } else {
-        double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-        s_tau = (beta - alpha) / beta;
-        double scale = 1.0 / (alpha - beta);
-        at[t] = beta;
-        red_v[0] = scale;
+    // reflector from column t, rows t..m-1 (first wave); v(t) = 1
+    if (wv == 0) {
+      double x[PQ_REG];
+      double part = 0.0;
+#pragma unroll
+      for (int q = 0; q < PQ_REG; ++q) {
+        const int r = t + 1 + lane + 64 * q;
+        x[q] = r < m ? at[r] : 0.0;
+        part += x[q] * x[q];
+      }
+      const double xn2 = wave_sum(part);
+      const double alpha = at[t];
+      double tau = 0.0, scale = 0.0;
+      if (xn2 != 0.0) {
+        const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+        if (lane == 0) at[t] = beta;
+      }
+#pragma unroll
+      for (int q = 0; q < PQ_REG; ++q) {
+        const int r = t + 1 + lane + 64 * q;
+        if (r < m) {
+          const double v = x[q] * scale;
+          if (tau != 0.0) at[r] = v;
+          s_v[r] = v;
+        }
+      }
+      if (lane == 0) {
+        s_v[t] = 1.0;
+        s_tau = tau;
+        it.diag[t] = pn;
       }
     }
     __syncthreads();
     const double tau = s_tau;
-    if (tau != 0.0) {
-      const double scale = red_v[0];
-      for (int r = t + 1 + tid; r < m; r += 256) at[r] *= scale;
-    }
-    __syncthreads();
-    // apply to columns c > t and recompute their norms below row t
-    for (int c = t + 1 + tid; c < n; c += 256) {
+    // apply I - tau v v^T to columns c > t and recompute their norms below row t
+    for (int c = t + 1 + wv; c < n; c += PQ_WAVES) {
       double* ac = A + (int64_t)c * lda;
-      if (tau != 0.0) {
-        double wsum = ac[t];
-        for (int r = t + 1; r < m; ++r) wsum += at[r] * ac[r];
-        wsum *= tau;
-        ac[t] -= wsum;
-        double s = 0.0;
-        for (int r = t + 1; r < m; ++r) {
-          double x = ac[r] - wsum * at[r];
-          ac[r] = x;
-          s += x * x;
-        }
-        nrm[c] = sqrt(s);
-      } else {
-        double s = 0.0;
-        for (int r = t + 1; r < m; ++r) s += ac[r] * ac[r];
-        nrm[c] = sqrt(s);
+      double x[PQ_REG];
+#pragma unroll
+      for (int q = 0; q < PQ_REG; ++q) {
+        const int r = t + lane + 64 * q;
+        x[q] = r < m ? ac[r] : 0.0;
       }
+      if (tau != 0.0) {
+        double dot = 0.0;
+#pragma unroll
+        for (int q = 0; q < PQ_REG; ++q) {
+          const int r = t + lane + 64 * q;
+          if (r < m) dot += s_v[r] * x[q];
+        }
+        const double w = wave_sum(dot) * tau;
+#pragma unroll
+        for (int q = 0; q < PQ_REG; ++q) {
+          const int r = t + lane + 64 * q;
+          if (r < m) {
+            x[q] -= w * s_v[r];
+            ac[r] = x[q];
+          }
+        }
+      }
+      double sq = 0.0;
+#pragma unroll
+      for (int q = 0; q < PQ_REG; ++q) {
+        const int r = t + lane + 64 * q;
+        if (r > t && r < m) sq += x[q] * x[q];
+      }
+      sq = wave_sum(sq);
+      if (lane == 0) s_nrm[c] = sqrt(sq);
     }
     k = t + 1;
     __syncthreads();
   }
   if (tid == 0) *it.kout = k;
-  // E = R11^-1 R12 in place over R12 (rows 0..k-1, columns k..n-1)
-  for (int c = k + tid; c < n; c += 256) {
+  for (int c = tid; c < n; c += 64 * PQ_WAVES) it.piv[c] = s_piv[c];
+  // E = R11^-1 R12 over R12 (rows 0..k-1, columns k..n-1): one wave per column,
+  // back substitution with the column in registers (row r in lane r % 64,
+  // register r / 64)
+  for (int c = k + wv; c < n; c += PQ_WAVES) {
     double* ac = A + (int64_t)c * lda;
-    for (int i = k - 1; i >= 0; --i) {
-      double s = ac[i];
-      for (int l = i + 1; l < k; ++l) s -= A[i + (int64_t)l * lda] * ac[l];
-      ac[i] = s / A[i + (int64_t)i * lda];
+    double x[PQ_REG];
+#pragma unroll
+    for (int q = 0; q < PQ_REG; ++q) {
+      const int r = lane + 64 * q;
+      x[q] = r < k ? ac[r] : 0.0;
+    }
+#pragma unroll
+    for (int q = PQ_REG - 1; q >= 0; --q) {
+      const int top = min(64, k - 64 * q);  // rows of this register block
+      for (int ii = top - 1; ii >= 0; --ii) {
+        const int i = 64 * q + ii;
+        const double* ri = A + (int64_t)i * lda;  // column i of R
+        const double xi = __shfl(x[q], ii, 64) / ri[i];
+        if (lane == ii) x[q] = xi;
+#pragma unroll
+        for (int q2 = 0; q2 <= q; ++q2) {
+          const int r = lane + 64 * q2;
+          if (r < i) x[q2] -= xi * ri[r];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PQ_REG; ++q) {
+      const int r = lane + 64 * q;
+      if (r < k) ac[r] = x[q];
     }
   }
 }
 
 void launch_pivqr(const PivQrItem* items, int nitems, hipStream_t s) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(pivqr_kernel, dim3(nitems), dim3(256), 0, s, items);
+  hipLaunchKernelGGL(pivqr_kernel, dim3(nitems), dim3(64 * PQ_WAVES), 0, s, items);
 }
 
 

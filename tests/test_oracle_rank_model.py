@@ -193,11 +193,15 @@ def test_predicted_mode_keeps_the_accuracy_class():
     e_plain = np.linalg.norm(O.solve(plain, b) - xs) / np.linalg.norm(xs)
     e_pred = np.linalg.norm(O.solve(fac, b) - xs) / np.linalg.norm(xs)
     assert e_pred < max(1e-3, 5 * e_plain), (e_pred, e_plain)
-    # every sketch is at most m - probes wide and wider than its predicted rank
+    # every sketch is at most m - probes wide, wider than its predicted rank
+    # unless that width is the cap, and an accepted one is wider than its rank
     for l in fac.levels:
         for bx in fac.levels[l]:
             if bx.sketch:
-                assert bx.khat < bx.ell <= bx.m - O.SKETCH_PROBES
+                assert 0 < bx.ell <= bx.m - O.SKETCH_PROBES
+                assert bx.khat < bx.ell or bx.ell == bx.m - O.SKETCH_PROBES
+            if bx.sketch in (1, 3):
+                assert bx.k < bx.ell
 
 
 def test_sketch_sized_by_prediction_saves_basis_work():
