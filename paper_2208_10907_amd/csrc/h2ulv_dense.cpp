@@ -296,7 +296,7 @@ void batched_lu(Stage& st, const std::vector<SqMat>& mats, int32_t* ipiv, int32_
           fl += 2.0 * h * w * w / 2.0;
         }
       ProfScope ps("lu_panel", fl, 0, st.s);
-      launch_lu_panel(dd, nmat, j0, nb, st.s);
+      launch_lu_panel(dd, nmat, j0, nb, maxm - j0, st.s);
     }
     H2ULV_HIP(hipGetLastError());
     std::vector<int64_t> sp(1, 0);

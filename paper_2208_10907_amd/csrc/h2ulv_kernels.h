@@ -122,7 +122,8 @@ void launch_kgen(const KgenItem* items, const int64_t* tile_ptr, int64_t ntiles,
 template <typename TI, typename TC>
 void launch_gemm(const GemmItem<TC>* items, const GemmTerm<TI>* terms, const int64_t* tile_ptr,
                  int64_t ntiles, int nitems, int tile, hipStream_t s);
-void launch_lu_panel(const MatDesc* d, int nmat, int j0, int nb, hipStream_t s);
+// maxrows: largest m - j0 over the matrices (selects the register-resident panel)
+void launch_lu_panel(const MatDesc* d, int nmat, int j0, int nb, int maxrows, hipStream_t s);
 void launch_lu_swap_trsm(const MatDesc* d, const int64_t* slab_ptr, int64_t nslabs, int nmat,
                          int j0, int nb, hipStream_t s);
 void launch_trinv_diag(const MatDesc* d, const int64_t* blk_ptr, int64_t nblk, int nmat, int nb,

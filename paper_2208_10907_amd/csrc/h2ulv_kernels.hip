@@ -400,9 +400,204 @@ __global__ __launch_bounds__(256) void lu_panel_kernel(const MatDesc* __restrict
   }
 }
 
-void launch_lu_panel(const MatDesc* d, int nmat, int j0, int nb, hipStream_t s) {
+// The same panel factorization with the panel held in registers: 1024 threads,
+// row r of the panel in thread r % 1024, slot r / 1024 (at most LUP_RPT * 1024
+// rows).  Columns are taken in groups of LUP_G, left-looking: a group is loaded
+// once, updated by the L columns left of it (unit-lower solve of its top rows,
+// then one product for the rest), factored with partial pivoting in registers
+// (lowest row on ties), written back, and its interchanges are applied to the
+// other panel columns.  Same pivots, factors and info as lu_panel_kernel up to
+// the summation order of the updates.
+constexpr int LUP_RPT = 4;
+constexpr int LUP_G = 4;
+constexpr int LUP_THREADS = 1024;
+constexpr int LUP_MAXROWS = LUP_RPT * LUP_THREADS;
+
+__global__ __launch_bounds__(LUP_THREADS) void lu_panel_reg_kernel(const MatDesc* __restrict__ ds,
+                                                                   int j0, int nb) {
+  __shared__ double s_u[64 * LUP_G];
+  __shared__ double s_prow[LUP_G], s_crow[LUP_G];
+  __shared__ double s_wv[LUP_THREADS / 64];
+  __shared__ int s_wi[LUP_THREADS / 64];
+  __shared__ int s_piv[64];
+  const MatDesc d = ds[blockIdx.x];
+  const int m = d.m;
+  if (m <= j0) return;
+  const int w = min(nb, m - j0);
+  const int h = m - j0;
+  const int64_t lda = d.lda;
+  double* P = d.A + j0 + (int64_t)j0 * lda;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int info_col = 0;  // first singular column (1-based), thread 0 only
+  for (int g0 = 0; g0 < w; g0 += LUP_G) {
+    const int gw = min(LUP_G, w - g0);
+    double x[LUP_RPT][LUP_G];
+#pragma unroll
+    for (int i = 0; i < LUP_RPT; ++i) {
+      const int r = tid + LUP_THREADS * i;
+#pragma unroll
+      for (int c = 0; c < LUP_G; ++c)
+        x[i][c] = (r < h && c < gw) ? P[r + (int64_t)(g0 + c) * lda] : 0.0;
+    }
+    if (g0 > 0) {
+      // top rows: U = L11^-1 A_top with L11 = P(0:g0, 0:g0), unit lower (one wave)
+      if (tid < g0) {
+#pragma unroll
+        for (int c = 0; c < LUP_G; ++c) s_u[tid + 64 * c] = x[0][c];
+      }
+      __syncthreads();
+      if (wv == 0) {
+        const double lrow_ok = lane < g0 ? 1.0 : 0.0;
+        for (int c = 0; c < gw; ++c) {
+          double val = lane < g0 ? s_u[lane + 64 * c] : 0.0;
+          for (int k = 0; k < g0 - 1; ++k) {
+            const double uk = __shfl(val, k, 64);
+            if (lane > k && lane < g0) val -= P[lane + (int64_t)k * lda] * uk;
+          }
+          if (lrow_ok != 0.0) s_u[lane + 64 * c] = val;
+        }
+      }
+      __syncthreads();
+      if (tid < g0) {
+#pragma unroll
+        for (int c = 0; c < LUP_G; ++c) x[0][c] = s_u[tid + 64 * c];
+      }
+      // rows g0..h-1: A -= L(:, 0:g0) U
+#pragma unroll
+      for (int i = 0; i < LUP_RPT; ++i) {
+        const int r = tid + LUP_THREADS * i;
+        if (r >= g0 && r < h) {
+          for (int k = 0; k < g0; ++k) {
+            const double l = P[r + (int64_t)k * lda];
+#pragma unroll
+            for (int c = 0; c < LUP_G; ++c) x[i][c] -= l * s_u[k + 64 * c];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < LUP_G; ++jj) {
+      if (jj >= gw) break;
+      const int col = g0 + jj;
+      double best = -1.0;
+      int bi = h;
+#pragma unroll
+      for (int i = 0; i < LUP_RPT; ++i) {
+        const int r = tid + LUP_THREADS * i;
+        if (r >= col && r < h) {
+          const double v = fabs(x[i][jj]);
+          if (v > best) {
+            best = v;
+            bi = r;
+          }
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double vo = __shfl_xor(best, off, 64);
+        const int io = __shfl_xor(bi, off, 64);
+        if (vo > best || (vo == best && io < bi)) {
+          best = vo;
+          bi = io;
+        }
+      }
+      if (lane == 0) {
+        s_wv[wv] = best;
+        s_wi[wv] = bi;
+      }
+      __syncthreads();
+      best = s_wv[0];
+      bi = s_wi[0];
+      for (int q = 1; q < LUP_THREADS / 64; ++q) {
+        const double vo = s_wv[q];
+        const int io = s_wi[q];
+        if (vo > best || (vo == best && io < bi)) {
+          best = vo;
+          bi = io;
+        }
+      }
+      int p = bi;
+      if (!(best > 0.0) || !isfinite(best) || p >= h) {
+        if (tid == 0 && info_col == 0) info_col = j0 + col + 1;
+        p = col;
+      }
+      // rows col and p: col < 64 lives in thread col, slot 0
+      const int pt = p % LUP_THREADS, ps = p / LUP_THREADS;
+      if (tid == pt) {
+#pragma unroll
+        for (int i = 0; i < LUP_RPT; ++i)
+          if (i == ps) {
+#pragma unroll
+            for (int c = 0; c < LUP_G; ++c) s_prow[c] = x[i][c];
+          }
+      }
+      if (tid == col) {
+#pragma unroll
+        for (int c = 0; c < LUP_G; ++c) s_crow[c] = x[0][c];
+      }
+      if (tid == 0) s_piv[col] = p;
+      __syncthreads();
+      if (p != col) {
+        if (tid == pt) {
+#pragma unroll
+          for (int i = 0; i < LUP_RPT; ++i)
+            if (i == ps) {
+#pragma unroll
+              for (int c = 0; c < LUP_G; ++c) x[i][c] = s_crow[c];
+            }
+        }
+        if (tid == col) {
+#pragma unroll
+          for (int c = 0; c < LUP_G; ++c) x[0][c] = s_prow[c];
+        }
+      }
+      const double inv = 1.0 / s_prow[jj];
+#pragma unroll
+      for (int i = 0; i < LUP_RPT; ++i) {
+        const int r = tid + LUP_THREADS * i;
+        if (r > col && r < h) {
+          const double l = x[i][jj] * inv;
+          x[i][jj] = l;
+#pragma unroll
+          for (int c = jj + 1; c < LUP_G; ++c) x[i][c] -= l * s_prow[c];
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < LUP_RPT; ++i) {
+      const int r = tid + LUP_THREADS * i;
+      if (r < h) {
+#pragma unroll
+        for (int c = 0; c < LUP_G; ++c)
+          if (c < gw) P[r + (int64_t)(g0 + c) * lda] = x[i][c];
+      }
+    }
+    // the group's interchanges on the other columns of the panel
+    for (int c = tid; c < w; c += LUP_THREADS) {
+      if (c >= g0 && c < g0 + gw) continue;
+      double* pc = P + (int64_t)c * lda;
+      for (int jj = 0; jj < gw; ++jj) {
+        const int col = g0 + jj, p = s_piv[col];
+        if (p != col) {
+          const double t0 = pc[col];
+          pc[col] = pc[p];
+          pc[p] = t0;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int c = tid; c < w; c += LUP_THREADS) d.ipiv[j0 + c] = j0 + s_piv[c];
+  if (tid == 0 && info_col != 0 && *d.info == 0) *d.info = info_col;
+}
+
+void launch_lu_panel(const MatDesc* d, int nmat, int j0, int nb, int maxrows, hipStream_t s) {
   if (nmat <= 0) return;
-  hipLaunchKernelGGL(lu_panel_kernel, dim3(nmat), dim3(256), 0, s, d, j0, nb);
+  if (maxrows <= LUP_MAXROWS && nb <= 64)
+    hipLaunchKernelGGL(lu_panel_reg_kernel, dim3(nmat), dim3(LUP_THREADS), 0, s, d, j0, nb);
+  else
+    hipLaunchKernelGGL(lu_panel_kernel, dim3(nmat), dim3(256), 0, s, d, j0, nb);
 }
 
 // Row swaps of panel [j0, j0+w) applied to every column outside the panel, then
