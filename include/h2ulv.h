@@ -154,6 +154,9 @@ h2ulv_status h2ulv_solve(const h2ulv_factor* f, double* b, int32_t nrhs, int64_t
 /*
  * y = A x with the exact kernel matrix generated on the fly in float64
  * (A_ii = diag; used for residuals).  x, y device, n x nrhs column-major.
+ * For n >= 65536 the sources are split over several workgroups whose partial
+ * sums are added in a fixed order (deterministic); the call then waits for
+ * its stream before returning.
  */
 h2ulv_status h2ulv_matvec_exact(const h2ulv_factor* f, const double* x, int64_t ldx,
                                 double* y, int64_t ldy, int32_t nrhs, void* stream);

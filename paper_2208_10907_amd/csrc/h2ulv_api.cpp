@@ -176,8 +176,14 @@ static h2ulv_factor* factorize_impl(const double* pts, int64_t n, const h2ulv_pa
 
 static void matvec_impl(const h2ulv_factor& F, const double* x, int64_t ldx, double* y,
                         int64_t ldy, int nrhs, hipStream_t s) {
-  launch_matvec(F.pts.as<double>(), F.n, kfn(F.p), x, ldx, y, ldy, nrhs, s);
+  // partial sums of the source ranges; the stream is drained before the
+  // buffer goes back to the cache, which other streams may draw from
+  const int64_t words = matvec_work_words(F.n, nrhs);
+  DBuf work(std::max<int64_t>(words, 1) * sizeof(double));
+  launch_matvec(F.pts.as<double>(), F.n, kfn(F.p), x, ldx, y, ldy, nrhs,
+                words > 0 ? work.as<double>() : nullptr, s);
   H2ULV_HIP(hipGetLastError());
+  if (words > 0) H2ULV_HIP(hipStreamSynchronize(s));
 }
 
 static h2ulv_status refine_impl(const h2ulv_factor& F, const double* b, int64_t ldb, double* x,

@@ -142,8 +142,11 @@ void launch_perm_matrix(const PermItem* items, const int64_t* slab_ptr, int64_t 
 void launch_wprime(const WpItem* items, int nitems, hipStream_t s);
 void launch_zero_lower(const CopyItem* items, int nitems, hipStream_t s);
 void launch_logdet(const MatDesc* d, int nmat, double* out, hipStream_t s);
+// Exact y = A x.  work: matvec_work_words(n, nrhs) doubles for the partial sums
+// of split source ranges (nullptr: one range per target block)
+int64_t matvec_work_words(int64_t n, int nrhs);
 void launch_matvec(const double* pts, int64_t n, KernelFn kf, const double* x, int64_t ldx,
-                   double* y, int64_t ldy, int nrhs, hipStream_t s);
+                   double* y, int64_t ldy, int nrhs, double* work, hipStream_t s);
 void launch_convert_d2f(const double* src, float* dst, int64_t count, hipStream_t s);
 void launch_convert_f2d(const float* src, double* dst, int64_t count, hipStream_t s);
 void launch_resid_norms(const double* b, int64_t ldb, const double* ax, int64_t ldax, double* r,

@@ -8,6 +8,7 @@
 // launch.  All matrices are column-major.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "h2ulv_kernels.h"
@@ -1289,18 +1290,23 @@ __device__ __forceinline__ double inv_sqrt(double r2) {
 }
 
 // Exact y = A x with the matrix generated on the fly.  Each thread owns two
-// target points (i and i + 256) and runs over all sources staged in LDS, 256 at
-// a time; the self term is excluded by a select on r^2 > 0 and diag x_i is
-// added at the end.
-template <int NR>
+// target points (i and i + 256) and runs over the sources [js, je) staged in
+// LDS, 256 at a time; the self term is excluded by a select on r^2 > 0.  The
+// kernel kind is a template parameter (no branch in the inner loop).  With one
+// source range the result y = diag x + sum is written directly; otherwise the
+// range blockIdx.y writes its partial sums to part and matvec_reduce_kernel
+// adds them in a fixed order.
+template <int NR, bool LAP>
 __global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ pts, int64_t n,
                                                      KernelFn kf, const double* __restrict__ x,
                                                      int64_t ldx, double* __restrict__ y,
-                                                     int64_t ldy) {
+                                                     int64_t ldy, double* __restrict__ part,
+                                                     int64_t chunk) {
   __shared__ double sp[3][256];
   __shared__ double sx[NR][256];
   const int64_t i0 = (int64_t)blockIdx.x * 512 + threadIdx.x;
   const int64_t i1 = i0 + 256;
+  const int64_t js = (int64_t)blockIdx.y * chunk, je = min(n, js + chunk);
   double p0[3] = {0, 0, 0}, p1[3] = {0, 0, 0};
   if (i0 < n)
     for (int d = 0; d < 3; ++d) p0[d] = pts[3 * i0 + d];
@@ -1309,11 +1315,10 @@ __global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ 
   double a0[NR], a1[NR];
 #pragma unroll
   for (int c = 0; c < NR; ++c) a0[c] = a1[c] = 0.0;
-  const bool lap = kf.kind == 0;
-  for (int64_t j0 = 0; j0 < n; j0 += 256) {
+  for (int64_t j0 = js; j0 < je; j0 += 256) {
     const int64_t j = j0 + threadIdx.x;
     __syncthreads();
-    if (j < n) {
+    if (j < je) {
       for (int d = 0; d < 3; ++d) sp[d][threadIdx.x] = pts[3 * j + d];
 #pragma unroll
       for (int c = 0; c < NR; ++c) sx[c][threadIdx.x] = x[j + c * ldx];
@@ -1324,7 +1329,7 @@ __global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ 
       for (int c = 0; c < NR; ++c) sx[c][threadIdx.x] = 0.0;
     }
     __syncthreads();
-    const int cnt = (int)min((int64_t)256, n - j0);
+    const int cnt = (int)min((int64_t)256, je - j0);
     for (int t = 0; t < cnt; ++t) {
       const double sx0 = sp[0][t], sy0 = sp[1][t], sz0 = sp[2][t];
       double dx = p0[0] - sx0, dy = p0[1] - sy0, dz = p0[2] - sz0;
@@ -1334,7 +1339,7 @@ __global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ 
       dz = p1[2] - sz0;
       const double q1 = fma(dx, dx, fma(dy, dy, dz * dz));
       double k0 = inv_sqrt(q0), k1 = inv_sqrt(q1);
-      if (!lap) {
+      if (!LAP) {
         k0 *= exp(-kf.alpha * (q0 * k0));
         k1 *= exp(-kf.alpha * (q1 * k1));
       }
@@ -1348,33 +1353,96 @@ __global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ 
       }
     }
   }
-  if (i0 < n) {
+  if (part == nullptr) {
+    if (i0 < n) {
 #pragma unroll
-    for (int c = 0; c < NR; ++c) y[i0 + c * ldy] = fma(kf.diag, x[i0 + c * ldx], a0[c]);
-  }
-  if (i1 < n) {
+      for (int c = 0; c < NR; ++c) y[i0 + c * ldy] = fma(kf.diag, x[i0 + c * ldx], a0[c]);
+    }
+    if (i1 < n) {
 #pragma unroll
-    for (int c = 0; c < NR; ++c) y[i1 + c * ldy] = fma(kf.diag, x[i1 + c * ldx], a1[c]);
+      for (int c = 0; c < NR; ++c) y[i1 + c * ldy] = fma(kf.diag, x[i1 + c * ldx], a1[c]);
+    }
+  } else {
+    double* pp = part + (int64_t)blockIdx.y * NR * n;
+    if (i0 < n) {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) pp[i0 + c * n] = a0[c];
+    }
+    if (i1 < n) {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) pp[i1 + c * n] = a1[c];
+    }
   }
 }
 
+// y(i, c) = diag x(i, c) + sum over ranges s (in order) of part[s][c][i]
+__global__ __launch_bounds__(256) void matvec_reduce_kernel(const double* __restrict__ part,
+                                                            int nsplit, int nr, int64_t n,
+                                                            double diag,
+                                                            const double* __restrict__ x,
+                                                            int64_t ldx, double* __restrict__ y,
+                                                            int64_t ldy) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * nr) return;
+  const int64_t i = e % n, c = e / n;
+  double acc = 0.0;
+  for (int q = 0; q < nsplit; ++q) acc += part[(int64_t)q * nr * n + c * n + i];
+  y[i + c * ldy] = fma(diag, x[i + c * ldx], acc);
+}
+
+namespace {
+constexpr int MV_MAX_SPLIT = 8;
+// source ranges per launch: enough workgroups to fill the chip several times
+int matvec_split(int64_t n) {
+  const int64_t grid = (n + 511) / 512;
+  if (n < 65536) return 1;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(MV_MAX_SPLIT, 4096 / grid));
+}
+
+template <int NR>
+void matvec_launch(const double* pts, int64_t n, KernelFn kf, const double* x, int64_t ldx,
+                   double* y, int64_t ldy, double* work, hipStream_t s) {
+  const int ns = work ? matvec_split(n) : 1;
+  const unsigned gx = (unsigned)((n + 511) / 512);
+  const int64_t chunk = ns > 1 ? ((n + ns - 1) / ns + 255) / 256 * 256 : n;
+  const int nsu = (int)((n + chunk - 1) / chunk);  // ranges actually used
+  double* part = nsu > 1 ? work : nullptr;
+  const dim3 grid(gx, (unsigned)std::max(nsu, 1));
+  if (kf.kind == 0)
+    hipLaunchKernelGGL((matvec_kernel<NR, true>), grid, dim3(256), 0, s, pts, n, kf, x, ldx, y,
+                       ldy, part, chunk);
+  else
+    hipLaunchKernelGGL((matvec_kernel<NR, false>), grid, dim3(256), 0, s, pts, n, kf, x, ldx, y,
+                       ldy, part, chunk);
+  if (part) {
+    const int64_t tot = n * NR;
+    hipLaunchKernelGGL(matvec_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       part, nsu, NR, n, kf.diag, x, ldx, y, ldy);
+  }
+}
+}  // namespace
+
+int64_t matvec_work_words(int64_t n, int nrhs) {
+  const int ns = matvec_split(n);
+  return ns > 1 ? (int64_t)ns * std::min(nrhs, 8) * n : 0;
+}
+
 void launch_matvec(const double* pts, int64_t n, KernelFn kf, const double* x, int64_t ldx,
-                   double* y, int64_t ldy, int nrhs, hipStream_t s) {
-  unsigned grid = (unsigned)((n + 511) / 512);
+                   double* y, int64_t ldy, int nrhs, double* work, hipStream_t s) {
+  if (n <= 0) return;
   int c = 0;
   while (c < nrhs) {
-    int left = nrhs - c;
+    const int left = nrhs - c;
+    const double* xc = x + (int64_t)c * ldx;
+    double* yc = y + (int64_t)c * ldy;
     if (left >= 8) {
-      hipLaunchKernelGGL(matvec_kernel<8>, dim3(grid), dim3(256), 0, s, pts, n, kf,
-                         x + (int64_t)c * ldx, ldx, y + (int64_t)c * ldy, ldy);
+      matvec_launch<8>(pts, n, kf, xc, ldx, yc, ldy, work, s);
       c += 8;
     } else if (left >= 4) {
-      hipLaunchKernelGGL(matvec_kernel<4>, dim3(grid), dim3(256), 0, s, pts, n, kf,
-                         x + (int64_t)c * ldx, ldx, y + (int64_t)c * ldy, ldy);
+      matvec_launch<4>(pts, n, kf, xc, ldx, yc, ldy, work, s);
       c += 4;
     } else {
-      hipLaunchKernelGGL(matvec_kernel<1>, dim3(grid), dim3(256), 0, s, pts, n, kf,
-                         x + (int64_t)c * ldx, ldx, y + (int64_t)c * ldy, ldy);
+      matvec_launch<1>(pts, n, kf, xc, ldx, yc, ldy, work, s);
       c += 1;
     }
   }
