@@ -53,6 +53,21 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
   return s;
 }
 
+// Block-wide sum over NW waves; every thread gets the result (same order in
+// every thread).
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) s += sh[q];
+  return s;
+}
+
 // ---------------------------------------------------------------------------
 // Kernel-matrix generation (dense near blocks, far-field samples, skeleton
 // couplings).  Tile 64 x 64, 256 threads; writes coalesced along rows.
@@ -716,9 +731,11 @@ void launch_trinv_diag(const MatDesc* d, const int64_t* blk_ptr, int64_t nblk, i
 // block-reflector factor T (H_0 ... H_{w-1} = I - V T V^T) into Tf (nb x nb).
 // The trailing columns are updated afterwards by GEMMs.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc* __restrict__ ds, int j0,
-                                                       int nb) {
-  __shared__ double sh[8];
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void qr_panel_kernel(const MatDesc* __restrict__ ds, int j0,
+                                                            int nb) {
+  constexpr int NT = 64 * NW;
+  __shared__ double sh[NW];
   __shared__ double s_tau, s_scale;
   __shared__ double dots[64];
   const MatDesc d = ds[blockIdx.x];
@@ -734,12 +751,12 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc* __restrict
     double* a = A + (int64_t)col * lda;
     double part = 0.0, part1 = 0.0;
     int rr = col + 1 + tid;
-    for (; rr + 256 < m; rr += 512) {
+    for (; rr + NT < m; rr += 2 * NT) {
       part += a[rr] * a[rr];
-      part1 += a[rr + 256] * a[rr + 256];
+      part1 += a[rr + NT] * a[rr + NT];
     }
-    for (; rr < m; rr += 256) part += a[rr] * a[rr];
-    double xn2 = block_sum256(part + part1, sh);
+    for (; rr < m; rr += NT) part += a[rr] * a[rr];
+    double xn2 = block_sum<NW>(part + part1, sh);
     double alpha = a[col];
     if (tid == 0) {
       if (xn2 == 0.0) {
@@ -757,7 +774,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc* __restrict
     __syncthreads();
     const double tau = s_tau, scale = s_scale;
     double* v = V + (int64_t)jj * m;
-    for (int r = tid; r < m; r += 256) {
+    for (int r = tid; r < m; r += NT) {
       double val;
       if (r < col)
         val = 0.0;
@@ -772,7 +789,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc* __restrict
     __syncthreads();
     if (tau != 0.0) {
       // apply H = I - tau v v^T to the panel columns right of col: one wave per column
-      for (int c = col + 1 + wv; c < j0 + w; c += 4) {
+      for (int c = col + 1 + wv; c < j0 + w; c += NW) {
         double* ac = A + (int64_t)c * lda;
         double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
         int r = col + lane;
@@ -799,12 +816,12 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc* __restrict
   // T factor (forward, columnwise): T[jj][jj] = tau_jj,
   // T[0:jj, jj] = -tau_jj T[0:jj, 0:jj] (V[:, 0:jj]^T v_jj)
   double* Tf = d.panel_ws ? d.Tf : d.Tf + (int64_t)(j0 / nb) * nb * nb;
-  for (int e = tid; e < nb * nb; e += 256) Tf[e] = 0.0;
+  for (int e = tid; e < nb * nb; e += NT) Tf[e] = 0.0;
   __syncthreads();
   for (int jj = 0; jj < w; ++jj) {
     const double tau = d.aux[j0 + jj];
     const double* vj = V + (int64_t)jj * m;
-    for (int l = wv; l < jj; l += 4) {
+    for (int l = wv; l < jj; l += NW) {
       const double* vl = V + (int64_t)l * m;
       double p = 0.0, q = 0.0;
       int r = j0 + jj + lane;
@@ -829,7 +846,8 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const MatDesc* __restrict
 
 void launch_qr_panel(const MatDesc* d, int nmat, int j0, int nb, hipStream_t s) {
   if (nmat <= 0) return;
-  hipLaunchKernelGGL(qr_panel_kernel, dim3(nmat), dim3(256), 0, s, d, j0, nb);
+  // 16 waves: each step updates 16 trailing panel columns at once
+  hipLaunchKernelGGL(qr_panel_kernel<16>, dim3(nmat), dim3(1024), 0, s, d, j0, nb);
 }
 
 
@@ -1086,14 +1104,18 @@ void launch_pivqr_init(const PivQrState* st, const int64_t* slab_ptr, int64_t ns
   hipLaunchKernelGGL(pivqr_init_kernel, dim3((unsigned)nslabs), dim3(256), 0, s, st, slab_ptr, n);
 }
 
-__global__ __launch_bounds__(256) void pivqr_pick_kernel(const PivQrState* __restrict__ sts,
-                                                         int t) {
-  __shared__ double red_v[256];
-  __shared__ int red_i[256];
-  __shared__ double sh[8];
+// One pivot step of a large box (one 1024-thread workgroup per box): pick the
+// column of largest norm among t..n-1 (lowest index on ties), swap it into
+// position t, form the reflector from its rows t..m-1 (scaled in place, R_tt
+// written), and leave tau and the rank so far for the apply kernel.
+__global__ __launch_bounds__(1024) void pivqr_pick_kernel(const PivQrState* __restrict__ sts,
+                                                          int t) {
+  __shared__ double s_wv[16];
+  __shared__ int s_wi[16];
+  __shared__ double sh[16];
   const PivQrState st = sts[blockIdx.x];
   if (st.flags[0]) return;
-  const int m = st.m, tid = threadIdx.x;
+  const int m = st.m, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (t >= st.cap) {
     if (tid == 0) st.flags[0] = 1;
     return;
@@ -1101,60 +1123,67 @@ __global__ __launch_bounds__(256) void pivqr_pick_kernel(const PivQrState* __res
   const int ncol = st.n;
   double best = -1.0;
   int bi = ncol;
-  for (int c = t + tid; c < ncol; c += 256) {
-    double v = st.nrm[c];
+  for (int c = t + tid; c < ncol; c += 1024) {
+    const double v = st.nrm[c];
     if (v > best) {
       best = v;
       bi = c;
     }
   }
-  red_v[tid] = best;
-  red_i[tid] = bi;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) {
-      double vo = red_v[tid + s];
-      int io = red_i[tid + s];
-      if (vo > red_v[tid] || (vo == red_v[tid] && io < red_i[tid])) {
-        red_v[tid] = vo;
-        red_i[tid] = io;
-      }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double vo = __shfl_xor(best, off, 64);
+    const int io = __shfl_xor(bi, off, 64);
+    if (vo > best || (vo == best && io < bi)) {
+      best = vo;
+      bi = io;
     }
-    __syncthreads();
   }
-  const double pn = red_v[0];
-  const int p = red_i[0];
-  const double thr = (t == 0) ? st.tol * pn : st.scal[1];
-  const bool stop = !(pn > thr) || !(pn > 0.0) || p >= ncol;
+  if (lane == 0) {
+    s_wv[wv] = best;
+    s_wi[wv] = bi;
+  }
   __syncthreads();
-  if (stop) {
+  best = s_wv[0];
+  bi = s_wi[0];
+  for (int q = 1; q < 16; ++q) {
+    const double vo = s_wv[q];
+    const int io = s_wi[q];
+    if (vo > best || (vo == best && io < bi)) {
+      best = vo;
+      bi = io;
+    }
+  }
+  const double pn = best;
+  const int p = bi;
+  const double thr = (t == 0) ? st.tol * pn : st.scal[1];
+  if (!(pn > thr) || !(pn > 0.0) || p >= ncol) {  // same decision in every thread
     if (tid == 0) st.flags[0] = 1;
     return;
   }
   double* A = st.A;
   const int64_t lda = st.lda;
+  double* at = A + (int64_t)t * lda;
   if (p != t) {
-    double* at = A + (int64_t)t * lda;
     double* ap = A + (int64_t)p * lda;
-    for (int r = tid; r < m; r += 256) {
-      double x = at[r];
+    for (int r = tid; r < m; r += 1024) {
+      const double x = at[r];
       at[r] = ap[r];
       ap[r] = x;
     }
   }
   __syncthreads();
   if (tid == 0 && p != t) {
-    double x = st.nrm[t];
+    const double x = st.nrm[t];
     st.nrm[t] = st.nrm[p];
     st.nrm[p] = x;
-    int q = st.piv[t];
+    const int q = st.piv[t];
     st.piv[t] = st.piv[p];
     st.piv[p] = q;
   }
-  double* at = A + (int64_t)t * lda;
   double part = 0.0;
-  for (int r = t + 1 + tid; r < m; r += 256) part += at[r] * at[r];
-  const double xn2 = block_sum256(part, sh);
+  for (int r = t + 1 + tid; r < m; r += 1024) part += at[r] * at[r];
+  const double xn2 = block_sum<16>(part, sh);
   const double alpha = at[t];
   double tau = 0.0, scale = 0.0;
   if (xn2 != 0.0) {
@@ -1164,7 +1193,7 @@ __global__ __launch_bounds__(256) void pivqr_pick_kernel(const PivQrState* __res
   }
   __syncthreads();
   if (tau != 0.0) {
-    for (int r = t + 1 + tid; r < m; r += 256) at[r] *= scale;
+    for (int r = t + 1 + tid; r < m; r += 1024) at[r] *= scale;
   }
   if (tid == 0) {
     if (tau != 0.0) at[t] = -copysign(sqrt(alpha * alpha + xn2), alpha);
@@ -1176,7 +1205,7 @@ __global__ __launch_bounds__(256) void pivqr_pick_kernel(const PivQrState* __res
 
 void launch_pivqr_pick(const PivQrState* st, int n, int t, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(pivqr_pick_kernel, dim3(n), dim3(256), 0, s, st, t);
+  hipLaunchKernelGGL(pivqr_pick_kernel, dim3(n), dim3(1024), 0, s, st, t);
 }
 
 __global__ __launch_bounds__(256) void pivqr_apply_kernel(const PivQrState* __restrict__ sts,
