@@ -511,7 +511,14 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
     then the root LU (Eq. BLR2final).
 
     ``level_stop``/``boxes``: stop after the basis step of that level, for the
-    given boxes only (used to time or check a sample of one level)."""
+    given boxes only (used to time or check a sample of one level).
+
+    Flop counts (``stats["flops"]``) follow the operations a device forms:
+    LU 2/3 m^3 per diagonal block; for a box whose M' is formed, the products
+    D_ik D_kk^-1 (2 m_i m_k^2 each) and the fill-ins (2 m_i m_k m_j per term);
+    for a sketched box, per attempt the far part 2 |far| m_i c and the fill part
+    2 c m_k m_i per near k, plus per pass the shared Q'_k (2 m_k^2 C + 2 m_k m_j C);
+    QR 2 n m^2 - 2/3 m^3; GEMM 2 m n k."""
     X = np.asarray(X, dtype=np.float64)
     check_params(X, p)
     tree = build_tree(X, p.leaf)
@@ -569,10 +576,11 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                 continue
             dlu[k] = lu(D[k, k])
             flops["fill"] += 2.0 / 3.0 * m[k] ** 3
+            # Y_kj = D_kk^-1 D_kj; the flops are counted per box below as the
+            # products D_ik D_kk^-1 of the boxes whose M' is formed
             for j in near[lev][k]:
                 if j != k:
                     Y[k, j] = sla.lu_solve(dlu[k], D[k, j], check_finite=False)
-                    flops["fill"] += 2.0 * m[k] ** 2 * m[j]
         fac.cand[lev] = Pl
         bf = [None] * nb
         first_attempts, retries = [], []
@@ -618,8 +626,8 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
 
             def attempt(width):
                 # M' Omega as formed without F: the far part K(P_i, far) Omega_far
-                # (basis) and the fill part sum_k Z'_ik Q_k (fill; the Q_k are
-                # shared by the level and counted after the loop)
+                # (basis) and the fill part T-hat^-1 sum_k D_ik Q'_k (fill; the
+                # Q'_k are shared by the level and counted after the loop)
                 cols = width + SKETCH_PROBES
                 flops["basis"] += 2.0 * len(fcols) * m[i] * cols
                 for k in near[lev][i]:
@@ -652,6 +660,8 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                 else:
                     ell = 0
             if state not in (1, 3):
+                # M' formed: the products D_ik D_kk^-1, then the fill-ins
+                flops["fill"] += sum(2.0 * m[i] * m[k] ** 2 for k in near[lev][i] if k != i)
                 flops["fill"] += fl_F
                 k_i, piv, Wp, dg = row_id(M, p.tol, p.rank_cap)
                 flops["basis"] += 2.0 * ncol * m[i] ** 2 - 2.0 / 3.0 * min(ncol, m[i]) ** 3 if ncol >= m[i] else 2.0 * m[i] * ncol ** 2 - 2.0 / 3.0 * ncol ** 3
@@ -668,15 +678,16 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
             flops["basis"] += 4.0 * m[i] * k_i * k_i + 4.0 * m[i] ** 2 * k_i
             bf[i] = BoxFactor(m[i], k_i, U, T, np.asarray(Pl[i])[piv[:k_i]], piv, absdiag=dg,
                               feat=feat, khat=khat, ell=ell, sketch=state)
-        # shared sketch blocks Q_k = sum_{j in Near(k), j != k} D_kj Omega_fill[P_j] for
-        # every box k next to a sketched box, as wide as the widest sketch of the
-        # pass (first attempts, then full-width retries)
+        # shared sketch blocks Q'_k = D_kk^-1 sum_{j in Near(k), j != k} D_kj Omega_fill[P_j]
+        # for every box k next to a sketched box, as wide as the widest sketch of
+        # the pass (first attempts, then full-width retries)
         for att in (first_attempts, retries):
             if not att:
                 continue
             cols = max(w for _, w in att) + SKETCH_PROBES
             ks = {k for i, _ in att for k in near[lev][i] if k != i and m[k] > 0}
             for k in ks:
+                flops["fill"] += 2.0 * m[k] ** 2 * cols
                 for j in near[lev][k]:
                     if j != k and m[j] > 0:
                         flops["fill"] += 2.0 * m[k] * m[j] * cols

@@ -238,6 +238,7 @@ struct Driver {
   void dense_blocks(Stage& st, const std::vector<Prob*>& G);
   void fill_products(Stage& st, const std::vector<Prob*>& G);
   void basis_prepare(Stage& st, const std::vector<Prob*>& G);
+  void fill_z(Stage& st, const std::vector<Box>& boxes);
   // rebuild: boxes whose sketch was rejected, sketched again at full width or
   // given their M' (kernel entries are not counted again)
   void build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebuild = false);
@@ -312,8 +313,6 @@ void Driver::fill_products(Stage& st, const std::vector<Prob*>& G) {
     for (Prob* P : G) {
       const int nb = P->nb;
       const std::vector<int>& m = P->lf().m;
-      P->offSq.assign(nb + 1, 0);
-      for (int i = 0; i < nb; ++i) P->offSq[i + 1] = P->offSq[i] + (int64_t)m[i] * m[i];
       P->Dinv.alloc(std::max<int64_t>(P->offSq[nb], 1) * sizeof(double));
       LUw.emplace_back(std::max<int64_t>(P->offSq[nb], 1) * sizeof(double));
       double* W = LUw.back().as<double>();
@@ -360,52 +359,62 @@ void Driver::fill_products(Stage& st, const std::vector<Prob*>& G) {
       st.sync();
     }
   }
-  // Z'_ik for k in Near(i) \ {i}, stored at the CSR position of (i, k)
-  {
-    std::vector<DBuf> Ztmp;
-    GemmBatch<double> g, g2;
-    for (Prob* P : G) {
-      const int nb = P->nb;
-      const std::vector<int>& m = P->lf().m;
-      const auto& np = P->np();
-      const auto& ni = P->ni();
-      const bool upper = P->lev < P->L();
-      const int64_t words = std::max<int64_t>(P->Doff[P->nnear()], 1);
-      P->Z.alloc(words * sizeof(double));
-      double* Zp = P->Z.as<double>();
-      double* Zt = Zp;
-      if (upper) {
+  // Z'_ik only for the boxes whose M' is formed (not sketched); D^-1 and
+  // T-hat^-1 stay until the basis step has settled every box
+  std::vector<Box> need;
+  for (Prob* P : G)
+    for (int i = 0; i < P->nb; ++i)
+      if (P->lf().sk_state[i] == 0) need.push_back(Box{P, i});
+  fill_z(st, need);
+}
+
+// Z'_ik = T-hat_i^-1 D_ik D_kk^-1 for k in Near(i) \ {i} of the given boxes,
+// stored at the CSR position of (i, k) (the buffer is allocated on first use)
+void Driver::fill_z(Stage& st, const std::vector<Box>& boxes) {
+  if (boxes.empty()) return;
+  std::vector<DBuf> Ztmp;
+  std::map<Prob*, double*> tmp;
+  GemmBatch<double> g, g2;
+  for (const Box& b : boxes) {
+    Prob* P = b.P;
+    const int i = b.i;
+    const std::vector<int>& m = P->lf().m;
+    const auto& np = P->np();
+    const auto& ni = P->ni();
+    const bool upper = P->lev < P->L();
+    const int64_t words = std::max<int64_t>(P->Doff[P->nnear()], 1);
+    if (!P->Z.p) P->Z.alloc(words * sizeof(double));
+    double* Zp = P->Z.as<double>();
+    double* Zt = Zp;
+    if (upper) {
+      if (!tmp.count(P)) {
         Ztmp.emplace_back(words * sizeof(double));
-        Zt = Ztmp.back().as<double>();
+        tmp[P] = Ztmp.back().as<double>();
       }
-      const double* Dp = P->D.as<double>();
-      for (int i = 0; i < nb; ++i)
-        for (int64_t e = np[i]; e < np[i + 1]; ++e) {
-          int k = ni[e];
-          if (k == i || m[i] == 0 || m[k] == 0) continue;
-          g.one(Zt + P->Doff[e], m[i], m[i], m[k], m[k], Dp + P->Doff[e], m[i], false,
-                P->Dinv.as<double>() + P->offSq[k], m[k], false);
-          P->fl_fill += 2.0 * m[i] * (double)m[k] * m[k];
-          if (!upper) continue;
-          const LevelFactor& ch = P->F->levels[P->lev + 1];
-          int k1 = ch.k[2 * i], k2 = ch.k[2 * i + 1];
-          const double* Ti = P->Tinv.as<double>();
-          if (k1 > 0)
-            g2.one(Zp + P->Doff[e], m[i], k1, m[k], k1, Ti + P->offTinv[2 * i], k1, false,
-                   Zt + P->Doff[e], m[i], false);
-          if (k2 > 0)
-            g2.one(Zp + P->Doff[e] + k1, m[i], k2, m[k], k2, Ti + P->offTinv[2 * i + 1], k2,
-                   false, Zt + P->Doff[e] + k1, m[i], false);
-        }
+      Zt = tmp[P];
     }
-    g.run(st, "fill_z");
-    g2.run(st, "fill_z");
-    st.sync();
+    const double* Dp = P->D.as<double>();
+    for (int64_t e = np[i]; e < np[i + 1]; ++e) {
+      const int k = ni[e];
+      if (k == i || m[i] == 0 || m[k] == 0) continue;
+      g.one(Zt + P->Doff[e], m[i], m[i], m[k], m[k], Dp + P->Doff[e], m[i], false,
+            P->Dinv.as<double>() + P->offSq[k], m[k], false);
+      P->fl_fill += 2.0 * m[i] * (double)m[k] * m[k];
+      if (!upper) continue;
+      const LevelFactor& ch = P->F->levels[P->lev + 1];
+      const int k1 = ch.k[2 * i], k2 = ch.k[2 * i + 1];
+      const double* Ti = P->Tinv.as<double>();
+      if (k1 > 0)
+        g2.one(Zp + P->Doff[e], m[i], k1, m[k], k1, Ti + P->offTinv[2 * i], k1, false,
+               Zt + P->Doff[e], m[i], false);
+      if (k2 > 0)
+        g2.one(Zp + P->Doff[e] + k1, m[i], k2, m[k], k2, Ti + P->offTinv[2 * i + 1], k2, false,
+               Zt + P->Doff[e] + k1, m[i], false);
+    }
   }
-  for (Prob* P : G) {
-    P->Dinv.reset();
-    P->Tinv.reset();
-  }
+  g.run(st, "fill_z");
+  g2.run(st, "fill_z");
+  st.sync();
 }
 
 // ---- (c) preparation of the basis step: fill targets, far-field columns,
@@ -426,6 +435,8 @@ void Driver::basis_prepare(Stage& st, const std::vector<Prob*>& G) {
     lf.sk_state.assign(nb, 0);
     P->Eptr.assign(nb, nullptr);
     P->ldE.assign(nb, 1);
+    P->offSq.assign(nb + 1, 0);
+    for (int i = 0; i < nb; ++i) P->offSq[i + 1] = P->offSq[i] + (int64_t)m[i] * m[i];
     const bool upper = P->lev < P->L();
     for (int i = 0; i < nb; ++i) {
       P->targets[i] = fill_targets(ls, P->lev, i);
@@ -494,11 +505,12 @@ void Driver::basis_prepare(Stage& st, const std::vector<Prob*>& G) {
 // ---- (c) sketch of M' without forming it.  Omega's rows are keyed by point:
 // far-field column p takes row p of the far stream, the fill-in columns of
 // target j take the rows G_j of j's candidates in the fill stream.  Since
-// T-hat^-1 F_ij = sum_k Z'_ik D_kj over the k next to both i and j,
-//   (M' Omega)^T = Omega_far^T K(P_i, far)^T + sum_{k in Near(i), k != i} Q_k^T Z'_ik^T,
-//   Q_k = sum_{j in Near(k), j != k} D_kj G_j,
-// and every Q_k is shared by all boxes next to k.  Q is as wide as the widest
-// sketch of the pass in its problem; box i takes its first l_i + q columns.
+// T-hat^-1 F_ij = T-hat^-1 sum_k D_ik D_kk^-1 D_kj over the k next to both i and j,
+//   (M' Omega)^T = Omega_far^T K(P_i, far)^T + (sum_{k in Near(i), k != i} Q'_k^T D_ik^T) T-hat^-T,
+//   Q'_k = D_kk^-1 Q_k,  Q_k = sum_{j in Near(k), j != k} D_kj G_j,
+// and every Q'_k is shared by all boxes next to k (no Z'_ik is formed).  Q is
+// as wide as the widest sketch of the pass in its problem; box i takes its
+// first l_i + q columns.
 void Driver::build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild) {
   struct PS {
     Prob* P;
@@ -549,7 +561,9 @@ void Driver::build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild
   double* Qp = Qb.as<double>();
   {
     DBuf Gb(std::max<int64_t>(gwords, 1) * sizeof(double));
+    DBuf Qtb(std::max<int64_t>(qwords, 1) * sizeof(double));
     double* Gp = Gb.as<double>();
+    double* Qt = Qtb.as<double>();
     std::vector<GaussItem> gi;
     std::vector<int64_t> tp(1, 0);
     GemmBatch<double> gq;
@@ -567,7 +581,7 @@ void Driver::build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild
       }
       for (int k = 0; k < P->nb; ++k) {
         if (x.qoff[k] < 0) continue;
-        gq.item(Qp + x.qoff[k], m[k], m[k], x.C);
+        gq.item(Qt + x.qoff[k], m[k], m[k], x.C);
         for (int64_t e = np[k]; e < np[k + 1]; ++e) {
           const int j = ni[e];
           if (j == k || m[j] == 0) continue;
@@ -586,6 +600,19 @@ void Driver::build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild
       H2ULV_HIP(hipGetLastError());
     }
     gq.run(st, "sketch_q");
+    // Q'_k = D_kk^-1 Q_k
+    GemmBatch<double> gi2;
+    for (PS& x : ps) {
+      Prob* P = x.P;
+      const std::vector<int>& m = P->lf().m;
+      for (int k = 0; k < P->nb; ++k) {
+        if (x.qoff[k] < 0) continue;
+        gi2.one(Qp + x.qoff[k], m[k], m[k], x.C, m[k], P->Dinv.as<double>() + P->offSq[k], m[k],
+                false, Qt + x.qoff[k], m[k], false);
+        P->fl_fill += 2.0 * m[k] * (double)m[k] * x.C;
+      }
+    }
+    gi2.run(st, "sketch_q");
   }
   // per box: K(P_i, far)^T and Omega_far, then [Y^T; Z^T] (chunked by memory)
   std::vector<Box> order;
@@ -595,7 +622,8 @@ void Driver::build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild
       std::max<int64_t>((int64_t)(free_device_bytes() * 0.4) / (int64_t)sizeof(double), 1 << 20);
   auto box_words = [&](const Box& b) {
     const int64_t nf = (int64_t)b.P->farcols[b.i].size();
-    return nf * (b.P->lf().m[b.i] + b.P->lf().ell[b.i] + SKETCH_PROBES) + 4096;
+    const int64_t mi = b.P->lf().m[b.i], ci = b.P->lf().ell[b.i] + SKETCH_PROBES;
+    return nf * (mi + ci) + ci * mi + 4096;
   };
   size_t b0 = 0;
   while (b0 < order.size()) {
@@ -606,20 +634,23 @@ void Driver::build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild
       ++b1;
     }
     const size_t nc = b1 - b0;
-    std::vector<int64_t> koff(nc + 1, 0), ooff(nc + 1, 0), fc_all, fc_off(nc, 0);
+    std::vector<int64_t> koff(nc + 1, 0), ooff(nc + 1, 0), roff(nc + 1, 0), fc_all, fc_off(nc, 0);
     for (size_t q = 0; q < nc; ++q) {
       const Box& b = order[b0 + q];
       const int64_t nf = (int64_t)b.P->farcols[b.i].size();
+      const int64_t ci = b.P->lf().ell[b.i] + SKETCH_PROBES;
       koff[q + 1] = koff[q] + nf * b.P->lf().m[b.i];
-      ooff[q + 1] = ooff[q] + nf * (b.P->lf().ell[b.i] + SKETCH_PROBES);
+      ooff[q + 1] = ooff[q] + nf * ci;
+      roff[q + 1] = roff[q] + (b.P->lev < b.P->L() ? ci * b.P->lf().m[b.i] : 0);
       fc_off[q] = (int64_t)fc_all.size();
       for (int64_t c : b.P->farcols[b.i]) fc_all.push_back(c + b.P->poff);
     }
     DBuf Kb(std::max<int64_t>(koff.back(), 1) * sizeof(double));
     DBuf Ob(std::max<int64_t>(ooff.back(), 1) * sizeof(double));
+    DBuf Rb(std::max<int64_t>(roff.back(), 1) * sizeof(double));
     const int64_t* dfc = st.up(std::move(fc_all));
     KgenBatch kb;
-    GemmBatch<double> gs;
+    GemmBatch<double> gr, gs;
     std::vector<GaussItem> gi;
     std::vector<int64_t> tp(1, 0);
     for (size_t q = 0; q < nc; ++q) {
@@ -633,7 +664,8 @@ void Driver::build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild
       const int64_t nf = (int64_t)P->farcols[i].size();
       double* Kf = Kb.as<double>() + koff[q];
       double* Of = Ob.as<double>() + ooff[q];
-      gs.item(P->PQ.as<double>() + P->offSq[i], ci, ci, mi);
+      double* PQi = P->PQ.as<double>() + P->offSq[i];
+      const bool upper = P->lev < P->L();
       if (nf > 0) {
         kb.add(dfc + fc_off[q], (int)nf, P->candp(i), mi, Kf, nf);
         if (!rebuild) P->kevals += (double)mi * nf;
@@ -641,16 +673,36 @@ void Driver::build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild
                                sketch_key(p.sketch_seed, P->lev, STREAM_BASE + STREAM_FAR),
                                (int32_t)nf, ci});
         tp.push_back(tp.back() + tiles64(nf, ci));
-        gs.term(Of, nf, true, Kf, nf, false, (int)nf);
         P->fl_basis += 2.0 * (double)nf * mi * ci;
       }
+      // fill part sum_k Q'_k^T D_ik^T: straight into the sketch at the leaves,
+      // into R_i above them (then times T-hat^-T)
+      double* Ri = upper ? Rb.as<double>() + roff[q] : PQi;
       const auto& np = P->np();
       const auto& ni = P->ni();
+      if (upper) gr.item(Ri, ci, ci, mi);
+      else gs.item(PQi, ci, ci, mi);
+      GemmBatch<double>& gf = upper ? gr : gs;
+      if (!upper && nf > 0) gs.term(Of, nf, true, Kf, nf, false, (int)nf);
       for (int64_t e = np[i]; e < np[i + 1]; ++e) {
         const int k = ni[e];
         if (k == i || m[k] == 0) continue;
-        gs.term(Qp + x->qoff[k], m[k], true, P->Z.as<double>() + P->Doff[e], mi, true, m[k]);
+        gf.term(Qp + x->qoff[k], m[k], true, P->D.as<double>() + P->Doff[e], mi, true, m[k]);
         P->fl_fill += 2.0 * ci * (double)m[k] * mi;
+      }
+      if (upper) {
+        // [Y^T; Z^T](:, child c) = Omega_far^T K_far^T(:, c) + R_i(:, c) T_c^-T
+        const LevelFactor& ch = P->F->levels[P->lev + 1];
+        const int kc[2] = {ch.k[2 * i], ch.k[2 * i + 1]};
+        int c0 = 0;
+        for (int h = 0; h < 2; ++h) {
+          if (kc[h] == 0) continue;
+          gs.item(PQi + (int64_t)c0 * ci, ci, ci, kc[h]);
+          if (nf > 0) gs.term(Of, nf, true, Kf + (int64_t)c0 * nf, nf, false, (int)nf);
+          gs.term(Ri + (int64_t)c0 * ci, ci, false, P->Tinv.as<double>() + P->offTinv[2 * i + h],
+                  kc[h], true, kc[h]);
+          c0 += kc[h];
+        }
       }
     }
     kb.run(st, pts, kf, dup);
@@ -663,6 +715,7 @@ void Driver::build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild
       launch_gauss(dgi, dtp, nt, ngi, s);
       H2ULV_HIP(hipGetLastError());
     }
+    gr.run(st, "sketch");
     gs.run(st, "sketch");
     tick("c_sketch");
     st.sync();
@@ -1076,7 +1129,6 @@ std::vector<Box> Driver::check_sketches(Stage& st, const std::vector<Box>& boxes
 // ---- (c) the basis step up to the pivots: sketches and triangles, pivoted QR,
 // checks and fallback; then skeletons on the host
 void Driver::row_ids(Stage& st, const std::vector<Prob*>& G) {
-  basis_prepare(st, G);
   std::vector<Box> all, sk;
   for (Prob* P : G)
     for (int i = 0; i < P->nb; ++i) {
@@ -1117,11 +1169,16 @@ void Driver::row_ids(Stage& st, const std::vector<Prob*>& G) {
         b.P->lf().sk_state[b.i] = 2;
         clear(b);
       }
+      fill_z(st, full);
       build_triangles(st, full, true);
       pivot_boxes(st, full);
     }
   }
-  for (Prob* P : G) P->Z.reset();
+  for (Prob* P : G) {
+    P->Z.reset();
+    P->Dinv.reset();
+    P->Tinv.reset();
+  }
   check_dup();
   // pivots to the host: skeletons
   std::vector<std::vector<int32_t>> hp(G.size());
@@ -1594,6 +1651,7 @@ void Driver::level(const std::vector<Prob*>& G) {
   tick(nullptr);
   dense_blocks(st, G);
   tick("a_dense");
+  basis_prepare(st, G);
   fill_products(st, G);
   tick("b_zprod");
   row_ids(st, G);
