@@ -44,6 +44,10 @@ size_t cache_bytes();
 int64_t cache_oom_releases();
 // Free device memory as seen by the library: hipMemGetInfo plus cached blocks.
 size_t free_device_bytes();
+// Pinned host staging buffers, kept for reuse (hipHostMalloc pins pages and is
+// slow); a buffer goes back only after the work that reads it has finished.
+char* pinned_get(size_t bytes, size_t* got);
+void pinned_put(char* p, size_t bytes);
 struct CacheScope {
   CacheScope();
   ~CacheScope();
@@ -161,7 +165,7 @@ struct DescArena {
   std::vector<Chunk> chunks;
   ~DescArena() {
     for (auto& c : chunks)
-      if (c.host) (void)hipHostFree(c.host);
+      if (c.host) pinned_put(c.host, c.cap);
   }
   void* put(const void* src, size_t bytes, hipStream_t s) {
     size_t need = (bytes + 255) & ~(size_t)255;
@@ -173,11 +177,7 @@ struct DescArena {
       }
     if (!c) {
       Chunk nc;
-      nc.cap = std::max<size_t>(need, (size_t)32 << 20);
-      if (hipHostMalloc((void**)&nc.host, nc.cap, hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        fail(H2ULV_ERR_OOM, "pinned host allocation failed");
-      }
+      nc.host = pinned_get(std::max<size_t>(need, (size_t)32 << 20), &nc.cap);
       nc.dev.alloc(nc.cap);
       chunks.push_back(std::move(nc));
       c = &chunks.back();

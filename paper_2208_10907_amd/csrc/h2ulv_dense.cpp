@@ -101,6 +101,53 @@ void* cache_alloc(size_t bytes, size_t* got) {
   return p;
 }
 
+namespace {
+struct PinnedPool {
+  std::mutex mu;
+  std::multimap<size_t, char*> blocks;
+  size_t held = 0;
+};
+PinnedPool& pinned_pool() {
+  static PinnedPool pp;
+  return pp;
+}
+constexpr size_t PINNED_KEEP = (size_t)4 << 30;  // most pinned bytes kept for reuse
+}  // namespace
+
+char* pinned_get(size_t bytes, size_t* got) {
+  PinnedPool& pp = pinned_pool();
+  const size_t want = round_block(bytes);
+  {
+    std::lock_guard<std::mutex> lk(pp.mu);
+    auto it = pp.blocks.lower_bound(want);
+    if (it != pp.blocks.end() && it->first <= 2 * want) {
+      char* p = it->second;
+      *got = it->first;
+      pp.held -= it->first;
+      pp.blocks.erase(it);
+      return p;
+    }
+  }
+  char* p = nullptr;
+  if (hipHostMalloc((void**)&p, want, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(H2ULV_ERR_OOM, "pinned host allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  *got = want;
+  return p;
+}
+
+void pinned_put(char* p, size_t bytes) {
+  PinnedPool& pp = pinned_pool();
+  std::lock_guard<std::mutex> lk(pp.mu);
+  if (pp.held + bytes > PINNED_KEEP) {
+    (void)hipHostFree(p);
+    return;
+  }
+  pp.blocks.emplace(bytes, p);
+  pp.held += bytes;
+}
+
 void cache_free(void* p, size_t bytes) {
   DevCache& c = dev_cache();
   std::lock_guard<std::mutex> lk(c.mu);

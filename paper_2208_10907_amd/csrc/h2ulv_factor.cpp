@@ -136,6 +136,8 @@ struct Prob {
   DBuf D, Dinv, Tinv, Z, D32, PQ, pivd, kd, S;
   std::vector<std::vector<int>> targets;
   std::vector<std::vector<int64_t>> farcols;
+  std::vector<int64_t> far_off;  // box i's far columns at dfar + far_off[i]
+  DBuf dfar;
   std::vector<const double*> Eptr;  // E = R11^-1 R12 of each box and its leading dimension
   std::vector<int64_t> ldE;
   std::vector<DBuf> Ebufs;
@@ -149,6 +151,7 @@ struct Prob {
   int64_t nnear() const { return np()[nb]; }
   int64_t nfar() const { return fp()[nb]; }
   const int64_t* candp(int i) const { return dcand.as<int64_t>() + cand_off[i]; }
+  const int64_t* farp(int i) const { return dfar.as<int64_t>() + far_off[i]; }
   double* Dblk(int i, int j) { return D.as<double>() + Doff[csr_find(np(), ni(), i, j)]; }
 
   const double* shat_block(int clev, int c, int d, int64_t* ld) {
@@ -184,10 +187,11 @@ struct Prob {
     ncols.clear();
     targets.clear();
     farcols.clear();
+    far_off.clear();
     Eptr.clear();
     ldE.clear();
     Ebufs.clear();
-    for (DBuf* b : {&dcand, &D, &Dinv, &Tinv, &Z, &D32, &PQ, &pivd, &kd, &S}) b->reset();
+    for (DBuf* b : {&dcand, &dfar, &D, &Dinv, &Tinv, &Z, &D32, &PQ, &pivd, &kd, &S}) b->reset();
   }
 };
 
@@ -214,6 +218,11 @@ struct Driver {
     dupbuf.alloc(sizeof(int));
     dup = dupbuf.as<int>();
     H2ULV_HIP(hipMemsetAsync(dup, 0, sizeof(int), s));
+  }
+
+  // host-only time of a section (verbose mode)
+  void htime(const char* name, double t0) {
+    if (p.verbose) step_time[name] += now_s() - t0;
   }
 
   void tick(const char* name) {
@@ -438,9 +447,10 @@ void Driver::basis_prepare(Stage& st, const std::vector<Prob*>& G) {
     P->offSq.assign(nb + 1, 0);
     for (int i = 0; i < nb; ++i) P->offSq[i + 1] = P->offSq[i] + (int64_t)m[i] * m[i];
     const bool upper = P->lev < P->L();
-    for (int i = 0; i < nb; ++i) {
-      P->targets[i] = fill_targets(ls, P->lev, i);
-      P->farcols[i] = far_columns(P->F->tree, ls, P->lev, i, lf.cand, p.far_sample);
+    const double th = now_s();
+    parallel_for(nb, 8, [&](int64_t i) {
+      P->targets[i] = fill_targets(ls, P->lev, (int)i);
+      P->farcols[i] = far_columns(P->F->tree, ls, P->lev, (int)i, lf.cand, p.far_sample);
       int64_t nc = (int64_t)P->farcols[i].size();
       for (int j : P->targets[i]) nc += m[j];
       P->ncols[i] = nc;
@@ -450,9 +460,30 @@ void Driver::basis_prepare(Stage& st, const std::vector<Prob*>& G) {
         const int den = ch.m[2 * i] + ch.m[2 * i + 1];
         ratio = den > 0 ? (double)(ch.k[2 * i] + ch.k[2 * i + 1]) / den : 0.0;
       }
-      box_features(*P->F, P->lev, i, m[i], (int)P->targets[i].size(), nc, ratio,
+      box_features(*P->F, P->lev, (int)i, m[i], (int)P->targets[i].size(), nc, ratio,
                    lf.feat.data() + (size_t)i * MLP_NF);
+    });
+    // far-field columns of every box as indices into the shared point buffer,
+    // one device array for the level (staged through pinned memory that lives
+    // until the stage synchronises)
+    P->far_off.assign(nb + 1, 0);
+    for (int i = 0; i < nb; ++i)
+      P->far_off[i + 1] = P->far_off[i] + (int64_t)P->farcols[i].size();
+    const int64_t nfar = P->far_off[nb];
+    P->dfar.alloc(std::max<int64_t>(nfar, 1) * sizeof(int64_t));
+    if (nfar > 0) {
+      size_t got = 0;
+      char* hb = pinned_get(nfar * sizeof(int64_t), &got);
+      st.host.push_back(std::shared_ptr<void>(hb, [got](void* q) { pinned_put((char*)q, got); }));
+      int64_t* hf = reinterpret_cast<int64_t*>(hb);
+      const int64_t poff = P->poff;
+      parallel_for(nb, 8, [&](int64_t i) {
+        int64_t* o = hf + P->far_off[i];
+        for (int64_t c : P->farcols[i]) *o++ = c + poff;
+      });
+      H2ULV_HIP(hipMemcpyAsync(P->dfar.p, hb, nfar * sizeof(int64_t), hipMemcpyHostToDevice, s));
     }
+    htime("h_prepare", th);
     // mixed precision: the rotations, low-rank couplings and Schur updates run on
     // FP32 matrix cores with FP32 accumulation; the fill-in products stay FP64
     // because they feed the rank-revealing QR, whose decisions at tol ~1e-6 sit
@@ -634,7 +665,8 @@ void Driver::build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild
       ++b1;
     }
     const size_t nc = b1 - b0;
-    std::vector<int64_t> koff(nc + 1, 0), ooff(nc + 1, 0), roff(nc + 1, 0), fc_all, fc_off(nc, 0);
+    const double th = now_s();
+    std::vector<int64_t> koff(nc + 1, 0), ooff(nc + 1, 0), roff(nc + 1, 0);
     for (size_t q = 0; q < nc; ++q) {
       const Box& b = order[b0 + q];
       const int64_t nf = (int64_t)b.P->farcols[b.i].size();
@@ -642,13 +674,10 @@ void Driver::build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild
       koff[q + 1] = koff[q] + nf * b.P->lf().m[b.i];
       ooff[q + 1] = ooff[q] + nf * ci;
       roff[q + 1] = roff[q] + (b.P->lev < b.P->L() ? ci * b.P->lf().m[b.i] : 0);
-      fc_off[q] = (int64_t)fc_all.size();
-      for (int64_t c : b.P->farcols[b.i]) fc_all.push_back(c + b.P->poff);
     }
     DBuf Kb(std::max<int64_t>(koff.back(), 1) * sizeof(double));
     DBuf Ob(std::max<int64_t>(ooff.back(), 1) * sizeof(double));
     DBuf Rb(std::max<int64_t>(roff.back(), 1) * sizeof(double));
-    const int64_t* dfc = st.up(std::move(fc_all));
     KgenBatch kb;
     GemmBatch<double> gr, gs;
     std::vector<GaussItem> gi;
@@ -667,9 +696,9 @@ void Driver::build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild
       double* PQi = P->PQ.as<double>() + P->offSq[i];
       const bool upper = P->lev < P->L();
       if (nf > 0) {
-        kb.add(dfc + fc_off[q], (int)nf, P->candp(i), mi, Kf, nf);
+        kb.add(P->farp(i), (int)nf, P->candp(i), mi, Kf, nf);
         if (!rebuild) P->kevals += (double)mi * nf;
-        gi.push_back(GaussItem{Of, nf, dfc + fc_off[q], P->poff, P->F->n,
+        gi.push_back(GaussItem{Of, nf, P->farp(i), P->poff, P->F->n,
                                sketch_key(p.sketch_seed, P->lev, STREAM_BASE + STREAM_FAR),
                                (int32_t)nf, ci});
         tp.push_back(tp.back() + tiles64(nf, ci));
@@ -705,6 +734,7 @@ void Driver::build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild
         }
       }
     }
+    htime("h_sketch", th);
     kb.run(st, pts, kf, dup);
     if (!gi.empty()) {
       const int ngi = (int)gi.size();
@@ -757,13 +787,6 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
     }
     DBuf Mb(std::max<int64_t>(moff.back(), 1) * sizeof(double));
     double* Mp = Mb.as<double>();
-    std::vector<int64_t> fc_all, fc_off(nc, 0);
-    for (size_t q = 0; q < nc; ++q) {
-      const Box& b = full[b0 + q];
-      fc_off[q] = (int64_t)fc_all.size();
-      for (int64_t c : b.P->farcols[b.i]) fc_all.push_back(c + b.P->poff);
-    }
-    const int64_t* dfc = st.up(std::move(fc_all));
     KgenBatch kb;
     GemmBatch<double> g;
     for (size_t q = 0; q < nc; ++q) {
@@ -776,7 +799,7 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
       double* Mi = Mp + moff[q];
       const int64_t ld = P->ncols[i];
       const int64_t nf = (int64_t)P->farcols[i].size();
-      kb.add(dfc + fc_off[q], (int)nf, P->candp(i), m[i], Mi, ld);
+      kb.add(P->farp(i), (int)nf, P->candp(i), m[i], Mi, ld);
       // a rebuilt box (a rejected sketch) has had its kernel entries counted
       if (!rebuild) P->kevals += (double)m[i] * nf;
       int64_t row = nf;
@@ -1790,6 +1813,7 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
     F[q]->hpts = std::move(hp);
   }
   double t1 = now_s();
+  if (params.verbose) std::fprintf(stderr, "[h2ulv] host setup (tree, lists) %.3f s\n", t1 - t0);
   for (size_t q = 0; q < np; ++q) {
     h2ulv_factor& f = *F[q];
     f.pts.alloc(f.n * 3 * sizeof(double));

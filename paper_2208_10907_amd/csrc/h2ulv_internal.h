@@ -1,10 +1,13 @@
 // Internal declarations of the H^2-ULV library (not part of the C-ABI).
 #pragma once
 
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/h2ulv.h"
@@ -18,6 +21,33 @@ struct Error : std::runtime_error {
 };
 
 [[noreturn]] inline void fail(h2ulv_status s, const std::string& m) { throw Error(s, m); }
+
+// fn(i) for i in [0, n) on up to 16 host threads (the calling thread takes
+// part); iterations are handed out in blocks of `grain`.  fn must not throw.
+template <class Fn>
+void parallel_for(int64_t n, int64_t grain, Fn&& fn) {
+  if (n <= 0) return;
+  const int64_t hw = std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency());
+  const int64_t nt = std::min<int64_t>({16, hw, (n + grain - 1) / grain});
+  if (nt <= 1) {
+    for (int64_t i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::atomic<int64_t> next(0);
+  auto work = [&]() {
+    for (;;) {
+      const int64_t b = next.fetch_add(grain);
+      if (b >= n) break;
+      const int64_t e = std::min(n, b + grain);
+      for (int64_t i = b; i < e; ++i) fn(i);
+    }
+  };
+  std::vector<std::thread> th;
+  th.reserve(nt - 1);
+  for (int64_t t = 1; t < nt; ++t) th.emplace_back(work);
+  work();
+  for (auto& t : th) t.join();
+}
 
 // ---------------------------------------------------------------------------
 // Cluster tree (binary k-d tree, Sec. III-D) and strong-admissibility lists.

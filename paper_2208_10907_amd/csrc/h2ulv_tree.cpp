@@ -47,15 +47,18 @@ Tree build_tree(const double* pts, int64_t n, int leaf) {
   std::iota(t.perm.begin(), t.perm.end(), (int64_t)0);
   std::vector<std::pair<int64_t, int64_t>> ranges{{0, n}};
   for (int lev = 0; lev <= t.L; ++lev) {
-    size_t nb = ranges.size();
+    const size_t nb = ranges.size();
     t.start.emplace_back(nb);
     t.end.emplace_back(nb);
     t.centre.emplace_back(3 * nb);
     t.radius.emplace_back(nb);
-    std::vector<std::pair<int64_t, int64_t>> next;
-    next.reserve(2 * nb);
-    for (size_t b = 0; b < nb; ++b) {
-      int64_t a0 = ranges[b].first, a1 = ranges[b].second;
+    std::vector<std::pair<int64_t, int64_t>> next(lev < t.L ? 2 * nb : 0);
+    // boxes of a level are independent; each split orders its range by
+    // (coordinate, index) along the widest axis.  Only the last split's order
+    // survives (every level re-orders the ranges of the previous one), so the
+    // earlier splits only partition at the median.
+    parallel_for((int64_t)nb, 1, [&](int64_t b) {
+      const int64_t a0 = ranges[b].first, a1 = ranges[b].second;
       t.start[lev][b] = a0;
       t.end[lev][b] = a1;
       double lo[3], hi[3];
@@ -65,24 +68,28 @@ Tree build_tree(const double* pts, int64_t n, int leaf) {
         t.centre[lev][3 * b + c] = 0.5 * (lo[c] + hi[c]);
         d[c] = hi[c] - lo[c];
       }
-      double s = d[0] * d[0];
-      s = s + d[1] * d[1];
-      s = s + d[2] * d[2];
-      t.radius[lev][b] = 0.5 * std::sqrt(s);
+      double sq = d[0] * d[0];
+      sq = sq + d[1] * d[1];
+      sq = sq + d[2] * d[2];
+      t.radius[lev][b] = 0.5 * std::sqrt(sq);
       if (lev < t.L) {
         int axis = 0;
         if (d[1] > d[axis]) axis = 1;
         if (d[2] > d[axis]) axis = 2;
         int64_t* p = t.perm.data() + a0;
-        std::sort(p, p + (a1 - a0), [&](int64_t u, int64_t v) {
-          double cu = pts[u * 3 + axis], cv = pts[v * 3 + axis];
-          return cu < cv || (cu == cv && u < v);
-        });
-        int64_t mid = a0 + (a1 - a0) / 2;
-        next.push_back({a0, mid});
-        next.push_back({mid, a1});
+        const int64_t cnt = a1 - a0;
+        std::vector<std::pair<double, int64_t>> key(cnt);
+        for (int64_t u = 0; u < cnt; ++u) key[u] = {pts[p[u] * 3 + axis], p[u]};
+        const int64_t half = cnt / 2;
+        if (lev + 1 == t.L)
+          std::sort(key.begin(), key.end());
+        else if (half > 0)
+          std::nth_element(key.begin(), key.begin() + half, key.end());
+        for (int64_t u = 0; u < cnt; ++u) p[u] = key[u].second;
+        next[2 * b] = {a0, a0 + half};
+        next[2 * b + 1] = {a0 + half, a1};
       }
-    }
+    });
     ranges.swap(next);
   }
   return t;
