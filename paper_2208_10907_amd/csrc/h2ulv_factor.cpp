@@ -1020,9 +1020,22 @@ void Driver::pivot_boxes(Stage& st, const std::vector<Box>& boxes) {
     int64_t* dsp = st.up(std::move(sp));
     ProfScope ps("pivqr_large", 0, 0, s);
     launch_pivqr_init(dst_, dsp, ns, nbig, s);
+    // every 64 steps the stop flags come back to the host, and the loop ends
+    // once every box has stopped (ranks are usually well below the step cap)
+    std::vector<int32_t> fl(2 * nbox + 2);
     for (int t = 0; t < maxcap; ++t) {
       launch_pivqr_pick(dst_, nbig, t, s);
       launch_pivqr_apply(dst_, dsp, ns, nbig, t, s);
+      if ((t + 1) % 64 == 0 && t + 1 < maxcap) {
+        H2ULV_HIP(hipGetLastError());
+        H2ULV_HIP(hipMemcpyAsync(fl.data(), flg, fl.size() * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, s));
+        H2ULV_HIP(hipStreamSynchronize(s));
+        bool any = false;  // a large box (flags at 2 q) still running
+        for (size_t q = 0; q < nbox; ++q)
+          if (boxes[q].P->lf().m[boxes[q].i] > BIG && fl[2 * q] == 0) any = true;
+        if (!any) break;
+      }
     }
     H2ULV_HIP(hipGetLastError());
   }
