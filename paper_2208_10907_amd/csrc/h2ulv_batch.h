@@ -189,6 +189,41 @@ struct DescArena {
     H2ULV_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
     return d;
   }
+  // several arrays in one region and one copy; dev[i] receives part i's address
+  void put_parts(const void* const* src, const size_t* bytes, int nparts, void** dev,
+                 hipStream_t s) {
+    size_t off[8];
+    size_t tot = 0;
+    for (int i = 0; i < nparts; ++i) {
+      off[i] = tot;
+      tot += (bytes[i] + 255) & ~(size_t)255;
+    }
+    if (tot == 0) {
+      for (int i = 0; i < nparts; ++i) dev[i] = nullptr;
+      return;
+    }
+    Chunk* c = nullptr;
+    for (auto& ch : chunks)
+      if (ch.cap - ch.used >= tot) {
+        c = &ch;
+        break;
+      }
+    if (!c) {
+      Chunk nc;
+      nc.host = pinned_get(std::max<size_t>(tot, (size_t)32 << 20), &nc.cap);
+      nc.dev.alloc(nc.cap);
+      chunks.push_back(std::move(nc));
+      c = &chunks.back();
+    }
+    char* h = c->host + c->used;
+    char* d = c->dev.as<char>() + c->used;
+    for (int i = 0; i < nparts; ++i) {
+      if (bytes[i]) std::memcpy(h + off[i], src[i], bytes[i]);
+      dev[i] = bytes[i] ? d + off[i] : nullptr;
+    }
+    c->used += tot;
+    H2ULV_HIP(hipMemcpyAsync(d, h, tot, hipMemcpyHostToDevice, s));
+  }
   void recycle() {
     for (auto& c : chunks) c.used = 0;
   }
@@ -209,6 +244,27 @@ struct Stage {
   template <class T>
   T* up(const std::vector<T>& v) {
     return up(std::vector<T>(v));
+  }
+  // two or three arrays in one copy
+  template <class A, class B>
+  void up2(const std::vector<A>& a, const std::vector<B>& b, A** da, B** db) {
+    const void* src[2] = {a.data(), b.data()};
+    const size_t by[2] = {a.size() * sizeof(A), b.size() * sizeof(B)};
+    void* dv[2];
+    desc.put_parts(src, by, 2, dv, s);
+    *da = static_cast<A*>(dv[0]);
+    *db = static_cast<B*>(dv[1]);
+  }
+  template <class A, class B, class C>
+  void up3(const std::vector<A>& a, const std::vector<B>& b, const std::vector<C>& c, A** da,
+           B** db, C** dc) {
+    const void* src[3] = {a.data(), b.data(), c.data()};
+    const size_t by[3] = {a.size() * sizeof(A), b.size() * sizeof(B), c.size() * sizeof(C)};
+    void* dv[3];
+    desc.put_parts(src, by, 3, dv, s);
+    *da = static_cast<A*>(dv[0]);
+    *db = static_cast<B*>(dv[1]);
+    *dc = static_cast<C*>(dv[2]);
   }
   template <class T>
   T* scratch(size_t count, bool zero = false) {
@@ -314,9 +370,10 @@ struct GemmBatch {
         }
     if (profiler().on)
       for (auto& it : its) by += (double)it.M * it.N * sizeof(TC) * (it.beta != 0.0 ? 2 : 1);
-    auto* di = st.up(std::move(its));
-    auto* dt = st.up(std::move(terms));
-    auto* dp = st.up(std::move(tp));
+    GemmItem<TC>* di;
+    GemmTerm<T>* dt;
+    int64_t* dp;
+    st.up3(its, terms, tp, &di, &dt, &dp);
     terms.clear();
     ProfScope ps(profiler().on ? profile_name(sizeof(T) == 8 ? "gemm_f64" : "gemm_f32", site)
                                : "",
@@ -340,8 +397,9 @@ struct KgenBatch {
     int ni = (int)items.size();
     double ev = 0;
     for (auto& it : items) ev += (double)it.m * it.n;
-    auto* di = st.up(std::move(items));
-    auto* dp = st.up(std::move(tp));
+    KgenItem* di;
+    int64_t* dp;
+    st.up2(items, tp, &di, &dp);
     items.clear();
     ProfScope ps("kgen", ev, ev * 8.0, st.s);
     launch_kgen(di, dp, nt, ni, pts, kf, dup, st.s);
@@ -365,8 +423,9 @@ struct CopyBatch {
     int ni = (int)items.size();
     double by = 0;
     for (auto& it : items) by += 16.0 * it.rows * it.cols;
-    auto* di = st.up(std::move(items));
-    auto* dp = st.up(std::move(tp));
+    CopyItem* di;
+    int64_t* dp;
+    st.up2(items, tp, &di, &dp);
     items.clear();
     ProfScope ps("copy", 0, by, st.s);
     launch_copy(di, dp, nt, ni, alpha, beta, st.s);
