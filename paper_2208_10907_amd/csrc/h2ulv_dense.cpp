@@ -451,7 +451,7 @@ void batched_triu_inverse(Stage& st, const std::vector<SqMat>& mats) {
 void batched_qr_R(Stage& st, const std::vector<TallQr>& ms) {
   if (ms.empty()) return;
   const int nb = QR_NB;
-  int maxk = 0;
+  int maxk = 0, maxh = 0;
   std::vector<MatDesc> ds;
   std::vector<double*> Vb, Tfb, Y1b, Y2b;
   int64_t sv = 0, sa = 0, sy = 0;
@@ -486,6 +486,7 @@ void batched_qr_R(Stage& st, const std::vector<TallQr>& ms) {
     sy += (int64_t)nb * std::max(a.m, 1);
     ds.push_back(d);
     maxk = std::max(maxk, std::min(a.h, a.m));
+    maxh = std::max(maxh, a.h);
   }
   const int nmat = (int)ms.size();
   MatDesc* dd = st.up(std::move(ds));
@@ -495,7 +496,7 @@ void batched_qr_R(Stage& st, const std::vector<TallQr>& ms) {
       for (auto& a : ms)
         if (std::min(a.h, a.m) > j0) fl += 2.0 * (a.h - j0) * (double)nb * nb;
       ProfScope ps("qr_panel:tsqr", fl, 0, st.s);
-      launch_qr_panel(dd, nmat, j0, nb, st.s);
+      launch_qr_panel(dd, nmat, j0, nb, maxh - j0, st.s);
     }
     H2ULV_HIP(hipGetLastError());
     GemmBatch<double> g1, g2, g3;
@@ -523,7 +524,7 @@ void batched_qr_R(Stage& st, const std::vector<TallQr>& ms) {
 void batched_qr_basis(Stage& st, const std::vector<QrW>& ws) {
   if (ws.empty()) return;
   const int nb = QR_NB;
-  int maxk = 0;
+  int maxk = 0, maxh = 0;
   std::vector<MatDesc> ds;
   std::vector<double*> Vb, Tfb, Y1b, Y2b;
   int64_t sv = 0, sa = 0, st_ = 0, sy = 0;
@@ -560,13 +561,14 @@ void batched_qr_basis(Stage& st, const std::vector<QrW>& ws) {
     sy += (int64_t)nb * std::max(std::max(w.m, w.k), 1);
     ds.push_back(d);
     maxk = std::max(maxk, std::min(w.k, w.m));
+    maxh = std::max(maxh, w.m);
   }
   const int nmat = (int)ws.size();
   MatDesc* dd = st.up(std::move(ds));
   for (int j0 = 0; j0 < maxk; j0 += nb) {
     {
       ProfScope ps("qr_panel:qrbasis", 0, 0, st.s);
-      launch_qr_panel(dd, nmat, j0, nb, st.s);
+      launch_qr_panel(dd, nmat, j0, nb, maxh - j0, st.s);
     }
     H2ULV_HIP(hipGetLastError());
     GemmBatch<double> g1, g2, g3;

@@ -128,7 +128,8 @@ void launch_lu_swap_trsm(const MatDesc* d, const int64_t* slab_ptr, int64_t nsla
                          int j0, int nb, hipStream_t s);
 void launch_trinv_diag(const MatDesc* d, const int64_t* blk_ptr, int64_t nblk, int nmat, int nb,
                        int upper, double* out, const int64_t* out_off, hipStream_t s);
-void launch_qr_panel(const MatDesc* d, int nmat, int j0, int nb, hipStream_t s);
+// maxrows: largest m - j0 over the matrices (selects the register-resident panel)
+void launch_qr_panel(const MatDesc* d, int nmat, int j0, int nb, int maxrows, hipStream_t s);
 void launch_pivqr_init(const PivQrState* st, const int64_t* slab_ptr, int64_t nslabs, int n,
                        hipStream_t s);
 void launch_pivqr_pick(const PivQrState* st, int n, int t, hipStream_t s);

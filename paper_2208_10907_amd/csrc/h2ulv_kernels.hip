@@ -844,10 +844,184 @@ __global__ __launch_bounds__(64 * NW) void qr_panel_kernel(const MatDesc* __rest
   }
 }
 
-void launch_qr_panel(const MatDesc* d, int nmat, int j0, int nb, hipStream_t s) {
+// The same Householder panel with each group of QRP_G columns staged in LDS
+// (at most QRP_MAXROWS rows from row j0; panel width at most 32), 16 waves.
+// Left-looking over the groups: a group is loaded once, the panel's earlier
+// reflectors are applied to it as a block (A_g -= V T^T V^T A_g), its columns
+// are factored in LDS, and it is written back with its explicit reflectors;
+// the T columns of the group come from V^T v.  Dot products over rows are
+// taken by one wave each (lanes over rows, then a wave sum).
+constexpr int QRP_G = 4;
+constexpr int QRP_MAXROWS = 4096;
+
+__global__ __launch_bounds__(1024) void qr_panel_lds_kernel(const MatDesc* __restrict__ ds, int j0,
+                                                            int nb) {
+  __shared__ double s_a[QRP_G * QRP_MAXROWS];  // group column c at s_a + c * QRP_MAXROWS
+  __shared__ double s_y[32 * QRP_G], s_z[32 * QRP_G];
+  __shared__ double s_T[32][33];
+  __shared__ double s_dot[QRP_G];
+  __shared__ double s_sc[3];  // tau, scale, beta of the current column
+  const MatDesc d = ds[blockIdx.x];
+  const int m = d.m, n = d.n;
+  if (n <= j0 || m <= j0) return;
+  const int w = min(nb, min(n, m) - j0);
+  const int h = m - j0;
+  const int64_t lda = d.lda;
+  double* P = d.A + j0 + (int64_t)j0 * lda;  // P(r, c) = P[r + c lda]
+  double* V = d.panel_ws ? d.V : d.V + (int64_t)j0 * m;  // column c at V + c m, full rows
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int e = tid; e < 32 * 33; e += 1024) (&s_T[0][0])[e] = 0.0;
+  for (int g0 = 0; g0 < w; g0 += QRP_G) {
+    const int gw = min(QRP_G, w - g0);
+    for (int c = 0; c < gw; ++c)
+      for (int r = tid; r < h; r += 1024) s_a[c * QRP_MAXROWS + r] = P[r + (int64_t)(g0 + c) * lda];
+    __syncthreads();
+    if (g0 > 0) {
+      // Y = V_p^T A_g: wave per reflector k (V_p(r, k) = 0 for r < k)
+      for (int k = wv; k < g0; k += 16) {
+        const double* vk = V + j0 + (int64_t)k * m;
+        double acc[QRP_G] = {0.0, 0.0, 0.0, 0.0};
+        for (int r = k + lane; r < h; r += 64) {
+          const double vv = vk[r];
+#pragma unroll
+          for (int c = 0; c < QRP_G; ++c) acc[c] += vv * s_a[c * QRP_MAXROWS + r];
+        }
+#pragma unroll
+        for (int c = 0; c < QRP_G; ++c) {
+          const double t = wave_sum(acc[c]);
+          if (lane == 0) s_y[k * QRP_G + c] = t;
+        }
+      }
+      __syncthreads();
+      // Z = T^T Y
+      if (tid < g0 * QRP_G) {
+        const int k = tid / QRP_G, c = tid % QRP_G;
+        double z = 0.0;
+        for (int l = 0; l <= k; ++l) z += s_T[l][k] * s_y[l * QRP_G + c];
+        s_z[tid] = z;
+      }
+      __syncthreads();
+      // A_g -= V_p Z, thread per row
+      for (int r = tid; r < h; r += 1024) {
+        double acc[QRP_G] = {0.0, 0.0, 0.0, 0.0};
+        const int kend = min(g0, r + 1);
+        for (int k = 0; k < kend; ++k) {
+          const double vv = V[(j0 + r) + (int64_t)k * m];
+#pragma unroll
+          for (int c = 0; c < QRP_G; ++c) acc[c] += vv * s_z[k * QRP_G + c];
+        }
+#pragma unroll
+        for (int c = 0; c < QRP_G; ++c)
+          if (c < gw) s_a[c * QRP_MAXROWS + r] -= acc[c];
+      }
+      __syncthreads();
+    }
+    // factor the group's columns
+    for (int jj = 0; jj < gw; ++jj) {
+      const int col = g0 + jj;
+      double* a = s_a + jj * QRP_MAXROWS;
+      if (wv == 0) {
+        double part = 0.0;
+        for (int r = col + 1 + lane; r < h; r += 64) part += a[r] * a[r];
+        const double xn2 = wave_sum(part);
+        if (lane == 0) {
+          const double alpha = a[col];
+          double tau = 0.0, scale = 0.0, beta = alpha;
+          if (xn2 != 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+          }
+          s_sc[0] = tau;
+          s_sc[1] = scale;
+          s_sc[2] = beta;
+          s_T[col][col] = tau;
+          d.aux[j0 + col] = tau;
+        }
+      }
+      __syncthreads();
+      const double tau = s_sc[0], scale = s_sc[1];
+      if (tau != 0.0) {
+        for (int r = col + 1 + tid; r < h; r += 1024) a[r] *= scale;
+        if (tid == 0) a[col] = s_sc[2];
+      }
+      __syncthreads();
+      if (tau != 0.0 && jj + 1 < gw) {
+        // dot_c = a_c(col) + sum_{r > col} v(r) a_c(r), wave per later column
+        if (wv < gw - jj - 1) {
+          const int c = jj + 1 + wv;
+          const double* ac = s_a + c * QRP_MAXROWS;
+          double part = 0.0;
+          for (int r = col + 1 + lane; r < h; r += 64) part += a[r] * ac[r];
+          const double dsum = wave_sum(part);
+          if (lane == 0) s_dot[c] = dsum + ac[col];
+        }
+        __syncthreads();
+        for (int r = col + tid; r < h; r += 1024) {
+          const double vr = r == col ? 1.0 : a[r];
+          for (int c = jj + 1; c < gw; ++c) s_a[c * QRP_MAXROWS + r] -= tau * s_dot[c] * vr;
+        }
+        __syncthreads();
+      }
+    }
+    // write the group back (R above and on the diagonal, v below) and its
+    // explicit reflectors (zero above the unit entry, full rows)
+    for (int c = 0; c < gw; ++c) {
+      const int col = g0 + c;
+      const double* ac = s_a + c * QRP_MAXROWS;
+      double* vc = V + (int64_t)col * m;
+      for (int r = tid; r < h; r += 1024) {
+        P[r + (int64_t)col * lda] = ac[r];
+        vc[j0 + r] = r < col ? 0.0 : (r == col ? 1.0 : ac[r]);
+      }
+      for (int r = tid; r < j0; r += 1024) vc[r] = 0.0;
+    }
+    // T columns of the group: T(0:k, k) = -tau_k T(0:k, 0:k) (V(:, 0:k)^T v_k);
+    // wave per earlier column l, the group's own columns from LDS
+    const int kmax = g0 + gw - 1;
+    for (int l = wv; l < kmax; l += 16) {
+      double acc[QRP_G] = {0.0, 0.0, 0.0, 0.0};
+      const bool own = l >= g0;
+      const double* vl = own ? s_a + (l - g0) * QRP_MAXROWS : V + j0 + (int64_t)l * m;
+      for (int r = l + 1 + lane; r < h; r += 64) {
+        const double x = vl[r];
+#pragma unroll
+        for (int c = 0; c < QRP_G; ++c) {
+          const int k = g0 + c;
+          if (c < gw && k > l && r >= k) acc[c] += x * (r == k ? 1.0 : s_a[c * QRP_MAXROWS + r]);
+        }
+      }
+      // the unit entry of v_l at row l meets v_k(l) = 0 for k > l
+#pragma unroll
+      for (int c = 0; c < QRP_G; ++c) {
+        const double t = wave_sum(acc[c]);
+        if (lane == 0) s_y[l * QRP_G + c] = t;
+      }
+    }
+    __syncthreads();
+    for (int c = 0; c < gw; ++c) {  // column k needs T(0:k, 0:k): one column at a time
+      const int k = g0 + c;
+      if (tid < k) {
+        double acc = 0.0;
+        for (int l2 = tid; l2 < k; ++l2) acc += s_T[tid][l2] * s_y[l2 * QRP_G + c];
+        s_T[tid][k] = -s_T[k][k] * acc;
+      }
+      __syncthreads();
+    }
+  }
+  double* Tf = d.panel_ws ? d.Tf : d.Tf + (int64_t)(j0 / nb) * nb * nb;
+  for (int e = tid; e < nb * nb; e += 1024) {
+    const int l = e % nb, k = e / nb;
+    Tf[e] = (l < w && k < w && l <= k) ? s_T[l][k] : 0.0;
+  }
+}
+
+void launch_qr_panel(const MatDesc* d, int nmat, int j0, int nb, int maxrows, hipStream_t s) {
   if (nmat <= 0) return;
-  // 16 waves: each step updates 16 trailing panel columns at once
-  hipLaunchKernelGGL(qr_panel_kernel<16>, dim3(nmat), dim3(1024), 0, s, d, j0, nb);
+  if (maxrows <= QRP_MAXROWS && nb <= 32)
+    hipLaunchKernelGGL(qr_panel_lds_kernel, dim3(nmat), dim3(1024), 0, s, d, j0, nb);
+  else  // 16 waves: each step updates 16 trailing panel columns at once
+    hipLaunchKernelGGL(qr_panel_kernel<16>, dim3(nmat), dim3(1024), 0, s, d, j0, nb);
 }
 
 
