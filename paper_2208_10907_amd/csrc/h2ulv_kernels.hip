@@ -1482,14 +1482,14 @@ void launch_copy(const CopyItem* items, const int64_t* tile_ptr, int64_t ntiles,
 // Exact matvec y = A x with A generated on the fly in float64 (residuals of the
 // iterative refinement).  One thread per row; source points staged in LDS.
 // ---------------------------------------------------------------------------
-// 1/r to full double precision: the hardware reciprocal square root (about 23
-// correct bits) followed by two Newton steps y <- y (3 - r2 y^2) / 2.
+// 1/r to full double precision: the hardware reciprocal square root y (about 23
+// correct bits, so e = 1 - r2 y^2 is below 2^-22) corrected by the series
+// (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + O(e^3): y (1 + e (1/2 + 3e/8)), whose
+// truncation error is of order e^3 (below 2^-66).
 __device__ __forceinline__ double inv_sqrt(double r2) {
-  double y = __builtin_amdgcn_rsq(r2);
-  double e = fma(-r2 * y, y, 1.0);
-  y = fma(0.5 * y, e, y);
-  e = fma(-r2 * y, y, 1.0);
-  return fma(0.5 * y, e, y);
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double e = fma(-r2 * y, y, 1.0);
+  return fma(y, e * fma(0.375, e, 0.5), y);
 }
 
 // Exact y = A x with the matrix generated on the fly.  Each thread owns two
