@@ -24,7 +24,8 @@ HIP_FLAGS = ["-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]
 SOURCES = [
-    ("h2ulv_kernels.hip", []),
+    # MFMA accumulators in ordinary VGPRs (no copies between register files in the K loop)
+    ("h2ulv_kernels.hip", ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]),
     ("h2ulv_learned.hip", []),
     ("h2ulv_rankmodel.cpp", ["-x", "hip"]),
     ("h2ulv_dense.cpp", ["-x", "hip"]),

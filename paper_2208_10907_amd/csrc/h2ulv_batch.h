@@ -335,26 +335,55 @@ struct GemmBatch {
       terms.clear();
       return;
     }
-    // tile shape (measured on gfx950): FP64 64 x 64 (the 128 x 128 variant runs one
-    // wave per SIMD and is slower); FP32 128 x 128 when the items fill the tiles;
-    // 32 x 128 when every item has at most 32 rows (Householder V^T A products)
-    double useful = 0, cover128 = 0;
-    int64_t n128 = 0;
+    // tile shape: 32 x 128 when every item has at most 32 rows (Householder
+    // V^T A products); otherwise the shape with the best estimated rate, i.e.
+    // the measured rate of the shape on full tiles (gfx950, TFLOP/s) times the
+    // useful fraction of its padded tiles, scaled down when the batch has fewer
+    // tiles than the chip has resident workgroup slots for that shape
+    struct Shape {
+      int tm, tn;
+      double rate;
+      int per_cu;  // resident workgroups per CU
+    };
+    static const Shape f64s[4] = {{64, 64, 53.5, 4}, {64, 128, 56.6, 3}, {128, 64, 56.1, 3},
+                                  {128, 128, 57.9, 2}};
+    static const Shape f32s[2] = {{64, 64, 96.8, 8}, {128, 128, 112.1, 3}};
+    const Shape* cand = sizeof(T) == 8 ? f64s : f32s;
+    const int ncand = sizeof(T) == 8 ? 4 : 2;
     int maxM = 0;
-    for (auto& it : its) {
-      useful += (double)it.M * it.N;
-      int64_t t = tiles_of(it.M, it.N, 128);
-      n128 += t;
-      cover128 += 16384.0 * t;
-      maxM = std::max(maxM, it.M);
+    std::vector<double> ksum(its.size(), 0.0);
+    for (size_t i = 0; i < its.size(); ++i) {
+      maxM = std::max(maxM, its[i].M);
+      for (int t = its[i].t0; t < its[i].t0 + its[i].nt; ++t) ksum[i] += terms[t].K;
     }
-    int tile = 64;
-    if (maxM <= 32)
-      tile = 32;
-    else if (sizeof(T) == 4 && n128 >= 512 && useful >= 0.6 * cover128)
-      tile = 128;
+    int tm = 64, tn = 64;
+    if (maxM <= 32) {
+      tm = 32;
+      tn = 128;
+    } else {
+      double best = -1.0;
+      for (int c = 0; c < ncand; ++c) {
+        double useful = 0, padded = 0;
+        int64_t nt = 0;
+        for (size_t i = 0; i < its.size(); ++i) {
+          const int64_t a = (its[i].M + cand[c].tm - 1) / cand[c].tm;
+          const int64_t b = (its[i].N + cand[c].tn - 1) / cand[c].tn;
+          nt += a * b;
+          const double kk = std::max(ksum[i], 1.0);
+          useful += (double)its[i].M * its[i].N * kk;
+          padded += (double)(a * cand[c].tm) * (b * cand[c].tn) * kk;
+        }
+        const double fill = std::min(1.0, (double)nt / (256.0 * cand[c].per_cu));
+        const double score = cand[c].rate * (useful / padded) * fill;
+        if (score > best) {
+          best = score;
+          tm = cand[c].tm;
+          tn = cand[c].tn;
+        }
+      }
+    }
     auto ntile = [&](const GemmItem<TC>& it) {
-      return tile == 32 ? (int64_t)((it.N + 127) / 128) : tiles_of(it.M, it.N, tile);
+      return (int64_t)((it.M + tm - 1) / tm) * ((it.N + tn - 1) / tn);
     };
     std::vector<int64_t> tp(its.size() + 1, 0);
     for (size_t i = 0; i < its.size(); ++i) tp[i + 1] = tp[i] + ntile(its[i]);
@@ -378,7 +407,7 @@ struct GemmBatch {
     ProfScope ps(profiler().on ? profile_name(sizeof(T) == 8 ? "gemm_f64" : "gemm_f32", site)
                                : "",
                  fl, by, st.s);
-    launch_gemm<T, TC>(di, dt, dp, nt, ni, tile, st.s);
+    launch_gemm<T, TC>(di, dt, dp, nt, ni, tm, tn, st.s);
     H2ULV_HIP(hipGetLastError());
   }
 };

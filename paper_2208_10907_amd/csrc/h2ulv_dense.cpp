@@ -214,7 +214,8 @@ Profiler& profiler() {
   return p;
 }
 
-static constexpr int LU_NB = 64;   // LU panel / triangular block width
+static constexpr int LU_NB = 64;   // triangular block width
+static constexpr int LU_PANEL = 64;  // LU panel width
 static constexpr int QR_NB = 32;   // Householder panel width
 
 // X = L^-1 B (L unit lower) by blocks of LU_NB rows; B is overwritten.
@@ -318,7 +319,7 @@ void trsm_upper(Stage& st, const std::vector<TriRhs>& sys) {
 void batched_lu(Stage& st, const std::vector<SqMat>& mats, int32_t* ipiv, int32_t* info,
                 const std::vector<int64_t>& ipiv_off) {
   if (mats.empty()) return;
-  const int nb = LU_NB;
+  const int nb = LU_PANEL;
   int maxm = 0;
   std::vector<MatDesc> ds;
   for (size_t b = 0; b < mats.size(); ++b) {

@@ -119,9 +119,10 @@ struct WpItem {
 void launch_kgen(const KgenItem* items, const int64_t* tile_ptr, int64_t ntiles, int nitems,
                  const double* pts, KernelFn kf, int* dup_flag, hipStream_t s);
 // TI: operand / MFMA type (f64 or f32, accumulation in that type); TC: type of C.
+// Tile shapes tm x tn: 64 x 64, 64 x 128, 128 x 64, 128 x 128, 32 x 128.
 template <typename TI, typename TC>
 void launch_gemm(const GemmItem<TC>* items, const GemmTerm<TI>* terms, const int64_t* tile_ptr,
-                 int64_t ntiles, int nitems, int tile, hipStream_t s);
+                 int64_t ntiles, int nitems, int tm, int tn, hipStream_t s);
 // maxrows: largest m - j0 over the matrices (selects the register-resident panel)
 void launch_lu_panel(const MatDesc* d, int nmat, int j0, int nb, int maxrows, hipStream_t s);
 void launch_lu_swap_trsm(const MatDesc* d, const int64_t* slab_ptr, int64_t nslabs, int nmat,

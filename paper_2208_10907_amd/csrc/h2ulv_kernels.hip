@@ -143,6 +143,15 @@ struct Mfma<float> {
   }
 };
 
+// Load through a global (address space 1) pointer: operand pointers read from
+// descriptor tables are generic, and generic (flat) loads also count against
+// the LDS wait counter, which would make every LDS wait of the GEMM wait for
+// the next tile's global loads as well.
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
 // C = beta C + alpha sum_t op(A_t) op(B_t) for a batch of items of any size.
 // A workgroup (4 waves, 2 x 2, each a (TM/2) x (TN/2) block of 16 x 16 MFMA
 // accumulators) owns a TM x TN tile of one item (found
@@ -178,20 +187,19 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<TC>* __restric
 #pragma unroll
     for (int b = 0; b < BN; ++b) acc[a][b] = v4{0, 0, 0, 0};
   T ra[LA], rb[LB];
-  auto load = [&](int t, int k0) {
-    const GemmTerm<T>& tt = terms[t];
+  auto load = [&](const GemmTerm<T>& tt, int k0) {
     const bool kin = k0 + 16 <= tt.K;
     if (!(tt.flags & 1)) {
       const int i = tid % TM, kb = tid / TM;
       const T* p = tt.A + (row0 + i) + (int64_t)(k0 + kb) * tt.lda;
       if (rows_in && kin) {
 #pragma unroll
-        for (int r = 0; r < LA; ++r) ra[r] = p[(int64_t)((256 / TM) * r) * tt.lda];
+        for (int r = 0; r < LA; ++r) ra[r] = gload(p + (int64_t)((256 / TM) * r) * tt.lda);
       } else {
 #pragma unroll
         for (int r = 0; r < LA; ++r) {
           const int kk = kb + (256 / TM) * r, gi = row0 + i, gk = k0 + kk;
-          ra[r] = (gi < it.M && gk < tt.K) ? tt.A[gi + (int64_t)gk * tt.lda] : T(0);
+          ra[r] = (gi < it.M && gk < tt.K) ? gload(tt.A + gi + (int64_t)gk * tt.lda) : T(0);
         }
       }
     } else {
@@ -199,12 +207,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<TC>* __restric
       const T* p = tt.A + (k0 + kk) + (int64_t)(row0 + ib) * tt.lda;
       if (rows_in && kin) {
 #pragma unroll
-        for (int r = 0; r < LA; ++r) ra[r] = p[(int64_t)(16 * r) * tt.lda];
+        for (int r = 0; r < LA; ++r) ra[r] = gload(p + (int64_t)(16 * r) * tt.lda);
       } else {
 #pragma unroll
         for (int r = 0; r < LA; ++r) {
           const int i = ib + 16 * r, gi = row0 + i, gk = k0 + kk;
-          ra[r] = (gi < it.M && gk < tt.K) ? tt.A[gk + (int64_t)gi * tt.lda] : T(0);
+          ra[r] = (gi < it.M && gk < tt.K) ? gload(tt.A + gk + (int64_t)gi * tt.lda) : T(0);
         }
       }
     }
@@ -213,12 +221,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<TC>* __restric
       const T* p = tt.B + (k0 + kk) + (int64_t)(col0 + jb) * tt.ldb;
       if (cols_in && kin) {
 #pragma unroll
-        for (int r = 0; r < LB; ++r) rb[r] = p[(int64_t)(16 * r) * tt.ldb];
+        for (int r = 0; r < LB; ++r) rb[r] = gload(p + (int64_t)(16 * r) * tt.ldb);
       } else {
 #pragma unroll
         for (int r = 0; r < LB; ++r) {
           const int j = jb + 16 * r, gj = col0 + j, gk = k0 + kk;
-          rb[r] = (gj < it.N && gk < tt.K) ? tt.B[gk + (int64_t)gj * tt.ldb] : T(0);
+          rb[r] = (gj < it.N && gk < tt.K) ? gload(tt.B + gk + (int64_t)gj * tt.ldb) : T(0);
         }
       }
     } else {
@@ -226,18 +234,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<TC>* __restric
       const T* p = tt.B + (col0 + j) + (int64_t)(k0 + kb) * tt.ldb;
       if (cols_in && kin) {
 #pragma unroll
-        for (int r = 0; r < LB; ++r) rb[r] = p[(int64_t)((256 / TN) * r) * tt.ldb];
+        for (int r = 0; r < LB; ++r) rb[r] = gload(p + (int64_t)((256 / TN) * r) * tt.ldb);
       } else {
 #pragma unroll
         for (int r = 0; r < LB; ++r) {
           const int kk = kb + (256 / TN) * r, gj = col0 + j, gk = k0 + kk;
-          rb[r] = (gj < it.N && gk < tt.K) ? tt.B[gj + (int64_t)gk * tt.ldb] : T(0);
+          rb[r] = (gj < it.N && gk < tt.K) ? gload(tt.B + gj + (int64_t)gk * tt.ldb) : T(0);
         }
       }
     }
   };
-  auto store = [&](int t, int buf) {
-    const GemmTerm<T>& tt = terms[t];
+  auto store = [&](const GemmTerm<T>& tt, int buf) {
     if (!(tt.flags & 1)) {
       const int i = tid % TM, kb = tid / TM;
 #pragma unroll
@@ -261,19 +268,24 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<TC>* __restric
   const int tend = it.t0 + it.nt;
   while (t < tend && terms[t].K <= 0) ++t;
   if (t < tend) {
+    // the current term's descriptor stays in registers; the table is read again
+    // only when the K loop moves on to the next term
+    GemmTerm<T> tc = terms[t];
     int k0 = 0, cur = 0;
-    load(t, k0);
-    store(t, 0);
+    load(tc, k0);
+    store(tc, 0);
     __syncthreads();
     for (;;) {
       int tn = t, kn = k0 + 16;
-      if (kn >= terms[tn].K) {
+      GemmTerm<T> tx = tc;
+      if (kn >= tc.K) {
         kn = 0;
         ++tn;
         while (tn < tend && terms[tn].K <= 0) ++tn;
+        if (tn < tend) tx = terms[tn];
       }
       const bool more = tn < tend;
-      if (more) load(tn, kn);
+      if (more) load(tx, kn);
       T av[2][BM], bv[2][BN];
       {
         const int kk = lane >> 4;
@@ -299,11 +311,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<TC>* __restric
           for (int b = 0; b < BN; ++b) acc[a][b] = Mfma<T>::mac(av[s & 1][a], bv[s & 1][b], acc[a][b]);
       }
       if (!more) break;
-      store(tn, cur ^ 1);
+      store(tx, cur ^ 1);
       __syncthreads();
       cur ^= 1;
       t = tn;
       k0 = kn;
+      tc = tx;
     }
   }
   const TC alpha = (TC)it.alpha, beta = (TC)it.beta;
@@ -326,24 +339,26 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<TC>* __restric
 
 template <typename TI, typename TC>
 void launch_gemm(const GemmItem<TC>* items, const GemmTerm<TI>* terms, const int64_t* tile_ptr,
-                 int64_t ntiles, int nitems, int tile, hipStream_t s) {
+                 int64_t ntiles, int nitems, int tm, int tn, hipStream_t s) {
   if (ntiles <= 0) return;
-  if (tile == 128)
-    hipLaunchKernelGGL((gemm_kernel<TI, TC, 128, 128>), dim3((unsigned)ntiles), dim3(256), 0, s,
-                       items, terms, tile_ptr, nitems);
-  else if (tile == 32)  // 32 x 128 tiles for batches whose items have M <= 32
-    hipLaunchKernelGGL((gemm_kernel<TI, TC, 32, 128>), dim3((unsigned)ntiles), dim3(256), 0, s,
-                       items, terms, tile_ptr, nitems);
+  const dim3 g((unsigned)ntiles), b(256);
+  if (tm == 32)  // 32 x 128 tiles for batches whose items have M <= 32
+    hipLaunchKernelGGL((gemm_kernel<TI, TC, 32, 128>), g, b, 0, s, items, terms, tile_ptr, nitems);
+  else if (tm == 128 && tn == 128)
+    hipLaunchKernelGGL((gemm_kernel<TI, TC, 128, 128>), g, b, 0, s, items, terms, tile_ptr, nitems);
+  else if (tm == 128)
+    hipLaunchKernelGGL((gemm_kernel<TI, TC, 128, 64>), g, b, 0, s, items, terms, tile_ptr, nitems);
+  else if (tn == 128)
+    hipLaunchKernelGGL((gemm_kernel<TI, TC, 64, 128>), g, b, 0, s, items, terms, tile_ptr, nitems);
   else
-    hipLaunchKernelGGL((gemm_kernel<TI, TC, 64, 64>), dim3((unsigned)ntiles), dim3(256), 0, s,
-                       items, terms, tile_ptr, nitems);
+    hipLaunchKernelGGL((gemm_kernel<TI, TC, 64, 64>), g, b, 0, s, items, terms, tile_ptr, nitems);
 }
 template void launch_gemm<double, double>(const GemmItem<double>*, const GemmTerm<double>*,
-                                          const int64_t*, int64_t, int, int, hipStream_t);
+                                          const int64_t*, int64_t, int, int, int, hipStream_t);
 template void launch_gemm<float, float>(const GemmItem<float>*, const GemmTerm<float>*,
-                                        const int64_t*, int64_t, int, int, hipStream_t);
+                                        const int64_t*, int64_t, int, int, int, hipStream_t);
 template void launch_gemm<float, double>(const GemmItem<double>*, const GemmTerm<float>*,
-                                         const int64_t*, int64_t, int, int, hipStream_t);
+                                         const int64_t*, int64_t, int, int, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Blocked LU with partial pivoting (Sec. II-B Eq. lu: LU of S^RR; also the
