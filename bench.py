@@ -55,8 +55,11 @@ def training_sets(name):
     """Point sets the rank model learns from: the same family, other seeds."""
     import workloads as W
     if name.startswith("ellipsoids"):
-        return [(f"ellipsoids65536 seed {s}", lambda s=s: W.ellipsoid_points(65536, s))
-                for s in (501, 502)]
+        # two smaller sets and one of the workload's size (its upper levels are
+        # larger than any box of the smaller sets)
+        return ([(f"ellipsoids65536 seed {s}", lambda s=s: W.ellipsoid_points(65536, s))
+                 for s in (501, 502)]
+                + [("ellipsoids262144 seed 503", lambda: W.ellipsoid_points(262144, 503))])
     if name.startswith("sphere"):
         return [(f"sphere16384 seed {s}", lambda s=s: W.sphere_points(16384, s))
                 for s in (501, 502)]
