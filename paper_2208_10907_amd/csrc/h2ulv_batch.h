@@ -385,20 +385,80 @@ struct GemmBatch {
     auto ntile = [&](const GemmItem<TC>& it) {
       return (int64_t)((it.M + tm - 1) / tm) * ((it.N + tn - 1) / tn);
     };
-    std::vector<int64_t> tp(its.size() + 1, 0);
-    for (size_t i = 0; i < its.size(); ++i) tp[i + 1] = tp[i] + ntile(its[i]);
-    int64_t nt = tp.back();
-    int ni = (int)its.size();
+    int64_t nt0 = 0;
+    double kmax = 0;
+    for (size_t i = 0; i < its.size(); ++i) {
+      nt0 += ntile(its[i]);
+      kmax = std::max(kmax, ksum[i]);
+    }
     double fl = 0, by = 0;
-    if (profiler().on)
+    if (profiler().on) {
       for (auto& it : its)
         for (int t = it.t0; t < it.t0 + it.nt; ++t) {
           double K = terms[t].K;
           fl += 2.0 * it.M * it.N * K;
           by += ((double)it.M * K + K * it.N) * sizeof(T);
         }
-    if (profiler().on)
       for (auto& it : its) by += (double)it.M * it.N * sizeof(TC) * (it.beta != 0.0 ? 2 : 1);
+    }
+    // split K over workgroups when the batch has few tiles and long sums: split
+    // s of item i writes its partial product into scratch (beta 0) and a
+    // reduction adds the partials in order into C with alpha and beta
+    int S = 1;
+    if (nt0 < 256 && kmax >= 512) {
+      S = (int)std::min<int64_t>(8, std::max<int64_t>(1, 512 / std::max<int64_t>(nt0, 1)));
+      S = (int)std::min<double>(S, std::floor(kmax / 256.0));
+    }
+    std::vector<SplitKItem<TC>> red;
+    if (S >= 2) {
+      int64_t pw = 0;
+      for (auto& it : its) pw += (int64_t)it.M * it.N * S;
+      TC* part = st.scratch<TC>(pw);
+      std::vector<GemmItem<TC>> sits;
+      std::vector<GemmTerm<T>> sterms;
+      int64_t po = 0;
+      for (size_t i = 0; i < its.size(); ++i) {
+        const GemmItem<TC>& it = its[i];
+        const int64_t mn = (int64_t)it.M * it.N;
+        red.push_back(SplitKItem<TC>{it.C, it.ldc, part + po, it.M, it.N, S, it.alpha, it.beta});
+        // K range [s * chunk, (s + 1) * chunk) of the item's concatenated terms
+        const int64_t kt = (int64_t)ksum[i];
+        const int64_t chunk = ((kt + S - 1) / S + 15) / 16 * 16;
+        for (int sp = 0; sp < S; ++sp) {
+          GemmItem<TC> ni_ = it;
+          ni_.C = part + po + sp * mn;
+          ni_.ldc = it.M;
+          ni_.alpha = 1.0;
+          ni_.beta = 0.0;
+          ni_.t0 = (int32_t)sterms.size();
+          ni_.nt = 0;
+          const int64_t lo = sp * chunk, hi = std::min(kt, lo + chunk);
+          int64_t base = 0;
+          for (int t = it.t0; t < it.t0 + it.nt; ++t) {
+            const GemmTerm<T>& tt = terms[t];
+            const int64_t a0 = std::max(lo, base), a1 = std::min(hi, base + tt.K);
+            if (a1 > a0) {
+              const int64_t k0 = a0 - base;
+              GemmTerm<T> st_ = tt;
+              st_.K = (int32_t)(a1 - a0);
+              st_.A = (tt.flags & 1) ? tt.A + k0 : tt.A + k0 * tt.lda;
+              st_.B = (tt.flags & 2) ? tt.B + k0 * tt.ldb : tt.B + k0;
+              sterms.push_back(st_);
+              ni_.nt++;
+            }
+            base += tt.K;
+          }
+          sits.push_back(ni_);
+        }
+        po += mn * S;
+      }
+      its.swap(sits);
+      terms.swap(sterms);
+    }
+    std::vector<int64_t> tp(its.size() + 1, 0);
+    for (size_t i = 0; i < its.size(); ++i) tp[i + 1] = tp[i] + ntile(its[i]);
+    int64_t nt = tp.back();
+    int ni = (int)its.size();
     GemmItem<TC>* di;
     GemmTerm<T>* dt;
     int64_t* dp;
@@ -409,6 +469,15 @@ struct GemmBatch {
                  fl, by, st.s);
     launch_gemm<T, TC>(di, dt, dp, nt, ni, tm, tn, st.s);
     H2ULV_HIP(hipGetLastError());
+    if (!red.empty()) {
+      std::vector<int64_t> rp(red.size() + 1, 0);
+      for (size_t i = 0; i < red.size(); ++i) rp[i + 1] = rp[i] + tiles64(red[i].M, red[i].N);
+      SplitKItem<TC>* dr;
+      int64_t* drp;
+      st.up2(red, rp, &dr, &drp);
+      launch_splitk_reduce<TC>(dr, drp, rp.back(), (int)red.size(), st.s);
+      H2ULV_HIP(hipGetLastError());
+    }
   }
 };
 

@@ -40,6 +40,17 @@ struct GemmTerm {
   int32_t flags;  // bit0: op(A) = A^T, bit1: op(B) = B^T
 };
 
+// C = alpha sum_{s < S} P_s + beta C with P_s = P + s M N (M x N, ld M): the
+// partial products of a GEMM item whose K range was split over S workgroups.
+template <typename T>
+struct SplitKItem {
+  T* C;
+  int64_t ldc;
+  const T* P;
+  int32_t M, N, S;
+  double alpha, beta;
+};
+
 // One square (or tall, for QR) matrix per box for the factorization kernels.
 struct MatDesc {
   double* A;
@@ -123,6 +134,9 @@ void launch_kgen(const KgenItem* items, const int64_t* tile_ptr, int64_t ntiles,
 template <typename TI, typename TC>
 void launch_gemm(const GemmItem<TC>* items, const GemmTerm<TI>* terms, const int64_t* tile_ptr,
                  int64_t ntiles, int nitems, int tm, int tn, hipStream_t s);
+template <typename T>
+void launch_splitk_reduce(const SplitKItem<T>* items, const int64_t* tile_ptr, int64_t ntiles,
+                          int nitems, hipStream_t s);
 // maxrows: largest m - j0 over the matrices (selects the register-resident panel)
 void launch_lu_panel(const MatDesc* d, int nmat, int j0, int nb, int maxrows, hipStream_t s);
 void launch_lu_swap_trsm(const MatDesc* d, const int64_t* slab_ptr, int64_t nslabs, int nmat,

@@ -353,6 +353,42 @@ void launch_gemm(const GemmItem<TC>* items, const GemmTerm<TI>* terms, const int
   else
     hipLaunchKernelGGL((gemm_kernel<TI, TC, 64, 64>), g, b, 0, s, items, terms, tile_ptr, nitems);
 }
+template <typename T>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const SplitKItem<T>* __restrict__ items,
+                                                            const int64_t* __restrict__ tile_ptr,
+                                                            int nitems) {
+  const int64_t tile = blockIdx.x;
+  const int id = find_item(tile_ptr, nitems, tile);
+  const SplitKItem<T> it = items[id];
+  const int64_t local = tile - tile_ptr[id];
+  const int tmr = (it.M + 63) / 64;
+  const int r = (int)(local % tmr) * 64 + (threadIdx.x & 63);
+  const int c0 = (int)(local / tmr) * 64 + (threadIdx.x >> 6);
+  if (r >= it.M) return;
+  const int64_t mn = (int64_t)it.M * it.N;
+  for (int c = c0; c < min(it.N, (int)(local / tmr) * 64 + 64); c += 4) {
+    const T* p = it.P + r + (int64_t)c * it.M;
+    T acc = 0;
+    for (int sp = 0; sp < it.S; ++sp) acc += p[sp * mn];
+    T* cp = it.C + r + (int64_t)c * it.ldc;
+    T v = (T)it.alpha * acc;
+    if (it.beta != 0.0) v += (T)it.beta * (*cp);
+    *cp = v;
+  }
+}
+
+template <typename T>
+void launch_splitk_reduce(const SplitKItem<T>* items, const int64_t* tile_ptr, int64_t ntiles,
+                          int nitems, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3((unsigned)ntiles), dim3(256), 0, s, items,
+                     tile_ptr, nitems);
+}
+template void launch_splitk_reduce<double>(const SplitKItem<double>*, const int64_t*, int64_t, int,
+                                           hipStream_t);
+template void launch_splitk_reduce<float>(const SplitKItem<float>*, const int64_t*, int64_t, int,
+                                          hipStream_t);
+
 template void launch_gemm<double, double>(const GemmItem<double>*, const GemmTerm<double>*,
                                           const int64_t*, int64_t, int, int, int, hipStream_t);
 template void launch_gemm<float, float>(const GemmItem<float>*, const GemmTerm<float>*,
