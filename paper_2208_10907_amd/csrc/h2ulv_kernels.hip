@@ -1466,14 +1466,14 @@ __global__ __launch_bounds__(256) void pivqr_apply_kernel(const PivQrState* __re
     for (; r + 64 < m; r += 128) {
       double x0 = ac[r] - wsum * v[r];
       double x1 = ac[r + 64] - wsum * v[r + 64];
-      ac[r] = x0;
-      ac[r + 64] = x1;
+      __builtin_nontemporal_store(x0, ac + r);
+      __builtin_nontemporal_store(x1, ac + r + 64);
       s0 += x0 * x0;
       s1 += x1 * x1;
     }
     for (; r < m; r += 64) {
       double x = ac[r] - wsum * v[r];
-      ac[r] = x;
+      __builtin_nontemporal_store(x, ac + r);
       s0 += x * x;
     }
     double s2 = wave_sum(s0 + s1);
