@@ -23,6 +23,11 @@ delivered accuracy.  The plain FP64 form is also timed (the reference) unless
 --no-reference; without it the form's own flop count is used.
 roofline = the dominant kernel (by time) of the timed steps measured with HIP
 events on its launch stream: summed algorithmic flops / summed duration.
+roofline.traffic = HBM bytes per launch of that kernel in the timed step, from
+the rocprofv3 FETCH_SIZE / WRITE_SIZE counters recorded in
+profiles/gemm_f64_traffic_ellipsoids262144.md (scaled by the same counters'
+reading for a plain copy of known size, --copy-probe); null when the library
+sources differ from those the counters were taken with (source hash).
 cpu_baseline = the CPU oracle timed on a bounded sample of leaf boxes of the
 same workload (GFLOP/s of the oracle's own flop count).
 """
@@ -38,6 +43,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "H² ULV factorize time + GFLOP/s, N=1M Laplace, mixed vs FP64 at 1e-10 resid"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f64_traffic_ellipsoids262144.md")
+
+
+def library_source_hash() -> str:
+    """sha256 over the library's device and host sources (sorted by name): the
+    launch mix and the GEMM kernel both come from them."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2208_10907_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".cpp", ".h")):
+            with open(os.path.join(d, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload: str):
+    """HBM bytes per launch of the FP64 GEMM recorded for this workload, if the
+    record was taken with the current library sources."""
+    if workload != "ellipsoids262144" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            line = line.strip().strip("`")
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    try:
+        if vals.get("library_source_sha256") != library_source_hash():
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 PEAK_TFLOPS = {"gemm_f64": 78.6, "gemm_f32": 157.3}
 
 
@@ -154,7 +193,19 @@ def main() -> int:
     ap.add_argument("--window-file", default=None,
                     help="write the timed region's start and end (time.monotonic_ns) here, "
                          "to match a profiler trace to the timed steps")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB from one device buffer to another (the known-size "
+                         "calibration kernel for HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(args.copy_probe << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe << 20}))
+        return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the distributed process tree of "
               "the paper is a design note, not built); use --gpus 1", file=sys.stderr)
@@ -250,7 +301,8 @@ def main() -> int:
         ach = g["flops"] / (g["time_ms"] / 1e3) / 1e12
         roof = {"bound": "mfma", "kernel": dom, "achieved": round(ach, 3),
                 "peak": PEAK_TFLOPS[dom], "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_TFLOPS[dom], 4), "traffic": None,
+                "frac": round(ach / PEAK_TFLOPS[dom], 4),
+                "traffic": recorded_traffic(args.workload) if dom == "gemm_f64" else None,
                 "launches": g["launches"],
                 "avg_launch_ms": round(g["time_ms"] / g["launches"], 4),
                 "flops_per_launch": g["flops"] / g["launches"]}
