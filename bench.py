@@ -290,10 +290,12 @@ def main() -> int:
     for k, v in prof.items():
         base = k.split(":")[0]
         if base in PEAK_TFLOPS:
-            a = gemms.setdefault(base, {"launches": 0, "time_ms": 0.0, "flops": 0.0})
+            a = gemms.setdefault(base, {"launches": 0, "time_ms": 0.0, "flops": 0.0,
+                                        "bytes": 0.0})
             a["launches"] += v["launches"]
             a["time_ms"] += v["time_ms"]
             a["flops"] += v["flops"]
+            a["bytes"] += v["bytes"]
     dom = max(gemms, key=lambda k: gemms[k]["time_ms"]) if gemms else None
     roof = None
     if dom:
@@ -305,7 +307,9 @@ def main() -> int:
                 "traffic": recorded_traffic(args.workload) if dom == "gemm_f64" else None,
                 "launches": g["launches"],
                 "avg_launch_ms": round(g["time_ms"] / g["launches"], 4),
-                "flops_per_launch": g["flops"] / g["launches"]}
+                "flops_per_launch": g["flops"] / g["launches"],
+                # operands read once and results written once, per launch
+                "algorithmic_bytes_per_launch": g["bytes"] / g["launches"]}
 
     out = {
         "metric": METRIC,
