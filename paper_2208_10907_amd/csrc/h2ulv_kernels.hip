@@ -152,6 +152,19 @@ __device__ __forceinline__ T gload(const T* p) {
   return *(const __attribute__((address_space(1))) T*)p;
 }
 
+// Workgroup b runs on XCD b % 8 (round-robin dispatch; each XCD has its own L2).
+// Within every block of 8 G consecutive tiles, the G consecutive tiles of chunk
+// x go to XCD x: neighbouring tiles of an item (the same column band of B)
+// then share that XCD's L2, while all XCDs still advance through the tiles
+// together.  Tiles past the last whole block keep their index.
+template <int G>
+__device__ __forceinline__ int64_t xcd_chunk_tile(int64_t b, int64_t n) {
+  const int64_t full = n / (8 * G) * (8 * G);
+  if (b >= full) return b;
+  const int64_t q = b / (8 * G), r = b % (8 * G);
+  return q * (8 * G) + (r % 8) * G + r / 8;
+}
+
 // C = beta C + alpha sum_t op(A_t) op(B_t) for a batch of items of any size.
 // A workgroup (4 waves, 2 x 2, each a (TM/2) x (TN/2) block of 16 x 16 MFMA
 // accumulators) owns a TM x TN tile of one item (found
@@ -172,7 +185,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<TC>* __restric
   constexpr int LA = TM / 16, LB = TN / 16;
   __shared__ T As[2][16][TM + 4];
   __shared__ T Bs[2][16][TN + 4];
-  const int64_t tile = blockIdx.x;
+  const int64_t tile = xcd_chunk_tile<4>(blockIdx.x, gridDim.x);
   const int id = find_item(tile_ptr, nitems, tile);
   const GemmItem<TC> it = items[id];
   const int64_t local = tile - tile_ptr[id];
