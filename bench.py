@@ -241,14 +241,15 @@ def main() -> int:
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         st = f.stats()
-        sk = [0, 0]
+        sk = [0, 0, 0, 0]  # outcome per box: not sketched, accepted, rejected, retried and accepted
         for lev in range(1, f.levels() + 1):
             s = f.sketch_info(lev)[2]
-            sk[0] += int((s == 1).sum())
-            sk[1] += int((s == 2).sum())
+            for o in range(4):
+                sk[o] += int((s == o).sum())
         del f
         return {"factor_s": t1 - t0, "refine_s": t2 - t1, "iters": iters, "rel": rel, "st": st,
-                "sketch_accepted": sk[0], "sketch_rejected": sk[1]}
+                "sketches": {"accepted": sk[1], "retried_accepted": sk[3],
+                             "rejected_full_qr": sk[2], "not_sketched": sk[0]}}
 
     form_params = params_of(args.form)
     for w in range(args.warmup):
@@ -335,7 +336,7 @@ def main() -> int:
         "max_rank": st["max_rank"],
         "root_size": st["root_size"],
         "device_gb": round(st["device_bytes"] / 1e9, 2),
-        "sketches": {"accepted": last["sketch_accepted"], "rejected": last["sketch_rejected"]},
+        "sketches": last["sketches"],
         "reference": ref,
         "speedup_vs_fp64": round(ref["step_s"] / (ms / 1e3), 3) if ref else None,
         "rank_model": model_info,
