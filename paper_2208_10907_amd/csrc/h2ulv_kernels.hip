@@ -481,17 +481,22 @@ __global__ __launch_bounds__(256) void lu_panel_kernel(const MatDesc* __restrict
 }
 
 // The same panel factorization with the panel held in registers: 1024 threads,
-// row r of the panel in thread r % 1024, slot r / 1024 (at most LUP_RPT * 1024
-// rows).  Columns are taken in groups of LUP_G, left-looking: a group is loaded
-// once, updated by the L columns left of it (unit-lower solve of its top rows,
-// then one product for the rest), factored with partial pivoting in registers
-// (lowest row on ties), written back, and its interchanges are applied to the
-// other panel columns.  Same pivots, factors and info as lu_panel_kernel up to
-// the summation order of the updates.
+// logical row r of the panel in thread r % 1024, slot r / 1024 (at most
+// LUP_RPT * 1024 rows).  Columns are taken in groups of LUP_G, left-looking: a
+// group is loaded once, updated by the L columns left of it (unit-lower solve
+// of its top rows, then one product for the rest), factored with partial
+// pivoting in registers (lowest row on ties) and written back.  Interchanges
+// are not applied to the other panel columns as they happen: the kernel keeps
+// the row permutation in LDS (logical row r lives in memory row perm[r] for
+// every panel column) and puts the moved rows in place once, at the end.
+// Same pivots, factors and info as lu_panel_kernel up to the summation order
+// of the updates.
 constexpr int LUP_RPT = 4;
 constexpr int LUP_G = 4;
 constexpr int LUP_THREADS = 1024;
 constexpr int LUP_MAXROWS = LUP_RPT * LUP_THREADS;
+constexpr int LUP_KB = 4;  // L columns per batch of loads in the update
+static_assert(LUP_G % LUP_KB == 0, "group width must be a multiple of the load batch");
 
 __global__ __launch_bounds__(LUP_THREADS) void lu_panel_reg_kernel(const MatDesc* __restrict__ ds,
                                                                    int j0, int nb) {
@@ -500,6 +505,7 @@ __global__ __launch_bounds__(LUP_THREADS) void lu_panel_reg_kernel(const MatDesc
   __shared__ double s_wv[LUP_THREADS / 64];
   __shared__ int s_wi[LUP_THREADS / 64];
   __shared__ int s_piv[64];
+  __shared__ int s_perm[LUP_MAXROWS];
   const MatDesc d = ds[blockIdx.x];
   const int m = d.m;
   if (m <= j0) return;
@@ -508,33 +514,54 @@ __global__ __launch_bounds__(LUP_THREADS) void lu_panel_reg_kernel(const MatDesc
   const int64_t lda = d.lda;
   double* P = d.A + j0 + (int64_t)j0 * lda;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int r = tid; r < h; r += LUP_THREADS) s_perm[r] = r;
+  __syncthreads();
   int info_col = 0;  // first singular column (1-based), thread 0 only
   for (int g0 = 0; g0 < w; g0 += LUP_G) {
     const int gw = min(LUP_G, w - g0);
+    // memory rows of this thread's logical rows (the permutation is only
+    // changed inside the column loop below)
+    int pr[LUP_RPT];
+#pragma unroll
+    for (int i = 0; i < LUP_RPT; ++i) {
+      const int r = tid + LUP_THREADS * i;
+      pr[i] = r < h ? s_perm[r] : 0;
+    }
     double x[LUP_RPT][LUP_G];
 #pragma unroll
     for (int i = 0; i < LUP_RPT; ++i) {
       const int r = tid + LUP_THREADS * i;
 #pragma unroll
       for (int c = 0; c < LUP_G; ++c)
-        x[i][c] = (r < h && c < gw) ? P[r + (int64_t)(g0 + c) * lda] : 0.0;
+        x[i][c] = (r < h && c < gw) ? gload(P + pr[i] + (int64_t)(g0 + c) * lda) : 0.0;
     }
     if (g0 > 0) {
-      // top rows: U = L11^-1 A_top with L11 = P(0:g0, 0:g0), unit lower (one wave)
+      // top rows: U = L11^-1 A_top with L11 = P(0:g0, 0:g0), unit lower (one wave,
+      // the columns of the group side by side)
       if (tid < g0) {
 #pragma unroll
         for (int c = 0; c < LUP_G; ++c) s_u[tid + 64 * c] = x[0][c];
       }
       __syncthreads();
       if (wv == 0) {
-        const double lrow_ok = lane < g0 ? 1.0 : 0.0;
-        for (int c = 0; c < gw; ++c) {
-          double val = lane < g0 ? s_u[lane + 64 * c] : 0.0;
-          for (int k = 0; k < g0 - 1; ++k) {
-            const double uk = __shfl(val, k, 64);
-            if (lane > k && lane < g0) val -= P[lane + (int64_t)k * lda] * uk;
+        const bool top = lane < g0;
+        double val[LUP_G];
+#pragma unroll
+        for (int c = 0; c < LUP_G; ++c) val[c] = top ? s_u[lane + 64 * c] : 0.0;
+        const double* lrow = P + (top ? s_perm[lane] : 0);
+        for (int k = 0; k < g0 - 1; ++k) {
+          const bool below = top && lane > k;
+          const double l = below ? gload(lrow + (int64_t)k * lda) : 0.0;
+#pragma unroll
+          for (int c = 0; c < LUP_G; ++c) {
+            const double uk = __shfl(val[c], k, 64);
+            if (below) val[c] -= l * uk;
           }
-          if (lrow_ok != 0.0) s_u[lane + 64 * c] = val;
+        }
+        if (top) {
+#pragma unroll
+          for (int c = 0; c < LUP_G; ++c)
+            if (c < gw) s_u[lane + 64 * c] = val[c];
         }
       }
       __syncthreads();
@@ -542,19 +569,36 @@ __global__ __launch_bounds__(LUP_THREADS) void lu_panel_reg_kernel(const MatDesc
 #pragma unroll
         for (int c = 0; c < LUP_G; ++c) x[0][c] = s_u[tid + 64 * c];
       }
-      // rows g0..h-1: A -= L(:, 0:g0) U
+      // rows g0..h-1: A -= L(:, 0:g0) U, LUP_KB columns of L per batch of loads
+      for (int k0 = 0; k0 < g0; k0 += LUP_KB) {
+        double l[LUP_RPT][LUP_KB];
 #pragma unroll
-      for (int i = 0; i < LUP_RPT; ++i) {
-        const int r = tid + LUP_THREADS * i;
-        if (r >= g0 && r < h) {
-          for (int k = 0; k < g0; ++k) {
-            const double l = P[r + (int64_t)k * lda];
+        for (int i = 0; i < LUP_RPT; ++i) {
+          const int r = tid + LUP_THREADS * i;
+          const bool ok = r >= g0 && r < h;
 #pragma unroll
-            for (int c = 0; c < LUP_G; ++c) x[i][c] -= l * s_u[k + 64 * c];
+          for (int kk = 0; kk < LUP_KB; ++kk)
+            l[i][kk] = ok ? gload(P + pr[i] + (int64_t)(k0 + kk) * lda) : 0.0;
+        }
+#pragma unroll
+        for (int kk = 0; kk < LUP_KB; ++kk) {
+          double u[LUP_G];
+#pragma unroll
+          for (int c = 0; c < LUP_G; ++c) u[c] = s_u[k0 + kk + 64 * c];
+#pragma unroll
+          for (int i = 0; i < LUP_RPT; ++i) {
+            const int r = tid + LUP_THREADS * i;
+            if (r >= g0 && r < h) {
+#pragma unroll
+              for (int c = 0; c < LUP_G; ++c) x[i][c] -= l[i][kk] * u[c];
+            }
           }
         }
       }
     }
+    // Two barriers per column: s_wv / s_wi are read before the second, and
+    // s_prow / s_crow are read before the next column's first, so neither is
+    // written again while a thread may still read it.
 #pragma unroll
     for (int jj = 0; jj < LUP_G; ++jj) {
       if (jj >= gw) break;
@@ -615,7 +659,14 @@ __global__ __launch_bounds__(LUP_THREADS) void lu_panel_reg_kernel(const MatDesc
 #pragma unroll
         for (int c = 0; c < LUP_G; ++c) s_crow[c] = x[0][c];
       }
-      if (tid == 0) s_piv[col] = p;
+      if (tid == 0) {
+        s_piv[col] = p;
+        if (p != col) {
+          const int t0 = s_perm[col];
+          s_perm[col] = s_perm[p];
+          s_perm[p] = t0;
+        }
+      }
       __syncthreads();
       if (p != col) {
         if (tid == pt) {
@@ -642,31 +693,54 @@ __global__ __launch_bounds__(LUP_THREADS) void lu_panel_reg_kernel(const MatDesc
           for (int c = jj + 1; c < LUP_G; ++c) x[i][c] -= l * s_prow[c];
         }
       }
-      __syncthreads();
     }
+    // write the group back to the memory rows of the logical rows as they are now
 #pragma unroll
     for (int i = 0; i < LUP_RPT; ++i) {
       const int r = tid + LUP_THREADS * i;
       if (r < h) {
+        const int q = s_perm[r];
 #pragma unroll
         for (int c = 0; c < LUP_G; ++c)
-          if (c < gw) P[r + (int64_t)(g0 + c) * lda] = x[i][c];
-      }
-    }
-    // the group's interchanges on the other columns of the panel
-    for (int c = tid; c < w; c += LUP_THREADS) {
-      if (c >= g0 && c < g0 + gw) continue;
-      double* pc = P + (int64_t)c * lda;
-      for (int jj = 0; jj < gw; ++jj) {
-        const int col = g0 + jj, p = s_piv[col];
-        if (p != col) {
-          const double t0 = pc[col];
-          pc[col] = pc[p];
-          pc[p] = t0;
-        }
+          if (c < gw) P[q + (int64_t)(g0 + c) * lda] = x[i][c];
       }
     }
     __syncthreads();
+  }
+  // put the moved rows in place: logical row r <- memory row perm[r], LUP_G
+  // columns at a time (all loads of a batch before any of its stores)
+  int src[LUP_RPT];
+  bool moved = false;
+#pragma unroll
+  for (int i = 0; i < LUP_RPT; ++i) {
+    const int r = tid + LUP_THREADS * i;
+    src[i] = r < h ? s_perm[r] : r;
+    moved = moved || src[i] != r;
+  }
+  for (int c0 = 0; c0 < w; c0 += LUP_G) {
+    double v[LUP_RPT][LUP_G];
+    if (moved) {
+#pragma unroll
+      for (int i = 0; i < LUP_RPT; ++i) {
+        const int r = tid + LUP_THREADS * i;
+#pragma unroll
+        for (int c = 0; c < LUP_G; ++c)
+          v[i][c] = (src[i] != r && c0 + c < w) ? gload(P + src[i] + (int64_t)(c0 + c) * lda)
+                                                 : 0.0;
+      }
+    }
+    __syncthreads();
+    if (moved) {
+#pragma unroll
+      for (int i = 0; i < LUP_RPT; ++i) {
+        const int r = tid + LUP_THREADS * i;
+        if (src[i] != r) {
+#pragma unroll
+          for (int c = 0; c < LUP_G; ++c)
+            if (c0 + c < w) P[r + (int64_t)(c0 + c) * lda] = v[i][c];
+        }
+      }
+    }
   }
   for (int c = tid; c < w; c += LUP_THREADS) d.ipiv[j0 + c] = j0 + s_piv[c];
   if (tid == 0 && info_col != 0 && *d.info == 0) *d.info = info_col;
