@@ -771,9 +771,10 @@ __global__ __launch_bounds__(64) void lu_swap_trsm_kernel(const MatDesc* __restr
   const int64_t lda = d.lda;
   double* A = d.A;
   const int lane = threadIdx.x;
-  // stage L11
+  // stage L11 (global loads, which cannot alias the LDS stores, so they stay in flight together)
+#pragma unroll 16
   for (int c = 0; c < w; ++c)
-    for (int r = lane; r < w; r += 64) L11[r][c] = A[(j0 + r) + (int64_t)(j0 + c) * lda];
+    if (lane < w) L11[lane][c] = gload(A + (j0 + lane) + (int64_t)(j0 + c) * lda);
   __syncthreads();
   const int c = (int)(slab - slab_ptr[id]) * 64 + lane;
   if (c >= m || (c >= j0 && c < j0 + w)) return;
@@ -789,7 +790,8 @@ __global__ __launch_bounds__(64) void lu_swap_trsm_kernel(const MatDesc* __restr
   if (c >= j0 + w) {
     // forward substitution with the unit lower L11; each lane keeps its column
     // in its own LDS column (no cross-lane traffic, no barrier)
-    for (int r = 0; r < w; ++r) X[r][lane] = col[j0 + r];
+#pragma unroll 16
+    for (int r = 0; r < w; ++r) X[r][lane] = gload(col + j0 + r);
     for (int l = 0; l < w; ++l) {
       const double xl = X[l][lane];
       for (int r = l + 1; r < w; ++r) X[r][lane] -= L11[r][l] * xl;
@@ -987,16 +989,20 @@ __global__ __launch_bounds__(64 * NW) void qr_panel_kernel(const MatDesc* __rest
 // Left-looking over the groups: a group is loaded once, the panel's earlier
 // reflectors are applied to it as a block (A_g -= V T^T V^T A_g), its columns
 // are factored in LDS, and it is written back with its explicit reflectors;
-// the T columns of the group come from V^T v.  Dot products over rows are
-// taken by one wave each (lanes over rows, then a wave sum).
+// the T columns of the group come from V^T v.  Products with earlier
+// reflectors are taken by one wave per reflector (lanes over rows, four rows
+// per lane in flight, then a wave sum); the norm and the dot products of the
+// column being factored are taken by all 16 waves.
 constexpr int QRP_G = 4;
 constexpr int QRP_MAXROWS = 4096;
+constexpr int QRP_RPT = QRP_MAXROWS / 1024;  // rows per thread
 
 __global__ __launch_bounds__(1024) void qr_panel_lds_kernel(const MatDesc* __restrict__ ds, int j0,
                                                             int nb) {
   __shared__ double s_a[QRP_G * QRP_MAXROWS];  // group column c at s_a + c * QRP_MAXROWS
   __shared__ double s_y[32 * QRP_G], s_z[32 * QRP_G];
   __shared__ double s_T[32][33];
+  __shared__ double s_red[16][QRP_G];  // per-wave partial sums
   __shared__ double s_dot[QRP_G];
   __shared__ double s_sc[3];  // tau, scale, beta of the current column
   const MatDesc d = ds[blockIdx.x];
@@ -1011,16 +1017,41 @@ __global__ __launch_bounds__(1024) void qr_panel_lds_kernel(const MatDesc* __res
   for (int e = tid; e < 32 * 33; e += 1024) (&s_T[0][0])[e] = 0.0;
   for (int g0 = 0; g0 < w; g0 += QRP_G) {
     const int gw = min(QRP_G, w - g0);
-    for (int c = 0; c < gw; ++c)
-      for (int r = tid; r < h; r += 1024) s_a[c * QRP_MAXROWS + r] = P[r + (int64_t)(g0 + c) * lda];
+    {  // all loads of a thread before its LDS stores
+      double x[QRP_RPT][QRP_G];
+#pragma unroll
+      for (int i = 0; i < QRP_RPT; ++i) {
+        const int r = tid + 1024 * i;
+#pragma unroll
+        for (int c = 0; c < QRP_G; ++c)
+          x[i][c] = (r < h && c < gw) ? gload(P + r + (int64_t)(g0 + c) * lda) : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < QRP_RPT; ++i) {
+        const int r = tid + 1024 * i;
+#pragma unroll
+        for (int c = 0; c < QRP_G; ++c)
+          if (r < h && c < gw) s_a[c * QRP_MAXROWS + r] = x[i][c];
+      }
+    }
     __syncthreads();
     if (g0 > 0) {
       // Y = V_p^T A_g: wave per reflector k (V_p(r, k) = 0 for r < k)
       for (int k = wv; k < g0; k += 16) {
         const double* vk = V + j0 + (int64_t)k * m;
         double acc[QRP_G] = {0.0, 0.0, 0.0, 0.0};
-        for (int r = k + lane; r < h; r += 64) {
-          const double vv = vk[r];
+        int r = k + lane;
+        for (; r + 192 < h; r += 256) {
+          double vv[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) vv[q] = gload(vk + r + 64 * q);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < QRP_G; ++c) acc[c] += vv[q] * s_a[c * QRP_MAXROWS + r + 64 * q];
+        }
+        for (; r < h; r += 64) {
+          const double vv = gload(vk + r);
 #pragma unroll
           for (int c = 0; c < QRP_G; ++c) acc[c] += vv * s_a[c * QRP_MAXROWS + r];
         }
@@ -1039,12 +1070,23 @@ __global__ __launch_bounds__(1024) void qr_panel_lds_kernel(const MatDesc* __res
         s_z[tid] = z;
       }
       __syncthreads();
-      // A_g -= V_p Z, thread per row
+      // A_g -= V_p Z, thread per row, four reflectors per batch of loads
       for (int r = tid; r < h; r += 1024) {
         double acc[QRP_G] = {0.0, 0.0, 0.0, 0.0};
         const int kend = min(g0, r + 1);
-        for (int k = 0; k < kend; ++k) {
-          const double vv = V[(j0 + r) + (int64_t)k * m];
+        const double* vr = V + j0 + r;
+        int k = 0;
+        for (; k + 3 < kend; k += 4) {
+          double vv[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) vv[q] = gload(vr + (int64_t)(k + q) * m);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < QRP_G; ++c) acc[c] += vv[q] * s_z[(k + q) * QRP_G + c];
+        }
+        for (; k < kend; ++k) {
+          const double vv = gload(vr + (int64_t)k * m);
 #pragma unroll
           for (int c = 0; c < QRP_G; ++c) acc[c] += vv * s_z[k * QRP_G + c];
         }
@@ -1058,24 +1100,28 @@ __global__ __launch_bounds__(1024) void qr_panel_lds_kernel(const MatDesc* __res
     for (int jj = 0; jj < gw; ++jj) {
       const int col = g0 + jj;
       double* a = s_a + jj * QRP_MAXROWS;
-      if (wv == 0) {
+      {
         double part = 0.0;
-        for (int r = col + 1 + lane; r < h; r += 64) part += a[r] * a[r];
-        const double xn2 = wave_sum(part);
-        if (lane == 0) {
-          const double alpha = a[col];
-          double tau = 0.0, scale = 0.0, beta = alpha;
-          if (xn2 != 0.0) {
-            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-            tau = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
-          }
-          s_sc[0] = tau;
-          s_sc[1] = scale;
-          s_sc[2] = beta;
-          s_T[col][col] = tau;
-          d.aux[j0 + col] = tau;
+        for (int r = col + 1 + tid; r < h; r += 1024) part += a[r] * a[r];
+        part = wave_sum(part);
+        if (lane == 0) s_red[wv][0] = part;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double xn2 = 0.0;
+        for (int q = 0; q < 16; ++q) xn2 += s_red[q][0];
+        const double alpha = a[col];
+        double tau = 0.0, scale = 0.0, beta = alpha;
+        if (xn2 != 0.0) {
+          beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+          tau = (beta - alpha) / beta;
+          scale = 1.0 / (alpha - beta);
         }
+        s_sc[0] = tau;
+        s_sc[1] = scale;
+        s_sc[2] = beta;
+        s_T[col][col] = tau;
+        d.aux[j0 + col] = tau;
       }
       __syncthreads();
       const double tau = s_sc[0], scale = s_sc[1];
@@ -1085,14 +1131,23 @@ __global__ __launch_bounds__(1024) void qr_panel_lds_kernel(const MatDesc* __res
       }
       __syncthreads();
       if (tau != 0.0 && jj + 1 < gw) {
-        // dot_c = a_c(col) + sum_{r > col} v(r) a_c(r), wave per later column
-        if (wv < gw - jj - 1) {
-          const int c = jj + 1 + wv;
-          const double* ac = s_a + c * QRP_MAXROWS;
-          double part = 0.0;
-          for (int r = col + 1 + lane; r < h; r += 64) part += a[r] * ac[r];
-          const double dsum = wave_sum(part);
-          if (lane == 0) s_dot[c] = dsum + ac[col];
+        // dot_c = a_c(col) + sum_{r > col} v(r) a_c(r) for the later columns
+        double pd[QRP_G] = {0.0, 0.0, 0.0, 0.0};
+        for (int r = col + 1 + tid; r < h; r += 1024) {
+          const double vr = a[r];
+#pragma unroll
+          for (int c = 0; c < QRP_G; ++c)
+            if (c > jj && c < gw) pd[c] += vr * s_a[c * QRP_MAXROWS + r];
+        }
+        for (int c = jj + 1; c < gw; ++c) {
+          const double t = wave_sum(pd[c]);
+          if (lane == 0) s_red[wv][c] = t;
+        }
+        __syncthreads();
+        if (tid > jj && tid < gw) {
+          double dsum = 0.0;
+          for (int q = 0; q < 16; ++q) dsum += s_red[q][tid];
+          s_dot[tid] = dsum + s_a[tid * QRP_MAXROWS + col];
         }
         __syncthreads();
         for (int r = col + tid; r < h; r += 1024) {
@@ -1120,9 +1175,26 @@ __global__ __launch_bounds__(1024) void qr_panel_lds_kernel(const MatDesc* __res
     for (int l = wv; l < kmax; l += 16) {
       double acc[QRP_G] = {0.0, 0.0, 0.0, 0.0};
       const bool own = l >= g0;
-      const double* vl = own ? s_a + (l - g0) * QRP_MAXROWS : V + j0 + (int64_t)l * m;
-      for (int r = l + 1 + lane; r < h; r += 64) {
-        const double x = vl[r];
+      const double* vg = V + j0 + (int64_t)l * m;
+      const double* vs = s_a + (own ? l - g0 : 0) * QRP_MAXROWS;
+      int r = l + 1 + lane;
+      for (; r + 192 < h; r += 256) {
+        double x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = own ? vs[r + 64 * q] : gload(vg + r + 64 * q);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rq = r + 64 * q;
+#pragma unroll
+          for (int c = 0; c < QRP_G; ++c) {
+            const int k = g0 + c;
+            if (c < gw && k > l && rq >= k)
+              acc[c] += x[q] * (rq == k ? 1.0 : s_a[c * QRP_MAXROWS + rq]);
+          }
+        }
+      }
+      for (; r < h; r += 64) {
+        const double x = own ? vs[r] : gload(vg + r);
 #pragma unroll
         for (int c = 0; c < QRP_G; ++c) {
           const int k = g0 + c;
