@@ -1548,15 +1548,55 @@ __global__ __launch_bounds__(1024) void pivqr_pick_kernel(const PivQrState* __re
   double* A = st.A;
   const int64_t lda = st.lda;
   double* at = A + (int64_t)t * lda;
+  double* ap = A + (int64_t)p * lda;
+  // Swap columns t and p.  Rows above t only move; rows below t are taken in
+  // the same thread / row assignment as the sum of squares of the reflector,
+  // their loads are issued together and their values stay in registers for
+  // the scaling (the first PK_KEEP * 1024 of them).
+  constexpr int PK_KEEP = 4;
   if (p != t) {
-    double* ap = A + (int64_t)p * lda;
-    for (int r = tid; r < m; r += 1024) {
-      const double x = at[r];
-      at[r] = ap[r];
+    for (int r = tid; r <= t && r < m; r += 1024) {
+      const double x = gload(at + r), y = gload(ap + r);
+      at[r] = y;
       ap[r] = x;
     }
   }
-  __syncthreads();
+  double keep[PK_KEEP];
+  double part = 0.0;
+#pragma unroll
+  for (int j = 0; j < PK_KEEP; ++j) {
+    const int r = t + 1 + tid + 1024 * j;
+    keep[j] = r < m ? gload(ap + r) : 0.0;  // the new column t (column p)
+  }
+  if (p != t) {
+    double old[PK_KEEP];
+#pragma unroll
+    for (int j = 0; j < PK_KEEP; ++j) {
+      const int r = t + 1 + tid + 1024 * j;
+      old[j] = r < m ? gload(at + r) : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < PK_KEEP; ++j) {
+      const int r = t + 1 + tid + 1024 * j;
+      if (r < m) {
+        at[r] = keep[j];
+        ap[r] = old[j];
+      }
+    }
+  }
+  // explicit fused multiply-adds in row order: contraction of a sum of
+  // products may otherwise fuse either product
+#pragma unroll
+  for (int j = 0; j < PK_KEEP; ++j) part = fma(keep[j], keep[j], part);
+  for (int r = t + 1 + tid + 1024 * PK_KEEP; r < m; r += 1024) {
+    const double y = gload(ap + r);
+    if (p != t) {
+      const double x = gload(at + r);
+      at[r] = y;
+      ap[r] = x;
+    }
+    part = fma(y, y, part);
+  }
   if (tid == 0 && p != t) {
     const double x = st.nrm[t];
     st.nrm[t] = st.nrm[p];
@@ -1565,9 +1605,7 @@ __global__ __launch_bounds__(1024) void pivqr_pick_kernel(const PivQrState* __re
     st.piv[t] = st.piv[p];
     st.piv[p] = q;
   }
-  double part = 0.0;
-  for (int r = t + 1 + tid; r < m; r += 1024) part += at[r] * at[r];
-  const double xn2 = block_sum<16>(part, sh);
+  const double xn2 = block_sum<16>(part, sh);  // its barriers also order the swap above
   const double alpha = at[t];
   double tau = 0.0, scale = 0.0;
   if (xn2 != 0.0) {
@@ -1575,9 +1613,14 @@ __global__ __launch_bounds__(1024) void pivqr_pick_kernel(const PivQrState* __re
     tau = (beta - alpha) / beta;
     scale = 1.0 / (alpha - beta);
   }
-  __syncthreads();
+  __syncthreads();  // every thread has read alpha before thread 0 overwrites it
   if (tau != 0.0) {
-    for (int r = t + 1 + tid; r < m; r += 1024) at[r] *= scale;
+#pragma unroll
+    for (int j = 0; j < PK_KEEP; ++j) {
+      const int r = t + 1 + tid + 1024 * j;
+      if (r < m) at[r] = keep[j] * scale;
+    }
+    for (int r = t + 1 + tid + 1024 * PK_KEEP; r < m; r += 1024) at[r] *= scale;
   }
   if (tid == 0) {
     if (tau != 0.0) at[t] = -copysign(sqrt(alpha * alpha + xn2), alpha);
