@@ -1009,11 +1009,12 @@ void Driver::pivot_boxes(Stage& st, const std::vector<Box>& boxes) {
   H2ULV_HIP(hipGetLastError());
   const int nbig = (int)big.size();
   if (nbig > 0) {
-    int maxcap = 0;
+    int maxcap = 0, maxcols = 0;
     std::vector<int64_t> sp(1, 0);
     for (auto& b : big) {
       sp.push_back(sp.back() + (b.n + 3) / 4);
       maxcap = std::max(maxcap, b.cap);
+      maxcols = std::max(maxcols, b.n);
     }
     const int64_t ns = sp.back();
     PivQrState* dst_ = st.up(std::move(big));
@@ -1025,7 +1026,7 @@ void Driver::pivot_boxes(Stage& st, const std::vector<Box>& boxes) {
     std::vector<int32_t> fl(2 * nbox + 2);
     for (int t = 0; t < maxcap; ++t) {
       launch_pivqr_pick(dst_, nbig, t, s);
-      launch_pivqr_apply(dst_, dsp, ns, nbig, t, s);
+      launch_pivqr_apply(dst_, nbig, maxcols, t, s);
       if ((t + 1) % 64 == 0 && t + 1 < maxcap) {
         H2ULV_HIP(hipGetLastError());
         H2ULV_HIP(hipMemcpyAsync(fl.data(), flg, fl.size() * sizeof(int32_t),

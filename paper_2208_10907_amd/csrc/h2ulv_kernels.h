@@ -148,8 +148,8 @@ void launch_qr_panel(const MatDesc* d, int nmat, int j0, int nb, int maxrows, hi
 void launch_pivqr_init(const PivQrState* st, const int64_t* slab_ptr, int64_t nslabs, int n,
                        hipStream_t s);
 void launch_pivqr_pick(const PivQrState* st, int n, int t, hipStream_t s);
-void launch_pivqr_apply(const PivQrState* st, const int64_t* slab_ptr, int64_t nslabs, int n,
-                        int t, hipStream_t s);
+// maxcols: largest column count over the n matrices
+void launch_pivqr_apply(const PivQrState* st, int n, int maxcols, int t, hipStream_t s);
 void launch_pivqr(const PivQrItem* items, int nitems, hipStream_t s);
 void launch_copy(const CopyItem* items, const int64_t* tile_ptr, int64_t ntiles, int nitems,
                  double alpha, double beta, hipStream_t s);

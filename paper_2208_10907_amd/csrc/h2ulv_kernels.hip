@@ -1454,8 +1454,8 @@ void launch_pivqr(const PivQrItem* items, int nitems, hipStream_t s) {
 // the one-workgroup kernel (largest exact remaining norm, lowest index on ties,
 // continue while it exceeds tol |R_00| and the cap allows), one step per pair
 // of launches: pick (one workgroup per matrix: pivot search, column swap,
-// reflector) and apply (one wave per trailing column: reflector update and
-// exact norm of the column below the new row).
+// reflector) and apply (one workgroup per trailing column: reflector update
+// and exact norm of the column below the new row).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void pivqr_init_kernel(const PivQrState* __restrict__ sts,
                                                          const int64_t* __restrict__ slab_ptr,
@@ -1635,67 +1635,87 @@ void launch_pivqr_pick(const PivQrState* st, int n, int t, hipStream_t s) {
   hipLaunchKernelGGL(pivqr_pick_kernel, dim3(n), dim3(1024), 0, s, st, t);
 }
 
+// Apply step: one 256-thread workgroup per trailing column.  Workgroup
+// b * per + q (per = widest trailing width) takes column t + 1 + q of matrix b.
+// The column's rows below t stay in registers (PA_RPT per thread, the rest are
+// read again) between the dot product with the reflector and the update, and
+// the exact norm of the updated rows below t comes from the same registers.
+constexpr int PA_RPT = 8;
+
 __global__ __launch_bounds__(256) void pivqr_apply_kernel(const PivQrState* __restrict__ sts,
-                                                          const int64_t* __restrict__ slab_ptr,
-                                                          int n, int t) {
-  int64_t slab = blockIdx.x;
-  int id = find_item(slab_ptr, n, slab);
-  const PivQrState st = sts[id];
+                                                          int per, int t) {
+  __shared__ double sh[4];
+  const int b = (int)(blockIdx.x / (unsigned)per);
+  const int q = (int)(blockIdx.x - (unsigned)b * (unsigned)per);
+  const PivQrState st = sts[b];
   // stopped before or at this step: flags[1] is the rank, equal to t + 1 only
   // when step t was taken
   if (st.flags[1] != t + 1) return;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int c = t + 1 + (int)(slab - slab_ptr[id]) * 4 + w;
+  const int c = t + 1 + q;
   if (c >= st.n) return;
+  const int tid = threadIdx.x;
   const double tau = st.scal[0];
   const int m = st.m;
   const double* v = st.A + (int64_t)t * st.lda;
   double* ac = st.A + (int64_t)c * st.lda;
+  const int r0 = t + 1 + tid;
+  double x[PA_RPT];
+#pragma unroll
+  for (int j = 0; j < PA_RPT; ++j) {
+    const int r = r0 + 256 * j;
+    x[j] = r < m ? gload(ac + r) : 0.0;
+  }
   if (tau != 0.0) {
-    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-    int r = t + 1 + lane;
-    for (; r + 192 < m; r += 256) {
-      p0 += v[r] * ac[r];
-      p1 += v[r + 64] * ac[r + 64];
-      p2 += v[r + 128] * ac[r + 128];
-      p3 += v[r + 192] * ac[r + 192];
+    double vv[PA_RPT];
+#pragma unroll
+    for (int j = 0; j < PA_RPT; ++j) {
+      const int r = r0 + 256 * j;
+      vv[j] = r < m ? gload(v + r) : 0.0;
     }
-    for (; r < m; r += 64) p0 += v[r] * ac[r];
-    const double p = wave_sum((p0 + p1) + (p2 + p3));
-    const double wsum = (ac[t] + p) * tau;
-    double s0 = 0.0, s1 = 0.0;
-    r = t + 1 + lane;
-    for (; r + 64 < m; r += 128) {
-      double x0 = ac[r] - wsum * v[r];
-      double x1 = ac[r + 64] - wsum * v[r + 64];
-      __builtin_nontemporal_store(x0, ac + r);
-      __builtin_nontemporal_store(x1, ac + r + 64);
-      s0 += x0 * x0;
-      s1 += x1 * x1;
+    double p = 0.0;
+#pragma unroll
+    for (int j = 0; j < PA_RPT; ++j) p = fma(vv[j], x[j], p);
+    for (int r = r0 + 256 * PA_RPT; r < m; r += 256) p = fma(gload(v + r), gload(ac + r), p);
+    const double dsum = block_sum256(p, sh);
+    const double wsum = (gload(ac + t) + dsum) * tau;
+    double s2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < PA_RPT; ++j) {
+      const int r = r0 + 256 * j;
+      if (r < m) {
+        const double y = x[j] - wsum * vv[j];
+        __builtin_nontemporal_store(y, ac + r);
+        s2 = fma(y, y, s2);
+      }
     }
-    for (; r < m; r += 64) {
-      double x = ac[r] - wsum * v[r];
-      __builtin_nontemporal_store(x, ac + r);
-      s0 += x * x;
+    for (int r = r0 + 256 * PA_RPT; r < m; r += 256) {
+      const double y = gload(ac + r) - wsum * gload(v + r);
+      __builtin_nontemporal_store(y, ac + r);
+      s2 = fma(y, y, s2);
     }
-    double s2 = wave_sum(s0 + s1);
-    if (lane == 0) {
+    s2 = block_sum256(s2, sh);  // its first barrier: every thread has read ac[t]
+    if (tid == 0) {
       ac[t] -= wsum;
       st.nrm[c] = sqrt(s2);
     }
   } else {
     double s2 = 0.0;
-    for (int r = t + 1 + lane; r < m; r += 64) s2 += ac[r] * ac[r];
-    s2 = wave_sum(s2);
-    if (lane == 0) st.nrm[c] = sqrt(s2);
+#pragma unroll
+    for (int j = 0; j < PA_RPT; ++j) s2 = fma(x[j], x[j], s2);
+    for (int r = r0 + 256 * PA_RPT; r < m; r += 256) {
+      const double y = gload(ac + r);
+      s2 = fma(y, y, s2);
+    }
+    s2 = block_sum256(s2, sh);
+    if (tid == 0) st.nrm[c] = sqrt(s2);
   }
 }
 
-void launch_pivqr_apply(const PivQrState* st, const int64_t* slab_ptr, int64_t nslabs, int n,
-                        int t, hipStream_t s) {
-  if (nslabs <= 0) return;
-  hipLaunchKernelGGL(pivqr_apply_kernel, dim3((unsigned)nslabs), dim3(256), 0, s, st, slab_ptr,
-                     n, t);
+void launch_pivqr_apply(const PivQrState* st, int n, int maxcols, int t, hipStream_t s) {
+  const int64_t per = (int64_t)maxcols - t - 1;  // widest trailing width
+  if (n <= 0 || per <= 0) return;
+  hipLaunchKernelGGL(pivqr_apply_kernel, dim3((unsigned)(per * n)), dim3(256), 0, s, st,
+                     (int)per, t);
 }
 
 // ---------------------------------------------------------------------------
