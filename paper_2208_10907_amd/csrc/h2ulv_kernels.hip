@@ -1369,14 +1369,25 @@ __global__ __launch_bounds__(1024) void pivqr_kernel(const PivQrItem* __restrict
     }
     __syncthreads();
     const double tau = s_tau;
-    // apply I - tau v v^T to columns c > t and recompute their norms below row t
-    for (int c = t + 1 + wv; c < n; c += PQ_WAVES) {
-      double* ac = A + (int64_t)c * lda;
-      double x[PQ_REG];
+    // apply I - tau v v^T to columns c > t and recompute their norms below row
+    // t; the wave's next column is loaded while the current one is processed
+    double x[PQ_REG];
+    {
+      const int c = t + 1 + wv;
 #pragma unroll
       for (int q = 0; q < PQ_REG; ++q) {
         const int r = t + lane + 64 * q;
-        x[q] = r < m ? ac[r] : 0.0;
+        x[q] = (c < n && r < m) ? gload(A + (int64_t)c * lda + r) : 0.0;
+      }
+    }
+    for (int c = t + 1 + wv; c < n; c += PQ_WAVES) {
+      double* ac = A + (int64_t)c * lda;
+      double xn[PQ_REG];
+      const int cn = c + PQ_WAVES;
+#pragma unroll
+      for (int q = 0; q < PQ_REG; ++q) {
+        const int r = t + lane + 64 * q;
+        xn[q] = (cn < n && r < m) ? gload(A + (int64_t)cn * lda + r) : 0.0;
       }
       if (tau != 0.0) {
         double dot = 0.0;
@@ -1403,22 +1414,29 @@ __global__ __launch_bounds__(1024) void pivqr_kernel(const PivQrItem* __restrict
       }
       sq = wave_sum(sq);
       if (lane == 0) s_nrm[c] = sqrt(sq);
+#pragma unroll
+      for (int q = 0; q < PQ_REG; ++q) x[q] = xn[q];
     }
     k = t + 1;
     __syncthreads();
   }
   if (tid == 0) *it.kout = k;
   for (int c = tid; c < n; c += 64 * PQ_WAVES) it.piv[c] = s_piv[c];
-  // E = R11^-1 R12 over R12 (rows 0..k-1, columns k..n-1): one wave per column,
-  // back substitution with the column in registers (row r in lane r % 64,
+  // E = R11^-1 R12 over R12 (rows 0..k-1, columns k..n-1): each wave takes
+  // PQ_NC columns at a time and solves them side by side, sharing the loads of
+  // R (back substitution with the columns in registers: row r in lane r % 64,
   // register r / 64)
-  for (int c = k + wv; c < n; c += PQ_WAVES) {
-    double* ac = A + (int64_t)c * lda;
-    double x[PQ_REG];
+  constexpr int PQ_NC = 4;
+  for (int c0 = k + wv; c0 < n; c0 += PQ_WAVES * PQ_NC) {
+    double x[PQ_NC][PQ_REG];
 #pragma unroll
-    for (int q = 0; q < PQ_REG; ++q) {
-      const int r = lane + 64 * q;
-      x[q] = r < k ? ac[r] : 0.0;
+    for (int j = 0; j < PQ_NC; ++j) {
+      const int c = c0 + PQ_WAVES * j;
+#pragma unroll
+      for (int q = 0; q < PQ_REG; ++q) {
+        const int r = lane + 64 * q;
+        x[j][q] = (c < n && r < k) ? gload(A + (int64_t)c * lda + r) : 0.0;
+      }
     }
 #pragma unroll
     for (int q = PQ_REG - 1; q >= 0; --q) {
@@ -1426,19 +1444,36 @@ __global__ __launch_bounds__(1024) void pivqr_kernel(const PivQrItem* __restrict
       for (int ii = top - 1; ii >= 0; --ii) {
         const int i = 64 * q + ii;
         const double* ri = A + (int64_t)i * lda;  // column i of R
-        const double xi = __shfl(x[q], ii, 64) / ri[i];
-        if (lane == ii) x[q] = xi;
+        const double dg = gload(ri + i);
+        double rv[PQ_REG];
 #pragma unroll
         for (int q2 = 0; q2 <= q; ++q2) {
           const int r = lane + 64 * q2;
-          if (r < i) x[q2] -= xi * ri[r];
+          rv[q2] = r < i ? gload(ri + r) : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < PQ_NC; ++j) {
+          const double xi = __shfl(x[j][q], ii, 64) / dg;
+          if (lane == ii) x[j][q] = xi;
+#pragma unroll
+          for (int q2 = 0; q2 <= q; ++q2) {
+            const int r = lane + 64 * q2;
+            if (r < i) x[j][q2] -= xi * rv[q2];
+          }
         }
       }
     }
 #pragma unroll
-    for (int q = 0; q < PQ_REG; ++q) {
-      const int r = lane + 64 * q;
-      if (r < k) ac[r] = x[q];
+    for (int j = 0; j < PQ_NC; ++j) {
+      const int c = c0 + PQ_WAVES * j;
+      if (c < n) {
+        double* ac = A + (int64_t)c * lda;
+#pragma unroll
+        for (int q = 0; q < PQ_REG; ++q) {
+          const int r = lane + 64 * q;
+          if (r < k) ac[r] = x[j][q];
+        }
+      }
     }
   }
 }
@@ -1635,16 +1670,17 @@ void launch_pivqr_pick(const PivQrState* st, int n, int t, hipStream_t s) {
   hipLaunchKernelGGL(pivqr_pick_kernel, dim3(n), dim3(1024), 0, s, st, t);
 }
 
-// Apply step: one 256-thread workgroup per trailing column.  Workgroup
+// Apply step: one PA_THREADS-thread workgroup per trailing column.  Workgroup
 // b * per + q (per = widest trailing width) takes column t + 1 + q of matrix b.
 // The column's rows below t stay in registers (PA_RPT per thread, the rest are
 // read again) between the dot product with the reflector and the update, and
 // the exact norm of the updated rows below t comes from the same registers.
+constexpr int PA_THREADS = 256;
 constexpr int PA_RPT = 8;
 
-__global__ __launch_bounds__(256) void pivqr_apply_kernel(const PivQrState* __restrict__ sts,
-                                                          int per, int t) {
-  __shared__ double sh[4];
+__global__ __launch_bounds__(PA_THREADS) void pivqr_apply_kernel(
+    const PivQrState* __restrict__ sts, int per, int t) {
+  __shared__ double sh[PA_THREADS / 64];
   const int b = (int)(blockIdx.x / (unsigned)per);
   const int q = (int)(blockIdx.x - (unsigned)b * (unsigned)per);
   const PivQrState st = sts[b];
@@ -1662,38 +1698,39 @@ __global__ __launch_bounds__(256) void pivqr_apply_kernel(const PivQrState* __re
   double x[PA_RPT];
 #pragma unroll
   for (int j = 0; j < PA_RPT; ++j) {
-    const int r = r0 + 256 * j;
+    const int r = r0 + PA_THREADS * j;
     x[j] = r < m ? gload(ac + r) : 0.0;
   }
   if (tau != 0.0) {
     double vv[PA_RPT];
 #pragma unroll
     for (int j = 0; j < PA_RPT; ++j) {
-      const int r = r0 + 256 * j;
+      const int r = r0 + PA_THREADS * j;
       vv[j] = r < m ? gload(v + r) : 0.0;
     }
     double p = 0.0;
 #pragma unroll
     for (int j = 0; j < PA_RPT; ++j) p = fma(vv[j], x[j], p);
-    for (int r = r0 + 256 * PA_RPT; r < m; r += 256) p = fma(gload(v + r), gload(ac + r), p);
-    const double dsum = block_sum256(p, sh);
+    for (int r = r0 + PA_THREADS * PA_RPT; r < m; r += PA_THREADS)
+      p = fma(gload(v + r), gload(ac + r), p);
+    const double dsum = block_sum<PA_THREADS / 64>(p, sh);
     const double wsum = (gload(ac + t) + dsum) * tau;
     double s2 = 0.0;
 #pragma unroll
     for (int j = 0; j < PA_RPT; ++j) {
-      const int r = r0 + 256 * j;
+      const int r = r0 + PA_THREADS * j;
       if (r < m) {
         const double y = x[j] - wsum * vv[j];
         __builtin_nontemporal_store(y, ac + r);
         s2 = fma(y, y, s2);
       }
     }
-    for (int r = r0 + 256 * PA_RPT; r < m; r += 256) {
+    for (int r = r0 + PA_THREADS * PA_RPT; r < m; r += PA_THREADS) {
       const double y = gload(ac + r) - wsum * gload(v + r);
       __builtin_nontemporal_store(y, ac + r);
       s2 = fma(y, y, s2);
     }
-    s2 = block_sum256(s2, sh);  // its first barrier: every thread has read ac[t]
+    s2 = block_sum<PA_THREADS / 64>(s2, sh);  // its first barrier: every thread has read ac[t]
     if (tid == 0) {
       ac[t] -= wsum;
       st.nrm[c] = sqrt(s2);
@@ -1702,11 +1739,11 @@ __global__ __launch_bounds__(256) void pivqr_apply_kernel(const PivQrState* __re
     double s2 = 0.0;
 #pragma unroll
     for (int j = 0; j < PA_RPT; ++j) s2 = fma(x[j], x[j], s2);
-    for (int r = r0 + 256 * PA_RPT; r < m; r += 256) {
+    for (int r = r0 + PA_THREADS * PA_RPT; r < m; r += PA_THREADS) {
       const double y = gload(ac + r);
       s2 = fma(y, y, s2);
     }
-    s2 = block_sum256(s2, sh);
+    s2 = block_sum<PA_THREADS / 64>(s2, sh);
     if (tid == 0) st.nrm[c] = sqrt(s2);
   }
 }
@@ -1714,7 +1751,7 @@ __global__ __launch_bounds__(256) void pivqr_apply_kernel(const PivQrState* __re
 void launch_pivqr_apply(const PivQrState* st, int n, int maxcols, int t, hipStream_t s) {
   const int64_t per = (int64_t)maxcols - t - 1;  // widest trailing width
   if (n <= 0 || per <= 0) return;
-  hipLaunchKernelGGL(pivqr_apply_kernel, dim3((unsigned)(per * n)), dim3(256), 0, s, st,
+  hipLaunchKernelGGL(pivqr_apply_kernel, dim3((unsigned)(per * n)), dim3(PA_THREADS), 0, s, st,
                      (int)per, t);
 }
 
