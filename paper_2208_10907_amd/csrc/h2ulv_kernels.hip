@@ -1802,13 +1802,48 @@ __device__ __forceinline__ double inv_sqrt(double r2) {
   return fma(y, e * fma(0.375, e, 0.5), y);
 }
 
+// Sources t < cnt of the staged tile against the thread's two targets.  SELF:
+// the tile holds target indices, whose self term (r^2 = 0) is excluded by a
+// select; other tiles have r^2 > 0 throughout, since the points are distinct
+// (a factorization rejects coinciding points).
+template <int NR, bool LAP, bool SELF>
+__device__ __forceinline__ void matvec_tile(const double (*sp)[256], const double (*sx)[256],
+                                            int cnt, const double* p0, const double* p1,
+                                            double alpha, double* a0, double* a1) {
+  for (int t = 0; t < cnt; ++t) {
+    const double sx0 = sp[0][t], sy0 = sp[1][t], sz0 = sp[2][t];
+    double dx = p0[0] - sx0, dy = p0[1] - sy0, dz = p0[2] - sz0;
+    const double q0 = fma(dx, dx, fma(dy, dy, dz * dz));
+    dx = p1[0] - sx0;
+    dy = p1[1] - sy0;
+    dz = p1[2] - sz0;
+    const double q1 = fma(dx, dx, fma(dy, dy, dz * dz));
+    double k0 = inv_sqrt(q0), k1 = inv_sqrt(q1);
+    if (!LAP) {
+      k0 *= exp(-alpha * (q0 * k0));
+      k1 *= exp(-alpha * (q1 * k1));
+    }
+    if (SELF) {
+      k0 = q0 > 0.0 ? k0 : 0.0;
+      k1 = q1 > 0.0 ? k1 : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      const double xs = sx[c][t];
+      a0[c] = fma(k0, xs, a0[c]);
+      a1[c] = fma(k1, xs, a1[c]);
+    }
+  }
+}
+
 // Exact y = A x with the matrix generated on the fly.  Each thread owns two
 // target points (i and i + 256) and runs over the sources [js, je) staged in
-// LDS, 256 at a time; the self term is excluded by a select on r^2 > 0.  The
-// kernel kind is a template parameter (no branch in the inner loop).  With one
-// source range the result y = diag x + sum is written directly; otherwise the
-// range blockIdx.y writes its partial sums to part and matvec_reduce_kernel
-// adds them in a fixed order.
+// LDS, 256 at a time; only the tiles that hold target indices of the
+// workgroup test for the self term.  The kernel kind is a template parameter
+// (no branch in the inner loop).  With one source range the result
+// y = diag x + sum is written directly; otherwise the range blockIdx.y writes
+// its partial sums to part and matvec_reduce_kernel adds them in a fixed
+// order.
 template <int NR, bool LAP>
 __global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ pts, int64_t n,
                                                      KernelFn kf, const double* __restrict__ x,
@@ -1843,28 +1878,11 @@ __global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ 
     }
     __syncthreads();
     const int cnt = (int)min((int64_t)256, je - j0);
-    for (int t = 0; t < cnt; ++t) {
-      const double sx0 = sp[0][t], sy0 = sp[1][t], sz0 = sp[2][t];
-      double dx = p0[0] - sx0, dy = p0[1] - sy0, dz = p0[2] - sz0;
-      const double q0 = fma(dx, dx, fma(dy, dy, dz * dz));
-      dx = p1[0] - sx0;
-      dy = p1[1] - sy0;
-      dz = p1[2] - sz0;
-      const double q1 = fma(dx, dx, fma(dy, dy, dz * dz));
-      double k0 = inv_sqrt(q0), k1 = inv_sqrt(q1);
-      if (!LAP) {
-        k0 *= exp(-kf.alpha * (q0 * k0));
-        k1 *= exp(-kf.alpha * (q1 * k1));
-      }
-      k0 = q0 > 0.0 ? k0 : 0.0;
-      k1 = q1 > 0.0 ? k1 : 0.0;
-#pragma unroll
-      for (int c = 0; c < NR; ++c) {
-        const double xs = sx[c][t];
-        a0[c] = fma(k0, xs, a0[c]);
-        a1[c] = fma(k1, xs, a1[c]);
-      }
-    }
+    const int64_t ib = (int64_t)blockIdx.x * 512;  // targets [ib, ib + 512)
+    if (j0 < ib + 512 && j0 + 256 > ib)
+      matvec_tile<NR, LAP, true>(sp, sx, cnt, p0, p1, kf.alpha, a0, a1);
+    else
+      matvec_tile<NR, LAP, false>(sp, sx, cnt, p0, p1, kf.alpha, a0, a1);
   }
   if (part == nullptr) {
     if (i0 < n) {
