@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -335,6 +336,18 @@ struct GemmBatch {
       terms.clear();
       return;
     }
+    // products with at most GEMV_MAXN columns (the solve's right-hand sides)
+    // are matrix-vector work: vector units, A read once, no MFMA tiles
+    if constexpr (sizeof(T) == 8 && sizeof(TC) == 8) {
+      int maxN = 0;
+      bool btrans = false;
+      for (auto& it : its) maxN = std::max(maxN, it.N);
+      for (auto& tt : terms) btrans = btrans || (tt.flags & 2) != 0;
+      if (maxN <= GEMV_MAXN && !btrans) {
+        run_gemv(st, its, site);
+        return;
+      }
+    }
     // tile shape: 32 x 128 when every item has at most 32 rows (Householder
     // V^T A products); otherwise the shape with the best estimated rate, i.e.
     // the measured rate of the shape on full tiles (gfx950, TFLOP/s) times the
@@ -468,6 +481,101 @@ struct GemmBatch {
                                : "",
                  fl, by, st.s);
     launch_gemm<T, TC>(di, dt, dp, nt, ni, tm, tn, st.s);
+    H2ULV_HIP(hipGetLastError());
+    if (!red.empty()) {
+      std::vector<int64_t> rp(red.size() + 1, 0);
+      for (size_t i = 0; i < red.size(); ++i) rp[i + 1] = rp[i] + tiles64(red[i].M, red[i].N);
+      SplitKItem<TC>* dr;
+      int64_t* drp;
+      st.up2(red, rp, &dr, &drp);
+      launch_splitk_reduce<TC>(dr, drp, rp.back(), (int)red.size(), st.s);
+      H2ULV_HIP(hipGetLastError());
+    }
+  }
+  // Few-column products on gemv_kernel (64-row tiles).  Long sums are split
+  // over up to 64 workgroups per tile (about 2048 workgroups in all, chunks of
+  // at least 512), the partial products added in order by the split-K
+  // reduction.
+  void run_gemv(Stage& st, std::vector<GemmItem<TC>>& its, const char* site) {
+    std::vector<double> ksum(its.size(), 0.0);
+    double kmax = 0;
+    int64_t nt0 = 0;
+    for (size_t i = 0; i < its.size(); ++i) {
+      for (int t = its[i].t0; t < its[i].t0 + its[i].nt; ++t) ksum[i] += terms[t].K;
+      kmax = std::max(kmax, ksum[i]);
+      nt0 += (its[i].M + 63) / 64;
+    }
+    double fl = 0, by = 0;
+    if (profiler().on) {
+      for (auto& it : its) {
+        for (int t = it.t0; t < it.t0 + it.nt; ++t) {
+          const double K = terms[t].K;
+          fl += 2.0 * it.M * it.N * K;
+          by += ((double)it.M * K + K * it.N) * sizeof(T);
+        }
+        by += (double)it.M * it.N * sizeof(TC) * (it.beta != 0.0 ? 2 : 1);
+      }
+    }
+    int S = 1;
+    if (nt0 < 2048 && kmax >= 1024) {
+      const double want = std::ceil(2048.0 / (double)std::max<int64_t>(nt0, 1));
+      S = (int)std::min(64.0, std::min(want, std::floor(kmax / 512.0)));
+      S = std::max(S, 1);
+    }
+    std::vector<SplitKItem<TC>> red;
+    if (S >= 2) {
+      int64_t pw = 0;
+      for (auto& it : its) pw += (int64_t)it.M * it.N * S;
+      TC* part = st.scratch<TC>(pw);
+      std::vector<GemmItem<TC>> sits;
+      std::vector<GemmTerm<T>> sterms;
+      int64_t po = 0;
+      for (size_t i = 0; i < its.size(); ++i) {
+        const GemmItem<TC>& it = its[i];
+        const int64_t mn = (int64_t)it.M * it.N;
+        red.push_back(SplitKItem<TC>{it.C, it.ldc, part + po, it.M, it.N, S, it.alpha, it.beta});
+        const int64_t kt = (int64_t)ksum[i];
+        const int64_t chunk = std::max<int64_t>(1, (kt + S - 1) / S);
+        for (int sp = 0; sp < S; ++sp) {
+          GemmItem<TC> ni_ = it;
+          ni_.C = part + po + sp * mn;
+          ni_.ldc = it.M;
+          ni_.alpha = 1.0;
+          ni_.beta = 0.0;
+          ni_.t0 = (int32_t)sterms.size();
+          ni_.nt = 0;
+          const int64_t lo = sp * chunk, hi = std::min(kt, lo + chunk);
+          int64_t base = 0;
+          for (int t = it.t0; t < it.t0 + it.nt; ++t) {
+            const GemmTerm<T>& tt = terms[t];
+            const int64_t a0 = std::max(lo, base), a1 = std::min(hi, base + tt.K);
+            if (a1 > a0) {
+              const int64_t k0 = a0 - base;
+              GemmTerm<T> st_ = tt;
+              st_.K = (int32_t)(a1 - a0);
+              st_.A = (tt.flags & 1) ? tt.A + k0 : tt.A + k0 * tt.lda;
+              st_.B = tt.B + k0;  // B is not transposed here
+              sterms.push_back(st_);
+              ni_.nt++;
+            }
+            base += tt.K;
+          }
+          sits.push_back(ni_);
+        }
+        po += mn * S;
+      }
+      its.swap(sits);
+      terms.swap(sterms);
+    }
+    std::vector<int64_t> tp(its.size() + 1, 0);
+    for (size_t i = 0; i < its.size(); ++i) tp[i + 1] = tp[i] + (its[i].M + 63) / 64;
+    GemmItem<TC>* di;
+    GemmTerm<T>* dt;
+    int64_t* dp;
+    st.up3(its, terms, tp, &di, &dt, &dp);
+    terms.clear();
+    ProfScope ps(profiler().on ? profile_name("gemv_f64", site) : "", fl, by, st.s);
+    launch_gemv(di, dt, dp, tp.back(), (int)its.size(), st.s);
     H2ULV_HIP(hipGetLastError());
     if (!red.empty()) {
       std::vector<int64_t> rp(red.size() + 1, 0);

@@ -137,6 +137,11 @@ void launch_gemm(const GemmItem<TC>* items, const GemmTerm<TI>* terms, const int
 template <typename T>
 void launch_splitk_reduce(const SplitKItem<T>* items, const int64_t* tile_ptr, int64_t ntiles,
                           int nitems, hipStream_t s);
+// Products with N <= GEMV_MAXN columns and B not transposed, on the vector
+// units; tiles of 64 rows (tile_ptr: per-item prefix of ceil(M / 64)).
+constexpr int GEMV_MAXN = 4;
+void launch_gemv(const GemmItem<double>* items, const GemmTerm<double>* terms,
+                 const int64_t* tile_ptr, int64_t ntiles, int nitems, hipStream_t s);
 // maxrows: largest m - j0 over the matrices (selects the register-resident panel)
 void launch_lu_panel(const MatDesc* d, int nmat, int j0, int nb, int maxrows, hipStream_t s);
 void launch_lu_swap_trsm(const MatDesc* d, const int64_t* slab_ptr, int64_t nslabs, int nmat,

@@ -390,6 +390,117 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const SplitKItem<T>*
   }
 }
 
+// ---------------------------------------------------------------------------
+// Products with at most GEMV_MAXN right-hand columns (the solve's vectors):
+// C = beta C + alpha sum_t op(A_t) B_t with B_t not transposed.  This is
+// matrix-vector work, bound by reading A once from HBM, so it runs on the
+// vector units: one 256-thread workgroup per 64 rows of an item.
+//   op(A) = A (column-major M x K): lane = row, wave = k mod 4, four columns of
+//     A in flight per wave (each a coalesced 64-row segment);
+//   op(A) = A^T (row i of op(A) contiguous): wave w takes rows 16w..16w+15,
+//     four at a time, lanes over k, then a wave sum per row and column.
+// Per-wave partial sums meet in LDS and are added in wave order (deterministic).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gemv_kernel(const GemmItem<double>* __restrict__ items,
+                                                   const GemmTerm<double>* __restrict__ terms,
+                                                   const int64_t* __restrict__ tile_ptr,
+                                                   int nitems) {
+  __shared__ double red[4][64][GEMV_MAXN];
+  const int64_t tile = blockIdx.x;
+  const int id = find_item(tile_ptr, nitems, tile);
+  const GemmItem<double> it = items[id];
+  const int i0 = (int)(tile - tile_ptr[id]) * 64;
+  const int M = it.M, N = it.N;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < GEMV_MAXN; ++j) red[w][lane][j] = 0.0;  // this wave's slots only
+  double acc[GEMV_MAXN];
+#pragma unroll
+  for (int j = 0; j < GEMV_MAXN; ++j) acc[j] = 0.0;
+  for (int t = it.t0; t < it.t0 + it.nt; ++t) {
+    const GemmTerm<double> tt = terms[t];
+    const int K = tt.K;
+    if (!(tt.flags & 1)) {
+      const int i = i0 + lane;
+      if (i < M) {
+        const double* a = tt.A + i;
+        int k = w;
+        for (; k + 12 < K; k += 16) {
+          double av[4], bv[4][GEMV_MAXN];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) av[q] = gload(a + (int64_t)(k + 4 * q) * tt.lda);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < GEMV_MAXN; ++j)
+              bv[q][j] = j < N ? gload(tt.B + (k + 4 * q) + (int64_t)j * tt.ldb) : 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < GEMV_MAXN; ++j) acc[j] = fma(av[q], bv[q][j], acc[j]);
+        }
+        for (; k < K; k += 4) {
+          const double av = gload(a + (int64_t)k * tt.lda);
+#pragma unroll
+          for (int j = 0; j < GEMV_MAXN; ++j)
+            acc[j] = fma(av, j < N ? gload(tt.B + k + (int64_t)j * tt.ldb) : 0.0, acc[j]);
+        }
+      }
+    } else {
+      for (int g = 0; g < 4; ++g) {  // rows 16w + 4g .. 16w + 4g + 3
+        const int rl = 16 * w + 4 * g;
+        double pr[4][GEMV_MAXN];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int j = 0; j < GEMV_MAXN; ++j) pr[q][j] = 0.0;
+        for (int k = lane; k < K; k += 64) {
+          double bv[GEMV_MAXN];
+#pragma unroll
+          for (int j = 0; j < GEMV_MAXN; ++j)
+            bv[j] = j < N ? gload(tt.B + k + (int64_t)j * tt.ldb) : 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = i0 + rl + q;
+            const double av = i < M ? gload(tt.A + k + (int64_t)i * tt.lda) : 0.0;
+#pragma unroll
+            for (int j = 0; j < GEMV_MAXN; ++j) pr[q][j] = fma(av, bv[j], pr[q][j]);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int j = 0; j < GEMV_MAXN; ++j) {
+            const double v = wave_sum(pr[q][j]);
+            if (lane == 0) red[w][rl + q][j] += v;
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < GEMV_MAXN; ++j) red[w][lane][j] += acc[j];
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int r = threadIdx.x, i = i0 + r;
+    if (i < M) {
+      for (int j = 0; j < N; ++j) {
+        const double sum = ((red[0][r][j] + red[1][r][j]) + red[2][r][j]) + red[3][r][j];
+        double* cp = it.C + i + (int64_t)j * it.ldc;
+        double v = it.alpha * sum;
+        if (it.beta != 0.0) v += it.beta * (*cp);
+        *cp = v;
+      }
+    }
+  }
+}
+
+void launch_gemv(const GemmItem<double>* items, const GemmTerm<double>* terms,
+                 const int64_t* tile_ptr, int64_t ntiles, int nitems, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(gemv_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, items, terms, tile_ptr,
+                     nitems);
+}
+
 template <typename T>
 void launch_splitk_reduce(const SplitKItem<T>* items, const int64_t* tile_ptr, int64_t ntiles,
                           int nitems, hipStream_t s) {
