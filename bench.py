@@ -207,8 +207,8 @@ def main() -> int:
         print(json.dumps({"copy_probe_bytes": args.copy_probe << 20}))
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the distributed process tree of "
-              "the paper is a design note, not built); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only (the distributed process tree of the paper "
+              "is a design note, not built); use --gpus 1", file=sys.stderr)
         return 2
 
     import torch

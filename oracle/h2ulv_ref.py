@@ -324,8 +324,8 @@ def complement_basis(W: np.ndarray):
 
 # ---------------------------------------------------------------------------
 # Learned-rank variant of the basis step: box features, and the row ID taken
-# from a Gaussian sketch of M' sized by the predicted rank, judged by a
-# randomized probe of its error (falls back to the full pivoted QR).
+# from a Gaussian sketch of M' sized by the predicted rank, accepted or
+# rejected by a randomized probe of its error (falls back to the full pivoted QR).
 # ---------------------------------------------------------------------------
 SKETCH_PROBES = 8       # probe columns of the error check
 SKETCH_SLACK = 10.0     # allowed factor over the pivoted-QR error bound

@@ -220,8 +220,8 @@ def test_bases_orthogonal_and_nested():
 @pytest.mark.parametrize("tol,bound", [(1e-6, 1e-3), (1e-8, 1e-5)])
 def test_accuracy_against_dense_lu(tol, bound):
     """Relative L2 error against a LAPACK dense solve, the paper's accuracy
-    metric (Sec. IV-A), at its two accuracy levels.  The bound is this build's
-    measurement of the method as read (parity with the paper's plotted values
+    metric (Sec. IV-A), at its two accuracy levels.  The bound is the measured
+    error of the method as read here (parity with the paper's plotted values
     is unpinned: the figures are not available)."""
     X = W.cube_points(2048, 1)
     p = O.Params(leaf=64, tol=tol, far_sample=0)
