@@ -1644,16 +1644,35 @@ __global__ __launch_bounds__(1024) void pivqr_pick_kernel(const PivQrState* __re
   __shared__ int s_wi[16];
   __shared__ double sh[16];
   const PivQrState st = sts[blockIdx.x];
-  if (st.flags[0]) return;
   const int m = st.m, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int ncol = st.n;
+  // the stop flag, the threshold and the first PK_NV candidate norms of this
+  // thread are loaded together (reading them is harmless for a stopped box)
+  constexpr int PK_NV = 4;
+  const int stopped = st.flags[0];
+  const double thr_prev = st.scal[1];
+  double nv[PK_NV];
+#pragma unroll
+  for (int i = 0; i < PK_NV; ++i) {
+    const int c = t + tid + 1024 * i;
+    nv[i] = c < ncol ? st.nrm[c] : -1.0;
+  }
+  if (stopped) return;
   if (t >= st.cap) {
     if (tid == 0) st.flags[0] = 1;
     return;
   }
-  const int ncol = st.n;
   double best = -1.0;
   int bi = ncol;
-  for (int c = t + tid; c < ncol; c += 1024) {
+#pragma unroll
+  for (int i = 0; i < PK_NV; ++i) {
+    const int c = t + tid + 1024 * i;
+    if (c < ncol && nv[i] > best) {
+      best = nv[i];
+      bi = c;
+    }
+  }
+  for (int c = t + tid + 1024 * PK_NV; c < ncol; c += 1024) {
     const double v = st.nrm[c];
     if (v > best) {
       best = v;
@@ -1686,7 +1705,7 @@ __global__ __launch_bounds__(1024) void pivqr_pick_kernel(const PivQrState* __re
   }
   const double pn = best;
   const int p = bi;
-  const double thr = (t == 0) ? st.tol * pn : st.scal[1];
+  const double thr = (t == 0) ? st.tol * pn : thr_prev;
   if (!(pn > thr) || !(pn > 0.0) || p >= ncol) {  // same decision in every thread
     if (tid == 0) st.flags[0] = 1;
     return;
