@@ -1,0 +1,38 @@
+"""Host-side pieces of bench.py that need no GPU: the traffic record it
+reports only while the library sources match, and the single-GPU guard."""
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+
+def test_traffic_record_matches_sources():
+    """The committed traffic record parses; bench.py reports it only while it
+    was taken with the current library sources (skipped, not failed, after a
+    change to the sources: the counters then have to be taken again)."""
+    text = open(bench.TRAFFIC_FILE).read()
+    assert "traffic_bytes_per_launch:" in text and "library_source_sha256:" in text
+    t = bench.recorded_traffic("ellipsoids262144")
+    if t is None:
+        pytest.skip("traffic record taken with other library sources")
+    assert 1e6 < t < 1e11
+
+
+def test_traffic_record_rejected_on_other_sources(monkeypatch):
+    monkeypatch.setattr(bench, "library_source_hash", lambda: "0" * 64)
+    assert bench.recorded_traffic("ellipsoids262144") is None
+    assert bench.recorded_traffic("cube2048") is None
+
+
+def test_source_hash_is_stable():
+    assert bench.library_source_hash() == bench.library_source_hash()
+    assert len(bench.library_source_hash()) == 64
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
