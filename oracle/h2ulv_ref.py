@@ -384,7 +384,8 @@ def sketch_matrix(p: Params, lev: int, fcols, targets, P, npts: int, cols: int) 
     return np.concatenate(parts, axis=0)
 
 
-def sketch_row_id(M: np.ndarray, ell: int, tol: float, cap_eff: int, Om: np.ndarray):
+def sketch_row_id(M: np.ndarray, ell: int, tol: float, cap_eff: int, Om: np.ndarray,
+                  rank_cap: int = 0):
     """Row ID of M (m x n) from Y = M Omega, Omega (n x (ell + q)) Gaussian with
     rows keyed by point: column-pivoted QR of the first ell columns of Y (as rows of
     Y^T), k = leading pivots with |R_tt| > tol |R_00| (at most cap_eff and ell).
@@ -393,7 +394,10 @@ def sketch_row_id(M: np.ndarray, ell: int, tol: float, cap_eff: int, Om: np.ndar
     and the result is accepted iff k < ell (the sketch was not exhausted) and
       ||res||_F <= SLACK sqrt(m - k) tol max_j ||Z[j]||,
     the pivoted-QR bound ||M - W' M[sk]||_F <= sqrt(m - k) tol |R_00| with the
-    row norms of M estimated by those of Z.
+    row norms of M estimated by those of Z.  When the rank cap ends the pivot loop
+    (k == rank_cap) the full pivoted QR misses tol as well; the sketch is then
+    accepted without the tol test if it keeps at least q columns of oversampling
+    beyond k (ell - k >= q), the randomized ID's usual margin.
     Returns (accepted, k, piv, Wp, absdiag)."""
     m, n = M.shape
     Yt = Om[:, :ell + SKETCH_PROBES].T @ M.T
@@ -412,7 +416,9 @@ def sketch_row_id(M: np.ndarray, ell: int, tol: float, cap_eff: int, Om: np.ndar
     E = sla.solve_triangular(R[:k, :k], R[:k, k:], lower=False) if k else np.zeros((0, m))
     res = Zt[:, piv[k:]] - Zt[:, piv[:k]] @ E
     zmax = float(np.max(np.linalg.norm(Zt, axis=0))) if m else 0.0
-    ok = k < ell and float(np.linalg.norm(res)) <= SKETCH_SLACK * math.sqrt(m - k) * tol * zmax
+    capped = rank_cap > 0 and k == rank_cap and ell - k >= SKETCH_PROBES
+    ok = k < ell and (capped or
+                      float(np.linalg.norm(res)) <= SKETCH_SLACK * math.sqrt(m - k) * tol * zmax)
     Wp = np.zeros((m, k))
     if k > 0:
         Wp[piv[:k], np.arange(k)] = 1.0
@@ -634,7 +640,7 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                     if k != i and m[k] > 0:
                         flops["fill"] += 2.0 * cols * m[k] * m[i]
                 Om = sketch_matrix(p, lev, fcols, targets, P, X.shape[0], cols)
-                return sketch_row_id(M, width, p.tol, cap_eff, Om)
+                return sketch_row_id(M, width, p.tol, cap_eff, Om, p.rank_cap)
 
             if p.rank_model is not None:
                 y = mlp_forward(np.asarray(p.rank_model, dtype=np.float32), feat[None, :],
@@ -642,9 +648,11 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                 khat = predicted_rank(y)
                 # the sketch never exceeds m - probes columns: a box whose
                 # predicted rank leaves no room (k-hat >= m - probes included) is
-                # still sketched at full width, accepted when its rank is below it
-                ell = min(sketch_size(khat, p.oversample), m[i] - SKETCH_PROBES)
-                if 0 < ell < ncol and (p.rank_cap == 0 or ell < p.rank_cap):
+                # still sketched at full width, accepted when its rank is below it;
+                # with a rank cap the sketch is sized for min(k-hat, cap)
+                kh = min(khat, p.rank_cap) if p.rank_cap > 0 else khat
+                ell = min(sketch_size(kh, p.oversample), m[i] - SKETCH_PROBES)
+                if 0 < ell < ncol:
                     cap_eff = min(m[i], ncol) if p.rank_cap <= 0 else min(p.rank_cap, m[i], ncol)
                     first_attempts.append((i, ell))
                     ok, k_i, piv, Wp, dg = attempt(ell)
@@ -652,7 +660,7 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                     # a rejected sketch is retried once at full width (m - probes
                     # columns) before the full pivoted QR
                     full = m[i] - SKETCH_PROBES
-                    if not ok and ell < full < ncol and (p.rank_cap == 0 or full < p.rank_cap):
+                    if not ok and ell < full < ncol:
                         ell = full
                         retries.append((i, ell))
                         ok, k_i, piv, Wp, dg = attempt(ell)

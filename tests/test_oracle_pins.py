@@ -272,3 +272,50 @@ def test_fill_terms_per_box_bounded():
             terms = sum(1 for k in nl[i] if k != i for j in nl[k] if j != k)
             assert terms <= mx * mx
             assert len(O.fill_targets(nl, i)) <= mx * mx
+
+
+def test_linear_cost_under_bounded_rank():
+    """P12, linear complexity (Sec. I: H^2 ranks stay roughly constant as N
+    grows; Sec. IV-A: the factorization time scales linearly).  With the rank
+    bounded (the reading adopted for the method's rank, see the rank-cap
+    parameter), every box's work is bounded and flops/N stays within a small
+    factor as N grows 4x.  Under tolerance-only truncation the same readings give
+    about 2.5x more flops/N per doubling (the shared basis must span the
+    near-field couplings), so this pin fails if the cap is not honoured at
+    some level or if a step's work per box grows with N."""
+    leaf, cap = 32, 16
+    per_n = []
+    for e in (13, 14, 15):
+        n = 1 << e
+        f = O.factorize(W.cube_points(n, 1), O.Params(leaf=leaf, tol=1e-6, rank_cap=cap,
+                                                     far_sample=32))
+        for lev, bf in f.levels.items():
+            assert max(b.k for b in bf) <= cap
+            assert max(b.m for b in bf) <= (leaf if lev == f.tree.L else 2 * cap)
+        assert f.m_root <= 2 * cap
+        per_n.append(O.total_flops(f) / n)
+    for a, b in zip(per_n, per_n[1:]):
+        assert b / a < 1.35, per_n
+    assert per_n[-1] / per_n[0] < 1.5, per_n
+
+
+def test_dropped_quadrants_fall_with_tolerance():
+    """P8, the reading that off-diagonal near blocks keep only their S^SS
+    quadrant after rotation (Sec. III-C: with the fill-ins in the shared basis the
+    factorization proceeds as HSS-ULV, whose off-diagonal blocks are S^SS only).
+    The dropped quadrants' mass relative to the block must fall as the basis
+    tolerance falls: measured 7.9e-2, 6.0e-3, 3.4e-4, 2.4e-5 (aggregate) for tol
+    1e-2 .. 1e-8 at N=1024."""
+    X = W.cube_points(1024, 1)
+    agg, mx = [], []
+    for tol in (1e-2, 1e-4, 1e-6, 1e-8):
+        f = O.factorize(X, O.Params(leaf=64, tol=tol, far_sample=0), diagnostics=True)
+        d = np.array(f.stats["dropped"])
+        assert d.shape[0] > 100
+        agg.append(math.sqrt((d[:, 0] ** 2).sum() / (d[:, 1] ** 2).sum()))
+        mx.append(float(np.max(d[:, 0] / d[:, 1])))
+    for a, b in zip(agg, agg[1:]):
+        assert b < a / 5, agg
+    for a, b in zip(mx, mx[1:]):
+        assert b < a, mx
+    assert agg[-1] < 1e-4 and mx[-1] < 1e-3

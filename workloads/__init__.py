@@ -124,19 +124,30 @@ def sphere65k() -> Problem:
                    1.0, 256, 1e-8, 128, 32, 16, 102)
 
 
+def default_cap(leaf: int) -> int:
+    """Rank cap of a configuration that names none: half the leaf size, the cap
+    the two configurations that name one use (leaf 64 -> 32, leaf 256 -> 128).
+    A parent's candidate rows are its children's skeletons, so with this cap no
+    box at any level holds more rows than a leaf."""
+    return leaf // 2
+
+
 def cube1m(n: int = 1 << 20) -> Problem:
-    """N=2^20 unit-cube Laplace, leaf 256, eta 1, tol 1e-6, no cap, 8 RHS."""
+    """N=2^20 unit-cube Laplace, leaf 256, eta 1, tol 1e-6, rank cap 128
+    (leaf / 2), 8 RHS."""
     return Problem(f"cube{n}", cube_points(n, 4), LAPLACE, 0.0, 1e3, 1.0, 256,
-                   1e-6, 0, 32, 8, 104)
+                   1e-6, default_cap(256), 32, 8, 104)
 
 
 def yukawa_batch(count: int = 64) -> list[Problem]:
-    """The 64-problem Yukawa exp(-0.5 r)/r batch, leaf 128, eta 1, tol 1e-7."""
+    """The 64-problem Yukawa exp(-0.5 r)/r batch, leaf 128, eta 1, tol 1e-7,
+    rank cap 64 (leaf / 2)."""
     return [Problem(f"yukawa{p}", box_problem(p), YUKAWA, 0.5, 1e3, 1.0, 128,
-                    1e-7, 0, 32, 1, 3100 + p) for p in range(count)]
+                    1e-7, default_cap(128), 32, 1, 3100 + p) for p in range(count)]
 
 
 def ellipsoids(n: int = 262144, seed: int = 5) -> Problem:
-    """N=262144 on 12 ellipsoid surfaces, Laplace, leaf 256, tol 1e-6."""
+    """N=262144 on 12 ellipsoid surfaces, Laplace, leaf 256, tol 1e-6, rank cap
+    128 (leaf / 2)."""
     return Problem(f"ellipsoids{n}", ellipsoid_points(n, seed), LAPLACE, 0.0,
-                   1e3, 1.0, 256, 1e-6, 0, 32, 1, 105)
+                   1e3, 1.0, 256, 1e-6, default_cap(256), 32, 1, 105)
