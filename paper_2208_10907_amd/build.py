@@ -43,11 +43,13 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> Path:
+    from concurrent.futures import ThreadPoolExecutor
     BUILD_DIR.mkdir(exist_ok=True)
     OUT_DIR.mkdir(exist_ok=True)
     cc = hipcc()
-    objs = []
-    for src, extra in SOURCES:
+
+    def compile_one(item):
+        src, extra = item
         obj = BUILD_DIR / (src.replace(".", "_") + ".o")
         cmd = [cc, *HIP_FLAGS, *extra, "-c", str(CSRC / src), "-o", str(obj)]
         if verbose:
@@ -55,7 +57,12 @@ def build(verbose: bool = False) -> Path:
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
-        objs.append(str(obj))
+        return str(obj)
+
+    # the sources compile independently; at most one hipcc per available core
+    workers = max(1, min(len(SOURCES), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(workers) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = OUT_DIR / "libh2ulv.so.tmp"
     cmd = [cc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", str(tmp)]
     r = subprocess.run(cmd, capture_output=True, text=True)

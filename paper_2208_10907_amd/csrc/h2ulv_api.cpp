@@ -229,120 +229,166 @@ static h2ulv_status refine_impl(const h2ulv_factor& F, const double* b, int64_t 
 // Restarted GMRES on A x = b, right-preconditioned by the ULV solve (the
 // correction equation of iterative refinement solved in a Krylov space): the
 // same two operations per step as classical refinement (one exact matvec, one
-// solve), but the correction is the best one in the space they span.  Arnoldi
-// with classical Gram-Schmidt applied twice; Givens rotations give the residual
-// estimate; every restart recomputes the true residual with the exact matvec.
+// solve), but the correction is the best one in the space they span.  The
+// right-hand sides run in lockstep: each has its own Krylov basis, Hessenberg
+// matrix and stopping test, while the solve and the exact matvec of a step act
+// on all of them at once (the matvec evaluates each kernel entry once for all
+// columns).  Arnoldi with classical Gram-Schmidt applied twice; Givens
+// rotations give the residual estimate; every restart recomputes the true
+// residuals with the exact matvec.
 static h2ulv_status gmres_impl(const h2ulv_factor& F, const double* b, int64_t ldb, double* x,
                                int64_t ldx, int nrhs, double rtol, int max_iter, int restart,
                                int32_t* iters, double* relres, hipStream_t s) {
   const int64_t n = F.n;
   const int m = std::max(1, std::min(restart, 30));
   constexpr int NBLK = 256;
-  DBuf Vb((int64_t)(m + 1) * n * sizeof(double)), Zb((int64_t)m * n * sizeof(double)),
-      wb(n * sizeof(double)), rb(n * sizeof(double)), part((int64_t)NBLK * 32 * sizeof(double)),
-      hd(3 * 32 * sizeof(double)), ys(32 * sizeof(double)), nr(2 * sizeof(double));
+  constexpr int HS = 3 * 32;  // per column: two Gram-Schmidt passes and the norm
+  // Krylov blocks: block j holds column u's j-th vector at offset u * n
+  DBuf Vb((int64_t)(m + 1) * n * nrhs * sizeof(double)),
+      Zb((int64_t)m * n * nrhs * sizeof(double)), wb(n * nrhs * sizeof(double)),
+      rb(n * nrhs * sizeof(double)), part((int64_t)NBLK * 32 * sizeof(double)),
+      hd((int64_t)nrhs * HS * sizeof(double)), ys((int64_t)nrhs * 32 * sizeof(double)),
+      nr(2 * nrhs * sizeof(double));
   double* V = Vb.as<double>();
   double* Z = Zb.as<double>();
   double* w = wb.as<double>();
   double* r = rb.as<double>();
-  double* h1 = hd.as<double>();
-  double* h2 = h1 + 32;
-  double* hn = h1 + 64;
+  double* h = hd.as<double>();
+  {
+    // x0 = M^-1 b
+    CopyBatch cb;
+    Stage st(s);
+    cb.add(b, ldb, x, ldx, (int)n, nrhs);
+    cb.run(st);
+    st.sync();
+  }
+  solve_impl(F, x, nrhs, ldx, s);
+  std::vector<int> steps(nrhs, 0);
+  std::vector<double> rel(nrhs, 0.0), bnorm(nrhs, 0.0), beta(nrhs, 0.0);
+  std::vector<char> done(nrhs, 0);
+  std::vector<double> hv(2 * nrhs), hh((size_t)nrhs * HS);
+  for (;;) {
+    // true residuals r = b - A x of every column
+    matvec_impl(F, x, ldx, w, n, nrhs, s);
+    launch_resid_norms(b, ldb, w, n, r, n, n, nrhs, nr.as<double>(), nr.as<double>() + nrhs, s);
+    H2ULV_HIP(hipMemcpyAsync(hv.data(), nr.p, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost,
+                             s));
+    H2ULV_HIP(hipStreamSynchronize(s));
+    std::vector<int> act;  // columns that take another cycle
+    for (int c = 0; c < nrhs; ++c) {
+      bnorm[c] = std::sqrt(hv[nrhs + c]);
+      beta[c] = std::sqrt(hv[c]);
+      rel[c] = bnorm[c] > 0 ? beta[c] / bnorm[c] : beta[c];
+      done[c] = rel[c] <= rtol;
+      if (!done[c] && steps[c] < max_iter) act.push_back(c);
+    }
+    if (act.empty()) break;
+    const int na = (int)act.size();
+    const int64_t ldk = n * na;  // stride between a column's Krylov vectors
+    // v0 = r / |r| per column
+    for (int u = 0; u < na; ++u)
+      launch_scale_inv_norm(V + (int64_t)u * n, r + (int64_t)act[u] * n,
+                            nr.as<double>() + act[u], n, s);
+    H2ULV_HIP(hipGetLastError());
+    std::vector<std::vector<double>> H(na, std::vector<double>((size_t)(m + 1) * m, 0.0)),
+        g(na, std::vector<double>(m + 1, 0.0)), cs(na, std::vector<double>(m, 0.0)),
+        sn(na, std::vector<double>(m, 0.0));
+    std::vector<int> jc(na, 0);
+    std::vector<char> run(na, 1);
+    for (int u = 0; u < na; ++u) g[u][0] = beta[act[u]];
+    for (int j = 0; j < m; ++j) {
+      std::vector<int> live;
+      for (int u = 0; u < na; ++u)
+        if (run[u]) live.push_back(u);
+      if (live.empty()) break;
+      double* Vj = V + (int64_t)j * ldk;
+      double* Zj = Z + (int64_t)j * ldk;
+      // z = M^-1 v and w = A z for all columns of the block at once
+      H2ULV_HIP(hipMemcpyAsync(Zj, Vj, ldk * sizeof(double), hipMemcpyDeviceToDevice, s));
+      solve_impl(F, Zj, na, n, s);
+      matvec_impl(F, Zj, n, w, n, na, s);
+      // w_u -= V_u h_u, twice (classical Gram-Schmidt with re-orthogonalisation)
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int u : live)
+          launch_multidot(V + (int64_t)u * n, ldk, j + 1, w + (int64_t)u * n, n,
+                          part.as<double>(), NBLK, h + (int64_t)u * HS + 32 * pass, s);
+        Stage st(s);
+        GemmBatch<double> gb;
+        for (int u : live)
+          gb.one(w + (int64_t)u * n, n, (int)n, 1, j + 1, V + (int64_t)u * n, ldk, false,
+                 h + (int64_t)u * HS + 32 * pass, j + 1, false, -1.0, 1.0);
+        gb.run(st, "gmres");
+        st.sync();
+      }
+      for (int u : live) {
+        launch_multidot(w + (int64_t)u * n, n, 1, w + (int64_t)u * n, n, part.as<double>(), NBLK,
+                        h + (int64_t)u * HS + 64, s);
+        launch_scale_inv_norm(V + (int64_t)(j + 1) * ldk + (int64_t)u * n, w + (int64_t)u * n,
+                              h + (int64_t)u * HS + 64, n, s);
+      }
+      H2ULV_HIP(hipGetLastError());
+      H2ULV_HIP(hipMemcpyAsync(hh.data(), h, (size_t)na * HS * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+      H2ULV_HIP(hipStreamSynchronize(s));
+      for (int u : live) {
+        const int c = act[u];
+        ++steps[c];
+        const double* hu = hh.data() + (size_t)u * HS;
+        // column j of the Hessenberg matrix
+        double* col = H[u].data() + (size_t)j * (m + 1);
+        for (int i = 0; i <= j; ++i) col[i] = hu[i] + hu[32 + i];
+        col[j + 1] = std::sqrt(std::max(hu[64], 0.0));
+        for (int i = 0; i < j; ++i) {
+          const double a0 = col[i], a1 = col[i + 1];
+          col[i] = cs[u][i] * a0 + sn[u][i] * a1;
+          col[i + 1] = -sn[u][i] * a0 + cs[u][i] * a1;
+        }
+        const double den = std::hypot(col[j], col[j + 1]);
+        cs[u][j] = den > 0 ? col[j] / den : 1.0;
+        sn[u][j] = den > 0 ? col[j + 1] / den : 0.0;
+        col[j] = den;
+        col[j + 1] = 0.0;
+        g[u][j + 1] = -sn[u][j] * g[u][j];
+        g[u][j] = cs[u][j] * g[u][j];
+        jc[u] = j + 1;
+        // stop early when the estimate is well below the target, on breakdown,
+        // or at the step limit
+        if (std::fabs(g[u][j + 1]) <= 0.5 * rtol * bnorm[c] || hu[64] <= 0.0 ||
+            steps[c] >= max_iter)
+          run[u] = 0;
+      }
+    }
+    // y = R^-1 g, x += Z y per column
+    std::vector<double> y((size_t)na * 32, 0.0);
+    for (int u = 0; u < na; ++u) {
+      const int jj = jc[u];
+      for (int i = jj - 1; i >= 0; --i) {
+        double sacc = g[u][i];
+        for (int l = i + 1; l < jj; ++l) sacc -= H[u][(size_t)l * (m + 1) + i] * y[u * 32 + l];
+        const double d = H[u][(size_t)i * (m + 1) + i];
+        y[u * 32 + i] = d != 0.0 ? sacc / d : 0.0;
+      }
+    }
+    H2ULV_HIP(hipMemcpyAsync(ys.p, y.data(), y.size() * sizeof(double), hipMemcpyHostToDevice,
+                             s));
+    {
+      Stage st(s);
+      GemmBatch<double> gb;
+      for (int u = 0; u < na; ++u)
+        if (jc[u] > 0)
+          gb.one(x + (int64_t)act[u] * ldx, ldx, (int)n, 1, jc[u], Z + (int64_t)u * n, ldk, false,
+                 ys.as<double>() + u * 32, jc[u], false, 1.0, 1.0);
+      gb.run(st, "gmres");
+      st.sync();
+    }
+  }
   int worst_it = 0;
   double worst_rel = 0.0;
   bool converged_all = true;
   for (int c = 0; c < nrhs; ++c) {
-    const double* bc = b + (int64_t)c * ldb;
-    double* xc = x + (int64_t)c * ldx;
-    // x0 = M^-1 b
-    H2ULV_HIP(hipMemcpyAsync(xc, bc, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    solve_impl(F, xc, 1, n, s);
-    int steps = 0;
-    double rel = 0.0, bnorm = 0.0;
-    bool done = false;
-    for (;;) {
-      // true residual r = b - A x
-      matvec_impl(F, xc, n, w, n, 1, s);
-      launch_resid_norms(bc, ldb, w, n, r, n, n, 1, nr.as<double>(), nr.as<double>() + 1, s);
-      double hv[2];
-      H2ULV_HIP(hipMemcpyAsync(hv, nr.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-      H2ULV_HIP(hipStreamSynchronize(s));
-      bnorm = std::sqrt(hv[1]);
-      const double beta = std::sqrt(hv[0]);
-      rel = bnorm > 0 ? beta / bnorm : beta;
-      if (rel <= rtol) {
-        done = true;
-        break;
-      }
-      if (steps >= max_iter) break;
-      // Arnoldi from v0 = r / |r|
-      launch_scale_inv_norm(V, r, nr.as<double>(), n, s);
-      std::vector<double> H((size_t)(m + 1) * m, 0.0), g(m + 1, 0.0), cs(m, 0.0), sn(m, 0.0);
-      g[0] = beta;
-      int j = 0;
-      while (j < m && steps < max_iter) {
-        double* vj = V + (int64_t)j * n;
-        double* zj = Z + (int64_t)j * n;
-        H2ULV_HIP(hipMemcpyAsync(zj, vj, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        solve_impl(F, zj, 1, n, s);
-        matvec_impl(F, zj, n, w, n, 1, s);
-        ++steps;
-        // w -= V h, twice (classical Gram-Schmidt with re-orthogonalisation)
-        for (int pass = 0; pass < 2; ++pass) {
-          double* hp = pass == 0 ? h1 : h2;
-          launch_multidot(V, n, j + 1, w, n, part.as<double>(), NBLK, hp, s);
-          Stage st(s);
-          GemmBatch<double> gb;
-          gb.one(w, n, (int)n, 1, j + 1, V, n, false, hp, j + 1, false, -1.0, 1.0);
-          gb.run(st, "gmres");
-          st.sync();
-        }
-        launch_multidot(w, n, 1, w, n, part.as<double>(), NBLK, hn, s);
-        launch_scale_inv_norm(V + (int64_t)(j + 1) * n, w, hn, n, s);
-        H2ULV_HIP(hipGetLastError());
-        std::vector<double> hh(65);
-        H2ULV_HIP(hipMemcpyAsync(hh.data(), h1, 65 * sizeof(double), hipMemcpyDeviceToHost, s));
-        H2ULV_HIP(hipStreamSynchronize(s));
-        // column j of the Hessenberg matrix
-        double* col = H.data() + (size_t)j * (m + 1);
-        for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[32 + i];
-        col[j + 1] = std::sqrt(std::max(hh[64], 0.0));
-        for (int i = 0; i < j; ++i) {
-          const double a0 = col[i], a1 = col[i + 1];
-          col[i] = cs[i] * a0 + sn[i] * a1;
-          col[i + 1] = -sn[i] * a0 + cs[i] * a1;
-        }
-        const double den = std::hypot(col[j], col[j + 1]);
-        cs[j] = den > 0 ? col[j] / den : 1.0;
-        sn[j] = den > 0 ? col[j + 1] / den : 0.0;
-        col[j] = den;
-        col[j + 1] = 0.0;
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
-        ++j;
-        // stop early when the estimate is well below the target, or on breakdown
-        if (std::fabs(g[j]) <= 0.5 * rtol * bnorm || hh[64] <= 0.0) break;
-      }
-      // y = R^-1 g, x += Z y
-      std::vector<double> y(j, 0.0);
-      for (int i = j - 1; i >= 0; --i) {
-        double sacc = g[i];
-        for (int l = i + 1; l < j; ++l) sacc -= H[(size_t)l * (m + 1) + i] * y[l];
-        const double d = H[(size_t)i * (m + 1) + i];
-        y[i] = d != 0.0 ? sacc / d : 0.0;
-      }
-      H2ULV_HIP(hipMemcpyAsync(ys.p, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
-      {
-        Stage st(s);
-        GemmBatch<double> gb;
-        gb.one(xc, n, (int)n, 1, j, Z, n, false, ys.as<double>(), std::max(j, 1), false, 1.0, 1.0);
-        gb.run(st, "gmres");
-        st.sync();
-      }
-    }
-    worst_it = std::max(worst_it, steps);
-    worst_rel = std::max(worst_rel, rel);
-    converged_all = converged_all && done;
+    worst_it = std::max(worst_it, steps[c]);
+    worst_rel = std::max(worst_rel, rel[c]);
+    converged_all = converged_all && done[c];
   }
   if (iters) *iters = worst_it;
   if (relres) *relres = worst_rel;
