@@ -16,11 +16,16 @@ predicted (bases from sketches sized by the learned rank model), and both
 combined.  A rank model is trained first (outside the timed steps) on the
 ranks of factorizations of two other point sets of the same family.
 
-value = algorithmic flops of the plain FP64 factorization of the workload (the
-paper's step costs from its actual ranks) / wall time of one step of the timed
-form: an effective rate, so that forms that skip work are compared at equal
-delivered accuracy.  The plain FP64 form is also timed (the reference) unless
---no-reference; without it the form's own flop count is used.
+Default workload: the N=2^20 unit-cube Laplace problem (leaf 256, eta 1, tol
+1e-6, rank cap 128 = leaf / 2, 8 Gaussian right-hand sides), default form
+mixed.  value = the timed form's own algorithmic flops (the method's step costs
+from its actual ranks, as the factorization counts them) / wall time of one
+step (factorize + refined solve).  The plain FP64 form is timed the same way
+(warmup, then timed steps) as the reference unless --no-reference, with its
+own flops, time, refinement and the relative difference of the two solutions.
+The learned-rank form (mixed precision + predicted ranks) is timed the same way
+and reported as a separate record (--no-predicted skips it); its model is
+trained outside the timed regions.
 roofline = the dominant kernel (by time) of the timed steps measured with HIP
 events on its launch stream: summed algorithmic flops / summed duration.
 roofline.traffic = HBM bytes per launch of that kernel in the timed step, from
@@ -43,7 +48,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "H² ULV factorize time + GFLOP/s, N=1M Laplace, mixed vs FP64 at 1e-10 resid"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f64_traffic_ellipsoids262144.md")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def traffic_file(kernel: str, workload: str) -> str:
+    """Where the HBM-traffic record of a kernel family on a workload lives."""
+    return os.path.join(PROFILES, f"{kernel}_traffic_{workload}.md")
 
 
 def library_source_hash() -> str:
@@ -59,13 +69,14 @@ def library_source_hash() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic(workload: str):
-    """HBM bytes per launch of the FP64 GEMM recorded for this workload, if the
+def recorded_traffic(workload: str, kernel: str = "gemm_f64"):
+    """HBM bytes per launch of a kernel family recorded for this workload, if the
     record was taken with the current library sources."""
-    if workload != "ellipsoids262144" or not os.path.exists(TRAFFIC_FILE):
+    path = traffic_file(kernel, workload)
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             line = line.strip().strip("`")
             if ":" in line:
@@ -77,7 +88,19 @@ def recorded_traffic(workload: str):
         return float(vals["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
-PEAK_TFLOPS = {"gemm_f64": 78.6, "gemm_f32": 157.3}
+
+
+# peaks of the kernel families the roofline can be taken for (MI355X): matrix
+# cores for the grouped GEMMs, FP64 vector units for the exact matvec and the
+# panel kernels, HBM for the solve's matrix-vector products
+ROOF = {
+    "gemm_f64": ("mfma", 78.6, "TFLOP/s"),
+    "gemm_f32": ("mfma", 157.3, "TFLOP/s"),
+    "matvec": ("alu", 78.6, "TFLOP/s"),
+    "qr_panel": ("alu", 78.6, "TFLOP/s"),
+    "lu_panel": ("alu", 78.6, "TFLOP/s"),
+    "gemv_f64": ("hbm", 8000.0, "GB/s"),
+}
 
 
 def workloads():
@@ -102,7 +125,9 @@ def training_sets(name):
     if name.startswith("sphere"):
         return [(f"sphere16384 seed {s}", lambda s=s: W.sphere_points(16384, s))
                 for s in (501, 502)]
-    return [(f"cube32768 seed {s}", lambda s=s: W.cube_points(32768, s)) for s in (501, 502)]
+    # two smaller cubes and one with many levels (the capped upper levels)
+    return ([(f"cube32768 seed {s}", lambda s=s: W.cube_points(32768, s)) for s in (501, 502)]
+            + [("cube262144 seed 503", lambda: W.cube_points(262144, 503))])
 
 
 def describe(prob):
@@ -126,22 +151,25 @@ def cpu_baseline(prob, budget_s=20.0):
     tree_L = O.tree_depth(prob.n, prob.leaf)
     nb = 1 << tree_L
     rng = np.random.default_rng(0)
-    total_fl, total_t, boxes = 0.0, 0.0, []
-    for _ in range(64):
-        box = int(rng.integers(nb))
+    # one oracle call over a set of leaf boxes (the tree and lists are built
+    # once, then each box's basis step with the near blocks it depends on);
+    # the set grows until a call takes about budget_s
+    nbox, total_fl, total_t, boxes = 4, 0.0, 0.0, []
+    while True:
+        boxes = sorted(set(int(b) for b in rng.integers(nb, size=nbox)))
         t0 = time.perf_counter()
-        f = O.factorize(prob.points, op, level_stop=tree_L, boxes={box})
-        dt = time.perf_counter() - t0
-        total_fl += sum(f.stats["flops"].values())
-        total_t += dt
-        boxes.append(box)
-        if total_t > budget_s:
+        f = O.factorize(prob.points, op, level_stop=tree_L, boxes=set(boxes))
+        total_t = time.perf_counter() - t0
+        total_fl = sum(f.stats["flops"].values())
+        if total_t > budget_s / 3 or nbox >= 64:
             break
+        nbox *= 2
     return {"value": round(total_fl / total_t / 1e9, 3), "unit": "GFLOP/s", "cores": int(cores),
             "kind": "oracle",
             "sample": (f"leaf-level basis step (dense blocks, fill-ins, row ID, complement) of "
-                       f"{len(boxes)} leaf boxes of {prob.name}, each with the near blocks it "
-                       f"depends on; {total_t:.1f} s of CPU time; oracle flop count")}
+                       f"{len(boxes)} leaf boxes of {prob.name} in one oracle call, with the "
+                       f"near blocks they depend on; {total_t:.1f} s of CPU time including the "
+                       f"host tree and lists; oracle flop count")}
 
 
 def log(msg):
@@ -177,14 +205,111 @@ def train_model(H, torch, prob, name):
                    "steps": 3000, "final_loss": round(loss, 5)}
 
 
+def batch_leg(H, torch, count, restart):
+    """The batched workload: Yukawa problems of log-uniform size in [8192,
+    131072] (leaf 128, tol 1e-7, rank cap 64), factorized together in one
+    h2ulv_factorize_batch call (shared launches per tree height) and one by
+    one, each problem refined to 1e-10 in both cases."""
+    import workloads as W
+    probs = W.yukawa_batch(count)
+    pts = [torch.tensor(p.points, device="cuda") for p in probs]
+    rhs = [torch.tensor(p.rhs(), device="cuda") for p in probs]
+    prm = H.params_from_problem(probs[0])
+    torch.cuda.synchronize()
+
+    def refine_all(fs):
+        worst, iters = 0.0, 0
+        for f, b in zip(fs, rhs):
+            _, it, rel = f.refine_gmres(b, rtol=1e-10, max_iter=300, restart=restart)
+            worst, iters = max(worst, rel), max(iters, it)
+        return worst, iters
+
+    out = {}
+    for mode in ("batched", "one_by_one", "batched", "one_by_one"):  # second pass timed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "batched":
+            fs = H.factorize_batch(pts, prm)
+        else:
+            fs = [H.factorize(x, prm) for x in pts]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        worst, iters = refine_all(fs)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        flops = sum(f.stats()["flops"] for f in fs)
+        out[mode] = {"factor_s": round(t1 - t0, 4), "refine_s": round(t2 - t1, 4),
+                     "max_relres": worst, "max_gmres_steps": iters, "flops": flops,
+                     "factor_gflops": round(flops / (t1 - t0) / 1e9, 3)}
+        log(f"{mode}: factorize {t1 - t0:.2f} s, refine {t2 - t1:.2f} s")
+        del fs
+    print(json.dumps({"batch_leg": out, "problems": count,
+                      "points": int(sum(p.n for p in probs)),
+                      "speedup_batched_factorize": round(out["one_by_one"]["factor_s"] /
+                                                         out["batched"]["factor_s"], 3),
+                      "workload": "Yukawa exp(-0.5 r)/r, diag 1e3, points uniform in boxes of "
+                                  "aspect ratio up to 4, N log-uniform in [8192, 131072], leaf "
+                                  "128, eta 1, tol 1e-7, rank cap 64, FP64, 1 RHS each"}),
+          flush=True)
+    return 0
+
+
+def leaf_sweep(H, torch, leaves, restart):
+    """Factorization time against leaf size on the N=131072 unit cube (the
+    problem of the paper's leaf-size study, Sec. IV-C), each leaf size with
+    rank cap leaf/2, tol 1e-8, FP64, one Gaussian RHS refined to 1e-10."""
+    import workloads as W
+    X = torch.tensor(W.cube_points(131072, 11), device="cuda")
+    b = torch.tensor(W.gaussian_rhs(131072, 1, 111), device="cuda")
+    rows = []
+    for leaf in leaves:
+        p = H.make_params(leaf=leaf, tol=1e-8, rank_cap=W.default_cap(leaf), far_sample=32)
+        H.factorize(X, p)  # warm-up of this shape
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = H.factorize(X, p)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, it, rel = f.refine_gmres(b, rtol=1e-10, max_iter=300, restart=restart)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st = f.stats()
+        rows.append({"leaf": leaf, "rank_cap": W.default_cap(leaf), "factor_s": round(t1 - t0, 4),
+                     "refine_s": round(t2 - t1, 4), "refine_iters": it, "relres": rel,
+                     "flops": st["flops"], "max_rank": st["max_rank"], "levels": st["levels"]})
+        log(f"leaf {leaf}: factorize {t1 - t0:.3f} s, {it} GMRES steps")
+        del f
+    print(json.dumps({"leaf_sweep": rows, "workload": "unit cube N=131072, Laplace, diag 1e3, "
+                      "eta 1, tol 1e-8, far samples 32, 1 Gaussian RHS"}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ellipsoids262144", choices=sorted(workloads()))
-    ap.add_argument("--form", default="mixed+predicted",
+    ap.add_argument("--workload", default="cube1048576", choices=sorted(workloads()))
+    ap.add_argument("--form", default="mixed",
                     choices=["fp64", "mixed", "predicted", "mixed+predicted"])
+    ap.add_argument("--no-predicted", dest="predicted", action="store_false",
+                    help="skip the mixed+predicted form (reported as a separate record)")
+    ap.add_argument("--restart", type=int, default=120,
+                    help="GMRES cycle length (the capped factorization leaves many outlying "
+                         "eigenvalues: short cycles restart too often)")
+    ap.add_argument("--allocator", default="torch", choices=["torch", "library"],
+                    help="device memory of the factorization: torch's caching allocator "
+                         "through the C-ABI callback, or the library's own cache")
+    ap.add_argument("--verbose", action="store_true", help="per-level timings on stderr")
+    ap.add_argument("--batch-leg", type=int, default=0, metavar="P",
+                    help="instead of the benchmark, factorize the first P problems of the "
+                         "64-problem Yukawa workload in one batched call and one by one "
+                         "(FP64, rank cap leaf/2), refine every problem to 1e-10, print one "
+                         "JSON line")
+    ap.add_argument("--leaf-sweep", default="", metavar="LEAVES",
+                    help="comma-separated leaf sizes: instead of the benchmark, factorize and "
+                         "refine the N=131072 unit cube (Sec. IV-C's leaf-size study; tol 1e-8, "
+                         "rank cap leaf/2, FP64) once per leaf size and print one JSON line")
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--refine", default="gmres", choices=["gmres", "classical"],
                     help="correction solver of the refinement (both forms use the same)")
@@ -214,6 +339,11 @@ def main() -> int:
     import torch
     from paper_2208_10907_amd import h2ulv as H
 
+    if args.leaf_sweep:
+        return leaf_sweep(H, torch, [int(x) for x in args.leaf_sweep.split(",")], args.restart)
+    if args.batch_leg:
+        return batch_leg(H, torch, args.batch_leg, args.restart)
+
     prob = workloads()[args.workload]()
     pts = torch.tensor(prob.points, device="cuda")
     b = torch.tensor(prob.rhs(), device="cuda")
@@ -225,21 +355,25 @@ def main() -> int:
 
     def params_of(form):
         prec = H.MIXED if "mixed" in form else H.FP64
-        return H.params_from_problem(prob, precision=prec,
+        return H.params_from_problem(prob, precision=prec, verbose=1 if args.verbose else 0,
                                      rank_model=model if "predicted" in form else None,
                                      sketch_seed=5)
 
+    allocator = "torch" if args.allocator == "torch" else None
+
     def step(params):
         t0 = time.perf_counter()
-        f = H.factorize(pts, params)
+        f = H.factorize(pts, params, allocator=allocator)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        prof_factor = H.profile_read()
         if args.refine == "gmres":
-            x, iters, rel = f.refine_gmres(b, rtol=args.rtol, max_iter=60, restart=30)
+            x, iters, rel = f.refine_gmres(b, rtol=args.rtol, max_iter=300, restart=args.restart)
         else:
-            x, iters, rel = f.refine(b, rtol=args.rtol, max_iter=60)
+            x, iters, rel = f.refine(b, rtol=args.rtol, max_iter=300)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        prof_refine = H.profile_read()
         st = f.stats()
         sk = [0, 0, 0, 0]  # outcome per box: not sketched, accepted, rejected, retried and accepted
         for lev in range(1, f.levels() + 1):
@@ -247,17 +381,21 @@ def main() -> int:
             for o in range(4):
                 sk[o] += int((s == o).sum())
         del f
+        refine_flops = sum(v["flops"] for v in prof_refine.values())
         return {"factor_s": t1 - t0, "refine_s": t2 - t1, "iters": iters, "rel": rel, "st": st,
+                "x": x, "prof": (prof_factor, prof_refine), "refine_flops": refine_flops,
                 "sketches": {"accepted": sk[1], "retried_accepted": sk[3],
                              "rejected_full_qr": sk[2], "not_sketched": sk[0]}}
 
     form_params = params_of(args.form)
+    # kernel timings (HIP events on the launch stream) for every step, warmups
+    # and the reference included, so every form carries the same overhead
+    H.profile_enable(True)
     for w in range(args.warmup):
         r = step(form_params)
         log(f"warmup step {w + 1}/{args.warmup} done ({r['factor_s']:.2f} s factorize, "
             f"{r['refine_s']:.2f} s refine)")
     torch.cuda.synchronize()
-    H.profile_enable(True)
     w_start = time.monotonic_ns()
     t_start = time.perf_counter()
     res = []
@@ -269,48 +407,83 @@ def main() -> int:
     if args.window_file:
         with open(args.window_file, "w") as fh:
             fh.write(f"{w_start} {time.monotonic_ns()}\n")
-    prof = H.profile_read()
-    H.profile_enable(False)
+    # per kernel family over the timed steps (the GEMM records are split by call
+    # site, "gemm_f64:<site>"; the factorization's and the refinement's kernels
+    # are read separately, then summed)
+    prof = {}
+    for r in res:
+        for part in r["prof"]:
+            for k, v in part.items():
+                a = prof.setdefault(k, {"launches": 0, "time_ms": 0.0, "flops": 0.0, "bytes": 0.0})
+                for q in a:
+                    a[q] += v[q]
     ms = 1e3 * t_total / args.steps
     last = res[-1]
     st = last["st"]
 
+    def run_form(form, warmup, steps, label):
+        prm = params_of(form)
+        for w in range(warmup):
+            r = step(prm)
+            log(f"{label} warmup step {w + 1}/{warmup} done ({r['factor_s']:.2f} s factorize)")
+        rs = []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            rs.append(step(prm))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        r = rs[-1]
+        log(f"{label} timed steps done ({r['factor_s']:.2f} s factorize, {dt:.2f} s per step)")
+        return {"form": form, "step_s": round(dt, 4), "factor_s": round(r["factor_s"], 4),
+                "refine_s": round(r["refine_s"], 4), "refine_iters": r["iters"],
+                "relres": r["rel"], "flops": r["st"]["flops"], "refine_flops": r["refine_flops"],
+                "gflops": round((r["st"]["flops"] + r["refine_flops"]) / dt / 1e9, 3),
+                "factor_gflops": round(r["st"]["flops"] / r["factor_s"] / 1e9, 3),
+                "max_rank": r["st"]["max_rank"], "root_size": r["st"]["root_size"],
+                "device_gb": round(r["st"]["device_bytes"] / 1e9, 2),
+                "sketches": r["sketches"]}, r["x"]
+
+    x_form = last["x"]
     ref = None
     if not args.no_reference and args.form != "fp64":
-        r = step(params_of("fp64"))
-        log(f"reference fp64 step done ({r['factor_s']:.2f} s factorize)")
-        ref = {"form": "fp64", "step_s": round(r["factor_s"] + r["refine_s"], 4),
-               "factor_s": round(r["factor_s"], 4), "refine_s": round(r["refine_s"], 4),
-               "refine_iters": r["iters"], "relres": r["rel"], "flops": r["st"]["flops"],
-               "max_rank": r["st"]["max_rank"], "device_gb": round(r["st"]["device_bytes"] / 1e9, 2)}
-    work = ref["flops"] if ref else st["flops"]
+        ref, x_ref = run_form("fp64", args.warmup, args.steps, "reference fp64")
+        ref["solution_rel_diff_vs_this_form"] = float(
+            (torch.linalg.norm(x_form - x_ref) / torch.linalg.norm(x_ref)).item())
+        del x_ref
+    pred = None
+    if args.predicted:
+        if model is None:
+            model, model_info = train_model(H, torch, prob, args.workload)
+        pred, x_pred = run_form("mixed+predicted", args.warmup, args.steps, "predicted")
+        pred["rank_model"] = model_info
+        pred["solution_rel_diff_vs_this_form"] = float(
+            (torch.linalg.norm(x_pred - x_form) / torch.linalg.norm(x_form)).item())
+        del x_pred
+    H.profile_enable(False)
+    work = st["flops"] + last["refine_flops"]
     value = work / (ms / 1e3) / 1e9
 
-    # the GEMM profile is split by call site ("gemm_f64:<site>"): one kernel, summed
-    gemms = {}
+    families = {}
     for k, v in prof.items():
         base = k.split(":")[0]
-        if base in PEAK_TFLOPS:
-            a = gemms.setdefault(base, {"launches": 0, "time_ms": 0.0, "flops": 0.0,
-                                        "bytes": 0.0})
-            a["launches"] += v["launches"]
-            a["time_ms"] += v["time_ms"]
-            a["flops"] += v["flops"]
-            a["bytes"] += v["bytes"]
-    dom = max(gemms, key=lambda k: gemms[k]["time_ms"]) if gemms else None
+        a = families.setdefault(base, {"launches": 0, "time_ms": 0.0, "flops": 0.0, "bytes": 0.0})
+        for q in a:
+            a[q] += v[q]
+    dom = max(families, key=lambda k: families[k]["time_ms"]) if families else None
     roof = None
-    if dom:
-        g = gemms[dom]
-        ach = g["flops"] / (g["time_ms"] / 1e3) / 1e12
-        roof = {"bound": "mfma", "kernel": dom, "achieved": round(ach, 3),
-                "peak": PEAK_TFLOPS[dom], "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_TFLOPS[dom], 4),
-                "traffic": recorded_traffic(args.workload) if dom == "gemm_f64" else None,
+    if dom in ROOF:
+        g = families[dom]
+        bound, peak, unit = ROOF[dom]
+        per_s = 1e3 / g["time_ms"]
+        ach = g["bytes"] * per_s / 1e9 if unit == "GB/s" else g["flops"] * per_s / 1e12
+        roof = {"bound": bound, "kernel": dom, "achieved": round(ach, 3), "peak": peak,
+                "unit": unit, "frac": round(ach / peak, 4),
+                "traffic": recorded_traffic(args.workload, dom),
                 "launches": g["launches"],
                 "avg_launch_ms": round(g["time_ms"] / g["launches"], 4),
                 "flops_per_launch": g["flops"] / g["launches"],
-                # operands read once and results written once, per launch
-                "algorithmic_bytes_per_launch": g["bytes"] / g["launches"]}
+                "algorithmic_bytes_per_launch": g["bytes"] / g["launches"],
+                "time_share_of_step": round(g["time_ms"] / 1e3 / args.steps / (ms / 1e3), 4)}
 
     out = {
         "metric": METRIC,
@@ -326,19 +499,27 @@ def main() -> int:
         "dtype": "f32+f64" if "mixed" in args.form else "f64",
         "data": "synthetic",
         "config": {"workload": describe(prob), "form": args.form, "refine_rtol": args.rtol,
-                   "refine": args.refine,
-                   "value_flops": "plain FP64 method" if ref else "this form"},
+                   "refine": args.refine, "gmres_restart": args.restart,
+                   "allocator": args.allocator,
+                   "value": "this form's algorithmic flops (factorization from its actual ranks + "
+                            "refinement: 2 n^2 per exact matvec column, the solves' products) / "
+                            "(factorize + refined solve) time"},
         "factor_s": round(last["factor_s"], 4),
         "refine_s": round(last["refine_s"], 4),
         "refine_iters": last["iters"],
         "relres": last["rel"],
         "flops": st["flops"],
+        "refine_flops": last["refine_flops"],
         "max_rank": st["max_rank"],
         "root_size": st["root_size"],
         "device_gb": round(st["device_bytes"] / 1e9, 2),
         "sketches": last["sketches"],
+        "factor_gflops": round(st["flops"] / last["factor_s"] / 1e9, 3),
         "reference": ref,
         "speedup_vs_fp64": round(ref["step_s"] / (ms / 1e3), 3) if ref else None,
+        "factor_speedup_vs_fp64": round(ref["factor_s"] / last["factor_s"], 3) if ref else None,
+        "predicted": pred,
+        "gemm_tile_rates_tflops": H.gemm_tile_rates(),
         "rank_model": model_info,
         "kernels": {k: {"launches": v["launches"], "ms": round(v["time_ms"], 2),
                         "tflops": round(v["flops"] / max(v["time_ms"], 1e-9) / 1e9, 3)}

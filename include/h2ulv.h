@@ -78,6 +78,16 @@ typedef struct h2ulv_params {
                           row ID replaces the full one when a randomized probe
                           accepts it (see h2ulv_rankmodel_create)              */
   uint64_t sketch_seed; /* key of the Gaussian sketch matrices                 */
+  int32_t fill_in;      /* 1 (default): shared bases from [F_i+ A_i+], the
+                          fill-ins included (Sec. III-C Eq. fillu).  0: ablation,
+                          bases from the low-rank blocks A_i+ alone (F = 0), as
+                          without the pre-computed fill-ins of Sec. III-B; not
+                          combinable with a rank model                          */
+  int32_t partition;    /* cluster tree: 0 (default) k-d split at the median of
+                          the widest bounding-box axis; 1 balanced 2-means
+                          bisection (the k-means partition of Sec. V: every
+                          box splits into two clusters of floor(n/2) and
+                          ceil(n/2) points, so leaves stay a power of two)      */
 } h2ulv_params;
 
 typedef struct h2ulv_factor h2ulv_factor; /* opaque */
@@ -111,20 +121,42 @@ typedef struct h2ulv_stats {
 h2ulv_status h2ulv_params_default(h2ulv_params* p);
 
 /*
+ * Device memory from the caller (the torch caching allocator from Python, a
+ * memory pool, ...).  alloc returns `bytes` bytes of device memory usable by work
+ * on `stream`, or NULL when it has none (the call then fails with OOM); free takes
+ * back a block from alloc.  free may be called while work queued on `stream`
+ * still reads the block: the allocator must not hand it to work on other
+ * streams before that work is done (stream-ordered reuse, as hipFreeAsync and
+ * torch's caching allocator give).  The struct is copied; ctx and the two
+ * functions must stay valid until every factor made with them is destroyed.
+ */
+typedef struct h2ulv_allocator {
+  void* ctx;
+  void* (*alloc)(void* ctx, size_t bytes, void* stream);
+  void (*free)(void* ctx, void* ptr, void* stream);
+} h2ulv_allocator;
+
+/*
  * Factorize A = [K(x_i, x_j)] (A_ii = diag) for n points.
  *   pts     device, n x 3 row-major (x0 y0 z0 x1 ...); read only; caller owns.
  *   n       number of points, >= 1.
  *   params  host; copied.
+ *   alloc   host, may be NULL: where all device memory of the call and of the
+ *           factor comes from (the factor keeps its blocks until
+ *           h2ulv_destroy; later calls on the factor draw their temporaries
+ *           from it too).  NULL: the library's own caching allocator.
  *   stream  hipStream_t.
  *   out     host; receives a new factor (free with h2ulv_destroy).
  * The call copies the points to the host to build the cluster tree and the
  * near/far lists (Sec. III-D), then runs every level of the sweep on the GPU.
  * It synchronises the stream once per level to read back the ranks.
- * Errors: INVALID_ARG (n < 1, NULL pointer, bad params, non-finite point),
- * DUPLICATE_POINTS, SINGULAR, OOM, HIP.  On error *out is NULL.
+ * Errors: INVALID_ARG (n < 1, NULL pointer, bad params, non-finite point, an
+ * allocator with a NULL function), DUPLICATE_POINTS, SINGULAR, OOM (also when
+ * the allocator returns NULL: the first device allocation precedes every
+ * launch), HIP.  On error *out is NULL.
  */
 h2ulv_status h2ulv_factorize(const double* pts, int64_t n, const h2ulv_params* params,
-                             void* stream, h2ulv_factor** out);
+                             const h2ulv_allocator* alloc, void* stream, h2ulv_factor** out);
 
 /*
  * Factorize several independent problems with one launch per kernel and level:
@@ -135,12 +167,13 @@ h2ulv_status h2ulv_factorize(const double* pts, int64_t n, const h2ulv_params* p
  *   pts     host array of nprob device pointers (n[p] x 3 row-major each).
  *   n       host array of nprob sizes.
  *   params  host; one set shared by all problems.
+ *   alloc   as for h2ulv_factorize (shared by all problems).
  *   out     host array of nprob factor handles.
  * Results are identical to nprob separate h2ulv_factorize calls.
  */
 h2ulv_status h2ulv_factorize_batch(int32_t nprob, const double* const* pts, const int64_t* n,
-                                   const h2ulv_params* params, void* stream,
-                                   h2ulv_factor** out);
+                                   const h2ulv_params* params, const h2ulv_allocator* alloc,
+                                   void* stream, h2ulv_factor** out);
 
 /*
  * Solve A~ x = b in place (Sec. II-B three-step solve, level by level).
@@ -161,6 +194,7 @@ h2ulv_status h2ulv_solve(const h2ulv_factor* f, double* b, int32_t nrhs, int64_t
 h2ulv_status h2ulv_matvec_exact(const h2ulv_factor* f, const double* x, int64_t ldx,
                                 double* y, int64_t ldy, int32_t nrhs, void* stream);
 
+
 /*
  * Iterative refinement with the exact float64 matvec:
  *   x = solve(b); repeat r = b - A x; stop when max_c |r_c| / |b_c| <= rtol,
@@ -179,13 +213,14 @@ h2ulv_status h2ulv_refine(const h2ulv_factor* f, const double* b, int64_t ldb, d
  * The refinement's correction equation solved by restarted GMRES, right-
  * preconditioned by the ULV solve: x0 = solve(b); each step applies one solve
  * and one exact matvec (as a classical refinement step does) and keeps the best
- * correction in the Krylov space; after at most `restart` (1..30) steps the
+ * correction in the Krylov space; after at most `restart` (1..128) steps the
  * correction is added and the true residual is recomputed with the exact
  * matvec; stop when max_c |r_c| / |b_c| <= rtol.  Right-hand sides are solved
  * one after another.
  *   iters  host (may be NULL): Krylov steps taken (largest over the columns).
  *   relres host (may be NULL): final max relative residual.
- * Synchronises the stream once per step.  Device scratch: (2 restart + 3) n doubles.
+ * Synchronises the stream once per step.  Device scratch: (2 restart + 3) n nrhs
+ * doubles (the right-hand sides advance together).
  * Errors: INVALID_ARG, NOT_CONVERGED (after max_iter steps; x holds the last
  * iterate), HIP, OOM.
  */
@@ -257,6 +292,16 @@ typedef struct h2ulv_kernel_profile {
 } h2ulv_kernel_profile;
 h2ulv_status h2ulv_profile_enable(int32_t on);
 h2ulv_status h2ulv_profile_read(h2ulv_kernel_profile* out, int32_t max, int32_t* count);
+
+/*
+ * The grouped GEMM's tile shapes are chosen per batch from their full-tile
+ * rates on the device, measured (autotuned) the first time a precision is used
+ * on a device and kept for the process.  out (host, 6 doubles) receives the
+ * measured rates in TFLOP/s: FP64 tiles 64x64, 64x128, 128x64, 128x128, then FP32
+ * tiles 64x64, 128x128; 0 where not measured yet on the current device.
+ * Errors: INVALID_ARG (NULL).
+ */
+h2ulv_status h2ulv_gemm_tile_rates(double* out);
 
 /*
  * Learned rank prediction for the shared-basis step (the row ID of Sec. II-A /

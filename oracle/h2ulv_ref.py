@@ -28,7 +28,8 @@ Readings where the paper is silent (each is listed in the design notes):
   * kernel 1/r (Laplace) or exp(-alpha r)/r (Yukawa), diagonal entry ``diag``;
   * k-d tree: split along the widest bounding-box axis (lowest axis on ties),
     stable sort by (coordinate, original index), left child gets floor(n/2);
-    L = smallest integer with leaf * 2^L >= N;
+    L = smallest integer with leaf * 2^L >= N; or (partition="kmeans") a
+    balanced 2-means bisection of every box (Sec. V);
   * admissible iff |c_i - c_j| > eta (r_i + r_j), centre = bounding-box
     midpoint, radius = half the bounding-box diagonal;
   * fill-in F_ij = sum over k in Near(i) cap Near(j), k not in {i,j}, of
@@ -36,7 +37,10 @@ Readings where the paper is silent (each is listed in the design notes):
   * the shared basis comes from a row interpolative decomposition of
     M'_i = [K(P_i, far) | T^-1 F_i+] (pivoted QR of M'^T), made orthogonal
     by a Householder QR of W = T W'; U = [U^S U^R] (skeleton columns first);
-  * rank k = number of leading pivots with |R_tt| > tol |R_00|, capped;
+  * rank k = number of leading pivots with |R_tt| > tol |R_00|, capped (a
+    configuration without a cap takes leaf/2: the rank stays independent of N,
+    which the linear cost of Sec. I / IV-A presumes);
+  * fill_in=False is the ablation without fill-ins in the basis (F = 0);
   * off-diagonal dense blocks keep only their S^SS quadrant after rotation;
   * symmetric kernels: V = U.
 """
@@ -83,6 +87,8 @@ class Params:
     rank_model: object = None  # MLP parameters (float32 array) or None
     sketch_seed: int = 0       # key of the Gaussian sketches
     oversample: int = 8        # sketch columns beyond 1.25 x the predicted rank
+    fill_in: bool = True       # False: ablation, bases from the far field alone (F = 0)
+    partition: str = "kd"      # "kd" median split of the widest axis, "kmeans" 2-means
 
 
 def params_from_problem(prob, **kw) -> Params:
@@ -103,6 +109,10 @@ def check_params(X: np.ndarray, p: Params) -> None:
         raise OracleError(ERR_INVALID_ARG, "unknown kernel or bad diagonal")
     if p.oversample < 0:
         raise OracleError(ERR_INVALID_ARG, "oversample must be >= 0")
+    if p.partition not in ("kd", "kmeans"):
+        raise OracleError(ERR_INVALID_ARG, "partition must be kd or kmeans")
+    if not p.fill_in and p.rank_model is not None:
+        raise OracleError(ERR_INVALID_ARG, "fill_in = False is not combined with a rank model")
 
 
 # ---------------------------------------------------------------------------
@@ -170,7 +180,41 @@ def tree_depth(n: int, leaf: int) -> int:
     return L
 
 
-def build_tree(X: np.ndarray, leaf: int) -> Tree:
+def _seq_mean(X: np.ndarray, idx: np.ndarray) -> np.ndarray:
+    """Mean of the points idx (ascending index order), each coordinate summed
+    one point after another (a running sum), then divided by the count."""
+    ids = np.sort(idx)
+    return np.array([np.cumsum(X[ids, c])[-1] for c in range(3)]) / float(ids.size)
+
+
+def kmeans_split(X: np.ndarray, pts: np.ndarray, axis: int) -> np.ndarray:
+    """Balanced 2-means bisection of a box (Sec. V: k-means clusters with a
+    power-of-two count).  Start from the k-d split along `axis`; then at most 10
+    Lloyd steps: centroids of the two clusters, each point keyed by
+    |x - c0|^2 - |x - c1|^2, the floor(n/2) smallest keys (ties: lower index)
+    form cluster 0; stop once cluster 0 repeats.  Returns the points in the
+    last (key, index) order."""
+    n = pts.size
+    half = n // 2
+    order = pts[np.lexsort((pts, X[pts, axis]))]
+    c0 = np.sort(order[:half])
+    for _ in range(10):
+        m0 = _seq_mean(X, c0)
+        m1 = _seq_mean(X, order[half:])
+        a = X[order] - m0
+        b = X[order] - m1
+        d0 = a[:, 0] * a[:, 0] + a[:, 1] * a[:, 1] + a[:, 2] * a[:, 2]
+        d1 = b[:, 0] * b[:, 0] + b[:, 1] * b[:, 1] + b[:, 2] * b[:, 2]
+        order = order[np.lexsort((order, d0 - d1))]
+        new0 = np.sort(order[:half])
+        done = np.array_equal(new0, c0)
+        c0 = new0
+        if done:
+            break
+    return order
+
+
+def build_tree(X: np.ndarray, leaf: int, partition: str = "kd") -> Tree:
     n = X.shape[0]
     L = tree_depth(n, leaf)
     perm = np.arange(n, dtype=np.int64)
@@ -191,8 +235,11 @@ def build_tree(X: np.ndarray, leaf: int) -> Tree:
             rad[bi] = 0.5 * math.sqrt(float(d[0]) * d[0] + float(d[1]) * d[1] + float(d[2]) * d[2])
             if lev < L:
                 axis = int(np.argmax(hi - lo))
-                order = np.lexsort((pts, X[pts, axis]))
-                perm[a:b] = pts[order]
+                if partition == "kmeans" and b - a >= 2:
+                    perm[a:b] = kmeans_split(X, pts, axis)
+                else:
+                    order = np.lexsort((pts, X[pts, axis]))
+                    perm[a:b] = pts[order]
                 mid = a + (b - a) // 2
                 nxt += [(a, mid), (mid, b)]
         start.append(st)
@@ -527,7 +574,7 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
     QR 2 n m^2 - 2/3 m^3; GEMM 2 m n k."""
     X = np.asarray(X, dtype=np.float64)
     check_params(X, p)
-    tree = build_tree(X, p.leaf)
+    tree = build_tree(X, p.leaf, p.partition)
     near, far = build_lists(tree, p.eta)
     fac = Factor(X, p, tree, near, far)
     L = tree.L
@@ -578,7 +625,8 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
         dlu = {}
         Y = {}
         for k in range(nb):
-            if m[k] == 0 or (need is not None and k not in need):
+            # the ablation without fill-ins in the basis has no fill-in step
+            if not p.fill_in or m[k] == 0 or (need is not None and k not in need):
                 continue
             dlu[k] = lu(D[k, k])
             flops["fill"] += 2.0 / 3.0 * m[k] ** 3
@@ -596,11 +644,13 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
             # basis comes from a sketch, which forms M' Omega without F)
             Fcols = []
             fl_F = 0.0
-            targets = fill_targets(near[lev], i)
+            # without fill-ins in the basis (the ablation) no block receives one
+            targets = fill_targets(near[lev], i) if p.fill_in else []
             for j in targets:
                 F = np.zeros((m[i], m[j]))
                 for k in near[lev][i]:
-                    if k == i or k == j or j not in near[lev][k]:
+                    # an empty box (both children fully eliminated) has no blocks
+                    if k == i or k == j or m[k] == 0 or j not in near[lev][k]:
                         continue
                     F += D[i, k] @ Y[k, j]
                     fl_F += 2.0 * m[i] * m[k] * m[j]
@@ -669,7 +719,8 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                     ell = 0
             if state not in (1, 3):
                 # M' formed: the products D_ik D_kk^-1, then the fill-ins
-                flops["fill"] += sum(2.0 * m[i] * m[k] ** 2 for k in near[lev][i] if k != i)
+                if p.fill_in:
+                    flops["fill"] += sum(2.0 * m[i] * m[k] ** 2 for k in near[lev][i] if k != i)
                 flops["fill"] += fl_F
                 k_i, piv, Wp, dg = row_id(M, p.tol, p.rank_cap)
                 flops["basis"] += 2.0 * ncol * m[i] ** 2 - 2.0 / 3.0 * min(ncol, m[i]) ** 3 if ncol >= m[i] else 2.0 * m[i] * ncol ** 2 - 2.0 / 3.0 * ncol ** 3
@@ -720,7 +771,9 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                     continue
                 Uj, kj = bf[j].U, bf[j].k
                 Snew[i, j] = Ui[:, :ki].T @ D[i, j] @ Uj[:, :kj]
-                flops["rotate"] += 2.0 * m[i] * m[j] * kj + 2.0 * ki * m[i] * kj
+                # an empty S^SS block (k_i or k_j = 0) costs nothing
+                if ki and kj:
+                    flops["rotate"] += 2.0 * m[i] * m[j] * kj + 2.0 * ki * m[i] * kj
                 if diagnostics:
                     dropped.append(_offdiag_dropped(Ui, D[i, j], Uj, ki, kj))
             S = Ui.T @ D[i, i] @ Ui

@@ -22,7 +22,9 @@ BUILD_DIR = PKG.parent / "_build"
 
 HIP_FLAGS = ["-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-Wno-unused-command-line-argument"]
+             "-Wno-unused-command-line-argument",
+             # per-kernel register / LDS / scratch report, checked below
+             "-Rpass-analysis=kernel-resource-usage"]
 SOURCES = [
     # MFMA accumulators in ordinary VGPRs (no copies between register files in the K loop)
     ("h2ulv_kernels.hip", ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]),
@@ -42,6 +44,22 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def scratch_users(remarks: str) -> list:
+    """Kernels whose resource report shows private (scratch) memory per lane:
+    register spills or stack arrays, which every kernel here is written to
+    avoid (they cost a memory round trip per access and a per-lane scratch
+    allocation at launch)."""
+    out, name = [], None
+    for line in remarks.splitlines():
+        if "Function Name:" in line:
+            name = line.split("Function Name:", 1)[1].split("[-Rpass")[0].strip()
+        elif "ScratchSize [bytes/lane]:" in line and name:
+            val = int(line.split("ScratchSize [bytes/lane]:", 1)[1].split("[")[0].strip())
+            if val > 0:
+                out.append((name, val))
+    return out
+
+
 def build(verbose: bool = False) -> Path:
     from concurrent.futures import ThreadPoolExecutor
     BUILD_DIR.mkdir(exist_ok=True)
@@ -57,6 +75,10 @@ def build(verbose: bool = False) -> Path:
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
+        bad = scratch_users(r.stderr)
+        if bad:
+            raise RuntimeError(f"{src}: kernels use scratch memory: " +
+                               ", ".join(f"{n} ({v} B/lane)" for n, v in bad))
         return str(obj)
 
     # the sources compile independently; at most one hipcc per available core

@@ -180,8 +180,14 @@ static void matvec_impl(const h2ulv_factor& F, const double* x, int64_t ldx, dou
   // buffer goes back to the cache, which other streams may draw from
   const int64_t words = matvec_work_words(F.n, nrhs);
   DBuf work(std::max<int64_t>(words, 1) * sizeof(double));
-  launch_matvec(F.pts.as<double>(), F.n, kfn(F.p), x, ldx, y, ldy, nrhs,
-                words > 0 ? work.as<double>() : nullptr, s);
+  {
+    // algorithmic work of a dense y = A x: 2 flops per matrix entry and column;
+    // bytes: the points, x and y
+    const double nn = (double)F.n;
+    ProfScope ps("matvec", 2.0 * nn * nn * nrhs, 8.0 * nn * (3.0 + 2.0 * nrhs), s);
+    launch_matvec(F.pts.as<double>(), F.n, kfn(F.p), x, ldx, y, ldy, nrhs,
+                  words > 0 ? work.as<double>() : nullptr, s);
+  }
   H2ULV_HIP(hipGetLastError());
   if (words > 0) H2ULV_HIP(hipStreamSynchronize(s));
 }
@@ -240,14 +246,15 @@ static h2ulv_status gmres_impl(const h2ulv_factor& F, const double* b, int64_t l
                                int64_t ldx, int nrhs, double rtol, int max_iter, int restart,
                                int32_t* iters, double* relres, hipStream_t s) {
   const int64_t n = F.n;
-  const int m = std::max(1, std::min(restart, 30));
+  constexpr int MAXM = 128;  // longest Krylov cycle
+  const int m = std::max(1, std::min(restart, MAXM));
   constexpr int NBLK = 256;
-  constexpr int HS = 3 * 32;  // per column: two Gram-Schmidt passes and the norm
+  constexpr int HS = 2 * MAXM + 32;  // per column: two Gram-Schmidt passes and the norm
   // Krylov blocks: block j holds column u's j-th vector at offset u * n
   DBuf Vb((int64_t)(m + 1) * n * nrhs * sizeof(double)),
       Zb((int64_t)m * n * nrhs * sizeof(double)), wb(n * nrhs * sizeof(double)),
       rb(n * nrhs * sizeof(double)), part((int64_t)NBLK * 32 * sizeof(double)),
-      hd((int64_t)nrhs * HS * sizeof(double)), ys((int64_t)nrhs * 32 * sizeof(double)),
+      hd((int64_t)nrhs * HS * sizeof(double)), ys((int64_t)nrhs * MAXM * sizeof(double)),
       nr(2 * nrhs * sizeof(double));
   double* V = Vb.as<double>();
   double* Z = Zb.as<double>();
@@ -309,22 +316,25 @@ static h2ulv_status gmres_impl(const h2ulv_factor& F, const double* b, int64_t l
       matvec_impl(F, Zj, n, w, n, na, s);
       // w_u -= V_u h_u, twice (classical Gram-Schmidt with re-orthogonalisation)
       for (int pass = 0; pass < 2; ++pass) {
+        // the dot products 32 basis vectors per launch
         for (int u : live)
-          launch_multidot(V + (int64_t)u * n, ldk, j + 1, w + (int64_t)u * n, n,
-                          part.as<double>(), NBLK, h + (int64_t)u * HS + 32 * pass, s);
+          for (int c0 = 0; c0 <= j; c0 += 32)
+            launch_multidot(V + (int64_t)c0 * ldk + (int64_t)u * n, ldk,
+                            std::min(32, j + 1 - c0), w + (int64_t)u * n, n, part.as<double>(),
+                            NBLK, h + (int64_t)u * HS + MAXM * pass + c0, s);
         Stage st(s);
         GemmBatch<double> gb;
         for (int u : live)
           gb.one(w + (int64_t)u * n, n, (int)n, 1, j + 1, V + (int64_t)u * n, ldk, false,
-                 h + (int64_t)u * HS + 32 * pass, j + 1, false, -1.0, 1.0);
+                 h + (int64_t)u * HS + MAXM * pass, j + 1, false, -1.0, 1.0);
         gb.run(st, "gmres");
         st.sync();
       }
       for (int u : live) {
         launch_multidot(w + (int64_t)u * n, n, 1, w + (int64_t)u * n, n, part.as<double>(), NBLK,
-                        h + (int64_t)u * HS + 64, s);
+                        h + (int64_t)u * HS + 2 * MAXM, s);
         launch_scale_inv_norm(V + (int64_t)(j + 1) * ldk + (int64_t)u * n, w + (int64_t)u * n,
-                              h + (int64_t)u * HS + 64, n, s);
+                              h + (int64_t)u * HS + 2 * MAXM, n, s);
       }
       H2ULV_HIP(hipGetLastError());
       H2ULV_HIP(hipMemcpyAsync(hh.data(), h, (size_t)na * HS * sizeof(double),
@@ -336,8 +346,8 @@ static h2ulv_status gmres_impl(const h2ulv_factor& F, const double* b, int64_t l
         const double* hu = hh.data() + (size_t)u * HS;
         // column j of the Hessenberg matrix
         double* col = H[u].data() + (size_t)j * (m + 1);
-        for (int i = 0; i <= j; ++i) col[i] = hu[i] + hu[32 + i];
-        col[j + 1] = std::sqrt(std::max(hu[64], 0.0));
+        for (int i = 0; i <= j; ++i) col[i] = hu[i] + hu[MAXM + i];
+        col[j + 1] = std::sqrt(std::max(hu[2 * MAXM], 0.0));
         for (int i = 0; i < j; ++i) {
           const double a0 = col[i], a1 = col[i + 1];
           col[i] = cs[u][i] * a0 + sn[u][i] * a1;
@@ -353,20 +363,21 @@ static h2ulv_status gmres_impl(const h2ulv_factor& F, const double* b, int64_t l
         jc[u] = j + 1;
         // stop early when the estimate is well below the target, on breakdown,
         // or at the step limit
-        if (std::fabs(g[u][j + 1]) <= 0.5 * rtol * bnorm[c] || hu[64] <= 0.0 ||
+        if (std::fabs(g[u][j + 1]) <= 0.5 * rtol * bnorm[c] || hu[2 * MAXM] <= 0.0 ||
             steps[c] >= max_iter)
           run[u] = 0;
       }
     }
     // y = R^-1 g, x += Z y per column
-    std::vector<double> y((size_t)na * 32, 0.0);
+    std::vector<double> y((size_t)na * MAXM, 0.0);
     for (int u = 0; u < na; ++u) {
       const int jj = jc[u];
+      double* yu = y.data() + (size_t)u * MAXM;
       for (int i = jj - 1; i >= 0; --i) {
         double sacc = g[u][i];
-        for (int l = i + 1; l < jj; ++l) sacc -= H[u][(size_t)l * (m + 1) + i] * y[u * 32 + l];
+        for (int l = i + 1; l < jj; ++l) sacc -= H[u][(size_t)l * (m + 1) + i] * yu[l];
         const double d = H[u][(size_t)i * (m + 1) + i];
-        y[u * 32 + i] = d != 0.0 ? sacc / d : 0.0;
+        yu[i] = d != 0.0 ? sacc / d : 0.0;
       }
     }
     H2ULV_HIP(hipMemcpyAsync(ys.p, y.data(), y.size() * sizeof(double), hipMemcpyHostToDevice,
@@ -377,7 +388,7 @@ static h2ulv_status gmres_impl(const h2ulv_factor& F, const double* b, int64_t l
       for (int u = 0; u < na; ++u)
         if (jc[u] > 0)
           gb.one(x + (int64_t)act[u] * ldx, ldx, (int)n, 1, jc[u], Z + (int64_t)u * n, ldk, false,
-                 ys.as<double>() + u * 32, jc[u], false, 1.0, 1.0);
+                 ys.as<double>() + (int64_t)u * MAXM, jc[u], false, 1.0, 1.0);
       gb.run(st, "gmres");
       st.sync();
     }
@@ -440,38 +451,58 @@ h2ulv_status h2ulv_params_default(h2ulv_params* p) {
   p->oversample = 8;
   p->rank_model = nullptr;
   p->sketch_seed = 0;
+  p->fill_in = 1;
+  p->partition = 0;
   return H2ULV_OK;
 }
 
+static bool bad_allocator(const h2ulv_allocator* a) {
+  return a && (!a->alloc || !a->free);
+}
+
+// the factors remember the caller's allocator for the temporaries of later calls
+static void keep_allocator(h2ulv_factor* f, const h2ulv_allocator* a) {
+  if (f && a) {
+    f->alloc = *a;
+    f->has_alloc = true;
+  }
+}
+
 h2ulv_status h2ulv_factorize(const double* pts, int64_t n, const h2ulv_params* params,
-                             void* stream, h2ulv_factor** out) {
-  if (!out) {
-    g_last_error = "out is NULL";
+                             const h2ulv_allocator* alloc, void* stream, h2ulv_factor** out) {
+  if (!out || bad_allocator(alloc)) {
+    g_last_error = !out ? "out is NULL" : "allocator with a NULL function";
     return H2ULV_ERR_INVALID_ARG;
   }
   *out = nullptr;
   return guarded([&] {
     CacheScope cs;
+    AllocScope as(alloc, stream);
     *out = factorize_impl(pts, n, params, (hipStream_t)stream);
+    keep_allocator(*out, alloc);
   });
 }
 
 h2ulv_status h2ulv_factorize_batch(int32_t nprob, const double* const* pts, const int64_t* n,
-                                   const h2ulv_params* params, void* stream,
-                                   h2ulv_factor** out) {
-  if (nprob < 1 || !pts || !n || !out) {
+                                   const h2ulv_params* params, const h2ulv_allocator* alloc,
+                                   void* stream, h2ulv_factor** out) {
+  if (nprob < 1 || !pts || !n || !out || bad_allocator(alloc)) {
     g_last_error = "bad batch arguments";
     return H2ULV_ERR_INVALID_ARG;
   }
   for (int p = 0; p < nprob; ++p) out[p] = nullptr;
   h2ulv_status st = guarded([&] {
     CacheScope cs;
+    AllocScope as(alloc, stream);
     if (!params) fail(H2ULV_ERR_INVALID_ARG, "params is NULL");
     validate_params(params);
     std::vector<const double*> pv(pts, pts + nprob);
     std::vector<int64_t> nv(n, n + nprob);
     std::vector<h2ulv_factor*> fs = factorize_many(pv, nv, *params, (hipStream_t)stream);
-    for (int p = 0; p < nprob; ++p) out[p] = fs[p];
+    for (int p = 0; p < nprob; ++p) {
+      out[p] = fs[p];
+      keep_allocator(out[p], alloc);
+    }
   });
   if (st != H2ULV_OK)
     for (int p = 0; p < nprob; ++p) {
@@ -489,6 +520,7 @@ h2ulv_status h2ulv_solve(const h2ulv_factor* f, double* b, int32_t nrhs, int64_t
   }
   return guarded([&] {
     CacheScope cs;
+    AllocScope as(f->has_alloc ? &f->alloc : nullptr, stream);
     solve_impl(*f, b, nrhs, ldb, (hipStream_t)stream);
   });
 }
@@ -499,7 +531,10 @@ h2ulv_status h2ulv_matvec_exact(const h2ulv_factor* f, const double* x, int64_t 
     g_last_error = "bad matvec arguments";
     return H2ULV_ERR_INVALID_ARG;
   }
-  return guarded([&] { matvec_impl(*f, x, ldx, y, ldy, nrhs, (hipStream_t)stream); });
+  return guarded([&] {
+    AllocScope as(f->has_alloc ? &f->alloc : nullptr, stream);
+    matvec_impl(*f, x, ldx, y, ldy, nrhs, (hipStream_t)stream);
+  });
 }
 
 h2ulv_status h2ulv_refine(const h2ulv_factor* f, const double* b, int64_t ldb, double* x,
@@ -512,6 +547,7 @@ h2ulv_status h2ulv_refine(const h2ulv_factor* f, const double* b, int64_t ldb, d
   h2ulv_status out = H2ULV_OK;
   h2ulv_status st = guarded([&] {
     CacheScope cs;
+    AllocScope as(f->has_alloc ? &f->alloc : nullptr, stream);
     out = refine_impl(*f, b, ldb, x, ldx, nrhs, rtol, max_iter, iters, relres,
                       (hipStream_t)stream);
   });
@@ -529,6 +565,7 @@ h2ulv_status h2ulv_refine_gmres(const h2ulv_factor* f, const double* b, int64_t 
   h2ulv_status out = H2ULV_OK;
   h2ulv_status st = guarded([&] {
     CacheScope cs;
+    AllocScope as(f->has_alloc ? &f->alloc : nullptr, stream);
     out = gmres_impl(*f, b, ldb, x, ldx, nrhs, rtol, max_iter, restart, iters, relres,
                      (hipStream_t)stream);
   });
@@ -605,7 +642,7 @@ h2ulv_status h2ulv_structure_create(const double* pts, int64_t n, const h2ulv_pa
     for (int64_t i = 0; i < 3 * n; ++i)
       if (!std::isfinite(pts[i])) fail(H2ULV_ERR_INVALID_ARG, "non-finite point coordinate");
     auto s = std::make_unique<h2ulv_structure>();
-    s->tree = build_tree(pts, n, params->leaf_size);
+    s->tree = build_tree(pts, n, params->leaf_size, params->partition);
     s->lists = build_lists(s->tree, params->eta);
     *out = s.release();
   });
@@ -788,6 +825,14 @@ h2ulv_status h2ulv_profile_enable(int32_t on) {
         p.pool.push_back(e);
       }
   });
+}
+
+h2ulv_status h2ulv_gemm_tile_rates(double* out) {
+  if (!out) {
+    g_last_error = "out is NULL";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  return guarded([&] { (void)gemm_tile_rates_known(out); });
 }
 
 h2ulv_status h2ulv_profile_read(h2ulv_kernel_profile* out, int32_t max, int32_t* count) {

@@ -103,16 +103,40 @@ struct ProfScope {
   }
 };
 
-// Owning device buffer (hipMalloc / hipFree).
+// The caller's device allocator of the running call (thread-local; unset: the
+// caching allocator above).  A buffer keeps the allocator it came from and
+// gives its block back to it.
+struct AllocHook {
+  h2ulv_allocator a{};
+  void* stream = nullptr;
+  bool set = false;
+};
+AllocHook& current_alloc_hook();
+struct AllocScope {
+  AllocHook prev;
+  AllocScope(const h2ulv_allocator* a, void* stream) : prev(current_alloc_hook()) {
+    AllocHook& h = current_alloc_hook();
+    h.set = a != nullptr;
+    if (a) h.a = *a;
+    h.stream = stream;
+  }
+  ~AllocScope() { current_alloc_hook() = prev; }
+  AllocScope(const AllocScope&) = delete;
+  AllocScope& operator=(const AllocScope&) = delete;
+};
+
+// Owning device buffer: from the caller's allocator when one is installed,
+// else from the caching allocator.
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;  // requested size
   size_t cap = 0;    // size of the block behind it
+  AllocHook hook;    // where the block came from (hook.set: the caller's allocator)
   DBuf() = default;
   explicit DBuf(size_t b) { alloc(b); }
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes), cap(o.cap) {
+  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes), cap(o.cap), hook(o.hook) {
     o.p = nullptr;
     o.bytes = 0;
     o.cap = 0;
@@ -123,6 +147,7 @@ struct DBuf {
       p = o.p;
       bytes = o.bytes;
       cap = o.cap;
+      hook = o.hook;
       o.p = nullptr;
       o.bytes = 0;
       o.cap = 0;
@@ -133,7 +158,16 @@ struct DBuf {
   void alloc(size_t b) {
     reset();
     if (b == 0) return;
-    p = cache_alloc(b, &cap);
+    hook = current_alloc_hook();
+    if (hook.set) {
+      p = hook.a.alloc(hook.a.ctx, b, hook.stream);
+      if (!p)
+        fail(H2ULV_ERR_OOM,
+             "the caller's allocator returned NULL for " + std::to_string(b) + " bytes");
+      cap = b;
+    } else {
+      p = cache_alloc(b, &cap);
+    }
     bytes = b;
     MemStats& ms = mem_stats();
     ms.live += b;
@@ -141,7 +175,10 @@ struct DBuf {
   }
   void reset() {
     if (p) {
-      cache_free(p, cap);
+      if (hook.set)
+        hook.a.free(hook.a.ctx, p, hook.stream);
+      else
+        cache_free(p, cap);
       mem_stats().live -= bytes;
     }
     p = nullptr;
@@ -290,6 +327,16 @@ struct Stage {
 inline int64_t tiles64(int64_t m, int64_t n) { return ((m + 63) / 64) * ((n + 63) / 64); }
 inline int64_t tiles_of(int64_t m, int64_t n, int t) { return ((m + t - 1) / t) * ((n + t - 1) / t); }
 
+// Full-tile rates (TFLOP/s) of the GEMM tile shapes on the current device,
+// measured the first time a precision is used on a device (autotuning: a
+// synthetic batch of 256 x 256 products in every shape, timed with events) and
+// kept for the process.  f64: 64x64, 64x128, 128x64, 128x128; f32: 64x64,
+// 128x128.
+const double* gemm_tile_rates(bool f64, hipStream_t s);
+// The rates measured so far on the current device (0 where not yet measured):
+// f64 x 4 then f32 x 2.  Returns false when nothing has been measured.
+bool gemm_tile_rates_known(double* out6);
+
 // TI: operand type (MFMA precision), TC: type of the result C.
 template <typename T, typename TC = T>
 struct GemmBatch {
@@ -358,11 +405,14 @@ struct GemmBatch {
       double rate;
       int per_cu;  // resident workgroups per CU
     };
-    static const Shape f64s[4] = {{64, 64, 53.5, 4}, {64, 128, 56.6, 3}, {128, 64, 56.1, 3},
-                                  {128, 128, 57.9, 2}};
-    static const Shape f32s[2] = {{64, 64, 96.8, 8}, {128, 128, 112.1, 3}};
-    const Shape* cand = sizeof(T) == 8 ? f64s : f32s;
+    Shape f64s[4] = {{64, 64, 0, 4}, {64, 128, 0, 3}, {128, 64, 0, 3}, {128, 128, 0, 2}};
+    Shape f32s[2] = {{64, 64, 0, 8}, {128, 128, 0, 3}};
+    Shape* cand = sizeof(T) == 8 ? f64s : f32s;
     const int ncand = sizeof(T) == 8 ? 4 : 2;
+    {
+      const double* rt = gemm_tile_rates(sizeof(T) == 8, st.s);
+      for (int c = 0; c < ncand; ++c) cand[c].rate = rt[c];
+    }
     int maxM = 0;
     std::vector<double> ksum(its.size(), 0.0);
     for (size_t i = 0; i < its.size(); ++i) {
@@ -398,10 +448,12 @@ struct GemmBatch {
     auto ntile = [&](const GemmItem<TC>& it) {
       return (int64_t)((it.M + tm - 1) / tm) * ((it.N + tn - 1) / tn);
     };
-    int64_t nt0 = 0;
+    // the split-K decision depends on the batch alone (counted in 64 x 64 tiles),
+    // not on the tuned tile shape, so the summation order is fixed by the batch
+    int64_t nt64 = 0;
     double kmax = 0;
     for (size_t i = 0; i < its.size(); ++i) {
-      nt0 += ntile(its[i]);
+      nt64 += tiles64(its[i].M, its[i].N);
       kmax = std::max(kmax, ksum[i]);
     }
     double fl = 0, by = 0;
@@ -418,8 +470,8 @@ struct GemmBatch {
     // s of item i writes its partial product into scratch (beta 0) and a
     // reduction adds the partials in order into C with alpha and beta
     int S = 1;
-    if (nt0 < 256 && kmax >= 512) {
-      S = (int)std::min<int64_t>(8, std::max<int64_t>(1, 512 / std::max<int64_t>(nt0, 1)));
+    if (nt64 < 1024 && kmax >= 512) {
+      S = (int)std::min<int64_t>(8, std::max<int64_t>(1, 2048 / std::max<int64_t>(nt64, 1)));
       S = (int)std::min<double>(S, std::floor(kmax / 256.0));
     }
     std::vector<SplitKItem<TC>> red;

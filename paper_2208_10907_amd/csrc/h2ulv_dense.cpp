@@ -45,6 +45,105 @@ void release_locked(DevCache& c) {
 
 }  // namespace
 
+namespace {
+
+// Tile-shape autotuning of the grouped GEMM.  The synthetic batch has the shape
+// of the fill-in products: 96 items of 256 x 256, each a sum of 4 products with
+// K = 256, the left operands shared by all items (like the D_kj blocks that many
+// boxes read) and the right ones per item.
+struct TileTune {
+  std::mutex mu;
+  bool have[2] = {false, false};
+  double rate[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // [0] f64, [1] f32
+};
+TileTune& tile_tune(int dev) {
+  static TileTune t[64];
+  return t[dev & 63];
+}
+
+template <typename T>
+void measure_tile_rates(hipStream_t s, double* out) {
+  constexpr int NI = 96, NT = 4, D = 256;
+  const int64_t blk = (int64_t)D * D;
+  DBuf A(NT * blk * sizeof(T)), B(NI * blk * sizeof(T)), Cb(NI * blk * sizeof(T));
+  H2ULV_HIP(hipMemsetAsync(A.p, 0, A.bytes, s));
+  H2ULV_HIP(hipMemsetAsync(B.p, 0, B.bytes, s));
+  std::vector<GemmItem<T>> items(NI);
+  std::vector<GemmTerm<T>> terms(NI * NT);
+  for (int i = 0; i < NI; ++i) {
+    items[i] = GemmItem<T>{Cb.as<T>() + i * blk, D, D, D, i * NT, NT, 1.0, 0.0};
+    for (int t = 0; t < NT; ++t)
+      terms[i * NT + t] = GemmTerm<T>{A.as<T>() + t * blk, B.as<T>() + i * blk, D, D, D, 0};
+  }
+  const int shapes64[4][2] = {{64, 64}, {64, 128}, {128, 64}, {128, 128}};
+  const int shapes32[2][2] = {{64, 64}, {128, 128}};
+  const bool f64 = sizeof(T) == 8;
+  const int ns = f64 ? 4 : 2;
+  DBuf di(items.size() * sizeof(GemmItem<T>)), dt(terms.size() * sizeof(GemmTerm<T>)),
+      dp((NI + 1) * sizeof(int64_t));
+  H2ULV_HIP(hipMemcpyAsync(di.p, items.data(), di.bytes, hipMemcpyHostToDevice, s));
+  H2ULV_HIP(hipMemcpyAsync(dt.p, terms.data(), dt.bytes, hipMemcpyHostToDevice, s));
+  hipEvent_t e0, e1;
+  H2ULV_HIP(hipEventCreate(&e0));
+  H2ULV_HIP(hipEventCreate(&e1));
+  const double flops = 2.0 * NI * NT * (double)D * D * D;
+  for (int c = 0; c < ns; ++c) {
+    const int tm = f64 ? shapes64[c][0] : shapes32[c][0];
+    const int tn = f64 ? shapes64[c][1] : shapes32[c][1];
+    const int64_t per = (int64_t)(D / tm) * (D / tn);
+    std::vector<int64_t> tp(NI + 1);
+    for (int i = 0; i <= NI; ++i) tp[i] = i * per;
+    H2ULV_HIP(hipMemcpyAsync(dp.p, tp.data(), dp.bytes, hipMemcpyHostToDevice, s));
+    launch_gemm<T, T>(di.as<GemmItem<T>>(), dt.as<GemmTerm<T>>(), dp.as<int64_t>(), NI * per,
+                      NI, tm, tn, s);  // warm-up
+    H2ULV_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < 3; ++r)
+      launch_gemm<T, T>(di.as<GemmItem<T>>(), dt.as<GemmTerm<T>>(), dp.as<int64_t>(), NI * per,
+                        NI, tm, tn, s);
+    H2ULV_HIP(hipEventRecord(e1, s));
+    H2ULV_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    H2ULV_HIP(hipEventElapsedTime(&ms, e0, e1));
+    out[c] = ms > 0 ? 3.0 * flops / (ms * 1e-3) / 1e12 : 1.0;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  H2ULV_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+const double* gemm_tile_rates(bool f64, hipStream_t s) {
+  int dev = 0;
+  H2ULV_HIP(hipGetDevice(&dev));
+  TileTune& t = tile_tune(dev);
+  std::lock_guard<std::mutex> lk(t.mu);
+  const int q = f64 ? 0 : 1;
+  if (!t.have[q]) {
+    if (f64)
+      measure_tile_rates<double>(s, t.rate[0]);
+    else
+      measure_tile_rates<float>(s, t.rate[1]);
+    t.have[q] = true;
+  }
+  return t.rate[q];
+}
+
+bool gemm_tile_rates_known(double* out6) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  TileTune& t = tile_tune(dev);
+  std::lock_guard<std::mutex> lk(t.mu);
+  for (int c = 0; c < 4; ++c) out6[c] = t.have[0] ? t.rate[0][c] : 0.0;
+  for (int c = 0; c < 2; ++c) out6[4 + c] = t.have[1] ? t.rate[1][c] : 0.0;
+  return t.have[0] || t.have[1];
+}
+
+AllocHook& current_alloc_hook() {
+  thread_local AllocHook h;
+  return h;
+}
+
 void* cache_alloc(size_t bytes, size_t* got) {
   DevCache& c = dev_cache();
   const size_t want = round_block(bytes);

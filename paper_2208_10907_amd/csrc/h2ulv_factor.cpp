@@ -20,6 +20,7 @@
 #include "h2ulv_factor.h"
 #include "h2ulv_learned.h"
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -133,7 +134,7 @@ struct Prob {
   std::vector<int64_t> cand_all, cand_off;
   DBuf dcand;
   std::vector<int64_t> Doff, offSq, offTinv, offW, ncols;
-  DBuf D, Dinv, Tinv, Z, D32, PQ, pivd, kd, S;
+  DBuf D, Dinv, Tinv, Z, D32, Z32, PQ, pivd, kd, S;
   std::vector<std::vector<int>> targets;
   std::vector<std::vector<int64_t>> farcols;
   std::vector<int64_t> far_off;  // box i's far columns at dfar + far_off[i]
@@ -174,7 +175,7 @@ struct Prob {
       sq += mi * mi;
       for (int64_t e = np()[i]; e < np()[i + 1]; ++e) dw += mi * (double)m[ni()[e]].size();
     }
-    return 8.0 * (3.0 * dw + 4.0 * sq) + (mixed ? 4.0 * dw : 0.0);
+    return 8.0 * (3.0 * dw + 4.0 * sq) + (mixed ? 8.0 * dw : 0.0);
   }
 
   void end_level() {
@@ -191,7 +192,8 @@ struct Prob {
     Eptr.clear();
     ldE.clear();
     Ebufs.clear();
-    for (DBuf* b : {&dcand, &dfar, &D, &Dinv, &Tinv, &Z, &D32, &PQ, &pivd, &kd, &S}) b->reset();
+    for (DBuf* b : {&dcand, &dfar, &D, &Dinv, &Tinv, &Z, &D32, &Z32, &PQ, &pivd, &kd, &S})
+      b->reset();
   }
 };
 
@@ -205,6 +207,9 @@ struct Driver {
   h2ulv_params p;
   KernelFn kf;
   bool mixed;
+  // mixed precision with a rank cap: the fill-in products run in FP32 as well
+  // (the cap bounds the basis, so FP32 rounding of M' cannot inflate ranks)
+  bool fill32;
   const double* pts = nullptr;  // shared points of all problems (n x 3 each)
   DBuf dupbuf;
   int* dup = nullptr;
@@ -214,7 +219,11 @@ struct Driver {
   double t_last = 0;
 
   Driver(hipStream_t st, const h2ulv_params& pr)
-      : s(st), p(pr), kf(kfn(pr)), mixed(pr.precision == H2ULV_MIXED) {
+      : s(st),
+        p(pr),
+        kf(kfn(pr)),
+        mixed(pr.precision == H2ULV_MIXED),
+        fill32(pr.precision == H2ULV_MIXED && pr.rank_cap > 0) {
     dupbuf.alloc(sizeof(int));
     dup = dupbuf.as<int>();
     H2ULV_HIP(hipMemsetAsync(dup, 0, sizeof(int), s));
@@ -315,6 +324,8 @@ void Driver::dense_blocks(Stage& st, const std::vector<Prob*>& G) {
 
 // ---- (b) fill-ins: inverses of the diagonal blocks and Z'_ik = T^-1 D_ik D_kk^-1
 void Driver::fill_products(Stage& st, const std::vector<Prob*>& G) {
+  // the ablation without fill-ins in the basis has no fill-in step
+  if (!p.fill_in) return;
   {
     std::vector<DBuf> LUw;
     CopyBatch cb;
@@ -423,6 +434,16 @@ void Driver::fill_z(Stage& st, const std::vector<Box>& boxes) {
   }
   g.run(st, "fill_z");
   g2.run(st, "fill_z");
+  if (fill32) {
+    // FP32 copy of Z' for the fill-in products (entries of sketched boxes are
+    // converted too but never read)
+    std::vector<Prob*> done;
+    for (const Box& b : boxes)
+      if (std::find(done.begin(), done.end(), b.P) == done.end()) {
+        done.push_back(b.P);
+        b.P->Z32 = to_f32(b.P->Z.as<double>(), b.P->Doff[b.P->nnear()], s);
+      }
+  }
   st.sync();
 }
 
@@ -449,7 +470,8 @@ void Driver::basis_prepare(Stage& st, const std::vector<Prob*>& G) {
     const bool upper = P->lev < P->L();
     const double th = now_s();
     parallel_for(nb, 8, [&](int64_t i) {
-      P->targets[i] = fill_targets(ls, P->lev, (int)i);
+      // the ablation without fill-ins in the basis has no fill targets
+      if (p.fill_in) P->targets[i] = fill_targets(ls, P->lev, (int)i);
       P->farcols[i] = far_columns(P->F->tree, ls, P->lev, (int)i, lf.cand, p.far_sample);
       int64_t nc = (int64_t)P->farcols[i].size();
       for (int j : P->targets[i]) nc += m[j];
@@ -485,10 +507,11 @@ void Driver::basis_prepare(Stage& st, const std::vector<Prob*>& G) {
     }
     htime("h_prepare", th);
     // mixed precision: the rotations, low-rank couplings and Schur updates run on
-    // FP32 matrix cores with FP32 accumulation; the fill-in products stay FP64
-    // because they feed the rank-revealing QR, whose decisions at tol ~1e-6 sit
-    // at FP32 rounding level (FP32 fill-ins inflate the upper-level ranks several
-    // times); inverses, QR/ID, solve and residual are FP64 as well
+    // FP32 matrix cores with FP32 accumulation.  The fill-in products feed the
+    // rank-revealing QR, whose decisions at tol ~1e-6 sit at FP32 rounding level:
+    // without a rank cap FP32 fill-ins inflate the upper-level ranks several
+    // times, so they are FP32 only when a cap bounds the ranks; inverses, QR/ID,
+    // solve and residual are FP64
     if (mixed) P->D32 = to_f32(P->D.as<double>(), P->Doff[P->nnear()], s);
     // per-box pivoted-QR matrices (m x m) kept until W' is built
     P->PQ.alloc(std::max<int64_t>(P->offSq[nb], 1) * sizeof(double));
@@ -522,10 +545,11 @@ void Driver::basis_prepare(Stage& st, const std::vector<Prob*>& G) {
       const int mi = lf.m[i];
       // at most m - probes columns: a box whose predicted rank leaves no room
       // (k-hat >= m - probes included) is still sketched at full width, which
-      // the probe check accepts whenever its true rank is below that width
-      const int64_t ell = std::min<int64_t>((5 * (int64_t)lf.khat[i] + 3) / 4 + p.oversample,
-                                            mi - SKETCH_PROBES);
-      if (ell > 0 && ell < P->ncols[i] && (p.rank_cap == 0 || ell < p.rank_cap)) {
+      // the probe check accepts whenever its true rank is below that width; with
+      // a rank cap the sketch is sized for min(k-hat, cap)
+      const int64_t ks = p.rank_cap > 0 ? std::min(lf.khat[i], p.rank_cap) : lf.khat[i];
+      const int64_t ell = std::min<int64_t>((5 * ks + 3) / 4 + p.oversample, mi - SKETCH_PROBES);
+      if (ell > 0 && ell < P->ncols[i]) {
         lf.ell[i] = (int)ell;
         lf.sk_state[i] = 1;
       }
@@ -789,6 +813,7 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
     double* Mp = Mb.as<double>();
     KgenBatch kb;
     GemmBatch<double> g;
+    GemmBatch<float, double> g32;
     for (size_t q = 0; q < nc; ++q) {
       Prob* P = full[b0 + q].P;
       const int i = full[b0 + q].i;
@@ -806,14 +831,21 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
       for (int j : P->targets[i]) {
         if (m[j] > 0) {
           // (T^-1 F_ij)^T = sum_k D_kj^T Z'_ik^T
-          g.item(Mi + row, ld, m[j], m[i]);
+          if (fill32)
+            g32.item(Mi + row, ld, m[j], m[i]);
+          else
+            g.item(Mi + row, ld, m[j], m[i]);
           for (int64_t e = np[i]; e < np[i + 1]; ++e) {
             int k = ni[e];
             if (k == i || k == j || m[k] == 0) continue;
             int64_t ekj = csr_find(np, ni, k, j);
             if (ekj < 0) continue;
-            g.term(P->D.as<double>() + P->Doff[ekj], m[k], true, P->Z.as<double>() + P->Doff[e],
-                   m[i], true, m[k]);
+            if (fill32)
+              g32.term(P->D32.as<float>() + P->Doff[ekj], m[k], true,
+                       P->Z32.as<float>() + P->Doff[e], m[i], true, m[k]);
+            else
+              g.term(P->D.as<double>() + P->Doff[ekj], m[k], true,
+                     P->Z.as<double>() + P->Doff[e], m[i], true, m[k]);
             P->fl_fill += 2.0 * m[i] * (double)m[k] * m[j];
           }
         }
@@ -822,6 +854,7 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
     }
     kb.run(st, pts, kf, dup);
     g.run(st, "fill_m");
+    g32.run(st, "fill_m");
     tick("c_fill_gemm");
     // tall QR of every other M'^T: a tree of blocked Householder QRs (leaf
     // chunks of 4m rows factored in place, then stacked triangles merged pairwise)
@@ -1097,7 +1130,8 @@ void Driver::pivot_boxes(Stage& st, const std::vector<Box>& boxes) {
 
 // ---- (c) randomized check of the sketched row IDs: with Z^T the probe rows
 // below the sketch, res = Z^T[:, piv[k:]] - Z^T[:, piv[:k]] E; accepted iff the
-// sketch was not exhausted and |res|_F <= slack sqrt(m - k) tol max_j |Z^T[:, j]|.
+// sketch was not exhausted and |res|_F <= slack sqrt(m - k) tol max_j |Z^T[:, j]|,
+// or the rank cap ended the pivot loop with q columns of oversampling left.
 // Returns the rejected boxes.
 std::vector<Box> Driver::check_sketches(Stage& st, const std::vector<Box>& boxes) {
   const int q = SKETCH_PROBES;
@@ -1155,7 +1189,11 @@ std::vector<Box> Driver::check_sketches(Stage& st, const std::vector<Box>& boxes
       const LevelFactor& lf = probed[u].P->lf();
       const int mi = lf.m[probed[u].i], k = lf.k[probed[u].i];
       const double res = std::sqrt(h[4 * u]), zmax = std::sqrt(h[4 * u + 3]);
-      if (!(res <= SKETCH_SLACK * std::sqrt((double)(mi - k)) * p.tol * zmax))
+      // the cap ended the pivot loop: the full pivoted QR misses tol as well, so
+      // the sketch stands if it keeps q columns of oversampling beyond k
+      const bool capped =
+          p.rank_cap > 0 && k == p.rank_cap && lf.ell[probed[u].i] - k >= SKETCH_PROBES;
+      if (!capped && !(res <= SKETCH_SLACK * std::sqrt((double)(mi - k)) * p.tol * zmax))
         fails.push_back(probed[u]);
     }
   }
@@ -1185,7 +1223,7 @@ void Driver::row_ids(Stage& st, const std::vector<Prob*>& G) {
     for (const Box& b : fails) {
       LevelFactor& lf = b.P->lf();
       const int w = lf.m[b.i] - SKETCH_PROBES;
-      if (lf.ell[b.i] < w && w < b.P->ncols[b.i] && (p.rank_cap == 0 || w < p.rank_cap)) {
+      if (lf.ell[b.i] < w && w < b.P->ncols[b.i]) {
         lf.ell[b.i] = w;
         retry.push_back(b);
       } else {
@@ -1822,7 +1860,7 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
     F[q]->p = params;
     F[q]->p.rank_model = nullptr;  // the factor does not keep the model
     F[q]->n = n[q];
-    F[q]->tree = build_tree(hp.data(), n[q], params.leaf_size);
+    F[q]->tree = build_tree(hp.data(), n[q], params.leaf_size, params.partition);
     F[q]->lists = build_lists(F[q]->tree, params.eta);
     F[q]->hpts = std::move(hp);
   }

@@ -57,6 +57,10 @@ struct h2ulv_factor {
   h2ulv::DBuf root_inv;
   int m_root = 0;
   h2ulv_stats stats{};
+  // the caller's allocator of the factorization (has_alloc), used again for the
+  // temporaries of later calls on this factor
+  h2ulv_allocator alloc{};
+  bool has_alloc = false;
 };
 
 struct h2ulv_rankmodel {

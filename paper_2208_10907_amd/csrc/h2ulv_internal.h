@@ -70,7 +70,7 @@ struct Lists {
 };
 
 int tree_depth(int64_t n, int leaf);
-Tree build_tree(const double* pts, int64_t n, int leaf);
+Tree build_tree(const double* pts, int64_t n, int leaf, int partition);
 Lists build_lists(const Tree& t, double eta);
 void validate_params(const h2ulv_params* p);
 

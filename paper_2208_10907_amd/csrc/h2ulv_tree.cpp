@@ -7,7 +7,10 @@
 // library uses
 //   * a k-d split along the widest bounding-box axis (lowest axis on ties),
 //     points stably ordered by (coordinate, original index), left child gets
-//     floor(n/2); depth L = smallest integer with leaf * 2^L >= N;
+//     floor(n/2); depth L = smallest integer with leaf * 2^L >= N; or, for
+//     point clouds on surfaces, a balanced 2-means bisection (Sec. V clusters
+//     the boundary-element points with k-means, the cluster count a power of
+//     two);
 //   * box centre = bounding-box midpoint, radius = half its diagonal;
 //   * (i, j) admissible iff |c_i - c_j| > eta (r_i + r_j), decided for the
 //     children of every near pair of the parent level (root: near to itself).
@@ -39,7 +42,58 @@ static void bbox(const double* pts, const int64_t* idx, int64_t cnt, double lo[3
     }
 }
 
-Tree build_tree(const double* pts, int64_t n, int leaf) {
+// Balanced 2-means bisection of the points p[0..cnt) (reordered in place):
+// start from the k-d split (order by coordinate of the widest axis, then index;
+// the first floor(cnt/2) points form cluster 0), then up to 10 Lloyd steps:
+// centroids as plain sums over each cluster's points in ascending index order
+// divided by the count, every point keyed by |x - c0|^2 - |x - c1|^2, the
+// floor(cnt/2) smallest keys (ties by index) form cluster 0; stop when
+// cluster 0 no longer changes.  The final order is the last (key, index) order.
+static void kmeans_split(const double* pts, int64_t* p, int64_t cnt, int axis) {
+  const int64_t half = cnt / 2;
+  std::vector<std::pair<double, int64_t>> key(cnt);
+  for (int64_t u = 0; u < cnt; ++u) key[u] = {pts[p[u] * 3 + axis], p[u]};
+  std::sort(key.begin(), key.end());
+  std::vector<int64_t> c0(half), prev;
+  for (int64_t u = 0; u < half; ++u) c0[u] = key[u].second;
+  std::sort(c0.begin(), c0.end());
+  for (int it = 0; it < 10; ++it) {
+    std::vector<int64_t> c1;
+    c1.reserve(cnt - half);
+    for (int64_t u = half; u < cnt; ++u) c1.push_back(key[u].second);
+    std::sort(c1.begin(), c1.end());
+    double m0[3] = {0, 0, 0}, m1[3] = {0, 0, 0};
+    for (int64_t q : c0)
+      for (int c = 0; c < 3; ++c) m0[c] = m0[c] + pts[q * 3 + c];
+    for (int64_t q : c1)
+      for (int c = 0; c < 3; ++c) m1[c] = m1[c] + pts[q * 3 + c];
+    for (int c = 0; c < 3; ++c) {
+      m0[c] = m0[c] / (double)c0.size();
+      m1[c] = m1[c] / (double)c1.size();
+    }
+    for (int64_t u = 0; u < cnt; ++u) {
+      const int64_t q = key[u].second;
+      double a0 = pts[q * 3] - m0[0], a1 = pts[q * 3 + 1] - m0[1], a2 = pts[q * 3 + 2] - m0[2];
+      double b0 = pts[q * 3] - m1[0], b1 = pts[q * 3 + 1] - m1[1], b2 = pts[q * 3 + 2] - m1[2];
+      double d0 = a0 * a0;
+      d0 = d0 + a1 * a1;
+      d0 = d0 + a2 * a2;
+      double d1 = b0 * b0;
+      d1 = d1 + b1 * b1;
+      d1 = d1 + b2 * b2;
+      key[u].first = d0 - d1;
+    }
+    std::sort(key.begin(), key.end());
+    prev.swap(c0);
+    c0.assign(half, 0);
+    for (int64_t u = 0; u < half; ++u) c0[u] = key[u].second;
+    std::sort(c0.begin(), c0.end());
+    if (c0 == prev) break;
+  }
+  for (int64_t u = 0; u < cnt; ++u) p[u] = key[u].second;
+}
+
+Tree build_tree(const double* pts, int64_t n, int leaf, int partition) {
   Tree t;
   t.n = n;
   t.L = tree_depth(n, leaf);
@@ -78,14 +132,18 @@ Tree build_tree(const double* pts, int64_t n, int leaf) {
         if (d[2] > d[axis]) axis = 2;
         int64_t* p = t.perm.data() + a0;
         const int64_t cnt = a1 - a0;
-        std::vector<std::pair<double, int64_t>> key(cnt);
-        for (int64_t u = 0; u < cnt; ++u) key[u] = {pts[p[u] * 3 + axis], p[u]};
         const int64_t half = cnt / 2;
-        if (lev + 1 == t.L)
-          std::sort(key.begin(), key.end());
-        else if (half > 0)
-          std::nth_element(key.begin(), key.begin() + half, key.end());
-        for (int64_t u = 0; u < cnt; ++u) p[u] = key[u].second;
+        if (partition == 1 && cnt >= 2) {
+          kmeans_split(pts, p, cnt, axis);
+        } else {
+          std::vector<std::pair<double, int64_t>> key(cnt);
+          for (int64_t u = 0; u < cnt; ++u) key[u] = {pts[p[u] * 3 + axis], p[u]};
+          if (lev + 1 == t.L)
+            std::sort(key.begin(), key.end());
+          else if (half > 0)
+            std::nth_element(key.begin(), key.begin() + half, key.end());
+          for (int64_t u = 0; u < cnt; ++u) p[u] = key[u].second;
+        }
         next[2 * b] = {a0, a0 + half};
         next[2 * b + 1] = {a0 + half, a1};
       }
@@ -165,6 +223,11 @@ void validate_params(const h2ulv_params* p) {
   if (p->precision != H2ULV_FP64 && p->precision != H2ULV_MIXED)
     fail(H2ULV_ERR_INVALID_ARG, "unknown precision");
   if (p->oversample < 0) fail(H2ULV_ERR_INVALID_ARG, "oversample must be >= 0");
+  if (p->fill_in != 0 && p->fill_in != 1) fail(H2ULV_ERR_INVALID_ARG, "fill_in must be 0 or 1");
+  if (p->partition != 0 && p->partition != 1)
+    fail(H2ULV_ERR_INVALID_ARG, "partition must be 0 (k-d) or 1 (k-means)");
+  if (p->fill_in == 0 && p->rank_model)
+    fail(H2ULV_ERR_INVALID_ARG, "fill_in = 0 must not be combined with a rank model");
 }
 
 }  // namespace h2ulv

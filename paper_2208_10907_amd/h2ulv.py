@@ -39,7 +39,7 @@ EXPORTS = [
     "h2ulv_rankmodel_destroy", "h2ulv_rankmodel_set_params", "h2ulv_rankmodel_get_params",
     "h2ulv_rankmodel_forward", "h2ulv_rankmodel_gradient", "h2ulv_rankmodel_adam_step",
     "h2ulv_rankmodel_train", "h2ulv_get_features", "h2ulv_get_sketch_info",
-    "h2ulv_release_cache", "h2ulv_refine_gmres",
+    "h2ulv_release_cache", "h2ulv_refine_gmres", "h2ulv_gemm_tile_rates",
 ]
 
 NFEAT = 16
@@ -52,7 +52,8 @@ class Params(C.Structure):
         ("diag", C.c_double), ("eta", C.c_double), ("leaf_size", C.c_int32),
         ("rank_cap", C.c_int32), ("tol", C.c_double), ("far_sample", C.c_int32),
         ("precision", C.c_int32), ("verbose", C.c_int32), ("oversample", C.c_int32),
-        ("rank_model", C.c_void_p), ("sketch_seed", C.c_uint64),
+        ("rank_model", C.c_void_p), ("sketch_seed", C.c_uint64), ("fill_in", C.c_int32),
+        ("partition", C.c_int32),
     ]
 
 
@@ -71,6 +72,69 @@ class Stats(C.Structure):
         d["flops"] = (self.flops_fill + self.flops_basis + self.flops_couple + self.flops_rotate
                       + self.flops_elim + self.flops_root)
         return d
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    """h2ulv_allocator: device memory from the caller."""
+    _fields_ = [("ctx", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN)]
+
+
+def make_allocator(alloc, free) -> Allocator:
+    """An h2ulv_allocator from two Python functions: alloc(nbytes, stream) ->
+    device address (0 on failure), free(ptr, stream).  An exception in alloc
+    counts as a failed allocation.  The returned object keeps the callbacks
+    alive; keep it as long as any factor made with it."""
+    def _a(ctx, nbytes, stream):
+        try:
+            return int(alloc(int(nbytes), stream or 0)) or None
+        except Exception:  # noqa: BLE001 - no exception may cross the C boundary
+            return None
+
+    def _f(ctx, ptr, stream):
+        try:
+            free(int(ptr), stream or 0)
+        except Exception:  # noqa: BLE001
+            pass
+
+    a = Allocator(None, ALLOC_FN(_a), FREE_FN(_f))
+    a._refs = (_a, _f, alloc, free)
+    return a
+
+
+_TORCH_ALLOCATOR = None
+
+
+def torch_allocator() -> Allocator:
+    """The torch caching allocator behind the library's device memory:
+    blocks are drawn on (and stream-ordered by) the stream of each call."""
+    global _TORCH_ALLOCATOR
+    if _TORCH_ALLOCATOR is None:
+        import torch
+
+        def alloc(nbytes, stream):
+            return torch.cuda.caching_allocator_alloc(nbytes, stream=stream or None)
+
+        def free(ptr, stream):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        _TORCH_ALLOCATOR = make_allocator(alloc, free)
+    return _TORCH_ALLOCATOR
+
+
+def _allocator(allocator):
+    """'torch' -> the torch caching allocator, None -> the library's own cache,
+    or an Allocator."""
+    if allocator is None:
+        return None
+    if isinstance(allocator, str):
+        if allocator != "torch":
+            raise ValueError(f"unknown allocator {allocator!r}")
+        return torch_allocator()
+    return allocator
 
 
 class KernelProfile(C.Structure):
@@ -100,8 +164,9 @@ def lib() -> C.CDLL:
     P = C.POINTER
     sig = {
         "h2ulv_params_default": (i32, [P(Params)]),
-        "h2ulv_factorize": (i32, [vp, i64, P(Params), vp, P(vp)]),
-        "h2ulv_factorize_batch": (i32, [i32, P(vp), P(i64), P(Params), vp, P(vp)]),
+        "h2ulv_factorize": (i32, [vp, i64, P(Params), P(Allocator), vp, P(vp)]),
+        "h2ulv_factorize_batch": (i32, [i32, P(vp), P(i64), P(Params), P(Allocator), vp,
+                                        P(vp)]),
         "h2ulv_solve": (i32, [vp, vp, i32, i64, vp]),
         "h2ulv_matvec_exact": (i32, [vp, vp, i64, vp, i64, i32, vp]),
         "h2ulv_refine": (i32, [vp, vp, i64, vp, i64, i32, dbl, i32, P(i32), P(dbl), vp]),
@@ -133,6 +198,7 @@ def lib() -> C.CDLL:
         "h2ulv_get_features": (i32, [vp, i32, vp, vp]),
         "h2ulv_get_sketch_info": (i32, [vp, i32, vp, vp, vp]),
         "h2ulv_release_cache": (i32, []),
+        "h2ulv_gemm_tile_rates": (i32, [P(dbl)]),
         "h2ulv_refine_gmres": (i32, [vp, vp, i64, vp, i64, i32, dbl, i32, i32, P(i32), P(dbl),
                                      vp]),
     }
@@ -152,13 +218,15 @@ def _check(status: int) -> None:
 
 def make_params(kernel=LAPLACE, alpha=0.0, diag=1e3, eta=1.0, leaf=256, tol=1e-8,
                 rank_cap=0, far_sample=32, precision=FP64, verbose=0, rank_model=None,
-                sketch_seed=0, oversample=8) -> Params:
+                sketch_seed=0, oversample=8, fill_in=True, partition="kd") -> Params:
     p = Params()
     _check(lib().h2ulv_params_default(C.byref(p)))
     p.kernel, p.alpha, p.diag, p.eta = int(kernel), float(alpha), float(diag), float(eta)
     p.leaf_size, p.rank_cap, p.tol = int(leaf), int(rank_cap), float(tol)
     p.far_sample, p.precision, p.verbose = int(far_sample), int(precision), int(verbose)
     p.oversample, p.sketch_seed = int(oversample), int(sketch_seed)
+    p.fill_in = 1 if fill_in else 0
+    p.partition = {"kd": 0, "kmeans": 1}[partition]
     p.rank_model = rank_model._h.value if rank_model is not None else None
     p._model_ref = rank_model  # keeps the model alive as long as the parameters
     return p
@@ -256,9 +324,10 @@ def _dev_points(points):
 class Factor:
     """Owns one h2ulv_factor handle."""
 
-    def __init__(self, handle: int, pts):
+    def __init__(self, handle: int, pts, allocator=None):
         self._h = C.c_void_p(handle)
         self._pts = pts
+        self._alloc = allocator  # must outlive the handle
         self.n = int(pts.shape[0])
 
     def __del__(self):
@@ -391,26 +460,34 @@ def release_cache() -> None:
     _check(lib().h2ulv_release_cache())
 
 
-def factorize(points, params: Params | None = None, stream=None, **kw) -> Factor:
-    """Factorize the kernel matrix of `points` (N x 3) on the current GPU."""
+def factorize(points, params: Params | None = None, stream=None, allocator="torch",
+              **kw) -> Factor:
+    """Factorize the kernel matrix of `points` (N x 3) on the current GPU.
+    allocator: 'torch' (the torch caching allocator supplies the device memory),
+    None (the library's own caching allocator) or an Allocator."""
     if params is None:
         params = make_params(**kw)
     pts = _dev_points(points)
+    al = _allocator(allocator)
     h = C.c_void_p()
     _check(lib().h2ulv_factorize(C.c_void_p(pts.data_ptr()), pts.shape[0], C.byref(params),
-                                 _stream(stream), C.byref(h)))
-    return Factor(h.value, pts)
+                                 C.byref(al) if al is not None else None, _stream(stream),
+                                 C.byref(h)))
+    return Factor(h.value, pts, al)
 
 
-def factorize_batch(points_list, params: Params, stream=None) -> list:
+def factorize_batch(points_list, params: Params, stream=None, allocator="torch") -> list:
     """Factorize several independent problems with shared batched launches."""
     pts = [_dev_points(p) for p in points_list]
     n = len(pts)
+    al = _allocator(allocator)
     ptrs = (C.c_void_p * n)(*[p.data_ptr() for p in pts])
     ns = (C.c_int64 * n)(*[p.shape[0] for p in pts])
     hs = (C.c_void_p * n)()
-    _check(lib().h2ulv_factorize_batch(n, ptrs, ns, C.byref(params), _stream(stream), hs))
-    return [Factor(hs[i], pts[i]) for i in range(n)]
+    _check(lib().h2ulv_factorize_batch(n, ptrs, ns, C.byref(params),
+                                       C.byref(al) if al is not None else None,
+                                       _stream(stream), hs))
+    return [Factor(hs[i], pts[i], al) for i in range(n)]
 
 
 class Structure:
@@ -466,6 +543,15 @@ class Structure:
 def profile_enable(on: bool = True) -> None:
     """Start (or stop) recording per-kernel launch times with HIP events."""
     _check(lib().h2ulv_profile_enable(1 if on else 0))
+
+
+def gemm_tile_rates() -> dict:
+    """Autotuned full-tile rates (TFLOP/s) of the GEMM tile shapes on the current
+    device (0 where not measured yet)."""
+    out = (C.c_double * 6)()
+    _check(lib().h2ulv_gemm_tile_rates(out))
+    names = ["f64_64x64", "f64_64x128", "f64_128x64", "f64_128x128", "f32_64x64", "f32_128x128"]
+    return {n: round(float(v), 2) for n, v in zip(names, out)}
 
 
 def profile_read() -> dict:

@@ -41,18 +41,22 @@ def test_params_default(lib):
 def test_invalid_arguments_rejected_before_device_work(lib):
     p = H.make_params(leaf=64)
     out = C.c_void_p()
-    assert lib.h2ulv_factorize(None, 10, C.byref(p), None, C.byref(out)) == H.ERR_INVALID_ARG
+    assert lib.h2ulv_factorize(None, 10, C.byref(p), None, None, C.byref(out)) == H.ERR_INVALID_ARG
     assert out.value is None
     for field, val in (("leaf_size", 1), ("eta", -1.0), ("tol", float("nan")), ("rank_cap", -1),
                        ("kernel", 9), ("far_sample", -3), ("precision", 5)):
         q = H.make_params(leaf=64)
         setattr(q, field, val)
         dummy = C.c_void_p(16)  # never dereferenced: validation fails first
-        assert lib.h2ulv_factorize(dummy, 10, C.byref(q), None, C.byref(out)) == H.ERR_INVALID_ARG
+        assert lib.h2ulv_factorize(dummy, 10, C.byref(q), None, None, C.byref(out)) == H.ERR_INVALID_ARG
         assert "must" in lib.h2ulv_last_error().decode() or "unknown" in lib.h2ulv_last_error().decode()
     bad = H.make_params(leaf=64)
     bad.struct_size = 4
-    assert lib.h2ulv_factorize(C.c_void_p(16), 10, C.byref(bad), None, C.byref(out)) == H.ERR_INVALID_ARG
+    assert lib.h2ulv_factorize(C.c_void_p(16), 10, C.byref(bad), None, None, C.byref(out)) == H.ERR_INVALID_ARG
+    # an allocator with a NULL function is refused before any device work
+    half = H.Allocator(None, H.ALLOC_FN(lambda c, n, s: None), H.FREE_FN())
+    assert lib.h2ulv_factorize(C.c_void_p(16), 10, C.byref(p), C.byref(half), None,
+                               C.byref(out)) == H.ERR_INVALID_ARG
     assert lib.h2ulv_solve(None, None, 1, 1, None) == H.ERR_INVALID_ARG
     assert lib.h2ulv_refine(None, None, 1, None, 1, 1, 1e-10, 5, None, None, None) == H.ERR_INVALID_ARG
     assert lib.h2ulv_status_string(H.ERR_SINGULAR) == b"singular block"
@@ -67,15 +71,18 @@ def test_structure_rejects_nan_points():
 
 
 @pytest.mark.parametrize("case", [
-    ("cube", 2048, 64, 1.0), ("cube-ragged", 3001, 64, 1.0), ("sphere", 5000, 100, 1.0),
-    ("line", 64, 16, 1.5), ("hss", 1024, 64, 0.0), ("boxes", 9000, 128, 1.0)])
+    ("cube", 2048, 64, 1.0, "kd"), ("cube-ragged", 3001, 64, 1.0, "kd"),
+    ("sphere", 5000, 100, 1.0, "kd"), ("line", 64, 16, 1.5, "kd"), ("hss", 1024, 64, 0.0, "kd"),
+    ("boxes", 9000, 128, 1.0, "kd"), ("ellipsoids", 6000, 64, 1.0, "kmeans"),
+    ("sphere", 5000, 100, 1.0, "kmeans"), ("cube-ragged", 3001, 64, 1.0, "kmeans")])
 def test_structure_identical_to_oracle(case):
-    name, n, leaf, eta = case
+    name, n, leaf, eta, part = case
     X = {"cube": lambda: W.cube_points(n, 1), "cube-ragged": lambda: W.cube_points(n, 2),
          "sphere": lambda: W.sphere_points(n, 2), "line": lambda: W.line_points(n),
-         "hss": lambda: W.cube_points(n, 5), "boxes": lambda: W.box_problem(3)[:n]}[name]()
-    s = H.Structure(X, H.make_params(leaf=leaf, eta=eta))
-    t = O.build_tree(X, leaf)
+         "hss": lambda: W.cube_points(n, 5), "boxes": lambda: W.box_problem(3)[:n],
+         "ellipsoids": lambda: W.ellipsoid_points(n, 7)}[name]()
+    s = H.Structure(X, H.make_params(leaf=leaf, eta=eta, partition=part))
+    t = O.build_tree(X, leaf, part)
     near, far = O.build_lists(t, eta)
     assert s.L == t.L
     assert np.array_equal(s.perm(), t.perm)
@@ -84,3 +91,18 @@ def test_structure_identical_to_oracle(case):
         assert n2 == near[lev] and f2 == far[lev]
         c, r = s.geometry(lev)
         assert np.array_equal(c, t.centre[lev]) and np.array_equal(r, t.radius[lev])
+
+
+def test_build_rejects_kernels_with_scratch():
+    """The build fails when any kernel's resource report shows scratch memory
+    per lane (register spills, stack arrays); the parser finds exactly those."""
+    from paper_2208_10907_amd import build as B
+    txt = "\n".join([
+        "a.hip:1:1: remark: Function Name: _Zfoo [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:1:1: remark:     VGPRs: 250 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:1:1: remark:     ScratchSize [bytes/lane]: 16 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark: Function Name: _Zbar [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]",
+    ])
+    assert B.scratch_users(txt) == [("_Zfoo", 16)]
+    assert "-Rpass-analysis=kernel-resource-usage" in B.HIP_FLAGS

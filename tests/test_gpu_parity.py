@@ -249,12 +249,17 @@ def test_sphere_65536_sampled():
     assert rel < 0.1  # rank cap 128 limits one solve's accuracy; refinement recovers it
     x2, it, rr = fg.refine(b, rtol=1e-10, max_iter=30)
     assert rr <= 1e-10
+    # the refined residual with the oracle's matvec (two of the 16 columns)
+    bn = b.cpu().numpy()[:, :2]
+    r = bn - O.matvec_exact(prob.points, x2.cpu().numpy()[:, :2], O.params_from_problem(prob))
+    assert np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(bn, axis=0)) < 2e-10
 
 
 def test_mixed_precision_refines_to_fp64_accuracy():
-    """FP32 fill-in products, couplings, rotations and Schur updates with FP64
-    QR/ID, inverses, solve and residual: one solve is close to the FP64
-    factor's, and refinement with the exact FP64 matvec reaches 1e-10."""
+    """FP32 couplings, rotations and Schur updates with FP64 fill-in products
+    (no rank cap), QR/ID, inverses, solve and residual: one solve is close to the
+    FP64 factor's, and refinement with the exact FP64 matvec reaches 1e-10,
+    rechecked with the oracle's matvec."""
     X = W.cube_points(6000, 21)
     prob_kw = dict(leaf=128, tol=1e-6, far_sample=32)
     f64 = H.factorize(X, H.make_params(**prob_kw))
@@ -267,5 +272,165 @@ def test_mixed_precision_refines_to_fp64_accuracy():
     y64, it64, r64 = f64.refine(b, rtol=1e-10, max_iter=40)
     y32, it32, r32 = f32.refine(b, rtol=1e-10, max_iter=40)
     assert r64 <= 1e-10 and r32 <= 1e-10
+    bn = b.cpu().numpy()
+    r = bn - O.matvec_exact(X, y32.cpu().numpy(), O.Params(**prob_kw))
+    assert np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(bn, axis=0)) < 2e-10
     assert (torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64)).item() < 1e-8
     assert it32 <= it64 + 3
+
+
+def test_batch_matches_oracle_per_problem():
+    """Several problems of different tree depths factorized in one batched pass
+    (shared launches per height) each match the oracle run on its own: ranks and
+    skeletons identical, solution within 1e-10 (Yukawa kernel, leaf 128, tol 1e-7,
+    rank cap 64 as the batched workload)."""
+    sizes = (900, 1700, 3300, 5000)  # 3, 4, 5 and 6 levels
+    pts = [W.aspect_box_points(n, 3200 + n) for n in sizes]
+    op = O.Params(kernel=O.YUKAWA, alpha=0.5, leaf=128, tol=1e-7, rank_cap=64, far_sample=32)
+    fb = H.factorize_batch(pts, _params(op))
+    depths = set()
+    for X, fg in zip(pts, fb):
+        fo = O.factorize(X, op)
+        depths.add(fo.tree.L)
+        _compare_structure(fg, fo)
+        b = W.gaussian_rhs(X.shape[0], 1, 9)
+        xo = O.solve(fo, b)
+        xg = fg.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+        assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < X_TOL
+    assert len(depths) == len(sizes)
+
+
+def test_panels_beyond_4096_rows():
+    """Leaf boxes of 4200 points: the LU of the diagonal blocks (fill-in step)
+    and the Householder panels of the tall QR run their >4096-row kernels; the
+    result still matches the oracle."""
+    X = W.cube_points(8400, 31)
+    op = O.Params(leaf=4200, tol=1e-6, far_sample=0)
+    fg, fo = _parity(X, op, check_basis=False)
+    m, k = fg.ranks(1)
+    assert m.min() > 4096
+
+
+def test_capped_mixed_precision_against_oracle_residual():
+    """Mixed precision with a rank cap (FP32 fill-in products as well): refinement
+    with the exact FP64 matvec reaches 1e-10, checked with the oracle's matvec,
+    and the solution agrees with the refined FP64 one."""
+    X = W.cube_points(6000, 22)
+    kw = dict(leaf=128, tol=1e-6, rank_cap=64, far_sample=32)
+    op = O.Params(**kw)
+    f64 = H.factorize(X, H.make_params(**kw))
+    f32 = H.factorize(X, H.make_params(precision=H.MIXED, **kw))
+    b = torch.tensor(W.gaussian_rhs(6000, 2, 5), device="cuda")
+    y64, _, r64 = f64.refine_gmres(b, rtol=1e-10, max_iter=60)
+    y32, _, r32 = f32.refine_gmres(b, rtol=1e-10, max_iter=60)
+    assert r64 <= 1e-10 and r32 <= 1e-10
+    bn = b.cpu().numpy()
+    for y in (y32, y64):
+        r = bn - O.matvec_exact(X, y.cpu().numpy(), op)
+        assert np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(bn, axis=0)) < 2e-10
+    assert (torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64)).item() < 1e-8
+
+
+def test_tolerance_one_eliminates_every_box():
+    """tol = 1: no pivot exceeds |R_00| strictly, so k = 0 in every leaf box, the
+    boxes above the leaves are empty (m = 0) and the root is 0 x 0; the result is
+    the leaf-level elimination alone, identical to the oracle's."""
+    X = W.cube_points(2000, 33)
+    op = O.Params(leaf=64, tol=1.0, far_sample=32)
+    fg, fo = _parity(X, op, check_basis=False)
+    L = fo.tree.L
+    m, k = fg.ranks(L)
+    assert k.max() == 0 and m.min() > 0
+    for lev in range(L - 1, 0, -1):
+        m, k = fg.ranks(lev)
+        assert m.max() == 0 and k.max() == 0
+    assert fg.stats()["root_size"] == 0
+
+
+def test_caller_allocator_supplies_all_factor_memory():
+    """h2ulv_allocator: every device block of the factorization and of later
+    calls comes from the caller (here torch's caching allocator, counted) and
+    goes back to it by h2ulv_destroy; results equal those with the library's
+    own cache.  A callback that returns NULL gives OOM at the first allocation,
+    before any device work."""
+    X = W.cube_points(3000, 41)
+    p = H.make_params(leaf=64, tol=1e-7, rank_cap=32)
+    live, calls = {}, {"alloc": 0, "free": 0}
+
+    def alloc(nbytes, stream):
+        ptr = torch.cuda.caching_allocator_alloc(nbytes, stream=stream or None)
+        live[ptr] = nbytes
+        calls["alloc"] += 1
+        return ptr
+
+    def free(ptr, stream):
+        assert ptr in live
+        del live[ptr]
+        calls["free"] += 1
+        torch.cuda.caching_allocator_delete(ptr)
+
+    al = H.make_allocator(alloc, free)
+    b = torch.tensor(W.gaussian_rhs(3000, 2, 3), device="cuda")
+    f = H.factorize(X, p, allocator=al)
+    held = len(live)
+    assert held > 0 and calls["alloc"] > held  # temporaries came and went
+    x = f.solve(b)
+    xr, _, rr = f.refine_gmres(b, rtol=1e-10)
+    assert rr <= 1e-10 and len(live) == held  # later calls' temporaries given back
+    g = H.factorize(X, p, allocator=None)
+    assert torch.equal(x, g.solve(b))
+    del f
+    torch.cuda.synchronize()
+    assert not live and calls["alloc"] == calls["free"]
+    refused = {"n": 0}
+
+    def no_memory(nbytes, stream):
+        refused["n"] += 1
+        return 0
+
+    with pytest.raises(H.H2ULVError) as e:
+        H.factorize(X, p, allocator=H.make_allocator(no_memory, lambda ptr, s: None))
+    assert e.value.status == H.ERR_OOM
+    assert refused["n"] == 1
+
+
+def test_no_fill_in_ablation_matches_oracle():
+    """The ablation with bases from the low-rank blocks alone (fill_in = 0)
+    matches the oracle run the same way (ranks, skeletons, solution, flops)."""
+    X = W.cube_points(3000, 44)
+    op = O.Params(leaf=64, tol=1e-6, far_sample=32, fill_in=False)
+    fg = H.factorize(X, _params(op, fill_in=False))
+    fo = O.factorize(X, op)
+    _compare_structure(fg, fo)
+    b = W.gaussian_rhs(3000, 1, 2)
+    xo = O.solve(fo, b)
+    xg = fg.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < X_TOL
+    assert abs(fg.stats()["flops"] - O.total_flops(fo)) <= 1e-9 * O.total_flops(fo)
+
+
+def test_gemm_tile_autotuner():
+    """The grouped GEMM's tile shapes are chosen from rates measured on the
+    device the first time a precision is used; the rates are plausible for the
+    matrix cores (below the FP64 / FP32 peaks of 78.6 / 157.3 TFLOP/s)."""
+    X = W.cube_points(3000, 45)
+    H.factorize(X, H.make_params(leaf=64, tol=1e-7, rank_cap=32, precision=H.MIXED))
+    r = H.gemm_tile_rates()
+    f64 = [r[k] for k in r if k.startswith("f64")]
+    f32 = [r[k] for k in r if k.startswith("f32")]
+    assert all(2.0 < v < 78.6 for v in f64), r
+    assert all(4.0 < v < 157.3 for v in f32), r
+
+
+def test_kmeans_partition_matches_oracle():
+    """The balanced 2-means cluster tree (the k-means partition of Sec. V) on a
+    surface point set: tree, ranks, skeletons and solution match the oracle."""
+    X = W.ellipsoid_points(4000, 8)
+    op = O.Params(leaf=64, tol=1e-6, rank_cap=32, far_sample=32, partition="kmeans")
+    fg = H.factorize(X, _params(op, partition="kmeans"))
+    fo = O.factorize(X, op)
+    _compare_structure(fg, fo)
+    b = W.gaussian_rhs(4000, 2, 6)
+    xo = O.solve(fo, b)
+    xg = fg.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < X_TOL

@@ -143,20 +143,23 @@ def _constant_model(k):
     return R.pack(parts).astype(np.float32)
 
 
-@pytest.mark.parametrize("n,leaf,tol,oversample,model", [
-    (4096, 128, 1e-6, 8, "trained"),   # sketched leaves (m = 128) and upper levels
-    (4096, 128, 1e-8, 8, "trained"),   # sketched boxes with m > 512 (multi-workgroup QR)
-    (3000, 64, 1e-6, 0, "constant"),   # k-hat = 10, no oversampling: every first
-                                       # sketch is exhausted; full-width retries,
-                                       # then the full QR where those fail too
+@pytest.mark.parametrize("n,leaf,tol,oversample,model,cap", [
+    (4096, 128, 1e-6, 8, "trained", 0),   # sketched leaves (m = 128) and upper levels
+    (4096, 128, 1e-8, 8, "trained", 0),   # sketched boxes with m > 512 (multi-workgroup QR)
+    (3000, 64, 1e-6, 0, "constant", 0),   # k-hat = 10, no oversampling: every first
+                                          # sketch is exhausted; full-width retries,
+                                          # then the full QR where those fail too
+    (4096, 128, 1e-6, 8, "trained", 32),  # rank cap 32: sketches sized for min(k-hat,
+                                          # cap), accepted at k = cap without the tol test
 ])
-def test_predicted_mode_parity(n, leaf, tol, oversample, model):
-    base = O.Params(leaf=leaf, tol=tol)
+def test_predicted_mode_parity(n, leaf, tol, oversample, model, cap):
+    base = O.Params(leaf=leaf, tol=tol, rank_cap=cap)
     if model == "trained":
         th = _oracle_model(W.cube_points(n, 900 + n), base)
     else:
         th = _constant_model(10)
-    op = O.Params(leaf=leaf, tol=tol, rank_model=th, sketch_seed=77, oversample=oversample)
+    op = O.Params(leaf=leaf, tol=tol, rank_cap=cap, rank_model=th, sketch_seed=77,
+                  oversample=oversample)
     X = W.cube_points(n, 901 + n)
     fo = O.factorize(X, op)
     gm = H.RankModel()
@@ -192,13 +195,21 @@ def test_predicted_mode_parity(n, leaf, tol, oversample, model):
     assert abs(st["flops"] - O.total_flops(fo)) <= 1e-9 * O.total_flops(fo)
     if tol == 1e-8:
         assert max(m_all) > 512
+    if cap:
+        # the capped acceptance is exercised: accepted sketches that stopped at the cap
+        capped = [b for l in fo.levels for b in fo.levels[l] if b.sketch in (1, 3) and b.k == cap]
+        assert len(capped) >= 2
 
 
 def test_trained_model_gain():
     """Train the rank model on the GPU from the ranks of two factorizations of
-    other point sets, then factorize a new one with predicted ranks: the basis
-    step needs far fewer flops, most sketches are accepted, and refinement
-    reaches the same 1e-10 residual."""
+    other point sets (no rank cap), then factorize a new one three ways: the
+    plain full pivoted QR; a control whose constant model predicts k-hat >= m, so
+    every box is sketched at full width (m - 8 columns: the gain of sketching
+    alone); and the trained model.  The trained model's sketches are narrower
+    than the control's, so its basis work is much smaller, almost every sketch
+    is accepted, and all three refine to the same 1e-10 residual.  Compared on
+    the flop counts (deterministic); the times are printed, not asserted."""
     mk = lambda seed: W.ellipsoid_points(32768, seed)
     base = H.make_params(leaf=256, tol=1e-6)
     F, T = [], []
@@ -214,12 +225,16 @@ def test_trained_model_gain():
     gm = H.RankModel(seed=1)
     loss = gm.train(torch.tensor(F, device="cuda"), torch.tensor(T, device="cuda"), 2000, 3e-3)
     assert loss < 0.05
+    ctl = H.RankModel(seed=1)
+    ctl.set_params(_constant_model(1 << 20))
     X = mk(503)
     b = torch.tensor(W.gaussian_rhs(X.shape[0], 1, 9), device="cuda")
     out = {}
     for name, prm in (("plain", base),
-                      ("predicted", H.make_params(leaf=256, tol=1e-6, rank_model=gm,
-                                                  sketch_seed=5))):
+                      ("control", H.make_params(leaf=256, tol=1e-6, rank_model=ctl,
+                                                sketch_seed=5)),
+                      ("trained", H.make_params(leaf=256, tol=1e-6, rank_model=gm,
+                                                sketch_seed=5))):
         f = H.factorize(X, prm)  # warm
         del f
         torch.cuda.synchronize()
@@ -227,19 +242,24 @@ def test_trained_model_gain():
         f = H.factorize(X, prm)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        x, it, rel = f.refine(b, rtol=1e-10, max_iter=40)
+        x, it, rel = f.refine_gmres(b, rtol=1e-10, max_iter=200, restart=120)
         st = f.stats()
-        acc = rej = 0
+        acc = rej = wide = boxes = 0
         for lev in range(1, f.levels() + 1):
-            s = f.sketch_info(lev)[2]
-            acc += int((s == 1).sum())
-            rej += int((s == 2).sum())
-        out[name] = dict(time=dt, basis=st["flops_basis"], iters=it, rel=rel, acc=acc, rej=rej)
+            kh, ell, s_ = f.sketch_info(lev)
+            m, _ = f.ranks(lev)
+            acc += int(((s_ == 1) | (s_ == 3)).sum())
+            rej += int((s_ == 2).sum())
+            wide += int(((s_ != 0) & (ell == m - 8)).sum())
+            boxes += len(s_)
+        out[name] = dict(time=dt, basis=st["flops_basis"], flops=st["flops"], iters=it, rel=rel,
+                         acc=acc, rej=rej, full_width=wide, boxes=boxes)
         del f
     print("rank model gain:", out)
-    p, q = out["plain"], out["predicted"]
-    assert q["rel"] <= 1e-10 and p["rel"] <= 1e-10
+    p, c, q = out["plain"], out["control"], out["trained"]
+    assert max(p["rel"], c["rel"], q["rel"]) <= 1e-10
+    assert c["full_width"] >= c["acc"] > 0        # the control sketches at full width
     assert q["acc"] > 4 * max(q["rej"], 1)
-    assert q["basis"] < 1.05 * p["basis"]
-    assert q["time"] < 0.9 * p["time"]
-    assert q["iters"] <= p["iters"] + 3
+    assert q["full_width"] < q["acc"]             # the trained model sizes its sketches
+    assert q["basis"] < c["basis"] and q["flops"] < c["flops"] < p["flops"]
+    assert q["iters"] <= p["iters"] + 5

@@ -319,3 +319,26 @@ def test_dropped_quadrants_fall_with_tolerance():
     for a, b in zip(mx, mx[1:]):
         assert b < a, mx
     assert agg[-1] < 1e-4 and mx[-1] < 1e-3
+
+
+def test_no_fill_in_ablation_loses_accuracy():
+    """Sec. III-A/III-C: the shared basis must contain the fill-ins, otherwise the
+    fill-ins that the factorization produces cannot be eliminated without
+    updating the basis.  The ablation with bases from the low-rank blocks alone
+    (F = 0) is far less accurate at the same tolerance (measured: 2.6e-2 against
+    5.4e-5 at N=2048); with no near blocks at all (eta = 0, the HSS structure)
+    there are no fill-ins and both forms coincide."""
+    X = W.cube_points(2048, 1)
+    b = W.gaussian_rhs(2048, 1, 101)[:, 0]
+    A = O.dense_matrix(X, O.Params())
+    xd = np.linalg.solve(A, b)
+    err = {}
+    for fill in (True, False):
+        f = O.factorize(X, O.Params(leaf=64, tol=1e-6, far_sample=0, fill_in=fill))
+        err[fill] = _rel(O.solve(f, b), xd)
+    assert err[False] > 100 * err[True], err
+    X2 = W.cube_points(600, 13)
+    b2 = W.gaussian_rhs(600, 1, 5)[:, 0]
+    xs = [O.solve(O.factorize(X2, O.Params(leaf=40, tol=1e-6, eta=0.0, far_sample=0,
+                                           fill_in=fill)), b2) for fill in (True, False)]
+    assert np.array_equal(xs[0], xs[1])

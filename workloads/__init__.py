@@ -59,6 +59,15 @@ def box_problem(p: int) -> np.ndarray:
     return rng.random((n, 3)) * sides
 
 
+def aspect_box_points(n: int, seed: int) -> np.ndarray:
+    """N points uniform in an axis-aligned box with sides (1, u1, u2), u ~ U[1, 4],
+    axes shuffled: the batched workload's geometry at a chosen size."""
+    rng = np.random.default_rng(seed)
+    sides = np.array([1.0, rng.uniform(1, 4), rng.uniform(1, 4)])
+    rng.shuffle(sides)
+    return rng.random((n, 3)) * sides
+
+
 def ellipsoid_points(n: int, seed: int, n_ell: int = 12) -> np.ndarray:
     """Union of n_ell random ellipsoid surfaces: semi-axes U[0.05, 0.5]^3, random
     rotation (QR of a Gaussian, column signs fixed by diag(R) > 0), centres
