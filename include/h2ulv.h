@@ -194,6 +194,23 @@ h2ulv_status h2ulv_solve(const h2ulv_factor* f, double* b, int32_t nrhs, int64_t
 h2ulv_status h2ulv_matvec_exact(const h2ulv_factor* f, const double* x, int64_t ldx,
                                 double* y, int64_t ldy, int32_t nrhs, void* stream);
 
+/*
+ * h2ulv_matvec_exact without any device allocation, for callers that cannot
+ * allocate: code under stream capture, tight serving loops, harnesses that
+ * forbid allocation.  Same arguments, launches, split and summation order as
+ * h2ulv_matvec_exact (the results are identical); it neither allocates nor
+ * synchronises the stream.  The partial sums of the split sources (n >= 65536)
+ * live in a file-scope device array of 8 Mi doubles (64 MiB) that each GPU the
+ * library runs on holds until the process ends:
+ * n * min(nrhs, 8) * splits doubles must fit, splits = min(8, 4096 / ceil(n /
+ * 512)), which holds for every n < 65536 (no partial sums) and every n <=
+ * 131072; larger requests return INVALID_ARG before any launch.  All calls on
+ * one GPU share that array: calls whose executions overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ * Errors: INVALID_ARG (as h2ulv_matvec_exact, or too large), HIP.
+ */
+h2ulv_status h2ulv_matvec_exact_noalloc(const h2ulv_factor* f, const double* x, int64_t ldx,
+                                        double* y, int64_t ldy, int32_t nrhs, void* stream);
 
 /*
  * Iterative refinement with the exact float64 matvec:

@@ -29,6 +29,7 @@ SOURCES = [
     # MFMA accumulators in ordinary VGPRs (no copies between register files in the K loop)
     ("h2ulv_kernels.hip", ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]),
     ("h2ulv_learned.hip", []),
+    ("h2ulv_noalloc.hip", []),
     ("h2ulv_rankmodel.cpp", ["-x", "hip"]),
     ("h2ulv_dense.cpp", ["-x", "hip"]),
     ("h2ulv_factor.cpp", ["-x", "hip"]),

@@ -537,6 +537,15 @@ h2ulv_status h2ulv_matvec_exact(const h2ulv_factor* f, const double* x, int64_t 
   });
 }
 
+h2ulv_status h2ulv_matvec_exact_noalloc(const h2ulv_factor* f, const double* x, int64_t ldx,
+                                        double* y, int64_t ldy, int32_t nrhs, void* stream) {
+  if (!f || !x || !y || nrhs < 1 || ldx < f->n || ldy < f->n) {
+    g_last_error = "bad matvec arguments";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  return guarded([&] { matvec_noalloc(*f, x, ldx, y, ldy, nrhs, (hipStream_t)stream); });
+}
+
 h2ulv_status h2ulv_refine(const h2ulv_factor* f, const double* b, int64_t ldb, double* x,
                           int64_t ldx, int32_t nrhs, double rtol, int32_t max_iter,
                           int32_t* iters, double* relres, void* stream) {

@@ -28,6 +28,10 @@ struct LevelFactor {
 double now_s();
 KernelFn kfn(const h2ulv_params& p);
 
+// Capacity, in doubles, of the per-GPU array that holds the partial sums of
+// the allocation-free exact matvec.
+int64_t matvec_noalloc_capacity();
+
 // Sketch probes and the acceptance slack of the learned-rank basis step.
 constexpr int SKETCH_PROBES = 8;
 constexpr double SKETCH_SLACK = 10.0;
@@ -67,3 +71,12 @@ struct h2ulv_rankmodel {
   h2ulv::DBuf theta, m, v;  // float parameters and Adam moments (device)
   int64_t step = 0;         // Adam steps taken
 };
+
+namespace h2ulv {
+// Exact y = A x like the allocating matvec (same split and summation order),
+// with the partial sums in the per-GPU array; fails with INVALID_ARG when they
+// need more than matvec_noalloc_capacity() doubles.  Allocates nothing and does
+// not synchronise the stream.
+void matvec_noalloc(const h2ulv_factor& F, const double* x, int64_t ldx, double* y, int64_t ldy,
+                    int nrhs, hipStream_t s);
+}  // namespace h2ulv

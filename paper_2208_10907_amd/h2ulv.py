@@ -40,6 +40,7 @@ EXPORTS = [
     "h2ulv_rankmodel_forward", "h2ulv_rankmodel_gradient", "h2ulv_rankmodel_adam_step",
     "h2ulv_rankmodel_train", "h2ulv_get_features", "h2ulv_get_sketch_info",
     "h2ulv_release_cache", "h2ulv_refine_gmres", "h2ulv_gemm_tile_rates",
+    "h2ulv_matvec_exact_noalloc",
 ]
 
 NFEAT = 16
@@ -169,6 +170,7 @@ def lib() -> C.CDLL:
                                         P(vp)]),
         "h2ulv_solve": (i32, [vp, vp, i32, i64, vp]),
         "h2ulv_matvec_exact": (i32, [vp, vp, i64, vp, i64, i32, vp]),
+        "h2ulv_matvec_exact_noalloc": (i32, [vp, vp, i64, vp, i64, i32, vp]),
         "h2ulv_refine": (i32, [vp, vp, i64, vp, i64, i32, dbl, i32, P(i32), P(dbl), vp]),
         "h2ulv_get_stats": (i32, [vp, P(Stats)]),
         "h2ulv_get_levels": (i32, [vp, P(i32)]),
@@ -368,6 +370,15 @@ class Factor:
                                         C.c_void_p(yt.data_ptr()), self.n, xt.shape[0],
                                         _stream(stream)))
         return self._back(vec, yt)
+
+    def matvec_noalloc(self, x, y, stream=None):
+        """y = A x through the allocation-free entry point; x and y are caller-owned
+        column-major device arrays (n x nrhs, Fortran order) and nothing is
+        allocated or synchronised."""
+        _check(lib().h2ulv_matvec_exact_noalloc(self._h, C.c_void_p(x.data_ptr()), x.stride(1),
+                                                C.c_void_p(y.data_ptr()), y.stride(1),
+                                                x.shape[1], _stream(stream)))
+        return y
 
     def refine(self, b, rtol=1e-10, max_iter=20, stream=None, raise_on_fail=True):
         import torch
