@@ -89,6 +89,7 @@ class Params:
     oversample: int = 8        # sketch columns beyond 1.25 x the predicted rank
     fill_in: bool = True       # False: ablation, bases from the far field alone (F = 0)
     partition: str = "kd"      # "kd" median split of the widest axis, "kmeans" 2-means
+    structure: str = "h2"      # "h2" the hierarchy; "blr2" one level of leaves (Sec. II-B)
 
 
 def params_from_problem(prob, **kw) -> Params:
@@ -109,6 +110,8 @@ def check_params(X: np.ndarray, p: Params) -> None:
         raise OracleError(ERR_INVALID_ARG, "unknown kernel or bad diagonal")
     if p.oversample < 0:
         raise OracleError(ERR_INVALID_ARG, "oversample must be >= 0")
+    if p.structure not in ("h2", "blr2"):
+        raise OracleError(ERR_INVALID_ARG, "structure must be h2 or blr2")
     if p.partition not in ("kd", "kmeans"):
         raise OracleError(ERR_INVALID_ARG, "partition must be kd or kmeans")
     if not p.fill_in and p.rank_model is not None:
@@ -273,6 +276,26 @@ def build_lists(tree: Tree, eta: float):
                             nl[i].append(j)
         near.append([sorted(x) for x in nl])
         far.append([sorted(x) for x in fl])
+    return near, far
+
+
+def build_flat_lists(tree: Tree, eta: float):
+    """Lists of the flat BLR^2 structure (Sec. II-B): one level of boxes, the
+    leaves of the tree, every pair classified directly by the admissibility
+    rule (no hierarchy).  Returned in the per-level layout of build_lists, with
+    only the leaf level filled in."""
+    L = tree.L
+    nb = 1 << L
+    c, r = tree.centre[L], tree.radius[L]
+    nl = [[] for _ in range(nb)]
+    fl = [[] for _ in range(nb)]
+    for i in range(nb):
+        for j in range(nb):
+            d = c[i] - c[j]
+            dist = math.sqrt(float(d[0]) * d[0] + float(d[1]) * d[1] + float(d[2]) * d[2])
+            (fl if dist > eta * (float(r[i]) + float(r[j])) else nl)[i].append(j)
+    near = [[[0]]] + [[[] for _ in range(1 << lev)] for lev in range(1, L)] + [nl]
+    far = [[[]]] + [[[] for _ in range(1 << lev)] for lev in range(1, L)] + [fl]
     return near, far
 
 
@@ -561,7 +584,10 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
       (e) rotation S_ii = U_i^T D_ii U_i, near S^SS_ij = U^S_i^T D_ij U^S_j (Eq. rs)
       (f) LU of S^RR, triangular solves, Schur update of S^SS    (Eq. lu ff.)
       merge children's S^SS into the parent's dense blocks       (Sec. II-C)
-    then the root LU (Eq. BLR2final).
+    then the root LU (Eq. BLR2final).  With ``structure="blr2"`` (the flat BLR^2
+    of Sec. II-B) only the leaf level is factorized, with lists that classify
+    every pair of leaves directly, and the root is the dense block of all leaves'
+    S^SS blocks (Eq. BLR2final).
 
     ``level_stop``/``boxes``: stop after the basis step of that level, for the
     given boxes only (used to time or check a sample of one level).
@@ -575,7 +601,8 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
     X = np.asarray(X, dtype=np.float64)
     check_params(X, p)
     tree = build_tree(X, p.leaf, p.partition)
-    near, far = build_lists(tree, p.eta)
+    flat = p.structure == "blr2"
+    near, far = build_flat_lists(tree, p.eta) if flat else build_lists(tree, p.eta)
     fac = Factor(X, p, tree, near, far)
     L = tree.L
     flops = {"fill": 0.0, "basis": 0.0, "rotate": 0.0, "couple": 0.0, "elim": 0.0, "root": 0.0}
@@ -596,7 +623,7 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
     prev_bf = None
     That = None                    # per box: list of triangular blocks (upper levels)
     Sblk = None                    # previous level's S^SS blocks: dict (c, d) -> array
-    for lev in range(L, 0, -1):
+    for lev in range(L, (L - 1) if flat else 0, -1):
         nb = 1 << lev
         Pl = P[lev]
         m = [len(Pl[i]) for i in range(nb)]
@@ -793,12 +820,13 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
         fac.levels[lev] = bf
         prev_bf = bf
         # merge: next level's candidate rows and T-hat
-        if lev > 1:
+        if lev > 1 and not flat:
             P[lev - 1] = [np.concatenate([bf[2 * q].sk, bf[2 * q + 1].sk]) for q in range(nb // 2)]
             That = [[bf[2 * q].T, bf[2 * q + 1].T] for q in range(nb // 2)]
         Sblk = Snew
-    # root
-    D0 = np.block([[Sblk[0, 0], Sblk[0, 1]], [Sblk[1, 0], Sblk[1, 1]]])
+    # root: the two children of the root box, or (flat) every leaf
+    kids = list(range(1 << L)) if flat else [0, 1]
+    D0 = np.block([[Sblk[a, b] for b in kids] for a in kids])
     fac.m_root = D0.shape[0]
     fac.root_lu = lu(D0) if fac.m_root > 0 else (D0, np.zeros(0, dtype=np.int32))
     flops["root"] += 2.0 / 3.0 * fac.m_root ** 3
@@ -824,10 +852,12 @@ def solve(fac: Factor, B: np.ndarray) -> np.ndarray:
         out = np.empty_like(x)
         out[tree.perm] = x
         return out.reshape(B.shape)
-    # forward
+    # forward (the flat BLR^2 structure has the leaf level only, and its root
+    # gathers the skeleton parts of every leaf)
+    flat = fac.params.structure == "blr2"
     rhs = [bt[tree.start[L][i]:tree.end[L][i]] for i in range(1 << L)]
     saved = {}
-    for lev in range(L, 0, -1):
+    for lev in range(L, (L - 1) if flat else 0, -1):
         bf = fac.levels[lev]
         cs = []
         for i, f in enumerate(bf):
@@ -841,12 +871,29 @@ def solve(fac: Factor, B: np.ndarray) -> np.ndarray:
                     cS -= f.LSR @ yR
             saved[lev, i] = yR
             cs.append(cS)
-        rhs = [np.concatenate([cs[2 * q], cs[2 * q + 1]]) for q in range(len(bf) // 2)]
+        if flat:
+            rhs = [np.concatenate(cs)]
+        else:
+            rhs = [np.concatenate([cs[2 * q], cs[2 * q + 1]]) for q in range(len(bf) // 2)]
     b0 = rhs[0]
     x0 = sla.lu_solve(fac.root_lu, b0, check_finite=False) if fac.m_root else b0
     xs = [x0]
+    if flat:
+        # skeleton parts of every leaf from the root, in leaf order
+        parts, off = [], 0
+        for f in fac.levels[L]:
+            parts.append(x0[off:off + f.k])
+            off += f.k
+        nxt = []
+        for i, (f, xS) in enumerate(zip(fac.levels[L], parts)):
+            if f.m - f.k > 0:
+                xR = upper_solve(f.lu, saved[L, i] - f.URS @ xS)
+                nxt.append(f.U @ np.concatenate([xS, xR]))
+            else:
+                nxt.append(f.U @ xS)
+        xs = nxt
     # backward
-    for lev in range(1, L + 1):
+    for lev in ([] if flat else range(1, L + 1)):
         bf = fac.levels[lev]
         nxt = []
         for q in range(len(bf) // 2):
@@ -902,9 +949,11 @@ def assemble_dense(fac: Factor) -> np.ndarray:
     """The matrix A~ that the factorization represents exactly, assembled densely
     in the original point order: at each level
       A~_l = U_l [[blkdiag S^RR, blkdiag S^RS], [blkdiag S^SR, A~_{l-1} + blkdiag S^SR S^RR^-1 S^RS]] U_l^T
-    (rows of each box ordered [S; R]).  Small N only."""
+    (rows of each box ordered [S; R]); the flat BLR^2 structure has the leaf
+    level alone, its root holding every leaf's skeleton.  Small N only."""
     tree = fac.tree
     L = tree.L
+    flat = fac.params.structure == "blr2"
     lu_, lp = fac.root_lu
     if fac.m_root:
         Lm = np.tril(lu_, -1) + np.eye(fac.m_root)
@@ -912,7 +961,7 @@ def assemble_dense(fac: Factor) -> np.ndarray:
         A = apply_pinv_inverse(lp, Lm @ Um)
     else:
         A = np.zeros((0, 0))
-    for lev in range(1, L + 1):
+    for lev in ([L] if flat else range(1, L + 1)):
         bf = fac.levels[lev]
         ks = [f.k for f in bf]
         ms = [f.m for f in bf]

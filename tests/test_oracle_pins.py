@@ -342,3 +342,48 @@ def test_no_fill_in_ablation_loses_accuracy():
     xs = [O.solve(O.factorize(X2, O.Params(leaf=40, tol=1e-6, eta=0.0, far_sample=0,
                                            fill_in=fill)), b2) for fill in (True, False)]
     assert np.array_equal(xs[0], xs[1])
+
+
+# --- flat BLR^2 structure (Sec. II-B) -----------------------------------------
+def test_blr2_full_rank_equals_dense_lu():
+    """Flat BLR^2 at tol = 0: nothing is truncated, the root holds every leaf's
+    skeleton, and the solution is the dense LU solution."""
+    X = W.cube_points(700, 8)
+    p = O.Params(leaf=40, tol=0.0, far_sample=0, structure="blr2")
+    f = O.factorize(X, p)
+    b = W.gaussian_rhs(700, 2, 3)
+    assert _rel(O.solve(f, b), np.linalg.solve(O.dense_matrix(X, p), b)) < 1e-11
+    assert list(f.levels) == [f.tree.L]
+    assert f.m_root == sum(bx.k for bx in f.levels[f.tree.L])
+
+
+def test_blr2_one_level_tree_coincides_with_h2():
+    """With a tree of depth 1 the hierarchy has a single level below the root, so
+    the flat and hierarchical factorizations perform the same steps."""
+    X = W.cube_points(120, 5)
+    b = W.gaussian_rhs(120, 1, 6)[:, 0]
+    xs = []
+    for st in ("h2", "blr2"):
+        f = O.factorize(X, O.Params(leaf=64, tol=1e-6, far_sample=0, structure=st))
+        assert f.tree.L == 1
+        xs.append(O.solve(f, b))
+    assert np.array_equal(xs[0], xs[1])
+
+
+def test_blr2_self_consistency_and_accuracy():
+    """The solve is exact for the represented matrix, whose distance from A is
+    controlled by tol; the root is larger than the hierarchical one (it keeps
+    every leaf skeleton instead of merging them level by level)."""
+    X = W.cube_points(1024, 12)
+    p = O.Params(leaf=64, tol=1e-6, far_sample=0, structure="blr2")
+    f = O.factorize(X, p)
+    At = O.assemble_dense(f)
+    b = W.gaussian_rhs(1024, 1, 4)[:, 0]
+    x = O.solve(f, b)
+    assert _rel(x, np.linalg.solve(At, b)) < 1e-12
+    sgn, ld = np.linalg.slogdet(At)
+    assert abs(O.logabsdet(f) - ld) < 1e-9 * abs(ld)
+    A = O.dense_matrix(X, p)
+    assert _rel(x, np.linalg.solve(A, b)) < 1e-3
+    fh = O.factorize(X, O.Params(leaf=64, tol=1e-6, far_sample=0))
+    assert f.m_root > fh.m_root
