@@ -245,6 +245,24 @@ h2ulv_status h2ulv_refine_gmres(const h2ulv_factor* f, const double* b, int64_t 
                                 int64_t ldx, int32_t nrhs, double rtol, int32_t max_iter,
                                 int32_t restart, int32_t* iters, double* relres, void* stream);
 
+/*
+ * Block GMRES for several right-hand sides: the refinement's correction
+ * equations of all nrhs columns share one Krylov space of the operator A M^-1
+ * (M the ULV solve), restarted after `restart` (1..128) block steps.  Each step
+ * applies one solve and one exact matvec to a block of up to nrhs vectors, so
+ * the outlying eigenvalues of the preconditioned operator, the same for every
+ * column, are found once for all columns.  Columns are scaled by 1/|b_c|;
+ * directions of a block below 1e-12 of its largest (or, in a restart's first
+ * block, below 1e-3 rtol) are dropped.  Stops when every column's relative
+ * residual (exact matvec) is <= rtol.  iters: block steps taken; relres: the
+ * largest relative residual.  Device scratch about (2 restart + 3) n nrhs
+ * doubles.  Same arguments and errors as h2ulv_refine_gmres.
+ */
+h2ulv_status h2ulv_refine_block_gmres(const h2ulv_factor* f, const double* b, int64_t ldb,
+                                      double* x, int64_t ldx, int32_t nrhs, double rtol,
+                                      int32_t max_iter, int32_t restart, int32_t* iters,
+                                      double* relres, void* stream);
+
 /* Statistics of a factor (host).  Synchronises nothing. */
 h2ulv_status h2ulv_get_stats(const h2ulv_factor* f, h2ulv_stats* s);
 

@@ -408,6 +408,308 @@ static h2ulv_status gmres_impl(const h2ulv_factor& F, const double* b, int64_t l
   return H2ULV_ERR_NOT_CONVERGED;
 }
 
+namespace {
+// Small dense host helpers of the block GMRES (matrices column-major).
+
+// Eigenpairs of a symmetric q x q matrix by cyclic Jacobi rotations:
+// A = E diag(lam) E^T.
+void sym_eig(std::vector<double> A, int q, std::vector<double>& lam, std::vector<double>& E) {
+  E.assign((size_t)q * q, 0.0);
+  for (int i = 0; i < q; ++i) E[i + (size_t)i * q] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int j = 0; j < q; ++j)
+      for (int i = 0; i < q; ++i)
+        (i == j ? dia : off) += A[i + (size_t)j * q] * A[i + (size_t)j * q];
+    if (off <= 1e-30 * dia || off == 0.0) break;
+    for (int p = 0; p < q; ++p)
+      for (int r = p + 1; r < q; ++r) {
+        const double apr = A[p + (size_t)r * q];
+        if (apr == 0.0) continue;
+        const double app = A[p + (size_t)p * q], arr = A[r + (size_t)r * q];
+        const double th = 0.5 * (arr - app) / apr;
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < q; ++k) {  // columns p, r
+          const double akp = A[k + (size_t)p * q], akr = A[k + (size_t)r * q];
+          A[k + (size_t)p * q] = c * akp - s * akr;
+          A[k + (size_t)r * q] = s * akp + c * akr;
+        }
+        for (int k = 0; k < q; ++k) {  // rows p, r
+          const double apk = A[p + (size_t)k * q], ark = A[r + (size_t)k * q];
+          A[p + (size_t)k * q] = c * apk - s * ark;
+          A[r + (size_t)k * q] = s * apk + c * ark;
+        }
+        for (int k = 0; k < q; ++k) {
+          const double ekp = E[k + (size_t)p * q], ekr = E[k + (size_t)r * q];
+          E[k + (size_t)p * q] = c * ekp - s * ekr;
+          E[k + (size_t)r * q] = s * ekp + c * ekr;
+        }
+      }
+  }
+  lam.resize(q);
+  for (int i = 0; i < q; ++i) lam[i] = A[i + (size_t)i * q];
+}
+
+// Upper Cholesky factor of a symmetric positive definite q x q matrix (G = R^T R);
+// false when a pivot is not positive.
+bool chol_upper(const std::vector<double>& G, int q, std::vector<double>& R) {
+  R.assign((size_t)q * q, 0.0);
+  for (int j = 0; j < q; ++j) {
+    for (int i = 0; i <= j; ++i) {
+      double s = G[i + (size_t)j * q];
+      for (int k = 0; k < i; ++k) s -= R[k + (size_t)i * q] * R[k + (size_t)j * q];
+      if (i == j) {
+        if (!(s > 0.0)) return false;
+        R[j + (size_t)j * q] = std::sqrt(s);
+      } else {
+        R[i + (size_t)j * q] = s / R[i + (size_t)i * q];
+      }
+    }
+  }
+  return true;
+}
+
+// min_Y |E - H Y|_F column by column for H (rows x cols, rows > cols) by
+// Householder QR; Y is cols x p, res[c] the residual norm of column c.
+void least_squares(std::vector<double> Hm, int rows, int cols, std::vector<double> E, int p,
+                   std::vector<double>& Y, std::vector<double>& res) {
+  for (int j = 0; j < cols; ++j) {
+    double nrm = 0.0;
+    for (int i = j; i < rows; ++i) nrm += Hm[i + (size_t)j * rows] * Hm[i + (size_t)j * rows];
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) continue;
+    const double a = Hm[j + (size_t)j * rows];
+    const double beta = a >= 0 ? -nrm : nrm;
+    std::vector<double> v(rows - j);
+    v[0] = a - beta;
+    for (int i = j + 1; i < rows; ++i) v[i - j] = Hm[i + (size_t)j * rows];
+    double vv = 0.0;
+    for (double x : v) vv += x * x;
+    if (vv == 0.0) continue;
+    auto reflect = [&](double* col) {
+      double d = 0.0;
+      for (int i = j; i < rows; ++i) d += v[i - j] * col[i];
+      d = 2.0 * d / vv;
+      for (int i = j; i < rows; ++i) col[i] -= d * v[i - j];
+    };
+    for (int k = j; k < cols; ++k) reflect(Hm.data() + (size_t)k * rows);
+    for (int k = 0; k < p; ++k) reflect(E.data() + (size_t)k * rows);
+  }
+  Y.assign((size_t)cols * p, 0.0);
+  res.assign(p, 0.0);
+  for (int k = 0; k < p; ++k) {
+    const double* e = E.data() + (size_t)k * rows;
+    double* y = Y.data() + (size_t)k * cols;
+    for (int i = cols - 1; i >= 0; --i) {
+      double s = e[i];
+      for (int l = i + 1; l < cols; ++l) s -= Hm[i + (size_t)l * rows] * y[l];
+      const double d = Hm[i + (size_t)i * rows];
+      y[i] = d != 0.0 ? s / d : 0.0;
+    }
+    double r = 0.0;
+    for (int i = cols; i < rows; ++i) r += e[i] * e[i];
+    res[k] = std::sqrt(r);
+  }
+}
+}  // namespace
+
+// Block GMRES for several right-hand sides (restarted, right-preconditioned by
+// the ULV solve).  All residuals span one Krylov space: every step applies the
+// solve and the exact matvec to a block of up to p vectors, and the outlying
+// eigenvalues of the preconditioned operator, the same for every right-hand
+// side, are found once for all of them.  The residual columns are scaled by
+// 1/|b_c|, so each column's least-squares residual is its relative residual.
+// Block orthonormalisation: the Gram matrix of the block (one GEMM), its
+// eigenvectors on the host with directions below 1e-12 of the largest (or, for
+// the starting block, below 1e-3 rtol) dropped (deflation), then a second pass
+// with the Cholesky factor of the new Gram matrix.  Block classical Gram-Schmidt
+// against all earlier blocks, applied twice, as GEMMs.
+static h2ulv_status block_gmres_impl(const h2ulv_factor& F, const double* b, int64_t ldb,
+                                     double* x, int64_t ldx, int p, double rtol, int max_iter,
+                                     int restart, int32_t* iters, double* relres, hipStream_t s) {
+  const int64_t n = F.n;
+  const int m = std::max(1, std::min(restart, 128));
+  const int QMAX = p * (m + 1);
+  DBuf Vb((int64_t)QMAX * n * sizeof(double)), Zb((int64_t)p * m * n * sizeof(double)),
+      Wb((int64_t)p * n * sizeof(double)), Rb((int64_t)p * n * sizeof(double)),
+      nr(2 * p * sizeof(double)), hd((int64_t)QMAX * p * sizeof(double)),
+      td((int64_t)p * p * sizeof(double)), yd((int64_t)QMAX * p * sizeof(double));
+  double* V = Vb.as<double>();
+  double* Z = Zb.as<double>();
+  double* Wm = Wb.as<double>();
+  double* R = Rb.as<double>();
+  double* hdev = hd.as<double>();
+  double* tdev = td.as<double>();
+  auto gemm = [&](double* C, int64_t ldc, int M, int N, int K, const double* A, int64_t lda,
+                  bool ta, const double* B, int64_t ldB, double alpha, double beta) {
+    if (M <= 0 || N <= 0) return;
+    Stage st(s);
+    GemmBatch<double> g;
+    g.one(C, ldc, M, N, K, A, lda, ta, B, ldB, false, alpha, beta);
+    g.run(st, "bgmres");
+    st.sync();
+  };
+  auto download = [&](const double* src, int64_t cnt) {
+    std::vector<double> h(cnt);
+    H2ULV_HIP(hipMemcpyAsync(h.data(), src, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+    H2ULV_HIP(hipStreamSynchronize(s));
+    return h;
+  };
+  auto upload = [&](double* dst, const std::vector<double>& h) {
+    H2ULV_HIP(hipMemcpyAsync(dst, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  };
+  // Orthonormal basis of the columns of A (n x q, column scales sc), written to
+  // out; returns its width q' and Rf (q' x q) with A diag(sc) = out Rf.
+  auto block_qr = [&](const double* A, int q, const std::vector<double>& sc, double floor_abs,
+                      double* out, std::vector<double>& Rf) -> int {
+    gemm(tdev, q, q, q, (int)n, A, n, true, A, n, 1.0, 0.0);
+    std::vector<double> G = download(tdev, (int64_t)q * q);
+    for (int j = 0; j < q; ++j)
+      for (int i = 0; i < q; ++i) G[i + (size_t)j * q] *= sc[i] * sc[j];
+    std::vector<double> lam, E;
+    sym_eig(G, q, lam, E);
+    double lmax = 0.0;
+    for (double l : lam) lmax = std::max(lmax, l);
+    std::vector<int> keep;
+    for (int i = 0; i < q; ++i)
+      if (lam[i] > 1e-24 * lmax && lam[i] > floor_abs * floor_abs) keep.push_back(i);
+    const int qk = (int)keep.size();
+    Rf.assign((size_t)qk * q, 0.0);
+    if (qk == 0) return 0;
+    // T = diag(sc) E_keep Lambda^-1/2 (q x qk); out = A T
+    std::vector<double> T((size_t)q * qk);
+    for (int c = 0; c < qk; ++c)
+      for (int i = 0; i < q; ++i)
+        T[i + (size_t)c * q] = sc[i] * E[i + (size_t)keep[c] * q] / std::sqrt(lam[keep[c]]);
+    upload(tdev, T);
+    gemm(out, n, (int)n, qk, q, A, n, false, tdev, q, 1.0, 0.0);
+    // second pass: out^T out = C^T C, out <- out C^-1
+    gemm(tdev, qk, qk, qk, (int)n, out, n, true, out, n, 1.0, 0.0);
+    std::vector<double> G2 = download(tdev, (int64_t)qk * qk), Cu;
+    if (!chol_upper(G2, qk, Cu)) fail(H2ULV_ERR_HIP, "block GMRES: orthonormalisation failed");
+    std::vector<double> Ci((size_t)qk * qk, 0.0);  // C^-1 (upper)
+    for (int j = 0; j < qk; ++j) {
+      Ci[j + (size_t)j * qk] = 1.0 / Cu[j + (size_t)j * qk];
+      for (int i = j - 1; i >= 0; --i) {
+        double acc = 0.0;
+        for (int k = i + 1; k <= j; ++k) acc += Cu[i + (size_t)k * qk] * Ci[k + (size_t)j * qk];
+        Ci[i + (size_t)j * qk] = -acc / Cu[i + (size_t)i * qk];
+      }
+    }
+    upload(tdev, Ci);
+    gemm(Wm, n, (int)n, qk, qk, out, n, false, tdev, qk, 1.0, 0.0);
+    H2ULV_HIP(hipMemcpyAsync(out, Wm, (size_t)qk * n * sizeof(double), hipMemcpyDeviceToDevice,
+                             s));
+    // Rf = C Lambda^1/2 E_keep^T
+    for (int j = 0; j < q; ++j)
+      for (int r = 0; r < qk; ++r) {
+        double acc = 0.0;
+        for (int k = r; k < qk; ++k)
+          acc += Cu[r + (size_t)k * qk] * std::sqrt(lam[keep[k]]) * E[j + (size_t)keep[k] * q];
+        Rf[r + (size_t)j * qk] = acc;
+      }
+    return qk;
+  };
+  {
+    CopyBatch cb;
+    Stage st(s);
+    cb.add(b, ldb, x, ldx, (int)n, p);
+    cb.run(st);
+    st.sync();
+  }
+  solve_impl(F, x, p, ldx, s);
+  int steps = 0;
+  std::vector<double> rel(p, 0.0), bn(p, 1.0);
+  for (;;) {
+    matvec_impl(F, x, ldx, Wm, n, p, s);
+    launch_resid_norms(b, ldb, Wm, n, R, n, n, p, nr.as<double>(), nr.as<double>() + p, s);
+    std::vector<double> hv = download(nr.as<double>(), 2 * p);
+    bool done = true;
+    for (int c = 0; c < p; ++c) {
+      bn[c] = std::sqrt(hv[p + c]);
+      if (bn[c] == 0.0) bn[c] = 1.0;
+      rel[c] = std::sqrt(hv[c]) / bn[c];
+      done = done && rel[c] <= rtol;
+    }
+    if (done || steps >= max_iter) break;
+    std::vector<double> sc(p);
+    for (int c = 0; c < p; ++c) sc[c] = 1.0 / bn[c];
+    std::vector<double> S0;
+    const int q0 = block_qr(R, p, sc, 1e-3 * rtol, V, S0);
+    if (q0 == 0) break;
+    std::vector<int> qs{q0};
+    std::vector<int64_t> qoff{0, q0};
+    std::vector<std::vector<double>> Hcol;  // per step: (qoff[j+1] + q_{j+1}) x q_j
+    std::vector<double> Y, res;
+    int Qz = 0;  // columns of Z
+    for (int j = 0; j < m && steps < max_iter; ++j) {
+      const int qj = qs[j];
+      double* Vj = V + qoff[j] * n;
+      double* Zj = Z + (int64_t)Qz * n;
+      H2ULV_HIP(hipMemcpyAsync(Zj, Vj, (size_t)qj * n * sizeof(double), hipMemcpyDeviceToDevice,
+                               s));
+      solve_impl(F, Zj, qj, n, s);
+      matvec_impl(F, Zj, n, Wm, n, qj, s);
+      ++steps;
+      Qz += qj;
+      const int Qj = (int)qoff[j + 1];
+      std::vector<double> h((size_t)Qj * qj, 0.0);
+      for (int pass = 0; pass < 2; ++pass) {
+        gemm(hdev, Qj, Qj, qj, (int)n, V, n, true, Wm, n, 1.0, 0.0);
+        std::vector<double> hp = download(hdev, (int64_t)Qj * qj);
+        for (size_t e = 0; e < hp.size(); ++e) h[e] += hp[e];
+        gemm(Wm, n, (int)n, qj, Qj, V, n, false, hdev, Qj, -1.0, 1.0);
+      }
+      std::vector<double> ones(qj, 1.0), Rn;
+      const int qn = block_qr(Wm, qj, ones, 0.0, V + (int64_t)Qj * n, Rn);
+      qs.push_back(qn);
+      qoff.push_back(Qj + qn);
+      std::vector<double> colblk((size_t)(Qj + qn) * qj, 0.0);
+      for (int c = 0; c < qj; ++c) {
+        for (int i = 0; i < Qj; ++i) colblk[i + (size_t)c * (Qj + qn)] = h[i + (size_t)c * Qj];
+        for (int i = 0; i < qn; ++i) colblk[Qj + i + (size_t)c * (Qj + qn)] = Rn[i + (size_t)c * qn];
+      }
+      Hcol.push_back(std::move(colblk));
+      // least squares over the block Hessenberg matrix
+      const int rows = Qj + qn, cols = Qz;
+      std::vector<double> Hm((size_t)rows * cols, 0.0);
+      int c0 = 0;
+      for (size_t jj = 0; jj < Hcol.size(); ++jj) {
+        const int rj = (int)qoff[jj + 1] + qs[jj + 1];
+        for (int c = 0; c < qs[jj]; ++c)
+          for (int i = 0; i < rj; ++i)
+            Hm[i + (size_t)(c0 + c) * rows] = Hcol[jj][i + (size_t)c * rj];
+        c0 += qs[jj];
+      }
+      std::vector<double> E1((size_t)rows * p, 0.0);
+      for (int c = 0; c < p; ++c)
+        for (int i = 0; i < q0; ++i) E1[i + (size_t)c * rows] = S0[i + (size_t)c * q0];
+      least_squares(Hm, rows, cols, E1, p, Y, res);
+      double worst = 0.0;
+      for (double r : res) worst = std::max(worst, r);
+      if (worst <= 0.5 * rtol || qn == 0) break;
+    }
+    if (Qz == 0) break;
+    // x_c += |b_c| (Z Y)_c
+    for (int c = 0; c < p; ++c)
+      for (int i = 0; i < Qz; ++i) Y[i + (size_t)c * Qz] *= bn[c];
+    upload(yd.as<double>(), Y);
+    gemm(x, ldx, (int)n, p, Qz, Z, n, false, yd.as<double>(), Qz, 1.0, 1.0);
+  }
+  double worst = 0.0;
+  bool ok = true;
+  for (int c = 0; c < p; ++c) {
+    worst = std::max(worst, rel[c]);
+    ok = ok && rel[c] <= rtol;
+  }
+  if (iters) *iters = steps;
+  if (relres) *relres = worst;
+  if (ok) return H2ULV_OK;
+  g_last_error = "block GMRES refinement did not reach the tolerance";
+  return H2ULV_ERR_NOT_CONVERGED;
+}
+
 template <class Fn>
 static h2ulv_status guarded(Fn&& fn) {
   try {
@@ -577,6 +879,25 @@ h2ulv_status h2ulv_refine_gmres(const h2ulv_factor* f, const double* b, int64_t 
     AllocScope as(f->has_alloc ? &f->alloc : nullptr, stream);
     out = gmres_impl(*f, b, ldb, x, ldx, nrhs, rtol, max_iter, restart, iters, relres,
                      (hipStream_t)stream);
+  });
+  return st != H2ULV_OK ? st : out;
+}
+
+h2ulv_status h2ulv_refine_block_gmres(const h2ulv_factor* f, const double* b, int64_t ldb,
+                                      double* x, int64_t ldx, int32_t nrhs, double rtol,
+                                      int32_t max_iter, int32_t restart, int32_t* iters,
+                                      double* relres, void* stream) {
+  if (!f || !b || !x || nrhs < 1 || ldb < f->n || ldx < f->n || !(rtol >= 0) || max_iter < 0 ||
+      restart < 1) {
+    g_last_error = "bad GMRES arguments";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  h2ulv_status out = H2ULV_OK;
+  h2ulv_status st = guarded([&] {
+    CacheScope cs;
+    AllocScope as(f->has_alloc ? &f->alloc : nullptr, stream);
+    out = block_gmres_impl(*f, b, ldb, x, ldx, nrhs, rtol, max_iter, restart, iters, relres,
+                           (hipStream_t)stream);
   });
   return st != H2ULV_OK ? st : out;
 }

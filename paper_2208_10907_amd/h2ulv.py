@@ -39,7 +39,8 @@ EXPORTS = [
     "h2ulv_rankmodel_destroy", "h2ulv_rankmodel_set_params", "h2ulv_rankmodel_get_params",
     "h2ulv_rankmodel_forward", "h2ulv_rankmodel_gradient", "h2ulv_rankmodel_adam_step",
     "h2ulv_rankmodel_train", "h2ulv_get_features", "h2ulv_get_sketch_info",
-    "h2ulv_release_cache", "h2ulv_refine_gmres", "h2ulv_gemm_tile_rates",
+    "h2ulv_release_cache", "h2ulv_refine_gmres", "h2ulv_refine_block_gmres",
+    "h2ulv_gemm_tile_rates",
     "h2ulv_matvec_exact_noalloc",
 ]
 
@@ -203,6 +204,8 @@ def lib() -> C.CDLL:
         "h2ulv_gemm_tile_rates": (i32, [P(dbl)]),
         "h2ulv_refine_gmres": (i32, [vp, vp, i64, vp, i64, i32, dbl, i32, i32, P(i32), P(dbl),
                                      vp]),
+        "h2ulv_refine_block_gmres": (i32, [vp, vp, i64, vp, i64, i32, dbl, i32, i32, P(i32),
+                                           P(dbl), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -406,6 +409,24 @@ class Factor:
                                       C.c_void_p(xt.data_ptr()), self.n, bt.shape[0],
                                       float(rtol), int(max_iter), int(restart), C.byref(it),
                                       C.byref(rr), _stream(stream))
+        if st != OK and (raise_on_fail or st != ERR_NOT_CONVERGED):
+            _check(st)
+        return self._back(vec, xt), int(it.value), float(rr.value)
+
+    def refine_block_gmres(self, b, rtol=1e-10, max_iter=200, restart=60, stream=None,
+                           raise_on_fail=True):
+        """Refinement whose correction equations (all columns together) are solved
+        by block GMRES preconditioned with the ULV solve.  Returns (x, block
+        steps, relres)."""
+        import torch
+        vec, bt = self._colmajor(b)
+        xt = torch.empty_like(bt)
+        it = C.c_int32(0)
+        rr = C.c_double(0.0)
+        st = lib().h2ulv_refine_block_gmres(self._h, C.c_void_p(bt.data_ptr()), self.n,
+                                            C.c_void_p(xt.data_ptr()), self.n, bt.shape[0],
+                                            float(rtol), int(max_iter), int(restart),
+                                            C.byref(it), C.byref(rr), _stream(stream))
         if st != OK and (raise_on_fail or st != ERR_NOT_CONVERGED):
             _check(st)
         return self._back(vec, xt), int(it.value), float(rr.value)

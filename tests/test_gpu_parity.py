@@ -434,3 +434,30 @@ def test_kmeans_partition_matches_oracle():
     xo = O.solve(fo, b)
     xg = fg.solve(torch.tensor(b, device="cuda")).cpu().numpy()
     assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < X_TOL
+
+
+def test_block_gmres_refinement():
+    """Block GMRES over all right-hand sides reaches the same 1e-10 residual
+    (rechecked with the oracle's matvec) and the same solution as the lockstep
+    GMRES, in no more block steps than the lockstep one takes steps; a too small
+    step budget reports NOT_CONVERGED."""
+    X = W.cube_points(5000, 46)
+    op = O.Params(leaf=64, tol=1e-4, rank_cap=16, far_sample=32)
+    fg = H.factorize(X, _params(op))
+    b = torch.tensor(W.gaussian_rhs(5000, 6, 10), device="cuda")
+    x1, it1, rel1 = fg.refine_gmres(b, rtol=1e-10, max_iter=200, restart=60)
+    x2, it2, rel2 = fg.refine_block_gmres(b, rtol=1e-10, max_iter=200, restart=60)
+    assert rel1 <= 1e-10 and rel2 <= 1e-10
+    assert it2 <= it1
+    assert torch.linalg.norm(x1 - x2) / torch.linalg.norm(x1) < 1e-8
+    bn = b.cpu().numpy()
+    r = bn - O.matvec_exact(X, x2.cpu().numpy(), op)
+    assert np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(bn, axis=0)) < 2e-10
+    # one right-hand side: block GMRES is ordinary GMRES
+    x3, it3, rel3 = fg.refine_block_gmres(b[:, :1], rtol=1e-10, max_iter=200, restart=60)
+    assert rel3 <= 1e-10
+    x4, it4, rel4 = fg.refine_block_gmres(b, rtol=1e-14, max_iter=2, raise_on_fail=False)
+    assert it4 <= 2 and rel4 > 1e-14
+    with pytest.raises(H.H2ULVError) as e:
+        fg.refine_block_gmres(b, rtol=1e-14, max_iter=2)
+    assert e.value.status == H.ERR_NOT_CONVERGED
