@@ -19,7 +19,7 @@ def test_traffic_record_matches_sources():
     for path in files:
         text = open(path).read()
         assert "traffic_bytes_per_launch:" in text and "library_source_sha256:" in text
-    t = bench.recorded_traffic("ellipsoids262144")
+    t = bench.recorded_traffic("cube1048576", "matvec")
     if t is None:
         pytest.skip("traffic record taken with other library sources")
     assert 1e6 < t < 1e11
@@ -27,7 +27,7 @@ def test_traffic_record_matches_sources():
 
 def test_traffic_record_rejected_on_other_sources(monkeypatch):
     monkeypatch.setattr(bench, "library_source_hash", lambda: "0" * 64)
-    assert bench.recorded_traffic("ellipsoids262144") is None
+    assert bench.recorded_traffic("cube1048576", "matvec") is None
     assert bench.recorded_traffic("cube2048") is None
 
 
