@@ -2036,6 +2036,116 @@ __global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ 
   }
 }
 
+// Matrix-core form of the exact matvec for blocks of 4 or 8 columns.  The
+// vector units evaluate one kernel entry per lane and the FP64 4x4x4 MFMA
+// (four independent 4x4 blocks per wave) multiplies it into the columns, so
+// the 8 multiply-adds per entry leave the vector pipe.  Operand layout of that
+// instruction, lane l = 16 q + 4 b + p (q, b, p < 4):
+//   A: block b, row p, k q     B: block b, column p, k q
+//   D: block b, column p, row q
+// A wave owns G groups of 16 targets; within a group, block b row p is target
+// 4 b + p, so lane l evaluates K(target l & 15, source q) and all four blocks
+// share the B operand x(source q, column p).  One step (a "chunk") consumes
+// four staged sources.  Targets beyond n sit at (+1e30, 0, 0) and padding
+// sources at (-1e30, 0, 0) with x = 0: every entry stays finite and only rows
+// that are never written see them.  Accumulation order: per target, the
+// sources of a chunk are summed by the instruction, chunks in ascending
+// source order.
+constexpr int MVM_G = 8;  // target groups of 16 per wave: 512 targets per workgroup
+
+template <bool LAP, bool SELF, int NB>
+__device__ __forceinline__ void matvec_mfma_tile(const double (*sp)[4], const double (*sx)[8],
+                                                 int cnt, const double* tx, const double* ty,
+                                                 const double* tz, double alpha,
+                                                 double (*acc)[2]) {
+  const int lane = threadIdx.x & 63;
+  const int q = lane >> 4, col = lane & 3;
+  for (int c0 = 0; c0 < cnt; c0 += 4) {
+    const int src = c0 + q;
+    const double sx0 = sp[src][0], sy0 = sp[src][1], sz0 = sp[src][2];
+    const double b0 = sx[src][col];
+    const double b1 = NB == 2 ? sx[src][4 + col] : 0.0;
+#pragma unroll
+    for (int g = 0; g < MVM_G; ++g) {
+      const double dx = tx[g] - sx0, dy = ty[g] - sy0, dz = tz[g] - sz0;
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      double k = inv_sqrt(r2);
+      if (!LAP) k *= exp(-alpha * (r2 * k));
+      if (SELF) k = r2 > 0.0 ? k : 0.0;
+      acc[g][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(k, b0, acc[g][0], 0, 0, 0);
+      if (NB == 2) acc[g][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(k, b1, acc[g][1], 0, 0, 0);
+    }
+  }
+}
+
+template <bool LAP, int NB>
+__global__ __launch_bounds__(256) void matvec_mfma_kernel(const double* __restrict__ pts,
+                                                          int64_t n, KernelFn kf,
+                                                          const double* __restrict__ x,
+                                                          int64_t ldx, double* __restrict__ y,
+                                                          int64_t ldy, double* __restrict__ part,
+                                                          int64_t chunk) {
+  constexpr int NR = 4 * NB;
+  constexpr int TPW = 16 * MVM_G;  // targets per wave
+  __shared__ double sp[256][4];
+  __shared__ double sx[256][8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t tb = (int64_t)blockIdx.x * (4 * TPW);  // targets [tb, tb + 4 TPW)
+  const int64_t tw = tb + (int64_t)wave * TPW;
+  const int64_t js = (int64_t)blockIdx.y * chunk, je = min(n, js + chunk);
+  double tx[MVM_G], ty[MVM_G], tz[MVM_G], acc[MVM_G][2];
+#pragma unroll
+  for (int g = 0; g < MVM_G; ++g) {
+    const int64_t t = tw + 16 * g + (lane & 15);
+    if (t < n) {
+      tx[g] = pts[3 * t];
+      ty[g] = pts[3 * t + 1];
+      tz[g] = pts[3 * t + 2];
+    } else {
+      tx[g] = 1e30;
+      ty[g] = 0.0;
+      tz[g] = 0.0;
+    }
+    acc[g][0] = acc[g][1] = 0.0;
+  }
+  for (int64_t j0 = js; j0 < je; j0 += 256) {
+    const int64_t j = j0 + threadIdx.x;
+    __syncthreads();
+    if (j < je) {
+      for (int d = 0; d < 3; ++d) sp[threadIdx.x][d] = pts[3 * j + d];
+#pragma unroll
+      for (int c = 0; c < NR; ++c) sx[threadIdx.x][c] = x[j + c * ldx];
+    } else {
+      sp[threadIdx.x][0] = -1e30;
+      sp[threadIdx.x][1] = sp[threadIdx.x][2] = 0.0;
+#pragma unroll
+      for (int c = 0; c < NR; ++c) sx[threadIdx.x][c] = 0.0;
+    }
+    __syncthreads();
+    const int cnt = (int)min((int64_t)256, je - j0);
+    if (j0 < tb + 4 * TPW && j0 + 256 > tb)
+      matvec_mfma_tile<LAP, true, NB>(sp, sx, cnt, tx, ty, tz, kf.alpha, acc);
+    else
+      matvec_mfma_tile<LAP, false, NB>(sp, sx, cnt, tx, ty, tz, kf.alpha, acc);
+  }
+  // D lane 16 q + 4 b + p holds target 4 b + q of each group, column p (+4)
+  const int col = lane & 3;
+  const int trow = 4 * ((lane >> 2) & 3) + (lane >> 4);
+#pragma unroll
+  for (int g = 0; g < MVM_G; ++g) {
+    const int64_t t = tw + 16 * g + trow;
+    if (t >= n) continue;
+#pragma unroll
+    for (int h = 0; h < NB; ++h) {
+      const int c = col + 4 * h;
+      if (part == nullptr)
+        y[t + c * ldy] = fma(kf.diag, x[t + c * ldx], acc[g][h]);
+      else
+        part[(int64_t)blockIdx.y * NR * n + c * n + t] = acc[g][h];
+    }
+  }
+}
+
 // y(i, c) = diag x(i, c) + sum over ranges s (in order) of part[s][c][i]
 __global__ __launch_bounds__(256) void matvec_reduce_kernel(const double* __restrict__ part,
                                                             int nsplit, int nr, int64_t n,
@@ -2069,12 +2179,23 @@ void matvec_launch(const double* pts, int64_t n, KernelFn kf, const double* x, i
   const int nsu = (int)((n + chunk - 1) / chunk);  // ranges actually used
   double* part = nsu > 1 ? work : nullptr;
   const dim3 grid(gx, (unsigned)std::max(nsu, 1));
-  if (kf.kind == 0)
-    hipLaunchKernelGGL((matvec_kernel<NR, true>), grid, dim3(256), 0, s, pts, n, kf, x, ldx, y,
-                       ldy, part, chunk);
-  else
-    hipLaunchKernelGGL((matvec_kernel<NR, false>), grid, dim3(256), 0, s, pts, n, kf, x, ldx, y,
-                       ldy, part, chunk);
+  static_assert(4 * 16 * MVM_G == 512, "both matvec forms cover 512 targets per workgroup");
+  if constexpr (NR == 8 || NR == 4) {
+    constexpr int NB = NR / 4;
+    if (kf.kind == 0)
+      hipLaunchKernelGGL((matvec_mfma_kernel<true, NB>), grid, dim3(256), 0, s, pts, n, kf, x,
+                         ldx, y, ldy, part, chunk);
+    else
+      hipLaunchKernelGGL((matvec_mfma_kernel<false, NB>), grid, dim3(256), 0, s, pts, n, kf, x,
+                         ldx, y, ldy, part, chunk);
+  } else {
+    if (kf.kind == 0)
+      hipLaunchKernelGGL((matvec_kernel<NR, true>), grid, dim3(256), 0, s, pts, n, kf, x, ldx, y,
+                         ldy, part, chunk);
+    else
+      hipLaunchKernelGGL((matvec_kernel<NR, false>), grid, dim3(256), 0, s, pts, n, kf, x, ldx, y,
+                         ldy, part, chunk);
+  }
   if (part) {
     const int64_t tot = n * NR;
     hipLaunchKernelGGL(matvec_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,

@@ -123,8 +123,9 @@ def test_root_only(n):
 @pytest.mark.parametrize("kernel,n,nrhs", [(O.YUKAWA, 3000, 9), (O.LAPLACE, 3001, 4),
                                              (O.LAPLACE, 700, 1)])
 def test_matvec_exact(kernel, n, nrhs):
-    """Exact matvec (two targets per thread, 512-point blocks with a ragged
-    tail, 8/4/1 right-hand-side variants) against the oracle, column by column."""
+    """Exact matvec (512-target workgroups with a ragged tail; blocks of 8 and 4
+    columns on the matrix cores, single columns on the vector units) against
+    the oracle, column by column."""
     X = W.sphere_points(n, 5)
     op = O.Params(kernel=kernel, alpha=0.5, leaf=128)
     fg = H.factorize(X, _params(op))
@@ -135,7 +136,8 @@ def test_matvec_exact(kernel, n, nrhs):
         assert np.linalg.norm(y[:, c] - yo[:, c]) / np.linalg.norm(yo[:, c]) < 1e-14, c
 
 
-@pytest.mark.parametrize("kernel,n,nrhs", [(O.LAPLACE, 70001, 5), (O.YUKAWA, 66000, 1)])
+@pytest.mark.parametrize("kernel,n,nrhs", [(O.LAPLACE, 70001, 13), (O.YUKAWA, 66000, 1),
+                                             (O.YUKAWA, 65537, 8)])
 def test_matvec_split_sampled(kernel, n, nrhs):
     """Exact matvec at sizes where the sources are split over several
     workgroups (partial sums added in a fixed order): sampled rows against the
