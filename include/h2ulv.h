@@ -88,6 +88,13 @@ typedef struct h2ulv_params {
                           bisection (the k-means partition of Sec. V: every
                           box splits into two clusters of floor(n/2) and
                           ceil(n/2) points, so leaves stay a power of two)      */
+  int32_t structure;    /* 0 (default): the H^2 hierarchy, skeletons merged level
+                          by level into the parent (Sec. III).  1: flat BLR^2
+                          (Sec. II-B): the leaves are the only level, every
+                          leaf pair is classified by the admissibility rule,
+                          and after the leaf sweep all skeletons form one dense
+                          root block (Eq. BLR2final); levels above the leaves
+                          hold nothing (their accessors return INVALID_ARG)    */
 } h2ulv_params;
 
 typedef struct h2ulv_factor h2ulv_factor; /* opaque */

@@ -47,11 +47,14 @@ static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, 
     return;
   }
   // per-level RHS blocks: rhs[lev] holds m_i x nrhs per box (ld m_i); the leaf
-  // level reads bt directly.
+  // level reads bt directly.  The top factored level is 1 (its two boxes meet
+  // at the root), or the leaf level for the flat structure (every leaf meets
+  // at the root).
+  const int top = F.p.structure == 1 ? L : 1;
   std::vector<std::vector<int64_t>> moff(L + 1), woff(L + 1);
   std::vector<double*> rhs(L + 1, nullptr), cbuf(L + 1, nullptr), wbuf(L + 1, nullptr),
       xbuf(L + 1, nullptr);
-  for (int lev = 1; lev <= L; ++lev) {
+  for (int lev = top; lev <= L; ++lev) {
     const LevelFactor& lf = F.levels[lev];
     moff[lev].assign(lf.nb + 1, 0);
     woff[lev].assign(lf.nb + 1, 0);
@@ -73,7 +76,7 @@ static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, 
     return rhs[lev] + moff[lev][i];
   };
   // forward
-  for (int lev = L; lev >= 1; --lev) {
+  for (int lev = L; lev >= top; --lev) {
     const LevelFactor& lf = F.levels[lev];
     GemmBatch<double> g1, g2, g3;
     for (int i = 0; i < lf.nb; ++i) {
@@ -97,7 +100,7 @@ static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, 
     g3.run(st, "solve");
     // gather c^S of both children into the parent's rhs
     CopyBatch cb;
-    if (lev > 1) {
+    if (lev > top) {
       const LevelFactor& pa = F.levels[lev - 1];
       for (int p = 0; p < pa.nb; ++p) {
         int k1 = lf.k[2 * p], k2 = lf.k[2 * p + 1];
@@ -109,22 +112,25 @@ static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, 
       cb.run(st);
     }
   }
-  // root
-  const LevelFactor& l1 = F.levels[1];
-  int m0 = F.m_root, k1 = l1.k[0];
+  // root: the skeleton parts of the top level's boxes, in box order
+  const LevelFactor& lt = F.levels[top];
+  const int m0 = F.m_root;
+  std::vector<int> koff(lt.nb + 1, 0);
+  for (int a = 0; a < lt.nb; ++a) koff[a + 1] = koff[a] + lt.k[a];
   double* b0 = st.scratch<double>(std::max<int64_t>((int64_t)m0 * nrhs, 1));
   double* x0 = st.scratch<double>(std::max<int64_t>((int64_t)m0 * nrhs, 1));
   {
     CopyBatch cb;
-    cb.add(cbuf[1] + moff[1][0], l1.m[0], b0, m0, k1, nrhs);
-    cb.add(cbuf[1] + moff[1][1], l1.m[1], b0 + k1, m0, l1.k[1], nrhs);
+    for (int a = 0; a < lt.nb; ++a)
+      if (lt.k[a] > 0)
+        cb.add(cbuf[top] + moff[top][a], lt.m[a], b0 + koff[a], m0, lt.k[a], nrhs);
     cb.run(st);
     GemmBatch<double> g;
     g.one(x0, m0, m0, nrhs, m0, F.root_inv.as<double>(), m0, false, b0, m0, false);
     g.run(st, "solve");
   }
   // backward
-  for (int lev = 1; lev <= L; ++lev) {
+  for (int lev = top; lev <= L; ++lev) {
     const LevelFactor& lf = F.levels[lev];
     GemmBatch<double> g1, g2;
     for (int i = 0; i < lf.nb; ++i) {
@@ -133,8 +139,8 @@ static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, 
       // skeleton part of the solution from the parent
       const double* xs;
       int64_t ldxs;
-      if (lev == 1) {
-        xs = x0 + (i == 0 ? 0 : k1);
+      if (lev == top) {
+        xs = x0 + koff[i];
         ldxs = std::max(m0, 1);
       } else {
         int p = i / 2;
@@ -755,6 +761,7 @@ h2ulv_status h2ulv_params_default(h2ulv_params* p) {
   p->sketch_seed = 0;
   p->fill_in = 1;
   p->partition = 0;
+  p->structure = 0;
   return H2ULV_OK;
 }
 
@@ -923,8 +930,13 @@ h2ulv_status h2ulv_get_perm(const h2ulv_factor* f, int64_t* perm) {
   return H2ULV_OK;
 }
 
+// levels that hold a factorization: 1..L, or only L for the flat structure
+static bool factored_level(const h2ulv_factor* f, int32_t lev) {
+  return f && lev >= 1 && lev <= f->tree.L && (f->p.structure == 0 || lev == f->tree.L);
+}
+
 h2ulv_status h2ulv_get_ranks(const h2ulv_factor* f, int32_t lev, int32_t* m, int32_t* k) {
-  if (!f || lev < 1 || lev > f->tree.L) {
+  if (!factored_level(f, lev)) {
     g_last_error = "bad level";
     return H2ULV_ERR_INVALID_ARG;
   }
@@ -937,7 +949,7 @@ h2ulv_status h2ulv_get_ranks(const h2ulv_factor* f, int32_t lev, int32_t* m, int
 }
 
 h2ulv_status h2ulv_get_skeleton(const h2ulv_factor* f, int32_t lev, int32_t box, int64_t* sk) {
-  if (!f || !sk || lev < 1 || lev > f->tree.L || box < 0 || box >= (1 << lev)) {
+  if (!sk || !factored_level(f, lev) || box < 0 || box >= (1 << lev)) {
     g_last_error = "bad level or box";
     return H2ULV_ERR_INVALID_ARG;
   }
@@ -947,7 +959,7 @@ h2ulv_status h2ulv_get_skeleton(const h2ulv_factor* f, int32_t lev, int32_t box,
 }
 
 h2ulv_status h2ulv_get_basis(const h2ulv_factor* f, int32_t lev, int32_t box, double* U) {
-  if (!f || !U || lev < 1 || lev > f->tree.L || box < 0 || box >= (1 << lev)) {
+  if (!U || !factored_level(f, lev) || box < 0 || box >= (1 << lev)) {
     g_last_error = "bad level or box";
     return H2ULV_ERR_INVALID_ARG;
   }
@@ -973,7 +985,7 @@ h2ulv_status h2ulv_structure_create(const double* pts, int64_t n, const h2ulv_pa
       if (!std::isfinite(pts[i])) fail(H2ULV_ERR_INVALID_ARG, "non-finite point coordinate");
     auto s = std::make_unique<h2ulv_structure>();
     s->tree = build_tree(pts, n, params->leaf_size, params->partition);
-    s->lists = build_lists(s->tree, params->eta);
+    s->lists = build_structure_lists(s->tree, *params);
     *out = s.release();
   });
 }
@@ -1089,7 +1101,7 @@ h2ulv_status h2ulv_rankmodel_train(h2ulv_rankmodel* m, const float* feat, const 
 }
 
 h2ulv_status h2ulv_get_features(const h2ulv_factor* f, int32_t lev, float* feat, float* target) {
-  if (!f || lev < 1 || lev > f->tree.L) {
+  if (!factored_level(f, lev)) {
     g_last_error = "bad level";
     return H2ULV_ERR_INVALID_ARG;
   }
@@ -1102,7 +1114,7 @@ h2ulv_status h2ulv_get_features(const h2ulv_factor* f, int32_t lev, float* feat,
 
 h2ulv_status h2ulv_get_sketch_info(const h2ulv_factor* f, int32_t lev, int32_t* khat,
                                    int32_t* ell, int32_t* state) {
-  if (!f || lev < 1 || lev > f->tree.L) {
+  if (!factored_level(f, lev)) {
     g_last_error = "bad level";
     return H2ULV_ERR_INVALID_ARG;
   }

@@ -1740,8 +1740,9 @@ void Driver::level(const std::vector<Prob*>& G) {
   tick("f_elim");
   st.sync();
   for (Prob* P : G) {
-    // next level's candidate rows: the children's skeletons
-    if (P->lev > 1) {
+    // next level's candidate rows: the children's skeletons (the flat
+    // structure has no next level: its root takes every leaf skeleton)
+    if (P->lev > 1 && p.structure == 0) {
       LevelFactor& lf = P->lf();
       LevelFactor& pa = P->F->levels[P->lev - 1];
       pa.cand.assign(P->nb / 2, {});
@@ -1778,17 +1779,24 @@ void Driver::roots(const std::vector<Prob*>& G) {
       kb.add(dperm + permoff[g], m0, dperm + permoff[g], m0, D0[g].as<double>(), m0);
       P->kevals += (double)m0 * m0;
     } else {
-      const std::vector<int>& k = F.levels[1].k;
-      m0 = k[0] + k[1];
+      // the skeleton blocks of the top factored level: the two children of the
+      // root, or (flat) every leaf, in box order (Eq. BLR2final)
+      const int top = p.structure == 1 ? P->L() : 1;
+      const std::vector<int>& k = F.levels[top].k;
+      const int nt = 1 << top;
+      m0 = 0;
+      for (int a = 0; a < nt; ++a) m0 += k[a];
       D0[g].alloc(std::max<size_t>((size_t)m0 * m0, 1) * sizeof(double));
       int ro = 0;
-      for (int a = 0; a < 2; ++a) {
+      for (int a = 0; a < nt; ++a) {
         int co = 0;
-        for (int b = 0; b < 2; ++b) {
-          int64_t ld;
-          const double* src = P->shat_block(1, a, b, &ld);
-          cb.add(src, std::max<int64_t>(ld, 1), D0[g].as<double>() + ro + (int64_t)co * m0, m0,
-                 k[a], k[b]);
+        for (int b = 0; b < nt; ++b) {
+          if (k[a] > 0 && k[b] > 0) {
+            int64_t ld;
+            const double* src = P->shat_block(top, a, b, &ld);
+            cb.add(src, std::max<int64_t>(ld, 1), D0[g].as<double>() + ro + (int64_t)co * m0,
+                   m0, k[a], k[b]);
+          }
           co += k[b];
         }
         ro += k[a];
@@ -1861,7 +1869,7 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
     F[q]->p.rank_model = nullptr;  // the factor does not keep the model
     F[q]->n = n[q];
     F[q]->tree = build_tree(hp.data(), n[q], params.leaf_size, params.partition);
-    F[q]->lists = build_lists(F[q]->tree, params.eta);
+    F[q]->lists = build_structure_lists(F[q]->tree, params);
     F[q]->hpts = std::move(hp);
   }
   double t1 = now_s();
@@ -1910,8 +1918,10 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
                         f.tree.perm.begin() + f.tree.end[L][i]);
   }
   // levels aligned by height above the leaves; the active problems of a height
-  // are split into groups whose level buffers fit the free device memory
-  for (int h = 0; h < H; ++h) {
+  // are split into groups whose level buffers fit the free device memory.  The
+  // flat structure has the leaf level only.
+  const bool flat = params.structure == 1;
+  for (int h = 0; h < (flat ? std::min(H, 1) : H); ++h) {
     std::vector<Prob*> act;
     for (Prob& P : probs)
       if (P.F->tree.L - h >= 1) {

@@ -72,6 +72,10 @@ struct Lists {
 int tree_depth(int64_t n, int leaf);
 Tree build_tree(const double* pts, int64_t n, int leaf, int partition);
 Lists build_lists(const Tree& t, double eta);
+// flat BLR^2 lists: the leaf level only (upper levels empty)
+Lists build_flat_lists(const Tree& t, double eta);
+// the lists of the structure params.structure selects
+Lists build_structure_lists(const Tree& t, const h2ulv_params& p);
 void validate_params(const h2ulv_params* p);
 
 }  // namespace h2ulv

@@ -201,6 +201,57 @@ Lists build_lists(const Tree& t, double eta) {
   return ls;
 }
 
+Lists build_flat_lists(const Tree& t, double eta) {
+  // one level of boxes, the leaves, every pair classified directly (no
+  // hierarchy); the levels above hold empty lists, the root level its box
+  Lists ls;
+  ls.near_ptr.push_back({0, 1});
+  ls.near_idx.push_back({0});
+  ls.far_ptr.push_back({0, 0});
+  ls.far_idx.push_back({});
+  for (int lev = 1; lev < t.L; ++lev) {
+    ls.near_ptr.emplace_back(((size_t)1 << lev) + 1, 0);
+    ls.near_idx.emplace_back();
+    ls.far_ptr.emplace_back(((size_t)1 << lev) + 1, 0);
+    ls.far_idx.emplace_back();
+  }
+  if (t.L == 0) return ls;
+  const int64_t nb = (int64_t)1 << t.L;
+  const std::vector<double>& c = t.centre[t.L];
+  const std::vector<double>& r = t.radius[t.L];
+  std::vector<std::vector<int32_t>> nl(nb), fl(nb);
+  parallel_for(nb, 16, [&](int64_t i) {
+    for (int64_t j = 0; j < nb; ++j) {
+      double d0 = c[3 * i] - c[3 * j], d1 = c[3 * i + 1] - c[3 * j + 1],
+             d2 = c[3 * i + 2] - c[3 * j + 2];
+      double s = d0 * d0;
+      s = s + d1 * d1;
+      s = s + d2 * d2;
+      if (std::sqrt(s) > eta * (r[i] + r[j]))
+        fl[i].push_back((int32_t)j);
+      else
+        nl[i].push_back((int32_t)j);
+    }
+  });
+  std::vector<int64_t> np(nb + 1, 0), fp(nb + 1, 0);
+  std::vector<int32_t> ni, fi;
+  for (int64_t i = 0; i < nb; ++i) {
+    ni.insert(ni.end(), nl[i].begin(), nl[i].end());
+    fi.insert(fi.end(), fl[i].begin(), fl[i].end());
+    np[i + 1] = (int64_t)ni.size();
+    fp[i + 1] = (int64_t)fi.size();
+  }
+  ls.near_ptr.push_back(std::move(np));
+  ls.near_idx.push_back(std::move(ni));
+  ls.far_ptr.push_back(std::move(fp));
+  ls.far_idx.push_back(std::move(fi));
+  return ls;
+}
+
+Lists build_structure_lists(const Tree& t, const h2ulv_params& p) {
+  return p.structure == 1 ? build_flat_lists(t, p.eta) : build_lists(t, p.eta);
+}
+
 bool Lists::is_near(int lev, int32_t i, int32_t j) const {
   const int32_t* b = near_idx[lev].data() + near_ptr[lev][i];
   const int32_t* e = near_idx[lev].data() + near_ptr[lev][i + 1];
@@ -226,6 +277,8 @@ void validate_params(const h2ulv_params* p) {
   if (p->fill_in != 0 && p->fill_in != 1) fail(H2ULV_ERR_INVALID_ARG, "fill_in must be 0 or 1");
   if (p->partition != 0 && p->partition != 1)
     fail(H2ULV_ERR_INVALID_ARG, "partition must be 0 (k-d) or 1 (k-means)");
+  if (p->structure != 0 && p->structure != 1)
+    fail(H2ULV_ERR_INVALID_ARG, "structure must be 0 (H^2) or 1 (flat BLR^2)");
   if (p->fill_in == 0 && p->rank_model)
     fail(H2ULV_ERR_INVALID_ARG, "fill_in = 0 must not be combined with a rank model");
 }

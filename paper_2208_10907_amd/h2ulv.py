@@ -55,7 +55,7 @@ class Params(C.Structure):
         ("rank_cap", C.c_int32), ("tol", C.c_double), ("far_sample", C.c_int32),
         ("precision", C.c_int32), ("verbose", C.c_int32), ("oversample", C.c_int32),
         ("rank_model", C.c_void_p), ("sketch_seed", C.c_uint64), ("fill_in", C.c_int32),
-        ("partition", C.c_int32),
+        ("partition", C.c_int32), ("structure", C.c_int32),
     ]
 
 
@@ -223,7 +223,8 @@ def _check(status: int) -> None:
 
 def make_params(kernel=LAPLACE, alpha=0.0, diag=1e3, eta=1.0, leaf=256, tol=1e-8,
                 rank_cap=0, far_sample=32, precision=FP64, verbose=0, rank_model=None,
-                sketch_seed=0, oversample=8, fill_in=True, partition="kd") -> Params:
+                sketch_seed=0, oversample=8, fill_in=True, partition="kd",
+                structure="h2") -> Params:
     p = Params()
     _check(lib().h2ulv_params_default(C.byref(p)))
     p.kernel, p.alpha, p.diag, p.eta = int(kernel), float(alpha), float(diag), float(eta)
@@ -232,6 +233,7 @@ def make_params(kernel=LAPLACE, alpha=0.0, diag=1e3, eta=1.0, leaf=256, tol=1e-8
     p.oversample, p.sketch_seed = int(oversample), int(sketch_seed)
     p.fill_in = 1 if fill_in else 0
     p.partition = {"kd": 0, "kmeans": 1}[partition]
+    p.structure = {"h2": 0, "blr2": 1}[structure]
     p.rank_model = rank_model._h.value if rank_model is not None else None
     p._model_ref = rank_model  # keeps the model alive as long as the parameters
     return p

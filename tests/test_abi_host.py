@@ -74,16 +74,18 @@ def test_structure_rejects_nan_points():
     ("cube", 2048, 64, 1.0, "kd"), ("cube-ragged", 3001, 64, 1.0, "kd"),
     ("sphere", 5000, 100, 1.0, "kd"), ("line", 64, 16, 1.5, "kd"), ("hss", 1024, 64, 0.0, "kd"),
     ("boxes", 9000, 128, 1.0, "kd"), ("ellipsoids", 6000, 64, 1.0, "kmeans"),
-    ("sphere", 5000, 100, 1.0, "kmeans"), ("cube-ragged", 3001, 64, 1.0, "kmeans")])
+    ("sphere", 5000, 100, 1.0, "kmeans"), ("cube-ragged", 3001, 64, 1.0, "kmeans"),
+    ("cube", 2048, 64, 1.0, "kd", "blr2"), ("sphere", 5000, 100, 1.5, "kd", "blr2")])
 def test_structure_identical_to_oracle(case):
-    name, n, leaf, eta, part = case
+    name, n, leaf, eta, part = case[:5]
+    structure = case[5] if len(case) > 5 else "h2"
     X = {"cube": lambda: W.cube_points(n, 1), "cube-ragged": lambda: W.cube_points(n, 2),
          "sphere": lambda: W.sphere_points(n, 2), "line": lambda: W.line_points(n),
          "hss": lambda: W.cube_points(n, 5), "boxes": lambda: W.box_problem(3)[:n],
          "ellipsoids": lambda: W.ellipsoid_points(n, 7)}[name]()
-    s = H.Structure(X, H.make_params(leaf=leaf, eta=eta, partition=part))
+    s = H.Structure(X, H.make_params(leaf=leaf, eta=eta, partition=part, structure=structure))
     t = O.build_tree(X, leaf, part)
-    near, far = O.build_lists(t, eta)
+    near, far = (O.build_flat_lists if structure == "blr2" else O.build_lists)(t, eta)
     assert s.L == t.L
     assert np.array_equal(s.perm(), t.perm)
     for lev in range(t.L + 1):

@@ -30,6 +30,7 @@ def _gpu():
 
 
 def _params(op: O.Params, **kw):
+    kw.setdefault("structure", op.structure)
     return H.make_params(kernel=op.kernel, alpha=op.alpha, diag=op.diag, eta=op.eta,
                          leaf=op.leaf, tol=op.tol, rank_cap=op.rank_cap,
                          far_sample=op.far_sample, **kw)
@@ -39,7 +40,7 @@ def _compare_structure(fg, fo):
     L = fo.tree.L
     assert fg.levels() == L
     assert np.array_equal(fg.perm(), fo.tree.perm)
-    for lev in range(L, 0, -1):
+    for lev in sorted(fo.levels, reverse=True):
         m, k = fg.ranks(lev)
         assert np.array_equal(m, [b.m for b in fo.levels[lev]]), f"m differs at level {lev}"
         assert np.array_equal(k, [b.k for b in fo.levels[lev]]), f"k differs at level {lev}"
@@ -463,3 +464,22 @@ def test_block_gmres_refinement():
     with pytest.raises(H.H2ULVError) as e:
         fg.refine_block_gmres(b, rtol=1e-14, max_iter=2)
     assert e.value.status == H.ERR_NOT_CONVERGED
+
+
+@pytest.mark.parametrize("n,leaf,tol,eta,fs,kernel", [
+    (2048, 64, 1e-8, 1.0, 0, O.LAPLACE), (3001, 100, 1e-6, 1.0, 16, O.YUKAWA),
+    (1500, 64, 1e-6, 0.0, 0, O.LAPLACE)])
+def test_flat_blr2_matches_oracle(n, leaf, tol, eta, fs, kernel):
+    """Flat BLR^2 (Sec. II-B): one level of leaves, every pair classified
+    directly, all skeletons in one root block.  Ranks and skeletons of the leaf
+    level identical, the root as large as the sum of the leaf ranks, solution
+    within 1e-10 of the oracle's; levels above the leaves hold nothing."""
+    X = W.cube_points(n, 4)
+    op = O.Params(kernel=kernel, alpha=0.5, leaf=leaf, tol=tol, eta=eta, far_sample=fs,
+                  structure="blr2")
+    fg, fo = _parity(X, op, nrhs=3)
+    L = fo.tree.L
+    assert fg.stats()["root_size"] == sum(b.k for b in fo.levels[L]) == fo.m_root
+    if L > 1:
+        with pytest.raises(H.H2ULVError):
+            fg.ranks(L - 1)
