@@ -42,7 +42,13 @@ Readings where the paper is silent (each is listed in the design notes):
     which the linear cost of Sec. I / IV-A presumes);
   * fill_in=False is the ablation without fill-ins in the basis (F = 0);
   * off-diagonal dense blocks keep only their S^SS quadrant after rotation;
-  * symmetric kernels: V = U.
+  * symmetric kernels: V = U.  Nonsymmetric matrices (the advection-diffusion
+    kernel exp(b.(x - y) - alpha r)/r, or bases="separate") take separate
+    row and column bases (Eq. fillu/fillv): the column basis of box j is the
+    row basis of A^T, whose fill-ins are F_ji^T; both interpolative
+    decompositions of a box keep the same number of pivots,
+    k = min(max(k_row, k_col), steps_row, steps_col), so that the redundant
+    block S^RR stays square.
 """
 from __future__ import annotations
 
@@ -66,6 +72,7 @@ ERR_NOT_CONVERGED = -6
 
 LAPLACE = 0
 YUKAWA = 1
+ADVECTION = 2   # exp(b.(x_i - x_j) - alpha r) / r: nonsymmetric for b != 0
 
 
 class OracleError(RuntimeError):
@@ -90,6 +97,13 @@ class Params:
     fill_in: bool = True       # False: ablation, bases from the far field alone (F = 0)
     partition: str = "kd"      # "kd" median split of the widest axis, "kmeans" 2-means
     structure: str = "h2"      # "h2" the hierarchy; "blr2" one level of leaves (Sec. II-B)
+    drift: tuple = (0.0, 0.0, 0.0)  # b of the advection-diffusion kernel
+    bases: str = "auto"        # "auto": V = U for symmetric kernels; "separate": always U, V
+
+
+def two_sided(p: Params) -> bool:
+    """Separate row and column bases (Eq. fillu and fillv)."""
+    return p.bases == "separate" or p.kernel == ADVECTION
 
 
 def params_from_problem(prob, **kw) -> Params:
@@ -106,8 +120,14 @@ def check_params(X: np.ndarray, p: Params) -> None:
         raise OracleError(ERR_INVALID_ARG, "leaf >= 2 and eta >= 0 required")
     if p.tol < 0 or not math.isfinite(p.tol) or p.rank_cap < 0 or p.far_sample < 0:
         raise OracleError(ERR_INVALID_ARG, "tol, rank_cap, far_sample must be >= 0")
-    if p.kernel not in (LAPLACE, YUKAWA) or not math.isfinite(p.diag):
+    if p.kernel not in (LAPLACE, YUKAWA, ADVECTION) or not math.isfinite(p.diag):
         raise OracleError(ERR_INVALID_ARG, "unknown kernel or bad diagonal")
+    if len(p.drift) != 3 or not all(math.isfinite(float(v)) for v in p.drift):
+        raise OracleError(ERR_INVALID_ARG, "drift must be three finite numbers")
+    if p.bases not in ("auto", "separate"):
+        raise OracleError(ERR_INVALID_ARG, "bases must be auto or separate")
+    if two_sided(p) and (p.rank_model is not None or p.structure != "h2"):
+        raise OracleError(ERR_INVALID_ARG, "separate bases need structure h2 and no rank model")
     if p.oversample < 0:
         raise OracleError(ERR_INVALID_ARG, "oversample must be >= 0")
     if p.structure not in ("h2", "blr2"):
@@ -141,8 +161,14 @@ def kernel_block(X: np.ndarray, rows: np.ndarray, cols: np.ndarray, p: Params) -
     rs = np.where(same, 1.0, r)
     if p.kernel == LAPLACE:
         K = 1.0 / rs
-    else:
+    elif p.kernel == YUKAWA:
         K = np.exp(-p.alpha * rs) / rs
+    else:
+        # b.(x_row - x_col): the drift term that makes K(x, y) != K(y, x)
+        bd = np.zeros((rows.size, cols.size))
+        for c in range(3):
+            bd += float(p.drift[c]) * (xr[:, c][:, None] - xc[:, c][None, :])
+        K = np.exp(bd - p.alpha * rs) / rs
     return np.where(same, p.diag, K)
 
 
@@ -349,6 +375,41 @@ def far_columns(tree: Tree, near, far, lev: int, i: int, P, s: int) -> np.ndarra
 # Row interpolative decomposition and orthogonal complement
 # (Sec. II-A Eq. (u): column-pivoted QR, Q kept; ID allowed; Sec. III-C)
 # ---------------------------------------------------------------------------
+def pivoted_qr(M: np.ndarray):
+    """Column-pivoted Householder QR of M^T (LAPACK dgeqp3): M^T Pi = Q R.
+    Returns (piv, R (steps x m), |diag R|), steps = min(m, n)."""
+    m, n = M.shape
+    qr, jpvt, tau, work, info = sla.lapack.dgeqp3(np.asfortranarray(M.T.copy()))
+    piv = np.asarray(jpvt, dtype=np.int64) - 1
+    steps = min(m, n)
+    R = np.triu(qr[:steps, :])
+    return piv, R, np.abs(np.diag(R))
+
+
+def id_matrix(piv, R, m: int, k: int) -> np.ndarray:
+    """W' (m x k) of the row ID that keeps the first k pivots: the identity on
+    rows piv[:k], (R11^-1 R12)^T on rows piv[k:]."""
+    Wp = np.zeros((m, k))
+    if k > 0:
+        Wp[piv[:k], np.arange(k)] = 1.0
+        if k < m:
+            E = sla.solve_triangular(R[:k, :k], R[:k, k:], lower=False)
+            Wp[piv[k:], :] = E.T
+    return Wp
+
+
+def id_rank(dg, tol: float, cap: int, m: int, n: int) -> int:
+    """Leading pivots with |R_tt| > tol |R_00|, at most the cap and min(m, n)."""
+    steps = min(m, n)
+    k = 0
+    if steps > 0 and dg[0] > 0:
+        thr = tol * dg[0]
+        while k < steps and dg[k] > thr:
+            k += 1
+    cap_eff = steps if cap <= 0 else min(cap, steps)
+    return min(k, cap_eff)
+
+
 def row_id(M: np.ndarray, tol: float, cap: int):
     """Row ID of M (m x n): M ~= W' M[piv[:k], :].
 
@@ -361,25 +422,9 @@ def row_id(M: np.ndarray, tol: float, cap: int):
         return 0, np.zeros(0, dtype=np.int64), np.zeros((0, 0)), np.zeros(0)
     if n == 0:
         return 0, np.arange(m), np.zeros((m, 0)), np.zeros(0)
-    qr, jpvt, tau, work, info = sla.lapack.dgeqp3(np.asfortranarray(M.T.copy()))
-    piv = np.asarray(jpvt, dtype=np.int64) - 1
-    steps = min(m, n)
-    R = np.triu(qr[:steps, :])
-    dg = np.abs(np.diag(R))
-    k = 0
-    if dg[0] > 0:
-        thr = tol * dg[0]
-        while k < steps and dg[k] > thr:
-            k += 1
-    cap_eff = min(m, n) if cap <= 0 else min(cap, m, n)
-    k = min(k, cap_eff)
-    Wp = np.zeros((m, k))
-    if k > 0:
-        Wp[piv[:k], np.arange(k)] = 1.0
-        if k < m:
-            E = sla.solve_triangular(R[:k, :k], R[:k, k:], lower=False)
-            Wp[piv[k:], :] = E.T
-    return k, piv, Wp, dg
+    piv, R, dg = pivoted_qr(M)
+    k = id_rank(dg, tol, cap, m, n)
+    return k, piv, id_matrix(piv, R, m, k), dg
 
 
 def complement_basis(W: np.ndarray):
@@ -548,6 +593,17 @@ class BoxFactor:
     ell: int = 0             # sketch columns (0: full pivoted QR)
     sketch: int = 0          # 0 not sketched, 1 sketch accepted, 2 fell back to the
                              # full QR, 3 accepted on the full-width retry
+    # separate column basis (nonsymmetric matrices; None: V = U)
+    V: np.ndarray = None     # m x m, [V^S V^R]
+    TV: np.ndarray = None    # k x k
+    skV: np.ndarray = None   # column skeleton point indices (pivot order)
+    pivV: np.ndarray = None
+    absdiagV: np.ndarray = None
+
+
+def right_basis(f: BoxFactor) -> np.ndarray:
+    """The column basis [V^S V^R] of a box (U itself for shared bases)."""
+    return f.U if f.V is None else f.V
 
 
 @dataclass
@@ -559,6 +615,7 @@ class Factor:
     far: list
     levels: dict = field(default_factory=dict)   # lev -> list[BoxFactor]
     cand: dict = field(default_factory=dict)     # lev -> list of candidate point arrays
+    cand_col: dict = field(default_factory=dict) # lev -> column candidates (separate bases)
     root_lu: tuple = None
     m_root: int = 0
     stats: dict = field(default_factory=dict)
@@ -617,6 +674,8 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
         flops["root"] += 2.0 / 3.0 * fac.m_root ** 3
         fac.stats = {"flops": flops, "kevals": D0.size}
         return fac
+    if two_sided(p):
+        return _factorize_two_sided(fac, flops)
 
     # candidate rows and T-hat blocks of the current level
     P = {L: [box_points(tree, L, i) for i in range(1 << L)]}
@@ -836,6 +895,183 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
     return fac
 
 
+def _block_tri_solve(Th, F):
+    """T-hat^-1 F for the block-diagonal upper-triangular T-hat (children's T)."""
+    F = F.copy()
+    off = 0
+    for Tc in Th:
+        kc = Tc.shape[0]
+        if kc:
+            F[off:off + kc] = sla.solve_triangular(Tc, F[off:off + kc], lower=False)
+        off += kc
+    return F
+
+
+def _block_tri_mul(Th, Wp):
+    """T-hat W' for the block-diagonal T-hat."""
+    W = np.zeros_like(Wp)
+    off = 0
+    for Tc in Th:
+        kc = Tc.shape[0]
+        W[off:off + kc] = Tc @ Wp[off:off + kc]
+        off += kc
+    return W
+
+
+def _factorize_two_sided(fac: Factor, flops: dict) -> Factor:
+    """H^2-ULV with separate row and column bases (Sec. III-C, Eq. fillu and
+    fillv), for matrices that are not symmetric.
+
+    Per level, with row candidates P^U and column candidates P^V of each box:
+      (a) D_ij = A(P^U_i, P^V_j) for j in Near(i) (upper levels: merged S^SS);
+      (b) one LU per diagonal block; the row fill-ins F_ij = sum_k D_ik D_kk^-1 D_kj
+          and, for the columns, the fill-ins of A^T, F_ji^T = sum_k D_ki^T D_kk^-T D_jk^T;
+      (c) row basis of box i from [K(P^U_i, far) | T-hat_U^-1 F_i+] and column
+          basis from [K(far, P^V_i)^T | T-hat_V^-1 F_+i^T]: the far-field samples
+          of own-level far boxes are their candidates of the other side (the
+          columns, resp. rows, of the far blocks); both pivoted QRs keep
+          k = min(max(k_U, k_V), steps_U, steps_V) pivots;
+      (d) S^SS_ij = T_U,i K(sk^U_i, sk^V_j) T_V,j^T for far pairs;
+      (e) S_ii = U_i^T D_ii V_i, near S^SS_ij = U^S_i^T D_ij V^S_j;
+      (f) LU of S^RR, triangular solves, Schur update (as for shared bases);
+      parents take the children's row skeletons as row candidates and their
+      column skeletons as column candidates.
+    Flop counts as for shared bases, the basis step (fill products, QR, ID,
+    complement) once per side; one LU per diagonal block serves both."""
+    X, p, tree, near, far = fac.X, fac.params, fac.tree, fac.near, fac.far
+    L = tree.L
+    kevals = 0
+    PU = {L: [box_points(tree, L, i) for i in range(1 << L)]}
+    PV = {L: [box_points(tree, L, i) for i in range(1 << L)]}
+    ThU = ThV = None
+    Sblk = None
+    fac.cand_col = {}
+    for lev in range(L, 0, -1):
+        nb = 1 << lev
+        m = [len(PU[lev][i]) for i in range(nb)]
+        # (a) dense blocks
+        D = {}
+        for i in range(nb):
+            for j in near[lev][i]:
+                if lev == L:
+                    D[i, j] = kernel_block(X, PU[lev][i], PV[lev][j], p)
+                    kevals += m[i] * m[j]
+                else:
+                    D[i, j] = np.block([[Sblk[2 * i, 2 * j], Sblk[2 * i, 2 * j + 1]],
+                                        [Sblk[2 * i + 1, 2 * j], Sblk[2 * i + 1, 2 * j + 1]]])
+        # (b) LU of the diagonal blocks; Y_kj = D_kk^-1 D_kj, Yt_kj = D_kk^-T D_jk^T
+        dlu, Y, Yt = {}, {}, {}
+        for k in range(nb):
+            if not p.fill_in or m[k] == 0:
+                continue
+            dlu[k] = lu(D[k, k])
+            flops["fill"] += 2.0 / 3.0 * m[k] ** 3
+            for j in near[lev][k]:
+                if j != k:
+                    Y[k, j] = sla.lu_solve(dlu[k], D[k, j], check_finite=False)
+                    Yt[k, j] = sla.lu_solve(dlu[k], D[j, k].T, trans=1, check_finite=False)
+        fac.cand[lev] = PU[lev]
+        fac.cand_col[lev] = PV[lev]
+        bf = [None] * nb
+        for i in range(nb):
+            targets = fill_targets(near[lev], i) if p.fill_in else []
+            side = []
+            for s_ in (0, 1):
+                # s_ = 0: rows of A (U basis); s_ = 1: rows of A^T (V basis)
+                Fcols = []
+                for j in targets:
+                    F = np.zeros((m[i], m[j]))
+                    for k in near[lev][i]:
+                        if k == i or k == j or m[k] == 0 or j not in near[lev][k]:
+                            continue
+                        F += D[i, k] @ Y[k, j] if s_ == 0 else D[k, i].T @ Yt[k, j]
+                        flops["fill"] += 2.0 * m[i] * m[k] * m[j]
+                    Fcols.append(F)
+                if p.fill_in:
+                    flops["fill"] += sum(2.0 * m[i] * m[k] ** 2 for k in near[lev][i] if k != i)
+                Fi = np.concatenate(Fcols, axis=1) if Fcols else np.zeros((m[i], 0))
+                Th = ThU if s_ == 0 else ThV
+                if lev < L and m[i] > 0:
+                    Fi = _block_tri_solve(Th[i], Fi)
+                Pown = (PU if s_ == 0 else PV)[lev]
+                fcols = far_columns(tree, near, far, lev, i, PV if s_ == 0 else PU, p.far_sample)
+                if s_ == 0:
+                    Kf = kernel_block(X, Pown[i], fcols, p)
+                else:
+                    Kf = kernel_block(X, fcols, Pown[i], p).T
+                kevals += Kf.size
+                M = np.concatenate([Kf, Fi], axis=1)
+                ncol = M.shape[1]
+                steps = min(m[i], ncol)
+                if steps > 0:
+                    piv, R, dg = pivoted_qr(M)
+                    flops["basis"] += (2.0 * ncol * m[i] ** 2 - 2.0 / 3.0 * m[i] ** 3
+                                       if ncol >= m[i] else
+                                       2.0 * m[i] * ncol ** 2 - 2.0 / 3.0 * ncol ** 3)
+                else:
+                    piv, R, dg = np.arange(m[i], dtype=np.int64), None, np.zeros(0)
+                side.append((piv, R, dg, ncol, steps, Pown[i], Th))
+            kU = id_rank(side[0][2], p.tol, p.rank_cap, m[i], side[0][3])
+            kV = id_rank(side[1][2], p.tol, p.rank_cap, m[i], side[1][3])
+            k = min(max(kU, kV), side[0][4], side[1][4])
+            out = []
+            for piv, R, dg, ncol, steps, Pown, Th in side:
+                Wp = id_matrix(piv, R, m[i], k) if k else np.zeros((m[i], 0))
+                W = _block_tri_mul(Th[i], Wp) if (lev < L and m[i] > 0) else Wp
+                B, T = complement_basis(W)
+                flops["basis"] += 4.0 * m[i] * k * k + 4.0 * m[i] ** 2 * k
+                out.append((B, T, np.asarray(Pown)[piv[:k]], piv, dg))
+            (U, TU, skU, pU, dU), (V, TV, skV, pV, dV) = out
+            bf[i] = BoxFactor(m[i], k, U, TU, skU, pU, absdiag=dU, V=V, TV=TV, skV=skV, pivV=pV,
+                              absdiagV=dV)
+        # (d) low-rank couplings
+        Snew = {}
+        for i in range(nb):
+            for j in far[lev][i]:
+                Kc = kernel_block(X, bf[i].sk, bf[j].skV, p)
+                kevals += Kc.size
+                Snew[i, j] = bf[i].T @ Kc @ bf[j].TV.T
+                ki, kj = bf[i].k, bf[j].k
+                flops["couple"] += 2.0 * ki * ki * kj + 2.0 * ki * kj * kj
+        # (e) rotation + (f) elimination
+        for i in range(nb):
+            Ui, Vi, ki = bf[i].U, bf[i].V, bf[i].k
+            for j in near[lev][i]:
+                if j == i:
+                    continue
+                kj = bf[j].k
+                Snew[i, j] = Ui[:, :ki].T @ D[i, j] @ bf[j].V[:, :kj]
+                if ki and kj:
+                    flops["rotate"] += 2.0 * m[i] * m[j] * kj + 2.0 * ki * m[i] * kj
+            S = Ui.T @ D[i, i] @ Vi
+            flops["rotate"] += 4.0 * m[i] ** 3
+            r = m[i] - ki
+            if r > 0:
+                lu_, lp = lu(S[ki:, ki:])
+                URS = lower_solve(lu_, apply_pinv(lp, S[ki:, :ki]))
+                LSR = sla.solve_triangular(lu_, S[:ki, ki:].T, trans="T", lower=False,
+                                           check_finite=False).T if ki else np.zeros((0, r))
+                Snew[i, i] = S[:ki, :ki] - LSR @ URS
+                bf[i].lu, bf[i].lupiv, bf[i].URS, bf[i].LSR = lu_, lp, URS, LSR
+                flops["elim"] += 2.0 / 3.0 * r ** 3 + 2.0 * r * r * ki + 2.0 * ki * ki * r
+            else:
+                Snew[i, i] = S[:ki, :ki].copy()
+        fac.levels[lev] = bf
+        if lev > 1:
+            PU[lev - 1] = [np.concatenate([bf[2 * q].sk, bf[2 * q + 1].sk]) for q in range(nb // 2)]
+            PV[lev - 1] = [np.concatenate([bf[2 * q].skV, bf[2 * q + 1].skV])
+                           for q in range(nb // 2)]
+            ThU = [[bf[2 * q].T, bf[2 * q + 1].T] for q in range(nb // 2)]
+            ThV = [[bf[2 * q].TV, bf[2 * q + 1].TV] for q in range(nb // 2)]
+        Sblk = Snew
+    D0 = np.block([[Sblk[0, 0], Sblk[0, 1]], [Sblk[1, 0], Sblk[1, 1]]])
+    fac.m_root = D0.shape[0]
+    fac.root_lu = lu(D0) if fac.m_root > 0 else (D0, np.zeros(0, dtype=np.int32))
+    flops["root"] += 2.0 / 3.0 * fac.m_root ** 3
+    fac.stats = {"flops": flops, "kevals": kevals}
+    return fac
+
+
 # ---------------------------------------------------------------------------
 # Solve (Sec. II-B: L z = U^T b, U y = z, x = V^T y, applied level by level)
 # ---------------------------------------------------------------------------
@@ -888,9 +1124,9 @@ def solve(fac: Factor, B: np.ndarray) -> np.ndarray:
         for i, (f, xS) in enumerate(zip(fac.levels[L], parts)):
             if f.m - f.k > 0:
                 xR = upper_solve(f.lu, saved[L, i] - f.URS @ xS)
-                nxt.append(f.U @ np.concatenate([xS, xR]))
+                nxt.append(right_basis(f) @ np.concatenate([xS, xR]))
             else:
-                nxt.append(f.U @ xS)
+                nxt.append(right_basis(f) @ xS)
         xs = nxt
     # backward
     for lev in ([] if flat else range(1, L + 1)):
@@ -903,9 +1139,9 @@ def solve(fac: Factor, B: np.ndarray) -> np.ndarray:
                 f = bf[i]
                 if f.m - f.k > 0:
                     xR = upper_solve(f.lu, saved[lev, i] - f.URS @ xS)
-                    nxt.append(f.U @ np.concatenate([xS, xR]))
+                    nxt.append(right_basis(f) @ np.concatenate([xS, xR]))
                 else:
-                    nxt.append(f.U @ xS)
+                    nxt.append(right_basis(f) @ xS)
         xs = nxt
     xt = np.concatenate(xs)
     out = np.empty_like(xt)
@@ -948,8 +1184,9 @@ def refine(fac: Factor, B: np.ndarray, rtol: float = 1e-10, max_iter: int = 20):
 def assemble_dense(fac: Factor) -> np.ndarray:
     """The matrix A~ that the factorization represents exactly, assembled densely
     in the original point order: at each level
-      A~_l = U_l [[blkdiag S^RR, blkdiag S^RS], [blkdiag S^SR, A~_{l-1} + blkdiag S^SR S^RR^-1 S^RS]] U_l^T
-    (rows of each box ordered [S; R]); the flat BLR^2 structure has the leaf
+      A~_l = U_l [[blkdiag S^RR, blkdiag S^RS], [blkdiag S^SR, A~_{l-1} + blkdiag S^SR S^RR^-1 S^RS]] V_l^T
+    (rows of each box ordered [S; R]; V = U for shared bases, the right factor
+    is V^T for separate ones); the flat BLR^2 structure has the leaf
     level alone, its root holding every leaf's skeleton.  Small N only."""
     tree = fac.tree
     L = tree.L
@@ -994,7 +1231,8 @@ def assemble_dense(fac: Factor) -> np.ndarray:
         order = np.concatenate([np.r_[s.start:s.stop, r.start:r.stop] for s, r in pos]).astype(np.int64)
         Gb = G[np.ix_(order, order)]
         Ubig = sla.block_diag(*[f.U for f in bf]) if bf else np.zeros((0, 0))
-        A = Ubig @ Gb @ Ubig.T
+        Vbig = sla.block_diag(*[right_basis(f) for f in bf]) if bf else np.zeros((0, 0))
+        A = Ubig @ Gb @ Vbig.T
     out = np.empty_like(A)
     out[np.ix_(tree.perm, tree.perm)] = A
     return out

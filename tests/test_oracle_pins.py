@@ -387,3 +387,99 @@ def test_blr2_self_consistency_and_accuracy():
     assert _rel(x, np.linalg.solve(A, b)) < 1e-3
     fh = O.factorize(X, O.Params(leaf=64, tol=1e-6, far_sample=0))
     assert f.m_root > fh.m_root
+
+
+# --- separate row and column bases (Sec. III-C, Eq. fillu / fillv) ------------
+DRIFT = (0.6, -0.3, 0.5)
+
+
+def test_advection_kernel_closed_form():
+    """exp(b.(x - y) - alpha r)/r: the entry at a hand-computed pair, the
+    transposition K_b(x, y) = K_-b(y, x), and b = 0 gives the Yukawa kernel."""
+    X = np.array([[0.0, 0, 0], [3.0, 4.0, 0], [0, 0, 2.0]])
+    p = O.Params(kernel=O.ADVECTION, alpha=1.0, drift=(0.5, 0.0, 0.25), diag=7.0)
+    K = O.kernel_block(X, np.arange(3), np.arange(3), p)
+    # x_0 - x_1 = (-3, -4, 0): b.d = -1.5, r = 5
+    assert abs(K[0, 1] - math.exp(-1.5 - 5.0) / 5.0) < 1e-18
+    assert abs(K[1, 0] - math.exp(1.5 - 5.0) / 5.0) < 1e-17
+    assert np.all(np.diag(K) == 7.0)
+    pm = O.Params(kernel=O.ADVECTION, alpha=1.0, drift=(-0.5, 0.0, -0.25), diag=7.0)
+    assert np.array_equal(O.kernel_block(X, np.arange(3), np.arange(3), pm), K.T)
+    py = O.Params(kernel=O.YUKAWA, alpha=1.0, diag=7.0)
+    p0 = O.Params(kernel=O.ADVECTION, alpha=1.0, drift=(0.0, 0.0, 0.0), diag=7.0)
+    assert np.allclose(O.kernel_block(X, np.arange(3), np.arange(3), p0),
+                       O.kernel_block(X, np.arange(3), np.arange(3), py), rtol=1e-15, atol=0)
+
+
+def test_two_sided_full_rank_equals_dense_lu():
+    """Nonsymmetric matrix, tol = 0, exact far field: nothing is truncated and
+    the two-sided factorization solves like dense LU."""
+    X = W.cube_points(900, 3)
+    p = O.Params(kernel=O.ADVECTION, alpha=1.0, drift=DRIFT, leaf=64, tol=0.0, far_sample=0)
+    A = O.dense_matrix(X, p)
+    assert np.linalg.norm(A - A.T) > 1e-2 * np.linalg.norm(A)
+    b = W.gaussian_rhs(900, 2, 5)
+    f = O.factorize(X, p)
+    assert _rel(O.solve(f, b), np.linalg.solve(A, b)) < 1e-11
+
+
+def test_two_sided_self_consistency_and_accuracy():
+    """The solve is exact for the represented matrix A~ = U G V^T, log|det A~|
+    is the sum over the LU diagonals, and A~ approximates A to the tolerance;
+    the column bases differ from the row bases."""
+    X = W.cube_points(1500, 3)
+    p = O.Params(kernel=O.ADVECTION, alpha=1.0, drift=DRIFT, leaf=64, tol=1e-8, far_sample=0)
+    f = O.factorize(X, p)
+    At = O.assemble_dense(f)
+    b = W.gaussian_rhs(1500, 1, 5)[:, 0]
+    x = O.solve(f, b)
+    assert _rel(x, np.linalg.solve(At, b)) < 1e-12
+    sgn, ld = np.linalg.slogdet(At)
+    assert abs(O.logabsdet(f) - ld) < 1e-9 * abs(ld)
+    A = O.dense_matrix(X, p)
+    assert _rel(x, np.linalg.solve(A, b)) < 2e-5        # measured 2.0e-6
+    diff = [np.abs(bb.U[:, :bb.k] @ bb.U[:, :bb.k].T - bb.V[:, :bb.k] @ bb.V[:, :bb.k].T).max()
+            for bfl in f.levels.values() for bb in bfl if 0 < bb.k < bb.m]
+    assert diff and max(diff) > 1e-3
+    for lev, bfl in f.levels.items():
+        for bb in bfl:
+            if bb.m:
+                assert np.abs(bb.V.T @ bb.V - np.eye(bb.m)).max() < 1e-13 * bb.m
+
+
+def test_separate_bases_on_symmetric_kernel_match_shared():
+    """For a symmetric matrix the column fill-ins are the transposed row
+    fill-ins and the column basis is the row basis: separate bases reproduce
+    the shared-basis factorization (ranks, skeleton sets, solution)."""
+    X = W.cube_points(1500, 3)
+    b = W.gaussian_rhs(1500, 1, 5)[:, 0]
+    fs = O.factorize(X, O.Params(leaf=64, tol=1e-8, far_sample=0, bases="separate"))
+    fh = O.factorize(X, O.Params(leaf=64, tol=1e-8, far_sample=0))
+    for lev in fh.levels:
+        for a, c in zip(fs.levels[lev], fh.levels[lev]):
+            assert a.k == c.k
+            assert sorted(a.sk.tolist()) == sorted(c.sk.tolist()) == sorted(a.skV.tolist())
+    assert _rel(O.solve(fs, b), O.solve(fh, b)) < 1e-9
+
+
+def test_column_basis_is_row_basis_of_transpose():
+    """Eq. fillv: the column basis of A is the row basis of A^T.  A^T is the
+    same kernel with the drift reversed; its row skeletons and bases equal the
+    column skeletons and bases of A (and vice versa), and its solution solves
+    A^T x = b."""
+    X = W.cube_points(1200, 6)
+    kw = dict(kernel=O.ADVECTION, alpha=1.0, leaf=64, tol=1e-8, far_sample=0)
+    f = O.factorize(X, O.Params(drift=DRIFT, **kw))
+    g = O.factorize(X, O.Params(drift=tuple(-v for v in DRIFT), **kw))
+    for lev in f.levels:
+        for a, c in zip(f.levels[lev], g.levels[lev]):
+            assert a.k == c.k
+            assert sorted(a.skV.tolist()) == sorted(c.sk.tolist())
+            assert sorted(a.sk.tolist()) == sorted(c.skV.tolist())
+            if a.k:
+                P1 = a.V[:, :a.k] @ a.V[:, :a.k].T
+                P2 = c.U[:, :c.k] @ c.U[:, :c.k].T
+                assert np.abs(P1 - P2).max() < 1e-8
+    A = O.dense_matrix(X, O.Params(drift=DRIFT, **kw))
+    b = W.gaussian_rhs(1200, 1, 2)[:, 0]
+    assert _rel(O.solve(g, b), np.linalg.solve(A.T, b)) < 1e-5
