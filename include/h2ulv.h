@@ -50,7 +50,7 @@ typedef enum {
   H2ULV_ERR_NOT_CONVERGED = -6     /* refinement did not reach the tolerance */
 } h2ulv_status;
 
-enum { H2ULV_LAPLACE = 0, H2ULV_YUKAWA = 1 };
+enum { H2ULV_LAPLACE = 0, H2ULV_YUKAWA = 1, H2ULV_ADVECTION = 2 };
 enum { H2ULV_FP64 = 0, H2ULV_MIXED = 1 };
 
 /*
@@ -60,7 +60,10 @@ enum { H2ULV_FP64 = 0, H2ULV_MIXED = 1 };
  */
 typedef struct h2ulv_params {
   int32_t struct_size; /* sizeof(h2ulv_params); set by h2ulv_params_default */
-  int32_t kernel;      /* H2ULV_LAPLACE: 1/r; H2ULV_YUKAWA: exp(-alpha r)/r    */
+  int32_t kernel;      /* H2ULV_LAPLACE: 1/r; H2ULV_YUKAWA: exp(-alpha r)/r;
+                          H2ULV_ADVECTION: exp(b.(x_i - x_j) - alpha r)/r with
+                          b = drift, the steady advection-diffusion Green's
+                          function (not symmetric for b != 0)                   */
   double alpha;        /* Yukawa decay constant                                 */
   double diag;         /* A_ii                                                  */
   double eta;          /* admissible iff |c_i - c_j| > eta (r_i + r_j); >= 0    */
@@ -95,6 +98,14 @@ typedef struct h2ulv_params {
                           and after the leaf sweep all skeletons form one dense
                           root block (Eq. BLR2final); levels above the leaves
                           hold nothing (their accessors return INVALID_ARG)    */
+  int32_t bases;        /* 0 (default): one shared basis per box (V = U) for the
+                          symmetric kernels, separate row and column bases for
+                          H2ULV_ADVECTION.  1: separate bases for any kernel.
+                          Separate bases (Sec. III-C: U from [F_i+ A_i+], V from
+                          [F_+j^T A_+j^T], Eq. fillu/fillv) need structure 0,
+                          precision FP64 and no rank model                     */
+  int32_t reserved;
+  double drift[3];      /* b of H2ULV_ADVECTION (ignored by the other kernels)  */
 } h2ulv_params;
 
 typedef struct h2ulv_factor h2ulv_factor; /* opaque */
@@ -283,12 +294,19 @@ h2ulv_status h2ulv_get_stats(const h2ulv_factor* f, h2ulv_stats* s);
  *                       indices (original numbering) in pivot order.
  *   h2ulv_get_basis:  U (m x m column-major, [U^S U^R]) of a box; copies from
  *                     the device and synchronises the stream.
+ *   h2ulv_get_column_skeleton, h2ulv_get_column_basis: the same for the
+ *                     column side, V (m x m, [V^S V^R]) and the column
+ *                     skeletons (Sec. III-C, Eq. fillv); with shared bases
+ *                     (V = U) they return the row side's.
  */
 h2ulv_status h2ulv_get_levels(const h2ulv_factor* f, int32_t* L);
 h2ulv_status h2ulv_get_perm(const h2ulv_factor* f, int64_t* perm);
 h2ulv_status h2ulv_get_ranks(const h2ulv_factor* f, int32_t lev, int32_t* m, int32_t* k);
 h2ulv_status h2ulv_get_skeleton(const h2ulv_factor* f, int32_t lev, int32_t box, int64_t* sk);
 h2ulv_status h2ulv_get_basis(const h2ulv_factor* f, int32_t lev, int32_t box, double* U);
+h2ulv_status h2ulv_get_column_skeleton(const h2ulv_factor* f, int32_t lev, int32_t box,
+                                        int64_t* sk);
+h2ulv_status h2ulv_get_column_basis(const h2ulv_factor* f, int32_t lev, int32_t box, double* V);
 
 void h2ulv_destroy(h2ulv_factor* f);
 

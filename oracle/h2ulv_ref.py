@@ -124,6 +124,9 @@ def check_params(X: np.ndarray, p: Params) -> None:
         raise OracleError(ERR_INVALID_ARG, "unknown kernel or bad diagonal")
     if len(p.drift) != 3 or not all(math.isfinite(float(v)) for v in p.drift):
         raise OracleError(ERR_INVALID_ARG, "drift must be three finite numbers")
+    if p.kernel == ADVECTION and not math.sqrt(sum(float(v) ** 2 for v in p.drift)) <= p.alpha:
+        # decay in every direction: b.(x - y) <= |b| r <= alpha r
+        raise OracleError(ERR_INVALID_ARG, "the advection kernel needs alpha >= |drift|")
     if p.bases not in ("auto", "separate"):
         raise OracleError(ERR_INVALID_ARG, "bases must be auto or separate")
     if two_sided(p) and (p.rank_model is not None or p.structure != "h2"):

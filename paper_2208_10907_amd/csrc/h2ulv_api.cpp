@@ -129,9 +129,10 @@ static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, 
     g.one(x0, m0, m0, nrhs, m0, F.root_inv.as<double>(), m0, false, b0, m0, false);
     g.run(st, "solve");
   }
-  // backward
+  // backward: x = V [x^S; x^R] with the column bases (V = U for shared bases)
   for (int lev = top; lev <= L; ++lev) {
     const LevelFactor& lf = F.levels[lev];
+    const LevelFactor& rv = F.colview ? F.colview->levels[lev] : lf;
     GemmBatch<double> g1, g2;
     for (int i = 0; i < lf.nb; ++i) {
       int mi = lf.m[i], ki = lf.k[i], r = mi - ki;
@@ -162,9 +163,9 @@ static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, 
         ldo = mi;
       }
       g2.item(xo, ldo, mi, nrhs);
-      if (ki > 0) g2.term(lf.U.as<double>() + lf.offU[i], mi, false, xs, ldxs, false, ki);
+      if (ki > 0) g2.term(rv.U.as<double>() + rv.offU[i], mi, false, xs, ldxs, false, ki);
       if (r > 0)
-        g2.term(lf.U.as<double>() + lf.offU[i] + (int64_t)ki * mi, mi, false, wi, r, false, r);
+        g2.term(rv.U.as<double>() + rv.offU[i] + (int64_t)ki * mi, mi, false, wi, r, false, r);
     }
     g1.run(st, "solve");
     g2.run(st, "solve");
@@ -762,6 +763,9 @@ h2ulv_status h2ulv_params_default(h2ulv_params* p) {
   p->fill_in = 1;
   p->partition = 0;
   p->structure = 0;
+  p->bases = 0;
+  p->reserved = 0;
+  p->drift[0] = p->drift[1] = p->drift[2] = 0.0;
   return H2ULV_OK;
 }
 
@@ -956,6 +960,33 @@ h2ulv_status h2ulv_get_skeleton(const h2ulv_factor* f, int32_t lev, int32_t box,
   const auto& v = f->levels[lev].sk[box];
   std::copy(v.begin(), v.end(), sk);
   return H2ULV_OK;
+}
+
+h2ulv_status h2ulv_get_column_skeleton(const h2ulv_factor* f, int32_t lev, int32_t box,
+                                        int64_t* sk) {
+  if (f && !f->colview) return h2ulv_get_skeleton(f, lev, box, sk);
+  if (!sk || !factored_level(f, lev) || box < 0 || box >= (1 << lev)) {
+    g_last_error = "bad level or box";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  const auto& v = f->colview->levels[lev].sk[box];
+  std::copy(v.begin(), v.end(), sk);
+  return H2ULV_OK;
+}
+
+h2ulv_status h2ulv_get_column_basis(const h2ulv_factor* f, int32_t lev, int32_t box, double* V) {
+  if (f && !f->colview) return h2ulv_get_basis(f, lev, box, V);
+  if (!V || !factored_level(f, lev) || box < 0 || box >= (1 << lev)) {
+    g_last_error = "bad level or box";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  return guarded([&] {
+    const LevelFactor& lf = f->colview->levels[lev];
+    int64_t mm = (int64_t)lf.m[box] * lf.m[box];
+    if (mm == 0) return;
+    H2ULV_HIP(hipMemcpy(V, lf.U.as<double>() + lf.offU[box], mm * sizeof(double),
+                        hipMemcpyDeviceToHost));
+  });
 }
 
 h2ulv_status h2ulv_get_basis(const h2ulv_factor* f, int32_t lev, int32_t box, double* U) {

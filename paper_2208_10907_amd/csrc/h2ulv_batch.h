@@ -643,9 +643,12 @@ struct GemmBatch {
 
 struct KgenBatch {
   std::vector<KgenItem> items;
-  void add(const int64_t* rows, int m, const int64_t* cols, int n, double* out, int64_t ld) {
+  // tr: entries of the transposed kernel K(x[cols], x[rows]) (the column side
+  // of a nonsymmetric matrix)
+  void add(const int64_t* rows, int m, const int64_t* cols, int n, double* out, int64_t ld,
+           bool tr = false) {
     if (m <= 0 || n <= 0) return;
-    items.push_back(KgenItem{rows, cols, out, ld, m, n});
+    items.push_back(KgenItem{rows, cols, out, ld, m, n, tr ? 1 : 0, 0});
   }
   void run(Stage& st, const double* pts, const KernelFn& kf, int* dup) {
     if (items.empty()) return;

@@ -35,7 +35,9 @@ double now_s() {
       .count();
 }
 
-KernelFn kfn(const h2ulv_params& p) { return KernelFn{p.kernel, p.alpha, p.diag}; }
+KernelFn kfn(const h2ulv_params& p) {
+  return KernelFn{p.kernel, p.alpha, p.diag, {p.drift[0], p.drift[1], p.drift[2]}};
+}
 
 namespace {
 
@@ -120,6 +122,10 @@ void check_info(const int32_t* dinfo, size_t n, hipStream_t s, const char* what)
 // and the state of the level being factored.
 struct Prob {
   h2ulv_factor* F = nullptr;
+  // separate bases: the row side (colside false) and the column side (the
+  // transposed matrix, colside true) of one problem point at each other
+  Prob* partner = nullptr;
+  bool colside = false;
   int64_t poff = 0;  // offset of its points in the shared point buffer
   double fl_fill = 0, fl_basis = 0, fl_couple = 0, fl_rotate = 0, fl_elim = 0, fl_root = 0,
          kevals = 0;
@@ -139,12 +145,15 @@ struct Prob {
   std::vector<std::vector<int64_t>> farcols;
   std::vector<int64_t> far_off;  // box i's far columns at dfar + far_off[i]
   DBuf dfar;
+  double* PQ0 = nullptr;  // separate bases: copy of PQ before pivoting (row_ids only)
   std::vector<const double*> Eptr;  // E = R11^-1 R12 of each box and its leading dimension
   std::vector<int64_t> ldE;
   std::vector<DBuf> Ebufs;
 
   int L() const { return F->tree.L; }
   LevelFactor& lf() { return F->levels[lev]; }
+  // the level factor holding the right-hand (column) bases of this level
+  LevelFactor& rlf() { return partner && !colside ? partner->lf() : lf(); }
   const std::vector<int64_t>& np() const { return F->lists.near_ptr[lev]; }
   const std::vector<int32_t>& ni() const { return F->lists.near_idx[lev]; }
   const std::vector<int64_t>& fp() const { return F->lists.far_ptr[lev]; }
@@ -261,7 +270,10 @@ struct Driver {
   // given their M' (kernel entries are not counted again)
   void build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebuild = false);
   void build_sketch(Stage& st, const std::vector<Box>& boxes, bool rebuild);
-  void pivot_boxes(Stage& st, const std::vector<Box>& boxes);
+  // force: per box of `boxes`, keep exactly that many pivots (tol 0, cap = it)
+  void pivot_boxes(Stage& st, const std::vector<Box>& boxes,
+                   const std::vector<int>* force = nullptr);
+  void couple_ranks(Stage& st, const std::vector<Prob*>& G);
   std::vector<Box> check_sketches(Stage& st, const std::vector<Box>& boxes);
   void row_ids(Stage& st, const std::vector<Prob*>& G);
   void bases(Stage& st, const std::vector<Prob*>& G);
@@ -287,6 +299,7 @@ void Driver::dense_blocks(Stage& st, const std::vector<Prob*>& G) {
         P->Doff[e + 1] = P->Doff[e] + (int64_t)m[i] * m[ni[e]];
     P->D.alloc(std::max<int64_t>(P->Doff[nnear], 1) * sizeof(double));
     double* Dp = P->D.as<double>();
+    if (P->colside) continue;  // transposed copies of the row side's blocks, below
     if (P->lev == P->L()) {
       for (int i = 0; i < nb; ++i)
         for (int64_t e = np[i]; e < np[i + 1]; ++e) {
@@ -318,6 +331,45 @@ void Driver::dense_blocks(Stage& st, const std::vector<Prob*>& G) {
   }
   kb.run(st, pts, kf, dup);
   cb.run(st);
+  // the column side works on A^T: D'_ij = D_ji^T, i.e. the leaf blocks of the
+  // row side transposed, and above the leaves the children's S^SS blocks of
+  // the row side transposed
+  CopyBatch ct;
+  for (Prob* P : G) {
+    if (!P->colside) continue;
+    Prob* R = P->partner;
+    const std::vector<int>& m = P->lf().m;
+    const auto& np = P->np();
+    const auto& ni = P->ni();
+    double* Dp = P->D.as<double>();
+    for (int i = 0; i < P->nb; ++i)
+      for (int64_t e = np[i]; e < np[i + 1]; ++e) {
+        const int j = ni[e];
+        if (P->lev == P->L()) {
+          ct.add(R->Dblk(j, i), std::max(m[j], 1), Dp + P->Doff[e], std::max(m[i], 1), m[i],
+                 m[j], true);
+          continue;
+        }
+        const std::vector<int>& kc = P->F->levels[P->lev + 1].k;
+        int ro = 0;
+        for (int a = 0; a < 2; ++a) {
+          const int c = 2 * i + a;
+          int co = 0;
+          for (int b = 0; b < 2; ++b) {
+            const int d = 2 * j + b;
+            if (kc[c] > 0 && kc[d] > 0) {
+              int64_t ld;
+              const double* src = R->shat_block(P->lev + 1, d, c, &ld);
+              ct.add(src, std::max<int64_t>(ld, 1), Dp + P->Doff[e] + ro + (int64_t)co * m[i],
+                     std::max(m[i], 1), kc[c], kc[d], true);
+            }
+            co += kc[d];
+          }
+          ro += kc[c];
+        }
+      }
+  }
+  ct.run(st);
   st.sync();
   for (Prob* P : G) P->Shat.reset();  // children's skeleton blocks are merged now
 }
@@ -336,6 +388,7 @@ void Driver::fill_products(Stage& st, const std::vector<Prob*>& G) {
       P->Dinv.alloc(std::max<int64_t>(P->offSq[nb], 1) * sizeof(double));
       LUw.emplace_back(std::max<int64_t>(P->offSq[nb], 1) * sizeof(double));
       double* W = LUw.back().as<double>();
+      if (P->colside) continue;  // (D_ii^T)^-1 = (D_ii^-1)^T, copied below
       for (int i = 0; i < nb; ++i) {
         if (m[i] == 0) continue;
         cb.add(P->Dblk(i, i), m[i], W + P->offSq[i], m[i], m[i], m[i]);
@@ -347,6 +400,16 @@ void Driver::fill_products(Stage& st, const std::vector<Prob*>& G) {
     int32_t* info = nullptr;
     batched_inverse(st, mats, &info, nullptr, nullptr);
     check_info(info, mats.size(), s, "a diagonal block (fill-in step)");
+    CopyBatch ct;
+    for (Prob* P : G) {
+      if (!P->colside) continue;
+      const std::vector<int>& m = P->lf().m;
+      for (int i = 0; i < P->nb; ++i)
+        if (m[i] > 0)
+          ct.add(P->partner->Dinv.as<double>() + P->offSq[i], m[i],
+                 P->Dinv.as<double>() + P->offSq[i], m[i], m[i], m[i], true);
+    }
+    ct.run(st);
     st.sync();
   }
   tick("b_inverse");
@@ -472,7 +535,11 @@ void Driver::basis_prepare(Stage& st, const std::vector<Prob*>& G) {
     parallel_for(nb, 8, [&](int64_t i) {
       // the ablation without fill-ins in the basis has no fill targets
       if (p.fill_in) P->targets[i] = fill_targets(ls, P->lev, (int)i);
-      P->farcols[i] = far_columns(P->F->tree, ls, P->lev, (int)i, lf.cand, p.far_sample);
+      // own-level far boxes are sampled at their candidates of the other side
+      // (the columns of the far blocks for the row basis, the rows for the column
+      // basis); shared bases have one candidate set
+      const auto& fc = P->partner ? P->partner->lf().cand : lf.cand;
+      P->farcols[i] = far_columns(P->F->tree, ls, P->lev, (int)i, fc, p.far_sample);
       int64_t nc = (int64_t)P->farcols[i].size();
       for (int j : P->targets[i]) nc += m[j];
       P->ncols[i] = nc;
@@ -824,7 +891,9 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
       double* Mi = Mp + moff[q];
       const int64_t ld = P->ncols[i];
       const int64_t nf = (int64_t)P->farcols[i].size();
-      kb.add(P->farp(i), (int)nf, P->candp(i), m[i], Mi, ld);
+      // M'^T(a, b) = K(cand_b, far_a) (row side; the column side of a
+      // nonsymmetric matrix has M'^T(a, b) = K(far_a, cand_b))
+      kb.add(P->farp(i), (int)nf, P->candp(i), m[i], Mi, ld, !P->colside);
       // a rebuilt box (a rejected sketch) has had its kernel entries counted
       if (!rebuild) P->kevals += (double)m[i] * nf;
       int64_t row = nf;
@@ -963,7 +1032,7 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
 // over many workgroups, one pivot step per pair of launches.  Ranks come back
 // to the host; E = R11^-1 R12 is left in place (small) or solved into a
 // buffer (large).
-void Driver::pivot_boxes(Stage& st, const std::vector<Box>& boxes) {
+void Driver::pivot_boxes(Stage& st, const std::vector<Box>& boxes, const std::vector<int>* force) {
   const int BIG = 512;
   struct Job {
     Prob* P;
@@ -991,6 +1060,11 @@ void Driver::pivot_boxes(Stage& st, const std::vector<Box>& boxes) {
     if (mi == 0) continue;
     int cap = (int)std::min<int64_t>(mi, P->ncols[i]);
     if (p.rank_cap > 0) cap = std::min(cap, p.rank_cap);
+    double tol = p.tol;
+    if (force) {
+      cap = std::min(cap, (*force)[q]);
+      tol = 0.0;
+    }
     int rows = mi;
     int64_t lda = mi;
     if (lf.sk_state[i] == 1) {
@@ -1012,7 +1086,7 @@ void Driver::pivot_boxes(Stage& st, const std::vector<Box>& boxes) {
       it.kout = P->kd.as<int32_t>() + i;
       it.diag = dg + co;
       it.work = nrm + co;
-      it.tol = p.tol;
+      it.tol = tol;
       it.cap = std::max(cap, 0);
       pq.push_back(it);
     } else {
@@ -1026,7 +1100,7 @@ void Driver::pivot_boxes(Stage& st, const std::vector<Box>& boxes) {
       ps.piv = P->pivd.as<int32_t>() + P->cand_off[i];
       ps.scal = scal + 2 * q;
       ps.flags = flg + 2 * q;
-      ps.tol = p.tol;
+      ps.tol = tol;
       jb.big = (int)big.size();
       big.push_back(ps);
     }
@@ -1203,6 +1277,52 @@ std::vector<Box> Driver::check_sketches(Stage& st, const std::vector<Box>& boxes
 
 // ---- (c) the basis step up to the pivots: sketches and triangles, pivoted QR,
 // checks and fallback; then skeletons on the host
+// Separate bases: the row and column IDs of a box keep the same number of
+// pivots, k = min(max(k_row, k_col), steps_row, steps_col) with steps =
+// min(m, columns of M'), so that S^RR stays square.  A side whose tolerance
+// rank differs pivots again from its saved triangle, keeping exactly k.
+void Driver::couple_ranks(Stage& st, const std::vector<Prob*>& G) {
+  for (int round = 0; round < 2; ++round) {
+    std::vector<Box> redo;
+    std::vector<int> want;
+    for (Prob* P : G) {
+      if (P->colside) continue;
+      Prob* C = P->partner;
+      LevelFactor& a = P->lf();
+      LevelFactor& b = C->lf();
+      for (int i = 0; i < P->nb; ++i) {
+        const int mi = a.m[i];
+        if (mi == 0) continue;
+        const int sa = (int)std::min<int64_t>(mi, P->ncols[i]);
+        const int sb = (int)std::min<int64_t>(mi, C->ncols[i]);
+        const int k = round == 0 ? std::min({std::max(a.k[i], b.k[i]), sa, sb})
+                                 : std::min(a.k[i], b.k[i]);
+        if (a.k[i] != k) {
+          redo.push_back(Box{P, i});
+          want.push_back(k);
+        }
+        if (b.k[i] != k) {
+          redo.push_back(Box{C, i});
+          want.push_back(k);
+        }
+      }
+    }
+    if (redo.empty()) return;
+    for (const Box& bx : redo) {
+      const int mi = bx.P->lf().m[bx.i];
+      const int64_t o = bx.P->offSq[bx.i];
+      H2ULV_HIP(hipMemcpyAsync(bx.P->PQ.as<double>() + o, bx.P->PQ0 + o,
+                               (size_t)mi * mi * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    pivot_boxes(st, redo, &want);
+  }
+  for (Prob* P : G)
+    if (!P->colside)
+      for (int i = 0; i < P->nb; ++i)
+        if (P->lf().k[i] != P->partner->lf().k[i])
+          fail(H2ULV_ERR_HIP, "internal: row and column ranks of a box differ");
+}
+
 void Driver::row_ids(Stage& st, const std::vector<Prob*>& G) {
   std::vector<Box> all, sk;
   for (Prob* P : G)
@@ -1211,7 +1331,16 @@ void Driver::row_ids(Stage& st, const std::vector<Prob*>& G) {
       if (P->lf().sk_state[i] == 1) sk.push_back(Box{P, i});
     }
   build_triangles(st, all);
+  const bool two = G.size() > 0 && G[0]->partner != nullptr;
+  std::vector<DBuf> keep;  // separate bases: the triangles before pivoting
+  if (two)
+    for (Prob* P : G) {
+      keep.emplace_back(P->PQ.bytes);
+      H2ULV_HIP(hipMemcpyAsync(keep.back().p, P->PQ.p, P->PQ.bytes, hipMemcpyDeviceToDevice, s));
+      P->PQ0 = keep.back().as<double>();
+    }
   pivot_boxes(st, all);
+  if (two) couple_ranks(st, G);
   if (!sk.empty()) {
     auto clear = [&](const Box& b) {
       const int mi = b.P->lf().m[b.i];
@@ -1375,8 +1504,10 @@ void Driver::couplings(Stage& st, const std::vector<Prob*>& G) {
       }
     P->Shat.alloc(std::max<int64_t>(tot, 1) * sizeof(double));
   }
+  // row skeletons of box i and column skeletons of box j (the same for shared
+  // bases): S^SS_ij = T_i K(sk_i, sk'_j) T'_j^T
   std::vector<int64_t> skall;
-  std::vector<std::vector<int64_t>> skoff(G.size()), kcoff(G.size());
+  std::vector<std::vector<int64_t>> skoff(G.size()), skoffc(G.size()), kcoff(G.size());
   for (size_t g = 0; g < G.size(); ++g) {
     Prob* P = G[g];
     const LevelFactor& lf = P->lf();
@@ -1384,6 +1515,14 @@ void Driver::couplings(Stage& st, const std::vector<Prob*>& G) {
     for (int i = 0; i < P->nb; ++i) {
       skoff[g][i] = (int64_t)skall.size();
       for (int64_t a : lf.sk[i]) skall.push_back(a + P->poff);
+    }
+    skoffc[g] = skoff[g];
+    if (P->partner) {
+      const LevelFactor& rl = P->rlf();
+      for (int i = 0; i < P->nb; ++i) {
+        skoffc[g][i] = (int64_t)skall.size();
+        for (int64_t a : rl.sk[i]) skall.push_back(a + P->poff);
+      }
     }
     const auto& fp = P->fp();
     const auto& fi = P->fi();
@@ -1407,7 +1546,7 @@ void Driver::couplings(Stage& st, const std::vector<Prob*>& G) {
       for (int64_t e = fp[i]; e < fp[i + 1]; ++e) {
         int j = fi[e];
         if (k[i] == 0 || k[j] == 0) continue;
-        kb.add(dsk + skoff[g][i], k[i], dsk + skoff[g][j], k[j], Kc[g] + kcoff[g][e], k[i]);
+        kb.add(dsk + skoff[g][i], k[i], dsk + skoffc[g][j], k[j], Kc[g] + kcoff[g][e], k[i]);
         P->kevals += (double)k[i] * k[j];
         P->fl_couple += 2.0 * k[i] * (double)k[j] * k[j] + 2.0 * k[i] * (double)k[i] * k[j];
       }
@@ -1419,6 +1558,7 @@ void Driver::couplings(Stage& st, const std::vector<Prob*>& G) {
     for (size_t g = 0; g < G.size(); ++g) {
       Prob* P = G[g];
       const LevelFactor& lf = P->lf();
+      const LevelFactor& rl = P->rlf();
       const std::vector<int>& k = lf.k;
       const auto& fp = P->fp();
       const auto& fi = P->fi();
@@ -1429,7 +1569,7 @@ void Driver::couplings(Stage& st, const std::vector<Prob*>& G) {
           if (k[i] == 0 || k[j] == 0) continue;
           const int64_t o = kcoff[g][e];
           g1.one(Tmp[g] + o, k[i], k[i], k[j], k[j], Kc[g] + o, k[i], false,
-                 lf.Tt.as<double>() + lf.offT[j], k[j], true);
+                 rl.Tt.as<double>() + rl.offT[j], k[j], true);
           g2.one(Sh + P->shat_far_off[e], k[i], k[i], k[j], k[i], lf.Tt.as<double>() + lf.offT[i],
                  k[i], false, Tmp[g] + o, k[i], false);
         }
@@ -1499,13 +1639,14 @@ void Driver::rotations(Stage& st, const std::vector<Prob*>& G) {
       if (!mixed) {
         double* Tmp = st.scratch<double>(std::max<int64_t>(toff.back(), 1));
         const double* U = lf.U.as<double>();
+        const LevelFactor& rl = P->rlf();  // V (= U for shared bases)
         const double* Dp = P->D.as<double>();
         for (int i = 0; i < P->nb; ++i)
           for (int64_t e = np[i]; e < np[i + 1]; ++e) {
             int j = ni[e];
             if (j == i || k[i] == 0 || k[j] == 0) continue;
             g1.one(Tmp + toff[e], m[i], m[i], k[j], m[j], Dp + P->Doff[e], m[i], false,
-                   U + lf.offU[j], m[j], false);
+                   rl.U.as<double>() + rl.offU[j], m[j], false);
             g2.one(Sh + P->shat_near_off[e], k[i], k[i], k[j], m[i], U + lf.offU[i], m[i], true,
                    Tmp + toff[e], m[i], false);
           }
@@ -1550,10 +1691,11 @@ void Driver::rotations(Stage& st, const std::vector<Prob*>& G) {
         Tmps.emplace_back(std::max<int64_t>(P->offSq[nb], 1) * sizeof(double));
         double* Tmp = Tmps.back().as<double>();
         const double* U = lf.U.as<double>();
+        const LevelFactor& rl = P->rlf();
         for (int i = 0; i < nb; ++i) {
           if (m[i] == 0) continue;
           g1.one(Tmp + P->offSq[i], m[i], m[i], m[i], m[i], P->Dblk(i, i), m[i], false,
-                 U + lf.offU[i], m[i], false);
+                 rl.U.as<double>() + rl.offU[i], m[i], false);
           g2.one(Sp + P->offSq[i], m[i], m[i], m[i], m[i], U + lf.offU[i], m[i], true,
                  Tmp + P->offSq[i], m[i], false);
         }
@@ -1732,11 +1874,16 @@ void Driver::level(const std::vector<Prob*>& G) {
   row_ids(st, G);
   bases(st, G);
   tick("c_basis_qr");
-  couplings(st, G);
+  // the column sides (separate bases) stop after their bases: the row side
+  // rotates with both and eliminates
+  std::vector<Prob*> rows;
+  for (Prob* P : G)
+    if (!P->colside) rows.push_back(P);
+  couplings(st, rows);
   tick("d_couple");
-  rotations(st, G);
+  rotations(st, rows);
   tick("e_rotate");
-  elimination(st, G);
+  elimination(st, rows);
   tick("f_elim");
   st.sync();
   for (Prob* P : G) {
@@ -1872,6 +2019,18 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
     F[q]->lists = build_structure_lists(F[q]->tree, params);
     F[q]->hpts = std::move(hp);
   }
+  // separate bases: each problem gets its column side, a factor of the
+  // transposed matrix on the same tree (bases only)
+  const bool two = separate_bases(params);
+  std::vector<std::unique_ptr<h2ulv_factor>> FV(two ? np : 0);
+  for (size_t q = 0; q < FV.size(); ++q) {
+    FV[q] = std::make_unique<h2ulv_factor>();
+    FV[q]->p = F[q]->p;
+    FV[q]->n = F[q]->n;
+    FV[q]->tree = F[q]->tree;
+    FV[q]->lists = F[q]->lists;
+    FV[q]->hpts = F[q]->hpts;
+  }
   double t1 = now_s();
   if (params.verbose) std::fprintf(stderr, "[h2ulv] host setup (tree, lists) %.3f s\n", t1 - t0);
   for (size_t q = 0; q < np; ++q) {
@@ -1886,7 +2045,7 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
   }
   // one point buffer for every kernel evaluation of the batch
   DBuf shared;
-  std::vector<Prob> probs(np);
+  std::vector<Prob> probs(two ? 2 * np : np);
   const double* allpts = F[0]->pts.as<double>();
   if (np > 1) {
     shared.alloc(ntot * 3 * sizeof(double));
@@ -1902,10 +2061,18 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
   mem_stats().peak = mem_stats().live;
   Driver drv(s, params);
   drv.pts = allpts;
+  for (size_t q = 0; q < FV.size(); ++q) {
+    Prob& C = probs[np + q];
+    C.F = FV[q].get();
+    C.poff = probs[q].poff;
+    C.colside = true;
+    C.partner = &probs[q];
+    probs[q].partner = &C;
+  }
   int H = 0;
-  for (size_t q = 0; q < np; ++q) {
+  for (size_t q = 0; q < probs.size(); ++q) {
     Prob& P = probs[q];
-    h2ulv_factor& f = *F[q];
+    h2ulv_factor& f = q < np ? *F[q] : *FV[q - np];
     P.F = &f;
     const int L = f.tree.L;
     H = std::max(H, L);
@@ -1922,13 +2089,18 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
   // flat structure has the leaf level only.
   const bool flat = params.structure == 1;
   for (int h = 0; h < (flat ? std::min(H, 1) : H); ++h) {
+    // a problem and its column side stay in one group
     std::vector<Prob*> act;
-    for (Prob& P : probs)
-      if (P.F->tree.L - h >= 1) {
-        P.lev = P.F->tree.L - h;
-        P.nb = 1 << P.lev;
-        act.push_back(&P);
+    for (size_t q = 0; q < np; ++q) {
+      Prob& P = probs[q];
+      if (P.F->tree.L - h < 1) continue;
+      for (Prob* Q : {&P, P.partner}) {
+        if (!Q) continue;
+        Q->lev = Q->F->tree.L - h;
+        Q->nb = 1 << Q->lev;
+        act.push_back(Q);
       }
+    }
     const size_t freeb = free_device_bytes();
     const double cap = 0.45 * (double)freeb;
     const bool mixed = params.precision == H2ULV_MIXED;
@@ -1938,10 +2110,12 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
       std::vector<Prob*> grp;
       double acc = 0;
       while (a0 < act.size()) {
-        double b = act[a0]->level_bytes(mixed);
+        const size_t w = act[a0]->partner ? 2 : 1;
+        double b = 0;
+        for (size_t u = 0; u < w; ++u) b += act[a0 + u]->level_bytes(mixed);
         if (!grp.empty() && acc + b > cap) break;
         acc += b;
-        grp.push_back(act[a0++]);
+        for (size_t u = 0; u < w; ++u) grp.push_back(act[a0++]);
       }
       drv.level(grp);
       if (params.verbose) {
@@ -1964,7 +2138,7 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
   }
   {
     std::vector<Prob*> all;
-    for (Prob& P : probs) all.push_back(&P);
+    for (size_t q = 0; q < np; ++q) all.push_back(&probs[q]);
     drv.roots(all);
   }
   H2ULV_HIP(hipStreamSynchronize(s));
@@ -1981,17 +2155,20 @@ std::vector<h2ulv_factor*> factorize_many(const std::vector<const double*>& pts,
     for (auto& lf : f.levels)
       for (int x : lf.k) mx = std::max(mx, x);
     st.max_rank = mx;
-    st.flops_fill = P.fl_fill;
-    st.flops_basis = P.fl_basis;
+    // the column side's work (separate bases) is part of the factorization
+    const Prob* C = P.partner;
+    st.flops_fill = P.fl_fill + (C ? C->fl_fill : 0.0);
+    st.flops_basis = P.fl_basis + (C ? C->fl_basis : 0.0);
     st.flops_couple = P.fl_couple;
     st.flops_rotate = P.fl_rotate;
     st.flops_elim = P.fl_elim;
     st.flops_root = P.fl_root;
-    st.kernel_evals = P.kevals;
+    st.kernel_evals = P.kevals + (C ? C->kevals : 0.0);
     st.time_setup_s = t1 - t0;
     st.time_factor_s = t2 - t0;
     st.device_bytes = (double)mem_stats().peak;
   }
+  for (size_t q = 0; q < FV.size(); ++q) F[q]->colview = std::move(FV[q]);
   for (size_t q = 0; q < np; ++q) out[q] = F[q].release();
   return out;
 }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -65,6 +66,10 @@ struct h2ulv_factor {
   // temporaries of later calls on this factor
   h2ulv_allocator alloc{};
   bool has_alloc = false;
+  // separate row and column bases: the column side of the factorization, the
+  // row bases of the transposed matrix (its levels hold V, T_V and the column
+  // skeletons in U, Tt and sk; its elimination fields stay empty)
+  std::unique_ptr<h2ulv_factor> colview;
 };
 
 struct h2ulv_rankmodel {

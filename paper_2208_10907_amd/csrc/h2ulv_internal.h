@@ -74,6 +74,8 @@ Tree build_tree(const double* pts, int64_t n, int leaf, int partition);
 Lists build_lists(const Tree& t, double eta);
 // flat BLR^2 lists: the leaf level only (upper levels empty)
 Lists build_flat_lists(const Tree& t, double eta);
+// separate row and column bases (nonsymmetric kernel, or asked for)
+bool separate_bases(const h2ulv_params& p);
 // the lists of the structure params.structure selects
 Lists build_structure_lists(const Tree& t, const h2ulv_params& p);
 void validate_params(const h2ulv_params* p);

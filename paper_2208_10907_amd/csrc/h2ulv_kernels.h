@@ -8,9 +8,10 @@
 namespace h2ulv {
 
 struct KernelFn {
-  int kind;      // 0 Laplace 1/r, 1 Yukawa exp(-alpha r)/r
+  int kind;      // 0 Laplace 1/r, 1 Yukawa exp(-alpha r)/r, 2 exp(b.(x - y) - alpha r)/r
   double alpha;
   double diag;   // value where row point == column point
+  double b[3];   // drift of kind 2
 };
 
 // out[a + b*ld] = K(x[rows[a]], x[cols[b]])   (a < m, b < n)
@@ -20,6 +21,8 @@ struct KgenItem {
   double* out;
   int64_t ld;
   int32_t m, n;
+  int32_t tr;   // 1: entries of the transposed kernel, K(x[cols[b]], x[rows[a]])
+  int32_t pad;
 };
 
 // C = beta C + alpha * sum_t op(A_t) op(B_t); op(A) is M x K, op(B) is K x N.

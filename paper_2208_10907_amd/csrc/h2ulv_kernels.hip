@@ -30,10 +30,14 @@ __device__ __forceinline__ int find_item(const int64_t* ptr, int n, int64_t tile
   return lo;
 }
 
-__device__ __forceinline__ double kernel_value(const KernelFn& kf, double r2) {
+// K(x, y) with d = x - y, r2 = |d|^2 > 0; sgn = -1 evaluates K(y, x)
+__device__ __forceinline__ double kernel_value(const KernelFn& kf, double r2, double dx,
+                                               double dy, double dz, double sgn) {
   double r = sqrt(r2);
   if (kf.kind == 0) return 1.0 / r;
-  return exp(-kf.alpha * r) / r;
+  if (kf.kind == 1) return exp(-kf.alpha * r) / r;
+  const double bd = sgn * (kf.b[0] * dx + kf.b[1] * dy + kf.b[2] * dz);
+  return exp(bd - kf.alpha * r) / r;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -87,6 +91,7 @@ __global__ __launch_bounds__(256) void kgen_kernel(const KgenItem* __restrict__ 
   if (a >= it.m) return;
   int64_t ra = it.rows[a];
   double xa = pts[3 * ra], ya = pts[3 * ra + 1], za = pts[3 * ra + 2];
+  const double sgn = it.tr ? -1.0 : 1.0;
   bool dup = false;
   for (int q = 0; q < 16; ++q) {
     int b = b0 + 4 * q;
@@ -102,7 +107,7 @@ __global__ __launch_bounds__(256) void kgen_kernel(const KgenItem* __restrict__ 
         dup = true;
         v = 0.0;
       } else {
-        v = kernel_value(kf, r2);
+        v = kernel_value(kf, r2, dx, dy, dz, sgn);
       }
     }
     it.out[a + (int64_t)b * it.ld] = v;
@@ -1936,22 +1941,23 @@ __device__ __forceinline__ double inv_sqrt(double r2) {
 // the tile holds target indices, whose self term (r^2 = 0) is excluded by a
 // select; other tiles have r^2 > 0 throughout, since the points are distinct
 // (a factorization rejects coinciding points).
-template <int NR, bool LAP, bool SELF>
+template <int NR, int KIND, bool SELF>
 __device__ __forceinline__ void matvec_tile(const double (*sp)[256], const double (*sx)[256],
                                             int cnt, const double* p0, const double* p1,
-                                            double alpha, double* a0, double* a1) {
+                                            const KernelFn& kf, double* a0, double* a1) {
   for (int t = 0; t < cnt; ++t) {
     const double sx0 = sp[0][t], sy0 = sp[1][t], sz0 = sp[2][t];
-    double dx = p0[0] - sx0, dy = p0[1] - sy0, dz = p0[2] - sz0;
-    const double q0 = fma(dx, dx, fma(dy, dy, dz * dz));
-    dx = p1[0] - sx0;
-    dy = p1[1] - sy0;
-    dz = p1[2] - sz0;
-    const double q1 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double dx0 = p0[0] - sx0, dy0 = p0[1] - sy0, dz0 = p0[2] - sz0;
+    const double q0 = fma(dx0, dx0, fma(dy0, dy0, dz0 * dz0));
+    const double dx1 = p1[0] - sx0, dy1 = p1[1] - sy0, dz1 = p1[2] - sz0;
+    const double q1 = fma(dx1, dx1, fma(dy1, dy1, dz1 * dz1));
     double k0 = inv_sqrt(q0), k1 = inv_sqrt(q1);
-    if (!LAP) {
-      k0 *= exp(-alpha * (q0 * k0));
-      k1 *= exp(-alpha * (q1 * k1));
+    if (KIND == 1) {
+      k0 *= exp(-kf.alpha * (q0 * k0));
+      k1 *= exp(-kf.alpha * (q1 * k1));
+    } else if (KIND == 2) {
+      k0 *= exp(fma(kf.b[0], dx0, fma(kf.b[1], dy0, kf.b[2] * dz0)) - kf.alpha * (q0 * k0));
+      k1 *= exp(fma(kf.b[0], dx1, fma(kf.b[1], dy1, kf.b[2] * dz1)) - kf.alpha * (q1 * k1));
     }
     if (SELF) {
       k0 = q0 > 0.0 ? k0 : 0.0;
@@ -1974,7 +1980,7 @@ __device__ __forceinline__ void matvec_tile(const double (*sp)[256], const doubl
 // y = diag x + sum is written directly; otherwise the range blockIdx.y writes
 // its partial sums to part and matvec_reduce_kernel adds them in a fixed
 // order.
-template <int NR, bool LAP>
+template <int NR, int KIND>
 __global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ pts, int64_t n,
                                                      KernelFn kf, const double* __restrict__ x,
                                                      int64_t ldx, double* __restrict__ y,
@@ -2010,9 +2016,9 @@ __global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ 
     const int cnt = (int)min((int64_t)256, je - j0);
     const int64_t ib = (int64_t)blockIdx.x * 512;  // targets [ib, ib + 512)
     if (j0 < ib + 512 && j0 + 256 > ib)
-      matvec_tile<NR, LAP, true>(sp, sx, cnt, p0, p1, kf.alpha, a0, a1);
+      matvec_tile<NR, KIND, true>(sp, sx, cnt, p0, p1, kf, a0, a1);
     else
-      matvec_tile<NR, LAP, false>(sp, sx, cnt, p0, p1, kf.alpha, a0, a1);
+      matvec_tile<NR, KIND, false>(sp, sx, cnt, p0, p1, kf, a0, a1);
   }
   if (part == nullptr) {
     if (i0 < n) {
@@ -2053,10 +2059,10 @@ __global__ __launch_bounds__(256) void matvec_kernel(const double* __restrict__ 
 // source order.
 constexpr int MVM_G = 8;  // target groups of 16 per wave: 512 targets per workgroup
 
-template <bool LAP, bool SELF, int NB>
+template <int KIND, bool SELF, int NB>
 __device__ __forceinline__ void matvec_mfma_tile(const double (*sp)[4], const double (*sx)[8],
                                                  int cnt, const double* tx, const double* ty,
-                                                 const double* tz, double alpha,
+                                                 const double* tz, const KernelFn& kf,
                                                  double (*acc)[2]) {
   const int lane = threadIdx.x & 63;
   const int q = lane >> 4, col = lane & 3;
@@ -2070,7 +2076,10 @@ __device__ __forceinline__ void matvec_mfma_tile(const double (*sp)[4], const do
       const double dx = tx[g] - sx0, dy = ty[g] - sy0, dz = tz[g] - sz0;
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
       double k = inv_sqrt(r2);
-      if (!LAP) k *= exp(-alpha * (r2 * k));
+      if (KIND == 1)
+        k *= exp(-kf.alpha * (r2 * k));
+      else if (KIND == 2)
+        k *= exp(fma(kf.b[0], dx, fma(kf.b[1], dy, kf.b[2] * dz)) - kf.alpha * (r2 * k));
       if (SELF) k = r2 > 0.0 ? k : 0.0;
       acc[g][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(k, b0, acc[g][0], 0, 0, 0);
       if (NB == 2) acc[g][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(k, b1, acc[g][1], 0, 0, 0);
@@ -2078,7 +2087,7 @@ __device__ __forceinline__ void matvec_mfma_tile(const double (*sp)[4], const do
   }
 }
 
-template <bool LAP, int NB>
+template <int KIND, int NB>
 __global__ __launch_bounds__(256) void matvec_mfma_kernel(const double* __restrict__ pts,
                                                           int64_t n, KernelFn kf,
                                                           const double* __restrict__ x,
@@ -2124,9 +2133,9 @@ __global__ __launch_bounds__(256) void matvec_mfma_kernel(const double* __restri
     __syncthreads();
     const int cnt = (int)min((int64_t)256, je - j0);
     if (j0 < tb + 4 * TPW && j0 + 256 > tb)
-      matvec_mfma_tile<LAP, true, NB>(sp, sx, cnt, tx, ty, tz, kf.alpha, acc);
+      matvec_mfma_tile<KIND, true, NB>(sp, sx, cnt, tx, ty, tz, kf, acc);
     else
-      matvec_mfma_tile<LAP, false, NB>(sp, sx, cnt, tx, ty, tz, kf.alpha, acc);
+      matvec_mfma_tile<KIND, false, NB>(sp, sx, cnt, tx, ty, tz, kf, acc);
   }
   // D lane 16 q + 4 b + p holds target 4 b + q of each group, column p (+4)
   const int col = lane & 3;
@@ -2183,17 +2192,23 @@ void matvec_launch(const double* pts, int64_t n, KernelFn kf, const double* x, i
   if constexpr (NR == 8 || NR == 4) {
     constexpr int NB = NR / 4;
     if (kf.kind == 0)
-      hipLaunchKernelGGL((matvec_mfma_kernel<true, NB>), grid, dim3(256), 0, s, pts, n, kf, x,
-                         ldx, y, ldy, part, chunk);
+      hipLaunchKernelGGL((matvec_mfma_kernel<0, NB>), grid, dim3(256), 0, s, pts, n, kf, x, ldx,
+                         y, ldy, part, chunk);
+    else if (kf.kind == 1)
+      hipLaunchKernelGGL((matvec_mfma_kernel<1, NB>), grid, dim3(256), 0, s, pts, n, kf, x, ldx,
+                         y, ldy, part, chunk);
     else
-      hipLaunchKernelGGL((matvec_mfma_kernel<false, NB>), grid, dim3(256), 0, s, pts, n, kf, x,
-                         ldx, y, ldy, part, chunk);
+      hipLaunchKernelGGL((matvec_mfma_kernel<2, NB>), grid, dim3(256), 0, s, pts, n, kf, x, ldx,
+                         y, ldy, part, chunk);
   } else {
     if (kf.kind == 0)
-      hipLaunchKernelGGL((matvec_kernel<NR, true>), grid, dim3(256), 0, s, pts, n, kf, x, ldx, y,
+      hipLaunchKernelGGL((matvec_kernel<NR, 0>), grid, dim3(256), 0, s, pts, n, kf, x, ldx, y,
+                         ldy, part, chunk);
+    else if (kf.kind == 1)
+      hipLaunchKernelGGL((matvec_kernel<NR, 1>), grid, dim3(256), 0, s, pts, n, kf, x, ldx, y,
                          ldy, part, chunk);
     else
-      hipLaunchKernelGGL((matvec_kernel<NR, false>), grid, dim3(256), 0, s, pts, n, kf, x, ldx, y,
+      hipLaunchKernelGGL((matvec_kernel<NR, 2>), grid, dim3(256), 0, s, pts, n, kf, x, ldx, y,
                          ldy, part, chunk);
   }
   if (part) {

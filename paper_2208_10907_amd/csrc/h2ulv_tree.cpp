@@ -201,6 +201,8 @@ Lists build_lists(const Tree& t, double eta) {
   return ls;
 }
 
+bool separate_bases(const h2ulv_params& p) { return p.bases == 1 || p.kernel == H2ULV_ADVECTION; }
+
 Lists build_flat_lists(const Tree& t, double eta) {
   // one level of boxes, the leaves, every pair classified directly (no
   // hierarchy); the levels above hold empty lists, the root level its box
@@ -262,8 +264,24 @@ void validate_params(const h2ulv_params* p) {
   if (!p) fail(H2ULV_ERR_INVALID_ARG, "params is NULL");
   if (p->struct_size != (int32_t)sizeof(h2ulv_params))
     fail(H2ULV_ERR_INVALID_ARG, "params.struct_size mismatch (use h2ulv_params_default)");
-  if (p->kernel != H2ULV_LAPLACE && p->kernel != H2ULV_YUKAWA)
+  if (p->kernel != H2ULV_LAPLACE && p->kernel != H2ULV_YUKAWA && p->kernel != H2ULV_ADVECTION)
     fail(H2ULV_ERR_INVALID_ARG, "unknown kernel");
+  if (p->kernel == H2ULV_ADVECTION) {
+    // decay in every direction: b.(x - y) <= |b| r <= alpha r
+    for (double v : p->drift)
+      if (!std::isfinite(v)) fail(H2ULV_ERR_INVALID_ARG, "drift must be finite");
+    double b2 = p->drift[0] * p->drift[0];
+    b2 = b2 + p->drift[1] * p->drift[1];
+    b2 = b2 + p->drift[2] * p->drift[2];
+    if (!(std::sqrt(b2) <= p->alpha))
+      fail(H2ULV_ERR_INVALID_ARG, "the advection kernel needs alpha >= |drift|");
+  }
+  if (p->bases != 0 && p->bases != 1)
+    fail(H2ULV_ERR_INVALID_ARG, "bases must be 0 (by kernel) or 1 (separate)");
+  if (separate_bases(*p) &&
+      (p->structure != 0 || p->precision != H2ULV_FP64 || p->rank_model))
+    fail(H2ULV_ERR_INVALID_ARG,
+         "separate row and column bases need structure 0, precision FP64 and no rank model");
   if (!std::isfinite(p->alpha) || !std::isfinite(p->diag))
     fail(H2ULV_ERR_INVALID_ARG, "alpha and diag must be finite");
   if (!(p->eta >= 0) || !std::isfinite(p->eta)) fail(H2ULV_ERR_INVALID_ARG, "eta must be >= 0");

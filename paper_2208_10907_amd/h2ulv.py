@@ -24,6 +24,7 @@ ERR_NOT_CONVERGED = -6
 
 LAPLACE = 0
 YUKAWA = 1
+ADVECTION = 2
 FP64 = 0
 MIXED = 1
 
@@ -32,6 +33,7 @@ EXPORTS = [
     "h2ulv_params_default", "h2ulv_factorize", "h2ulv_factorize_batch", "h2ulv_solve",
     "h2ulv_matvec_exact", "h2ulv_refine", "h2ulv_get_stats", "h2ulv_get_levels",
     "h2ulv_get_perm", "h2ulv_get_ranks", "h2ulv_get_skeleton", "h2ulv_get_basis",
+    "h2ulv_get_column_skeleton", "h2ulv_get_column_basis",
     "h2ulv_destroy", "h2ulv_structure_create", "h2ulv_structure_levels",
     "h2ulv_structure_perm", "h2ulv_structure_lists", "h2ulv_structure_geometry",
     "h2ulv_structure_destroy", "h2ulv_status_string", "h2ulv_last_error",
@@ -55,7 +57,8 @@ class Params(C.Structure):
         ("rank_cap", C.c_int32), ("tol", C.c_double), ("far_sample", C.c_int32),
         ("precision", C.c_int32), ("verbose", C.c_int32), ("oversample", C.c_int32),
         ("rank_model", C.c_void_p), ("sketch_seed", C.c_uint64), ("fill_in", C.c_int32),
-        ("partition", C.c_int32), ("structure", C.c_int32),
+        ("partition", C.c_int32), ("structure", C.c_int32), ("bases", C.c_int32),
+        ("reserved", C.c_int32), ("drift", C.c_double * 3),
     ]
 
 
@@ -179,6 +182,8 @@ def lib() -> C.CDLL:
         "h2ulv_get_ranks": (i32, [vp, i32, vp, vp]),
         "h2ulv_get_skeleton": (i32, [vp, i32, i32, vp]),
         "h2ulv_get_basis": (i32, [vp, i32, i32, vp]),
+        "h2ulv_get_column_skeleton": (i32, [vp, i32, i32, vp]),
+        "h2ulv_get_column_basis": (i32, [vp, i32, i32, vp]),
         "h2ulv_destroy": (None, [vp]),
         "h2ulv_structure_create": (i32, [vp, i64, P(Params), P(vp)]),
         "h2ulv_structure_levels": (i32, [vp, P(i32)]),
@@ -224,7 +229,7 @@ def _check(status: int) -> None:
 def make_params(kernel=LAPLACE, alpha=0.0, diag=1e3, eta=1.0, leaf=256, tol=1e-8,
                 rank_cap=0, far_sample=32, precision=FP64, verbose=0, rank_model=None,
                 sketch_seed=0, oversample=8, fill_in=True, partition="kd",
-                structure="h2") -> Params:
+                structure="h2", drift=(0.0, 0.0, 0.0), bases="auto") -> Params:
     p = Params()
     _check(lib().h2ulv_params_default(C.byref(p)))
     p.kernel, p.alpha, p.diag, p.eta = int(kernel), float(alpha), float(diag), float(eta)
@@ -234,6 +239,9 @@ def make_params(kernel=LAPLACE, alpha=0.0, diag=1e3, eta=1.0, leaf=256, tol=1e-8
     p.fill_in = 1 if fill_in else 0
     p.partition = {"kd": 0, "kmeans": 1}[partition]
     p.structure = {"h2": 0, "blr2": 1}[structure]
+    p.bases = {"auto": 0, "separate": 1}[bases]
+    for c in range(3):
+        p.drift[c] = float(drift[c])
     p.rank_model = rank_model._h.value if rank_model is not None else None
     p._model_ref = rank_model  # keeps the model alive as long as the parameters
     return p
@@ -461,6 +469,24 @@ class Factor:
         out = np.empty(max(int(k[box]), 1), dtype=np.int64)
         _check(lib().h2ulv_get_skeleton(self._h, lev, box, out.ctypes.data_as(C.c_void_p)))
         return out[: int(k[box])]
+
+    def column_skeleton(self, lev: int, box: int) -> np.ndarray:
+        """Column skeleton of a box (separate bases; the row skeleton otherwise)."""
+        _, k = self.ranks(lev)
+        out = np.empty(max(int(k[box]), 1), dtype=np.int64)
+        _check(lib().h2ulv_get_column_skeleton(self._h, lev, box,
+                                               out.ctypes.data_as(C.c_void_p)))
+        return out[: int(k[box])]
+
+    def column_basis(self, lev: int, box: int) -> np.ndarray:
+        """V = [V^S V^R] of a box (separate bases; U otherwise)."""
+        m, _ = self.ranks(lev)
+        mm = int(m[box])
+        out = np.empty((mm, mm), dtype=np.float64, order="F")
+        if mm:
+            _check(lib().h2ulv_get_column_basis(self._h, lev, box,
+                                                out.ctypes.data_as(C.c_void_p)))
+        return out
 
     def features(self, lev: int):
         """(features (2^lev x 16, float32), targets log2(1 + k)) of a level."""

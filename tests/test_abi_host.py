@@ -108,3 +108,20 @@ def test_build_rejects_kernels_with_scratch():
     ])
     assert B.scratch_users(txt) == [("_Zfoo", 16)]
     assert "-Rpass-analysis=kernel-resource-usage" in B.HIP_FLAGS
+
+
+def test_separate_bases_parameter_checks():
+    """The advection kernel needs alpha >= |drift| (decay in every direction);
+    separate bases are refused with the flat structure or mixed precision,
+    before any device work."""
+    X = W.cube_points(200, 1)
+    bad = [dict(kernel=H.ADVECTION, alpha=0.5, drift=(0.6, 0.0, 0.0)),
+           dict(kernel=H.ADVECTION, alpha=1.0, drift=(float("nan"), 0.0, 0.0)),
+           dict(kernel=H.ADVECTION, alpha=1.0, drift=(0.5, 0.0, 0.0), structure="blr2"),
+           dict(bases="separate", precision=H.MIXED)]
+    for kw in bad:
+        with pytest.raises(H.H2ULVError) as e:
+            H.Structure(X, H.make_params(leaf=32, **kw))
+        assert e.value.status == H.ERR_INVALID_ARG, kw
+    with pytest.raises(O.OracleError):
+        O.factorize(X, O.Params(kernel=O.ADVECTION, alpha=0.5, drift=(0.6, 0.0, 0.0)))
