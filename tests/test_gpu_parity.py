@@ -99,6 +99,7 @@ def test_small_cube_fp64():
     (3000, 64, 1e-6, 0, 32, 3),      # ragged leaves, sampled far field, rank growth
     (4096, 128, 1e-8, 0, 32, 1),     # several 64-tiles per block, ranks > 256 above
     (1500, 40, 0.0, 0, 0, 2),        # tol 0: no truncation (k = m)
+    (512, 64, 1e-8, 0, 0, 1),        # small cube, exact far field
     (1200, 64, 1e-3, 1, 16, 1),      # rank cap 1
     (2000, 64, 1e-7, 0, 32, 4),      # widest right-hand side of the vector-unit products
     (2000, 64, 1e-7, 0, 32, 5),      # one column more: the solve's products on MFMA tiles
