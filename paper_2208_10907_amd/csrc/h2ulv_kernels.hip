@@ -2155,6 +2155,154 @@ __global__ __launch_bounds__(256) void matvec_mfma_kernel(const double* __restri
   }
 }
 
+// Exact matvec of a symmetric kernel (Laplace, Yukawa) for blocks of 8
+// columns, each unordered pair evaluated once.  The points are cut into tiles
+// of 512; the pair of tiles {I, J} adds K(I, J) x_J to y_I and K(I, J)^T x_I to
+// y_J.  One launch per diagonal (I = J, both orders, the self term excluded),
+// then launches over cyclic offsets: workgroup I takes the tiles
+// (I, (I + k) mod nb) for MVS_R consecutive offsets k (offset nb/2 of an even
+// nb only for I < nb/2, so every unordered pair comes once).  The y_I sums stay
+// in registers over a launch and are added to slot 0; the y_J sums of offset
+// slot r go to slot 1 + r, which within a launch only workgroup J - k writes,
+// so every sum is taken in a fixed order and the result is deterministic.
+//   Inside a tile the 8 waves own 64 targets each (4 groups of 16).  y_I uses
+// the FP64 4x4x4 MFMA as in matvec_mfma_kernel: lane 16 q + 4 b + p evaluates
+// K(target 4 b + p of the group, source q of the step).  For y_J the same entry
+// is the B operand of a second MFMA whose k index runs over targets: the lane
+// takes the entry of lane 16 p + 4 b + q (the transposed 4x4 block), the A
+// operand is x(target 4 b + q, column p), and the 4x4 result of block b holds
+// that block's targets' contribution to (source p, column q); the four blocks
+// are summed by two exchanges and added to the tile's y_J accumulator in LDS.
+// The 8 sub-blocks of 64 sources rotate among the waves, one step per sub-block
+// with a barrier between steps, so no two waves add to one row at a time.
+constexpr int MVS_TB = 512;         // points per tile
+constexpr int MVS_R = 8;            // offsets per launch (slots of y_J sums)
+constexpr int MVS_MIN_TILES = 512;  // the pair form from 512 tiles (n > 261632) on
+
+template <int KIND, bool DIAG>
+__global__ __launch_bounds__(512) void matvec_sym_kernel(const double* __restrict__ pts,
+                                                         int64_t n, KernelFn kf,
+                                                         const double* __restrict__ x,
+                                                         int64_t ldx, double* __restrict__ Y,
+                                                         int nb, int k0, int kmax) {
+  __shared__ double sp[3][MVS_TB];
+  __shared__ double sx[MVS_TB][8];
+  __shared__ double sy[MVS_TB][8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, b = (lane >> 2) & 3, p = lane & 3;
+  const int I = blockIdx.x;
+  const int64_t tw = (int64_t)I * MVS_TB + wave * 64;  // the wave's 64 targets
+  double tx[4], ty[4], tz[4], xt[4][2], acc[4][2];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int64_t t = tw + 16 * g + (lane & 15);
+    if (t < n) {
+      tx[g] = pts[3 * t];
+      ty[g] = pts[3 * t + 1];
+      tz[g] = pts[3 * t + 2];
+    } else {
+      tx[g] = 1e30;
+      ty[g] = 0.0;
+      tz[g] = 0.0;
+    }
+    const int64_t tq = tw + 16 * g + 4 * b + q;
+    xt[g][0] = tq < n ? x[tq + p * ldx] : 0.0;
+    xt[g][1] = tq < n ? x[tq + (4 + p) * ldx] : 0.0;
+    acc[g][0] = acc[g][1] = 0.0;
+  }
+  const int ntile = DIAG ? 1 : MVS_R;
+  for (int r = 0; r < ntile; ++r) {
+    const int k = k0 + r;
+    if (!DIAG) {
+      if (k > kmax) break;
+      if (2 * k == nb && I >= nb / 2) continue;
+    }
+    const int J = DIAG ? I : (I + k) % nb;
+    const int64_t js = (int64_t)J * MVS_TB;
+    __syncthreads();
+    {
+      const int t = threadIdx.x;
+      const int64_t sidx = js + t;
+      if (sidx < n) {
+        for (int d = 0; d < 3; ++d) sp[d][t] = pts[3 * sidx + d];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) sx[t][c] = x[sidx + c * ldx];
+      } else {
+        sp[0][t] = -1e30;
+        sp[1][t] = sp[2][t] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) sx[t][c] = 0.0;
+      }
+      if (!DIAG)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) sy[t][c] = 0.0;
+    }
+    __syncthreads();
+    for (int step = 0; step < 8; ++step) {
+      const int sub = DIAG ? step : (wave + step) & 7;
+      for (int c = 0; c < 16; ++c) {
+        const int s0 = sub * 64 + 4 * c;
+        const int src = s0 + q;
+        const double sx0 = sp[0][src], sy0 = sp[1][src], sz0 = sp[2][src];
+        const double b0 = sx[src][p], b1 = sx[src][4 + p];
+        double e0 = 0.0, e1 = 0.0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const double dx = tx[g] - sx0, dy = ty[g] - sy0, dz = tz[g] - sz0;
+          const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+          double kv = inv_sqrt(r2);
+          if (KIND == 1) kv *= exp(-kf.alpha * (r2 * kv));
+          if (DIAG) kv = r2 > 0.0 ? kv : 0.0;
+          acc[g][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(kv, b0, acc[g][0], 0, 0, 0);
+          acc[g][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(kv, b1, acc[g][1], 0, 0, 0);
+          if (!DIAG) {
+            const double kt = __shfl(kv, (p << 4) | (b << 2) | q, 64);
+            e0 = __builtin_amdgcn_mfma_f64_4x4x4f64(xt[g][0], kt, e0, 0, 0, 0);
+            e1 = __builtin_amdgcn_mfma_f64_4x4x4f64(xt[g][1], kt, e1, 0, 0, 0);
+          }
+        }
+        if (!DIAG) {
+          e0 += __shfl_xor(e0, 4, 64);
+          e1 += __shfl_xor(e1, 4, 64);
+          e0 += __shfl_xor(e0, 8, 64);
+          e1 += __shfl_xor(e1, 8, 64);
+          if (b == 0) {
+            sy[s0 + p][q] += e0;
+            sy[s0 + p][4 + q] += e1;
+          }
+        }
+      }
+      if (!DIAG) __syncthreads();
+    }
+    if (!DIAG) {
+      const int t = threadIdx.x;
+      const int64_t sidx = js + t;
+      if (sidx < n) {
+        double* Yr = Y + (int64_t)(1 + r) * 8 * n;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) Yr[c * n + sidx] += sy[t][c];
+      }
+    }
+  }
+  // y_I sums: D lane 16 q + 4 b + p holds target 4 b + q of each group, column p (+4)
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int64_t t = tw + 16 * g + 4 * b + q;
+    if (t >= n) continue;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = p + 4 * h;
+      Y[c * n + t] = DIAG ? acc[g][h] : Y[c * n + t] + acc[g][h];
+    }
+  }
+}
+
+__global__ void zero_kernel(double* __restrict__ p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
 // y(i, c) = diag x(i, c) + sum over ranges s (in order) of part[s][c][i]
 __global__ __launch_bounds__(256) void matvec_reduce_kernel(const double* __restrict__ part,
                                                             int nsplit, int nr, int64_t n,
@@ -2179,9 +2327,40 @@ int matvec_split(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(MV_MAX_SPLIT, 4096 / grid));
 }
 
+// the pair form: 8 columns, a symmetric kernel, at least MVS_MIN_TILES tiles
+bool matvec_pairs(int64_t n, int kind) {
+  return kind != 2 && (n + MVS_TB - 1) / MVS_TB >= MVS_MIN_TILES;
+}
+
+template <int KIND>
+void matvec_sym_launch(const double* pts, int64_t n, KernelFn kf, const double* x, int64_t ldx,
+                       double* y, int64_t ldy, double* work, hipStream_t s) {
+  const int nb = (int)((n + MVS_TB - 1) / MVS_TB);
+  const int kmax = nb / 2;
+  const int64_t slots = (int64_t)MVS_R * 8 * n;
+  hipLaunchKernelGGL(zero_kernel, dim3(2048), dim3(256), 0, s, work + 8 * n, slots);
+  hipLaunchKernelGGL((matvec_sym_kernel<KIND, true>), dim3(nb), dim3(512), 0, s, pts, n, kf, x,
+                     ldx, work, nb, 0, 0);
+  for (int k0 = 1; k0 <= kmax; k0 += MVS_R)
+    hipLaunchKernelGGL((matvec_sym_kernel<KIND, false>), dim3(nb), dim3(512), 0, s, pts, n, kf,
+                       x, ldx, work, nb, k0, kmax);
+  const int64_t tot = n * 8;
+  hipLaunchKernelGGL(matvec_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                     work, 1 + MVS_R, 8, n, kf.diag, x, ldx, y, ldy);
+}
+
 template <int NR>
 void matvec_launch(const double* pts, int64_t n, KernelFn kf, const double* x, int64_t ldx,
                    double* y, int64_t ldy, double* work, hipStream_t s) {
+  if constexpr (NR == 8) {
+    if (work && matvec_pairs(n, kf.kind)) {
+      if (kf.kind == 0)
+        matvec_sym_launch<0>(pts, n, kf, x, ldx, y, ldy, work, s);
+      else
+        matvec_sym_launch<1>(pts, n, kf, x, ldx, y, ldy, work, s);
+      return;
+    }
+  }
   const int ns = work ? matvec_split(n) : 1;
   const unsigned gx = (unsigned)((n + 511) / 512);
   const int64_t chunk = ns > 1 ? ((n + ns - 1) / ns + 255) / 256 * 256 : n;
@@ -2221,7 +2400,11 @@ void matvec_launch(const double* pts, int64_t n, KernelFn kf, const double* x, i
 
 int64_t matvec_work_words(int64_t n, int nrhs) {
   const int ns = matvec_split(n);
-  return ns > 1 ? (int64_t)ns * std::min(nrhs, 8) * n : 0;
+  int64_t w = ns > 1 ? (int64_t)ns * std::min(nrhs, 8) * n : 0;
+  // the pair form (8 columns of a symmetric kernel): sums of y_I and the
+  // MVS_R slots of y_J sums
+  if (nrhs >= 8 && matvec_pairs(n, 0)) w = std::max<int64_t>(w, (int64_t)(1 + MVS_R) * 8 * n);
+  return w;
 }
 
 void launch_matvec(const double* pts, int64_t n, KernelFn kf, const double* x, int64_t ldx,
