@@ -57,13 +57,22 @@ def traffic_file(kernel: str, workload: str) -> str:
     return os.path.join(PROFILES, f"{kernel}_traffic_{workload}.md")
 
 
-def library_source_hash() -> str:
-    """sha256 over the library's device and host sources (sorted by name): the
-    launch mix and the GEMM kernel both come from them."""
+# the sources that define a kernel family's launches (its kernels and their launch
+# geometry); a family not listed depends on every library source
+FAMILY_SOURCES = {"matvec": ("h2ulv_kernels.h", "h2ulv_kernels.hip")}
+
+
+def library_source_hash(kernel: str = "") -> str:
+    """sha256 over the library sources (sorted by name) that a kernel family's
+    launches come from: its own files when FAMILY_SOURCES lists them, else every
+    device and host source."""
     import hashlib
     d = os.path.join(ROOT, "paper_2208_10907_amd", "csrc")
+    names = FAMILY_SOURCES.get(kernel)
     h = hashlib.sha256()
     for name in sorted(os.listdir(d)):
+        if names is not None and name not in names:
+            continue
         if name.endswith((".hip", ".cpp", ".h")):
             with open(os.path.join(d, name), "rb") as fh:
                 h.update(name.encode() + b"\0" + fh.read())
@@ -84,7 +93,7 @@ def recorded_traffic(workload: str, kernel: str = "gemm_f64"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     try:
-        if vals.get("library_source_sha256") != library_source_hash():
+        if vals.get("library_source_sha256") != library_source_hash(kernel):
             return None
         return float(vals["traffic_bytes_per_launch"])
     except (KeyError, ValueError):

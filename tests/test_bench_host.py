@@ -26,7 +26,7 @@ def test_traffic_record_matches_sources():
 
 
 def test_traffic_record_rejected_on_other_sources(monkeypatch):
-    monkeypatch.setattr(bench, "library_source_hash", lambda: "0" * 64)
+    monkeypatch.setattr(bench, "library_source_hash", lambda kernel="": "0" * 64)
     assert bench.recorded_traffic("cube1048576", "matvec") is None
     assert bench.recorded_traffic("cube2048") is None
 
@@ -34,6 +34,9 @@ def test_traffic_record_rejected_on_other_sources(monkeypatch):
 def test_source_hash_is_stable():
     assert bench.library_source_hash() == bench.library_source_hash()
     assert len(bench.library_source_hash()) == 64
+    # a family with its own sources hashes only those
+    assert bench.library_source_hash("matvec") != bench.library_source_hash()
+    assert bench.library_source_hash("gemm_f64") == bench.library_source_hash()
 
 
 def test_more_than_one_gpu_is_refused():
