@@ -557,6 +557,16 @@ static h2ulv_status block_gmres_impl(const h2ulv_factor& F, const double* b, int
     g.run(st, "bgmres");
     st.sync();
   };
+  // C (M x N) = A^T B over the n rows (inner products with the basis): row
+  // chunks in parallel, summed in a fixed order, 8 columns of B at a time
+  DBuf gpart((int64_t)GRAM_CHUNKS * QMAX * 8 * sizeof(double));
+  auto inner = [&](double* C, int64_t ldc, int M, int N, const double* A, const double* B) {
+    for (int j0 = 0; j0 < N; j0 += 8) {
+      launch_gram(A, n, M, B + (int64_t)j0 * n, n, std::min(8, N - j0), n,
+                  C + (int64_t)j0 * ldc, ldc, gpart.as<double>(), s);
+      H2ULV_HIP(hipGetLastError());
+    }
+  };
   auto download = [&](const double* src, int64_t cnt) {
     std::vector<double> h(cnt);
     H2ULV_HIP(hipMemcpyAsync(h.data(), src, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -570,7 +580,7 @@ static h2ulv_status block_gmres_impl(const h2ulv_factor& F, const double* b, int
   // out; returns its width q' and Rf (q' x q) with A diag(sc) = out Rf.
   auto block_qr = [&](const double* A, int q, const std::vector<double>& sc, double floor_abs,
                       double* out, std::vector<double>& Rf) -> int {
-    gemm(tdev, q, q, q, (int)n, A, n, true, A, n, 1.0, 0.0);
+    inner(tdev, q, q, q, A, A);
     std::vector<double> G = download(tdev, (int64_t)q * q);
     for (int j = 0; j < q; ++j)
       for (int i = 0; i < q; ++i) G[i + (size_t)j * q] *= sc[i] * sc[j];
@@ -592,7 +602,7 @@ static h2ulv_status block_gmres_impl(const h2ulv_factor& F, const double* b, int
     upload(tdev, T);
     gemm(out, n, (int)n, qk, q, A, n, false, tdev, q, 1.0, 0.0);
     // second pass: out^T out = C^T C, out <- out C^-1
-    gemm(tdev, qk, qk, qk, (int)n, out, n, true, out, n, 1.0, 0.0);
+    inner(tdev, qk, qk, qk, out, out);
     std::vector<double> G2 = download(tdev, (int64_t)qk * qk), Cu;
     if (!chol_upper(G2, qk, Cu)) fail(H2ULV_ERR_HIP, "block GMRES: orthonormalisation failed");
     std::vector<double> Ci((size_t)qk * qk, 0.0);  // C^-1 (upper)
@@ -663,7 +673,7 @@ static h2ulv_status block_gmres_impl(const h2ulv_factor& F, const double* b, int
       const int Qj = (int)qoff[j + 1];
       std::vector<double> h((size_t)Qj * qj, 0.0);
       for (int pass = 0; pass < 2; ++pass) {
-        gemm(hdev, Qj, Qj, qj, (int)n, V, n, true, Wm, n, 1.0, 0.0);
+        inner(hdev, Qj, Qj, qj, V, Wm);
         std::vector<double> hp = download(hdev, (int64_t)Qj * qj);
         for (size_t e = 0; e < hp.size(); ++e) h[e] += hp[e];
         gemm(Wm, n, (int)n, qj, Qj, V, n, false, hdev, Qj, -1.0, 1.0);

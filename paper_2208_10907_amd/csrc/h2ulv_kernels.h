@@ -176,6 +176,11 @@ void launch_convert_f2d(const float* src, double* dst, int64_t count, hipStream_
 void launch_resid_norms(const double* b, int64_t ldb, const double* ax, int64_t ldax, double* r,
                         int64_t ldr, int64_t n, int nrhs, double* rnorm2, double* bnorm2,
                         hipStream_t s);
+// C = A^T B (M x N, N <= 8) for a long inner dimension n; partial holds
+// GRAM_CHUNKS * M * N doubles.  Deterministic.
+constexpr int GRAM_CHUNKS = 256;
+void launch_gram(const double* A, int64_t lda, int M, const double* B, int64_t ldb, int N,
+                 int64_t n, double* C, int64_t ldc, double* partial, hipStream_t s);
 void launch_multidot(const double* V, int64_t ldv, int k, const double* w, int64_t n,
                      double* partial, int nblk, double* out, hipStream_t s);
 void launch_scale_inv_norm(double* dst, const double* src, const double* nrm2, int64_t n,

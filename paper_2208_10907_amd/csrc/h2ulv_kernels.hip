@@ -2499,6 +2499,71 @@ void launch_axpy_cols(double* x, int64_t ldx, const double* d, int64_t ldd, int6
                      n);
 }
 
+// C (M x N, ld ldc) = A^T B for a long inner dimension n (A n x M, B n x N,
+// column-major), N <= 8.  Workgroup (chunk, group of 8 columns of A) sums the
+// products over its contiguous rows into partial[chunk][j][i]; gram_sum_kernel
+// adds the chunks in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void gram_partial_kernel(const double* __restrict__ A,
+                                                           int64_t lda, int M,
+                                                           const double* __restrict__ B,
+                                                           int64_t ldb, int N, int64_t n,
+                                                           double* __restrict__ partial) {
+  __shared__ double sh[4][64];
+  const int i0 = blockIdx.y * 8;
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(n, r0 + per);
+  double acc[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+    double av[8], bv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) bv[j] = j < N ? B[r + j * ldb] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) av[i] = i0 + i < M ? A[r + (int64_t)(i0 + i) * lda] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int e = 0; e < 64; ++e) {
+    const double v = wave_sum(acc[e >> 3][e & 7]);
+    if (lane == 0) sh[wv][e] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int e = threadIdx.x, i = e >> 3, j = e & 7;
+    if (i0 + i < M && j < N)
+      partial[((int64_t)blockIdx.x * N + j) * M + i0 + i] =
+          (sh[0][e] + sh[1][e]) + (sh[2][e] + sh[3][e]);
+  }
+}
+
+__global__ __launch_bounds__(256) void gram_sum_kernel(const double* __restrict__ partial,
+                                                       int nchunk, int M, int N,
+                                                       double* __restrict__ C, int64_t ldc) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= M * N) return;
+  const int i = e % M, j = e / M;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += partial[((int64_t)c * N + j) * M + i];
+  C[i + (int64_t)j * ldc] = s;
+}
+
+void launch_gram(const double* A, int64_t lda, int M, const double* B, int64_t ldb, int N,
+                 int64_t n, double* C, int64_t ldc, double* partial, hipStream_t s) {
+  if (M <= 0 || N <= 0) return;
+  const dim3 grid(GRAM_CHUNKS, (unsigned)((M + 7) / 8));
+  hipLaunchKernelGGL(gram_partial_kernel, grid, dim3(256), 0, s, A, lda, M, B, ldb, N, n,
+                     partial);
+  hipLaunchKernelGGL(gram_sum_kernel, dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, s,
+                     partial, GRAM_CHUNKS, M, N, C, ldc);
+}
+
 // Several dot products with one vector: partial[b k + c] = sum over the rows of
 // block b of V(r, c) w(r), c < k <= 32 (grid-stride rows, fixed block count),
 // then out[c] = sum over blocks in a fixed order (deterministic).
