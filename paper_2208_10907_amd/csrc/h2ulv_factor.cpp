@@ -926,7 +926,7 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
     g32.run(st, "fill_m");
     tick("c_fill_gemm");
     // tall QR of every other M'^T: a tree of blocked Householder QRs (leaf
-    // chunks of 4m rows factored in place, then stacked triangles merged pairwise)
+    // chunks factored in place, then stacked triangles merged in groups)
     struct Rref {
       double* p;
       int64_t ld;
@@ -943,7 +943,10 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
       mq[q] = mi;
       if (mi == 0 || nci == 0) continue;
       double* Mi = Mp + moff[q];
-      const int64_t h = std::max<int64_t>(4 * (int64_t)mi, 256);
+      // leaf chunks as tall as the LDS panel kernel takes (4096 rows), at least
+      // 4m: the panel's cost per column hardly grows with its height, and fewer
+      // chunks mean fewer panels and merge rounds
+      const int64_t h = std::max<int64_t>(4 * (int64_t)mi, std::min<int64_t>(16 * (int64_t)mi, 4096));
       for (int64_t r0 = 0; r0 < nci; r0 += h) {
         int hc = (int)std::min<int64_t>(h, nci - r0);
         leaf.push_back(TallQr{Mi + r0, nci, hc, mi});
@@ -955,14 +958,21 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
     }
     batched_qr_R(st, leaf);
     std::vector<DBuf> rounds;
+    // merge rounds: each stacks as many consecutive triangles as fit in the LDS
+    // panel kernel's 4096 rows (at least two) and factors the stack
+    auto group_of = [](int mi) { return std::max(2, 4096 / std::max(mi, 1)); };
     for (;;) {
       int64_t words = 0;
       bool more = false;
-      for (size_t q = 0; q < nc; ++q)
-        for (size_t u = 0; u + 1 < cur[q].size(); u += 2) {
-          words += (int64_t)(cur[q][u].r + cur[q][u + 1].r) * mq[q];
+      for (size_t q = 0; q < nc; ++q) {
+        const size_t G = (size_t)group_of(mq[q]);
+        for (size_t u = 0; u < cur[q].size(); u += G) {
+          const size_t e = std::min(cur[q].size(), u + G);
+          if (e - u < 2) continue;
+          for (size_t v = u; v < e; ++v) words += (int64_t)cur[q][v].r * mq[q];
           more = true;
         }
+      }
       if (!more) break;
       DBuf buf(std::max<int64_t>(words, 1) * sizeof(double));
       double* bp = buf.as<double>();
@@ -973,21 +983,24 @@ void Driver::build_triangles(Stage& st, const std::vector<Box>& boxes, bool rebu
       for (size_t q = 0; q < nc; ++q) {
         auto& v = cur[q];
         const int mi = mq[q];
+        const size_t G = (size_t)group_of(mi);
         std::vector<Rref> nxt;
-        for (size_t u = 0; u < v.size(); u += 2) {
-          if (u + 1 == v.size()) {
+        for (size_t u = 0; u < v.size(); u += G) {
+          const size_t e = std::min(v.size(), u + G);
+          if (e - u == 1) {
             nxt.push_back(v[u]);
             continue;
           }
-          const Rref& ra = v[u];
-          const Rref& rb = v[u + 1];
-          const int hs = ra.r + rb.r;
+          int hs = 0;
+          for (size_t t = u; t < e; ++t) hs += v[t].r;
           double* Sb = bp + off;
           off += (int64_t)hs * mi;
-          cb.add(ra.p, ra.ld, Sb, hs, ra.r, mi);
-          cb.add(rb.p, rb.ld, Sb + ra.r, hs, rb.r, mi);
-          zl.push_back(CopyItem{nullptr, Sb, 0, hs, ra.r, mi, 0, 0});
-          zl.push_back(CopyItem{nullptr, Sb + ra.r, 0, hs, rb.r, mi, 0, 0});
+          int ro = 0;
+          for (size_t t = u; t < e; ++t) {
+            cb.add(v[t].p, v[t].ld, Sb + ro, hs, v[t].r, mi);
+            zl.push_back(CopyItem{nullptr, Sb + ro, 0, hs, v[t].r, mi, 0, 0});
+            ro += v[t].r;
+          }
           qs.push_back(TallQr{Sb, hs, hs, mi});
           nxt.push_back(Rref{Sb, hs, std::min(hs, mi)});
         }
