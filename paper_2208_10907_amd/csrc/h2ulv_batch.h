@@ -65,6 +65,15 @@ struct Profiler {
   bool on = false;
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
+  // the work of the last record of a scope, once it is known (after the launch)
+  void amend_last(const char* name, double flops, double bytes) {
+    for (auto it = recs.rbegin(); it != recs.rend(); ++it)
+      if (std::strcmp(it->name, name) == 0) {
+        it->flops = flops;
+        it->bytes = bytes;
+        return;
+      }
+  }
   hipEvent_t ev() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();

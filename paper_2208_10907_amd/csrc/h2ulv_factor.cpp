@@ -1175,6 +1175,10 @@ void Driver::pivot_boxes(Stage& st, const std::vector<Box>& boxes, const std::ve
   if (nbig > 0)
     H2ULV_HIP(hipMemcpyAsync(hf.data(), flg, hf.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   H2ULV_HIP(hipStreamSynchronize(s));
+  // algorithmic work of the pivoted QRs from the ranks reached: k Householder
+  // steps on a rows x m matrix, 4 sum_t (rows - t)(m - t) flops, then
+  // E = R11^-1 R12 (k^2 (m - k)); bytes: the matrix read and written once
+  double fl_small = 0, by_small = 0, fl_large = 0, by_large = 0;
   std::map<Prob*, int64_t> ewords;
   for (size_t q = 0, j = 0; q < nbox && j < jobs.size(); ++q) {
     if (boxes[q].P != jobs[j].P || boxes[q].i != jobs[j].i) continue;
@@ -1183,6 +1187,13 @@ void Driver::pivot_boxes(Stage& st, const std::vector<Box>& boxes, const std::ve
     const size_t g = std::find(probs.begin(), probs.end(), jb.P) - probs.begin();
     const int k = jb.big >= 0 ? hf[2 * q + 1] : hk[g][jb.i];
     lf.k[jb.i] = k;
+    {
+      const double rw = jb.rows, mm = lf.m[jb.i];
+      double fl = (double)k * k * (mm - k);
+      for (int t = 0; t < k; ++t) fl += 4.0 * (rw - t) * (mm - t);
+      (jb.big >= 0 ? fl_large : fl_small) += fl;
+      (jb.big >= 0 ? by_large : by_small) += 16.0 * rw * mm;
+    }
     if (jb.big >= 0) {
       ewords[jb.P] += (int64_t)k * (lf.m[jb.i] - k);
     } else {
@@ -1190,6 +1201,8 @@ void Driver::pivot_boxes(Stage& st, const std::vector<Box>& boxes, const std::ve
       jb.P->ldE[jb.i] = jb.lda;
     }
   }
+  profiler().amend_last("pivqr_small", fl_small, by_small);
+  if (nbig > 0) profiler().amend_last("pivqr_large", fl_large, by_large);
   // E = R11^-1 R12 of the large boxes by triangular blocks
   std::map<Prob*, double*> ebase;
   for (auto& kv : ewords) {
