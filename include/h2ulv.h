@@ -203,6 +203,19 @@ h2ulv_status h2ulv_solve(const h2ulv_factor* f, double* b, int32_t nrhs, int64_t
                          void* stream);
 
 /*
+ * h2ulv_solve for callers that apply one factor many times (iterative
+ * methods; the library's refinement calls use it): the first call for a given
+ * nrhs records the solve's launches in a HIP graph on buffers the factor
+ * keeps (an n x nrhs staging block, scratch and descriptors) and takes longer;
+ * later calls copy b in, replay the graph and copy the result back.  Results
+ * are identical to h2ulv_solve.  Replays on one factor are ordered through an
+ * event, whatever their streams.  The recorded graphs live until
+ * h2ulv_destroy.  Errors as h2ulv_solve.
+ */
+h2ulv_status h2ulv_solve_repeated(const h2ulv_factor* f, double* b, int32_t nrhs, int64_t ldb,
+                                  void* stream);
+
+/*
  * y = A x with the exact kernel matrix generated on the fly in float64
  * (A_ii = diag; used for residuals).  x, y device, n x nrhs column-major.
  * For n >= 65536 the sources are split over several workgroups whose partial

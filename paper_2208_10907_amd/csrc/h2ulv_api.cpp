@@ -29,8 +29,8 @@ static thread_local std::string g_last_error;
 // ---------------------------------------------------------------------------
 // solve: forward sweep over levels, root, backward sweep (Sec. II-B)
 // ---------------------------------------------------------------------------
-static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, hipStream_t s) {
-  Stage st(s);
+static void solve_body(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, Stage& st) {
+  hipStream_t s = st.s;
   const Tree& T = F.tree;
   const int L = T.L;
   const int64_t n = F.n;
@@ -43,7 +43,6 @@ static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, 
     g.one(x, n, (int)n, nrhs, (int)n, F.root_inv.as<double>(), n, false, bt, n, false);
     g.run(st, "solve");
     launch_permute_rows(x, n, b, ldb, F.perm.as<int64_t>(), n, nrhs, 1, s);
-    st.sync();
     return;
   }
   // per-level RHS blocks: rhs[lev] holds m_i x nrhs per box (ld m_i); the leaf
@@ -172,7 +171,88 @@ static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, 
   }
   launch_permute_rows(bt, n, b, ldb, F.perm.as<int64_t>(), n, nrhs, 1, s);
   H2ULV_HIP(hipGetLastError());
+}
+
+
+static void solve_impl(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, hipStream_t s) {
+  Stage st(s);
+  solve_body(F, b, nrhs, ldb, st);
   st.sync();
+}
+
+// A solve recorded in a HIP graph for one right-hand-side count: the launches
+// of solve_body on fixed buffers (an n x nrhs staging block in and out), its
+// scratch and descriptor uploads kept for the graph's lifetime.  Recorded on a
+// stream of its own after a first eager pass that allocated everything, so the
+// capture allocates nothing; replays on the caller's stream.
+struct SolveGraph {
+  int nrhs = 0;
+  hipStream_t cs = nullptr;
+  std::unique_ptr<Stage> st;
+  DBuf io;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  hipEvent_t done = nullptr;  // the last replay's copy-out (the staging block is free after it)
+  ~SolveGraph() {
+    if (cs) (void)hipStreamSynchronize(cs);
+    if (done) (void)hipEventSynchronize(done);
+    if (ex) (void)hipGraphExecDestroy(ex);
+    if (g) (void)hipGraphDestroy(g);
+    st.reset();
+    if (done) (void)hipEventDestroy(done);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+};
+
+static std::shared_ptr<SolveGraph> solve_graph_for(const h2ulv_factor& F, int nrhs) {
+  std::lock_guard<std::mutex> lk(F.graph_mu);
+  for (auto& gp : F.solve_graphs)
+    if (gp->nrhs == nrhs) return gp;
+  auto gp = std::make_shared<SolveGraph>();
+  gp->nrhs = nrhs;
+  // the GEMM tile rates are measured outside the capture (a factorization has
+  // normally done it already)
+  (void)gemm_tile_rates(true, nullptr);
+  H2ULV_HIP(hipStreamCreateWithFlags(&gp->cs, hipStreamNonBlocking));
+  H2ULV_HIP(hipEventCreateWithFlags(&gp->done, hipEventDisableTiming));
+  gp->io.alloc((size_t)F.n * nrhs * sizeof(double));
+  H2ULV_HIP(hipMemsetAsync(gp->io.p, 0, (size_t)F.n * nrhs * sizeof(double), gp->cs));
+  gp->st = std::make_unique<Stage>(gp->cs);
+  solve_body(F, gp->io.as<double>(), nrhs, F.n, *gp->st);  // first pass: allocates
+  H2ULV_HIP(hipStreamSynchronize(gp->cs));
+  gp->st->begin_replay();
+  H2ULV_HIP(hipStreamBeginCapture(gp->cs, hipStreamCaptureModeRelaxed));
+  try {
+    solve_body(F, gp->io.as<double>(), nrhs, F.n, *gp->st);
+  } catch (...) {
+    hipGraph_t junk = nullptr;
+    (void)hipStreamEndCapture(gp->cs, &junk);
+    if (junk) (void)hipGraphDestroy(junk);
+    throw;
+  }
+  H2ULV_HIP(hipStreamEndCapture(gp->cs, &gp->g));
+  H2ULV_HIP(hipGraphInstantiate(&gp->ex, gp->g, nullptr, nullptr, 0));
+  F.solve_graphs.push_back(gp);
+  return gp;
+}
+
+// solve_impl through the recorded graph of this right-hand-side count: copy b
+// into the staging block, replay, copy back.  Solves of one factor are
+// serialised on the staging block by an event (a replay waits for the previous
+// replay's copy-out).
+static void solve_graph(const h2ulv_factor& F, double* b, int nrhs, int64_t ldb, hipStream_t s) {
+  std::shared_ptr<SolveGraph> gp = solve_graph_for(F, nrhs);
+  const int64_t n = F.n;
+  H2ULV_HIP(hipStreamWaitEvent(s, gp->done, 0));
+  H2ULV_HIP(hipMemcpy2DAsync(gp->io.p, n * sizeof(double), b, ldb * sizeof(double),
+                             n * sizeof(double), nrhs, hipMemcpyDeviceToDevice, s));
+  {
+    ProfScope ps("solve_graph", 0, 0, s);
+    H2ULV_HIP(hipGraphLaunch(gp->ex, s));
+  }
+  H2ULV_HIP(hipMemcpy2DAsync(b, ldb * sizeof(double), gp->io.p, n * sizeof(double),
+                             n * sizeof(double), nrhs, hipMemcpyDeviceToDevice, s));
+  H2ULV_HIP(hipEventRecord(gp->done, s));
 }
 
 static h2ulv_factor* factorize_impl(const double* pts, int64_t n, const h2ulv_params* params,
@@ -211,7 +291,7 @@ static h2ulv_status refine_impl(const h2ulv_factor& F, const double* b, int64_t 
   cb.add(b, ldb, x, ldx, (int)n, nrhs);
   cb.run(st);
   st.sync();
-  solve_impl(F, x, nrhs, ldx, s);
+  solve_graph(F, x, nrhs, ldx, s);
   double rel = 0;
   std::vector<double> h(2 * nrhs);
   for (int it = 0; it <= max_iter; ++it) {
@@ -231,7 +311,7 @@ static h2ulv_status refine_impl(const h2ulv_factor& F, const double* b, int64_t 
     if (iters) *iters = it;
     if (rel <= rtol) return H2ULV_OK;
     if (it == max_iter) break;
-    solve_impl(F, r.as<double>(), nrhs, n, s);
+    solve_graph(F, r.as<double>(), nrhs, n, s);
     launch_axpy_cols(x, ldx, r.as<double>(), n, n, nrhs, s);
     H2ULV_HIP(hipGetLastError());
   }
@@ -276,7 +356,7 @@ static h2ulv_status gmres_impl(const h2ulv_factor& F, const double* b, int64_t l
     cb.run(st);
     st.sync();
   }
-  solve_impl(F, x, nrhs, ldx, s);
+  solve_graph(F, x, nrhs, ldx, s);
   std::vector<int> steps(nrhs, 0);
   std::vector<double> rel(nrhs, 0.0), bnorm(nrhs, 0.0), beta(nrhs, 0.0);
   std::vector<char> done(nrhs, 0);
@@ -319,7 +399,7 @@ static h2ulv_status gmres_impl(const h2ulv_factor& F, const double* b, int64_t l
       double* Zj = Z + (int64_t)j * ldk;
       // z = M^-1 v and w = A z for all columns of the block at once
       H2ULV_HIP(hipMemcpyAsync(Zj, Vj, ldk * sizeof(double), hipMemcpyDeviceToDevice, s));
-      solve_impl(F, Zj, na, n, s);
+      solve_graph(F, Zj, na, n, s);
       matvec_impl(F, Zj, n, w, n, na, s);
       // w_u -= V_u h_u, twice (classical Gram-Schmidt with re-orthogonalisation)
       for (int pass = 0; pass < 2; ++pass) {
@@ -635,7 +715,7 @@ static h2ulv_status block_gmres_impl(const h2ulv_factor& F, const double* b, int
     cb.run(st);
     st.sync();
   }
-  solve_impl(F, x, p, ldx, s);
+  solve_graph(F, x, p, ldx, s);
   int steps = 0;
   std::vector<double> rel(p, 0.0), bn(p, 1.0);
   for (;;) {
@@ -666,7 +746,7 @@ static h2ulv_status block_gmres_impl(const h2ulv_factor& F, const double* b, int
       double* Zj = Z + (int64_t)Qz * n;
       H2ULV_HIP(hipMemcpyAsync(Zj, Vj, (size_t)qj * n * sizeof(double), hipMemcpyDeviceToDevice,
                                s));
-      solve_impl(F, Zj, qj, n, s);
+      solve_graph(F, Zj, qj, n, s);
       matvec_impl(F, Zj, n, Wm, n, qj, s);
       ++steps;
       Qz += qj;
@@ -845,6 +925,19 @@ h2ulv_status h2ulv_solve(const h2ulv_factor* f, double* b, int32_t nrhs, int64_t
     CacheScope cs;
     AllocScope as(f->has_alloc ? &f->alloc : nullptr, stream);
     solve_impl(*f, b, nrhs, ldb, (hipStream_t)stream);
+  });
+}
+
+h2ulv_status h2ulv_solve_repeated(const h2ulv_factor* f, double* b, int32_t nrhs, int64_t ldb,
+                                  void* stream) {
+  if (!f || !b || nrhs < 1 || ldb < f->n) {
+    g_last_error = "bad solve arguments";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  return guarded([&] {
+    CacheScope cs;
+    AllocScope as(f->has_alloc ? &f->alloc : nullptr, stream);
+    solve_graph(*f, b, nrhs, ldb, (hipStream_t)stream);
   });
 }
 

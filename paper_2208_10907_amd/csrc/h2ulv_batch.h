@@ -97,6 +97,9 @@ struct ProfScope {
   ProfScope(const char* name, double flops, double bytes, hipStream_t st) : s(st) {
     Profiler& pr = profiler();
     if (!pr.on) return;
+    // work recorded into a graph is timed where the graph is launched
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone) return;
     p = &pr;
     r.name = name;
     r.flops = flops;
@@ -282,7 +285,17 @@ struct Stage {
   std::vector<DBuf> bufs;
   std::vector<std::shared_ptr<void>> host;
   DescArena desc;
+  // replay mode (graph capture): the same sequence of requests as a first pass
+  // gets that pass's scratch buffers and descriptor offsets back, so nothing is
+  // allocated while the stream captures
+  bool replay = false;
+  size_t next = 0;
   explicit Stage(hipStream_t st) : s(st) {}
+  void begin_replay() {
+    replay = true;
+    next = 0;
+    desc.recycle();
+  }
   template <class T>
   T* up(std::vector<T>&& v) {
     if (v.empty()) return nullptr;
@@ -316,6 +329,11 @@ struct Stage {
   template <class T>
   T* scratch(size_t count, bool zero = false) {
     if (count == 0) return nullptr;
+    if (replay) {
+      if (zero || next >= bufs.size() || bufs[next].bytes < count * sizeof(T))
+        fail(H2ULV_ERR_HIP, "internal: replayed stage differs from its first pass");
+      return bufs[next++].as<T>();
+    }
     DBuf b(count * sizeof(T));
     if (zero) H2ULV_HIP(hipMemsetAsync(b.p, 0, count * sizeof(T), s));
     bufs.push_back(std::move(b));

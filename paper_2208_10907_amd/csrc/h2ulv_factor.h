@@ -4,12 +4,15 @@
 #include <hip/hip_runtime.h>
 
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "h2ulv_dense.h"
 
 namespace h2ulv {
+
+struct SolveGraph;  // a solve recorded in a HIP graph (h2ulv_api.cpp)
 
 struct LevelFactor {
   int lev = 0;
@@ -70,6 +73,10 @@ struct h2ulv_factor {
   // row bases of the transposed matrix (its levels hold V, T_V and the column
   // skeletons in U, Tt and sk; its elimination fields stay empty)
   std::unique_ptr<h2ulv_factor> colview;
+  // solves recorded in HIP graphs, one per right-hand-side count (refinement
+  // repeats the solve); destroyed first
+  mutable std::mutex graph_mu;
+  mutable std::vector<std::shared_ptr<h2ulv::SolveGraph>> solve_graphs;
 };
 
 struct h2ulv_rankmodel {

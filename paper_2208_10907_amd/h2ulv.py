@@ -33,7 +33,7 @@ EXPORTS = [
     "h2ulv_params_default", "h2ulv_factorize", "h2ulv_factorize_batch", "h2ulv_solve",
     "h2ulv_matvec_exact", "h2ulv_refine", "h2ulv_get_stats", "h2ulv_get_levels",
     "h2ulv_get_perm", "h2ulv_get_ranks", "h2ulv_get_skeleton", "h2ulv_get_basis",
-    "h2ulv_get_column_skeleton", "h2ulv_get_column_basis",
+    "h2ulv_get_column_skeleton", "h2ulv_get_column_basis", "h2ulv_solve_repeated",
     "h2ulv_destroy", "h2ulv_structure_create", "h2ulv_structure_levels",
     "h2ulv_structure_perm", "h2ulv_structure_lists", "h2ulv_structure_geometry",
     "h2ulv_structure_destroy", "h2ulv_status_string", "h2ulv_last_error",
@@ -184,6 +184,7 @@ def lib() -> C.CDLL:
         "h2ulv_get_basis": (i32, [vp, i32, i32, vp]),
         "h2ulv_get_column_skeleton": (i32, [vp, i32, i32, vp]),
         "h2ulv_get_column_basis": (i32, [vp, i32, i32, vp]),
+        "h2ulv_solve_repeated": (i32, [vp, vp, i32, i64, vp]),
         "h2ulv_destroy": (None, [vp]),
         "h2ulv_structure_create": (i32, [vp, i64, P(Params), P(vp)]),
         "h2ulv_structure_levels": (i32, [vp, P(i32)]),
@@ -373,6 +374,14 @@ class Factor:
         vec, bt = self._colmajor(b)
         _check(lib().h2ulv_solve(self._h, C.c_void_p(bt.data_ptr()), bt.shape[0], self.n,
                                  _stream(stream)))
+        return self._back(vec, bt)
+
+    def solve_repeated(self, b, stream=None):
+        """solve() through the factor's recorded HIP graph for this number of
+        right-hand sides (recorded on the first call); identical results."""
+        vec, bt = self._colmajor(b)
+        _check(lib().h2ulv_solve_repeated(self._h, C.c_void_p(bt.data_ptr()), bt.shape[0],
+                                          self.n, _stream(stream)))
         return self._back(vec, bt)
 
     def matvec(self, x, stream=None):

@@ -548,3 +548,50 @@ def test_advection_matvec_and_refinement():
     r = b - O.matvec_exact(X, xs, op)
     assert np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(b, axis=0)) < 1e-10
     assert iters > 0
+
+
+@pytest.mark.parametrize("kw", [dict(kernel=O.ADVECTION, alpha=1.0, drift=(0.6, -0.3, 0.5)),
+                                dict(kernel=O.LAPLACE, structure="blr2")])
+def test_batch_separate_bases_and_flat(kw):
+    """Batched factorization with separate row and column bases (each problem's
+    column side in the same launches) and with the flat BLR^2 structure: every
+    problem matches the oracle run on its own (row and column skeletons, solution
+    within 1e-10)."""
+    sizes = (700, 1500, 2600)
+    pts = [W.cube_points(n, 4100 + n) for n in sizes]
+    op = O.Params(leaf=64, tol=1e-7, far_sample=16, **kw)
+    fb = H.factorize_batch(pts, _params(op))
+    for X, fg in zip(pts, fb):
+        fo = O.factorize(X, op)
+        _compare_structure(fg, fo)
+        if op.kernel == O.ADVECTION:
+            for lev in fo.levels:
+                for i in range(1 << lev):
+                    _compare_skeleton(fg.column_skeleton(lev, i),
+                                      _ColumnSide(fo.levels[lev][i]), ("col", lev, i))
+        b = W.gaussian_rhs(X.shape[0], 2, 9)
+        xo = O.solve(fo, b)
+        xg = fg.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+        assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < X_TOL
+
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(kernel=O.ADVECTION, alpha=1.0, drift=(0.6, -0.3, 0.5)),
+                                dict(structure="blr2")])
+def test_solve_graph_replays_equal_eager_solves(kw):
+    """The solve recorded in a HIP graph (h2ulv_solve_repeated, used by the
+    refinement loops) gives the eager solve's bits on every replay: several
+    right-hand-side counts, new right-hand sides each time, eager solves and
+    matvecs between the replays."""
+    n = 6000 if kw.get("structure") == "blr2" else 20000
+    X = W.cube_points(n, 77)
+    op = O.Params(leaf=128, tol=1e-6, far_sample=16, **kw)
+    fg = H.factorize(X, _params(op))
+    for nrhs in (1, 3, 8):
+        for rep in range(4):
+            b = torch.tensor(W.gaussian_rhs(n, nrhs, 100 * nrhs + rep), device="cuda")
+            xe = fg.solve(b.clone())
+            xg = fg.solve_repeated(b.clone())
+            torch.cuda.synchronize()
+            assert torch.equal(xe, xg), (nrhs, rep)
+            fg.matvec(xg)  # eager work between replays
