@@ -2,7 +2,8 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--form fp64|mixed|predicted|mixed+predicted]
-                    [--refine gmres|classical] [--no-reference] [--no-cpu-baseline]
+                    [--refine block|gmres|classical] [--no-reference] [--no-cpu-baseline]
+                    [--leaf-sweep LEAVES] [--batch-leg P]
 
 One step = factorize the workload's kernel matrix, then solve its right-hand
 sides with iterative refinement (exact float64 matvec) down to a relative
