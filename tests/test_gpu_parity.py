@@ -359,8 +359,9 @@ def test_tolerance_one_eliminates_every_box():
 def test_caller_allocator_supplies_all_factor_memory():
     """h2ulv_allocator: every device block of the factorization and of later
     calls comes from the caller (here torch's caching allocator, counted) and
-    goes back to it by h2ulv_destroy; results equal those with the library's
-    own cache.  A callback that returns NULL gives OOM at the first allocation,
+    goes back to it by h2ulv_destroy (a solve's temporaries right away, the
+    recorded solve graphs' buffers with the factor); results equal those with
+    the library's own cache.  A callback that returns NULL gives OOM at the first allocation,
     before any device work."""
     X = W.cube_points(3000, 41)
     p = H.make_params(leaf=64, tol=1e-7, rank_cap=32)
@@ -384,8 +385,15 @@ def test_caller_allocator_supplies_all_factor_memory():
     held = len(live)
     assert held > 0 and calls["alloc"] > held  # temporaries came and went
     x = f.solve(b)
+    assert len(live) == held  # a solve's temporaries given back
     xr, _, rr = f.refine_gmres(b, rtol=1e-10)
-    assert rr <= 1e-10 and len(live) == held  # later calls' temporaries given back
+    assert rr <= 1e-10
+    # the refinement records its solves in HIP graphs whose buffers (from the
+    # caller's allocator) the factor keeps; a second refinement replays them and
+    # holds nothing more
+    held_graphs = len(live)
+    xr2, _, rr2 = f.refine_gmres(b, rtol=1e-10)
+    assert len(live) == held_graphs and torch.equal(xr, xr2)
     g = H.factorize(X, p, allocator=None)
     assert torch.equal(x, g.solve(b))
     del f
