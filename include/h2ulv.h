@@ -47,7 +47,9 @@ typedef enum {
   H2ULV_ERR_HIP = -3,              /* a HIP runtime call failed */
   H2ULV_ERR_SINGULAR = -4,         /* zero or non-finite pivot in a block LU */
   H2ULV_ERR_DUPLICATE_POINTS = -5, /* two distinct points coincide (r = 0) */
-  H2ULV_ERR_NOT_CONVERGED = -6     /* refinement did not reach the tolerance */
+  H2ULV_ERR_NOT_CONVERGED = -6,    /* refinement did not reach the tolerance */
+  H2ULV_ERR_RANK_CHECK = -7        /* a predicted-rank basis failed its randomized
+                                      check and params.sketch_fallback is 0 */
 } h2ulv_status;
 
 enum { H2ULV_LAPLACE = 0, H2ULV_YUKAWA = 1, H2ULV_ADVECTION = 2 };
@@ -104,7 +106,12 @@ typedef struct h2ulv_params {
                           Separate bases (Sec. III-C: U from [F_i+ A_i+], V from
                           [F_+j^T A_+j^T], Eq. fillu/fillv) need structure 0,
                           precision FP64 and no rank model                     */
-  int32_t reserved;
+  int32_t sketch_fallback; /* rank model only.  1 (default): a box whose sketched
+                          row ID fails the randomized check twice (first width,
+                          then full width) takes the full column-pivoted QR.
+                          0: the factorization stops with H2ULV_ERR_RANK_CHECK
+                          instead (for callers that want to know when the model
+                          under-predicts)                                      */
   double drift[3];      /* b of H2ULV_ADVECTION (ignored by the other kernels)  */
 } h2ulv_params;
 

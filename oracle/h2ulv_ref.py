@@ -69,6 +69,7 @@ ERR_HIP = -3
 ERR_SINGULAR = -4
 ERR_DUPLICATE_POINTS = -5
 ERR_NOT_CONVERGED = -6
+ERR_RANK_CHECK = -7
 
 LAPLACE = 0
 YUKAWA = 1
@@ -99,6 +100,7 @@ class Params:
     structure: str = "h2"      # "h2" the hierarchy; "blr2" one level of leaves (Sec. II-B)
     drift: tuple = (0.0, 0.0, 0.0)  # b of the advection-diffusion kernel
     bases: str = "auto"        # "auto": V = U for symmetric kernels; "separate": always U, V
+    sketch_fallback: bool = True  # False: a twice-rejected sketch stops with ERR_RANK_CHECK
 
 
 def two_sided(p: Params) -> bool:
@@ -806,6 +808,8 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                         state = 3 if ok else 2
                 else:
                     ell = 0
+            if state == 2 and not p.sketch_fallback:
+                raise OracleError(ERR_RANK_CHECK, "a sketched row ID failed its check")
             if state not in (1, 3):
                 # M' formed: the products D_ik D_kk^-1, then the fill-ins
                 if p.fill_in:

@@ -854,7 +854,7 @@ h2ulv_status h2ulv_params_default(h2ulv_params* p) {
   p->partition = 0;
   p->structure = 0;
   p->bases = 0;
-  p->reserved = 0;
+  p->sketch_fallback = 1;
   p->drift[0] = p->drift[1] = p->drift[2] = 0.0;
   return H2ULV_OK;
 }
@@ -1277,6 +1277,7 @@ const char* h2ulv_status_string(h2ulv_status s) {
     case H2ULV_ERR_SINGULAR: return "singular block";
     case H2ULV_ERR_DUPLICATE_POINTS: return "duplicate points";
     case H2ULV_ERR_NOT_CONVERGED: return "refinement not converged";
+    case H2ULV_ERR_RANK_CHECK: return "sketched basis rejected (no fallback)";
   }
   return "unknown status";
 }

@@ -1393,6 +1393,8 @@ void Driver::row_ids(Stage& st, const std::vector<Prob*>& G) {
       for (const Box& b : retry) b.P->lf().sk_state[b.i] = 3;
       full.insert(full.end(), again.begin(), again.end());
     }
+    if (!full.empty() && !p.sketch_fallback)
+      fail(H2ULV_ERR_RANK_CHECK, "a sketched row ID failed its randomized check (no fallback)");
     if (!full.empty()) {
       // the full pivoted QR of their M' (rebuilt)
       for (const Box& b : full) {

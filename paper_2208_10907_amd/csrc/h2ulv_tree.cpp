@@ -276,6 +276,8 @@ void validate_params(const h2ulv_params* p) {
     if (!(std::sqrt(b2) <= p->alpha))
       fail(H2ULV_ERR_INVALID_ARG, "the advection kernel needs alpha >= |drift|");
   }
+  if (p->sketch_fallback != 0 && p->sketch_fallback != 1)
+    fail(H2ULV_ERR_INVALID_ARG, "sketch_fallback must be 0 or 1");
   if (p->bases != 0 && p->bases != 1)
     fail(H2ULV_ERR_INVALID_ARG, "bases must be 0 (by kernel) or 1 (separate)");
   if (separate_bases(*p) &&

@@ -201,6 +201,26 @@ def test_predicted_mode_parity(n, leaf, tol, oversample, model, cap):
         assert len(capped) >= 2
 
 
+def test_rank_check_without_fallback():
+    """With the fallback switched off, a factorization whose sketches are
+    rejected twice stops with RANK_CHECK, as the oracle does; with it (the
+    default) the same case completes (test_predicted_mode_parity)."""
+    th = _constant_model(10)
+    op = O.Params(leaf=64, tol=1e-6, rank_model=th, sketch_seed=77, oversample=0,
+                  sketch_fallback=False)
+    X = W.cube_points(3000, 3901)
+    with pytest.raises(O.OracleError) as eo:
+        O.factorize(X, op)
+    assert eo.value.status == O.ERR_RANK_CHECK
+    gm = H.RankModel()
+    gm.set_params(th)
+    p = _gpu_params(op, gm)
+    p.sketch_fallback = 0
+    with pytest.raises(H.H2ULVError) as eg:
+        H.factorize(X, p)
+    assert eg.value.status == H.ERR_RANK_CHECK
+
+
 def test_trained_model_gain():
     """Train the rank model on the GPU from the ranks of two factorizations of
     other point sets (no rank cap), then factorize a new one three ways: the

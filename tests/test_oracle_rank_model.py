@@ -230,3 +230,20 @@ def _constant_mlp(k):
     parts = {name: np.zeros(s) for name, s in R.SHAPES}
     parts["b4"][0] = math.log2(1 + k)
     return R.pack(parts).astype(np.float32)
+
+
+def test_rejected_sketch_without_fallback_reports_rank_check():
+    """A model that predicts rank 10 everywhere with no oversampling exhausts
+    every first sketch; boxes whose full-width retry fails too take the full
+    pivoted QR by default, or stop the factorization with RANK_CHECK when the
+    fallback is switched off."""
+    parts = {name: np.zeros(s) for name, s in R.SHAPES}
+    parts["b4"][0] = math.log2(1 + 10)
+    th = R.pack(parts).astype(np.float32)
+    X = W.cube_points(3000, 3901)
+    kw = dict(leaf=64, tol=1e-6, rank_model=th, sketch_seed=77, oversample=0)
+    f = O.factorize(X, O.Params(**kw))
+    assert any(b.sketch == 2 for lev in f.levels.values() for b in lev)
+    with pytest.raises(O.OracleError) as e:
+        O.factorize(X, O.Params(sketch_fallback=False, **kw))
+    assert e.value.status == O.ERR_RANK_CHECK
