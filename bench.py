@@ -1,9 +1,9 @@
 """Benchmark of the H^2-ULV factorization (+ refined solve) on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--form fp64|mixed|predicted|mixed+predicted]
-                    [--refine block|gmres|classical] [--no-reference] [--no-cpu-baseline]
-                    [--leaf-sweep LEAVES] [--batch-leg P]
+                    [--form fp64|mixed|predicted|mixed+predicted] [--oversample P]
+                    [--refine block|gmres|classical] [--no-reference] [--no-alternate]
+                    [--no-cpu-baseline] [--leaf-sweep LEAVES] [--batch-leg P]
 
 One step = factorize the workload's kernel matrix, then solve its right-hand
 sides with iterative refinement (exact float64 matvec) down to a relative
@@ -16,25 +16,31 @@ Prints one JSON line.
 Forms: fp64 (the plain method), mixed (FP32 products where the method allows),
 predicted (bases from sketches sized by the learned rank model), and both
 combined.  A rank model is trained first (outside the timed steps) on the
-ranks of factorizations of two other point sets of the same family.
+ranks of factorizations of two other point sets of the same family.  The
+sketch oversampling of the predicted forms defaults to the value that gives a
+box predicted at the rank cap a sketch of the full width m - 8 (leaf - 8 -
+ceil(1.25 cap), at least 8): at the default workload every box is at the cap,
+and the wider sketch shortens the refinement more than it costs.
 
 Default workload: the N=2^20 unit-cube Laplace problem (leaf 256, eta 1, tol
 1e-6, rank cap 128 = leaf / 2, 8 Gaussian right-hand sides), default form
-mixed.  value = the timed form's own algorithmic flops (the method's step costs
-from its actual ranks, as the factorization counts them) / wall time of one
-step (factorize + refined solve).  The plain FP64 form is timed the same way
-(warmup, then timed steps) as the reference unless --no-reference, with its
-own flops, time, refinement and the relative difference of the two solutions.
-The learned-rank form (mixed precision + predicted ranks) is timed the same way
-and reported as a separate record (--no-predicted skips it); its model is
-trained outside the timed regions.
+mixed+predicted (mixed precision, learned ranks).  value = the timed form's own
+algorithmic flops (the method's step costs from its actual ranks, as the
+factorization counts them) / wall time of one step (factorize + refined
+solve).  The plain FP64 form is timed the same way (warmup, then timed steps)
+as the reference unless --no-reference, with its own flops, time, refinement
+and the relative difference of the two solutions.  The other mixed form (mixed
+with full pivoted QR bases when the headline is mixed+predicted, else
+mixed+predicted) is timed the same way and reported as the `alternate` record
+unless --no-alternate.
 roofline = the dominant kernel (by time) of the timed steps measured with HIP
 events on its launch stream: summed algorithmic flops / summed duration.
 roofline.traffic = HBM bytes per launch of that kernel in the timed step, from
 the rocprofv3 FETCH_SIZE / WRITE_SIZE counters recorded in
-profiles/gemm_f64_traffic_ellipsoids262144.md (scaled by the same counters'
-reading for a plain copy of known size, --copy-probe); null when the library
-sources differ from those the counters were taken with (source hash).
+profiles/<kernel>_traffic_<workload>.md (for the default workload the exact
+matvec: profiles/matvec_traffic_cube1048576.md), scaled by the same counters'
+reading for a plain copy of known size (--copy-probe); null when the sources
+of that kernel family differ from those the counters were taken with (hash).
 cpu_baseline = the CPU oracle timed on a bounded sample of leaf boxes of the
 same workload (GFLOP/s of the oracle's own flop count).
 """
@@ -187,6 +193,16 @@ def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+def default_oversample(prob) -> int:
+    """Sketch oversampling that gives a box predicted at the rank cap a sketch
+    of the full width m - 8 (m = leaf at the leaves, at most 2 cap above), at
+    least the library's default 8."""
+    import math
+    if prob.rank_cap <= 0:
+        return 8
+    return max(8, min(prob.leaf, 2 * prob.rank_cap) - 8 - math.ceil(1.25 * prob.rank_cap))
+
+
 def train_model(H, torch, prob, name):
     """Factorize the training point sets (plain FP64), collect the per-box
     features and ranks, train the rank MLP on the GPU."""
@@ -301,10 +317,13 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cube1048576", choices=sorted(workloads()))
-    ap.add_argument("--form", default="mixed",
+    ap.add_argument("--form", default="mixed+predicted",
                     choices=["fp64", "mixed", "predicted", "mixed+predicted"])
-    ap.add_argument("--no-predicted", dest="predicted", action="store_false",
-                    help="skip the mixed+predicted form (reported as a separate record)")
+    ap.add_argument("--no-alternate", dest="alternate", action="store_false",
+                    help="skip the other mixed form (mixed vs mixed+predicted)")
+    ap.add_argument("--oversample", type=int, default=-1,
+                    help="sketch oversampling of the predicted forms (default: full-width "
+                         "sketches at the rank cap)")
     ap.add_argument("--restart", type=int, default=60,
                     help="GMRES cycle length in (block) steps (the capped factorization leaves "
                          "many outlying eigenvalues: short cycles restart too often)")
@@ -362,15 +381,20 @@ def main() -> int:
     b = torch.tensor(prob.rhs(), device="cuda")
     torch.cuda.synchronize()
 
+    alt_form = None
+    if args.alternate and args.form in ("mixed", "mixed+predicted"):
+        alt_form = "mixed" if args.form == "mixed+predicted" else "mixed+predicted"
     model, model_info = None, None
-    if "predicted" in args.form:
+    if "predicted" in args.form or (alt_form and "predicted" in alt_form):
         model, model_info = train_model(H, torch, prob, args.workload)
+    oversample = args.oversample if args.oversample >= 0 else default_oversample(prob)
 
     def params_of(form):
         prec = H.MIXED if "mixed" in form else H.FP64
+        pred = "predicted" in form
         return H.params_from_problem(prob, precision=prec, verbose=1 if args.verbose else 0,
-                                     rank_model=model if "predicted" in form else None,
-                                     sketch_seed=5)
+                                     rank_model=model if pred else None, sketch_seed=5,
+                                     oversample=oversample if pred else 8)
 
     allocator = "torch" if args.allocator == "torch" else None
 
@@ -466,15 +490,14 @@ def main() -> int:
         ref["solution_rel_diff_vs_this_form"] = float(
             (torch.linalg.norm(x_form - x_ref) / torch.linalg.norm(x_ref)).item())
         del x_ref
-    pred = None
-    if args.predicted:
-        if model is None:
-            model, model_info = train_model(H, torch, prob, args.workload)
-        pred, x_pred = run_form("mixed+predicted", args.warmup, args.steps, "predicted")
-        pred["rank_model"] = model_info
-        pred["solution_rel_diff_vs_this_form"] = float(
-            (torch.linalg.norm(x_pred - x_form) / torch.linalg.norm(x_form)).item())
-        del x_pred
+    alt = None
+    if alt_form:
+        alt, x_alt = run_form(alt_form, args.warmup, args.steps, alt_form)
+        alt["solution_rel_diff_vs_this_form"] = float(
+            (torch.linalg.norm(x_alt - x_form) / torch.linalg.norm(x_form)).item())
+        if ref:
+            alt["speedup_vs_fp64"] = round(ref["step_s"] / alt["step_s"], 3)
+        del x_alt
     H.profile_enable(False)
     work = st["flops"] + last["refine_flops"]
     value = work / (ms / 1e3) / 1e9
@@ -515,6 +538,7 @@ def main() -> int:
         "dtype": "f32+f64" if "mixed" in args.form else "f64",
         "data": "synthetic",
         "config": {"workload": describe(prob), "form": args.form, "refine_rtol": args.rtol,
+                   "sketch_oversample": oversample if "predicted" in args.form else None,
                    "refine": args.refine, "gmres_restart": args.restart,
                    "allocator": args.allocator,
                    "value": "this form's algorithmic flops (factorization from its actual ranks + "
@@ -534,7 +558,7 @@ def main() -> int:
         "reference": ref,
         "speedup_vs_fp64": round(ref["step_s"] / (ms / 1e3), 3) if ref else None,
         "factor_speedup_vs_fp64": round(ref["factor_s"] / last["factor_s"], 3) if ref else None,
-        "predicted": pred,
+        "alternate": alt,
         "gemm_tile_rates_tflops": H.gemm_tile_rates(),
         "rank_model": model_info,
         "kernels": {k: {"launches": v["launches"], "ms": round(v["time_ms"], 2),
