@@ -151,13 +151,16 @@ def _constant_model(k):
                                           # then the full QR where those fail too
     (4096, 128, 1e-6, 8, "trained", 32),  # rank cap 32: sketches sized for min(k-hat,
                                           # cap), accepted at k = cap without the tol test
+    (4096, 256, 1e-6, 88, "above_cap", 128),  # the benchmark's regime: k-hat above the cap
+                                          # at leaf 256, every box sketched at the full
+                                          # width m - 8 and accepted, mostly at k = cap
 ])
 def test_predicted_mode_parity(n, leaf, tol, oversample, model, cap):
     base = O.Params(leaf=leaf, tol=tol, rank_cap=cap)
     if model == "trained":
         th = _oracle_model(W.cube_points(n, 900 + n), base)
     else:
-        th = _constant_model(10)
+        th = _constant_model(10 if model == "constant" else 10000)
     op = O.Params(leaf=leaf, tol=tol, rank_cap=cap, rank_model=th, sketch_seed=77,
                   oversample=oversample)
     X = W.cube_points(n, 901 + n)
@@ -174,6 +177,9 @@ def test_predicted_mode_parity(n, leaf, tol, oversample, model, cap):
         states += stt.tolist()
     if model == "trained":
         assert states.count(1) >= 2
+    elif model == "above_cap":
+        assert states.count(1) == len(states)
+        assert all(b.ell == b.m - 8 for l in fo.levels for b in fo.levels[l])
     else:
         assert states.count(2) + states.count(3) == len(states) and states.count(2) >= 1
     m_all = [b.m for l in fo.levels for b in fo.levels[l] if b.sketch == 1]
