@@ -2169,10 +2169,14 @@ __global__ __launch_bounds__(256) void matvec_mfma_kernel(const double* __restri
 // the FP64 4x4x4 MFMA as in matvec_mfma_kernel: lane 16 q + 4 b + p evaluates
 // K(target 4 b + p of the group, source q of the step).  For y_J the same entry
 // is the B operand of a second MFMA whose k index runs over targets: the lane
-// takes the entry of lane 16 p + 4 b + q (the transposed 4x4 block), the A
-// operand is x(target 4 b + q, column p), and the 4x4 result of block b holds
-// that block's targets' contribution to (source p, column q); the four blocks
-// are summed by two exchanges and added to the tile's y_J accumulator in LDS.
+// takes the entry of lane 16 p + 4 b + q (the transposed 4x4 block), and the
+// 4x4 result of block b holds that block's targets' contribution to (source p,
+// column q + c0) for the columns c0..c0+3 of its A operand x(target 4 b + q,
+// column c0 + p).  The first product (e0) of block b takes c0 = 4 (b & 1) and
+// the second (e1) the other half, so e0 of block b and e1 of block b ^ 1 cover
+// the same columns: one exchange adds that pair, a second adds block b ^ 2, and
+// the lanes of blocks 0 and 1 add columns 0-3 and 4-7 to the tile's y_J
+// accumulator in LDS (the blocks are summed as (0 + 1) + (2 + 3) either way).
 // The 8 sub-blocks of 64 sources rotate among the waves, one step per sub-block
 // with a barrier between steps, so no two waves add to one row at a time.
 constexpr int MVS_TB = 512;         // points per tile
@@ -2206,8 +2210,9 @@ __global__ __launch_bounds__(512) void matvec_sym_kernel(const double* __restric
       tz[g] = 0.0;
     }
     const int64_t tq = tw + 16 * g + 4 * b + q;
-    xt[g][0] = tq < n ? x[tq + p * ldx] : 0.0;
-    xt[g][1] = tq < n ? x[tq + (4 + p) * ldx] : 0.0;
+    const int h0 = 4 * (b & 1);  // column half of this lane's first y_J product
+    xt[g][0] = tq < n ? x[tq + (h0 + p) * ldx] : 0.0;
+    xt[g][1] = tq < n ? x[tq + (4 - h0 + p) * ldx] : 0.0;
     acc[g][0] = acc[g][1] = 0.0;
   }
   const int ntile = DIAG ? 1 : MVS_R;
@@ -2262,14 +2267,10 @@ __global__ __launch_bounds__(512) void matvec_sym_kernel(const double* __restric
           }
         }
         if (!DIAG) {
-          e0 += __shfl_xor(e0, 4, 64);
-          e1 += __shfl_xor(e1, 4, 64);
-          e0 += __shfl_xor(e0, 8, 64);
-          e1 += __shfl_xor(e1, 8, 64);
-          if (b == 0) {
-            sy[s0 + p][q] += e0;
-            sy[s0 + p][4 + q] += e1;
-          }
+          // e0 of block b and e1 of block b ^ 1 hold the same columns
+          double s1 = e0 + __shfl_xor(e1, 4, 64);
+          s1 += __shfl_xor(s1, 8, 64);
+          if (b < 2) sy[s0 + p][4 * b + q] += s1;
         }
       }
       if (!DIAG) __syncthreads();
