@@ -107,8 +107,9 @@ typedef struct h2ulv_params {
                           [F_+j^T A_+j^T], Eq. fillu/fillv) need structure 0,
                           precision FP64 and no rank model                     */
   int32_t sketch_fallback; /* rank model only.  1 (default): a box whose sketched
-                          row ID fails the randomized check twice (first width,
-                          then full width) takes the full column-pivoted QR.
+                          row ID fails the randomized check (at its first width
+                          and, when that was narrower than m - 8, again at the
+                          full width m - 8) takes the full column-pivoted QR.
                           0: the factorization stops with H2ULV_ERR_RANK_CHECK
                           instead (for callers that want to know when the model
                           under-predicts)                                      */
@@ -178,7 +179,8 @@ typedef struct h2ulv_allocator {
  * Errors: INVALID_ARG (n < 1, NULL pointer, bad params, non-finite point, an
  * allocator with a NULL function), DUPLICATE_POINTS, SINGULAR, OOM (also when
  * the allocator returns NULL: the first device allocation precedes every
- * launch), HIP.  On error *out is NULL.
+ * launch), RANK_CHECK (a rank model with sketch_fallback 0 and a sketch that
+ * failed its check), HIP.  On error *out is NULL.
  */
 h2ulv_status h2ulv_factorize(const double* pts, int64_t n, const h2ulv_params* params,
                              const h2ulv_allocator* alloc, void* stream, h2ulv_factor** out);
@@ -195,6 +197,8 @@ h2ulv_status h2ulv_factorize(const double* pts, int64_t n, const h2ulv_params* p
  *   alloc   as for h2ulv_factorize (shared by all problems).
  *   out     host array of nprob factor handles.
  * Results are identical to nprob separate h2ulv_factorize calls.
+ * Errors: as h2ulv_factorize, and INVALID_ARG for nprob < 1 or a NULL array;
+ * on any error every out[p] is NULL (no partial batch is returned).
  */
 h2ulv_status h2ulv_factorize_batch(int32_t nprob, const double* const* pts, const int64_t* n,
                                    const h2ulv_params* params, const h2ulv_allocator* alloc,
