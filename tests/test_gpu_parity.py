@@ -264,6 +264,53 @@ def test_sphere_65536_sampled():
     assert np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(bn, axis=0)) < 2e-10
 
 
+def test_cube_1048576_full_size():
+    """The benchmark's workload at its full size (N = 2^20 in the unit cube,
+    leaf 256, tol 1e-6, cap 128, 8 right-hand sides), checked where the oracle
+    can follow one output at a time: leaf boxes of the FP64 form against the
+    oracle; the pair-form exact matvec (2048 tiles) on sampled rows against the
+    oracle's kernel rows, twice with the same bits; and the benchmark's form
+    (mixed precision, every box sketched at full width by a rank model that
+    predicts above the cap, oversampling 88) refined to 1e-10 with block GMRES,
+    its residual recomputed on sampled rows from the oracle's kernel rows."""
+    import math
+    from oracle import rank_model as R
+    prob = W.cube1m()
+    n = prob.n
+    op = O.params_from_problem(prob)
+    fg = _sampled_leaf_parity(prob, [0, 1777, 4095])
+    b = torch.tensor(prob.rhs(), device="cuda")
+    rows = np.random.default_rng(3).choice(n, 32, replace=False)
+    rows[0], rows[1] = 0, n - 1
+    Krows = O.kernel_block(prob.points, rows, np.arange(n), op)
+    y = fg.matvec(b)
+    y2 = fg.matvec(b)
+    assert torch.equal(y, y2)
+    yo = Krows @ prob.rhs()
+    assert np.linalg.norm(y.cpu().numpy().reshape(n, -1)[rows] - yo) / np.linalg.norm(yo) < 1e-14
+    del fg, y, y2
+    parts = {name: np.zeros(s) for name, s in R.SHAPES}
+    parts["b4"][0] = math.log2(1 + 10000)
+    gm = H.RankModel()
+    gm.set_params(R.pack(parts).astype(np.float32))
+    fh = H.factorize(prob.points, H.params_from_problem(prob, precision=H.MIXED, rank_model=gm,
+                                                        sketch_seed=5, oversample=88))
+    for lev in range(1, fh.levels() + 1):
+        m, _ = fh.ranks(lev)
+        kh, ell, st = fh.sketch_info(lev)
+        assert (st == 1).all() and np.array_equal(ell, m - 8), lev
+    x, it, rel = fh.refine_block_gmres(b, rtol=1e-10, max_iter=100, restart=60)
+    assert rel <= 1e-10 and it < 60, (rel, it)
+    r = (b - fh.matvec(x)).cpu().numpy().reshape(n, -1)
+    xn, bn = x.cpu().numpy().reshape(n, -1), prob.rhs()
+    ro = bn[rows] - Krows @ xn
+    # the sampled rows of the residual, recomputed from the oracle's kernel rows,
+    # are as small as the whole; the GPU's agree with them to the rounding of
+    # the two sums over 2^20 terms (|A_ij x_j| summed is ~1e3 |b_i|)
+    assert np.linalg.norm(ro) / np.linalg.norm(bn[rows]) < 1e-9
+    assert np.abs(r[rows] - ro).max() <= 1e-11 * np.abs(bn[rows]).max()
+
+
 def test_mixed_precision_refines_to_fp64_accuracy():
     """FP32 couplings, rotations and Schur updates with FP64 fill-in products
     (no rank cap), QR/ID, inverses, solve and residual: one solve is close to the
