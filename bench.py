@@ -324,9 +324,11 @@ def main() -> int:
     ap.add_argument("--oversample", type=int, default=-1,
                     help="sketch oversampling of the predicted forms (default: full-width "
                          "sketches at the rank cap)")
-    ap.add_argument("--restart", type=int, default=60,
-                    help="GMRES cycle length in (block) steps (the capped factorization leaves "
-                         "many outlying eigenvalues: short cycles restart too often)")
+    ap.add_argument("--restart", type=int, default=128,
+                    help="GMRES cycle length in (block) steps, at most 128 (the capped "
+                         "factorization leaves many outlying eigenvalues: a restart discards "
+                         "them, and with one right-hand side the 262144-point ellipsoids need "
+                         "about 100 steps)")
     ap.add_argument("--allocator", default="torch", choices=["torch", "library"],
                     help="device memory of the factorization: torch's caching allocator "
                          "through the C-ABI callback, or the library's own cache")

@@ -435,7 +435,7 @@ class Factor:
             _check(st)
         return self._back(vec, xt), int(it.value), float(rr.value)
 
-    def refine_block_gmres(self, b, rtol=1e-10, max_iter=200, restart=60, stream=None,
+    def refine_block_gmres(self, b, rtol=1e-10, max_iter=200, restart=128, stream=None,
                            raise_on_fail=True):
         """Refinement whose correction equations (all columns together) are solved
         by block GMRES preconditioned with the ULV solve.  Returns (x, block

@@ -311,6 +311,52 @@ def test_cube_1048576_full_size():
     assert np.abs(r[rows] - ro).max() <= 1e-11 * np.abs(bn[rows]).max()
 
 
+def test_ellipsoids_262144_full_size():
+    """The learned-rank workload at its full size (N = 262144 on 12 ellipsoid
+    surfaces, leaf 256, tol 1e-6, cap 128): leaf boxes of the plain FP64 form
+    against the oracle box by box; a rank model trained on the GPU from the
+    ranks of two 65536-point sets of the same family; the predicted form
+    (mixed precision, the benchmark's oversampling 88) refined to 1e-10 with
+    block GMRES in one cycle of up to 128 steps, with nearly every
+    sketch accepted, and its residual recomputed on sampled rows from the
+    oracle's kernel rows."""
+    prob = W.ellipsoids()
+    n = prob.n
+    op = O.params_from_problem(prob)
+    fg = _sampled_leaf_parity(prob, [0, 500, 1023])
+    del fg
+    F, T = [], []
+    for seed in (501, 502):
+        f = H.factorize(W.ellipsoid_points(65536, seed), H.params_from_problem(prob))
+        for lev in range(1, f.levels() + 1):
+            a, t = f.features(lev)
+            F.append(a)
+            T.append(t)
+        del f
+    gm = H.RankModel(seed=1)
+    loss = gm.train(torch.tensor(np.concatenate(F), device="cuda"),
+                    torch.tensor(np.concatenate(T), device="cuda"), 2000, 3e-3)
+    assert loss < 0.05
+    fh = H.factorize(prob.points, H.params_from_problem(prob, precision=H.MIXED, rank_model=gm,
+                                                        sketch_seed=5, oversample=88))
+    acc = tot = 0
+    for lev in range(1, fh.levels() + 1):
+        kh, ell, st = fh.sketch_info(lev)
+        acc += int(((st == 1) | (st == 3)).sum())
+        tot += int((st != 0).sum())
+    assert tot > 0 and acc >= 0.9 * tot, (acc, tot)
+    b = torch.tensor(prob.rhs(), device="cuda")
+    # one right-hand side and a weak capped preconditioner: about 100 block steps,
+    # which a restart after 60 would stall
+    x, it, rel = fh.refine_block_gmres(b, rtol=1e-10, max_iter=200, restart=128)
+    assert rel <= 1e-10, (rel, it)
+    rows = np.random.default_rng(5).choice(n, 32, replace=False)
+    rows[0], rows[1] = 0, n - 1
+    xn, bn = x.cpu().numpy().reshape(n, -1), prob.rhs().reshape(n, -1)
+    ro = bn[rows] - O.kernel_block(prob.points, rows, np.arange(n), op) @ xn
+    assert np.linalg.norm(ro) / np.linalg.norm(bn[rows]) < 1e-9
+
+
 def test_mixed_precision_refines_to_fp64_accuracy():
     """FP32 couplings, rotations and Schur updates with FP64 fill-in products
     (no rank cap), QR/ID, inverses, solve and residual: one solve is close to the
