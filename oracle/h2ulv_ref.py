@@ -100,7 +100,8 @@ class Params:
     structure: str = "h2"      # "h2" the hierarchy; "blr2" one level of leaves (Sec. II-B)
     drift: tuple = (0.0, 0.0, 0.0)  # b of the advection-diffusion kernel
     bases: str = "auto"        # "auto": V = U for symmetric kernels; "separate": always U, V
-    sketch_fallback: bool = True  # False: a twice-rejected sketch stops with ERR_RANK_CHECK
+    sketch_fallback: bool = True  # False: a sketch still rejected after its full-width
+                                  # retry (if any) stops with ERR_RANK_CHECK
 
 
 def two_sided(p: Params) -> bool:
