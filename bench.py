@@ -2,6 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--form fp64|mixed|predicted|mixed+predicted] [--oversample P]
+                    [--sketch-min-level L]
                     [--refine block|gmres|classical] [--no-reference] [--no-alternate]
                     [--no-cpu-baseline] [--leaf-sweep LEAVES] [--batch-leg P]
 
@@ -20,7 +21,10 @@ ranks of factorizations of two other point sets of the same family.  The
 sketch oversampling of the predicted forms defaults to the value that gives a
 box predicted at the rank cap a sketch of the full width m - 8 (leaf - 8 -
 ceil(1.25 cap), at least 8): at the default workload every box is at the cap,
-and the wider sketch shortens the refinement more than it costs.
+and the wider sketch shortens the refinement more than it costs.  The levels
+above --sketch-min-level (default 8: fewer boxes than the GPU's 256 compute
+units) keep the full pivoted QR: cheap for so few boxes, and sketched top
+levels lengthened the refinement from 29 to 34 block steps.
 
 Default workload: the N=2^20 unit-cube Laplace problem (leaf 256, eta 1, tol
 1e-6, rank cap 128 = leaf / 2, 8 Gaussian right-hand sides), default form
@@ -193,6 +197,12 @@ def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+# predicted forms: the top levels (fewer boxes than the GPU's 256 compute units,
+# levels 1-7) keep the full pivoted QR; their few boxes cost little in full and
+# their bases decide much of the preconditioner's quality
+SKETCH_MIN_LEVEL = 8
+
+
 def default_oversample(prob) -> int:
     """Sketch oversampling that gives a box predicted at the rank cap a sketch
     of the full width m - 8 (m = leaf at the leaves, at most 2 cap above), at
@@ -324,6 +334,10 @@ def main() -> int:
     ap.add_argument("--oversample", type=int, default=-1,
                     help="sketch oversampling of the predicted forms (default: full-width "
                          "sketches at the rank cap)")
+    ap.add_argument("--sketch-min-level", type=int, default=SKETCH_MIN_LEVEL,
+                    help="predicted forms: levels above this one keep the full pivoted QR "
+                         "(default 8: the levels with fewer boxes than the GPU has compute "
+                         "units, 256)")
     ap.add_argument("--restart", type=int, default=128,
                     help="GMRES cycle length in (block) steps, at most 128 (the capped "
                          "factorization leaves many outlying eigenvalues: a restart discards "
@@ -396,7 +410,8 @@ def main() -> int:
         pred = "predicted" in form
         return H.params_from_problem(prob, precision=prec, verbose=1 if args.verbose else 0,
                                      rank_model=model if pred else None, sketch_seed=5,
-                                     oversample=oversample if pred else 8)
+                                     oversample=oversample if pred else 8,
+                                     sketch_min_level=args.sketch_min_level if pred else 0)
 
     allocator = "torch" if args.allocator == "torch" else None
 
@@ -541,6 +556,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": describe(prob), "form": args.form, "refine_rtol": args.rtol,
                    "sketch_oversample": oversample if "predicted" in args.form else None,
+                   "sketch_min_level": args.sketch_min_level if "predicted" in args.form
+                   else None,
                    "refine": args.refine, "gmres_restart": args.restart,
                    "allocator": args.allocator,
                    "value": "this form's algorithmic flops (factorization from its actual ranks + "

@@ -113,6 +113,13 @@ typedef struct h2ulv_params {
                           0: the factorization stops with H2ULV_ERR_RANK_CHECK
                           instead (for callers that want to know when the model
                           under-predicts)                                      */
+  int32_t sketch_min_level; /* rank model only: the levels above this one (level
+                          l < sketch_min_level, the root's children at l = 1)
+                          take the full column-pivoted QR; the others use the
+                          predicted-rank sketches.  0 (default): every level.
+                          The few boxes of the top levels cost little in full,
+                          and their bases decide much of the preconditioner's
+                          quality                                             */
   double drift[3];      /* b of H2ULV_ADVECTION (ignored by the other kernels)  */
 } h2ulv_params;
 

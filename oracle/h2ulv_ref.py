@@ -102,6 +102,7 @@ class Params:
     bases: str = "auto"        # "auto": V = U for symmetric kernels; "separate": always U, V
     sketch_fallback: bool = True  # False: a sketch still rejected after its full-width
                                   # retry (if any) stops with ERR_RANK_CHECK
+    sketch_min_level: int = 0  # levels above this one (lev < it) keep the full pivoted QR
 
 
 def two_sided(p: Params) -> bool:
@@ -136,6 +137,8 @@ def check_params(X: np.ndarray, p: Params) -> None:
         raise OracleError(ERR_INVALID_ARG, "separate bases need structure h2 and no rank model")
     if p.oversample < 0:
         raise OracleError(ERR_INVALID_ARG, "oversample must be >= 0")
+    if p.sketch_min_level < 0:
+        raise OracleError(ERR_INVALID_ARG, "sketch_min_level must be >= 0")
     if p.structure not in ("h2", "blr2"):
         raise OracleError(ERR_INVALID_ARG, "structure must be h2 or blr2")
     if p.partition not in ("kd", "kmeans"):
@@ -794,7 +797,7 @@ def factorize(X: np.ndarray, p: Params, diagnostics: bool = False,
                 # with a rank cap the sketch is sized for min(k-hat, cap)
                 kh = min(khat, p.rank_cap) if p.rank_cap > 0 else khat
                 ell = min(sketch_size(kh, p.oversample), m[i] - SKETCH_PROBES)
-                if 0 < ell < ncol:
+                if 0 < ell < ncol and lev >= p.sketch_min_level:
                     cap_eff = min(m[i], ncol) if p.rank_cap <= 0 else min(p.rank_cap, m[i], ncol)
                     first_attempts.append((i, ell))
                     ok, k_i, piv, Wp, dg = attempt(ell)

@@ -855,6 +855,7 @@ h2ulv_status h2ulv_params_default(h2ulv_params* p) {
   p->structure = 0;
   p->bases = 0;
   p->sketch_fallback = 1;
+  p->sketch_min_level = 0;
   p->drift[0] = p->drift[1] = p->drift[2] = 0.0;
   return H2ULV_OK;
 }

@@ -613,10 +613,11 @@ void Driver::basis_prepare(Stage& st, const std::vector<Prob*>& G) {
       // at most m - probes columns: a box whose predicted rank leaves no room
       // (k-hat >= m - probes included) is still sketched at full width, which
       // the probe check accepts whenever its true rank is below that width; with
-      // a rank cap the sketch is sized for min(k-hat, cap)
+      // a rank cap the sketch is sized for min(k-hat, cap).  Levels above
+      // sketch_min_level keep the full pivoted QR.
       const int64_t ks = p.rank_cap > 0 ? std::min(lf.khat[i], p.rank_cap) : lf.khat[i];
       const int64_t ell = std::min<int64_t>((5 * ks + 3) / 4 + p.oversample, mi - SKETCH_PROBES);
-      if (ell > 0 && ell < P->ncols[i]) {
+      if (ell > 0 && ell < P->ncols[i] && P->lev >= p.sketch_min_level) {
         lf.ell[i] = (int)ell;
         lf.sk_state[i] = 1;
       }

@@ -278,6 +278,8 @@ void validate_params(const h2ulv_params* p) {
   }
   if (p->sketch_fallback != 0 && p->sketch_fallback != 1)
     fail(H2ULV_ERR_INVALID_ARG, "sketch_fallback must be 0 or 1");
+  if (p->sketch_min_level < 0)
+    fail(H2ULV_ERR_INVALID_ARG, "sketch_min_level must be >= 0");
   if (p->bases != 0 && p->bases != 1)
     fail(H2ULV_ERR_INVALID_ARG, "bases must be 0 (by kernel) or 1 (separate)");
   if (separate_bases(*p) &&

@@ -59,7 +59,8 @@ class Params(C.Structure):
         ("precision", C.c_int32), ("verbose", C.c_int32), ("oversample", C.c_int32),
         ("rank_model", C.c_void_p), ("sketch_seed", C.c_uint64), ("fill_in", C.c_int32),
         ("partition", C.c_int32), ("structure", C.c_int32), ("bases", C.c_int32),
-        ("sketch_fallback", C.c_int32), ("drift", C.c_double * 3),
+        ("sketch_fallback", C.c_int32), ("sketch_min_level", C.c_int32),
+        ("drift", C.c_double * 3),
     ]
 
 
@@ -232,7 +233,7 @@ def make_params(kernel=LAPLACE, alpha=0.0, diag=1e3, eta=1.0, leaf=256, tol=1e-8
                 rank_cap=0, far_sample=32, precision=FP64, verbose=0, rank_model=None,
                 sketch_seed=0, oversample=8, fill_in=True, partition="kd",
                 structure="h2", drift=(0.0, 0.0, 0.0), bases="auto",
-                sketch_fallback=True) -> Params:
+                sketch_fallback=True, sketch_min_level=0) -> Params:
     p = Params()
     _check(lib().h2ulv_params_default(C.byref(p)))
     p.kernel, p.alpha, p.diag, p.eta = int(kernel), float(alpha), float(diag), float(eta)
@@ -244,6 +245,7 @@ def make_params(kernel=LAPLACE, alpha=0.0, diag=1e3, eta=1.0, leaf=256, tol=1e-8
     p.structure = {"h2": 0, "blr2": 1}[structure]
     p.bases = {"auto": 0, "separate": 1}[bases]
     p.sketch_fallback = 1 if sketch_fallback else 0
+    p.sketch_min_level = int(sketch_min_level)
     for c in range(3):
         p.drift[c] = float(drift[c])
     p.rank_model = rank_model._h.value if rank_model is not None else None

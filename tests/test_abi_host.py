@@ -35,6 +35,7 @@ def test_params_default(lib):
     assert lib.h2ulv_params_default(C.byref(p)) == 0
     assert p.struct_size == C.sizeof(H.Params)
     assert (p.kernel, p.diag, p.eta, p.leaf_size, p.tol, p.far_sample) == (0, 1e3, 1.0, 256, 1e-8, 32)
+    assert (p.sketch_fallback, p.sketch_min_level) == (1, 0)
     assert lib.h2ulv_params_default(None) == H.ERR_INVALID_ARG
 
 
@@ -44,7 +45,8 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.h2ulv_factorize(None, 10, C.byref(p), None, None, C.byref(out)) == H.ERR_INVALID_ARG
     assert out.value is None
     for field, val in (("leaf_size", 1), ("eta", -1.0), ("tol", float("nan")), ("rank_cap", -1),
-                       ("kernel", 9), ("far_sample", -3), ("precision", 5)):
+                       ("kernel", 9), ("far_sample", -3), ("precision", 5),
+                       ("sketch_fallback", 2), ("sketch_min_level", -1)):
         q = H.make_params(leaf=64)
         setattr(q, field, val)
         dummy = C.c_void_p(16)  # never dereferenced: validation fails first

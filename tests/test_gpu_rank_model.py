@@ -114,7 +114,8 @@ def _gpu_params(op: O.Params, model=None):
     return H.make_params(kernel=op.kernel, alpha=op.alpha, diag=op.diag, eta=op.eta,
                          leaf=op.leaf, tol=op.tol, rank_cap=op.rank_cap,
                          far_sample=op.far_sample, rank_model=model,
-                         sketch_seed=op.sketch_seed, oversample=op.oversample)
+                         sketch_seed=op.sketch_seed, oversample=op.oversample,
+                         sketch_min_level=op.sketch_min_level)
 
 
 def test_features_match_oracle():
@@ -143,26 +144,28 @@ def _constant_model(k):
     return R.pack(parts).astype(np.float32)
 
 
-@pytest.mark.parametrize("n,leaf,tol,oversample,model,cap", [
-    (4096, 128, 1e-6, 8, "trained", 0),   # sketched leaves (m = 128) and upper levels
-    (4096, 128, 1e-8, 8, "trained", 0),   # sketched boxes with m > 512 (multi-workgroup QR)
-    (3000, 64, 1e-6, 0, "constant", 0),   # k-hat = 10, no oversampling: every first
-                                          # sketch is exhausted; full-width retries,
-                                          # then the full QR where those fail too
-    (4096, 128, 1e-6, 8, "trained", 32),  # rank cap 32: sketches sized for min(k-hat,
-                                          # cap), accepted at k = cap without the tol test
-    (4096, 256, 1e-6, 88, "above_cap", 128),  # the benchmark's regime: k-hat above the cap
-                                          # at leaf 256, every box sketched at the full
-                                          # width m - 8 and accepted, mostly at k = cap
+@pytest.mark.parametrize("n,leaf,tol,oversample,model,cap,minlev", [
+    (4096, 128, 1e-6, 8, "trained", 0, 0),   # sketched leaves (m = 128) and upper levels
+    (4096, 128, 1e-8, 8, "trained", 0, 0),   # sketched boxes with m > 512 (multi-workgroup QR)
+    (3000, 64, 1e-6, 0, "constant", 0, 0),   # k-hat = 10, no oversampling: every first
+                                             # sketch is exhausted; full-width retries,
+                                             # then the full QR where those fail too
+    (4096, 128, 1e-6, 8, "trained", 32, 0),  # rank cap 32: sketches sized for min(k-hat,
+                                             # cap), accepted at k = cap without the tol test
+    (4096, 256, 1e-6, 88, "above_cap", 128, 0),  # the benchmark's regime: k-hat above the
+                                             # cap at leaf 256, every box sketched at the
+                                             # full width m - 8, accepted mostly at k = cap
+    (8192, 128, 1e-6, 88, "above_cap", 64, 4),  # levels 1-3 by the full pivoted QR, the
+                                             # sketched levels below them built on those bases
 ])
-def test_predicted_mode_parity(n, leaf, tol, oversample, model, cap):
+def test_predicted_mode_parity(n, leaf, tol, oversample, model, cap, minlev):
     base = O.Params(leaf=leaf, tol=tol, rank_cap=cap)
     if model == "trained":
         th = _oracle_model(W.cube_points(n, 900 + n), base)
     else:
         th = _constant_model(10 if model == "constant" else 10000)
     op = O.Params(leaf=leaf, tol=tol, rank_cap=cap, rank_model=th, sketch_seed=77,
-                  oversample=oversample)
+                  oversample=oversample, sketch_min_level=minlev)
     X = W.cube_points(n, 901 + n)
     fo = O.factorize(X, op)
     gm = H.RankModel()
@@ -178,8 +181,11 @@ def test_predicted_mode_parity(n, leaf, tol, oversample, model, cap):
     if model == "trained":
         assert states.count(1) >= 2
     elif model == "above_cap":
-        assert states.count(1) == len(states)
-        assert all(b.ell == b.m - 8 for l in fo.levels for b in fo.levels[l])
+        sk_boxes = [b for l in fo.levels for b in fo.levels[l] if l >= minlev]
+        assert states.count(1) == len(sk_boxes)
+        assert all(b.ell == b.m - 8 for b in sk_boxes)
+        assert all(b.ell == 0 and b.sketch == 0
+                   for l in fo.levels if l < minlev for b in fo.levels[l])
     else:
         assert states.count(2) + states.count(3) == len(states) and states.count(2) >= 1
     m_all = [b.m for l in fo.levels for b in fo.levels[l] if b.sketch == 1]

@@ -247,3 +247,32 @@ def test_rejected_sketch_without_fallback_reports_rank_check():
     with pytest.raises(O.OracleError) as e:
         O.factorize(X, O.Params(sketch_fallback=False, **kw))
     assert e.value.status == O.ERR_RANK_CHECK
+
+
+def test_sketch_min_level_keeps_the_top_levels_on_the_full_qr():
+    """With sketch_min_level the levels above it take the full pivoted QR (no
+    sketch, same boxes as the plain method where the levels below agree) and
+    the levels from it down are sketched; a threshold below the leaves'
+    level + 1 leaves nothing sketched, which is the plain factorization."""
+    parts = {name: np.zeros(s) for name, s in R.SHAPES}
+    parts["b4"][0] = math.log2(1 + 10000)
+    th = R.pack(parts).astype(np.float32)
+    X = W.cube_points(4096, 3907)
+    kw = dict(leaf=128, tol=1e-6, rank_cap=32, rank_model=th, sketch_seed=77, oversample=8)
+    plain = O.factorize(X, O.Params(leaf=128, tol=1e-6, rank_cap=32))
+    L = plain.tree.L
+    f = O.factorize(X, O.Params(sketch_min_level=L, **kw))
+    for lev in range(1, L + 1):
+        st = [b.sketch for b in f.levels[lev]]
+        if lev < L:
+            assert all(s_ == 0 for s_ in st) and all(b.ell == 0 for b in f.levels[lev])
+        else:
+            assert any(s_ in (1, 3) for s_ in st)
+    none = O.factorize(X, O.Params(sketch_min_level=L + 1, **kw))
+    b = W.gaussian_rhs(4096, 1, 2)
+    assert all(bx.sketch == 0 for lev in none.levels.values() for bx in lev)
+    for lev in range(1, L + 1):
+        assert [bx.k for bx in none.levels[lev]] == [bx.k for bx in plain.levels[lev]]
+    assert np.array_equal(O.solve(none, b), O.solve(plain, b))
+    with pytest.raises(O.OracleError):
+        O.factorize(X, O.Params(sketch_min_level=-1, **kw))
