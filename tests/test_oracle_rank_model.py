@@ -251,9 +251,8 @@ def test_rejected_sketch_without_fallback_reports_rank_check():
 
 def test_sketch_min_level_keeps_the_top_levels_on_the_full_qr():
     """With sketch_min_level the levels above it take the full pivoted QR (no
-    sketch, same boxes as the plain method where the levels below agree) and
-    the levels from it down are sketched; a threshold below the leaves'
-    level + 1 leaves nothing sketched, which is the plain factorization."""
+    sketch) and the levels from it down are sketched; the threshold L + 1, one
+    past the leaf level, sketches nothing and gives the plain factorization."""
     parts = {name: np.zeros(s) for name, s in R.SHAPES}
     parts["b4"][0] = math.log2(1 + 10000)
     th = R.pack(parts).astype(np.float32)
