@@ -461,9 +461,11 @@ h2ulv_status h2ulv_rankmodel_train(h2ulv_rankmodel* m, const float* feat, const 
 /* Features of level lev (1..L) of a factor: feat host 2^lev x 16 row-major,
  * target host 2^lev (log2(1 + k)); either may be NULL. */
 h2ulv_status h2ulv_get_features(const h2ulv_factor* f, int32_t lev, float* feat, float* target);
-/* Per box of level lev: predicted rank (-1 without a model), sketch columns of
- * the last attempt (0: not sketched) and outcome (0 not sketched, 1 accepted,
- * 2 fell back to the full pivoted QR, 3 accepted on the full-width retry). */
+/* Per box of level lev: predicted rank (-1 without a model; predicted also on
+ * the levels above params.sketch_min_level, which are not sketched), sketch
+ * columns of the last attempt (0: not sketched) and outcome (0 not sketched,
+ * 1 accepted, 2 fell back to the full pivoted QR, 3 accepted on the full-width
+ * retry). */
 h2ulv_status h2ulv_get_sketch_info(const h2ulv_factor* f, int32_t lev, int32_t* khat,
                                    int32_t* ell, int32_t* state);
 
