@@ -442,6 +442,18 @@ void h2ulv_rankmodel_destroy(h2ulv_rankmodel* m);
 /* Copy the H2ULV_MLP_NPARAM parameters from / to host memory (synchronous). */
 h2ulv_status h2ulv_rankmodel_set_params(h2ulv_rankmodel* m, const float* host);
 h2ulv_status h2ulv_rankmodel_get_params(const h2ulv_rankmodel* m, float* host);
+/* Write the model (parameters, both Adam moments and the Adam step count) to
+ * the file at path, in the library's versioned binary format ("H2RM", format
+ * version 1, H2ULV_MLP_NPARAM float32 values per array, host byte order), so a
+ * model trained in one process can size the sketches of another.  Synchronous.
+ * Errors: INVALID_ARG (NULL argument, a file that cannot be written), HIP. */
+h2ulv_status h2ulv_rankmodel_save(const h2ulv_rankmodel* m, const char* path);
+/* New model read from a file that h2ulv_rankmodel_save wrote, with its Adam
+ * state, so training can continue.  The file is checked (magic, version,
+ * parameter count, exact size) before any device work.  Free with
+ * h2ulv_rankmodel_destroy.  Errors: INVALID_ARG (NULL argument, missing,
+ * foreign, truncated or oversized file; *out is then NULL), OOM, HIP. */
+h2ulv_status h2ulv_rankmodel_load(const char* path, h2ulv_rankmodel** out);
 /* y[s] = model(feat[s, :]) for n samples; feat device n x 16 row-major, y device. */
 h2ulv_status h2ulv_rankmodel_forward(const h2ulv_rankmodel* m, const float* feat, int64_t n,
                                      float* y, void* stream);

@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <string>
+#include <memory>
 
 #include "h2ulv_factor.h"
 #include "h2ulv_learned.h"
@@ -1186,6 +1188,71 @@ h2ulv_status h2ulv_rankmodel_get_params(const h2ulv_rankmodel* m, float* host) {
   }
   return guarded([&] {
     H2ULV_HIP(hipMemcpy(host, m->theta.p, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+  });
+}
+
+// Rank model file: the 4 bytes "H2RM", the format version and the parameter
+// count (uint32 each), the Adam step count (int64), then the parameters and
+// the two Adam moments (H2ULV_MLP_NPARAM float32 each), in host byte order.
+namespace {
+constexpr char RM_MAGIC[4] = {'H', '2', 'R', 'M'};
+constexpr uint32_t RM_VERSION = 1;
+using FileHandle = std::unique_ptr<FILE, int (*)(FILE*)>;
+}  // namespace
+
+h2ulv_status h2ulv_rankmodel_save(const h2ulv_rankmodel* m, const char* path) {
+  if (!m || !path) {
+    g_last_error = "NULL argument";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  return guarded([&] {
+    const size_t np = MLP_NPARAM;
+    std::vector<float> buf(3 * np);
+    H2ULV_HIP(hipMemcpy(buf.data(), m->theta.p, np * sizeof(float), hipMemcpyDeviceToHost));
+    H2ULV_HIP(hipMemcpy(buf.data() + np, m->m.p, np * sizeof(float), hipMemcpyDeviceToHost));
+    H2ULV_HIP(hipMemcpy(buf.data() + 2 * np, m->v.p, np * sizeof(float), hipMemcpyDeviceToHost));
+    FileHandle f(std::fopen(path, "wb"), &std::fclose);
+    if (!f) fail(H2ULV_ERR_INVALID_ARG, std::string("cannot open ") + path + " for writing");
+    const uint32_t head[2] = {RM_VERSION, (uint32_t)np};
+    const int64_t step = m->step;
+    bool ok = std::fwrite(RM_MAGIC, 1, 4, f.get()) == 4 &&
+              std::fwrite(head, sizeof(uint32_t), 2, f.get()) == 2 &&
+              std::fwrite(&step, sizeof(int64_t), 1, f.get()) == 1 &&
+              std::fwrite(buf.data(), sizeof(float), buf.size(), f.get()) == buf.size();
+    ok = (std::fclose(f.release()) == 0) && ok;
+    if (!ok) fail(H2ULV_ERR_INVALID_ARG, std::string("writing ") + path + " failed");
+  });
+}
+
+h2ulv_status h2ulv_rankmodel_load(const char* path, h2ulv_rankmodel** out) {
+  if (!path || !out) {
+    g_last_error = "NULL argument";
+    return H2ULV_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  return guarded([&] {
+    FileHandle f(std::fopen(path, "rb"), &std::fclose);
+    if (!f) fail(H2ULV_ERR_INVALID_ARG, std::string("cannot open ") + path);
+    char magic[4];
+    uint32_t head[2];
+    int64_t step = 0;
+    const size_t np = MLP_NPARAM;
+    if (std::fread(magic, 1, 4, f.get()) != 4 || std::memcmp(magic, RM_MAGIC, 4) != 0)
+      fail(H2ULV_ERR_INVALID_ARG, std::string(path) + " is not a rank model file");
+    if (std::fread(head, sizeof(uint32_t), 2, f.get()) != 2 || head[0] != RM_VERSION ||
+        head[1] != (uint32_t)np)
+      fail(H2ULV_ERR_INVALID_ARG, std::string(path) + ": unsupported version or parameter count");
+    std::vector<float> buf(3 * np);
+    if (std::fread(&step, sizeof(int64_t), 1, f.get()) != 1 || step < 0 ||
+        std::fread(buf.data(), sizeof(float), buf.size(), f.get()) != buf.size() ||
+        std::fgetc(f.get()) != EOF)
+      fail(H2ULV_ERR_INVALID_ARG, std::string(path) + ": truncated or oversized rank model file");
+    std::unique_ptr<h2ulv_rankmodel> M(rankmodel_create(0));
+    H2ULV_HIP(hipMemcpy(M->theta.p, buf.data(), np * sizeof(float), hipMemcpyHostToDevice));
+    H2ULV_HIP(hipMemcpy(M->m.p, buf.data() + np, np * sizeof(float), hipMemcpyHostToDevice));
+    H2ULV_HIP(hipMemcpy(M->v.p, buf.data() + 2 * np, np * sizeof(float), hipMemcpyHostToDevice));
+    M->step = step;
+    *out = M.release();
   });
 }
 

@@ -8,6 +8,7 @@ loudly otherwise.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from pathlib import Path
 
 import numpy as np
@@ -41,7 +42,8 @@ EXPORTS = [
     "h2ulv_profile_enable", "h2ulv_profile_read", "h2ulv_rankmodel_create",
     "h2ulv_rankmodel_destroy", "h2ulv_rankmodel_set_params", "h2ulv_rankmodel_get_params",
     "h2ulv_rankmodel_forward", "h2ulv_rankmodel_gradient", "h2ulv_rankmodel_adam_step",
-    "h2ulv_rankmodel_train", "h2ulv_get_features", "h2ulv_get_sketch_info",
+    "h2ulv_rankmodel_train", "h2ulv_rankmodel_save", "h2ulv_rankmodel_load",
+    "h2ulv_get_features", "h2ulv_get_sketch_info",
     "h2ulv_release_cache", "h2ulv_refine_gmres", "h2ulv_refine_block_gmres",
     "h2ulv_gemm_tile_rates",
     "h2ulv_matvec_exact_noalloc",
@@ -206,6 +208,8 @@ def lib() -> C.CDLL:
         "h2ulv_rankmodel_gradient": (i32, [vp, vp, vp, i64, vp, P(C.c_float), vp]),
         "h2ulv_rankmodel_adam_step": (i32, [vp, vp, C.c_float, vp]),
         "h2ulv_rankmodel_train": (i32, [vp, vp, vp, i64, i32, C.c_float, P(C.c_float), vp]),
+        "h2ulv_rankmodel_save": (i32, [vp, C.c_char_p]),
+        "h2ulv_rankmodel_load": (i32, [C.c_char_p, P(vp)]),
         "h2ulv_get_features": (i32, [vp, i32, vp, vp]),
         "h2ulv_get_sketch_info": (i32, [vp, i32, vp, vp, vp]),
         "h2ulv_release_cache": (i32, []),
@@ -278,6 +282,19 @@ class RankModel:
         if h is not None and h.value and _lib is not None:
             _lib.h2ulv_rankmodel_destroy(h)
             self._h = None
+
+    def save(self, path) -> None:
+        """Write the model and its Adam state to a file (h2ulv_rankmodel_save)."""
+        _check(lib().h2ulv_rankmodel_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path) -> "RankModel":
+        """A model read from a file that save() wrote (h2ulv_rankmodel_load)."""
+        h = C.c_void_p()
+        _check(lib().h2ulv_rankmodel_load(os.fsencode(path), C.byref(h)))
+        obj = cls.__new__(cls)
+        obj._h = h
+        return obj
 
     def get_params(self) -> np.ndarray:
         out = np.empty(MLP_NPARAM, dtype=np.float32)

@@ -127,3 +127,34 @@ def test_separate_bases_parameter_checks():
         assert e.value.status == H.ERR_INVALID_ARG, kw
     with pytest.raises(O.OracleError):
         O.factorize(X, O.Params(kernel=O.ADVECTION, alpha=0.5, drift=(0.6, 0.0, 0.0)))
+
+
+def test_rankmodel_load_rejects_bad_files_before_device_work(lib, tmp_path):
+    """h2ulv_rankmodel_load checks the file (magic, format version, parameter
+    count, exact size) before it allocates anything on a device, so every bad
+    file is refused here, without a GPU; NULL arguments too."""
+    import struct
+    out = C.c_void_p(123)
+    assert lib.h2ulv_rankmodel_load(str(tmp_path / "missing.h2rm").encode(),
+                                    C.byref(out)) == H.ERR_INVALID_ARG
+    assert out.value is None
+    n = H.MLP_NPARAM
+    good_head = b"H2RM" + struct.pack("<IIq", 1, n, 7)
+    body = bytes(3 * n * 4)
+    cases = {"foreign": b"XXXX" + good_head[4:] + body,
+             "version": b"H2RM" + struct.pack("<IIq", 2, n, 7) + body,
+             "count": b"H2RM" + struct.pack("<IIq", 1, n - 1, 7) + body,
+             "negative step": b"H2RM" + struct.pack("<IIq", 1, n, -1) + body,
+             "truncated": good_head + body[:-4],
+             "oversized": good_head + body + b"\0",
+             "empty": b""}
+    for name, data in cases.items():
+        f = tmp_path / f"{name}.h2rm"
+        f.write_bytes(data)
+        out = C.c_void_p(123)
+        assert lib.h2ulv_rankmodel_load(str(f).encode(), C.byref(out)) == H.ERR_INVALID_ARG, name
+        assert out.value is None, name
+        assert lib.h2ulv_last_error().decode(), name
+    assert lib.h2ulv_rankmodel_load(None, C.byref(out)) == H.ERR_INVALID_ARG
+    assert lib.h2ulv_rankmodel_load(str(tmp_path / "x").encode(), None) == H.ERR_INVALID_ARG
+    assert lib.h2ulv_rankmodel_save(None, str(tmp_path / "x").encode()) == H.ERR_INVALID_ARG

@@ -91,6 +91,34 @@ def test_adam_steps_match_oracle():
         assert np.abs(got - tho).max() <= 1e-6 * max(1.0, np.abs(tho).max()), step
 
 
+def test_rankmodel_save_load_roundtrip(tmp_path):
+    """A model trained for a few steps, saved and loaded in a new handle, has
+    the same parameters, predicts the same values, and continues training
+    exactly as the original (the Adam moments and step count came along)."""
+    rng = np.random.default_rng(11)
+    feat = torch.tensor(rng.standard_normal((300, H.NFEAT)), dtype=torch.float32, device="cuda")
+    target = torch.tensor(rng.uniform(0, 7, 300), dtype=torch.float32, device="cuda")
+    gm = H.RankModel(seed=3)
+    gm.train(feat, target, 25, 3e-3)
+    path = tmp_path / "model.h2rm"
+    gm.save(path)
+    assert path.stat().st_size == 4 + 4 + 4 + 8 + 3 * H.MLP_NPARAM * 4
+    lm = H.RankModel.load(path)
+    assert np.array_equal(lm.get_params(), gm.get_params())
+    assert torch.equal(lm.forward(feat), gm.forward(feat))
+    g, _ = gm.gradient(feat, target)
+    gm.adam_step(g, 3e-3)
+    lm.adam_step(g, 3e-3)
+    torch.cuda.synchronize()
+    assert np.array_equal(lm.get_params(), gm.get_params())
+    # a fresh model with the same parameters but no Adam state steps differently
+    fm = H.RankModel(seed=0)
+    fm.set_params(H.RankModel.load(path).get_params())
+    fm.adam_step(g, 3e-3)
+    torch.cuda.synchronize()
+    assert not np.array_equal(fm.get_params(), gm.get_params())
+
+
 def test_training_follows_oracle_and_fits():
     X, _ = _inputs(500, 41)
     t = (X @ np.linspace(-1, 1, R.NFEAT) + 3.0).astype(np.float32)
