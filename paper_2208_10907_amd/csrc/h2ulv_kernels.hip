@@ -2298,6 +2298,117 @@ __global__ __launch_bounds__(512) void matvec_sym_kernel(const double* __restric
   }
 }
 
+// Exact matvec of a symmetric kernel for one column, each unordered pair
+// evaluated once: the one-column counterpart of matvec_sym_kernel (same tile
+// pairs, launches, rotation and slots).  Lane 16 q + 4 b + p of a wave
+// evaluates K(target 16 g + 4 b + q of the wave's 64, source p of the step) for
+// the four target groups g.  y_I: a vector FMA with x of the lane's source; the
+// four lanes of a target (p = 0..3) are added once, at the end of the launch.
+// y_J: the entry is, as it stands, the B operand of the FP64 4x4x4 MFMA (k index
+// q over the four targets of block b, column p over the sources); the A operand
+// holds x of those targets in its row 0 (lanes p = 0) and zeros in rows 1-3, so
+// row 0 of block b's result is that block's contribution to the four sources.
+// Two exchanges add the blocks, and lanes 0-3 (q = 0, b = 0) add the four
+// sources' sums to the tile's y_J accumulator in LDS.
+template <int KIND, bool DIAG>
+__global__ __launch_bounds__(512) void matvec_sym1_kernel(const double* __restrict__ pts,
+                                                          int64_t n, KernelFn kf,
+                                                          const double* __restrict__ x,
+                                                          double* __restrict__ Y, int nb, int k0,
+                                                          int kmax) {
+  __shared__ double sp[3][MVS_TB];
+  __shared__ double sx[MVS_TB];
+  __shared__ double sy[MVS_TB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, b = (lane >> 2) & 3, p = lane & 3;
+  const int I = blockIdx.x;
+  const int64_t tw = (int64_t)I * MVS_TB + wave * 64;  // the wave's 64 targets
+  double tx[4], ty[4], tz[4], xa[4], acc[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int64_t t = tw + 16 * g + 4 * b + q;
+    if (t < n) {
+      tx[g] = pts[3 * t];
+      ty[g] = pts[3 * t + 1];
+      tz[g] = pts[3 * t + 2];
+    } else {
+      tx[g] = 1e30;
+      ty[g] = 0.0;
+      tz[g] = 0.0;
+    }
+    xa[g] = (p == 0 && t < n) ? x[t] : 0.0;
+    acc[g] = 0.0;
+  }
+  const int ntile = DIAG ? 1 : MVS_R;
+  for (int r = 0; r < ntile; ++r) {
+    const int k = k0 + r;
+    if (!DIAG) {
+      if (k > kmax) break;
+      if (2 * k == nb && I >= nb / 2) continue;
+    }
+    const int J = DIAG ? I : (I + k) % nb;
+    const int64_t js = (int64_t)J * MVS_TB;
+    __syncthreads();
+    {
+      const int t = threadIdx.x;
+      const int64_t sidx = js + t;
+      if (sidx < n) {
+        for (int d = 0; d < 3; ++d) sp[d][t] = pts[3 * sidx + d];
+        sx[t] = x[sidx];
+      } else {
+        sp[0][t] = -1e30;
+        sp[1][t] = sp[2][t] = 0.0;
+        sx[t] = 0.0;
+      }
+      if (!DIAG) sy[t] = 0.0;
+    }
+    __syncthreads();
+    for (int step = 0; step < 8; ++step) {
+      const int sub = DIAG ? step : (wave + step) & 7;
+      // unrolled 4 times: 1.7% faster than not unrolled, 20% faster than fully
+      // (whose 244 registers halve the occupancy)
+#pragma unroll 4
+      for (int c = 0; c < 16; ++c) {
+        const int s0 = sub * 64 + 4 * c;
+        const int src = s0 + p;
+        const double sx0 = sp[0][src], sy0 = sp[1][src], sz0 = sp[2][src];
+        const double xs = sx[src];
+        double e = 0.0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const double dx = tx[g] - sx0, dy = ty[g] - sy0, dz = tz[g] - sz0;
+          const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+          double kv = inv_sqrt(r2);
+          if (KIND == 1) kv *= exp(-kf.alpha * (r2 * kv));
+          if (DIAG) kv = r2 > 0.0 ? kv : 0.0;
+          acc[g] = fma(kv, xs, acc[g]);
+          if (!DIAG) e = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[g], kv, e, 0, 0, 0);
+        }
+        if (!DIAG) {
+          e += __shfl_xor(e, 4, 64);
+          e += __shfl_xor(e, 8, 64);
+          if (lane < 4) sy[s0 + lane] += e;
+        }
+      }
+      if (!DIAG) __syncthreads();
+    }
+    if (!DIAG) {
+      const int t = threadIdx.x;
+      const int64_t sidx = js + t;
+      if (sidx < n) Y[(int64_t)(1 + r) * n + sidx] += sy[t];
+    }
+  }
+  // y_I sums: the four source lanes of each target, (p0 + p1) + (p2 + p3)
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    double v = acc[g];
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    const int64_t t = tw + 16 * g + 4 * b + q;
+    if (p == 0 && t < n) Y[t] = DIAG ? v : Y[t] + v;
+  }
+}
+
 __global__ void zero_kernel(double* __restrict__ p, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -2328,7 +2439,8 @@ int matvec_split(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(MV_MAX_SPLIT, 4096 / grid));
 }
 
-// the pair form: 8 columns, a symmetric kernel, at least MVS_MIN_TILES tiles
+// the pair forms (blocks of 8 columns, single columns): a symmetric kernel and
+// at least MVS_MIN_TILES tiles
 bool matvec_pairs(int64_t n, int kind) {
   return kind != 2 && (n + MVS_TB - 1) / MVS_TB >= MVS_MIN_TILES;
 }
@@ -2350,9 +2462,33 @@ void matvec_sym_launch(const double* pts, int64_t n, KernelFn kf, const double* 
                      work, 1 + MVS_R, 8, n, kf.diag, x, ldx, y, ldy);
 }
 
+template <int KIND>
+void matvec_sym1_launch(const double* pts, int64_t n, KernelFn kf, const double* x, int64_t ldx,
+                        double* y, int64_t ldy, double* work, hipStream_t s) {
+  const int nb = (int)((n + MVS_TB - 1) / MVS_TB);
+  const int kmax = nb / 2;
+  hipLaunchKernelGGL(zero_kernel, dim3(2048), dim3(256), 0, s, work + n, (int64_t)MVS_R * n);
+  hipLaunchKernelGGL((matvec_sym1_kernel<KIND, true>), dim3(nb), dim3(512), 0, s, pts, n, kf, x,
+                     work, nb, 0, 0);
+  for (int k0 = 1; k0 <= kmax; k0 += MVS_R)
+    hipLaunchKernelGGL((matvec_sym1_kernel<KIND, false>), dim3(nb), dim3(512), 0, s, pts, n, kf,
+                       x, work, nb, k0, kmax);
+  hipLaunchKernelGGL(matvec_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     work, 1 + MVS_R, 1, n, kf.diag, x, ldx, y, ldy);
+}
+
 template <int NR>
 void matvec_launch(const double* pts, int64_t n, KernelFn kf, const double* x, int64_t ldx,
                    double* y, int64_t ldy, double* work, hipStream_t s) {
+  if constexpr (NR == 1) {
+    if (work && matvec_pairs(n, kf.kind)) {
+      if (kf.kind == 0)
+        matvec_sym1_launch<0>(pts, n, kf, x, ldx, y, ldy, work, s);
+      else
+        matvec_sym1_launch<1>(pts, n, kf, x, ldx, y, ldy, work, s);
+      return;
+    }
+  }
   if constexpr (NR == 8) {
     if (work && matvec_pairs(n, kf.kind)) {
       if (kf.kind == 0)
@@ -2402,9 +2538,10 @@ void matvec_launch(const double* pts, int64_t n, KernelFn kf, const double* x, i
 int64_t matvec_work_words(int64_t n, int nrhs) {
   const int ns = matvec_split(n);
   int64_t w = ns > 1 ? (int64_t)ns * std::min(nrhs, 8) * n : 0;
-  // the pair form (8 columns of a symmetric kernel): sums of y_I and the
-  // MVS_R slots of y_J sums
+  // the pair forms (blocks of 8 columns, single columns; a symmetric kernel):
+  // sums of y_I and the MVS_R slots of y_J sums
   if (nrhs >= 8 && matvec_pairs(n, 0)) w = std::max<int64_t>(w, (int64_t)(1 + MVS_R) * 8 * n);
+  if (nrhs % 4 != 0 && matvec_pairs(n, 0)) w = std::max<int64_t>(w, (int64_t)(1 + MVS_R) * n);
   return w;
 }
 

@@ -151,13 +151,14 @@ def test_matvec_exact(kernel, n, nrhs):
 
 @pytest.mark.parametrize("kernel,n,nrhs", [(O.LAPLACE, 70001, 13), (O.YUKAWA, 66000, 1),
                                              (O.YUKAWA, 65537, 8), (O.LAPLACE, 300001, 9),
-                                             (O.YUKAWA, 262657, 8)])
+                                             (O.YUKAWA, 262657, 8), (O.LAPLACE, 300001, 1),
+                                             (O.YUKAWA, 262657, 13)])
 def test_matvec_split_sampled(kernel, n, nrhs):
     """Exact matvec at sizes where the sources are split over several
     workgroups (partial sums added in a fixed order) and, from 512 tiles of 512
-    points on, in the pair form (each unordered pair evaluated once, ragged last
-    tile): sampled rows against the oracle's kernel rows, and two calls give
-    identical bits."""
+    points on, in the pair forms (each unordered pair evaluated once, ragged
+    last tile; blocks of 8 columns and single columns, 13 = 8 + 4 + 1): sampled
+    rows against the oracle's kernel rows, and two calls give identical bits."""
     X = W.sphere_points(n, 8)
     op = O.Params(kernel=kernel, alpha=0.5, leaf=256, tol=1e-3)
     fg = H.factorize(X, _params(op))
