@@ -2304,12 +2304,11 @@ __global__ __launch_bounds__(512) void matvec_sym_kernel(const double* __restric
 // evaluates K(target 16 g + 4 b + q of the wave's 64, source p of the step) for
 // the four target groups g.  y_I: a vector FMA with x of the lane's source; the
 // four lanes of a target (p = 0..3) are added once, at the end of the launch.
-// y_J: the entry is, as it stands, the B operand of the FP64 4x4x4 MFMA (k index
-// q over the four targets of block b, column p over the sources); the A operand
-// holds x of those targets in its row 0 (lanes p = 0) and zeros in rows 1-3, so
-// row 0 of block b's result is that block's contribution to the four sources.
-// Two exchanges add the blocks, and lanes 0-3 (q = 0, b = 0) add the four
-// sources' sums to the tile's y_J accumulator in LDS.
+// y_J: a vector FMA with x of the lane's target over the four groups, then four
+// exchanges add the 16 lanes of each source (lane bits 2-5), and lanes 0-3 add
+// the four sources' sums to the tile's y_J accumulator in LDS.  (The FP64 MFMA
+// with x in one row of A, the entry as B, gave the same sums 3% slower: three
+// of its four rows were zeros.)
 template <int KIND, bool DIAG>
 __global__ __launch_bounds__(512) void matvec_sym1_kernel(const double* __restrict__ pts,
                                                           int64_t n, KernelFn kf,
@@ -2336,7 +2335,7 @@ __global__ __launch_bounds__(512) void matvec_sym1_kernel(const double* __restri
       ty[g] = 0.0;
       tz[g] = 0.0;
     }
-    xa[g] = (p == 0 && t < n) ? x[t] : 0.0;
+    xa[g] = t < n ? x[t] : 0.0;
     acc[g] = 0.0;
   }
   const int ntile = DIAG ? 1 : MVS_R;
@@ -2365,8 +2364,9 @@ __global__ __launch_bounds__(512) void matvec_sym1_kernel(const double* __restri
     __syncthreads();
     for (int step = 0; step < 8; ++step) {
       const int sub = DIAG ? step : (wave + step) & 7;
-      // unrolled 4 times: 1.7% faster than not unrolled, 20% faster than fully
-      // (whose 244 registers halve the occupancy)
+      // unrolled 4 times (measured with the MFMA form of the y_J sums: 1.7%
+      // faster than not unrolled, 20% faster than fully, whose 244 registers
+      // halved the occupancy)
 #pragma unroll 4
       for (int c = 0; c < 16; ++c) {
         const int s0 = sub * 64 + 4 * c;
@@ -2382,11 +2382,13 @@ __global__ __launch_bounds__(512) void matvec_sym1_kernel(const double* __restri
           if (KIND == 1) kv *= exp(-kf.alpha * (r2 * kv));
           if (DIAG) kv = r2 > 0.0 ? kv : 0.0;
           acc[g] = fma(kv, xs, acc[g]);
-          if (!DIAG) e = __builtin_amdgcn_mfma_f64_4x4x4f64(xa[g], kv, e, 0, 0, 0);
+          if (!DIAG) e = fma(kv, xa[g], e);
         }
         if (!DIAG) {
           e += __shfl_xor(e, 4, 64);
           e += __shfl_xor(e, 8, 64);
+          e += __shfl_xor(e, 16, 64);
+          e += __shfl_xor(e, 32, 64);
           if (lane < 4) sy[s0 + lane] += e;
         }
       }
