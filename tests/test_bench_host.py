@@ -44,3 +44,15 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_predicted_form_defaults():
+    """The benchmark's learned-rank defaults: capped boxes sketched at the full
+    width m - 8 (oversampling leaf - 8 - ceil(1.25 cap), 8 without a cap), and
+    levels 1-7 on the full pivoted QR."""
+    import workloads as W
+    assert bench.default_oversample(W.cube1m()) == 256 - 8 - 160
+    assert bench.default_oversample(W.small_cube()) == 64 - 8 - 40
+    assert bench.SKETCH_MIN_LEVEL == 8
+    import argparse
+    assert bench.default_oversample(argparse.Namespace(leaf=256, rank_cap=0)) == 8
