@@ -248,12 +248,14 @@ h2ulv_status h2ulv_matvec_exact(const h2ulv_factor* f, const double* x, int64_t 
  * allocate: code under stream capture, tight serving loops, harnesses that
  * forbid allocation.  Same arguments, launches, split and summation order as
  * h2ulv_matvec_exact (the results are identical); it neither allocates nor
- * synchronises the stream.  The partial sums of the split sources (n >= 65536)
- * live in a file-scope device array of 8 Mi doubles (64 MiB) that each GPU the
- * library runs on holds until the process ends:
- * n * min(nrhs, 8) * splits doubles must fit, splits = min(8, 4096 / ceil(n /
- * 512)), which holds for every n < 65536 (no partial sums) and every n <=
- * 131072; larger requests return INVALID_ARG before any launch.  All calls on
+ * synchronises the stream.  The partial sums live in a file-scope device
+ * array of 16 Mi doubles (128 MiB) that each GPU the library runs on holds
+ * until the process ends.  A request needs the largest of: n * min(nrhs, 8) *
+ * splits doubles for the split sources (splits = min(8, 4096 / ceil(n / 512))
+ * from n >= 65536 on, none below) and, for the Laplace and Yukawa kernels from
+ * n > 261632 on (the pair forms), 72 n when nrhs >= 8 and 9 n when nrhs is
+ * not a multiple of 4.  So every n <= 261632 fits, one column fits up to
+ * n = 1864135, and larger requests return INVALID_ARG before any launch.  All calls on
  * one GPU share that array: calls whose executions overlap on one GPU (other
  * streams, other threads) race and must be serialised by the caller.
  * Errors: INVALID_ARG (as h2ulv_matvec_exact, or too large), HIP.

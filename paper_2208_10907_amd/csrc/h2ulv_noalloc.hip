@@ -13,7 +13,7 @@
 #include "h2ulv_kernels.h"
 
 namespace {
-constexpr int64_t kScratchWords = int64_t(8) << 20;  // 64 MiB of doubles per GPU
+constexpr int64_t kScratchWords = int64_t(16) << 20;  // 128 MiB of doubles per GPU
 constexpr int kMaxDevices = 64;
 }  // namespace
 

@@ -1,7 +1,8 @@
 """The allocation-free exact matvec (h2ulv_matvec_exact_noalloc) against the
 allocating one (h2ulv_matvec_exact), called through the C-ABI: two calls in a
 row on one GPU, the second with a smaller input, both large enough that the
-split partial sums go through the per-GPU array; then a request beyond the
+split partial sums go through the per-GPU array; a third with one column at
+n = 2^20 (the single-column pair form's slots); then a request beyond the
 array's size, rejected before any launch."""
 import ctypes as C
 
@@ -26,18 +27,24 @@ def _like(x, fill):
     return y.t()  # column-major like x
 
 
+def _ld(t):
+    # leading dimension of a column-major block; a single column's stride along
+    # the column index is not meaningful (torch may report 1), so it is n
+    return t.stride(1) if t.shape[1] > 1 else t.shape[0]
+
+
 def _reference(f, x):
     y = _like(x, 0.0)
-    st = H.lib().h2ulv_matvec_exact(f._h, C.c_void_p(x.data_ptr()), x.stride(1),
-                                    C.c_void_p(y.data_ptr()), y.stride(1), x.shape[1], None)
+    st = H.lib().h2ulv_matvec_exact(f._h, C.c_void_p(x.data_ptr()), _ld(x),
+                                    C.c_void_p(y.data_ptr()), _ld(y), x.shape[1], None)
     assert st == H.OK, H.lib().h2ulv_last_error()
     return y
 
 
 def _noalloc(f, x):
     y = _like(x, float("nan"))
-    st = H.lib().h2ulv_matvec_exact_noalloc(f._h, C.c_void_p(x.data_ptr()), x.stride(1),
-                                            C.c_void_p(y.data_ptr()), y.stride(1), x.shape[1],
+    st = H.lib().h2ulv_matvec_exact_noalloc(f._h, C.c_void_p(x.data_ptr()), _ld(x),
+                                            C.c_void_p(y.data_ptr()), _ld(y), x.shape[1],
                                             None)
     assert st == H.OK, H.lib().h2ulv_last_error()
     torch.cuda.synchronize()
@@ -50,7 +57,7 @@ def _cols(n, nrhs, seed):
 
 
 def test_noalloc_matvec_equals_allocating_matvec():
-    # first call: the largest size the array holds (n = 131072, 8 columns, 8 splits)
+    # first call: n = 131072, 8 columns, 8 splits (half the array)
     fa = _factor(131072, 21)
     xa = _cols(131072, 8, 22)
     ya = _noalloc(fa, xa)
@@ -72,7 +79,17 @@ def test_noalloc_matvec_equals_allocating_matvec():
     rows = np.random.default_rng(5).choice(65536, 24, replace=False)
     yo = O.kernel_block(Xb, rows, np.arange(65536), O.Params()) @ xb.cpu().numpy()
     assert np.linalg.norm(yb.cpu().numpy()[rows] - yo) / np.linalg.norm(yo) < 1e-14
+    # third call: one column at n = 2^20, the single-column pair form, whose y_I
+    # and y_J slots (9 n doubles, over half the array) go through it
+    fd = _factor(1 << 20, 27)
+    xd = _cols(1 << 20, 1, 28)
+    yd = _noalloc(fd, xd)
+    rd = _reference(fd, xd)
+    torch.cuda.synchronize()
+    assert torch.equal(yd, rd)
+    del fd
     # a request whose partial sums exceed the array is refused before any launch
+    # (n = 262144, 8 columns: the 8-column pair form's 72 n doubles)
     fc = _factor(262144, 25)
     xc = _cols(262144, 8, 26)
     yc = _like(xc, 0.0)
